@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the hash join hot path on one MI355X.
+
+A step is one PHJ join of the 16M x 16M workload (R keys a permutation of
+1..2^24, S keys uniform over 1..2^25, so about half of S matches), inputs
+resident in HBM before timing starts, output materialised in HBM.  Prints one
+JSON line: input tuples/s of PHJ (the headline value), the same for SHJ on the
+same inputs, per-kernel times and the roofline of the dominant kernel
+(algorithmic bytes / HIP-event duration, against 8 TB/s), and the CPU oracle
+timed on the host as a reference point.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "input tuples/s, SHJ & PHJ 16M⋈16M; batched joins/s; p50/p99 latency at fixed QPS"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--bits", type=str, default="6,6")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--hash", type=str, default="identity", choices=["identity", "murmur2"])
+    ap.add_argument("--n", type=int, default=1 << 24, help="|R| = |S| (default 2^24)")
+    ap.add_argument("--no-shj", action="store_true", help="skip the SHJ line")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="also time every radix configuration")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(name: str, n_r: int, n_s: int, m: int) -> float | None:
+    """Bytes a launch of `name` must move (SoA int32 keys and rids)."""
+    n = n_r + n_s
+    return {
+        "part_hist": 4.0 * n,            # read keys
+        "part_scatter": 16.0 * n,        # read key+rid, write key+rid
+        "join_count": 4.0 * n,           # read R_i and S_i keys
+        "join_write": 8.0 * n + 8.0 * m,  # read key+rid of R_i and S_i, write the pairs
+        "shj_build": 4.0 * n_r,          # read R keys (table traffic is random, counted separately)
+        "shj_count": 4.0 * n_s,
+        "shj_write": 8.0 * n_s + 8.0 * m,
+    }.get(name)
+
+
+def time_steps(fn, steps: int, warmup: int, torch) -> float:
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def kernel_times(hj, p, t, out_r, out_s, ws, d_count, reps: int):
+    """Average HIP-event duration of each kernel over `reps` timed joins."""
+    acc: dict[str, list[float]] = {}
+    for _ in range(reps):
+        for name, ms in hj.hj_join_timed(p, *t, out_r, out_s, ws, d_count):
+            acc.setdefault(name, []).append(ms)
+    return acc
+
+
+def summarize(acc, reps, n_r, n_s, m):
+    rows = {}
+    for name, v in acc.items():
+        per_join = sum(v) / reps
+        launches = len(v) / reps
+        avg = sum(v) / len(v)
+        ab = algorithmic_bytes(name, n_r, n_s, m)
+        row = {"ms_per_join": round(per_join, 4), "launches_per_join": launches, "avg_launch_ms": round(avg, 4)}
+        if ab is not None:
+            # algorithmic bytes of one launch: passes launch the kernel once each
+            row["gbs"] = round(ab / (avg * 1e-3) / 1e9, 1)
+        rows[name] = row
+    return rows
+
+
+def cpu_baseline(n: int) -> dict:
+    """The oracle (single-threaded chained hash join) on the full 16M x 16M inputs."""
+    import oracle
+    from paper_1307_1955_amd import gen
+    r, s = gen.config_c2(n=n)
+    t0 = time.perf_counter()
+    with oracle.Table(r.key, r.rid) as tb:
+        o_r, o_s = tb.probe(s.key, s.rid)
+    el = time.perf_counter() - t0
+    return {"value": (len(r) + len(s)) / el, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+            "sample": "one full %d x %d join (build + probe + emit %d pairs), %.1f s" % (len(r), len(s), len(o_r), el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the join runs on a single MI355X; multi-GPU sharding is a design "
+              "note only (--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1307_1955_amd.hj as hj
+    from paper_1307_1955_amd.gen import device as dgen
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    bits = tuple(int(b) for b in args.bits.split(","))
+    p = hj.params("phj", args.passes, bits, hash=args.hash, tile=args.tile)
+    print("bench: generating 16M x 16M inputs on the device", file=sys.stderr, flush=True)
+    t = dgen.config_c2(n=n, device=dev)
+    n_r, n_s = n, n
+    cap = n_s
+    out_r = torch.empty(cap, dtype=torch.int32, device=dev)
+    out_s = torch.empty(cap, dtype=torch.int32, device=dev)
+    d_count = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = hj.workspace(p, n_r, n_s, dev)
+
+    def step():
+        hj.hj_join(p, *t, out_r, out_s, ws, d_count)
+
+    print("bench: PHJ %r, %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr, flush=True)
+    ms = time_steps(step, args.steps, args.warmup, torch)
+    m = int(d_count.item())
+    value = (n_r + n_s) / (ms * 1e-3)
+
+    reps = 5
+    acc = kernel_times(hj, p, t, out_r, out_s, ws, d_count, reps)
+    phases = summarize(acc, reps, n_r, n_s, m)
+    # dominant kernel: most time per join among kernels with an algorithmic byte count
+    dom = max((k for k in phases if "gbs" in phases[k]), key=lambda k: phases[k]["ms_per_join"])
+    dom_bytes = algorithmic_bytes(dom, n_r, n_s, m)
+    dom_ms = phases[dom]["avg_launch_ms"]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    total_bytes = (20.0 * args.passes + 12.0) * (n_r + n_s) + 8.0 * m
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded, generated in HBM)",
+        "config": {
+            "workload": "PHJ 16M x 16M: |R| = |S| = %d int32 (key, rid); R keys a permutation of 1..|R|, "
+                        "S keys uniform over 1..2|R| (~50%% match)" % n,
+            "algo": "phj", "passes": args.passes, "bits": list(bits), "hash": args.hash,
+            "tile": p.tile or 4096, "matches": m,
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms,
+        },
+        "path_gbs": round(total_bytes / (ms * 1e-3) / 1e9, 1),
+        "path_frac": round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels": phases,
+    }
+    if not args.no_shj:
+        ps = hj.params("shj")
+        ws_s = hj.workspace(ps, n_r, n_s, dev)
+        print("bench: SHJ", file=sys.stderr, flush=True)
+        ms_s = time_steps(lambda: hj.hj_join(ps, *t, out_r, out_s, ws_s, d_count), args.steps, args.warmup, torch)
+        m_s = int(d_count.item())
+        acc_s = kernel_times(hj, ps, t, out_r, out_s, ws_s, d_count, reps)
+        result["shj"] = {"value": (n_r + n_s) / (ms_s * 1e-3), "unit": "tuples/s", "ms_per_step": ms_s,
+                         "matches": m_s, "kernels": summarize(acc_s, reps, n_r, n_s, m_s)}
+        del ws_s
+    if args.sweep:
+        sweep = []
+        for passes, bb in [(1, (b,)) for b in range(6, 15)] + [(2, (a, b)) for a in range(3, 8) for b in range(3, 8)]:
+            if sum(bb) < 6 or sum(bb) > 14 or max(bb) > 13:
+                continue
+            q = hj.params("phj", passes, bb, hash=args.hash, tile=args.tile)
+            wq = hj.workspace(q, n_r, n_s, dev)
+            msq = time_steps(lambda: hj.hj_join(q, *t, out_r, out_s, wq, d_count), 5, 2, torch)
+            sweep.append({"passes": passes, "bits": list(bb), "ms": round(msq, 4),
+                          "tuples_per_s": (n_r + n_s) / (msq * 1e-3)})
+            print("bench: sweep %s" % sweep[-1], file=sys.stderr, flush=True)
+            del wq
+        result["sweep"] = sweep
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,153 @@
+/*
+ * hj.h -- C ABI of an MI355X (gfx950) equi hash join library.
+ *
+ * The operation (Section 3.1, "Fine-grained Steps in Hash Joins"): given two
+ * relations R and S of <key, rid> tuples (two 4-byte integers each, Section
+ * 5.1), R the build side and S the probe side, produce every pair
+ * (rid_R, rid_S) whose tuples carry equal keys (Algorithm 1, step p4), and the
+ * number of such pairs.  Two forms are offered, as in the paper:
+ *   HJ_SHJ  simple hash join: build one table over all of R, probe it with S
+ *           (Algorithm 1);
+ *   HJ_PHJ  radix-partitioned hash join: split R and S into 2^B partitions on
+ *           B low bits of the key's hash, in one or two passes, then join each
+ *           partition pair (Algorithm 2, Section 3.1).
+ * The number of passes and the radix bits of each pass are parameters, as the
+ * paper tunes them to the memory hierarchy (Section 3.1).
+ *
+ * Conventions shared by every call:
+ *  - All relation and output buffers are DEVICE pointers owned by the caller;
+ *    the library never allocates device memory.  Scratch space comes from the
+ *    caller's workspace (size from hj_workspace_bytes).
+ *  - Relations are structure-of-arrays: key[n] and rid[n], int32, n < 2^31.
+ *    Any int32 value is a legal key (no sentinel key); duplicates are allowed
+ *    on both sides and produce cnt_R(k) * cnt_S(k) pairs for key k.
+ *  - R is always the build side, even when |R| > |S|; the output columns are
+ *    therefore fixed: rid_r[i] comes from R, rid_s[i] from S.
+ *  - Output order is unspecified; the result is a multiset of pairs.
+ *  - Calls are asynchronous on the given HIP stream (a hipStream_t passed as
+ *    void*, NULL = the null stream) unless named *_sync.  Inputs must stay
+ *    alive and unmodified until the stream has passed the call.  hj_join does
+ *    no host synchronisation and no host<->device copy, so it can be captured
+ *    into a HIP graph.
+ *  - Every call returns an hj_status.  Argument validation happens on the host
+ *    before any launch; on an error nothing is launched and hj_last_error()
+ *    (thread-local) describes the cause.
+ *  - The library holds no global mutable state apart from that thread-local
+ *    message and a per-device attribute cache; concurrent calls on different
+ *    streams with different workspaces are safe.
+ */
+#ifndef HJ_H
+#define HJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hj_status {
+    HJ_OK = 0,
+    HJ_ERR_INVALID = 1,     /* bad argument (NULL buffer with n > 0, bad bits/passes, n >= 2^31) */
+    HJ_ERR_CAPACITY = 2,    /* *_sync only: more pairs than out->capacity; the count is still reported */
+    HJ_ERR_WORKSPACE = 3,   /* ws_bytes below hj_workspace_bytes(), or ws NULL */
+    HJ_ERR_DEVICE = 4,      /* a HIP runtime call failed; see hj_last_error() */
+    HJ_ERR_UNSUPPORTED = 5  /* a parameter combination this build does not implement */
+} hj_status;
+
+typedef enum hj_algo { HJ_SHJ = 0, HJ_PHJ = 1 } hj_algo;
+
+/* Hash applied to a key before its radix bits are taken (Section 3.1 partitions
+   on the low bits of the integer hash value).  The join result does not depend
+   on it; it only changes which partition a tuple lands in. */
+typedef enum hj_hash {
+    HJ_HASH_IDENTITY = 0,   /* the key's own bits */
+    HJ_HASH_MURMUR2 = 1     /* MurmurHash 2.0 of the key's 4 bytes (the paper's choice, Section 5.1) */
+} hj_hash;
+
+/* A relation: `n` tuples, device arrays key[n] and rid[n] (int32). */
+typedef struct hj_rel {
+    const int32_t* key;
+    const int32_t* rid;
+    uint64_t n;
+} hj_rel;
+
+/* The result buffers: device arrays rid_r[capacity] and rid_s[capacity].
+   Pair i is (rid_r[i], rid_s[i]).  When the join has more pairs than
+   `capacity`, no element at or beyond `capacity` is written and the contents
+   of [0, capacity) are unspecified. */
+typedef struct hj_out {
+    int32_t* rid_r;
+    int32_t* rid_s;
+    uint64_t capacity;
+} hj_out;
+
+/* Join parameters.
+   algo    HJ_SHJ or HJ_PHJ.
+   passes  PHJ: number of radix passes, 1 or 2 (ignored by SHJ).
+   bits    PHJ: radix bits of pass 1 and pass 2.  B = bits[0] (+ bits[1] when
+           passes == 2) must be in 1..16 and each used entry in 1..13.  The
+           2^B partitions are the values of the B low bits of the hash; pass 1
+           splits on the high bits[0] of them, pass 2 on the low bits[1].
+   hash    an hj_hash value.
+   tile    tuples per partitioning tile: 0 (default 4096) or a power of two
+           in 1024..8192.
+   lds_cap largest R partition (tuples) joined from an LDS-resident table:
+           0 = chosen from |R| and B; else a multiple of 64 in 256..8192.
+           Larger partitions take the HBM-table path.
+   flags   must be 0. */
+typedef struct hj_params {
+    uint32_t algo;
+    uint32_t passes;
+    uint32_t bits[2];
+    uint32_t hash;
+    uint32_t tile;
+    uint32_t lds_cap;
+    uint32_t flags;
+} hj_params;
+
+/* Fills `p` with the library defaults: PHJ, 2 passes of 6 bits, identity hash. */
+void hj_default_params(hj_params* p);
+
+/* Bytes of device workspace hj_join needs for these parameters and sizes.
+   Returns 0 if the parameters are invalid (hj_last_error() says why). */
+size_t hj_workspace_bytes(const hj_params* p, uint64_t n_r, uint64_t n_s);
+
+/* Joins R and S into `out` (Algorithm 1 for SHJ, Algorithm 2 for PHJ).
+   ws/ws_bytes: device workspace of at least hj_workspace_bytes(p, R->n, S->n)
+   bytes, 256-byte aligned, not used by any other call in flight.
+   d_count: device pointer to one uint64; always receives the total number of
+   pairs, also when it exceeds out->capacity.
+   Asynchronous on `stream`; returns after enqueueing the work. */
+hj_status hj_join(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out,
+                  void* ws, size_t ws_bytes, uint64_t* d_count, void* stream);
+
+/* hj_join followed by a synchronisation of `stream` and a copy of the count
+   into *h_count.  Returns HJ_ERR_CAPACITY when *h_count > out->capacity. */
+hj_status hj_join_sync(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out,
+                       void* ws, size_t ws_bytes, uint64_t* d_count, uint64_t* h_count,
+                       void* stream);
+
+/* Per-kernel timing of one hj_join: each launch is bracketed with HIP events
+   recorded on `stream`; the call synchronises the stream before returning.
+   names[i] (static strings) and ms[i] describe launch i, for at most
+   max_launches launches; *n_launches receives the number of launches made. */
+hj_status hj_join_timed(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out,
+                        void* ws, size_t ws_bytes, uint64_t* d_count, void* stream,
+                        const char** names, float* ms, uint32_t max_launches,
+                        uint32_t* n_launches);
+
+/* Static description of a status code. */
+const char* hj_status_str(hj_status s);
+
+/* Thread-local description of the last error returned on this thread ("" if none). */
+const char* hj_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+uint32_t hj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HJ_H */

@@ -1,0 +1,207 @@
+// Device-side helpers shared by the join kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hj {
+
+constexpr int kWave = 64;
+constexpr uint64_t kEmptySlot = ~0ull;  // empty slot of the HBM hash tables
+
+// MurmurHash 2.0 (32-bit) of one 4-byte block, from Appleby's public description.
+__device__ __forceinline__ uint32_t murmur2(uint32_t k) {
+    const uint32_t m = 0x5bd1e995u;
+    uint32_t h = 0x9747b28cu ^ 4u;
+    k *= m;
+    k ^= k >> 24;
+    k *= m;
+    h *= m;
+    h ^= k;
+    h ^= h >> 13;
+    h *= m;
+    h ^= h >> 15;
+    return h;
+}
+
+// The value whose low bits select the partition (hj_hash).
+__device__ __forceinline__ uint32_t radix_hash(int32_t key, uint32_t kind) {
+    return kind ? murmur2((uint32_t)key) : (uint32_t)key;
+}
+
+// Full-avalanche 32-bit mixer (the MurmurHash3 finaliser) used to place keys in
+// hash tables; independent of the radix bits so a partition's table is uniform.
+__device__ __forceinline__ uint32_t slot_hash(int32_t key) {
+    uint32_t h = (uint32_t)key;
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// ---- Open-addressing tables with per-key rid chains (SHJ and HBM partition tables).
+// A slot holds (key, head): key in the low 32 bits, the head of the key's row
+// chain in the high 32.  kLast in a head/next field marks the chain's last row,
+// so a key seen once costs one slot and no chain read.  The empty slot is all
+// ones: its row field 0x7FFFFFFF can never be a row (n < 2^31 rows).
+constexpr uint32_t kLast = 0x80000000u;
+constexpr uint32_t kNotFound = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint64_t chain_slot(int32_t key, uint32_t head) {
+    return ((uint64_t)head << 32) | (uint32_t)key;
+}
+
+// Inserts `row` under key `k`, probing from slot `s` with `step(s)`.
+template <typename Step>
+__device__ __forceinline__ void chain_insert(uint64_t* table, uint32_t* next, uint64_t s, int32_t k,
+                                             uint32_t row, Step step) {
+    while (true) {
+        uint64_t cur = __hip_atomic_load(&table[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == kEmptySlot) {
+            cur = atomicCAS((unsigned long long*)&table[s], (unsigned long long)kEmptySlot,
+                            (unsigned long long)chain_slot(k, row | kLast));
+            if (cur == kEmptySlot) return;
+        }
+        if ((uint32_t)cur == (uint32_t)k) {
+            // Key present: push the row in front of its chain.
+            while (true) {
+                next[row] = (uint32_t)(cur >> 32);
+                const uint64_t prev = atomicCAS((unsigned long long*)&table[s], (unsigned long long)cur,
+                                                (unsigned long long)chain_slot(k, row));
+                if (prev == cur) return;
+                cur = prev;
+            }
+        }
+        s = step(s);
+    }
+}
+
+// Head field of key `k`'s chain, or kNotFound.
+template <typename Step>
+__device__ __forceinline__ uint32_t chain_find(const uint64_t* __restrict__ table, uint64_t s, int32_t k,
+                                               Step step) {
+    while (true) {
+        const uint64_t e = table[s];
+        if (e == kEmptySlot) return kNotFound;
+        if ((uint32_t)e == (uint32_t)k) return (uint32_t)(e >> 32);
+        s = step(s);
+    }
+}
+
+// Length of the chain starting at head field `h` (h != kNotFound).
+__device__ __forceinline__ uint32_t chain_len(const uint32_t* __restrict__ next, uint32_t h) {
+    uint32_t c = 1;
+    while (!(h & kLast)) {
+        h = next[h];
+        ++c;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Wave-wide inclusive prefix sum (64 lanes).
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T u = __shfl_up(v, d, kWave);
+        if (l >= (uint32_t)d) v += u;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread.  `wave_tot` is LDS scratch
+// of at least blockDim/64 entries.  Returns the exclusive prefix; *total gets
+// the block total.  Contains __syncthreads().
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* wave_tot, T* total) {
+    const uint32_t l = lane_id();
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t nw = blockDim.x / kWave;
+    T incl = wave_incl_scan(v);
+    if (l == kWave - 1) wave_tot[w] = incl;
+    __syncthreads();
+    T before = 0, tot = 0;
+    for (uint32_t i = 0; i < nw; ++i) {
+        T t = wave_tot[i];
+        if (i < w) before += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+// In-place exclusive scan of an LDS array a[0..n) (n a multiple of 64) by the
+// whole block.  `chunk_tot` is LDS scratch of n/64 entries.  Returns the total.
+// Contains __syncthreads() (callers must sync before reading `a`).
+__device__ __forceinline__ uint32_t lds_excl_scan(uint32_t* a, uint32_t n, uint32_t* chunk_tot) {
+    const uint32_t l = lane_id();
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t nw = blockDim.x / kWave;
+    const uint32_t nchunks = n / kWave;
+    for (uint32_t c = w; c < nchunks; c += nw) {
+        uint32_t v = a[c * kWave + l];
+        uint32_t incl = wave_incl_scan(v);
+        a[c * kWave + l] = incl - v;
+        if (l == kWave - 1) chunk_tot[c] = incl;
+    }
+    __syncthreads();
+    // Scan chunk totals with wave 0 (nchunks <= 64 * iterations).
+    __shared__ uint32_t s_total;
+    if (w == 0) {
+        uint32_t carry = 0;
+        for (uint32_t base = 0; base < nchunks; base += kWave) {
+            uint32_t i = base + l;
+            uint32_t v = i < nchunks ? chunk_tot[i] : 0;
+            uint32_t incl = wave_incl_scan(v);
+            if (i < nchunks) chunk_tot[i] = carry + incl - v;
+            carry += __shfl(incl, kWave - 1, kWave);
+        }
+        if (l == 0) s_total = carry;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) a[i] += chunk_tot[i / kWave];
+    uint32_t t = s_total;
+    return t;
+}
+
+// Block index -> work index such that each of the 8 XCDs (which receive blocks
+// round-robin) processes one contiguous range of work indices.  A bijection on
+// [0, grid).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t grid) {
+    constexpr uint32_t kXcd = 8;
+    const uint32_t x = b % kXcd;
+    const uint32_t i = b / kXcd;
+    const uint32_t q = grid / kXcd, r = grid % kXcd;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Largest s in [0, n) with begin[s] <= v, for a nondecreasing begin[0..n].
+template <typename T>
+__device__ __forceinline__ uint32_t upper_index(const T* begin, uint32_t n, T v) {
+    uint32_t lo = 0, hi = n;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (begin[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace hj

@@ -1,0 +1,330 @@
+// Radix partitioning for the partitioned hash join (Algorithm 2, "Partition",
+// steps n1-n3; Section 3.1: passes on the low bits of the integer hash value).
+//
+// A pass works on a list of segments (pass 1: R and S; pass 2: every pass-1
+// partition of R and of S) cut into tiles of `tile` tuples.  Per tile:
+//   hist     n1: partition number of every tuple; the tuples of one wave that
+//            share a partition are found with one ballot per radix bit and
+//            their leader adds the group size to an LDS counter; the tile's
+//            counters go to hist[segment block + p * ntiles + tile].
+//   scan     (scan.hip) exclusive scan of hist: partition-major inside each
+//            segment, so each (partition, tile) run has one global offset.
+//   scatter  n2-n3: the tile is re-read, every tuple gets its rank inside its
+//            partition (leader atomic + popcount of lower group lanes), the
+//            tile is reordered by partition in LDS and written out run by run,
+//            so consecutive lanes store to consecutive addresses.
+// The paper's partition "buckets" with dynamically allocated storage
+// (Section 3.1, Section 3.3) become contiguous partitions at counted offsets.
+#include "hj_device.h"
+#include "hj_internal.h"
+
+namespace hj {
+
+namespace {
+
+constexpr uint32_t kPartBlock = 256;
+
+struct TileLoc {
+    uint32_t seg, tl, nt, start, len;
+};
+
+__device__ __forceinline__ TileLoc locate(const PartSeg* __restrict__ segs,
+                                          const uint32_t* __restrict__ tile_begin, uint32_t nseg,
+                                          uint32_t tile, uint32_t T) {
+    TileLoc t;
+    t.seg = upper_index(tile_begin, nseg, tile);
+    const uint32_t b0 = tile_begin[t.seg];
+    t.tl = tile - b0;
+    t.nt = tile_begin[t.seg + 1] - b0;
+    t.start = t.tl * T;
+    const uint32_t n = segs[t.seg].n;
+    t.len = min(T, n - t.start);
+    return t;
+}
+
+__device__ __forceinline__ uint32_t part_of(int32_t key, const PassCfg& c) {
+    return (radix_hash(key, c.hash_kind) >> c.shift) & ((1u << c.bits) - 1u);
+}
+
+// Lanes of this wave whose `p` equals this lane's (only lanes with `valid`).
+__device__ __forceinline__ uint64_t match_mask(uint32_t p, uint32_t bits, bool valid) {
+    uint64_t m = __ballot(valid);
+    for (uint32_t b = 0; b < bits; ++b) {
+        const bool bit = (p >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        m &= bit ? bal : ~bal;
+    }
+    return valid ? m : 0ull;
+}
+
+template <uint32_t IPT>
+__global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restrict__ segs,
+                                                         const uint32_t* __restrict__ tile_begin,
+                                                         uint32_t nseg, PassCfg cfg,
+                                                         uint32_t* __restrict__ hist) {
+    extern __shared__ uint32_t lds[];
+    constexpr uint32_t T = kPartBlock * IPT;
+    uint32_t* cnt = lds;
+    const uint32_t P = 1u << cfg.bits;
+    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= tile_begin[nseg]) return;
+    const TileLoc t = locate(segs, tile_begin, nseg, tile, T);
+    const PartSeg sg = segs[t.seg];
+    for (uint32_t i = threadIdx.x; i < P; i += kPartBlock) cnt[i] = 0;
+    __syncthreads();
+    const int32_t* __restrict__ kin = sg.key_in + t.start;
+    int32_t keys[IPT];
+#pragma unroll
+    for (uint32_t k = 0; k < IPT; ++k) {
+        const uint32_t idx = k * kPartBlock + threadIdx.x;
+        keys[k] = idx < t.len ? kin[idx] : 0;
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (uint32_t k = 0; k < IPT; ++k) {
+        const uint32_t idx = k * kPartBlock + threadIdx.x;
+        const bool valid = idx < t.len;
+        const uint32_t p = part_of(keys[k], cfg);
+        const uint64_t m = match_mask(p, cfg.bits, valid);
+        if (valid && (m & lt) == 0) atomicAdd(&cnt[p], (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    uint32_t* __restrict__ h = hist + sg.hist_base + t.tl;
+    for (uint32_t p = threadIdx.x; p < P; p += kPartBlock) h[(uint64_t)p * t.nt] = cnt[p];
+}
+
+template <uint32_t IPT>
+__global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __restrict__ segs,
+                                                            const uint32_t* __restrict__ tile_begin,
+                                                            uint32_t nseg, PassCfg cfg,
+                                                            const uint32_t* __restrict__ hist_scan,
+                                                            int32_t* __restrict__ key_out,
+                                                            int32_t* __restrict__ rid_out) {
+    extern __shared__ uint32_t lds[];
+    constexpr uint32_t T = kPartBlock * IPT;
+    const uint32_t P = 1u << cfg.bits;
+    const uint32_t Pp = P < kWave ? kWave : P;  // scan length, a multiple of 64
+    uint32_t* cnt = lds;                         // [Pp]  counts, then local starts
+    uint32_t* delta = cnt + Pp;                  // [P]   global offset - local start
+    uint32_t* ctot = delta + Pp;                 // [Pp/64]
+    int32_t* skey = (int32_t*)(ctot + Pp / kWave);  // [T]
+    int32_t* srid = skey + T;                        // [T]
+
+    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= tile_begin[nseg]) return;
+    const TileLoc t = locate(segs, tile_begin, nseg, tile, T);
+    const PartSeg sg = segs[t.seg];
+    for (uint32_t i = threadIdx.x; i < Pp; i += kPartBlock) cnt[i] = 0;
+    __syncthreads();
+
+    const int32_t* __restrict__ kin = sg.key_in + t.start;
+    const int32_t* __restrict__ rin = sg.rid_in + t.start;
+    int32_t keys[IPT], rids[IPT];
+    uint32_t rank[IPT];
+#pragma unroll
+    for (uint32_t k = 0; k < IPT; ++k) {
+        const uint32_t idx = k * kPartBlock + threadIdx.x;
+        const bool valid = idx < t.len;
+        keys[k] = valid ? kin[idx] : 0;
+        rids[k] = valid ? rin[idx] : 0;
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (uint32_t k = 0; k < IPT; ++k) {
+        const uint32_t idx = k * kPartBlock + threadIdx.x;
+        const bool valid = idx < t.len;
+        const uint32_t p = part_of(keys[k], cfg);
+        const uint64_t m = match_mask(p, cfg.bits, valid);
+        const uint32_t below = (uint32_t)__popcll(m & lt);
+        uint32_t old = 0;
+        if (valid && below == 0) old = atomicAdd(&cnt[p], (uint32_t)__popcll(m));
+        const uint32_t leader = m ? (uint32_t)(__ffsll((long long)m) - 1) : 0u;
+        old = __shfl(old, (int)leader, kWave);
+        rank[k] = old + below;
+    }
+    __syncthreads();
+    lds_excl_scan(cnt, Pp, ctot);
+    __syncthreads();
+    const uint32_t* __restrict__ hs = hist_scan + sg.hist_base;
+    const uint32_t seg0 = hs[0];
+    for (uint32_t p = threadIdx.x; p < P; p += kPartBlock) {
+        const uint32_t rel = hs[(uint64_t)p * t.nt + t.tl] - seg0;  // exact: < segment length
+        delta[p] = rel - cnt[p];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < IPT; ++k) {
+        const uint32_t idx = k * kPartBlock + threadIdx.x;
+        if (idx < t.len) {
+            const uint32_t p = part_of(keys[k], cfg);
+            const uint32_t pos = cnt[p] + rank[k];
+            skey[pos] = keys[k];
+            srid[pos] = rids[k];
+        }
+    }
+    __syncthreads();
+    int32_t* __restrict__ kout = key_out + sg.out_base;
+    int32_t* __restrict__ rout = rid_out + sg.out_base;
+#pragma unroll
+    for (uint32_t k = 0; k < IPT; ++k) {
+        const uint32_t j = k * kPartBlock + threadIdx.x;
+        if (j < t.len) {
+            const int32_t key = skey[j];
+            const uint32_t dst = delta[part_of(key, cfg)] + j;
+            kout[dst] = key;
+            rout[dst] = srid[j];
+        }
+    }
+}
+
+__global__ void k_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, const int32_t* rr,
+                              uint32_t n_r, const int32_t* sk, const int32_t* sr, uint32_t n_s,
+                              uint32_t tile, uint32_t bits) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t nt_r = (n_r + tile - 1) / tile;
+    const uint32_t nt_s = (n_s + tile - 1) / tile;
+    PartSeg a;
+    a.key_in = rk; a.rid_in = rr; a.out_base = 0; a.hist_base = 0; a.n = n_r; a.pad = 0;
+    PartSeg b;
+    b.key_in = sk; b.rid_in = sr; b.out_base = n_r; b.hist_base = (uint64_t)nt_r << bits; b.n = n_s;
+    b.pad = 0;
+    segs[0] = a;
+    segs[1] = b;
+    tile_begin[0] = 0;
+    tile_begin[1] = nt_r;
+    tile_begin[2] = nt_r + nt_s;
+}
+
+constexpr uint32_t kSetupBlock = 1024;
+
+// Start of partition q of a pass-1 segment relative to the segment.
+__device__ __forceinline__ uint32_t seg_part_start(const uint32_t* __restrict__ hs_seg, uint32_t nt,
+                                                   uint32_t q) {
+    return nt ? hs_seg[(uint64_t)q * nt] - hs_seg[0] : 0u;
+}
+
+__global__ void __launch_bounds__(kSetupBlock) k_setup_pass2(
+    const uint32_t* __restrict__ hist1_scan, const uint32_t* __restrict__ tile_begin1, uint32_t bits1,
+    uint32_t n_r, uint32_t n_s, const int32_t* key_in, const int32_t* rid_in, uint32_t tile,
+    uint32_t bits2, PartSeg* __restrict__ segs2, uint32_t* __restrict__ tile_begin2) {
+    __shared__ uint32_t wt[kSetupBlock / kWave];
+    const uint32_t P1 = 1u << bits1;
+    const uint32_t nseg = 2 * P1;
+    const uint32_t per = (nseg + kSetupBlock - 1) / kSetupBlock;
+    const uint32_t a = threadIdx.x * per;
+    const uint32_t b = min(a + per, nseg);
+    const uint32_t nt_r = tile_begin1[1], nt_s = tile_begin1[2] - tile_begin1[1];
+    // pass 1 used hist_base = 0 for R and nt_r << bits1 for S
+    auto seg_range = [&](uint32_t s, uint32_t* off, uint32_t* len, uint32_t* base) {
+        const uint32_t rel = s >= P1;
+        const uint32_t q = s - rel * P1;
+        const uint32_t nt = rel ? nt_s : nt_r;
+        const uint32_t* hs = hist1_scan + (rel ? ((uint64_t)nt_r << bits1) : 0ull);
+        const uint32_t n = rel ? n_s : n_r;
+        const uint32_t st = seg_part_start(hs, nt, q);
+        const uint32_t en = q + 1 < P1 ? seg_part_start(hs, nt, q + 1) : n;
+        *off = st;
+        *len = en - st;
+        *base = rel ? n_r : 0u;
+    };
+    uint32_t ntiles = 0;
+    for (uint32_t s = a; s < b; ++s) {
+        uint32_t off, len, base;
+        seg_range(s, &off, &len, &base);
+        ntiles += (len + tile - 1) / tile;
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(ntiles, wt, &total);
+    for (uint32_t s = a; s < b; ++s) {
+        uint32_t off, len, base;
+        seg_range(s, &off, &len, &base);
+        PartSeg g;
+        g.key_in = key_in + base + off;
+        g.rid_in = rid_in + base + off;
+        g.out_base = (uint64_t)base + off;
+        g.hist_base = (uint64_t)run << bits2;
+        g.n = len;
+        g.pad = 0;
+        segs2[s] = g;
+        tile_begin2[s] = run;
+        run += (len + tile - 1) / tile;
+    }
+    if (threadIdx.x == 0) tile_begin2[nseg] = total;
+}
+
+template <uint32_t IPT>
+void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
+                 const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
+    const size_t lds = sizeof(uint32_t) * ((size_t)1 << cfg.bits);
+    rec.before("part_hist");
+    hipLaunchKernelGGL(k_part_hist<IPT>, dim3(grid), dim3(kPartBlock), lds, rec.stream, segs, tile_begin,
+                       nseg, cfg, hist);
+    rec.after();
+}
+
+template <uint32_t IPT>
+void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
+                    const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out, int32_t* rid_out,
+                    Recorder& rec) {
+    const size_t P = (size_t)1 << cfg.bits;
+    const size_t Pp = P < kWave ? kWave : P;
+    const size_t lds = sizeof(uint32_t) * (2 * Pp + Pp / kWave) + sizeof(int32_t) * 2 * kPartBlock * IPT;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)k_part_scatter<IPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    rec.before("part_scatter");
+    hipLaunchKernelGGL(k_part_scatter<IPT>, dim3(grid), dim3(kPartBlock), lds, rec.stream, segs,
+                       tile_begin, nseg, cfg, hist_scan, key_out, rid_out);
+    rec.after();
+}
+
+}  // namespace
+
+size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile) {
+    const size_t P = (size_t)1 << bits;
+    const size_t Pp = P < kWave ? kWave : P;
+    return sizeof(uint32_t) * (2 * Pp + Pp / kWave) + sizeof(int32_t) * 2 * tile;
+}
+
+void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, const int32_t* rr,
+                      uint32_t n_r, const int32_t* sk, const int32_t* sr, uint32_t n_s, uint32_t tile,
+                      uint32_t bits, Recorder& rec) {
+    rec.before("part_setup1");
+    hipLaunchKernelGGL(k_setup_pass1, dim3(1), dim3(64), 0, rec.stream, segs, tile_begin, rk, rr, n_r,
+                       sk, sr, n_s, tile, bits);
+    rec.after();
+}
+
+void part_setup_pass2(const uint32_t* hist1_scan, const uint32_t* tile_begin1, uint32_t bits1,
+                      uint32_t n_r, uint32_t n_s, const int32_t* key_in, const int32_t* rid_in,
+                      uint32_t tile, uint32_t bits2, PartSeg* segs2, uint32_t* tile_begin2,
+                      Recorder& rec) {
+    rec.before("part_setup2");
+    hipLaunchKernelGGL(k_setup_pass2, dim3(1), dim3(kSetupBlock), 0, rec.stream, hist1_scan,
+                       tile_begin1, bits1, n_r, n_s, key_in, rid_in, tile, bits2, segs2, tile_begin2);
+    rec.after();
+}
+
+void part_hist(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
+               const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
+    if (grid == 0) return;
+    switch (cfg.tile) {
+        case 1024: launch_hist<4>(segs, tile_begin, nseg, grid, cfg, hist, rec); break;
+        case 2048: launch_hist<8>(segs, tile_begin, nseg, grid, cfg, hist, rec); break;
+        case 4096: launch_hist<16>(segs, tile_begin, nseg, grid, cfg, hist, rec); break;
+        default: launch_hist<32>(segs, tile_begin, nseg, grid, cfg, hist, rec); break;
+    }
+}
+
+void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
+                  const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out, int32_t* rid_out,
+                  Recorder& rec) {
+    if (grid == 0) return;
+    switch (cfg.tile) {
+        case 1024: launch_scatter<4>(segs, tile_begin, nseg, grid, cfg, hist_scan, key_out, rid_out, rec); break;
+        case 2048: launch_scatter<8>(segs, tile_begin, nseg, grid, cfg, hist_scan, key_out, rid_out, rec); break;
+        case 4096: launch_scatter<16>(segs, tile_begin, nseg, grid, cfg, hist_scan, key_out, rid_out, rec); break;
+        default: launch_scatter<32>(segs, tile_begin, nseg, grid, cfg, hist_scan, key_out, rid_out, rec); break;
+    }
+}
+
+}  // namespace hj

@@ -67,29 +67,45 @@ def stream_key(seed: int, stream: int) -> int:
     return mix64_int(mix64_int((seed + GAMMA) & MASK64) ^ ((stream * _STREAM_MUL) & MASK64))
 
 
-def draws(seed: int, stream: int, start: int, count: int) -> np.ndarray:
-    """Draws ``start .. start+count-1`` of a stream as uint64."""
+def draws_at(seed: int, stream: int, idx) -> np.ndarray:
+    """Draws number ``idx`` (any uint64 index array) of a stream."""
     key = stream_key(seed, stream)
-    i = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    i = np.asarray(idx, dtype=np.uint64) + np.uint64(1)
     with np.errstate(over="ignore"):
         z = np.uint64(key) + i * np.uint64(GAMMA)
     return mix64(z)
 
 
-def uniform_int(seed: int, stream: int, start: int, count: int, lo: int, m: int) -> np.ndarray:
-    """Integers in ``[lo, lo + m)`` by multiply-shift of the draw's top 32 bits."""
+def draws(seed: int, stream: int, start: int, count: int) -> np.ndarray:
+    """Draws ``start .. start+count-1`` of a stream as uint64."""
+    return draws_at(seed, stream, np.arange(start, start + count, dtype=np.uint64))
+
+
+def _uniform_from(d: np.ndarray, lo: int, m: int) -> np.ndarray:
     if not (1 <= m <= (1 << 32)):
         raise ValueError("range size must be in [1, 2^32]")
-    d = draws(seed, stream, start, count) >> np.uint64(32)
+    d = d >> np.uint64(32)
     with np.errstate(over="ignore"):
         v = (d * np.uint64(m)) >> np.uint64(32)
     return v.astype(np.int64) + lo
 
 
+def uniform_int(seed: int, stream: int, start: int, count: int, lo: int, m: int) -> np.ndarray:
+    """Integers in ``[lo, lo + m)`` by multiply-shift of the draw's top 32 bits."""
+    return _uniform_from(draws(seed, stream, start, count), lo, m)
+
+
+def uniform_int_at(seed: int, stream: int, idx, lo: int, m: int) -> np.ndarray:
+    return _uniform_from(draws_at(seed, stream, idx), lo, m)
+
+
+def _unit_from(d: np.ndarray) -> np.ndarray:
+    return (d >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+
 def unit_float(seed: int, stream: int, start: int, count: int) -> np.ndarray:
     """Floats in ``[0, 1)`` with 53 random bits."""
-    d = draws(seed, stream, start, count) >> np.uint64(11)
-    return d.astype(np.float64) * (1.0 / (1 << 53))
+    return _unit_from(draws(seed, stream, start, count))
 
 
 def _feistel_half_bits(n: int) -> int:
@@ -102,16 +118,19 @@ def feistel_round_keys(seed: int, stream: int) -> list[int]:
     return [mix64_int((key + (r + 1) * GAMMA) & MASK64) for r in range(4)]
 
 
-def permutation(seed: int, stream: int, n: int, start: int = 0, count: int | None = None) -> np.ndarray:
-    """Elements ``start .. start+count-1`` of a pseudo-random permutation of ``[0, n)``."""
-    if count is None:
-        count = n - start
-    if n <= 0 or count <= 0:
+def feistel_half_bits(n: int) -> int:
+    """Half width h of the Feistel domain 2^(2h) used for a permutation of [0, n)."""
+    return _feistel_half_bits(n)
+
+
+def permutation_at(seed: int, stream: int, n: int, idx) -> np.ndarray:
+    """Elements ``idx`` (index array into [0, n)) of a pseudo-random permutation of ``[0, n)``."""
+    x = np.asarray(idx, dtype=np.uint64)
+    if n <= 0 or x.size == 0:
         return np.zeros(0, dtype=np.int64)
     h = _feistel_half_bits(n)
     mask = np.uint64((1 << h) - 1)
     rk = [np.uint64(k) for k in feistel_round_keys(seed, stream)]
-    x = np.arange(start, start + count, dtype=np.uint64)
 
     def enc(v: np.ndarray) -> np.ndarray:
         left = v >> np.uint64(h)
@@ -129,6 +148,15 @@ def permutation(seed: int, stream: int, n: int, start: int = 0, count: int | Non
     return y.astype(np.int64)
 
 
+def permutation(seed: int, stream: int, n: int, start: int = 0, count: int | None = None) -> np.ndarray:
+    """Elements ``start .. start+count-1`` of a pseudo-random permutation of ``[0, n)``."""
+    if count is None:
+        count = n - start
+    if n <= 0 or count <= 0:
+        return np.zeros(0, dtype=np.int64)
+    return permutation_at(seed, stream, n, np.arange(start, start + count, dtype=np.uint64))
+
+
 def zipf_cdf(n: int, theta: float) -> np.ndarray:
     """CDF table of Zipf(theta) over ranks 1..n; the last entry is exactly 1."""
     k = np.arange(1, n + 1, dtype=np.float64)
@@ -139,12 +167,20 @@ def zipf_cdf(n: int, theta: float) -> np.ndarray:
     return cdf
 
 
-def zipf_ranks(seed: int, stream: int, start: int, count: int, cdf: np.ndarray) -> np.ndarray:
-    """Zipf ranks (1-based): the first index whose CDF entry exceeds the variate, plus one."""
-    u = unit_float(seed, stream, start, count)
+def _zipf_from(d: np.ndarray, cdf: np.ndarray) -> np.ndarray:
+    u = _unit_from(d)
     idx = np.searchsorted(cdf, u, side="right")
     np.minimum(idx, len(cdf) - 1, out=idx)
     return idx.astype(np.int64) + 1
+
+
+def zipf_ranks(seed: int, stream: int, start: int, count: int, cdf: np.ndarray) -> np.ndarray:
+    """Zipf ranks (1-based): the first index whose CDF entry exceeds the variate, plus one."""
+    return _zipf_from(draws(seed, stream, start, count), cdf)
+
+
+def zipf_ranks_at(seed: int, stream: int, idx, cdf: np.ndarray) -> np.ndarray:
+    return _zipf_from(draws_at(seed, stream, idx), cdf)
 
 
 # ---------------------------------------------------------------------------

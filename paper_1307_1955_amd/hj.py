@@ -1,0 +1,250 @@
+"""Python binding of ``include/hj.h`` (ctypes; argument marshalling only).
+
+Every function here forwards to ``libhj.so``; no step of the join runs in
+Python and there is no fallback: if the library is missing, loading fails
+loudly.  PyTorch supplies device memory and streams.  ``torch`` is imported
+before the library is loaded so that the library binds to the HIP runtime
+torch already loaded (one runtime per process).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhj.so")
+
+HJ_OK = 0
+HJ_ERR_INVALID = 1
+HJ_ERR_CAPACITY = 2
+HJ_ERR_WORKSPACE = 3
+HJ_ERR_DEVICE = 4
+HJ_ERR_UNSUPPORTED = 5
+
+HJ_SHJ = 0
+HJ_PHJ = 1
+HJ_HASH_IDENTITY = 0
+HJ_HASH_MURMUR2 = 1
+
+# Every symbol include/hj.h declares.
+EXPORTED = (
+    "hj_default_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
+    "hj_status_str", "hj_last_error", "hj_version",
+)
+
+
+class HjRel(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("rid", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+class HjOut(ctypes.Structure):
+    _fields_ = [("rid_r", ctypes.c_void_p), ("rid_s", ctypes.c_void_p), ("capacity", ctypes.c_uint64)]
+
+
+class HjParams(ctypes.Structure):
+    _fields_ = [
+        ("algo", ctypes.c_uint32), ("passes", ctypes.c_uint32), ("bits", ctypes.c_uint32 * 2),
+        ("hash", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("lds_cap", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+    def __repr__(self) -> str:
+        return ("HjParams(algo=%s, passes=%d, bits=(%d, %d), hash=%d, tile=%d, lds_cap=%d)" % (
+            "phj" if self.algo == HJ_PHJ else "shj", self.passes, self.bits[0], self.bits[1],
+            self.hash, self.tile, self.lds_cap))
+
+
+class HJError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (status %d): %s" % (_status_name(status), status, message))
+        self.status = status
+        self.message = message
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads ``libhj.so`` (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise FileNotFoundError(
+                    "%s is missing: build it with `python -m paper_1307_1955_amd.build`" % LIB_PATH)
+            lib = ctypes.CDLL(LIB_PATH)
+            P = ctypes.POINTER
+            vp = ctypes.c_void_p
+            lib.hj_default_params.restype = None
+            lib.hj_default_params.argtypes = [P(HjParams)]
+            lib.hj_workspace_bytes.restype = ctypes.c_size_t
+            lib.hj_workspace_bytes.argtypes = [P(HjParams), ctypes.c_uint64, ctypes.c_uint64]
+            lib.hj_join.restype = ctypes.c_int
+            lib.hj_join.argtypes = [P(HjParams), P(HjRel), P(HjRel), P(HjOut), vp, ctypes.c_size_t, vp, vp]
+            lib.hj_join_sync.restype = ctypes.c_int
+            lib.hj_join_sync.argtypes = [P(HjParams), P(HjRel), P(HjRel), P(HjOut), vp, ctypes.c_size_t, vp,
+                                         P(ctypes.c_uint64), vp]
+            lib.hj_join_timed.restype = ctypes.c_int
+            lib.hj_join_timed.argtypes = [P(HjParams), P(HjRel), P(HjRel), P(HjOut), vp, ctypes.c_size_t, vp,
+                                          vp, P(ctypes.c_char_p), P(ctypes.c_float), ctypes.c_uint32,
+                                          P(ctypes.c_uint32)]
+            lib.hj_status_str.restype = ctypes.c_char_p
+            lib.hj_status_str.argtypes = [ctypes.c_int]
+            lib.hj_last_error.restype = ctypes.c_char_p
+            lib.hj_last_error.argtypes = []
+            lib.hj_version.restype = ctypes.c_uint32
+            lib.hj_version.argtypes = []
+            _lib = lib
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return load().hj_status_str(s).decode()
+    except Exception:
+        return "status"
+
+
+def _check(status: int) -> None:
+    if status != HJ_OK:
+        raise HJError(status, load().hj_last_error().decode())
+
+
+def hj_default_params() -> HjParams:
+    p = HjParams()
+    load().hj_default_params(ctypes.byref(p))
+    return p
+
+
+def params(algo: str = "phj", passes: int = 2, bits=(6, 6), hash: str = "identity", tile: int = 0,
+           lds_cap: int = 0) -> HjParams:
+    """Builds an ``hj_params``.  ``algo`` is "shj" or "phj"; ``hash`` "identity" or "murmur2"."""
+    p = HjParams()
+    p.algo = {"shj": HJ_SHJ, "phj": HJ_PHJ}[algo]
+    p.passes = passes
+    b = tuple(bits) + (0,) * (2 - len(tuple(bits)))
+    p.bits[0], p.bits[1] = int(b[0]), int(b[1])
+    p.hash = {"identity": HJ_HASH_IDENTITY, "murmur2": HJ_HASH_MURMUR2}[hash]
+    p.tile = tile
+    p.lds_cap = lds_cap
+    p.flags = 0
+    return p
+
+
+def hj_workspace_bytes(p: HjParams, n_r: int, n_s: int) -> int:
+    v = load().hj_workspace_bytes(ctypes.byref(p), n_r, n_s)
+    if v == 0:
+        raise HJError(HJ_ERR_INVALID, load().hj_last_error().decode())
+    return int(v)
+
+
+def hj_version() -> int:
+    return int(load().hj_version())
+
+
+def _dev_i32(t: torch.Tensor, name: str) -> int:
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 1:
+        raise ValueError("%s must be a contiguous 1-D int32 CUDA tensor" % name)
+    return t.data_ptr()
+
+
+def _rel(key: torch.Tensor, rid: torch.Tensor, name: str) -> HjRel:
+    if key.numel() != rid.numel():
+        raise ValueError("%s: key and rid lengths differ" % name)
+    return HjRel(_dev_i32(key, name + ".key"), _dev_i32(rid, name + ".rid"), key.numel())
+
+
+def _out(out_r: torch.Tensor, out_s: torch.Tensor) -> HjOut:
+    if out_r.numel() != out_s.numel():
+        raise ValueError("output columns differ in length")
+    return HjOut(_dev_i32(out_r, "out_r"), _dev_i32(out_s, "out_s"), out_r.numel())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ws(ws: torch.Tensor) -> tuple[int, int]:
+    if not ws.is_cuda or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous CUDA tensor")
+    return ws.data_ptr(), ws.numel() * ws.element_size()
+
+
+def workspace(p: HjParams, n_r: int, n_s: int, device="cuda") -> torch.Tensor:
+    """A device workspace tensor of the size hj_workspace_bytes asks for."""
+    nbytes = hj_workspace_bytes(p, n_r, n_s)
+    # torch's allocator returns 512-byte aligned blocks
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def hj_join(p: HjParams, r_key, r_rid, s_key, s_rid, out_r, out_s, ws: torch.Tensor,
+            d_count: torch.Tensor, stream=None) -> None:
+    """Enqueues the join on ``stream`` (torch's current stream by default)."""
+    if d_count.dtype != torch.int64 or not d_count.is_cuda or d_count.numel() < 1:
+        raise ValueError("d_count must be an int64 CUDA tensor with at least one element")
+    R, S, O = _rel(r_key, r_rid, "R"), _rel(s_key, s_rid, "S"), _out(out_r, out_s)
+    wp, wb = _ws(ws)
+    _check(load().hj_join(ctypes.byref(p), ctypes.byref(R), ctypes.byref(S), ctypes.byref(O), wp, wb,
+                          d_count.data_ptr(), _stream(stream)))
+
+
+def hj_join_sync(p: HjParams, r_key, r_rid, s_key, s_rid, out_r, out_s, ws: torch.Tensor,
+                 d_count: torch.Tensor, stream=None, raise_on_capacity: bool = True) -> int:
+    """Joins, synchronises the stream and returns the number of pairs."""
+    if d_count.dtype != torch.int64 or not d_count.is_cuda or d_count.numel() < 1:
+        raise ValueError("d_count must be an int64 CUDA tensor with at least one element")
+    R, S, O = _rel(r_key, r_rid, "R"), _rel(s_key, s_rid, "S"), _out(out_r, out_s)
+    wp, wb = _ws(ws)
+    h = ctypes.c_uint64(0)
+    st = load().hj_join_sync(ctypes.byref(p), ctypes.byref(R), ctypes.byref(S), ctypes.byref(O), wp, wb,
+                             d_count.data_ptr(), ctypes.byref(h), _stream(stream))
+    if st == HJ_ERR_CAPACITY and not raise_on_capacity:
+        return int(h.value)
+    _check(st)
+    return int(h.value)
+
+
+def hj_join_timed(p: HjParams, r_key, r_rid, s_key, s_rid, out_r, out_s, ws: torch.Tensor,
+                  d_count: torch.Tensor, stream=None, max_launches: int = 64) -> list[tuple[str, float]]:
+    """One join with every launch bracketed by HIP events; returns (kernel, ms) per launch."""
+    R, S, O = _rel(r_key, r_rid, "R"), _rel(s_key, s_rid, "S"), _out(out_r, out_s)
+    wp, wb = _ws(ws)
+    names = (ctypes.c_char_p * max_launches)()
+    ms = (ctypes.c_float * max_launches)()
+    n = ctypes.c_uint32(0)
+    _check(load().hj_join_timed(ctypes.byref(p), ctypes.byref(R), ctypes.byref(S), ctypes.byref(O), wp, wb,
+                                d_count.data_ptr(), _stream(stream), names, ms, max_launches,
+                                ctypes.byref(n)))
+    return [(names[i].decode(), float(ms[i])) for i in range(min(n.value, max_launches))]
+
+
+def join(r_key, r_rid, s_key, s_rid, p: HjParams | None = None, capacity: int | None = None,
+         stream=None):
+    """Convenience: allocates workspace and output, joins, and returns
+    ``(rid_r, rid_s, count)`` as CUDA tensors trimmed to ``count``.
+
+    The output is first sized to ``capacity`` (default ``len(S)``, exact when
+    R's keys are unique); if the join has more pairs it is rerun once with an
+    output of the exact size."""
+    if p is None:
+        p = hj_default_params()
+    dev = r_key.device
+    ws = workspace(p, r_key.numel(), s_key.numel(), dev)
+    d_count = torch.zeros(1, dtype=torch.int64, device=dev)
+    cap = s_key.numel() if capacity is None else int(capacity)
+    out_r = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    out_s = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    cnt = hj_join_sync(p, r_key, r_rid, s_key, s_rid, out_r[:cap], out_s[:cap], ws, d_count, stream,
+                       raise_on_capacity=False)
+    if cnt > cap:
+        out_r = torch.empty(cnt, dtype=torch.int32, device=dev)
+        out_s = torch.empty(cnt, dtype=torch.int32, device=dev)
+        cnt2 = hj_join_sync(p, r_key, r_rid, s_key, s_rid, out_r, out_s, ws, d_count, stream)
+        assert cnt2 == cnt
+    return out_r[:cnt], out_s[:cnt], cnt

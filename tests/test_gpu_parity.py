@@ -1,0 +1,256 @@
+"""GPU parity: the HIP join (through the C ABI) against the CPU oracle.
+
+Results are integer pair multisets, so the bar is exact equality of the
+canonical (sorted) forms.  Small cases span many tiles, partitions and work
+items with ragged tails; full-size workloads are checked by closed forms on
+every row plus the oracle on a sample of S rows.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1307_1955_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1307_1955_amd.hj as hj  # noqa: E402
+from paper_1307_1955_amd.gen import device as dgen  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def to_dev(*arrays):
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(DEV) for a in arrays]
+
+
+def gpu_join(p, rk, rr, sk, sr, capacity=None):
+    o_r, o_s, cnt = hj.join(rk, rr, sk, sr, p=p, capacity=capacity)
+    return o_r.cpu().numpy(), o_s.cpu().numpy(), cnt
+
+
+def check_small(p, rk, rr, sk, sr):
+    want_r, want_s = oracle.join(rk, rr, sk, sr)
+    got_r, got_s, cnt = gpu_join(p, *to_dev(rk, rr, sk, sr))
+    assert cnt == len(want_r), (cnt, len(want_r))
+    assert np.array_equal(oracle.canonical(got_r, got_s), oracle.canonical(want_r, want_s))
+
+
+def dup_relations(seed, n_r, n_s, domain):
+    """Keys with duplicates on both sides, negative keys and int32 extremes."""
+    rng = np.random.default_rng(seed)
+    rk = rng.integers(-domain // 2, domain // 2, size=n_r).astype(np.int64)
+    sk = rng.integers(-domain // 2, domain // 2 + domain // 4, size=n_s).astype(np.int64)
+    ext = np.array([-(2 ** 31), 2 ** 31 - 1, 0, -1], dtype=np.int64)
+    rk[: len(ext)] = ext
+    sk[-len(ext):] = ext[::-1]
+    rr = rng.permutation(n_r).astype(np.int32) * 3 + 1
+    sr = rng.permutation(n_s).astype(np.int32) - 5
+    return rk.astype(np.int32), rr, sk.astype(np.int32), sr
+
+
+CASES = [
+    ("shj", dict(algo="shj")),
+    ("phj1_b1", dict(algo="phj", passes=1, bits=(1,))),
+    ("phj1_b4", dict(algo="phj", passes=1, bits=(4,))),
+    ("phj1_b8_t1024", dict(algo="phj", passes=1, bits=(8,), tile=1024)),
+    ("phj1_b13_t8192", dict(algo="phj", passes=1, bits=(13,), tile=8192)),
+    ("phj2_3_3", dict(algo="phj", passes=2, bits=(3, 3))),
+    ("phj2_6_6", dict(algo="phj", passes=2, bits=(6, 6))),
+    ("phj2_7_5_t2048", dict(algo="phj", passes=2, bits=(7, 5), tile=2048)),
+    ("phj2_8_8", dict(algo="phj", passes=2, bits=(8, 8))),
+    ("phj2_6_6_murmur", dict(algo="phj", passes=2, bits=(6, 6), hash="murmur2")),
+    ("phj1_10_murmur", dict(algo="phj", passes=1, bits=(10,), hash="murmur2")),
+    ("phj2_2_2_ldscap256", dict(algo="phj", passes=2, bits=(2, 2), lds_cap=256)),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_small_duplicates(name, kw):
+    rk, rr, sk, sr = dup_relations(1, 20011, 50021, 12000)
+    check_small(hj.params(**kw), rk, rr, sk, sr)
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_small_unique_ragged(name, kw):
+    r, s = gen.unique_uniform(5, 77777, 100003, 120000)
+    check_small(hj.params(**kw), r.key, r.rid, s.key, s.rid)
+
+
+@pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="phj", passes=2, bits=(6, 6)),
+                                dict(algo="phj", passes=1, bits=(5,))])
+def test_empty_and_tiny(kw):
+    p = hj.params(**kw)
+    e = np.zeros(0, dtype=np.int32)
+    one = np.array([42], dtype=np.int32)
+    for rk, sk in [(e, e), (e, one), (one, e), (one, one), (one, -one)]:
+        check_small(p, rk, np.arange(len(rk)), sk, np.arange(len(sk)) + 9)
+
+
+@pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="phj", passes=2, bits=(5, 5)),
+                                dict(algo="phj", passes=2, bits=(5, 5), lds_cap=256)])
+def test_cartesian_all_equal(kw):
+    rk = np.full(300, 77, dtype=np.int32)
+    sk = np.full(700, 77, dtype=np.int32)
+    check_small(hj.params(**kw), rk, np.arange(300), sk, np.arange(700))
+
+
+@pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="phj", passes=2, bits=(6, 6)),
+                                dict(algo="phj", passes=1, bits=(8,), hash="murmur2")])
+def test_r_side_skew(kw):
+    """10% of R shares one key (a heavy partition that overflows the LDS budget)."""
+    n_r, n_s = 1 << 17, 1 << 18
+    r, s = gen.unique_uniform(8, n_r, n_s, 2 * n_r)
+    rk = r.key.copy()
+    rng = np.random.default_rng(3)
+    rk[rng.choice(n_r, n_r // 10, replace=False)] = 12345
+    sk = s.key.copy()
+    sk[:50] = 12345
+    check_small(hj.params(**kw), rk, r.rid, sk, s.rid)
+
+
+@pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="phj", passes=2, bits=(6, 6)),
+                                dict(algo="phj", passes=1, bits=(3,))])
+def test_capacity_guard(kw):
+    """Too small an output: the full count is reported, nothing is written past capacity."""
+    p = hj.params(**kw)
+    r, s = gen.unique_uniform(9, 30000, 60000, 40000)
+    rk, rr, sk, sr = to_dev(r.key, r.rid, s.key, s.rid)
+    want = oracle.join_count(r.key, r.rid, s.key)
+    cap = want // 3
+    buf_r = torch.full((want,), -7, dtype=torch.int32, device=DEV)
+    buf_s = torch.full((want,), -7, dtype=torch.int32, device=DEV)
+    ws = hj.workspace(p, len(r), len(s))
+    d_count = torch.zeros(1, dtype=torch.int64, device=DEV)
+    with pytest.raises(hj.HJError) as e:
+        hj.hj_join_sync(p, rk, rr, sk, sr, buf_r[:cap], buf_s[:cap], ws, d_count)
+    assert e.value.status == hj.HJ_ERR_CAPACITY
+    assert int(d_count.item()) == want
+    assert torch.all(buf_r[cap:] == -7) and torch.all(buf_s[cap:] == -7)
+    # the asynchronous call reports the count in device memory as well
+    d_count.zero_()
+    hj.hj_join(p, rk, rr, sk, sr, buf_r[:0], buf_s[:0], ws, d_count)
+    torch.cuda.synchronize()
+    assert int(d_count.item()) == want
+
+
+def test_repeatable_and_timed():
+    p = hj.params("phj", 2, (6, 6))
+    r, s = gen.unique_uniform(4, 1 << 16, 1 << 17, 1 << 17)
+    t = to_dev(r.key, r.rid, s.key, s.rid)
+    a = gen_canon(p, t)
+    b = gen_canon(p, t)
+    assert np.array_equal(a, b)
+    out_r = torch.empty(len(s), dtype=torch.int32, device=DEV)
+    out_s = torch.empty(len(s), dtype=torch.int32, device=DEV)
+    ws = hj.workspace(p, len(r), len(s))
+    d_count = torch.zeros(1, dtype=torch.int64, device=DEV)
+    launches = hj.hj_join_timed(p, *t, out_r, out_s, ws, d_count)
+    names = [n for n, _ in launches]
+    assert "part_scatter" in names and "join_write" in names
+    assert all(ms >= 0 for _, ms in launches)
+    cnt = int(d_count.item())
+    assert np.array_equal(oracle.canonical(out_r[:cnt].cpu().numpy(), out_s[:cnt].cpu().numpy()), a)
+
+
+def gen_canon(p, t):
+    o_r, o_s, cnt = hj.join(*t, p=p)
+    return oracle.canonical(o_r.cpu().numpy(), o_s.cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# Device generator == host generator (so device-made inputs are the generator's)
+# ---------------------------------------------------------------------------
+
+
+def test_device_generator_matches_host():
+    rng = np.random.default_rng(0)
+    n = (1 << 20) + 17
+    idx = rng.integers(0, n, size=5000)
+    pk = dgen.perm_keys(3, 1, n).cpu().numpy()
+    assert np.array_equal(pk[idx], gen.permutation_at(3, 1, n, idx) + 1)
+    assert np.array_equal(np.sort(pk), np.arange(1, n + 1))
+    uk = dgen.uniform_keys(3, 2, n, 999983).cpu().numpy()
+    assert np.array_equal(uk[idx], gen.uniform_int_at(3, 2, idx, 1, 999983))
+    cdf = gen.zipf_cdf(1 << 16, 1.0)
+    zk = dgen.zipf_keys(3, 2, n, torch.from_numpy(cdf).to(DEV)).cpu().numpy()
+    assert np.array_equal(zk[idx], gen.zipf_ranks_at(3, 2, idx, cdf))
+    r_host, s_host = gen.config_c1(seed=1, n=1 << 16)
+    rk, rr, sk, sr = dgen.config_c1(seed=1, n=1 << 16)
+    assert np.array_equal(rk.cpu().numpy(), r_host.key) and np.array_equal(sk.cpu().numpy(), s_host.key)
+    assert np.array_equal(rr.cpu().numpy(), r_host.rid) and np.array_equal(sr.cpu().numpy(), s_host.rid)
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads
+# ---------------------------------------------------------------------------
+
+
+def closed_form_unique(r_key, s_key):
+    n = len(r_key)
+    inv = np.empty(n + 1, dtype=np.int64)
+    inv[r_key.astype(np.int64)] = np.arange(n)
+    m = np.full(len(s_key), -1, dtype=np.int64)
+    hit = s_key.astype(np.int64) <= n
+    m[hit] = inv[s_key[hit].astype(np.int64)]
+    return m
+
+
+def check_full(p, rk, rr, sk, sr, seed, sample=1 << 16):
+    """Every row against the closed form; a sample of S rows against the oracle;
+    sampled rows of the device-made input against the host generator."""
+    o_r, o_s, cnt = hj.join(rk, rr, sk, sr, p=p)
+    r_key, s_key = rk.cpu().numpy(), sk.cpu().numpy()
+    m = oracle.match_of(o_r.cpu().numpy(), o_s.cpu().numpy(), len(s_key))
+    expect = closed_form_unique(r_key, s_key)
+    assert cnt == int(np.sum(expect >= 0))
+    assert np.array_equal(m, expect)
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(len(s_key), size=min(sample, len(s_key)), replace=False))
+    w_r, w_s = oracle.join(r_key, np.arange(len(r_key)), s_key[rows], rows)
+    got = np.stack([m[rows], rows], axis=1)
+    got = got[got[:, 0] >= 0]
+    assert np.array_equal(oracle.canonical(got[:, 0], got[:, 1]), oracle.canonical(w_r, w_s))
+    return r_key, s_key, rows
+
+
+C1_C2_PARAMS = [
+    ("shj", dict(algo="shj")),
+    ("phj2_6_6", dict(algo="phj", passes=2, bits=(6, 6))),
+    ("phj1_12", dict(algo="phj", passes=1, bits=(12,))),
+    ("phj2_7_6_murmur", dict(algo="phj", passes=2, bits=(7, 6), hash="murmur2")),
+]
+
+
+@pytest.mark.parametrize("name,kw", C1_C2_PARAMS, ids=[c[0] for c in C1_C2_PARAMS])
+def test_c1_full_vs_oracle(name, kw):
+    """1M x 1M, every S tuple matches once: compared in full with the oracle."""
+    r, s = gen.config_c1()
+    want = oracle.match_of(*oracle.join(r.key, r.rid, s.key, s.rid), len(s))
+    o_r, o_s, cnt = hj.join(*to_dev(r.key, r.rid, s.key, s.rid), p=hj.params(**kw))
+    assert cnt == 1 << 20
+    assert np.array_equal(oracle.match_of(o_r.cpu().numpy(), o_s.cpu().numpy(), len(s)), want)
+
+
+@pytest.mark.parametrize("name,kw", C1_C2_PARAMS, ids=[c[0] for c in C1_C2_PARAMS])
+def test_c2_full(name, kw):
+    """16M x 16M, about half of S matches."""
+    rk, rr, sk, sr = dgen.config_c2()
+    r_key, s_key, rows = check_full(hj.params(**kw), rk, rr, sk, sr, seed=2)
+    assert np.array_equal(r_key[rows[:1000] % len(r_key)],
+                          gen.permutation_at(2, gen.STREAM_R_KEYS, 1 << 24, rows[:1000] % len(r_key)) + 1)
+    assert np.array_equal(s_key[rows], gen.uniform_int_at(2, gen.STREAM_S_KEYS, rows, 1, 1 << 25))
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+@pytest.mark.parametrize("kw", [dict(algo="phj", passes=2, bits=(6, 6)), dict(algo="shj")],
+                         ids=["phj2_6_6", "shj"])
+def test_c3_zipf_full(theta, kw):
+    """16M R, 64M Zipf S: every S tuple matches; heavy hitters split over many work items."""
+    rk, rr, sk, sr = dgen.config_c3(theta=theta)
+    r_key, s_key, rows = check_full(hj.params(**kw), rk, rr, sk, sr, seed=3)
+    cdf = gen.zipf_cdf(1 << 24, theta)
+    assert np.array_equal(s_key[rows[:2000]], gen.zipf_ranks_at(3, gen.STREAM_S_KEYS, rows[:2000], cdf))
