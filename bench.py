@@ -35,9 +35,12 @@ def parse():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--hash", type=str, default="identity", choices=["identity", "murmur2"])
     ap.add_argument("--n", type=int, default=1 << 24, help="|R| = |S| (default 2^24)")
+    ap.add_argument("--one-pass", action="store_true", help="PHJ with the one-pass output (HJ_FLAG_ONE_PASS)")
     ap.add_argument("--no-shj", action="store_true", help="skip the SHJ line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="also time every radix configuration")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -49,9 +52,11 @@ def algorithmic_bytes(name: str, n_r: int, n_s: int, m: int) -> float | None:
         "part_scatter": 16.0 * n,        # read key+rid, write key+rid
         "join_count": 4.0 * n,           # read R_i and S_i keys
         "join_write": 8.0 * n + 8.0 * m,  # read key+rid of R_i and S_i, write the pairs
+        "join_write_1pass": 8.0 * n + 8.0 * m,
         "shj_build": 4.0 * n_r,          # read R keys (table traffic is random, counted separately)
         "shj_count": 4.0 * n_s,
         "shj_write": 8.0 * n_s + 8.0 * m,
+        "shj_write_1pass": 8.0 * n_s + 8.0 * m,
     }.get(name)
 
 
@@ -114,13 +119,23 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        x = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+        return
+
     import paper_1307_1955_amd.hj as hj
     from paper_1307_1955_amd.gen import device as dgen
 
     dev = torch.device("cuda:0")
     n = args.n
     bits = tuple(int(b) for b in args.bits.split(","))
-    p = hj.params("phj", args.passes, bits, hash=args.hash, tile=args.tile)
+    p = hj.params("phj", args.passes, bits, hash=args.hash, tile=args.tile, one_pass=args.one_pass)
     print("bench: generating 16M x 16M inputs on the device", file=sys.stderr, flush=True)
     t = dgen.config_c2(n=n, device=dev)
     n_r, n_s = n, n
@@ -146,7 +161,8 @@ def main():
     dom_bytes = algorithmic_bytes(dom, n_r, n_s, m)
     dom_ms = phases[dom]["avg_launch_ms"]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    total_bytes = (20.0 * args.passes + 12.0) * (n_r + n_s) + 8.0 * m
+    # partition passes 20 B/tuple each; join: count pass 4 B/tuple (two-pass output only) + write pass 8 B/tuple
+    total_bytes = (20.0 * args.passes + (8.0 if args.one_pass else 12.0)) * (n_r + n_s) + 8.0 * m
     result = {
         "metric": METRIC,
         "value": value,
@@ -164,7 +180,7 @@ def main():
             "workload": "PHJ 16M x 16M: |R| = |S| = %d int32 (key, rid); R keys a permutation of 1..|R|, "
                         "S keys uniform over 1..2|R| (~50%% match)" % n,
             "algo": "phj", "passes": args.passes, "bits": list(bits), "hash": args.hash,
-            "tile": p.tile or 4096, "matches": m,
+            "tile": p.tile or 4096, "one_pass_output": bool(args.one_pass), "matches": m,
         },
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -176,7 +192,7 @@ def main():
         "kernels": phases,
     }
     if not args.no_shj:
-        ps = hj.params("shj")
+        ps = hj.params("shj", one_pass=args.one_pass)
         ws_s = hj.workspace(ps, n_r, n_s, dev)
         print("bench: SHJ", file=sys.stderr, flush=True)
         ms_s = time_steps(lambda: hj.hj_join(ps, *t, out_r, out_s, ws_s, d_count), args.steps, args.warmup, torch)
@@ -187,16 +203,19 @@ def main():
         del ws_s
     if args.sweep:
         sweep = []
-        for passes, bb in [(1, (b,)) for b in range(6, 15)] + [(2, (a, b)) for a in range(3, 8) for b in range(3, 8)]:
-            if sum(bb) < 6 or sum(bb) > 14 or max(bb) > 13:
-                continue
-            q = hj.params("phj", passes, bb, hash=args.hash, tile=args.tile)
-            wq = hj.workspace(q, n_r, n_s, dev)
-            msq = time_steps(lambda: hj.hj_join(q, *t, out_r, out_s, wq, d_count), 5, 2, torch)
-            sweep.append({"passes": passes, "bits": list(bb), "ms": round(msq, 4),
-                          "tuples_per_s": (n_r + n_s) / (msq * 1e-3)})
-            print("bench: sweep %s" % sweep[-1], file=sys.stderr, flush=True)
-            del wq
+        configs = [(1, (b,)) for b in range(8, 15)] + [(2, (a, b)) for a in range(4, 9) for b in range(4, 9)]
+        for one in (False, True):
+            for passes, bb in configs:
+                if sum(bb) < 8 or sum(bb) > 14 or max(bb) > 13:
+                    continue
+                for tile in (0, 8192) if passes == 1 else (0,):
+                    q = hj.params("phj", passes, bb, hash=args.hash, tile=tile, one_pass=one)
+                    wq = hj.workspace(q, n_r, n_s, dev)
+                    msq = time_steps(lambda: hj.hj_join(q, *t, out_r, out_s, wq, d_count), 5, 2, torch)
+                    sweep.append({"passes": passes, "bits": list(bb), "tile": tile or 4096, "one_pass": one,
+                                  "ms": round(msq, 4), "tuples_per_s": (n_r + n_s) / (msq * 1e-3)})
+                    print("bench: sweep %s" % sweep[-1], file=sys.stderr, flush=True)
+                    del wq
         result["sweep"] = sweep
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)

@@ -82,6 +82,13 @@ typedef struct hj_out {
     uint64_t capacity;
 } hj_out;
 
+/* Output in one pass: each workgroup counts its pairs, reserves that many
+   output slots with one atomic add on the running total, then writes them
+   (Section 3.3's block allocator, one block per workgroup), instead of a count
+   pass, a scan and a write pass.  Same multiset of pairs.  Applies to SHJ and
+   PHJ. */
+#define HJ_FLAG_ONE_PASS 1u
+
 /* Join parameters.
    algo    HJ_SHJ or HJ_PHJ.
    passes  PHJ: number of radix passes, 1 or 2 (ignored by SHJ).
@@ -95,7 +102,7 @@ typedef struct hj_out {
    lds_cap largest R partition (tuples) joined from an LDS-resident table:
            0 = chosen from |R| and B; else a multiple of 64 in 256..8192.
            Larger partitions take the HBM-table path.
-   flags   must be 0. */
+   flags   0 or HJ_FLAG_ONE_PASS. */
 typedef struct hj_params {
     uint32_t algo;
     uint32_t passes;

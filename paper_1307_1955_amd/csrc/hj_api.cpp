@@ -62,13 +62,13 @@ struct Carver {
 };
 
 struct Plan {
-    bool phj;
+    bool phj, one_pass;
     uint32_t passes, b1, b2, B, P1, P2, P, tile, hash, lds_cap;
 };
 
 hj_status check_params(const hj_params* p, uint64_t n_r, Plan* pl) {
     if (!p) return fail(HJ_ERR_INVALID, "params is NULL");
-    if (p->flags != 0) return fail(HJ_ERR_INVALID, "flags must be 0");
+    if (p->flags & ~HJ_FLAG_ONE_PASS) return fail(HJ_ERR_INVALID, "unknown flags 0x%x", p->flags);
     if (p->algo != HJ_SHJ && p->algo != HJ_PHJ) return fail(HJ_ERR_INVALID, "unknown algo %u", p->algo);
     if (p->hash != HJ_HASH_IDENTITY && p->hash != HJ_HASH_MURMUR2)
         return fail(HJ_ERR_INVALID, "unknown hash %u", p->hash);
@@ -76,6 +76,7 @@ hj_status check_params(const hj_params* p, uint64_t n_r, Plan* pl) {
     if (tile != 1024 && tile != 2048 && tile != 4096 && tile != 8192)
         return fail(HJ_ERR_INVALID, "tile must be 0 or a power of two in 1024..8192 (got %u)", p->tile);
     pl->phj = p->algo == HJ_PHJ;
+    pl->one_pass = (p->flags & HJ_FLAG_ONE_PASS) != 0;
     pl->tile = tile;
     pl->hash = p->hash;
     pl->passes = 0;
@@ -118,11 +119,14 @@ struct PhjWs {
     int32_t *keyA, *ridA;
     hj::PartSeg* segs2;
     uint32_t* tb2;
+    uint32_t* tseg2;
     uint32_t* hist2;
     int32_t *keyB, *ridB;
     hj::PartPair* pairs;
     uint32_t* item_begin;
     uint32_t* ovf_begin;
+    uint32_t* item_part;
+    uint32_t* ovf_part;
     uint64_t* wave_cnt;
     uint64_t* ovf_table;
     uint32_t* ovf_next;
@@ -147,6 +151,7 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, void* base) {
         w.tiles2_ub = cdiv(n, pl.tile) + 2ull * pl.P1;
         w.segs2 = c.take<hj::PartSeg>(2ull * pl.P1);
         w.tb2 = c.take<uint32_t>(2ull * pl.P1 + 1);
+        w.tseg2 = c.take<uint32_t>(w.tiles2_ub);
         w.hist2 = c.take<uint32_t>(w.tiles2_ub * pl.P2);
         w.keyB = c.take<int32_t>(n);
         w.ridB = c.take<int32_t>(n);
@@ -157,6 +162,8 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, void* base) {
     w.ovf_begin = c.take<uint32_t>(pl.P + 1ull);
     w.items_ub = hj::join_grid(pl.P, n_s);
     w.ovf_ub = hj::ovf_grid(pl.P, n_r);
+    w.item_part = c.take<uint32_t>(w.items_ub);
+    w.ovf_part = c.take<uint32_t>(w.ovf_ub);
     w.wave_cnt = c.take<uint64_t>(w.items_ub * hj::kJoinWaves);
     w.ovf_table = c.take<uint64_t>(2 * n_r);
     w.ovf_next = c.take<uint32_t>(n_r);
@@ -212,15 +219,17 @@ hj_status check_call(const hj_params* p, const hj_rel* R, const hj_rel* S, const
     return HJ_OK;
 }
 
-void run_shj(const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws, uint64_t* d_count,
-             hj::Recorder& rec) {
+void run_shj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
+             uint64_t* d_count, hj::Recorder& rec) {
     ShjWs w = shj_layout(R.n, S.n, ws);
-    hj::shj_fill(w.table, 1ull << w.log2_slots, rec);
+    hj::shj_fill(w.table, 1ull << w.log2_slots, pl.one_pass ? d_count : nullptr, rec);
     hj::shj_build(R.key, R.n, w.table, w.next, w.log2_slots, rec);
-    hj::shj_count(S.key, S.n, w.table, w.next, w.log2_slots, w.wave_cnt, rec);
-    hj::scan_u64(w.wave_cnt, w.wave_cnt, w.tiles * hj::kShjWavesPerBlock, w.part64, d_count, rec);
-    hj::shj_write(S.key, S.rid, S.n, w.table, w.next, w.log2_slots, R.rid, w.wave_cnt, out.rid_r,
-                  out.rid_s, out.capacity, rec);
+    if (!pl.one_pass) {
+        hj::shj_count(S.key, S.n, w.table, w.next, w.log2_slots, w.wave_cnt, rec);
+        hj::scan_u64(w.wave_cnt, w.wave_cnt, w.tiles * hj::kShjWavesPerBlock, w.part64, d_count, rec);
+    }
+    hj::shj_write(S.key, S.rid, S.n, w.table, w.next, w.log2_slots, R.rid, pl.one_pass ? nullptr : w.wave_cnt,
+                  d_count, out.rid_r, out.rid_s, out.capacity, rec);
 }
 
 void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
@@ -229,9 +238,9 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
     const uint32_t n_r = (uint32_t)R.n, n_s = (uint32_t)S.n;
     hj::part_setup_pass1(w.segs1, w.tb1, R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, rec);
     hj::PassCfg c1{pl.b2, pl.b1, pl.hash, pl.tile};
-    hj::part_hist(w.segs1, w.tb1, 2, (uint32_t)w.tiles1, c1, w.hist1, rec);
+    hj::part_hist(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, rec);
     hj::scan_u32(w.hist1, w.hist1, w.tiles1 * pl.P1, w.part32, nullptr, rec);
-    hj::part_scatter(w.segs1, w.tb1, 2, (uint32_t)w.tiles1, c1, w.hist1, w.keyA, w.ridA, rec);
+    hj::part_scatter(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, w.keyA, w.ridA, rec);
     const hj::PartSeg* segs = w.segs1;
     const uint32_t* tb = w.tb1;
     uint32_t nseg = 2, bits_last = pl.b1;
@@ -239,12 +248,12 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
     int32_t *fk = w.keyA, *fr = w.ridA;
     if (pl.passes == 2) {
         hj::part_setup_pass2(w.hist1, w.tb1, pl.b1, n_r, n_s, w.keyA, w.ridA, pl.tile, pl.b2, w.segs2,
-                             w.tb2, rec);
+                             w.tb2, w.tseg2, rec);
         hj::PassCfg c2{0, pl.b2, pl.hash, pl.tile};
-        hj::part_hist(w.segs2, w.tb2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, rec);
+        hj::part_hist(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, rec);
         hj::scan_u32(w.hist2, w.hist2, w.tiles2_ub * pl.P2, w.part32, nullptr, rec);
-        hj::part_scatter(w.segs2, w.tb2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, w.keyB, w.ridB,
-                         rec);
+        hj::part_scatter(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, w.keyB,
+                         w.ridB, rec);
         segs = w.segs2;
         tb = w.tb2;
         nseg = 2 * pl.P1;
@@ -253,15 +262,19 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
         fk = w.keyB;
         fr = w.ridB;
     }
-    hj::JoinPlanOut po{w.pairs, w.item_begin, w.ovf_begin};
-    hj::join_plan(segs, tb, nseg, bits_last, hist_last, n_r, n_s, pl.B, pl.lds_cap, po, rec);
-    hj::join_ovf_build(w.pairs, w.ovf_begin, pl.P, (uint32_t)w.ovf_ub, fk, w.ovf_table, w.ovf_next, rec);
-    hj::join_count(w.pairs, w.item_begin, pl.P, (uint32_t)w.items_ub, fk, fk + n_r, pl.lds_cap,
-                   w.ovf_table, w.ovf_next, w.wave_cnt, rec);
-    hj::scan_u64(w.wave_cnt, w.wave_cnt, w.items_ub * hj::kJoinWaves, w.part64, d_count, rec);
-    hj::join_write(w.pairs, w.item_begin, pl.P, (uint32_t)w.items_ub, fk, fr, fk + n_r, fr + n_r,
-                   pl.lds_cap, w.ovf_table, w.ovf_next, w.wave_cnt, out.rid_r, out.rid_s, out.capacity,
-                   rec);
+    hj::JoinPlanOut po{w.pairs, w.item_begin, w.ovf_begin, w.item_part, w.ovf_part};
+    hj::join_plan(segs, tb, nseg, bits_last, hist_last, n_r, n_s, pl.B, pl.lds_cap, po,
+                  pl.one_pass ? d_count : nullptr, rec);
+    hj::join_ovf_build(w.pairs, w.ovf_begin, w.ovf_part, pl.P, (uint32_t)w.ovf_ub, fk, w.ovf_table, w.ovf_next,
+                       rec);
+    if (!pl.one_pass) {
+        hj::join_count(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, fk, fk + n_r, pl.lds_cap,
+                       w.ovf_table, w.ovf_next, w.wave_cnt, rec);
+        hj::scan_u64(w.wave_cnt, w.wave_cnt, w.items_ub * hj::kJoinWaves, w.part64, d_count, rec);
+    }
+    hj::join_write(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, fk, fr, fk + n_r, fr + n_r,
+                   pl.lds_cap, w.ovf_table, w.ovf_next, pl.one_pass ? nullptr : w.wave_cnt, d_count,
+                   out.rid_r, out.rid_s, out.capacity, rec);
 }
 
 hj_status launch_join(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,
@@ -275,7 +288,7 @@ hj_status launch_join(const hj_params* p, const hj_rel* R, const hj_rel* S, cons
     } else if (pl.phj) {
         run_phj(pl, *R, *S, *out, ws, d_count, rec);
     } else {
-        run_shj(*R, *S, *out, ws, d_count, rec);
+        run_shj(pl, *R, *S, *out, ws, d_count, rec);
     }
     if (rec.err != hipSuccess)
         return fail(HJ_ERR_DEVICE, "launch failed: %s", hipGetErrorString(rec.err));

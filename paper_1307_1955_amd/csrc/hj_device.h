@@ -58,6 +58,8 @@ template <typename Step>
 __device__ __forceinline__ void chain_insert(uint64_t* table, uint32_t* next, uint64_t s, int32_t k,
                                              uint32_t row, Step step) {
     while (true) {
+        // Read first and CAS only a free slot (faster on MI355X than an
+        // unconditional CAS: the read brings the line in, the CAS then hits it).
         uint64_t cur = __hip_atomic_load(&table[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == kEmptySlot) {
             cur = atomicCAS((unsigned long long*)&table[s], (unsigned long long)kEmptySlot,
@@ -107,7 +109,8 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Wave-wide inclusive prefix sum (64 lanes).
+// Wave-wide inclusive prefix sum (64 lanes) through LDS-crossbar shuffles;
+// used for 64-bit values.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
     const uint32_t l = lane_id();
@@ -119,11 +122,47 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     return v;
 }
 
+// 32-bit specialisation without LDS traffic: DPP row shifts (row_shr 1, 2, 4, 8)
+// give inclusive sums inside each row of 16 lanes; the row totals (lanes 15,
+// 31, 47) are then read into scalar registers and added to the later rows.
+template <>
+__device__ __forceinline__ uint32_t wave_incl_scan<uint32_t>(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+    const uint32_t l = lane_id();
+    v += (l >= 16 ? r0 : 0u) + (l >= 32 ? r1 : 0u) + (l >= 48 ? r2 : 0u);
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
     return v;
+}
+
+// Exclusive prefix and total over the wave of per-lane pair counts `c`.
+// Fast paths: every count 0 or 1 (unique build keys) -> ballot + popcount;
+// small counts -> 32-bit DPP scan; otherwise a 64-bit shuffle scan.
+__device__ __forceinline__ void wave_offsets(uint32_t c, uint64_t* excl, uint64_t* total) {
+    if (__ballot(c > 1) == 0) {
+        const uint64_t m = __ballot(c != 0);
+        *excl = (uint64_t)__popcll(m & lanemask_lt());
+        *total = (uint64_t)__popcll(m);
+    } else if (__ballot(c >= (1u << 25)) == 0) {
+        const uint32_t incl = wave_incl_scan(c);
+        *excl = incl - c;
+        *total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    } else {
+        const uint64_t incl = wave_incl_scan((uint64_t)c);
+        *excl = incl - c;
+        *total = __shfl(incl, kWave - 1, kWave);
+    }
 }
 
 // Block-wide exclusive scan of one value per thread.  `wave_tot` is LDS scratch
@@ -149,38 +188,39 @@ __device__ __forceinline__ T block_excl_scan(T v, T* wave_tot, T* total) {
 }
 
 // In-place exclusive scan of an LDS array a[0..n) (n a multiple of 64) by the
-// whole block.  `chunk_tot` is LDS scratch of n/64 entries.  Returns the total.
-// Contains __syncthreads() (callers must sync before reading `a`).
-__device__ __forceinline__ uint32_t lds_excl_scan(uint32_t* a, uint32_t n, uint32_t* chunk_tot) {
+// whole block.  Wave w scans a contiguous run of 64-element chunks with a
+// running carry; `wave_tot` (LDS, >= blockDim/64 entries) then carries the
+// wave totals across waves.  Returns the total.  Contains __syncthreads()
+// (callers must sync before reading `a`).
+__device__ __forceinline__ uint32_t lds_excl_scan(uint32_t* a, uint32_t n, uint32_t* wave_tot) {
     const uint32_t l = lane_id();
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t nw = blockDim.x / kWave;
     const uint32_t nchunks = n / kWave;
-    for (uint32_t c = w; c < nchunks; c += nw) {
-        uint32_t v = a[c * kWave + l];
-        uint32_t incl = wave_incl_scan(v);
-        a[c * kWave + l] = incl - v;
-        if (l == kWave - 1) chunk_tot[c] = incl;
+    const uint32_t per = (nchunks + nw - 1) / nw;
+    const uint32_t c0 = min(w * per, nchunks), c1 = min(c0 + per, nchunks);
+    uint32_t carry = 0;
+    for (uint32_t c = c0; c < c1; ++c) {
+        const uint32_t v = a[c * kWave + l];
+        const uint32_t incl = wave_incl_scan(v);
+        a[c * kWave + l] = carry + incl - v;
+        carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
     }
+    if (l == 0) wave_tot[w] = carry;
     __syncthreads();
-    // Scan chunk totals with wave 0 (nchunks <= 64 * iterations).
-    __shared__ uint32_t s_total;
-    if (w == 0) {
-        uint32_t carry = 0;
-        for (uint32_t base = 0; base < nchunks; base += kWave) {
-            uint32_t i = base + l;
-            uint32_t v = i < nchunks ? chunk_tot[i] : 0;
-            uint32_t incl = wave_incl_scan(v);
-            if (i < nchunks) chunk_tot[i] = carry + incl - v;
-            carry += __shfl(incl, kWave - 1, kWave);
-        }
-        if (l == 0) s_total = carry;
+    uint32_t off = 0, total = 0;
+    for (uint32_t i = 0; i < nw; ++i) {
+        const uint32_t t = wave_tot[i];
+        off += i < w ? t : 0u;
+        total += t;
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) a[i] += chunk_tot[i / kWave];
-    uint32_t t = s_total;
-    return t;
+    if (off)
+        for (uint32_t c = c0; c < c1; ++c) a[c * kWave + l] += off;
+    return total;
 }
+
+// Scratch entries `lds_excl_scan` needs (one per wave of the largest block).
+constexpr uint32_t kScanScratch = 16;
 
 // Block index -> work index such that each of the 8 XCDs (which receive blocks
 // round-robin) processes one contiguous range of work indices.  A bijection on

@@ -50,15 +50,16 @@ void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* partials,
 constexpr uint32_t kShjBlock = 256;
 constexpr uint32_t kShjTile = 2048;  // S tuples per probe tile
 constexpr uint32_t kShjWavesPerBlock = kShjBlock / 64;
-void shj_fill(uint64_t* table, uint64_t nslots, Recorder& rec);
+// Fills the table with empty slots; zero_total (optional) is set to 0.
+void shj_fill(uint64_t* table, uint64_t nslots, uint64_t* zero_total, Recorder& rec);
 void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint32_t log2_slots,
                Recorder& rec);
 void shj_count(const int32_t* s_key, uint64_t n_s, const uint64_t* table, const uint32_t* next,
                uint32_t log2_slots, uint64_t* wave_cnt, Recorder& rec);
 void shj_write(const int32_t* s_key, const int32_t* s_rid, uint64_t n_s, const uint64_t* table,
                const uint32_t* next, uint32_t log2_slots, const int32_t* r_rid,
-               const uint64_t* wave_base, int32_t* out_r, int32_t* out_s, uint64_t capacity,
-               Recorder& rec);
+               const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
+               uint64_t capacity, Recorder& rec);  // wave_base == nullptr: one-pass output into *total
 
 // ---- phj_partition.hip ----
 struct PassCfg {
@@ -71,48 +72,57 @@ struct PassCfg {
 void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, const int32_t* rr,
                       uint32_t n_r, const int32_t* sk, const int32_t* sr, uint32_t n_s,
                       uint32_t tile, uint32_t bits, Recorder& rec);
-void part_hist(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
-               const PassCfg& cfg, uint32_t* hist, Recorder& rec);
-void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
-                  const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out, int32_t* rid_out,
-                  Recorder& rec);
+// tile_seg: segment of every tile (nullptr: binary search over tile_begin).
+void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
+               uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec);
+void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
+                  uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
+                  int32_t* rid_out, Recorder& rec);
 // Pass-2 setup: one segment per pass-1 partition of R and of S, reading from
 // (key_in, rid_in) = pass-1 output.
 void part_setup_pass2(const uint32_t* hist1_scan, const uint32_t* tile_begin1, uint32_t bits1,
                       uint32_t n_r, uint32_t n_s, const int32_t* key_in, const int32_t* rid_in,
                       uint32_t tile, uint32_t bits2, PartSeg* segs2, uint32_t* tile_begin2,
-                      Recorder& rec);
+                      uint32_t* tile_seg2, Recorder& rec);
 
 // ---- phj_join.hip ----
-constexpr uint32_t kJoinBlock = 256;
+constexpr uint32_t kJoinBlock = 512;
 constexpr uint32_t kJoinWaves = kJoinBlock / 64;
-constexpr uint32_t kJoinChunk = 4096;  // S tuples per work item
+constexpr uint32_t kJoinChunk = 4096;   // S tuples per work item
+constexpr uint32_t kMaxLdsCap = 8192;   // largest R partition held in LDS
 struct JoinPlanOut {
     PartPair* pairs;       // [P]
     uint32_t* item_begin;  // [P + 1] exclusive scan of work items per partition
     uint32_t* ovf_begin;   // [P + 1] exclusive scan of HBM-table build chunks per partition
+    uint32_t* item_part;   // [join_grid] partition of every work item
+    uint32_t* ovf_part;    // [ovf_grid] partition of every HBM-table build chunk
 };
 // Final partition table from the last pass's histogram scan, work-item and
 // overflow-chunk scans.  `segs`/`tile_begin`/`nseg` are the last pass's.
 void join_plan(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t bits_last,
                const uint32_t* hist_scan, uint32_t n_r, uint32_t n_s, uint32_t total_bits,
-               uint32_t lds_cap, const JoinPlanOut& o, Recorder& rec);
+               uint32_t lds_cap, const JoinPlanOut& o, uint64_t* zero_total, Recorder& rec);
 // Upper bounds of the HBM-table build items and of the join work items.
 uint32_t ovf_grid(uint32_t P, uint64_t n_r);
 uint32_t join_grid(uint32_t P, uint64_t n_s);
 // Dynamic LDS bytes of the join kernels for a given lds_cap.
 size_t join_lds_bytes(uint32_t lds_cap, bool write);
 size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile);
-void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, uint32_t P, uint32_t grid,
-                    const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, Recorder& rec);
-void join_count(const PartPair* pairs, const uint32_t* item_begin, uint32_t P, uint32_t grid,
+void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint32_t* ovf_part, uint32_t P,
+                    uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, Recorder& rec);
+// item_begin/item_part come from join_plan (JoinPlanOut).
+void join_count(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+                uint32_t grid,
                 const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
                 const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec);
-void join_write(const PartPair* pairs, const uint32_t* item_begin, uint32_t P, uint32_t grid,
+void join_write(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+                uint32_t grid,
                 const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                 uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
-                const uint64_t* wave_base, int32_t* out_r, int32_t* out_s, uint64_t capacity,
-                Recorder& rec);
+                const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
+                uint64_t capacity, Recorder& rec);
+// wave_base == nullptr selects the one-pass write: `total` must be zero on entry
+// and ends as the number of pairs.
 // Writes zero to *d_count (joins with an empty side).
 void write_zero_count(uint64_t* d_count, Recorder& rec);
 

@@ -27,11 +27,6 @@ constexpr uint32_t kOvfChunk = 4096;                  // R tuples per HBM-table 
 constexpr uint32_t kSubJ = kJoinChunk / kJoinWaves;   // S tuples per wave of an item
 constexpr uint32_t kPlanBlock = 1024;
 
-__device__ __forceinline__ uint32_t floor_log2_min6(uint32_t n) {
-    const uint32_t v = n < 64 ? 64u : n;
-    return 31u - (uint32_t)__clz(v);
-}
-
 // Start of final partition i of one relation (positions relative to the relation).
 __device__ __forceinline__ uint32_t final_start(const PartSeg* __restrict__ segs,
                                                 const uint32_t* __restrict__ tile_begin,
@@ -47,42 +42,67 @@ __device__ __forceinline__ uint32_t final_start(const PartSeg* __restrict__ segs
     return (uint32_t)(segs[seg].out_base - base_rel) + r;
 }
 
+__device__ __forceinline__ uint32_t items_of(const PartPair& pp) {
+    return (pp.r_len && pp.s_len) ? (pp.s_len + kJoinChunk - 1) / kJoinChunk : 0u;
+}
+
+__device__ __forceinline__ uint32_t ovf_chunks_of(const PartPair& pp, uint32_t lds_cap) {
+    return (pp.r_len > lds_cap && pp.s_len) ? (pp.r_len + kOvfChunk - 1) / kOvfChunk : 0u;
+}
+
 __global__ void __launch_bounds__(kPlanBlock) k_join_plan(
     const PartSeg* __restrict__ segs, const uint32_t* __restrict__ tile_begin, uint32_t nseg,
     uint32_t bits_last, const uint32_t* __restrict__ hist_scan, uint32_t n_r, uint32_t n_s,
     uint32_t total_bits, uint32_t lds_cap, PartPair* __restrict__ pairs,
-    uint32_t* __restrict__ item_begin, uint32_t* __restrict__ ovf_begin) {
+    uint32_t* __restrict__ item_begin, uint32_t* __restrict__ ovf_begin, uint32_t* __restrict__ item_part,
+    uint32_t* __restrict__ ovf_part, uint64_t* __restrict__ zero_total) {
     __shared__ uint32_t wt[kPlanBlock / kWave];
     const uint32_t P = 1u << total_bits;
     const uint32_t nseg_rel = nseg / 2;
+    // Phase A: start of every partition (independent loads, strided over the block).
+    for (uint32_t i = threadIdx.x; i < P; i += kPlanBlock) {
+        PartPair pp;
+        pp.r_off = min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i, n_r, 0, P), n_r);
+        pp.s_off = min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i, n_s, n_r, P), n_s);
+        pp.r_len = 0;
+        pp.s_len = 0;
+        pairs[i] = pp;
+    }
+    if (threadIdx.x == 0 && zero_total) *zero_total = 0;
+    __syncthreads();
+    // Phase B: lengths and work counts of a contiguous range per thread, then scans.
     const uint32_t per = (P + kPlanBlock - 1) / kPlanBlock;
     const uint32_t a = min(threadIdx.x * per, P);
     const uint32_t b = min(a + per, P);
     uint32_t items = 0, ovf = 0;
-    uint32_t r0 = final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, a, n_r, 0, P);
-    uint32_t s0 = final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, a, n_s, n_r, P);
     for (uint32_t i = a; i < b; ++i) {
-        const uint32_t r1 = final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i + 1, n_r, 0, P);
-        const uint32_t s1 = final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i + 1, n_s, n_r, P);
-        PartPair pp;
-        pp.r_off = r0; pp.r_len = r1 - r0; pp.s_off = s0; pp.s_len = s1 - s0;
-        pairs[i] = pp;
-        const bool live = pp.r_len && pp.s_len;
-        items += live ? (pp.s_len + kJoinChunk - 1) / kJoinChunk : 0u;
-        ovf += (live && pp.r_len > lds_cap) ? (pp.r_len + kOvfChunk - 1) / kOvfChunk : 0u;
-        r0 = r1;
-        s0 = s1;
+        PartPair pp = pairs[i];
+        // clamped: a partition never extends past its relation or runs backwards
+        const uint32_t r1 = max(pp.r_off, i + 1 < P ? pairs[i + 1].r_off : n_r);
+        const uint32_t s1 = max(pp.s_off, i + 1 < P ? pairs[i + 1].s_off : n_s);
+        pp.r_len = r1 - pp.r_off;
+        pp.s_len = s1 - pp.s_off;
+        items += items_of(pp);
+        ovf += ovf_chunks_of(pp, lds_cap);
+        // lengths are written after every thread has read the offsets it needs
+        item_begin[i] = pp.r_len;
+        ovf_begin[i] = pp.s_len;
     }
     uint32_t tot_items, tot_ovf;
     uint32_t run_i = block_excl_scan(items, wt, &tot_items);
     uint32_t run_o = block_excl_scan(ovf, wt, &tot_ovf);
     for (uint32_t i = a; i < b; ++i) {
-        const PartPair pp = pairs[i];
-        const bool live = pp.r_len && pp.s_len;
+        PartPair pp = pairs[i];
+        pp.r_len = item_begin[i];
+        pp.s_len = ovf_begin[i];
+        pairs[i] = pp;
         item_begin[i] = run_i;
         ovf_begin[i] = run_o;
-        run_i += live ? (pp.s_len + kJoinChunk - 1) / kJoinChunk : 0u;
-        run_o += (live && pp.r_len > lds_cap) ? (pp.r_len + kOvfChunk - 1) / kOvfChunk : 0u;
+        const uint32_t ni = items_of(pp), no = ovf_chunks_of(pp, lds_cap);
+        for (uint32_t x = 0; x < ni; ++x) item_part[run_i + x] = i;
+        for (uint32_t x = 0; x < no; ++x) ovf_part[run_o + x] = i;
+        run_i += ni;
+        run_o += no;
     }
     if (threadIdx.x == 0) {
         item_begin[P] = tot_items;
@@ -95,11 +115,12 @@ __device__ __forceinline__ uint64_t region_slot(int32_t key, uint32_t H) {
 }
 
 __global__ void __launch_bounds__(256) k_ovf_clear(const PartPair* __restrict__ pairs,
-                                                  const uint32_t* __restrict__ ovf_begin, uint32_t P,
+                                                  const uint32_t* __restrict__ ovf_begin,
+                                                  const uint32_t* __restrict__ ovf_part, uint32_t P,
                                                   uint64_t* __restrict__ ovf_table) {
     const uint32_t item = blockIdx.x;
     if (item >= ovf_begin[P]) return;
-    const uint32_t i = upper_index(ovf_begin, P, item);
+    const uint32_t i = ovf_part[item];
     const uint32_t c = item - ovf_begin[i];
     const PartPair pp = pairs[i];
     uint64_t* region = ovf_table + 2ull * pp.r_off;
@@ -114,13 +135,14 @@ struct RegionStep {
 };
 
 __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ pairs,
-                                                  const uint32_t* __restrict__ ovf_begin, uint32_t P,
+                                                  const uint32_t* __restrict__ ovf_begin,
+                                                  const uint32_t* __restrict__ ovf_part, uint32_t P,
                                                   const int32_t* __restrict__ rk,
                                                   uint64_t* __restrict__ ovf_table,
                                                   uint32_t* __restrict__ ovf_next) {
     const uint32_t item = blockIdx.x;
     if (item >= ovf_begin[P]) return;
-    const uint32_t i = upper_index(ovf_begin, P, item);
+    const uint32_t i = ovf_part[item];
     const uint32_t c = item - ovf_begin[i];
     const PartPair pp = pairs[i];
     uint64_t* region = ovf_table + 2ull * pp.r_off;
@@ -133,46 +155,47 @@ __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ 
     }
 }
 
-// Builds the bucketed LDS table over R_i: afterwards bucket b holds
-// skey/srid[(b ? bend[b-1] : 0) .. bend[b]).  H = 2^log2H buckets.
+constexpr uint32_t kRU = kMaxLdsCap / kJoinBlock;  // R tuples per thread when building
+constexpr uint32_t kSU = kSubJ / kWave;              // S tuples per lane of an item
+
+// Builds the bucketed LDS table over R_i (n <= kMaxLdsCap tuples).  Afterwards
+// bucket b holds skey/srid[bcnt[b] .. bcnt[b+1]).  H = 2^log2H buckets; bcnt has
+// H + 1 entries.  Each R tuple is loaded once: its bucket and its rank inside
+// the bucket (from the counting atomic) stay in a register until placement.
 template <bool kRids>
 __device__ __forceinline__ void build_lds(const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
-                                          uint32_t n, uint32_t log2H, uint32_t* bend, int32_t* skey,
+                                          uint32_t n, uint32_t log2H, uint32_t* bcnt, int32_t* skey,
                                           int32_t* srid, uint32_t* ctot) {
     const uint32_t H = 1u << log2H;
     const uint32_t sh = 32 - log2H;
-    for (uint32_t x = threadIdx.x; x < H; x += blockDim.x) bend[x] = 0;
+    int32_t k[kRU], r[kRU];
+    uint32_t br[kRU];
+#pragma unroll
+    for (uint32_t u = 0; u < kRU; ++u) {
+        const uint32_t j = u * kJoinBlock + threadIdx.x;
+        k[u] = j < n ? rk[j] : 0;
+        if (kRids) r[u] = j < n ? rr[j] : 0;
+    }
+    for (uint32_t x = threadIdx.x; x <= H; x += kJoinBlock) bcnt[x] = 0;
     __syncthreads();
-    constexpr uint32_t U = 4;
-    for (uint32_t base = 0; base < n; base += U * kJoinBlock) {
-        int32_t k[U];
 #pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-            const uint32_t j = base + u * kJoinBlock + threadIdx.x;
-            k[u] = j < n ? rk[j] : 0;
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-            const uint32_t j = base + u * kJoinBlock + threadIdx.x;
-            if (j < n) atomicAdd(&bend[slot_hash(k[u]) >> sh], 1u);
+    for (uint32_t u = 0; u < kRU; ++u) {
+        const uint32_t j = u * kJoinBlock + threadIdx.x;
+        if (j < n) {
+            const uint32_t b = slot_hash(k[u]) >> sh;
+            br[u] = (b << 16) | atomicAdd(&bcnt[b], 1u);  // b < 2^13, rank < 2^13
         }
     }
     __syncthreads();
-    lds_excl_scan(bend, H, ctot);
+    lds_excl_scan(bcnt, H, ctot);
+    if (threadIdx.x == 0) bcnt[H] = n;
     __syncthreads();
-    for (uint32_t base = 0; base < n; base += U * kJoinBlock) {
-        int32_t k[U], r[U];
 #pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-            const uint32_t j = base + u * kJoinBlock + threadIdx.x;
-            k[u] = j < n ? rk[j] : 0;
-            if (kRids) r[u] = j < n ? rr[j] : 0;
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-            const uint32_t j = base + u * kJoinBlock + threadIdx.x;
-            if (j < n) {
-                const uint32_t pos = atomicAdd(&bend[slot_hash(k[u]) >> sh], 1u);
+    for (uint32_t u = 0; u < kRU; ++u) {
+        const uint32_t j = u * kJoinBlock + threadIdx.x;
+        if (j < n) {
+            const uint32_t pos = bcnt[br[u] >> 16] + (br[u] & 0xFFFFu);
+            if (pos < n) {  // always true for a correct scan; keeps LDS writes inside R_i's run
                 skey[pos] = k[u];
                 if (kRids) srid[pos] = r[u];
             }
@@ -189,12 +212,13 @@ struct ItemLoc {
 };
 
 __device__ __forceinline__ ItemLoc locate_item(const PartPair* __restrict__ pairs,
-                                               const uint32_t* __restrict__ item_begin, uint32_t P) {
+                                               const uint32_t* __restrict__ item_begin,
+                                               const uint32_t* __restrict__ item_part, uint32_t P) {
     ItemLoc L;
     L.item = xcd_remap(blockIdx.x, gridDim.x);
     L.live = L.item < item_begin[P];
     if (!L.live) return L;
-    const uint32_t i = upper_index(item_begin, P, L.item);
+    const uint32_t i = item_part[L.item];
     const uint32_t c = L.item - item_begin[i];
     L.pp = pairs[i];
     L.s_begin = L.pp.s_off + c * kJoinChunk;
@@ -202,8 +226,63 @@ __device__ __forceinline__ ItemLoc locate_item(const PartPair* __restrict__ pair
     return L;
 }
 
+// LDS layout of the join kernels: bcnt[cap + 64] | skey[cap] | srid[cap] (write) | ctot[kScanScratch]
+struct LdsView {
+    uint32_t* bcnt;
+    int32_t* skey;
+    int32_t* srid;
+    uint32_t* ctot;
+};
+
+__device__ __forceinline__ LdsView lds_view(uint32_t* lds, uint32_t cap, bool rids) {
+    LdsView v;
+    v.bcnt = lds;
+    v.skey = (int32_t*)(lds + cap + kWave);
+    v.srid = v.skey + cap;
+    v.ctot = (uint32_t*)(v.skey + (rids ? 2 : 1) * cap);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t floor_log2_min6(uint32_t n) {
+    const uint32_t v = n < 64 ? 64u : n;
+    return 31u - (uint32_t)__clz(v);
+}
+
+// S keys (and rids) of this lane for the wave's range of the item.
+template <bool kRids>
+__device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const int32_t* __restrict__ srp,
+                                       uint32_t wb, uint32_t we, int32_t* q, int32_t* qr) {
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        const uint32_t j = wb + u * kWave + lane_id();
+        q[u] = j < we ? skp[j] : 0;
+        if (kRids) qr[u] = j < we ? srp[j] : 0;
+    }
+}
+
+// First and one-past-last position of the bucket run of every S key of this
+// lane (empty for lanes past the item's end).  All 2*kSU LDS reads are issued
+// before any key is compared.  Clamped to [0, n] so a run never leaves R_i.
+__device__ __forceinline__ void bucket_runs(const uint32_t* bcnt, uint32_t log2H, uint32_t n, const int32_t* q,
+                                            uint32_t wb, uint32_t we, uint32_t* lo, uint32_t* hi) {
+    const uint32_t sh = 32 - log2H;
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        const bool ok = wb + u * kWave + lane_id() < we;
+        const uint32_t b = slot_hash(q[u]) >> sh;
+        lo[u] = ok ? bcnt[b] : 0u;
+        hi[u] = ok ? bcnt[b + 1] : 0u;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        hi[u] = min(hi[u], n);
+        lo[u] = min(lo[u], hi[u]);
+    }
+}
+
 __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __restrict__ pairs,
                                                           const uint32_t* __restrict__ item_begin,
+                                                          const uint32_t* __restrict__ item_part,
                                                           uint32_t P, const int32_t* __restrict__ rk,
                                                           const int32_t* __restrict__ sk, uint32_t lds_cap,
                                                           const uint64_t* __restrict__ ovf_table,
@@ -212,41 +291,35 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
     extern __shared__ uint32_t lds[];
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
-    const ItemLoc L = locate_item(pairs, item_begin, P);
+    const ItemLoc L = locate_item(pairs, item_begin, item_part, P);
     if (!L.live) {
         if (lane == 0) wave_cnt[(uint64_t)L.item * kJoinWaves + w] = 0;
         return;
     }
-    uint64_t cnt = 0;
     const uint32_t wb = w * kSubJ;
     const uint32_t we = min(wb + kSubJ, L.s_n);
-    const int32_t* __restrict__ skp = sk + L.s_begin;
+    int32_t q[kSU], qr[kSU];
+    load_s<false>(sk + L.s_begin, nullptr, wb, we, q, qr);
+    uint64_t cnt = 0;
     if (L.pp.r_len <= lds_cap) {
-        uint32_t* bend = lds;
-        int32_t* skey = (int32_t*)(lds + lds_cap);
-        uint32_t* ctot = lds + 2 * lds_cap;
+        const LdsView v = lds_view(lds, lds_cap, false);
         const uint32_t log2H = floor_log2_min6(L.pp.r_len);
-        build_lds<false>(rk + L.pp.r_off, nullptr, L.pp.r_len, log2H, bend, skey, nullptr, ctot);
-        const uint32_t sh = 32 - log2H;
-        for (uint32_t r = wb; r < we; r += kWave) {
-            const uint32_t j = r + lane;
-            if (j < we) {
-                const int32_t k = skp[j];
-                const uint32_t b = slot_hash(k) >> sh;
-                const uint32_t lo = b ? bend[b - 1] : 0u;
-                const uint32_t hi = bend[b];
-                for (uint32_t x = lo; x < hi; ++x) cnt += (skey[x] == k);
-            }
-        }
+        build_lds<false>(rk + L.pp.r_off, nullptr, L.pp.r_len, log2H, v.bcnt, v.skey, nullptr, v.ctot);
+        uint32_t lo[kSU], hi[kSU];
+        bucket_runs(v.bcnt, log2H, L.pp.r_len, q, wb, we, lo, hi);
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u)
+            for (uint32_t x = lo[u]; x < hi[u]; ++x) c += (v.skey[x] == q[u]);
+        cnt = c;
     } else {
         const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
         const uint32_t* __restrict__ next = ovf_next + L.pp.r_off;
         const RegionStep step{2u * L.pp.r_len};
-        for (uint32_t r = wb; r < we; r += kWave) {
-            const uint32_t j = r + lane;
-            if (j < we) {
-                const int32_t k = skp[j];
-                const uint32_t h = chain_find(region, region_slot(k, step.H), k, step);
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) {
+            if (wb + u * kWave + lane < we) {
+                const uint32_t h = chain_find(region, region_slot(q[u], step.H), q[u], step);
                 if (h != kNotFound) cnt += chain_len(next, h);
             }
         }
@@ -255,77 +328,97 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
     if (lane == 0) wave_cnt[(uint64_t)L.item * kJoinWaves + w] = cnt;
 }
 
+// Write pass.  kOnePass: instead of reading a scanned per-wave offset, the
+// block counts its pairs, reserves that many output slots with one atomic add
+// on the running total (the block allocator of Section 3.3 with a block sized
+// to the work item), and writes them there.
+template <bool kOnePass>
 __global__ void __launch_bounds__(kJoinBlock) k_join_write(
-    const PartPair* __restrict__ pairs, const uint32_t* __restrict__ item_begin, uint32_t P,
-    const int32_t* __restrict__ rk, const int32_t* __restrict__ rr, const int32_t* __restrict__ sk,
-    const int32_t* __restrict__ sr, uint32_t lds_cap, const uint64_t* __restrict__ ovf_table,
-    const uint32_t* __restrict__ ovf_next, const uint64_t* __restrict__ wave_base, int32_t* __restrict__ out_r, int32_t* __restrict__ out_s,
+    const PartPair* __restrict__ pairs, const uint32_t* __restrict__ item_begin,
+    const uint32_t* __restrict__ item_part, uint32_t P, const int32_t* __restrict__ rk,
+    const int32_t* __restrict__ rr, const int32_t* __restrict__ sk, const int32_t* __restrict__ sr,
+    uint32_t lds_cap, const uint64_t* __restrict__ ovf_table,
+    const uint32_t* __restrict__ ovf_next, const uint64_t* __restrict__ wave_base,
+    unsigned long long* __restrict__ total, int32_t* __restrict__ out_r, int32_t* __restrict__ out_s,
     uint64_t capacity) {
     extern __shared__ uint32_t lds[];
+    __shared__ uint64_t wtot[kJoinWaves + 1];
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
-    const ItemLoc L = locate_item(pairs, item_begin, P);
+    const ItemLoc L = locate_item(pairs, item_begin, item_part, P);
     if (!L.live) return;
-    uint64_t pos0 = wave_base[(uint64_t)L.item * kJoinWaves + w];
     const uint32_t wb = w * kSubJ;
     const uint32_t we = min(wb + kSubJ, L.s_n);
-    const int32_t* __restrict__ skp = sk + L.s_begin;
-    const int32_t* __restrict__ srp = sr + L.s_begin;
-    if (L.pp.r_len <= lds_cap) {
-        uint32_t* bend = lds;
-        int32_t* skey = (int32_t*)(lds + lds_cap);
-        int32_t* srid = skey + lds_cap;
-        uint32_t* ctot = (uint32_t*)(srid + lds_cap);
+    int32_t q[kSU], qr[kSU];
+    load_s<true>(sk + L.s_begin, sr + L.s_begin, wb, we, q, qr);
+    const bool in_lds = L.pp.r_len <= lds_cap;
+    const LdsView v = lds_view(lds, lds_cap, true);
+    const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
+    const uint32_t* __restrict__ next = ovf_next + L.pp.r_off;
+    const int32_t* __restrict__ rrp = rr + L.pp.r_off;
+    const RegionStep step{2u * L.pp.r_len};
+    // Per S tuple: match count c[u] and where its matches are (LDS run start, or chain head).
+    uint32_t c[kSU], at[kSU];
+    uint32_t hi[kSU];
+    if (in_lds) {
         const uint32_t log2H = floor_log2_min6(L.pp.r_len);
-        build_lds<true>(rk + L.pp.r_off, rr + L.pp.r_off, L.pp.r_len, log2H, bend, skey, srid, ctot);
-        const uint32_t sh = 32 - log2H;
-        for (uint32_t r = wb; r < we; r += kWave) {
-            const uint32_t j = r + lane;
-            uint64_t c = 0;
-            uint32_t lo = 0, hi = 0;
-            int32_t k = 0;
-            if (j < we) {
-                k = skp[j];
-                const uint32_t b = slot_hash(k) >> sh;
-                lo = b ? bend[b - 1] : 0u;
-                hi = bend[b];
-                for (uint32_t x = lo; x < hi; ++x) c += (skey[x] == k);
+        build_lds<true>(rk + L.pp.r_off, rrp, L.pp.r_len, log2H, v.bcnt, v.skey, v.srid, v.ctot);
+        bucket_runs(v.bcnt, log2H, L.pp.r_len, q, wb, we, at, hi);
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) {
+            c[u] = 0;
+            for (uint32_t x = at[u]; x < hi[u]; ++x) c[u] += (v.skey[x] == q[u]);
+        }
+    } else {
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) {
+            c[u] = 0;
+            at[u] = kNotFound;
+            if (wb + u * kWave + lane < we) {
+                at[u] = chain_find(region, region_slot(q[u], step.H), q[u], step);
+                if (at[u] != kNotFound) c[u] = chain_len(next, at[u]);
             }
-            const uint64_t incl = wave_incl_scan(c);
-            uint64_t pos = pos0 + incl - c;
-            pos0 += __shfl(incl, kWave - 1, kWave);
-            if (c) {
-                const int32_t rs = srp[j];
-                for (uint32_t x = lo; x < hi; ++x) {
-                    if (skey[x] == k) {
+        }
+    }
+    uint64_t pos0;
+    if (kOnePass) {
+        uint64_t mine = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) mine += c[u];
+        mine = wave_sum(mine);
+        if (lane == 0) wtot[w] = mine;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t t = 0;
+            for (uint32_t i = 0; i < kJoinWaves; ++i) t += wtot[i];
+            wtot[kJoinWaves] = t ? atomicAdd(total, (unsigned long long)t) : 0ull;
+        }
+        __syncthreads();
+        pos0 = wtot[kJoinWaves];
+        for (uint32_t i = 0; i < w; ++i) pos0 += wtot[i];
+    } else {
+        pos0 = wave_base[(uint64_t)L.item * kJoinWaves + w];
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        uint64_t excl, wtotal;
+        wave_offsets(c[u], &excl, &wtotal);
+        uint64_t pos = pos0 + excl;
+        pos0 += wtotal;
+        if (c[u]) {
+            const int32_t key = q[u], rs = qr[u];
+            if (in_lds) {
+                for (uint32_t x = at[u]; x < hi[u]; ++x) {
+                    if (v.skey[x] == key) {
                         if (pos < capacity) {
-                            out_r[pos] = srid[x];
+                            out_r[pos] = v.srid[x];
                             out_s[pos] = rs;
                         }
                         ++pos;
                     }
                 }
-            }
-        }
-    } else {
-        const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
-        const uint32_t* __restrict__ next = ovf_next + L.pp.r_off;
-        const int32_t* __restrict__ rrp = rr + L.pp.r_off;
-        const RegionStep step{2u * L.pp.r_len};
-        for (uint32_t r = wb; r < we; r += kWave) {
-            const uint32_t j = r + lane;
-            uint64_t c = 0;
-            uint32_t h = kNotFound;
-            if (j < we) {
-                const int32_t k = skp[j];
-                h = chain_find(region, region_slot(k, step.H), k, step);
-                if (h != kNotFound) c = chain_len(next, h);
-            }
-            const uint64_t incl = wave_incl_scan(c);
-            uint64_t pos = pos0 + incl - c;
-            pos0 += __shfl(incl, kWave - 1, kWave);
-            if (c) {
-                const int32_t rs = srp[j];
+            } else {
+                uint32_t h = at[u];
                 while (true) {
                     const uint32_t row = h & ~kLast;
                     if (pos < capacity) {
@@ -348,7 +441,7 @@ __global__ void k_write_zero(uint64_t* p) {
 }  // namespace
 
 size_t join_lds_bytes(uint32_t lds_cap, bool write) {
-    return sizeof(uint32_t) * ((size_t)lds_cap * (write ? 3 : 2) + lds_cap / kWave);
+    return sizeof(uint32_t) * ((size_t)lds_cap + kWave + (size_t)lds_cap * (write ? 2 : 1) + kScanScratch);
 }
 
 void write_zero_count(uint64_t* d_count, Recorder& rec) {
@@ -359,11 +452,11 @@ void write_zero_count(uint64_t* d_count, Recorder& rec) {
 
 void join_plan(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t bits_last,
                const uint32_t* hist_scan, uint32_t n_r, uint32_t n_s, uint32_t total_bits,
-               uint32_t lds_cap, const JoinPlanOut& o, Recorder& rec) {
+               uint32_t lds_cap, const JoinPlanOut& o, uint64_t* zero_total, Recorder& rec) {
     rec.before("join_plan");
     hipLaunchKernelGGL(k_join_plan, dim3(1), dim3(kPlanBlock), 0, rec.stream, segs, tile_begin, nseg,
                        bits_last, hist_scan, n_r, n_s, total_bits, lds_cap, o.pairs, o.item_begin,
-                       o.ovf_begin);
+                       o.ovf_begin, o.item_part, o.ovf_part, zero_total);
     rec.after();
 }
 
@@ -375,19 +468,21 @@ uint32_t join_grid(uint32_t P, uint64_t n_s) {
     return (uint32_t)(P + (n_s + kJoinChunk - 1) / kJoinChunk);
 }
 
-void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, uint32_t P, uint32_t grid,
-                    const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, Recorder& rec) {
+void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint32_t* ovf_part, uint32_t P,
+                    uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, Recorder& rec) {
     if (grid == 0) return;
     rec.before("ovf_clear");
-    hipLaunchKernelGGL(k_ovf_clear, dim3(grid), dim3(256), 0, rec.stream, pairs, ovf_begin, P, ovf_table);
+    hipLaunchKernelGGL(k_ovf_clear, dim3(grid), dim3(256), 0, rec.stream, pairs, ovf_begin, ovf_part, P,
+                       ovf_table);
     rec.after();
     rec.before("ovf_build");
-    hipLaunchKernelGGL(k_ovf_build, dim3(grid), dim3(256), 0, rec.stream, pairs, ovf_begin, P, rk,
+    hipLaunchKernelGGL(k_ovf_build, dim3(grid), dim3(256), 0, rec.stream, pairs, ovf_begin, ovf_part, P, rk,
                        ovf_table, ovf_next);
     rec.after();
 }
 
-void join_count(const PartPair* pairs, const uint32_t* item_begin, uint32_t P, uint32_t grid,
+void join_count(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+                uint32_t grid,
                 const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
                 const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec) {
     if (grid == 0) return;
@@ -396,24 +491,32 @@ void join_count(const PartPair* pairs, const uint32_t* item_begin, uint32_t P, u
         (void)hipFuncSetAttribute((const void*)k_join_count, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
     rec.before("join_count");
-    hipLaunchKernelGGL(k_join_count, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin, P,
+    hipLaunchKernelGGL(k_join_count, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin,
+                       item_part, P,
                        rk, sk, lds_cap, ovf_table, ovf_next, wave_cnt);
     rec.after();
 }
 
-void join_write(const PartPair* pairs, const uint32_t* item_begin, uint32_t P, uint32_t grid,
+void join_write(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+                uint32_t grid,
                 const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                 uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
-                const uint64_t* wave_base, int32_t* out_r, int32_t* out_s, uint64_t capacity,
-                Recorder& rec) {
+                const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
+                uint64_t capacity, Recorder& rec) {
     if (grid == 0) return;
     const size_t lds = join_lds_bytes(lds_cap, true);
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)k_join_write, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-    rec.before("join_write");
-    hipLaunchKernelGGL(k_join_write, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin, P,
-                       rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, wave_base, out_r, out_s, capacity);
+    const bool one_pass = wave_base == nullptr;
+    const void* fn = one_pass ? (const void*)k_join_write<true> : (const void*)k_join_write<false>;
+    if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    rec.before(one_pass ? "join_write_1pass" : "join_write");
+    if (one_pass)
+        hipLaunchKernelGGL(k_join_write<true>, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin,
+                           item_part, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, wave_base,
+                           (unsigned long long*)total, out_r, out_s, capacity);
+    else
+        hipLaunchKernelGGL(k_join_write<false>, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs,
+                           item_begin, item_part, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, wave_base,
+                           (unsigned long long*)total, out_r, out_s, capacity);
     rec.after();
 }
 

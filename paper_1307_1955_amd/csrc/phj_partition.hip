@@ -28,11 +28,14 @@ struct TileLoc {
     uint32_t seg, tl, nt, start, len;
 };
 
+// tile_seg (optional): the segment of every tile, written by the pass's setup
+// kernel; without it the segment is found by binary search over tile_begin.
 __device__ __forceinline__ TileLoc locate(const PartSeg* __restrict__ segs,
-                                          const uint32_t* __restrict__ tile_begin, uint32_t nseg,
+                                          const uint32_t* __restrict__ tile_begin,
+                                          const uint32_t* __restrict__ tile_seg, uint32_t nseg,
                                           uint32_t tile, uint32_t T) {
     TileLoc t;
-    t.seg = upper_index(tile_begin, nseg, tile);
+    t.seg = tile_seg ? tile_seg[tile] : upper_index(tile_begin, nseg, tile);
     const uint32_t b0 = tile_begin[t.seg];
     t.tl = tile - b0;
     t.nt = tile_begin[t.seg + 1] - b0;
@@ -60,6 +63,7 @@ __device__ __forceinline__ uint64_t match_mask(uint32_t p, uint32_t bits, bool v
 template <uint32_t IPT>
 __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restrict__ segs,
                                                          const uint32_t* __restrict__ tile_begin,
+                                                         const uint32_t* __restrict__ tile_seg,
                                                          uint32_t nseg, PassCfg cfg,
                                                          uint32_t* __restrict__ hist) {
     extern __shared__ uint32_t lds[];
@@ -68,7 +72,7 @@ __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restr
     const uint32_t P = 1u << cfg.bits;
     const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= tile_begin[nseg]) return;
-    const TileLoc t = locate(segs, tile_begin, nseg, tile, T);
+    const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
     const PartSeg sg = segs[t.seg];
     for (uint32_t i = threadIdx.x; i < P; i += kPartBlock) cnt[i] = 0;
     __syncthreads();
@@ -96,6 +100,7 @@ __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restr
 template <uint32_t IPT>
 __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __restrict__ segs,
                                                             const uint32_t* __restrict__ tile_begin,
+                                                            const uint32_t* __restrict__ tile_seg,
                                                             uint32_t nseg, PassCfg cfg,
                                                             const uint32_t* __restrict__ hist_scan,
                                                             int32_t* __restrict__ key_out,
@@ -106,13 +111,13 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     const uint32_t Pp = P < kWave ? kWave : P;  // scan length, a multiple of 64
     uint32_t* cnt = lds;                         // [Pp]  counts, then local starts
     uint32_t* delta = cnt + Pp;                  // [P]   global offset - local start
-    uint32_t* ctot = delta + Pp;                 // [Pp/64]
-    int32_t* skey = (int32_t*)(ctot + Pp / kWave);  // [T]
+    uint32_t* ctot = delta + Pp;                 // [kScanScratch]
+    int32_t* skey = (int32_t*)(ctot + kScanScratch);  // [T]
     int32_t* srid = skey + T;                        // [T]
 
     const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= tile_begin[nseg]) return;
-    const TileLoc t = locate(segs, tile_begin, nseg, tile, T);
+    const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
     const PartSeg sg = segs[t.seg];
     for (uint32_t i = threadIdx.x; i < Pp; i += kPartBlock) cnt[i] = 0;
     __syncthreads();
@@ -170,8 +175,10 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
         if (j < t.len) {
             const int32_t key = skey[j];
             const uint32_t dst = delta[part_of(key, cfg)] + j;
-            kout[dst] = key;
-            rout[dst] = srid[j];
+            if (dst < sg.n) {  // always true for a consistent histogram scan; keeps stores in the segment
+                kout[dst] = key;
+                rout[dst] = srid[j];
+            }
         }
     }
 }
@@ -205,7 +212,8 @@ __device__ __forceinline__ uint32_t seg_part_start(const uint32_t* __restrict__ 
 __global__ void __launch_bounds__(kSetupBlock) k_setup_pass2(
     const uint32_t* __restrict__ hist1_scan, const uint32_t* __restrict__ tile_begin1, uint32_t bits1,
     uint32_t n_r, uint32_t n_s, const int32_t* key_in, const int32_t* rid_in, uint32_t tile,
-    uint32_t bits2, PartSeg* __restrict__ segs2, uint32_t* __restrict__ tile_begin2) {
+    uint32_t bits2, PartSeg* __restrict__ segs2, uint32_t* __restrict__ tile_begin2,
+    uint32_t* __restrict__ tile_seg2) {
     __shared__ uint32_t wt[kSetupBlock / kWave];
     const uint32_t P1 = 1u << bits1;
     const uint32_t nseg = 2 * P1;
@@ -220,8 +228,9 @@ __global__ void __launch_bounds__(kSetupBlock) k_setup_pass2(
         const uint32_t nt = rel ? nt_s : nt_r;
         const uint32_t* hs = hist1_scan + (rel ? ((uint64_t)nt_r << bits1) : 0ull);
         const uint32_t n = rel ? n_s : n_r;
-        const uint32_t st = seg_part_start(hs, nt, q);
-        const uint32_t en = q + 1 < P1 ? seg_part_start(hs, nt, q + 1) : n;
+        // clamped so a segment always lies inside its relation
+        const uint32_t st = min(seg_part_start(hs, nt, q), n);
+        const uint32_t en = max(st, q + 1 < P1 ? min(seg_part_start(hs, nt, q + 1), n) : n);
         *off = st;
         *len = en - st;
         *base = rel ? n_r : 0u;
@@ -246,34 +255,36 @@ __global__ void __launch_bounds__(kSetupBlock) k_setup_pass2(
         g.pad = 0;
         segs2[s] = g;
         tile_begin2[s] = run;
-        run += (len + tile - 1) / tile;
+        const uint32_t nt = (len + tile - 1) / tile;
+        for (uint32_t x = 0; x < nt; ++x) tile_seg2[run + x] = s;
+        run += nt;
     }
     if (threadIdx.x == 0) tile_begin2[nseg] = total;
 }
 
 template <uint32_t IPT>
-void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
-                 const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
+void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
+                 uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
     const size_t lds = sizeof(uint32_t) * ((size_t)1 << cfg.bits);
     rec.before("part_hist");
     hipLaunchKernelGGL(k_part_hist<IPT>, dim3(grid), dim3(kPartBlock), lds, rec.stream, segs, tile_begin,
-                       nseg, cfg, hist);
+                       tile_seg, nseg, cfg, hist);
     rec.after();
 }
 
 template <uint32_t IPT>
-void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
-                    const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out, int32_t* rid_out,
-                    Recorder& rec) {
+void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
+                    uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
+                    int32_t* rid_out, Recorder& rec) {
     const size_t P = (size_t)1 << cfg.bits;
     const size_t Pp = P < kWave ? kWave : P;
-    const size_t lds = sizeof(uint32_t) * (2 * Pp + Pp / kWave) + sizeof(int32_t) * 2 * kPartBlock * IPT;
+    const size_t lds = sizeof(uint32_t) * (2 * Pp + kScanScratch) + sizeof(int32_t) * 2 * kPartBlock * IPT;
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_part_scatter<IPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
     rec.before("part_scatter");
     hipLaunchKernelGGL(k_part_scatter<IPT>, dim3(grid), dim3(kPartBlock), lds, rec.stream, segs,
-                       tile_begin, nseg, cfg, hist_scan, key_out, rid_out);
+                       tile_begin, tile_seg, nseg, cfg, hist_scan, key_out, rid_out);
     rec.after();
 }
 
@@ -282,7 +293,7 @@ void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, uint32_t ns
 size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile) {
     const size_t P = (size_t)1 << bits;
     const size_t Pp = P < kWave ? kWave : P;
-    return sizeof(uint32_t) * (2 * Pp + Pp / kWave) + sizeof(int32_t) * 2 * tile;
+    return sizeof(uint32_t) * (2 * Pp + kScanScratch) + sizeof(int32_t) * 2 * tile;
 }
 
 void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, const int32_t* rr,
@@ -297,34 +308,38 @@ void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, co
 void part_setup_pass2(const uint32_t* hist1_scan, const uint32_t* tile_begin1, uint32_t bits1,
                       uint32_t n_r, uint32_t n_s, const int32_t* key_in, const int32_t* rid_in,
                       uint32_t tile, uint32_t bits2, PartSeg* segs2, uint32_t* tile_begin2,
-                      Recorder& rec) {
+                      uint32_t* tile_seg2, Recorder& rec) {
     rec.before("part_setup2");
     hipLaunchKernelGGL(k_setup_pass2, dim3(1), dim3(kSetupBlock), 0, rec.stream, hist1_scan,
-                       tile_begin1, bits1, n_r, n_s, key_in, rid_in, tile, bits2, segs2, tile_begin2);
+                       tile_begin1, bits1, n_r, n_s, key_in, rid_in, tile, bits2, segs2, tile_begin2,
+                       tile_seg2);
     rec.after();
 }
 
-void part_hist(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
-               const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
+void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
+               uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
     if (grid == 0) return;
     switch (cfg.tile) {
-        case 1024: launch_hist<4>(segs, tile_begin, nseg, grid, cfg, hist, rec); break;
-        case 2048: launch_hist<8>(segs, tile_begin, nseg, grid, cfg, hist, rec); break;
-        case 4096: launch_hist<16>(segs, tile_begin, nseg, grid, cfg, hist, rec); break;
-        default: launch_hist<32>(segs, tile_begin, nseg, grid, cfg, hist, rec); break;
+        case 1024: launch_hist<4>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
+        case 2048: launch_hist<8>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
+        case 4096: launch_hist<16>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
+        default: launch_hist<32>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
     }
 }
 
-void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t grid,
-                  const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out, int32_t* rid_out,
-                  Recorder& rec) {
+void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
+                  uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
+                  int32_t* rid_out, Recorder& rec) {
     if (grid == 0) return;
+#define HJ_SCATTER(IPT) \
+    launch_scatter<IPT>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist_scan, key_out, rid_out, rec)
     switch (cfg.tile) {
-        case 1024: launch_scatter<4>(segs, tile_begin, nseg, grid, cfg, hist_scan, key_out, rid_out, rec); break;
-        case 2048: launch_scatter<8>(segs, tile_begin, nseg, grid, cfg, hist_scan, key_out, rid_out, rec); break;
-        case 4096: launch_scatter<16>(segs, tile_begin, nseg, grid, cfg, hist_scan, key_out, rid_out, rec); break;
-        default: launch_scatter<32>(segs, tile_begin, nseg, grid, cfg, hist_scan, key_out, rid_out, rec); break;
+        case 1024: HJ_SCATTER(4); break;
+        case 2048: HJ_SCATTER(8); break;
+        case 4096: HJ_SCATTER(16); break;
+        default: HJ_SCATTER(32); break;
     }
+#undef HJ_SCATTER
 }
 
 }  // namespace hj

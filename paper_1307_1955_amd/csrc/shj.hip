@@ -54,58 +54,100 @@ __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ k
 }
 
 // Probe tiles: tile t covers S rows [t*kShjTile, ...); wave w of the block takes
-// the contiguous range [w*kSub, (w+1)*kSub) of it, 64 rows per round.
+// the contiguous range [w*kSub, (w+1)*kSub) of it; lane l handles rows
+// u*64 + l, one round per u.  (Issuing all kSU first reads together was
+// measured slower on MI355X: the random reads into a table far larger than
+// the caches are bound by line fetches, not by latency.)
 constexpr uint32_t kSub = kShjTile / kShjWavesPerBlock;
+constexpr uint32_t kSU = kSub / kWave;
+
+template <bool kRids>
+__device__ __forceinline__ void shj_probe(const int32_t* __restrict__ s_key, const int32_t* __restrict__ s_rid,
+                                          uint64_t begin, uint64_t n_s, const uint64_t* __restrict__ table,
+                                          const uint32_t* __restrict__ next, uint32_t log2_slots, int32_t* q,
+                                          int32_t* qr, uint32_t* head, uint32_t* cnt) {
+    const PowStep step{(1ull << log2_slots) - 1};
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        const uint64_t j = begin + u * kWave + lane_id();
+        head[u] = kNotFound;
+        cnt[u] = 0;
+        q[u] = 0;
+        if (kRids) qr[u] = 0;
+        if (j < n_s) {
+            q[u] = s_key[j];
+            if (kRids) qr[u] = s_rid[j];
+            head[u] = chain_find(table, home_slot(q[u], log2_slots), q[u], step);
+            if (head[u] != kNotFound) cnt[u] = chain_len(next, head[u]);
+        }
+    }
+}
 
 __global__ void __launch_bounds__(kShjBlock) k_shj_count(const int32_t* __restrict__ s_key, uint64_t n_s,
                                                         const uint64_t* __restrict__ table,
                                                         const uint32_t* __restrict__ next,
                                                         uint32_t log2_slots,
                                                         uint64_t* __restrict__ wave_cnt) {
-    const PowStep step{(1ull << log2_slots) - 1};
     const uint32_t w = threadIdx.x / kWave;
     const uint64_t begin = (uint64_t)blockIdx.x * kShjTile + (uint64_t)w * kSub;
+    int32_t q[kSU], qr[kSU];
+    uint32_t head[kSU], c[kSU];
+    shj_probe<false>(s_key, nullptr, begin, n_s, table, next, log2_slots, q, qr, head, c);
     uint64_t cnt = 0;
-    for (uint32_t r = 0; r < kSub; r += kWave) {
-        const uint64_t j = begin + r + lane_id();
-        if (j < n_s) {
-            const int32_t k = s_key[j];
-            const uint32_t h = chain_find(table, home_slot(k, log2_slots), k, step);
-            if (h != kNotFound) cnt += chain_len(next, h);
-        }
-    }
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) cnt += c[u];
     cnt = wave_sum(cnt);
     if (lane_id() == 0) wave_cnt[(uint64_t)blockIdx.x * kShjWavesPerBlock + w] = cnt;
 }
 
+// Write pass; kOnePass reserves the block's output with one atomic add on the
+// running total instead of reading a scanned offset (see HJ_FLAG_ONE_PASS).
+template <bool kOnePass>
 __global__ void __launch_bounds__(kShjBlock) k_shj_write(
     const int32_t* __restrict__ s_key, const int32_t* __restrict__ s_rid, uint64_t n_s,
     const uint64_t* __restrict__ table, const uint32_t* __restrict__ next, uint32_t log2_slots,
     const int32_t* __restrict__ r_rid, const uint64_t* __restrict__ wave_base,
-    int32_t* __restrict__ out_r, int32_t* __restrict__ out_s, uint64_t capacity) {
-    const PowStep step{(1ull << log2_slots) - 1};
+    unsigned long long* __restrict__ total, int32_t* __restrict__ out_r, int32_t* __restrict__ out_s,
+    uint64_t capacity) {
+    __shared__ uint64_t wtot[kShjWavesPerBlock + 1];
     const uint32_t w = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
     const uint64_t begin = (uint64_t)blockIdx.x * kShjTile + (uint64_t)w * kSub;
-    uint64_t pos0 = wave_base[(uint64_t)blockIdx.x * kShjWavesPerBlock + w];
-    for (uint32_t r = 0; r < kSub; r += kWave) {
-        const uint64_t j = begin + r + lane_id();
-        uint64_t c = 0;
-        uint32_t h = kNotFound;
-        if (j < n_s) {
-            const int32_t k = s_key[j];
-            h = chain_find(table, home_slot(k, log2_slots), k, step);
-            if (h != kNotFound) c = chain_len(next, h);
+    int32_t q[kSU], qr[kSU];
+    uint32_t head[kSU], c[kSU];
+    shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, q, qr, head, c);
+    uint64_t pos0;
+    if (kOnePass) {
+        uint64_t mine = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) mine += c[u];
+        mine = wave_sum(mine);
+        if (lane == 0) wtot[w] = mine;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint64_t t = 0;
+            for (uint32_t i = 0; i < kShjWavesPerBlock; ++i) t += wtot[i];
+            wtot[kShjWavesPerBlock] = t ? atomicAdd(total, (unsigned long long)t) : 0ull;
         }
-        const uint64_t incl = wave_incl_scan(c);
-        uint64_t pos = pos0 + incl - c;
-        pos0 += __shfl(incl, kWave - 1, kWave);
-        if (c) {
-            const int32_t sr = s_rid[j];
+        __syncthreads();
+        pos0 = wtot[kShjWavesPerBlock];
+        for (uint32_t i = 0; i < w; ++i) pos0 += wtot[i];
+    } else {
+        pos0 = wave_base[(uint64_t)blockIdx.x * kShjWavesPerBlock + w];
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        uint64_t excl, wtotal;
+        wave_offsets(c[u], &excl, &wtotal);
+        uint64_t pos = pos0 + excl;
+        pos0 += wtotal;
+        if (c[u]) {
+            uint32_t h = head[u];
             while (true) {
                 const uint32_t row = h & ~kLast;
                 if (pos < capacity) {
                     out_r[pos] = r_rid[row];
-                    out_s[pos] = sr;
+                    out_s[pos] = qr[u];
                 }
                 ++pos;
                 if (h & kLast) break;
@@ -115,9 +157,13 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_write(
     }
 }
 
+__global__ void k_zero_u64(uint64_t* p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
 }  // namespace
 
-void shj_fill(uint64_t* table, uint64_t nslots, Recorder& rec) {
+void shj_fill(uint64_t* table, uint64_t nslots, uint64_t* zero_total, Recorder& rec) {
     uint64_t blocks = (nslots / 2 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
@@ -125,6 +171,11 @@ void shj_fill(uint64_t* table, uint64_t nslots, Recorder& rec) {
     hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)blocks), dim3(256), 0, rec.stream, table, nslots,
                        kEmptySlot);
     rec.after();
+    if (zero_total) {
+        rec.before("zero_count");
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, rec.stream, zero_total);
+        rec.after();
+    }
 }
 
 void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint32_t log2_slots,
@@ -150,13 +201,21 @@ void shj_count(const int32_t* s_key, uint64_t n_s, const uint64_t* table, const 
 
 void shj_write(const int32_t* s_key, const int32_t* s_rid, uint64_t n_s, const uint64_t* table,
                const uint32_t* next, uint32_t log2_slots, const int32_t* r_rid,
-               const uint64_t* wave_base, int32_t* out_r, int32_t* out_s, uint64_t capacity,
-               Recorder& rec) {
+               const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
+               uint64_t capacity, Recorder& rec) {
     const uint64_t tiles = (n_s + kShjTile - 1) / kShjTile;
     if (tiles == 0) return;
-    rec.before("shj_write");
-    hipLaunchKernelGGL(k_shj_write, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key, s_rid,
-                       n_s, table, next, log2_slots, r_rid, wave_base, out_r, out_s, capacity);
+    if (wave_base == nullptr) {
+        rec.before("shj_write_1pass");
+        hipLaunchKernelGGL(k_shj_write<true>, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key,
+                           s_rid, n_s, table, next, log2_slots, r_rid, wave_base, (unsigned long long*)total,
+                           out_r, out_s, capacity);
+    } else {
+        rec.before("shj_write");
+        hipLaunchKernelGGL(k_shj_write<false>, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key,
+                           s_rid, n_s, table, next, log2_slots, r_rid, wave_base, (unsigned long long*)total,
+                           out_r, out_s, capacity);
+    }
     rec.after();
 }
 

@@ -28,6 +28,7 @@ HJ_SHJ = 0
 HJ_PHJ = 1
 HJ_HASH_IDENTITY = 0
 HJ_HASH_MURMUR2 = 1
+HJ_FLAG_ONE_PASS = 1
 
 # Every symbol include/hj.h declares.
 EXPORTED = (
@@ -52,9 +53,9 @@ class HjParams(ctypes.Structure):
     ]
 
     def __repr__(self) -> str:
-        return ("HjParams(algo=%s, passes=%d, bits=(%d, %d), hash=%d, tile=%d, lds_cap=%d)" % (
+        return ("HjParams(algo=%s, passes=%d, bits=(%d, %d), hash=%d, tile=%d, lds_cap=%d, flags=%d)" % (
             "phj" if self.algo == HJ_PHJ else "shj", self.passes, self.bits[0], self.bits[1],
-            self.hash, self.tile, self.lds_cap))
+            self.hash, self.tile, self.lds_cap, self.flags))
 
 
 class HJError(RuntimeError):
@@ -121,8 +122,9 @@ def hj_default_params() -> HjParams:
 
 
 def params(algo: str = "phj", passes: int = 2, bits=(6, 6), hash: str = "identity", tile: int = 0,
-           lds_cap: int = 0) -> HjParams:
-    """Builds an ``hj_params``.  ``algo`` is "shj" or "phj"; ``hash`` "identity" or "murmur2"."""
+           lds_cap: int = 0, one_pass: bool = False) -> HjParams:
+    """Builds an ``hj_params``.  ``algo`` is "shj" or "phj"; ``hash`` "identity" or "murmur2";
+    ``one_pass`` selects the single-pass PHJ output (HJ_FLAG_ONE_PASS)."""
     p = HjParams()
     p.algo = {"shj": HJ_SHJ, "phj": HJ_PHJ}[algo]
     p.passes = passes
@@ -131,7 +133,7 @@ def params(algo: str = "phj", passes: int = 2, bits=(6, 6), hash: str = "identit
     p.hash = {"identity": HJ_HASH_IDENTITY, "murmur2": HJ_HASH_MURMUR2}[hash]
     p.tile = tile
     p.lds_cap = lds_cap
-    p.flags = 0
+    p.flags = HJ_FLAG_ONE_PASS if one_pass else 0
     return p
 
 

@@ -74,7 +74,7 @@ def test_invalid_params_rejected(hj, kw):
 
 def test_flags_and_hash_rejected(hj):
     p = hj.params("shj")
-    p.flags = 1
+    p.flags = 2
     with pytest.raises(hj.HJError):
         hj.hj_workspace_bytes(p, 10, 10)
     p = hj.params("shj")

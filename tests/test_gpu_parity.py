@@ -54,6 +54,7 @@ def dup_relations(seed, n_r, n_s, domain):
 
 CASES = [
     ("shj", dict(algo="shj")),
+    ("shj_1pass", dict(algo="shj", one_pass=True)),
     ("phj1_b1", dict(algo="phj", passes=1, bits=(1,))),
     ("phj1_b4", dict(algo="phj", passes=1, bits=(4,))),
     ("phj1_b8_t1024", dict(algo="phj", passes=1, bits=(8,), tile=1024)),
@@ -65,6 +66,9 @@ CASES = [
     ("phj2_6_6_murmur", dict(algo="phj", passes=2, bits=(6, 6), hash="murmur2")),
     ("phj1_10_murmur", dict(algo="phj", passes=1, bits=(10,), hash="murmur2")),
     ("phj2_2_2_ldscap256", dict(algo="phj", passes=2, bits=(2, 2), lds_cap=256)),
+    ("phj2_6_6_1pass", dict(algo="phj", passes=2, bits=(6, 6), one_pass=True)),
+    ("phj1_3_1pass_ldscap256", dict(algo="phj", passes=1, bits=(3,), lds_cap=256, one_pass=True)),
+    ("phj2_8_5_1pass_murmur", dict(algo="phj", passes=2, bits=(8, 5), hash="murmur2", one_pass=True)),
 ]
 
 
@@ -91,7 +95,9 @@ def test_empty_and_tiny(kw):
 
 
 @pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="phj", passes=2, bits=(5, 5)),
-                                dict(algo="phj", passes=2, bits=(5, 5), lds_cap=256)])
+                                dict(algo="phj", passes=2, bits=(5, 5), lds_cap=256),
+                                dict(algo="shj", one_pass=True),
+                                dict(algo="phj", passes=2, bits=(5, 5), lds_cap=256, one_pass=True)])
 def test_cartesian_all_equal(kw):
     rk = np.full(300, 77, dtype=np.int32)
     sk = np.full(700, 77, dtype=np.int32)
@@ -99,7 +105,8 @@ def test_cartesian_all_equal(kw):
 
 
 @pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="phj", passes=2, bits=(6, 6)),
-                                dict(algo="phj", passes=1, bits=(8,), hash="murmur2")])
+                                dict(algo="phj", passes=1, bits=(8,), hash="murmur2"),
+                                dict(algo="phj", passes=2, bits=(6, 6), one_pass=True)])
 def test_r_side_skew(kw):
     """10% of R shares one key (a heavy partition that overflows the LDS budget)."""
     n_r, n_s = 1 << 17, 1 << 18
@@ -113,7 +120,9 @@ def test_r_side_skew(kw):
 
 
 @pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="phj", passes=2, bits=(6, 6)),
-                                dict(algo="phj", passes=1, bits=(3,))])
+                                dict(algo="phj", passes=1, bits=(3,)),
+                                dict(algo="phj", passes=2, bits=(6, 6), one_pass=True),
+                                dict(algo="shj", one_pass=True)])
 def test_capacity_guard(kw):
     """Too small an output: the full count is reported, nothing is written past capacity."""
     p = hj.params(**kw)
@@ -222,6 +231,8 @@ C1_C2_PARAMS = [
     ("phj2_6_6", dict(algo="phj", passes=2, bits=(6, 6))),
     ("phj1_12", dict(algo="phj", passes=1, bits=(12,))),
     ("phj2_7_6_murmur", dict(algo="phj", passes=2, bits=(7, 6), hash="murmur2")),
+    ("phj2_6_6_1pass", dict(algo="phj", passes=2, bits=(6, 6), one_pass=True)),
+    ("shj_1pass", dict(algo="shj", one_pass=True)),
 ]
 
 
@@ -246,8 +257,9 @@ def test_c2_full(name, kw):
 
 
 @pytest.mark.parametrize("theta", [0.5, 1.0])
-@pytest.mark.parametrize("kw", [dict(algo="phj", passes=2, bits=(6, 6)), dict(algo="shj")],
-                         ids=["phj2_6_6", "shj"])
+@pytest.mark.parametrize("kw", [dict(algo="phj", passes=2, bits=(6, 6)), dict(algo="shj"),
+                                dict(algo="phj", passes=2, bits=(6, 6), one_pass=True)],
+                         ids=["phj2_6_6", "shj", "phj2_6_6_1pass"])
 def test_c3_zipf_full(theta, kw):
     """16M R, 64M Zipf S: every S tuple matches; heavy hitters split over many work items."""
     rk, rr, sk, sr = dgen.config_c3(theta=theta)
