@@ -66,6 +66,30 @@ struct Plan {
     uint32_t passes, b1, b2, B, P1, P2, P, tile, hash, lds_cap;
 };
 
+// LDS per CU on gfx950, and what a join workgroup takes beyond its dynamic
+// tables (static LDS plus allocation rounding; measured: a 54,080-byte table
+// set no longer fits three workgroups per CU, 53,312 bytes does).
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr size_t kJoinStaticLds = 1024;
+
+uint32_t join_blocks_per_cu(uint32_t cap) {
+    return (uint32_t)(kLdsPerCu / (hj::join_lds_bytes(cap, true) + kJoinStaticLds));
+}
+
+// Default LDS table capacity: room for a partition three standard deviations
+// above the mean size (uniform hashing), then grown to the largest capacity
+// that keeps the same number of write-kernel workgroups per CU.
+uint32_t auto_lds_cap(uint64_t n_r, uint32_t P) {
+    const double avg = std::ceil((double)n_r / (double)P);
+    const double need = avg + 3.0 * std::sqrt(avg) + 32.0;
+    uint32_t cap = (uint32_t)std::min<double>(hj::kMaxLdsCap, std::max(256.0, need));
+    cap = (cap + 63) / 64 * 64;
+    if (cap > hj::kMaxLdsCap) cap = hj::kMaxLdsCap;
+    const uint32_t bpc = join_blocks_per_cu(cap);
+    while (cap + 64 <= hj::kMaxLdsCap && join_blocks_per_cu(cap + 64) == bpc) cap += 64;
+    return cap;
+}
+
 hj_status check_params(const hj_params* p, uint64_t n_r, Plan* pl) {
     if (!p) return fail(HJ_ERR_INVALID, "params is NULL");
     if (p->flags & ~HJ_FLAG_ONE_PASS) return fail(HJ_ERR_INVALID, "unknown flags 0x%x", p->flags);
@@ -102,11 +126,7 @@ hj_status check_params(const hj_params* p, uint64_t n_r, Plan* pl) {
                         p->lds_cap);
         pl->lds_cap = p->lds_cap;
     } else {
-        const double avg = std::ceil((double)n_r / (double)pl->P);
-        double cap = avg + 4.0 * std::sqrt(avg) + 64.0;
-        uint32_t c = (uint32_t)std::min(8192.0, std::max(256.0, cap));
-        pl->lds_cap = (c + 63) / 64 * 64;
-        if (pl->lds_cap > 8192) pl->lds_cap = 8192;
+        pl->lds_cap = auto_lds_cap(n_r, pl->P);
     }
     return HJ_OK;
 }

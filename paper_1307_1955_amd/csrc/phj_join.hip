@@ -50,55 +50,56 @@ __device__ __forceinline__ uint32_t ovf_chunks_of(const PartPair& pp, uint32_t l
     return (pp.r_len > lds_cap && pp.s_len) ? (pp.r_len + kOvfChunk - 1) / kOvfChunk : 0u;
 }
 
-__global__ void __launch_bounds__(kPlanBlock) k_join_plan(
+// Plan, step 1 (one thread per partition pair): ranges of R_i and S_i from the
+// last pass's histogram scan, and the number of work items and of HBM-table
+// build chunks of the pair (temporarily in item_begin / ovf_begin).
+__global__ void __launch_bounds__(256) k_join_pairs(
     const PartSeg* __restrict__ segs, const uint32_t* __restrict__ tile_begin, uint32_t nseg,
     uint32_t bits_last, const uint32_t* __restrict__ hist_scan, uint32_t n_r, uint32_t n_s,
-    uint32_t total_bits, uint32_t lds_cap, PartPair* __restrict__ pairs,
-    uint32_t* __restrict__ item_begin, uint32_t* __restrict__ ovf_begin, uint32_t* __restrict__ item_part,
-    uint32_t* __restrict__ ovf_part, uint64_t* __restrict__ zero_total) {
-    __shared__ uint32_t wt[kPlanBlock / kWave];
+    uint32_t total_bits, uint32_t lds_cap, PartPair* __restrict__ pairs, uint32_t* __restrict__ item_cnt,
+    uint32_t* __restrict__ ovf_cnt, uint64_t* __restrict__ zero_total) {
     const uint32_t P = 1u << total_bits;
     const uint32_t nseg_rel = nseg / 2;
-    // Phase A: start of every partition (independent loads, strided over the block).
-    for (uint32_t i = threadIdx.x; i < P; i += kPlanBlock) {
-        PartPair pp;
-        pp.r_off = min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i, n_r, 0, P), n_r);
-        pp.s_off = min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i, n_s, n_r, P), n_s);
-        pp.r_len = 0;
-        pp.s_len = 0;
-        pairs[i] = pp;
-    }
-    if (threadIdx.x == 0 && zero_total) *zero_total = 0;
-    __syncthreads();
-    // Phase B: lengths and work counts of a contiguous range per thread, then scans.
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && zero_total) *zero_total = 0;
+    if (i >= P) return;
+    const uint32_t r0 = min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i, n_r, 0, P), n_r);
+    const uint32_t s0 = min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i, n_s, n_r, P), n_s);
+    // clamped: a partition never extends past its relation or runs backwards
+    const uint32_t r1 = max(r0, min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i + 1, n_r, 0, P), n_r));
+    const uint32_t s1 = max(s0, min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i + 1, n_s, n_r, P), n_s));
+    PartPair pp;
+    pp.r_off = r0;
+    pp.r_len = r1 - r0;
+    pp.s_off = s0;
+    pp.s_len = s1 - s0;
+    pairs[i] = pp;
+    item_cnt[i] = items_of(pp);
+    ovf_cnt[i] = ovf_chunks_of(pp, lds_cap);
+}
+
+// Plan, step 2 (one block): exclusive scans of the per-pair counts (in place)
+// and the item -> pair maps.
+__global__ void __launch_bounds__(kPlanBlock) k_join_plan(uint32_t P, uint32_t* __restrict__ item_begin,
+                                                         uint32_t* __restrict__ ovf_begin,
+                                                         uint32_t* __restrict__ item_part,
+                                                         uint32_t* __restrict__ ovf_part) {
+    __shared__ uint32_t wt[kPlanBlock / kWave];
     const uint32_t per = (P + kPlanBlock - 1) / kPlanBlock;
     const uint32_t a = min(threadIdx.x * per, P);
     const uint32_t b = min(a + per, P);
     uint32_t items = 0, ovf = 0;
     for (uint32_t i = a; i < b; ++i) {
-        PartPair pp = pairs[i];
-        // clamped: a partition never extends past its relation or runs backwards
-        const uint32_t r1 = max(pp.r_off, i + 1 < P ? pairs[i + 1].r_off : n_r);
-        const uint32_t s1 = max(pp.s_off, i + 1 < P ? pairs[i + 1].s_off : n_s);
-        pp.r_len = r1 - pp.r_off;
-        pp.s_len = s1 - pp.s_off;
-        items += items_of(pp);
-        ovf += ovf_chunks_of(pp, lds_cap);
-        // lengths are written after every thread has read the offsets it needs
-        item_begin[i] = pp.r_len;
-        ovf_begin[i] = pp.s_len;
+        items += item_begin[i];
+        ovf += ovf_begin[i];
     }
     uint32_t tot_items, tot_ovf;
     uint32_t run_i = block_excl_scan(items, wt, &tot_items);
     uint32_t run_o = block_excl_scan(ovf, wt, &tot_ovf);
     for (uint32_t i = a; i < b; ++i) {
-        PartPair pp = pairs[i];
-        pp.r_len = item_begin[i];
-        pp.s_len = ovf_begin[i];
-        pairs[i] = pp;
+        const uint32_t ni = item_begin[i], no = ovf_begin[i];
         item_begin[i] = run_i;
         ovf_begin[i] = run_o;
-        const uint32_t ni = items_of(pp), no = ovf_chunks_of(pp, lds_cap);
         for (uint32_t x = 0; x < ni; ++x) item_part[run_i + x] = i;
         for (uint32_t x = 0; x < no; ++x) ovf_part[run_o + x] = i;
         run_i += ni;
@@ -453,10 +454,15 @@ void write_zero_count(uint64_t* d_count, Recorder& rec) {
 void join_plan(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t bits_last,
                const uint32_t* hist_scan, uint32_t n_r, uint32_t n_s, uint32_t total_bits,
                uint32_t lds_cap, const JoinPlanOut& o, uint64_t* zero_total, Recorder& rec) {
+    const uint32_t P = 1u << total_bits;
+    rec.before("join_pairs");
+    hipLaunchKernelGGL(k_join_pairs, dim3((P + 255) / 256), dim3(256), 0, rec.stream, segs, tile_begin, nseg,
+                       bits_last, hist_scan, n_r, n_s, total_bits, lds_cap, o.pairs, o.item_begin, o.ovf_begin,
+                       zero_total);
+    rec.after();
     rec.before("join_plan");
-    hipLaunchKernelGGL(k_join_plan, dim3(1), dim3(kPlanBlock), 0, rec.stream, segs, tile_begin, nseg,
-                       bits_last, hist_scan, n_r, n_s, total_bits, lds_cap, o.pairs, o.item_begin,
-                       o.ovf_begin, o.item_part, o.ovf_part, zero_total);
+    hipLaunchKernelGGL(k_join_plan, dim3(1), dim3(kPlanBlock), 0, rec.stream, P, o.item_begin, o.ovf_begin,
+                       o.item_part, o.ovf_part);
     rec.after();
 }
 
