@@ -91,7 +91,9 @@ typedef struct hj_out {
 
 /* Join parameters.
    algo    HJ_SHJ or HJ_PHJ.
-   passes  PHJ: number of radix passes, 1 or 2 (ignored by SHJ).
+   passes  PHJ: number of radix passes, 1 or 2; or 0 = no partitioning, for
+           |R| <= 8192: R is one LDS-resident table probed by every S chunk
+           (ignored by SHJ).
    bits    PHJ: radix bits of pass 1 and pass 2.  B = bits[0] (+ bits[1] when
            passes == 2) must be in 1..16 and each used entry in 1..13.  The
            2^B partitions are the values of the B low bits of the hash; pass 1
@@ -143,6 +145,51 @@ hj_status hj_join_timed(const hj_params* p, const hj_rel* R, const hj_rel* S, co
                         void* ws, size_t ws_bytes, uint64_t* d_count, void* stream,
                         const char** names, float* ms, uint32_t max_launches,
                         uint32_t* n_launches);
+
+/* ---- Batched joins ------------------------------------------------------
+   Many independent joins of uneven sizes enqueued together.  A plan fixes the
+   jobs (pointers and sizes) and the per-job parameters; running it enqueues
+   every job on the given stream.  Jobs with PHJ and passes == 0 (R fits one
+   LDS table) run together in one multi-job kernel; the others run their own
+   launch sequences on four concurrent lanes whose workspace slices are reused
+   job after job.  Unless HJ_BATCH_NO_GRAPH is set, the first run with a given
+   workspace captures the whole batch into one HIP graph (on a stream of the
+   plan) and every run launches that graph on the caller's stream. */
+
+/* One join of a batch: R, S, its output buffers and a device uint64 count. */
+typedef struct hj_job {
+    hj_rel R;
+    hj_rel S;
+    hj_out out;
+    uint64_t* d_count;
+} hj_job;
+
+typedef struct hj_batch_plan hj_batch_plan;
+
+/* Enqueue the batch directly on the streams instead of through a HIP graph. */
+#define HJ_BATCH_NO_GRAPH 1u
+
+/* Creates a plan for `njobs` jobs (host array, copied).  params: host array of
+   njobs parameter sets, or NULL for the library's size rule (passes 0 when |R|
+   fits the LDS budget, else PHJ with about 4096 R tuples per partition and
+   HJ_FLAG_ONE_PASS).  Pointers inside the jobs must stay valid while the plan
+   is used.  Allocates pinned host memory and creates streams and events; no
+   device memory. */
+hj_status hj_batch_plan_create(uint32_t njobs, const hj_job* jobs, const hj_params* params, uint32_t flags,
+                               hj_batch_plan** plan);
+
+/* Device workspace bytes hj_batch_run needs for this plan. */
+size_t hj_batch_workspace_bytes(const hj_batch_plan* plan);
+
+/* Number of jobs of the plan that run in the multi-job direct kernel. */
+uint32_t hj_batch_direct_jobs(const hj_batch_plan* plan);
+
+/* Enqueues every job of the plan on `stream` (asynchronous).  Each job's
+   d_count receives its pair count; a job whose count exceeds its capacity
+   writes nothing past its capacity. */
+hj_status hj_batch_run(hj_batch_plan* plan, void* ws, size_t ws_bytes, void* stream);
+
+void hj_batch_plan_destroy(hj_batch_plan* plan);
 
 /* Static description of a status code. */
 const char* hj_status_str(hj_status s);

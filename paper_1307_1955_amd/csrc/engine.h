@@ -1,0 +1,47 @@
+// Join engine shared by the single-join ABI (hj_api.cpp) and the batch
+// executor (batch.cpp).  Host code only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/hj.h"
+#include "hj_internal.h"
+
+namespace hj {
+namespace eng {
+
+constexpr size_t kAlign = 256;
+constexpr uint64_t kMaxRows = 0x7FFFFFFFull;  // n < 2^31
+
+// Thread-local error message of the last failing call.
+const char* last_error();
+void clear_error();
+hj_status fail(hj_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+size_t align_up(size_t x);
+uint64_t cdiv(uint64_t a, uint64_t b);
+
+// Validated parameters of one join.
+struct Plan {
+    bool phj, one_pass;
+    uint32_t passes, b1, b2, B, P1, P2, P, tile, hash, lds_cap;
+};
+
+// Default LDS table capacity for |R| = n_r split into P partitions.
+uint32_t auto_lds_cap(uint64_t n_r, uint32_t P);
+hj_status check_params(const hj_params* p, uint64_t n_r, Plan* pl);
+hj_status check_call(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,
+                     size_t ws_bytes, uint64_t* d_count, Plan* pl);
+size_t ws_bytes_for(const Plan& pl, uint64_t n_r, uint64_t n_s);
+
+// Enqueues one validated join on rec.stream (ws must hold ws_bytes_for bytes).
+void run_join(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
+              uint64_t* d_count, Recorder& rec);
+// check_call + run_join; returns HJ_ERR_DEVICE if a launch failed.
+hj_status launch_join(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,
+                      size_t ws_bytes, uint64_t* d_count, Recorder& rec);
+
+}  // namespace eng
+}  // namespace hj

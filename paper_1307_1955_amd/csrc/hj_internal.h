@@ -126,4 +126,26 @@ void join_write(const PartPair* pairs, const uint32_t* item_begin, const uint32_
 // Writes zero to *d_count (joins with an empty side).
 void write_zero_count(uint64_t* d_count, Recorder& rec);
 
+// ---- direct joins (no partitioning: R fits one LDS table) ----
+// One job of the multi-job direct kernel.  Work item = (job, chunk of
+// kJoinChunk S tuples); items of job j are [item0, item0 + ceil(n_s / chunk)).
+struct DirectJob {
+    const int32_t* rk;
+    const int32_t* rr;
+    const int32_t* sk;
+    const int32_t* sr;
+    int32_t* out_r;
+    int32_t* out_s;
+    uint64_t capacity;
+    uint64_t* count;  // running total of the job's pairs (zeroed by direct_zero)
+    uint32_t n_r, n_s, item0, pad;
+};
+// Writes one job descriptor and item map from kernel arguments and zeroes the
+// job's count (single join).
+void direct_setup_one(DirectJob* job, uint32_t* item_job, const DirectJob& j, uint32_t nitems, Recorder& rec);
+void direct_zero(const DirectJob* jobs, uint32_t njobs, Recorder& rec);
+// lds_cap >= every job's n_r (<= kMaxLdsCap).
+void direct_join(const DirectJob* jobs, const uint32_t* item_job, uint32_t nitems, uint32_t lds_cap,
+                 Recorder& rec);
+
 }  // namespace hj

@@ -435,6 +435,82 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_write(
     }
 }
 
+// Joins whose whole R fits one LDS table, several jobs per launch: one
+// workgroup per (job, S chunk) builds the table over the job's R and writes
+// the chunk's pairs to the job's output with one-pass reservation.
+__global__ void __launch_bounds__(kJoinBlock) k_direct_join(const DirectJob* __restrict__ jobs,
+                                                           const uint32_t* __restrict__ item_job,
+                                                           uint32_t lds_cap) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint64_t wtot[kJoinWaves + 1];
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    const uint32_t item = xcd_remap(blockIdx.x, gridDim.x);
+    const DirectJob J = jobs[item_job[item]];
+    const uint32_t s_begin = (item - J.item0) * kJoinChunk;
+    const uint32_t s_n = min(kJoinChunk, J.n_s - s_begin);
+    const uint32_t r_len = min(J.n_r, lds_cap);  // the planner guarantees n_r <= lds_cap
+    const uint32_t wb = w * kSubJ;
+    const uint32_t we = min(wb + kSubJ, s_n);
+    int32_t q[kSU], qr[kSU];
+    load_s<true>(J.sk + s_begin, J.sr + s_begin, wb, we, q, qr);
+    const LdsView v = lds_view(lds, lds_cap, true);
+    const uint32_t log2H = floor_log2_min6(r_len);
+    build_lds<true>(J.rk, J.rr, r_len, log2H, v.bcnt, v.skey, v.srid, v.ctot);
+    uint32_t c[kSU], lo[kSU], hi[kSU];
+    bucket_runs(v.bcnt, log2H, r_len, q, wb, we, lo, hi);
+    uint64_t mine = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        c[u] = 0;
+        for (uint32_t x = lo[u]; x < hi[u]; ++x) c[u] += (v.skey[x] == q[u]);
+        mine += c[u];
+    }
+    mine = wave_sum(mine);
+    if (lane == 0) wtot[w] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (uint32_t i = 0; i < kJoinWaves; ++i) t += wtot[i];
+        wtot[kJoinWaves] = t ? atomicAdd((unsigned long long*)J.count, (unsigned long long)t) : 0ull;
+    }
+    __syncthreads();
+    uint64_t pos0 = wtot[kJoinWaves];
+    for (uint32_t i = 0; i < w; ++i) pos0 += wtot[i];
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        uint64_t excl, wtotal;
+        wave_offsets(c[u], &excl, &wtotal);
+        uint64_t pos = pos0 + excl;
+        pos0 += wtotal;
+        if (c[u]) {
+            for (uint32_t x = lo[u]; x < hi[u]; ++x) {
+                if (v.skey[x] == q[u]) {
+                    if (pos < J.capacity) {
+                        J.out_r[pos] = v.srid[x];
+                        J.out_s[pos] = qr[u];
+                    }
+                    ++pos;
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_direct_zero(const DirectJob* __restrict__ jobs, uint32_t njobs) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < njobs; j += gridDim.x * blockDim.x)
+        *jobs[j].count = 0;
+}
+
+__global__ void k_direct_setup_one(DirectJob* job, uint32_t* item_job, DirectJob j, uint32_t nitems) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *job = j;
+        *j.count = 0;
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nitems; i += gridDim.x * blockDim.x)
+        item_job[i] = 0;
+}
+
 __global__ void k_write_zero(uint64_t* p) {
     if (threadIdx.x == 0) *p = 0;
 }
@@ -443,6 +519,31 @@ __global__ void k_write_zero(uint64_t* p) {
 
 size_t join_lds_bytes(uint32_t lds_cap, bool write) {
     return sizeof(uint32_t) * ((size_t)lds_cap + kWave + (size_t)lds_cap * (write ? 2 : 1) + kScanScratch);
+}
+
+void direct_setup_one(DirectJob* job, uint32_t* item_job, const DirectJob& j, uint32_t nitems, Recorder& rec) {
+    rec.before("direct_setup");
+    hipLaunchKernelGGL(k_direct_setup_one, dim3(1), dim3(256), 0, rec.stream, job, item_job, j, nitems);
+    rec.after();
+}
+
+void direct_zero(const DirectJob* jobs, uint32_t njobs, Recorder& rec) {
+    if (njobs == 0) return;
+    rec.before("direct_zero");
+    hipLaunchKernelGGL(k_direct_zero, dim3((njobs + 255) / 256), dim3(256), 0, rec.stream, jobs, njobs);
+    rec.after();
+}
+
+void direct_join(const DirectJob* jobs, const uint32_t* item_job, uint32_t nitems, uint32_t lds_cap,
+                 Recorder& rec) {
+    if (nitems == 0) return;
+    const size_t lds = join_lds_bytes(lds_cap, true);
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)k_direct_join, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    rec.before("direct_join");
+    hipLaunchKernelGGL(k_direct_join, dim3(nitems), dim3(kJoinBlock), lds, rec.stream, jobs, item_job, lds_cap);
+    rec.after();
 }
 
 void write_zero_count(uint64_t* d_count, Recorder& rec) {

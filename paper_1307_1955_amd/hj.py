@@ -30,10 +30,13 @@ HJ_HASH_IDENTITY = 0
 HJ_HASH_MURMUR2 = 1
 HJ_FLAG_ONE_PASS = 1
 
+HJ_BATCH_NO_GRAPH = 1
+
 # Every symbol include/hj.h declares.
 EXPORTED = (
     "hj_default_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
-    "hj_status_str", "hj_last_error", "hj_version",
+    "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_run",
+    "hj_batch_plan_destroy", "hj_status_str", "hj_last_error", "hj_version",
 )
 
 
@@ -56,6 +59,10 @@ class HjParams(ctypes.Structure):
         return ("HjParams(algo=%s, passes=%d, bits=(%d, %d), hash=%d, tile=%d, lds_cap=%d, flags=%d)" % (
             "phj" if self.algo == HJ_PHJ else "shj", self.passes, self.bits[0], self.bits[1],
             self.hash, self.tile, self.lds_cap, self.flags))
+
+
+class HjJob(ctypes.Structure):
+    _fields_ = [("R", HjRel), ("S", HjRel), ("out", HjOut), ("d_count", ctypes.c_void_p)]
 
 
 class HJError(RuntimeError):
@@ -99,6 +106,17 @@ def load() -> ctypes.CDLL:
             lib.hj_last_error.argtypes = []
             lib.hj_version.restype = ctypes.c_uint32
             lib.hj_version.argtypes = []
+            lib.hj_batch_plan_create.restype = ctypes.c_int
+            lib.hj_batch_plan_create.argtypes = [ctypes.c_uint32, P(HjJob), P(HjParams), ctypes.c_uint32,
+                                                 P(ctypes.c_void_p)]
+            lib.hj_batch_workspace_bytes.restype = ctypes.c_size_t
+            lib.hj_batch_workspace_bytes.argtypes = [ctypes.c_void_p]
+            lib.hj_batch_direct_jobs.restype = ctypes.c_uint32
+            lib.hj_batch_direct_jobs.argtypes = [ctypes.c_void_p]
+            lib.hj_batch_run.restype = ctypes.c_int
+            lib.hj_batch_run.argtypes = [ctypes.c_void_p, vp, ctypes.c_size_t, vp]
+            lib.hj_batch_plan_destroy.restype = None
+            lib.hj_batch_plan_destroy.argtypes = [ctypes.c_void_p]
             _lib = lib
     return _lib
 
@@ -250,3 +268,67 @@ def join(r_key, r_rid, s_key, s_rid, p: HjParams | None = None, capacity: int | 
         cnt2 = hj_join_sync(p, r_key, r_rid, s_key, s_rid, out_r, out_s, ws, d_count, stream)
         assert cnt2 == cnt
     return out_r[:cnt], out_s[:cnt], cnt
+
+
+# ---------------------------------------------------------------------------
+# Batches
+# ---------------------------------------------------------------------------
+
+
+class BatchPlan:
+    """``hj_batch_plan`` over jobs given as tensors.
+
+    jobs: sequence of (r_key, r_rid, s_key, s_rid, out_r, out_s) CUDA tensors;
+    d_counts: int64 CUDA tensor with one element per job (job j's count is
+    d_counts[j]); params: sequence of HjParams (one per job) or None for the
+    library's size rule; graph=False enqueues without a HIP graph.
+    The tensors must stay alive while the plan is used."""
+
+    def __init__(self, jobs, d_counts: torch.Tensor, params=None, graph: bool = True):
+        if d_counts.dtype != torch.int64 or not d_counts.is_cuda or d_counts.numel() < len(jobs):
+            raise ValueError("d_counts must be an int64 CUDA tensor with one element per job")
+        n = len(jobs)
+        self._keep = (jobs, d_counts)
+        arr = (HjJob * max(n, 1))()
+        base = d_counts.data_ptr()
+        for j, (rk, rr, sk, sr, o_r, o_s) in enumerate(jobs):
+            arr[j].R = _rel(rk, rr, "R")
+            arr[j].S = _rel(sk, sr, "S")
+            arr[j].out = _out(o_r, o_s)
+            arr[j].d_count = base + 8 * j
+        pp = None
+        if params is not None:
+            if len(params) != n:
+                raise ValueError("one HjParams per job")
+            parr = (HjParams * max(n, 1))(*params)
+            pp = parr
+        h = ctypes.c_void_p()
+        _check(load().hj_batch_plan_create(n, arr, pp, 0 if graph else HJ_BATCH_NO_GRAPH, ctypes.byref(h)))
+        self._h = h
+        self.njobs = n
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(load().hj_batch_workspace_bytes(self._h))
+
+    @property
+    def direct_jobs(self) -> int:
+        return int(load().hj_batch_direct_jobs(self._h))
+
+    def workspace(self, device="cuda") -> torch.Tensor:
+        return torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
+
+    def run(self, ws: torch.Tensor, stream=None) -> None:
+        wp, wb = _ws(ws)
+        _check(load().hj_batch_run(self._h, wp, wb, _stream(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().hj_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
