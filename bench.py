@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-shj", action="store_true", help="skip the SHJ line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="also time every radix configuration")
+    ap.add_argument("--batch-jobs", type=int, default=4096, help="jobs of the batched workload (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -96,6 +98,57 @@ def summarize(acc, reps, n_r, n_s, m):
             row["gbs"] = round(ab / (avg * 1e-3) / 1e9, 1)
         rows[name] = row
     return rows
+
+
+def bench_batched(args, torch, hj) -> dict:
+    """4096 joins of log-uniform sizes: one graph-captured batch vs plain per-join calls."""
+    from paper_1307_1955_amd import tune, workloads
+    print("bench: building the batched workload (%d jobs) in HBM" % args.batch_jobs, file=sys.stderr, flush=True)
+    wl = workloads.batch_workload(njobs=args.batch_jobs)
+    table = tune.load_table()
+    params = workloads.tuned_params(wl.specs, table)
+    plan = hj.BatchPlan(wl.jobs, wl.d_counts, params=params)
+    ws = plan.workspace()
+    expected = torch.tensor(wl.expected, dtype=torch.int64, device="cuda")
+    print("bench: batch plan: %d direct jobs, workspace %.2f GB; capturing the graph" % (
+        plan.direct_jobs, plan.workspace_bytes / 1e9), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    plan.run(ws)
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
+    ok = bool(torch.equal(wl.d_counts, expected))
+    ms = time_steps(lambda: plan.run(ws), args.batch_steps, 0, torch)
+    ok = ok and bool(torch.equal(wl.d_counts, expected))
+    # the same jobs through plain per-join calls on one stream, one workspace
+    print("bench: plain per-join path", file=sys.stderr, flush=True)
+    ws_one = torch.empty(max(hj.hj_workspace_bytes(q, sp.n_r, sp.n_s) for q, sp in zip(params, wl.specs)),
+                         dtype=torch.uint8, device="cuda")
+    d_one = torch.zeros(1, dtype=torch.int64, device="cuda")
+    one_counts = torch.zeros(len(wl.jobs), dtype=torch.int64, device="cuda")
+
+    def plain():
+        for j, (job, q) in enumerate(zip(wl.jobs, params)):
+            hj.hj_join(q, *job, ws_one, one_counts[j:j + 1])
+
+    ms_plain = time_steps(plain, 1, 1, torch)
+    same = bool(torch.equal(one_counts, expected))
+    del d_one
+    res = {
+        "metric": "joins/s", "value": len(wl.jobs) / (ms * 1e-3), "jobs": len(wl.jobs), "ms_per_batch": ms,
+        "tuples_per_s": wl.tuples / (ms * 1e-3),
+        "config": "4096 joins, |R| log-uniform in [1024, 4194304], |S| = |R| x U{1..16}, 25-100%% match; "
+                  "sum |R|+|S| = %d tuples, %d pairs" % (wl.tuples, wl.pairs),
+        "params": "tuning table" if table else "cost model",
+        "direct_jobs": plan.direct_jobs, "graph": True, "first_run_s_incl_capture": round(first_s, 3),
+        "counts_match_closed_form": ok,
+        "plain_per_join": {"value": len(wl.jobs) / (ms_plain * 1e-3), "ms": ms_plain,
+                           "counts_match_closed_form": same},
+        "speedup_vs_plain": ms_plain / ms,
+    }
+    plan.close()
+    del ws, ws_one, wl
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(n: int) -> dict:
@@ -217,6 +270,10 @@ def main():
                     print("bench: sweep %s" % sweep[-1], file=sys.stderr, flush=True)
                     del wq
         result["sweep"] = sweep
+    if args.batch_jobs:
+        del ws, out_r, out_s, t
+        torch.cuda.empty_cache()
+        result["batched"] = bench_batched(args, torch, hj)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(n)
