@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--sweep", action="store_true", help="also time every radix configuration")
     ap.add_argument("--batch-jobs", type=int, default=4096, help="jobs of the batched workload (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=12288, help="requests per served level (0: skip)")
+    ap.add_argument("--serve-warmup", type=int, default=2048)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -100,13 +102,8 @@ def summarize(acc, reps, n_r, n_s, m):
     return rows
 
 
-def bench_batched(args, torch, hj) -> dict:
+def bench_batched(args, torch, hj, wl, params, table) -> dict:
     """4096 joins of log-uniform sizes: one graph-captured batch vs plain per-join calls."""
-    from paper_1307_1955_amd import tune, workloads
-    print("bench: building the batched workload (%d jobs) in HBM" % args.batch_jobs, file=sys.stderr, flush=True)
-    wl = workloads.batch_workload(njobs=args.batch_jobs)
-    table = tune.load_table()
-    params = workloads.tuned_params(wl.specs, table)
     plan = hj.BatchPlan(wl.jobs, wl.d_counts, params=params)
     ws = plan.workspace()
     expected = torch.tensor(wl.expected, dtype=torch.int64, device="cuda")
@@ -146,9 +143,97 @@ def bench_batched(args, torch, hj) -> dict:
         "speedup_vs_plain": ms_plain / ms,
     }
     plan.close()
-    del ws, ws_one, wl
+    del ws, ws_one
     torch.cuda.empty_cache()
     return res
+
+
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def bench_served(args, torch, hj, wl, params, qps_levels) -> dict:
+    """Open-loop Poisson arrivals of requests drawn from the batched workload,
+    served with continuous batching under a 64 GiB footprint cap, against the
+    same trace through plain per-join calls run serially."""
+    import ctypes
+
+    from paper_1307_1955_amd import gen
+    njobs = len(wl.jobs)
+    n = args.serve_requests
+    warm = min(args.serve_warmup, n // 2)
+    ws_max = max(hj.hj_workspace_bytes(q, sp.n_r, sp.n_s) for q, sp in zip(params, wl.specs))
+    slots = 4
+    pool = torch.empty(slots * (ws_max + (64 << 20)), dtype=torch.uint8, device="cuda")
+    jobs = [hj.make_job(*wl.jobs[j], wl.d_counts.data_ptr() + 8 * j) for j in range(njobs)]
+    fps = [8 * (sp.n_r + sp.n_s) + 8 * e + hj.hj_workspace_bytes(q, sp.n_r, sp.n_s)
+           for sp, e, q in zip(wl.specs, wl.expected, params)]
+    lib = hj.load()
+    out = {"requests": n, "warmup_requests": warm, "cap_bytes": 64 << 30, "slots": slots, "levels": []}
+    for qps in qps_levels:
+        arr = gen.poisson_arrivals(17, n, qps)
+        sv = hj.Server(pool, mem_cap_bytes=64 << 30, slots=slots, max_batch_jobs=64)
+        ticket = ctypes.c_uint64(0)
+        lag = []
+        submit_t = [0.0] * n
+        print("bench: serving %d requests at %.0f/s" % (n, qps), file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        for i in range(n):
+            target = t0 + arr[i]
+            while time.perf_counter() < target:
+                pass
+            now = time.perf_counter()
+            j = i % njobs
+            st = lib.hj_server_submit(sv._h, ctypes.byref(jobs[j]), ctypes.byref(params[j]), fps[j],
+                                      ctypes.byref(ticket))
+            if st != 0:
+                raise RuntimeError("submit failed: %s" % lib.hj_last_error().decode())
+            submit_t[i] = now - t0
+            lag.append(now - target)
+        sv.drain()
+        done = sv.poll(n + 16)
+        stats = sv.stats()
+        sv.close()
+        by_ticket = {t: (s_, lat, q_) for t, s_, lat, q_ in done}
+        # tickets are issued 1..n in submission order
+        lat = [by_ticket[i + 1][1] for i in range(warm, n)]
+        ends = [submit_t[i] + by_ticket[i + 1][1] for i in range(warm, n)]
+        span = max(ends) - arr[warm]
+        ok = all(by_ticket[i + 1][0] == 0 for i in range(n))
+        # the same trace through plain per-join calls, one at a time
+        print("bench: plain per-join serial path at %.0f/s" % qps, file=sys.stderr, flush=True)
+        ws_one = pool[: ws_max]
+        lat_plain = []
+        h = ctypes.c_uint64(0)
+        t0 = time.perf_counter()
+        for i in range(n):
+            target = t0 + arr[i]
+            while time.perf_counter() < target:
+                pass
+            j = i % njobs
+            st = lib.hj_join_sync(ctypes.byref(params[j]), ctypes.byref(jobs[j].R), ctypes.byref(jobs[j].S),
+                                  ctypes.byref(jobs[j].out), ws_one.data_ptr(), ws_max, jobs[j].d_count,
+                                  ctypes.byref(h), torch.cuda.current_stream().cuda_stream)
+            if st != 0:
+                raise RuntimeError("plain join failed: %s" % lib.hj_last_error().decode())
+            if i >= warm:
+                lat_plain.append(time.perf_counter() - target)
+        span_plain = time.perf_counter() - (t0 + arr[warm])
+        ok = ok and bool(torch.equal(wl.d_counts, torch.tensor(wl.expected, dtype=torch.int64, device="cuda")))
+        out["levels"].append({
+            "offered_qps": qps,
+            "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
+            "throughput_joins_per_s": (n - warm) / span,
+            "batches": stats["batches"], "rejected": stats["rejected"],
+            "max_submit_lag_ms": max(lag) * 1e3, "all_ok": ok,
+            "plain_serial": {"p50_ms": percentile(lat_plain, 50) * 1e3, "p99_ms": percentile(lat_plain, 99) * 1e3,
+                             "throughput_joins_per_s": (n - warm) / span_plain},
+        })
+        print("bench: served %s" % out["levels"][-1], file=sys.stderr, flush=True)
+    del pool
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(n: int) -> dict:
@@ -273,7 +358,17 @@ def main():
     if args.batch_jobs:
         del ws, out_r, out_s, t
         torch.cuda.empty_cache()
-        result["batched"] = bench_batched(args, torch, hj)
+        from paper_1307_1955_amd import tune, workloads
+        print("bench: building the batched workload (%d jobs) in HBM" % args.batch_jobs, file=sys.stderr, flush=True)
+        wl = workloads.batch_workload(njobs=args.batch_jobs)
+        table = tune.load_table()
+        params = workloads.tuned_params(wl.specs, table)
+        result["batched"] = bench_batched(args, torch, hj, wl, params, table)
+        if args.serve_requests:
+            rate = result["batched"]["value"]
+            result["served"] = bench_served(args, torch, hj, wl, params, [0.5 * rate, 0.8 * rate])
+        del wl
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(n)

@@ -191,6 +191,56 @@ hj_status hj_batch_run(hj_batch_plan* plan, void* ws, size_t ws_bytes, void* str
 
 void hj_batch_plan_destroy(hj_batch_plan* plan);
 
+/* ---- Serving ------------------------------------------------------------
+   A server accepts join requests as they arrive (from any thread) and runs
+   them with continuous batching: a dispatcher thread owns `slots` streams;
+   whenever a slot is idle it admits waiting requests, first come first
+   served, while the summed footprints of all requests on the device stay
+   within mem_cap_bytes, and runs them there as one batch (requests with PHJ
+   and passes == 0 together in the multi-job direct kernel, the others one
+   after another).  Batches on different slots overlap on the device, and a
+   finished batch frees its footprint and its slot for the next requests.
+   The server's device workspace (split evenly between the slots) comes from
+   the caller; the inputs of every request stay resident in device memory
+   until the request completes. */
+
+typedef struct hj_server hj_server;
+
+typedef struct hj_server_config {
+    uint64_t mem_cap_bytes;   /* admission cap on the summed request footprints */
+    uint32_t slots;           /* concurrent batches (streams), 1..16 */
+    uint32_t max_batch_jobs;  /* requests admitted into one batch */
+    uint32_t flags;           /* must be 0 */
+} hj_server_config;
+
+/* Starts a server.  ws: device workspace (256-byte aligned) shared by the
+   slots; a request whose hj_workspace_bytes exceeds a slot's share is
+   rejected.  Creates streams, events, pinned host staging and one thread. */
+hj_status hj_server_create(const hj_server_config* cfg, void* ws, size_t ws_bytes, hj_server** server);
+
+/* Queues one request (thread-safe, returns at once).  footprint: the bytes the
+   request holds on the device while admitted (inputs, output, workspace), as
+   the caller accounts them.  *ticket identifies it in hj_server_poll. */
+hj_status hj_server_submit(hj_server* server, const hj_job* job, const hj_params* params, uint64_t footprint,
+                           uint64_t* ticket);
+
+/* Moves up to `max` finished requests out of the server: ticket, status
+   (HJ_OK, HJ_ERR_CAPACITY if rejected by admission, HJ_ERR_DEVICE), seconds
+   from submission to completion and from submission to admission.  *n gets
+   the number returned.  Returns a device error if the server has stopped. */
+hj_status hj_server_poll(hj_server* server, uint64_t* tickets, int32_t* status, double* latency_s,
+                         double* queue_s, uint32_t max, uint32_t* n);
+
+/* Blocks until every submitted request has finished. */
+hj_status hj_server_drain(hj_server* server);
+
+/* Counters: requests completed and rejected, batches launched, footprint bytes now admitted. */
+hj_status hj_server_stats(hj_server* server, uint64_t* completed, uint64_t* rejected, uint64_t* batches,
+                          uint64_t* bytes_in_use);
+
+/* Finishes the queued requests, stops the dispatcher and frees the server. */
+void hj_server_destroy(hj_server* server);
+
 /* Static description of a status code. */
 const char* hj_status_str(hj_status s);
 

@@ -36,7 +36,8 @@ HJ_BATCH_NO_GRAPH = 1
 EXPORTED = (
     "hj_default_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
     "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_run",
-    "hj_batch_plan_destroy", "hj_status_str", "hj_last_error", "hj_version",
+    "hj_batch_plan_destroy", "hj_server_create", "hj_server_submit", "hj_server_poll", "hj_server_drain",
+    "hj_server_stats", "hj_server_destroy", "hj_status_str", "hj_last_error", "hj_version",
 )
 
 
@@ -63,6 +64,11 @@ class HjParams(ctypes.Structure):
 
 class HjJob(ctypes.Structure):
     _fields_ = [("R", HjRel), ("S", HjRel), ("out", HjOut), ("d_count", ctypes.c_void_p)]
+
+
+class HjServerConfig(ctypes.Structure):
+    _fields_ = [("mem_cap_bytes", ctypes.c_uint64), ("slots", ctypes.c_uint32),
+                ("max_batch_jobs", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class HJError(RuntimeError):
@@ -117,6 +123,21 @@ def load() -> ctypes.CDLL:
             lib.hj_batch_run.argtypes = [ctypes.c_void_p, vp, ctypes.c_size_t, vp]
             lib.hj_batch_plan_destroy.restype = None
             lib.hj_batch_plan_destroy.argtypes = [ctypes.c_void_p]
+            lib.hj_server_create.restype = ctypes.c_int
+            lib.hj_server_create.argtypes = [P(HjServerConfig), vp, ctypes.c_size_t, P(ctypes.c_void_p)]
+            lib.hj_server_submit.restype = ctypes.c_int
+            lib.hj_server_submit.argtypes = [ctypes.c_void_p, P(HjJob), P(HjParams), ctypes.c_uint64,
+                                             P(ctypes.c_uint64)]
+            lib.hj_server_poll.restype = ctypes.c_int
+            lib.hj_server_poll.argtypes = [ctypes.c_void_p, P(ctypes.c_uint64), P(ctypes.c_int32),
+                                           P(ctypes.c_double), P(ctypes.c_double), ctypes.c_uint32,
+                                           P(ctypes.c_uint32)]
+            lib.hj_server_drain.restype = ctypes.c_int
+            lib.hj_server_drain.argtypes = [ctypes.c_void_p]
+            lib.hj_server_stats.restype = ctypes.c_int
+            lib.hj_server_stats.argtypes = [ctypes.c_void_p] + [P(ctypes.c_uint64)] * 4
+            lib.hj_server_destroy.restype = None
+            lib.hj_server_destroy.argtypes = [ctypes.c_void_p]
             _lib = lib
     return _lib
 
@@ -326,6 +347,82 @@ class BatchPlan:
         if getattr(self, "_h", None):
             load().hj_batch_plan_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+
+
+def make_job(r_key, r_rid, s_key, s_rid, out_r, out_s, d_count_ptr: int) -> HjJob:
+    """An hj_job over tensors; d_count_ptr is the device address of its uint64 count."""
+    j = HjJob()
+    j.R = _rel(r_key, r_rid, "R")
+    j.S = _rel(s_key, s_rid, "S")
+    j.out = _out(out_r, out_s)
+    j.d_count = d_count_ptr
+    return j
+
+
+class Server:
+    """``hj_server``: continuous batching of join requests (see include/hj.h)."""
+
+    def __init__(self, ws: torch.Tensor, mem_cap_bytes: int, slots: int = 4, max_batch_jobs: int = 64):
+        cfg = HjServerConfig(mem_cap_bytes, slots, max_batch_jobs, 0)
+        wp, wb = _ws(ws)
+        h = ctypes.c_void_p()
+        _check(load().hj_server_create(ctypes.byref(cfg), wp, wb, ctypes.byref(h)))
+        self._h = h
+        self._ws = ws
+        self._keep = {}
+
+    def submit_job(self, job: HjJob, params: HjParams, footprint: int, keep=None) -> int:
+        """Queues a prepared HjJob; `keep` holds tensors alive until the request is polled."""
+        t = ctypes.c_uint64(0)
+        _check(load().hj_server_submit(self._h, ctypes.byref(job), ctypes.byref(params), footprint,
+                                       ctypes.byref(t)))
+        if keep is not None:
+            self._keep[t.value] = keep
+        return int(t.value)
+
+    def submit(self, r_key, r_rid, s_key, s_rid, out_r, out_s, d_count: torch.Tensor, params: HjParams,
+               footprint: int) -> int:
+        job = make_job(r_key, r_rid, s_key, s_rid, out_r, out_s, d_count.data_ptr())
+        return self.submit_job(job, params, footprint, keep=(r_key, r_rid, s_key, s_rid, out_r, out_s, d_count))
+
+    def poll(self, max_n: int = 4096):
+        """Finished requests: list of (ticket, status, latency_s, queue_s)."""
+        tk = (ctypes.c_uint64 * max_n)()
+        st = (ctypes.c_int32 * max_n)()
+        lat = (ctypes.c_double * max_n)()
+        qu = (ctypes.c_double * max_n)()
+        n = ctypes.c_uint32(0)
+        _check(load().hj_server_poll(self._h, tk, st, lat, qu, max_n, ctypes.byref(n)))
+        out = [(int(tk[i]), int(st[i]), float(lat[i]), float(qu[i])) for i in range(n.value)]
+        for t, *_ in out:
+            self._keep.pop(t, None)
+        return out
+
+    def drain(self) -> None:
+        _check(load().hj_server_drain(self._h))
+
+    def stats(self) -> dict:
+        v = [ctypes.c_uint64(0) for _ in range(4)]
+        _check(load().hj_server_stats(self._h, *[ctypes.byref(x) for x in v]))
+        return {"completed": v[0].value, "rejected": v[1].value, "batches": v[2].value,
+                "bytes_in_use": v[3].value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().hj_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:
