@@ -163,10 +163,13 @@ constexpr uint32_t kSU = kSubJ / kWave;              // S tuples per lane of an 
 // bucket b holds skey/srid[bcnt[b] .. bcnt[b+1]).  H = 2^log2H buckets; bcnt has
 // H + 1 entries.  Each R tuple is loaded once: its bucket and its rank inside
 // the bucket (from the counting atomic) stay in a register until placement.
+// The per-tuple LDS operations carry no branches (lanes past n use a private
+// spare counter, `spare`, and clamped addresses), so a wave keeps all of its
+// LDS atomics and reads in flight instead of waiting on each one.
 template <bool kRids>
 __device__ __forceinline__ void build_lds(const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
-                                          uint32_t n, uint32_t log2H, uint32_t* bcnt, int32_t* skey,
-                                          int32_t* srid, uint32_t* ctot) {
+                                          uint32_t n, uint32_t log2H, uint32_t* bcnt, uint32_t* spare,
+                                          int32_t* skey, int32_t* srid, uint32_t* ctot) {
     const uint32_t H = 1u << log2H;
     const uint32_t sh = 32 - log2H;
     int32_t k[kRU], r[kRU];
@@ -179,27 +182,31 @@ __device__ __forceinline__ void build_lds(const int32_t* __restrict__ rk, const 
     }
     for (uint32_t x = threadIdx.x; x <= H; x += kJoinBlock) bcnt[x] = 0;
     __syncthreads();
+    // Every lane issues all kRU counting atomics back to back (lanes past n
+    // count into their own spare word), and only then consumes the ranks.
+    uint32_t bk[kRU], old[kRU];
 #pragma unroll
     for (uint32_t u = 0; u < kRU; ++u) {
         const uint32_t j = u * kJoinBlock + threadIdx.x;
-        if (j < n) {
-            const uint32_t b = slot_hash(k[u]) >> sh;
-            br[u] = (b << 16) | atomicAdd(&bcnt[b], 1u);  // b < 2^13, rank < 2^13
-        }
+        bk[u] = slot_hash(k[u]) >> sh;
+        old[u] = atomicAdd(j < n ? &bcnt[bk[u]] : &spare[lane_id()], 1u);
     }
+#pragma unroll
+    for (uint32_t u = 0; u < kRU; ++u) br[u] = (bk[u] << 16) | old[u];  // b < 2^13, rank < 2^13
     __syncthreads();
     lds_excl_scan(bcnt, H, ctot);
     if (threadIdx.x == 0) bcnt[H] = n;
     __syncthreads();
+    uint32_t start[kRU];
+#pragma unroll
+    for (uint32_t u = 0; u < kRU; ++u) start[u] = bcnt[br[u] >> 16];
 #pragma unroll
     for (uint32_t u = 0; u < kRU; ++u) {
         const uint32_t j = u * kJoinBlock + threadIdx.x;
-        if (j < n) {
-            const uint32_t pos = bcnt[br[u] >> 16] + (br[u] & 0xFFFFu);
-            if (pos < n) {  // always true for a correct scan; keeps LDS writes inside R_i's run
-                skey[pos] = k[u];
-                if (kRids) srid[pos] = r[u];
-            }
+        const uint32_t pos = start[u] + (br[u] & 0xFFFFu);
+        if (j < n && pos < n) {  // pos < n always holds for a correct scan
+            skey[pos] = k[u];
+            if (kRids) srid[pos] = r[u];
         }
     }
     __syncthreads();
@@ -227,9 +234,11 @@ __device__ __forceinline__ ItemLoc locate_item(const PartPair* __restrict__ pair
     return L;
 }
 
-// LDS layout of the join kernels: bcnt[cap + 64] | skey[cap] | srid[cap] (write) | ctot[kScanScratch]
+// LDS layout of the join kernels:
+//   bcnt[cap + 64] | spare[64] | skey[cap] | srid[cap] (write) | ctot[kScanScratch]
 struct LdsView {
     uint32_t* bcnt;
+    uint32_t* spare;
     int32_t* skey;
     int32_t* srid;
     uint32_t* ctot;
@@ -238,7 +247,8 @@ struct LdsView {
 __device__ __forceinline__ LdsView lds_view(uint32_t* lds, uint32_t cap, bool rids) {
     LdsView v;
     v.bcnt = lds;
-    v.skey = (int32_t*)(lds + cap + kWave);
+    v.spare = lds + cap + kWave;
+    v.skey = (int32_t*)(v.spare + kWave);
     v.srid = v.skey + cap;
     v.ctot = (uint32_t*)(v.skey + (rids ? 2 : 1) * cap);
     return v;
@@ -261,23 +271,66 @@ __device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const in
     }
 }
 
-// First and one-past-last position of the bucket run of every S key of this
-// lane (empty for lanes past the item's end).  All 2*kSU LDS reads are issued
-// before any key is compared.  Clamped to [0, n] so a run never leaves R_i.
-__device__ __forceinline__ void bucket_runs(const uint32_t* bcnt, uint32_t log2H, uint32_t n, const int32_t* q,
-                                            uint32_t wb, uint32_t we, uint32_t* lo, uint32_t* hi) {
+// p1-p4 for the lane's kSU S keys against the LDS table, without branches per
+// key: the bucket bounds of all keys are read first, then the keys' runs are
+// walked in lockstep (step i reads entry lo[u] + i of every key's run, clamped
+// to a valid address), so each step keeps kSU LDS reads in flight and a wave
+// runs only as many steps as its longest run.  c[u] = matches of key u;
+// first[u] = position of its first match (meaningful when c[u] > 0); lo/hi its
+// bucket run, clamped to [0, n].
+__device__ __forceinline__ void probe_lds(const uint32_t* bcnt, const int32_t* skey, uint32_t log2H, uint32_t n,
+                                          const int32_t* q, uint32_t wb, uint32_t we, uint32_t* lo, uint32_t* hi,
+                                          uint32_t* c, uint32_t* first) {
     const uint32_t sh = 32 - log2H;
+    uint32_t len = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
-        const bool ok = wb + u * kWave + lane_id() < we;
         const uint32_t b = slot_hash(q[u]) >> sh;
-        lo[u] = ok ? bcnt[b] : 0u;
-        hi[u] = ok ? bcnt[b + 1] : 0u;
+        lo[u] = bcnt[b];
+        hi[u] = bcnt[b + 1];
     }
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
-        hi[u] = min(hi[u], n);
+        const bool ok = wb + u * kWave + lane_id() < we;
+        hi[u] = ok ? min(hi[u], n) : 0u;
         lo[u] = min(lo[u], hi[u]);
+        len = max(len, hi[u] - lo[u]);
+        c[u] = 0;
+        first[u] = 0;
+    }
+    for (uint32_t i = 0; i < len; ++i) {
+        int32_t v[kSU];
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) v[u] = skey[lo[u] + i < hi[u] ? lo[u] + i : 0u];
+        __builtin_amdgcn_sched_barrier(0);  // keep the kSU reads of a step together, in flight at once
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) {
+            const bool hit = lo[u] + i < hi[u] && v[u] == q[u];
+            first[u] = (hit && c[u] == 0) ? lo[u] + i : first[u];
+            c[u] += hit;
+        }
+    }
+}
+
+// Writes the c >= 1 matches of `key` found from position `first` of its bucket
+// run (ending at hi) to out[pos ...]; the common single match is one store.
+__device__ __forceinline__ void write_lds_matches(const LdsView& v, int32_t key, int32_t rs, uint32_t first,
+                                                  uint32_t hi, uint32_t c, uint64_t pos, uint64_t capacity,
+                                                  int32_t* __restrict__ out_r, int32_t* __restrict__ out_s) {
+    if (pos < capacity) {
+        out_r[pos] = v.srid[first];
+        out_s[pos] = rs;
+    }
+    if (c == 1) return;
+    ++pos;
+    for (uint32_t x = first + 1; x < hi; ++x) {
+        if (v.skey[x] == key) {
+            if (pos < capacity) {
+                out_r[pos] = v.srid[x];
+                out_s[pos] = rs;
+            }
+            ++pos;
+        }
     }
 }
 
@@ -305,14 +358,11 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
     if (L.pp.r_len <= lds_cap) {
         const LdsView v = lds_view(lds, lds_cap, false);
         const uint32_t log2H = floor_log2_min6(L.pp.r_len);
-        build_lds<false>(rk + L.pp.r_off, nullptr, L.pp.r_len, log2H, v.bcnt, v.skey, nullptr, v.ctot);
-        uint32_t lo[kSU], hi[kSU];
-        bucket_runs(v.bcnt, log2H, L.pp.r_len, q, wb, we, lo, hi);
-        uint32_t c = 0;
+        build_lds<false>(rk + L.pp.r_off, nullptr, L.pp.r_len, log2H, v.bcnt, v.spare, v.skey, nullptr, v.ctot);
+        uint32_t lo[kSU], hi[kSU], c[kSU], first[kSU];
+        probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, lo, hi, c, first);
 #pragma unroll
-        for (uint32_t u = 0; u < kSU; ++u)
-            for (uint32_t x = lo[u]; x < hi[u]; ++x) c += (v.skey[x] == q[u]);
-        cnt = c;
+        for (uint32_t u = 0; u < kSU; ++u) cnt += c[u];
     } else {
         const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
         const uint32_t* __restrict__ next = ovf_next + L.pp.r_off;
@@ -358,18 +408,14 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_write(
     const uint32_t* __restrict__ next = ovf_next + L.pp.r_off;
     const int32_t* __restrict__ rrp = rr + L.pp.r_off;
     const RegionStep step{2u * L.pp.r_len};
-    // Per S tuple: match count c[u] and where its matches are (LDS run start, or chain head).
-    uint32_t c[kSU], at[kSU];
-    uint32_t hi[kSU];
+    // Per S tuple: match count c[u] and where its matches are (first match and
+    // bucket run end in LDS, or the chain head in HBM).
+    uint32_t c[kSU], at[kSU], hi[kSU];
     if (in_lds) {
         const uint32_t log2H = floor_log2_min6(L.pp.r_len);
-        build_lds<true>(rk + L.pp.r_off, rrp, L.pp.r_len, log2H, v.bcnt, v.skey, v.srid, v.ctot);
-        bucket_runs(v.bcnt, log2H, L.pp.r_len, q, wb, we, at, hi);
-#pragma unroll
-        for (uint32_t u = 0; u < kSU; ++u) {
-            c[u] = 0;
-            for (uint32_t x = at[u]; x < hi[u]; ++x) c[u] += (v.skey[x] == q[u]);
-        }
+        build_lds<true>(rk + L.pp.r_off, rrp, L.pp.r_len, log2H, v.bcnt, v.spare, v.skey, v.srid, v.ctot);
+        uint32_t lo[kSU];
+        probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, lo, hi, c, at);
     } else {
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) {
@@ -409,15 +455,7 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_write(
         if (c[u]) {
             const int32_t key = q[u], rs = qr[u];
             if (in_lds) {
-                for (uint32_t x = at[u]; x < hi[u]; ++x) {
-                    if (v.skey[x] == key) {
-                        if (pos < capacity) {
-                            out_r[pos] = v.srid[x];
-                            out_s[pos] = rs;
-                        }
-                        ++pos;
-                    }
-                }
+                write_lds_matches(v, key, rs, at[u], hi[u], c[u], pos, capacity, out_r, out_s);
             } else {
                 uint32_t h = at[u];
                 while (true) {
@@ -456,16 +494,12 @@ __global__ void __launch_bounds__(kJoinBlock) k_direct_join(const DirectJob* __r
     load_s<true>(J.sk + s_begin, J.sr + s_begin, wb, we, q, qr);
     const LdsView v = lds_view(lds, lds_cap, true);
     const uint32_t log2H = floor_log2_min6(r_len);
-    build_lds<true>(J.rk, J.rr, r_len, log2H, v.bcnt, v.skey, v.srid, v.ctot);
-    uint32_t c[kSU], lo[kSU], hi[kSU];
-    bucket_runs(v.bcnt, log2H, r_len, q, wb, we, lo, hi);
+    build_lds<true>(J.rk, J.rr, r_len, log2H, v.bcnt, v.spare, v.skey, v.srid, v.ctot);
+    uint32_t c[kSU], lo[kSU], hi[kSU], first[kSU];
+    probe_lds(v.bcnt, v.skey, log2H, r_len, q, wb, we, lo, hi, c, first);
     uint64_t mine = 0;
 #pragma unroll
-    for (uint32_t u = 0; u < kSU; ++u) {
-        c[u] = 0;
-        for (uint32_t x = lo[u]; x < hi[u]; ++x) c[u] += (v.skey[x] == q[u]);
-        mine += c[u];
-    }
+    for (uint32_t u = 0; u < kSU; ++u) mine += c[u];
     mine = wave_sum(mine);
     if (lane == 0) wtot[w] = mine;
     __syncthreads();
@@ -483,17 +517,7 @@ __global__ void __launch_bounds__(kJoinBlock) k_direct_join(const DirectJob* __r
         wave_offsets(c[u], &excl, &wtotal);
         uint64_t pos = pos0 + excl;
         pos0 += wtotal;
-        if (c[u]) {
-            for (uint32_t x = lo[u]; x < hi[u]; ++x) {
-                if (v.skey[x] == q[u]) {
-                    if (pos < J.capacity) {
-                        J.out_r[pos] = v.srid[x];
-                        J.out_s[pos] = qr[u];
-                    }
-                    ++pos;
-                }
-            }
-        }
+        if (c[u]) write_lds_matches(v, q[u], qr[u], first[u], hi[u], c[u], pos, J.capacity, J.out_r, J.out_s);
     }
 }
 
@@ -518,7 +542,7 @@ __global__ void k_write_zero(uint64_t* p) {
 }  // namespace
 
 size_t join_lds_bytes(uint32_t lds_cap, bool write) {
-    return sizeof(uint32_t) * ((size_t)lds_cap + kWave + (size_t)lds_cap * (write ? 2 : 1) + kScanScratch);
+    return sizeof(uint32_t) * ((size_t)lds_cap + 2 * kWave + (size_t)lds_cap * (write ? 2 : 1) + kScanScratch);
 }
 
 void direct_setup_one(DirectJob* job, uint32_t* item_job, const DirectJob& j, uint32_t nitems, Recorder& rec) {
