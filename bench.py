@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--hash", type=str, default="identity", choices=["identity", "murmur2"])
     ap.add_argument("--n", type=int, default=1 << 24, help="|R| = |S| (default 2^24)")
-    ap.add_argument("--one-pass", action="store_true", help="PHJ with the one-pass output (HJ_FLAG_ONE_PASS)")
+    ap.add_argument("--two-pass", action="store_true",
+                    help="headline PHJ with the two-pass output (count, scan, write) instead of one-pass")
     ap.add_argument("--no-shj", action="store_true", help="skip the SHJ line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="also time every radix configuration")
@@ -249,6 +250,44 @@ def cpu_baseline(n: int) -> dict:
             "sample": "one full %d x %d join (build + probe + emit %d pairs), %.1f s" % (len(r), len(s), len(o_r), el)}
 
 
+def measure_phj(hj, torch, p, t, out_r, out_s, d_count, n_r, n_s, steps, warmup, passes, one_pass):
+    """Throughput of one PHJ configuration plus its per-kernel breakdown."""
+    ws = hj.workspace(p, n_r, n_s)
+    ms = time_steps(lambda: hj.hj_join(p, *t, out_r, out_s, ws, d_count), steps, warmup, torch)
+    m = int(d_count.item())
+    reps = 5
+    phases = summarize(kernel_times(hj, p, t, out_r, out_s, ws, d_count, reps), reps, n_r, n_s, m)
+    # partition passes 20 B/tuple each; join: count pass 4 B/tuple (two-pass output) + write pass 8 B/tuple
+    total_bytes = (20.0 * passes + (8.0 if one_pass else 12.0)) * (n_r + n_s) + 8.0 * m
+    del ws
+    return {"ms": ms, "value": (n_r + n_s) / (ms * 1e-3), "matches": m, "kernels": phases,
+            "path_gbs": round(total_bytes / (ms * 1e-3) / 1e9, 1),
+            "path_frac": round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+PROFILE = os.path.join(ROOT, "profiles", "phj_16m_x_16m_hbm.json")
+KERNEL_OF_PHASE = {"part_hist": "k_part_hist", "part_scatter": "k_part_scatter", "join_count": "k_join_count",
+                   "join_write": "k_join_write<false>", "join_write_1pass": "k_join_write<true>"}
+
+
+def counter_traffic(phase: str):
+    """HBM bytes per launch of `phase` from the committed rocprofv3 counters, or
+    None when there are none or the kernel sources changed since they were taken."""
+    try:
+        from paper_1307_1955_amd import profsum
+        with open(PROFILE) as f:
+            rec = json.load(f)
+        if rec.get("sources_sha256") != profsum.sources_hash():
+            return None
+        want = KERNEL_OF_PHASE.get(phase)
+        for r in rec["kernels"]:
+            if want and r["kernel"].startswith(want) and r["hbm_read_mb"] is not None:
+                return round((r["hbm_read_mb"] + r["hbm_write_mb"]) * 1e6, 0)
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -273,42 +312,33 @@ def main():
     dev = torch.device("cuda:0")
     n = args.n
     bits = tuple(int(b) for b in args.bits.split(","))
-    p = hj.params("phj", args.passes, bits, hash=args.hash, tile=args.tile, one_pass=args.one_pass)
+    one_pass = not args.two_pass
+    p = hj.params("phj", args.passes, bits, hash=args.hash, tile=args.tile, one_pass=one_pass)
     print("bench: generating 16M x 16M inputs on the device", file=sys.stderr, flush=True)
     t = dgen.config_c2(n=n, device=dev)
     n_r, n_s = n, n
-    cap = n_s
-    out_r = torch.empty(cap, dtype=torch.int32, device=dev)
-    out_s = torch.empty(cap, dtype=torch.int32, device=dev)
+    out_r = torch.empty(n_s, dtype=torch.int32, device=dev)
+    out_s = torch.empty(n_s, dtype=torch.int32, device=dev)
     d_count = torch.zeros(1, dtype=torch.int64, device=dev)
-    ws = hj.workspace(p, n_r, n_s, dev)
-
-    def step():
-        hj.hj_join(p, *t, out_r, out_s, ws, d_count)
 
     print("bench: PHJ %r, %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr, flush=True)
-    ms = time_steps(step, args.steps, args.warmup, torch)
-    m = int(d_count.item())
-    value = (n_r + n_s) / (ms * 1e-3)
-
-    reps = 5
-    acc = kernel_times(hj, p, t, out_r, out_s, ws, d_count, reps)
-    phases = summarize(acc, reps, n_r, n_s, m)
+    head = measure_phj(hj, torch, p, t, out_r, out_s, d_count, n_r, n_s, args.steps, args.warmup, args.passes,
+                       one_pass)
+    phases = head["kernels"]
+    m = head["matches"]
     # dominant kernel: most time per join among kernels with an algorithmic byte count
     dom = max((k for k in phases if "gbs" in phases[k]), key=lambda k: phases[k]["ms_per_join"])
     dom_bytes = algorithmic_bytes(dom, n_r, n_s, m)
     dom_ms = phases[dom]["avg_launch_ms"]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    # partition passes 20 B/tuple each; join: count pass 4 B/tuple (two-pass output only) + write pass 8 B/tuple
-    total_bytes = (20.0 * args.passes + (8.0 if args.one_pass else 12.0)) * (n_r + n_s) + 8.0 * m
     result = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "tuples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -318,27 +348,36 @@ def main():
             "workload": "PHJ 16M x 16M: |R| = |S| = %d int32 (key, rid); R keys a permutation of 1..|R|, "
                         "S keys uniform over 1..2|R| (~50%% match)" % n,
             "algo": "phj", "passes": args.passes, "bits": list(bits), "hash": args.hash,
-            "tile": p.tile or 4096, "one_pass_output": bool(args.one_pass), "matches": m,
+            "tile": p.tile or 4096, "output": "one-pass (block reservation)" if one_pass else
+            "two-pass (count, scan, write)", "matches": m,
         },
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom),
             "bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms,
         },
-        "path_gbs": round(total_bytes / (ms * 1e-3) / 1e9, 1),
-        "path_frac": round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "path_gbs": head["path_gbs"],
+        "path_frac": head["path_frac"],
         "kernels": phases,
     }
+    # the other output materialisation on the same inputs (both give the same multiset)
+    q = hj.params("phj", args.passes, bits, hash=args.hash, tile=args.tile, one_pass=not one_pass)
+    alt = measure_phj(hj, torch, q, t, out_r, out_s, d_count, n_r, n_s, args.steps, args.warmup, args.passes,
+                      not one_pass)
+    result["two_pass_output" if one_pass else "one_pass_output"] = alt
     if not args.no_shj:
-        ps = hj.params("shj", one_pass=args.one_pass)
-        ws_s = hj.workspace(ps, n_r, n_s, dev)
-        print("bench: SHJ", file=sys.stderr, flush=True)
-        ms_s = time_steps(lambda: hj.hj_join(ps, *t, out_r, out_s, ws_s, d_count), args.steps, args.warmup, torch)
-        m_s = int(d_count.item())
-        acc_s = kernel_times(hj, ps, t, out_r, out_s, ws_s, d_count, reps)
-        result["shj"] = {"value": (n_r + n_s) / (ms_s * 1e-3), "unit": "tuples/s", "ms_per_step": ms_s,
-                         "matches": m_s, "kernels": summarize(acc_s, reps, n_r, n_s, m_s)}
-        del ws_s
+        for shj_one in (True, False):
+            ps = hj.params("shj", one_pass=shj_one)
+            ws_s = hj.workspace(ps, n_r, n_s, dev)
+            print("bench: SHJ (%s output)" % ("one-pass" if shj_one else "two-pass"), file=sys.stderr, flush=True)
+            ms_s = time_steps(lambda: hj.hj_join(ps, *t, out_r, out_s, ws_s, d_count), args.steps, args.warmup,
+                              torch)
+            m_s = int(d_count.item())
+            acc_s = kernel_times(hj, ps, t, out_r, out_s, ws_s, d_count, 5)
+            result["shj" if shj_one else "shj_two_pass_output"] = {
+                "value": (n_r + n_s) / (ms_s * 1e-3), "unit": "tuples/s", "ms_per_step": ms_s, "matches": m_s,
+                "kernels": summarize(acc_s, 5, n_r, n_s, m_s)}
+            del ws_s
     if args.sweep:
         sweep = []
         configs = [(1, (b,)) for b in range(8, 15)] + [(2, (a, b)) for a in range(4, 9) for b in range(4, 9)]
@@ -356,7 +395,7 @@ def main():
                     del wq
         result["sweep"] = sweep
     if args.batch_jobs:
-        del ws, out_r, out_s, t
+        del out_r, out_s, t
         torch.cuda.empty_cache()
         from paper_1307_1955_amd import tune, workloads
         print("bench: building the batched workload (%d jobs) in HBM" % args.batch_jobs, file=sys.stderr, flush=True)

@@ -1,0 +1,116 @@
+"""Summaries of rocprofv3 runs of the join kernels (for the profiles/ folder).
+
+Reads the CSV output of
+  * one ``rocprofv3 --kernel-trace --stats`` run (per-kernel average duration),
+  * one ``--pmc FETCH_SIZE`` and one ``--pmc WRITE_SIZE`` run of the same
+    command (KiB per dispatch),
+  * the same two counters for a plain device copy of known size,
+and writes a short markdown table plus a JSON record.  HBM bytes of a kernel
+= counter KiB * 1024 * (copy bytes / copy counter bytes): the copy scales each
+counter to true bytes.  The JSON keeps a hash of the kernel sources so a
+consumer can tell whether the kernels changed since the counters were taken.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/phj_partition.hip", "csrc/phj_join.hip", "csrc/shj.hip", "csrc/scan.hip",
+                  "csrc/hj_device.h", "csrc/hj_internal.h"]
+
+
+def sources_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def short_name(name: str) -> str:
+    """"void hj::(anonymous namespace)::k_part_scatter<16u>(...)" -> "k_part_scatter<16u>"."""
+    m = re.search(r"(k_[A-Za-z0-9_]+(?:<[^>(]*>)?)\(", name)
+    if m:
+        return m.group(1)
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def one_csv(d: str, suffix: str) -> str:
+    hits = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not hits:
+        raise FileNotFoundError("no *%s under %s" % (suffix, d))
+    return hits[0]
+
+
+def counters(d: str) -> dict:
+    acc = collections.defaultdict(list)
+    for r in csv.DictReader(open(one_csv(d, "counter_collection.csv"))):
+        acc[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def stats(d: str) -> dict:
+    out = {}
+    for r in csv.DictReader(open(one_csv(d, "kernel_stats.csv"))):
+        out[short_name(r["Name"])] = {"calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+                                      "total_ns": float(r["TotalDurationNs"])}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--commands", required=True, help="the commands that produced the CSVs")
+    ap.add_argument("--prefix", default="k_", help="only kernels whose name starts with this")
+    ap.add_argument("--out-md", required=True)
+    ap.add_argument("--out-json", required=True)
+    a = ap.parse_args()
+    st = stats(a.trace)
+    fe, wr = counters(a.fetch), counters(a.write)
+    cf, cw = counters(a.copy_fetch), counters(a.copy_write)
+    copy_name = max(cf, key=lambda k: cf[k])
+    f_factor = a.copy_bytes / (cf[copy_name] * 1024.0)
+    w_factor = a.copy_bytes / (cw[copy_name] * 1024.0)
+    rows = []
+    for k in sorted(st, key=lambda x: -st[x]["total_ns"]):
+        if not k.startswith(a.prefix):
+            continue
+        rows.append({"kernel": k, "calls": st[k]["calls"], "avg_us": st[k]["avg_ns"] / 1e3,
+                     "hbm_read_mb": fe.get(k, 0.0) * 1024 * f_factor / 1e6 if k in fe else None,
+                     "hbm_write_mb": wr.get(k, 0.0) * 1024 * w_factor / 1e6 if k in wr else None})
+    rec = {"workload": a.workload, "commands": a.commands, "copy_kernel": copy_name, "copy_bytes": a.copy_bytes,
+           "fetch_factor": f_factor, "write_factor": w_factor, "sources_sha256": sources_hash(), "kernels": rows}
+    with open(a.out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = ["# rocprofv3: %s" % a.workload, "", "Commands (run from the repository root on an MI355X):", "",
+             "```", a.commands, "```", "",
+             "HBM bytes = counter KiB x 1024 x factor; factors from a plain %d-byte device copy (%s): "
+             "FETCH_SIZE x %.3f, WRITE_SIZE x %.3f." % (a.copy_bytes, copy_name, f_factor, w_factor), "",
+             "| kernel | calls | avg us | HBM read MB / dispatch | HBM write MB / dispatch |",
+             "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        fmt = lambda v: "-" if v is None else "%.1f" % v
+        lines.append("| %s | %d | %.1f | %s | %s |" % (r["kernel"], r["calls"], r["avg_us"], fmt(r["hbm_read_mb"]),
+                                                      fmt(r["hbm_write_mb"])))
+    lines.append("")
+    lines.append("Kernel sources sha256 at measurement: `%s`" % rec["sources_sha256"])
+    with open(a.out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(a.out_md, a.out_json)
+
+
+if __name__ == "__main__":
+    main()
