@@ -73,7 +73,8 @@ uint32_t join_blocks_per_cu(uint32_t cap) {
 
 // Default LDS table capacity: room for a partition three standard deviations
 // above the mean size (uniform hashing), then grown to the largest capacity
-// that keeps the same number of write-kernel workgroups per CU.
+// that keeps the same number of write-kernel workgroups per CU and the same
+// build kernel (registers per thread grow with the build's tuples per thread).
 uint32_t auto_lds_cap(uint64_t n_r, uint32_t P) {
     const double avg = std::ceil((double)n_r / (double)P);
     const double need = avg + 3.0 * std::sqrt(avg) + 32.0;
@@ -81,7 +82,9 @@ uint32_t auto_lds_cap(uint64_t n_r, uint32_t P) {
     cap = (cap + 63) / 64 * 64;
     if (cap > hj::kMaxLdsCap) cap = hj::kMaxLdsCap;
     const uint32_t bpc = join_blocks_per_cu(cap);
-    while (cap + 64 <= hj::kMaxLdsCap && join_blocks_per_cu(cap + 64) == bpc) cap += 64;
+    while (cap + 64 <= hj::kMaxLdsCap && join_blocks_per_cu(cap + 64) == bpc &&
+           hj::join_rpt(cap + 64) == hj::join_rpt(cap))
+        cap += 64;
     return cap;
 }
 

@@ -165,6 +165,19 @@ __device__ __forceinline__ void wave_offsets(uint32_t c, uint64_t* excl, uint64_
     }
 }
 
+// The same for counts below 2^25 (matches in an LDS table), in 32 bits.
+__device__ __forceinline__ void wave_offsets32(uint32_t c, uint32_t* excl, uint32_t* total) {
+    if (__ballot(c > 1) == 0) {
+        const uint64_t m = __ballot(c != 0);
+        *excl = (uint32_t)__popcll(m & lanemask_lt());
+        *total = (uint32_t)__popcll(m);
+    } else {
+        const uint32_t incl = wave_incl_scan(c);
+        *excl = incl - c;
+        *total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    }
+}
+
 // Block-wide exclusive scan of one value per thread.  `wave_tot` is LDS scratch
 // of at least blockDim/64 entries.  Returns the exclusive prefix; *total gets
 // the block total.  Contains __syncthreads().
@@ -219,6 +232,41 @@ __device__ __forceinline__ uint32_t lds_excl_scan(uint32_t* a, uint32_t n, uint3
     return total;
 }
 
+// In-place exclusive scan of an LDS array a[0..n) by the whole block, for
+// n <= blockDim.x * kMaxE: thread t owns the run [t*E, t*E + E), E =
+// ceil(n / blockDim.x), which it sums in registers; one wave scan of the run
+// sums and one exchange of wave totals (through `wave_tot`, >= blockDim/64
+// entries) give every run its offset.  One barrier inside; callers sync before
+// reading `a`.  Returns the total.
+template <uint32_t kMaxE>
+__device__ __forceinline__ uint32_t lds_excl_scan_runs(uint32_t* a, uint32_t n, uint32_t* wave_tot) {
+    const uint32_t E = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t b = threadIdx.x * E;
+    const uint32_t w = threadIdx.x / kWave;
+    uint32_t v[kMaxE];
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kMaxE; ++e) {
+        v[e] = (e < E && b + e < n) ? a[b + e] : 0u;
+        s += v[e];
+    }
+    const uint32_t incl = wave_incl_scan(s);
+    if (lane_id() == kWave - 1) wave_tot[w] = incl;
+    __syncthreads();
+    uint32_t off = incl - s, total = 0;
+    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) {
+        const uint32_t t = wave_tot[i];
+        off += i < w ? t : 0u;
+        total += t;
+    }
+#pragma unroll
+    for (uint32_t e = 0; e < kMaxE; ++e) {
+        if (e < E && b + e < n) a[b + e] = off;
+        off += v[e];
+    }
+    return total;
+}
+
 // Scratch entries `lds_excl_scan` needs (one per wave of the largest block).
 constexpr uint32_t kScanScratch = 16;
 
@@ -231,6 +279,13 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t grid) {
     const uint32_t i = b / kXcd;
     const uint32_t q = grid / kXcd, r = grid % kXcd;
     return x * q + (x < r ? x : r) + i;
+}
+
+// Work index of block b when only the first `live` blocks of the grid have
+// work: the live blocks are spread over all XCDs (xcd_remap over [0, live));
+// blocks past `live` keep their index and find no work.
+__device__ __forceinline__ uint32_t live_remap(uint32_t b, uint32_t live) {
+    return b < live ? xcd_remap(b, live) : b;
 }
 
 // Largest s in [0, n) with begin[s] <= v, for a nondecreasing begin[0..n].

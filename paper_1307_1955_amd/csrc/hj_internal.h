@@ -88,8 +88,15 @@ void part_setup_pass2(const uint32_t* hist1_scan, const uint32_t* tile_begin1, u
 // ---- phj_join.hip ----
 constexpr uint32_t kJoinBlock = 512;
 constexpr uint32_t kJoinWaves = kJoinBlock / 64;
-constexpr uint32_t kJoinChunk = 4096;   // S tuples per work item
+constexpr uint32_t kJoinChunk = 8192;   // S tuples per work item (probed kJoinSub at a time)
+constexpr uint32_t kJoinSub = 4096;     // S tuples per probe round of a work item (8 per lane)
 constexpr uint32_t kMaxLdsCap = 8192;   // largest R partition held in LDS
+// R tuples per thread of the LDS build (a kernel template argument: the build
+// keeps them in registers), by lds_cap class.
+constexpr uint32_t kRptSmall = 4, kRptMid = 9, kRptLarge = kMaxLdsCap / kJoinBlock;
+inline uint32_t join_rpt(uint32_t lds_cap) {
+    return lds_cap <= kRptSmall * kJoinBlock ? kRptSmall : (lds_cap <= kRptMid * kJoinBlock ? kRptMid : kRptLarge);
+}
 struct JoinPlanOut {
     PartPair* pairs;       // [P]
     uint32_t* item_begin;  // [P + 1] exclusive scan of work items per partition

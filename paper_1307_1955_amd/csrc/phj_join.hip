@@ -1,8 +1,8 @@
 // Join of the partition pairs of a PHJ ("apply SHJ on each partition pair",
 // Algorithm 2; steps b1-b4 and p1-p4 of Algorithm 1 inside each pair).
 //
-// Work item = (partition pair i, chunk of kJoinChunk S tuples of S_i).  One
-// workgroup per item:
+// Work item = (partition pair i, chunk of up to kJoinChunk S tuples of S_i),
+// probed kJoinSub tuples at a time.  One workgroup per item:
 //  * |R_i| <= lds_cap: R_i becomes a bucketed table in LDS.  The paper's
 //    bucket header + key list + rid list (Section 3.1) is laid out without
 //    pointers: bucket counts (LDS atomics, the latch of Section 3.3), an
@@ -24,7 +24,7 @@ namespace hj {
 namespace {
 
 constexpr uint32_t kOvfChunk = 4096;                  // R tuples per HBM-table build item
-constexpr uint32_t kSubJ = kJoinChunk / kJoinWaves;   // S tuples per wave of an item
+constexpr uint32_t kSubJ = kJoinSub / kJoinWaves;     // S tuples per wave of a probe round
 constexpr uint32_t kPlanBlock = 1024;
 
 // Start of final partition i of one relation (positions relative to the relation).
@@ -156,57 +156,68 @@ __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ 
     }
 }
 
-constexpr uint32_t kRU = kMaxLdsCap / kJoinBlock;  // R tuples per thread when building
-constexpr uint32_t kSU = kSubJ / kWave;              // S tuples per lane of an item
+constexpr uint32_t kSU = kSubJ / kWave;  // S tuples per lane of a probe round
 
-// Builds the bucketed LDS table over R_i (n <= kMaxLdsCap tuples).  Afterwards
-// bucket b holds skey/srid[bcnt[b] .. bcnt[b+1]).  H = 2^log2H buckets; bcnt has
-// H + 1 entries.  Each R tuple is loaded once: its bucket and its rank inside
-// the bucket (from the counting atomic) stay in a register until placement.
-// The per-tuple LDS operations carry no branches (lanes past n use a private
-// spare counter, `spare`, and clamped addresses), so a wave keeps all of its
-// LDS atomics and reads in flight instead of waiting on each one.
-template <bool kRids>
-__device__ __forceinline__ void build_lds(const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
-                                          uint32_t n, uint32_t log2H, uint32_t* bcnt, uint32_t* spare,
-                                          int32_t* skey, int32_t* srid, uint32_t* ctot) {
-    const uint32_t H = 1u << log2H;
-    const uint32_t sh = 32 - log2H;
-    int32_t k[kRU], r[kRU];
-    uint32_t br[kRU];
+static_assert(kRptLarge * kJoinBlock == kMaxLdsCap, "largest build covers kMaxLdsCap");
+
+// Buckets of the LDS table for n tuples: largest power of two <= max(64, n).
+__device__ __forceinline__ uint32_t floor_log2_min6(uint32_t n) {
+    const uint32_t v = n < 64 ? 64u : n;
+    return 31u - (uint32_t)__clz(v);
+}
+
+// R_i's keys (and rids) of this thread, n <= RPT * kJoinBlock.
+template <bool kRids, uint32_t RPT>
+__device__ __forceinline__ void load_r(const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
+                                       uint32_t n, int32_t* k, int32_t* r) {
 #pragma unroll
-    for (uint32_t u = 0; u < kRU; ++u) {
+    for (uint32_t u = 0; u < RPT; ++u) {
         const uint32_t j = u * kJoinBlock + threadIdx.x;
         k[u] = j < n ? rk[j] : 0;
         if (kRids) r[u] = j < n ? rr[j] : 0;
     }
+}
+
+// Builds the bucketed LDS table over the n <= RPT * kJoinBlock tuples held in
+// registers (k, r).  Afterwards bucket b holds skey/srid[bcnt[b] .. bcnt[b+1]);
+// H = 2^log2H buckets, bcnt has H + 1 entries.  The rank of a tuple inside its
+// bucket comes from the counting atomic and stays in a register until
+// placement.  Rounds past n are skipped as a whole (n is uniform over the
+// block); inside a round, lanes past n count into a private spare word so the
+// round's atomics are issued without branches.
+template <bool kRids, uint32_t RPT>
+__device__ __forceinline__ void build_lds(const int32_t* k, const int32_t* r, uint32_t n, uint32_t log2H,
+                                          uint32_t* bcnt, uint32_t* spare, int32_t* skey, int32_t* srid,
+                                          uint32_t* ctot) {
+    constexpr uint32_t kMaxE = RPT >= 16 ? 16 : (RPT >= 8 ? 8 : 4);  // H <= RPT * kJoinBlock buckets
+    const uint32_t H = 1u << log2H;
+    const uint32_t sh = 32 - log2H;
     for (uint32_t x = threadIdx.x; x <= H; x += kJoinBlock) bcnt[x] = 0;
     __syncthreads();
-    // Every lane issues all kRU counting atomics back to back (lanes past n
-    // count into their own spare word), and only then consumes the ranks.
-    uint32_t bk[kRU], old[kRU];
+    uint32_t br[RPT];
 #pragma unroll
-    for (uint32_t u = 0; u < kRU; ++u) {
-        const uint32_t j = u * kJoinBlock + threadIdx.x;
-        bk[u] = slot_hash(k[u]) >> sh;
-        old[u] = atomicAdd(j < n ? &bcnt[bk[u]] : &spare[lane_id()], 1u);
+    for (uint32_t u = 0; u < RPT; ++u) {
+        br[u] = 0;
+        if (u * kJoinBlock < n) {
+            const uint32_t j = u * kJoinBlock + threadIdx.x;
+            const uint32_t b = slot_hash(k[u]) >> sh;
+            const uint32_t old = atomicAdd(j < n ? &bcnt[b] : &spare[lane_id()], 1u);
+            br[u] = (b << 16) | old;  // b < 2^13, rank < 2^13
+        }
     }
-#pragma unroll
-    for (uint32_t u = 0; u < kRU; ++u) br[u] = (bk[u] << 16) | old[u];  // b < 2^13, rank < 2^13
     __syncthreads();
-    lds_excl_scan(bcnt, H, ctot);
+    lds_excl_scan_runs<kMaxE>(bcnt, H, ctot);
     if (threadIdx.x == 0) bcnt[H] = n;
     __syncthreads();
-    uint32_t start[kRU];
 #pragma unroll
-    for (uint32_t u = 0; u < kRU; ++u) start[u] = bcnt[br[u] >> 16];
-#pragma unroll
-    for (uint32_t u = 0; u < kRU; ++u) {
-        const uint32_t j = u * kJoinBlock + threadIdx.x;
-        const uint32_t pos = start[u] + (br[u] & 0xFFFFu);
-        if (j < n && pos < n) {  // pos < n always holds for a correct scan
-            skey[pos] = k[u];
-            if (kRids) srid[pos] = r[u];
+    for (uint32_t u = 0; u < RPT; ++u) {
+        if (u * kJoinBlock < n) {
+            const uint32_t j = u * kJoinBlock + threadIdx.x;
+            const uint32_t pos = bcnt[br[u] >> 16] + (br[u] & 0xFFFFu);
+            if (j < n && pos < n) {  // pos < n always holds for a correct scan
+                skey[pos] = k[u];
+                if (kRids) srid[pos] = r[u];
+            }
         }
     }
     __syncthreads();
@@ -223,8 +234,9 @@ __device__ __forceinline__ ItemLoc locate_item(const PartPair* __restrict__ pair
                                                const uint32_t* __restrict__ item_begin,
                                                const uint32_t* __restrict__ item_part, uint32_t P) {
     ItemLoc L;
-    L.item = xcd_remap(blockIdx.x, gridDim.x);
-    L.live = L.item < item_begin[P];
+    const uint32_t live = item_begin[P];
+    L.item = live_remap(blockIdx.x, live);
+    L.live = L.item < live;
     if (!L.live) return L;
     const uint32_t i = item_part[L.item];
     const uint32_t c = L.item - item_begin[i];
@@ -254,12 +266,7 @@ __device__ __forceinline__ LdsView lds_view(uint32_t* lds, uint32_t cap, bool ri
     return v;
 }
 
-__device__ __forceinline__ uint32_t floor_log2_min6(uint32_t n) {
-    const uint32_t v = n < 64 ? 64u : n;
-    return 31u - (uint32_t)__clz(v);
-}
-
-// S keys (and rids) of this lane for the wave's range of the item.
+// S keys (and rids) of this lane for the wave's range [wb, we) of the item.
 template <bool kRids>
 __device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const int32_t* __restrict__ srp,
                                        uint32_t wb, uint32_t we, int32_t* q, int32_t* qr) {
@@ -273,41 +280,63 @@ __device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const in
 
 // p1-p4 for the lane's kSU S keys against the LDS table, without branches per
 // key: the bucket bounds of all keys are read first, then the keys' runs are
-// walked in lockstep (step i reads entry lo[u] + i of every key's run, clamped
-// to a valid address), so each step keeps kSU LDS reads in flight and a wave
-// runs only as many steps as its longest run.  c[u] = matches of key u;
-// first[u] = position of its first match (meaningful when c[u] > 0); lo/hi its
-// bucket run, clamped to [0, n].
+// walked in lockstep (step i reads entry lo + i of every key's run, clamped to
+// a valid address), so each step keeps kSU LDS reads in flight and a wave runs
+// only as many steps as its longest run.  Per key, packed in 16-bit halves
+// (n <= kMaxLdsCap < 2^16): run[u] = lo | hi << 16, its bucket run clamped to
+// [0, n]; cf[u] = matches | first << 16, first = position of its first match
+// (meaningful when it has one).
 __device__ __forceinline__ void probe_lds(const uint32_t* bcnt, const int32_t* skey, uint32_t log2H, uint32_t n,
-                                          const int32_t* q, uint32_t wb, uint32_t we, uint32_t* lo, uint32_t* hi,
-                                          uint32_t* c, uint32_t* first) {
+                                          const int32_t* q, uint32_t wb, uint32_t we, uint32_t* run,
+                                          uint32_t* cf) {
     const uint32_t sh = 32 - log2H;
     uint32_t len = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
         const uint32_t b = slot_hash(q[u]) >> sh;
-        lo[u] = bcnt[b];
-        hi[u] = bcnt[b + 1];
+        const uint32_t lo = bcnt[b];
+        const uint32_t hi = bcnt[b + 1];
+        run[u] = lo | (hi << 16);
     }
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
         const bool ok = wb + u * kWave + lane_id() < we;
-        hi[u] = ok ? min(hi[u], n) : 0u;
-        lo[u] = min(lo[u], hi[u]);
-        len = max(len, hi[u] - lo[u]);
-        c[u] = 0;
-        first[u] = 0;
+        const uint32_t hi = ok ? min(run[u] >> 16, n) : 0u;
+        const uint32_t lo = min(run[u] & 0xFFFFu, hi);
+        run[u] = lo | (hi << 16);
+        len = max(len, hi - lo);
+        cf[u] = 0;
     }
     for (uint32_t i = 0; i < len; ++i) {
         int32_t v[kSU];
 #pragma unroll
-        for (uint32_t u = 0; u < kSU; ++u) v[u] = skey[lo[u] + i < hi[u] ? lo[u] + i : 0u];
+        for (uint32_t u = 0; u < kSU; ++u) {
+            const uint32_t x = (run[u] & 0xFFFFu) + i;
+            v[u] = skey[x < (run[u] >> 16) ? x : 0u];
+        }
         __builtin_amdgcn_sched_barrier(0);  // keep the kSU reads of a step together, in flight at once
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) {
-            const bool hit = lo[u] + i < hi[u] && v[u] == q[u];
-            first[u] = (hit && c[u] == 0) ? lo[u] + i : first[u];
-            c[u] += hit;
+            const uint32_t x = (run[u] & 0xFFFFu) + i;
+            const bool hit = x < (run[u] >> 16) && v[u] == q[u];
+            const uint32_t first = (cf[u] & 0xFFFFu) == 0 ? x << 16 : cf[u] & 0xFFFF0000u;
+            cf[u] = hit ? first | ((cf[u] & 0xFFFFu) + 1u) : cf[u];
+        }
+    }
+}
+
+// Matches of the lane's kSU S keys in the partition-local HBM table.
+__device__ __forceinline__ void probe_hbm(const uint64_t* __restrict__ region, const uint32_t* __restrict__ next,
+                                          uint32_t H, const int32_t* q, uint32_t wb, uint32_t we, uint32_t* c,
+                                          uint32_t* at) {
+    const RegionStep step{H};
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        c[u] = 0;
+        at[u] = kNotFound;
+        if (wb + u * kWave + lane_id() < we) {
+            at[u] = chain_find(region, region_slot(q[u], H), q[u], step);
+            if (at[u] != kNotFound) c[u] = chain_len(next, at[u]);
         }
     }
 }
@@ -334,6 +363,88 @@ __device__ __forceinline__ void write_lds_matches(const LdsView& v, int32_t key,
     }
 }
 
+// Block-wide output reservation for one probe round (the block allocator of
+// Section 3.3 with a block sized to the round's pairs): one atomic add of the
+// round's total on the running count.  `mine` = this lane's pairs.  Returns the
+// first slot of this wave.  `again`: a previous round used `wtot` (uniform over
+// the block).
+// T: uint32_t for the LDS table (a round has at most kJoinSub x kMaxLdsCap
+// pairs), uint64_t for the HBM table (duplicate-heavy R can exceed 2^32).
+template <typename T>
+__device__ __forceinline__ uint64_t block_reserve(T mine, unsigned long long* total, uint64_t* wtot,
+                                                  bool again) {
+    const uint32_t w = threadIdx.x / kWave;
+    mine = wave_sum(mine);
+    if (again) __syncthreads();  // every wave has read the previous round's offsets
+    if (lane_id() == 0) wtot[w] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (uint32_t i = 0; i < kJoinWaves; ++i) t += wtot[i];
+        wtot[kJoinWaves] = t ? atomicAdd(total, (unsigned long long)t) : 0ull;
+    }
+    __syncthreads();
+    uint64_t pos0 = wtot[kJoinWaves];
+    for (uint32_t i = 0; i < w; ++i) pos0 += wtot[i];
+    return pos0;
+}
+
+__device__ __forceinline__ uint32_t lane_pairs_lds(const uint32_t* cf) {
+    uint32_t m = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) m += cf[u] & 0xFFFFu;
+    return m;
+}
+
+// Stores the round's pairs of this wave from output slot pos0 on (wave-compacted
+// by match counts); returns the slot after the wave's last pair.  LDS table.
+__device__ __forceinline__ uint64_t write_round_lds(const LdsView& v, const int32_t* q, const int32_t* qr,
+                                                    const uint32_t* run, const uint32_t* cf, uint64_t pos0,
+                                                    uint64_t capacity, int32_t* __restrict__ out_r,
+                                                    int32_t* __restrict__ out_s) {
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        const uint32_t c = cf[u] & 0xFFFFu;
+        uint32_t excl, wtotal;
+        wave_offsets32(c, &excl, &wtotal);
+        const uint64_t pos = pos0 + excl;
+        pos0 += wtotal;
+        if (c) write_lds_matches(v, q[u], qr[u], cf[u] >> 16, run[u] >> 16, c, pos, capacity, out_r, out_s);
+    }
+    return pos0;
+}
+
+// The same for the partition-local HBM table: c[u] matches on the row chain
+// that starts at at[u].
+__device__ __forceinline__ uint64_t write_round_hbm(const uint32_t* __restrict__ next,
+                                                    const int32_t* __restrict__ rrp, const int32_t* qr,
+                                                    const uint32_t* c, const uint32_t* at, uint64_t pos0,
+                                                    uint64_t capacity, int32_t* __restrict__ out_r,
+                                                    int32_t* __restrict__ out_s) {
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        uint64_t excl, wtotal;
+        wave_offsets(c[u], &excl, &wtotal);
+        uint64_t pos = pos0 + excl;
+        pos0 += wtotal;
+        if (c[u]) {
+            uint32_t h = at[u];
+            while (true) {
+                const uint32_t row = h & ~kLast;
+                if (pos < capacity) {
+                    out_r[pos] = rrp[row];
+                    out_s[pos] = qr[u];
+                }
+                ++pos;
+                if (h & kLast) break;
+                h = next[row];
+            }
+        }
+    }
+    return pos0;
+}
+
+template <uint32_t RPT>
 __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __restrict__ pairs,
                                                           const uint32_t* __restrict__ item_begin,
                                                           const uint32_t* __restrict__ item_part,
@@ -350,41 +461,42 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
         if (lane == 0) wave_cnt[(uint64_t)L.item * kJoinWaves + w] = 0;
         return;
     }
-    const uint32_t wb = w * kSubJ;
-    const uint32_t we = min(wb + kSubJ, L.s_n);
-    int32_t q[kSU], qr[kSU];
-    load_s<false>(sk + L.s_begin, nullptr, wb, we, q, qr);
+    const int32_t* __restrict__ skp = sk + L.s_begin;
     uint64_t cnt = 0;
+    int32_t q[kSU];
     if (L.pp.r_len <= lds_cap) {
+        int32_t k[RPT];
+        load_r<false, RPT>(rk + L.pp.r_off, nullptr, L.pp.r_len, k, nullptr);
+        load_s<false>(skp, nullptr, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, nullptr);
         const LdsView v = lds_view(lds, lds_cap, false);
         const uint32_t log2H = floor_log2_min6(L.pp.r_len);
-        build_lds<false>(rk + L.pp.r_off, nullptr, L.pp.r_len, log2H, v.bcnt, v.spare, v.skey, nullptr, v.ctot);
-        uint32_t lo[kSU], hi[kSU], c[kSU], first[kSU];
-        probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, lo, hi, c, first);
-#pragma unroll
-        for (uint32_t u = 0; u < kSU; ++u) cnt += c[u];
+        build_lds<false, RPT>(k, nullptr, L.pp.r_len, log2H, v.bcnt, v.spare, v.skey, nullptr, v.ctot);
+        for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
+            const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
+            if (sb) load_s<false>(skp, nullptr, wb, we, q, nullptr);
+            uint32_t run[kSU], cf[kSU];
+            probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, run, cf);
+            cnt += lane_pairs_lds(cf);
+        }
     } else {
-        const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
-        const uint32_t* __restrict__ next = ovf_next + L.pp.r_off;
-        const RegionStep step{2u * L.pp.r_len};
+        for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
+            const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
+            load_s<false>(skp, nullptr, wb, we, q, nullptr);
+            uint32_t c[kSU], at[kSU];
+            probe_hbm(ovf_table + 2ull * L.pp.r_off, ovf_next + L.pp.r_off, 2u * L.pp.r_len, q, wb, we, c, at);
 #pragma unroll
-        for (uint32_t u = 0; u < kSU; ++u) {
-            if (wb + u * kWave + lane < we) {
-                const uint32_t h = chain_find(region, region_slot(q[u], step.H), q[u], step);
-                if (h != kNotFound) cnt += chain_len(next, h);
-            }
+            for (uint32_t u = 0; u < kSU; ++u) cnt += c[u];
         }
     }
     cnt = wave_sum(cnt);
     if (lane == 0) wave_cnt[(uint64_t)L.item * kJoinWaves + w] = cnt;
 }
 
-// Write pass.  kOnePass: instead of reading a scanned per-wave offset, the
-// block counts its pairs, reserves that many output slots with one atomic add
-// on the running total (the block allocator of Section 3.3 with a block sized
-// to the work item), and writes them there.
-template <bool kOnePass>
-__global__ void __launch_bounds__(kJoinBlock) k_join_write(
+// Write pass.  kOnePass: instead of reading a scanned per-wave offset, each
+// probe round reserves its pairs' output slots with block_reserve.
+template <bool kOnePass, uint32_t RPT>
+__global__ void __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(RPT > kRptMid ? 4 : 6)))
+k_join_write(
     const PartPair* __restrict__ pairs, const uint32_t* __restrict__ item_begin,
     const uint32_t* __restrict__ item_part, uint32_t P, const int32_t* __restrict__ rk,
     const int32_t* __restrict__ rr, const int32_t* __restrict__ sk, const int32_t* __restrict__ sr,
@@ -395,129 +507,77 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_write(
     extern __shared__ uint32_t lds[];
     __shared__ uint64_t wtot[kJoinWaves + 1];
     const uint32_t w = threadIdx.x / kWave;
-    const uint32_t lane = lane_id();
     const ItemLoc L = locate_item(pairs, item_begin, item_part, P);
     if (!L.live) return;
-    const uint32_t wb = w * kSubJ;
-    const uint32_t we = min(wb + kSubJ, L.s_n);
-    int32_t q[kSU], qr[kSU];
-    load_s<true>(sk + L.s_begin, sr + L.s_begin, wb, we, q, qr);
-    const bool in_lds = L.pp.r_len <= lds_cap;
-    const LdsView v = lds_view(lds, lds_cap, true);
-    const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
-    const uint32_t* __restrict__ next = ovf_next + L.pp.r_off;
     const int32_t* __restrict__ rrp = rr + L.pp.r_off;
-    const RegionStep step{2u * L.pp.r_len};
-    // Per S tuple: match count c[u] and where its matches are (first match and
-    // bucket run end in LDS, or the chain head in HBM).
-    uint32_t c[kSU], at[kSU], hi[kSU];
-    if (in_lds) {
+    const int32_t* __restrict__ skp = sk + L.s_begin;
+    const int32_t* __restrict__ srp = sr + L.s_begin;
+    uint64_t base = kOnePass ? 0ull : wave_base[(uint64_t)L.item * kJoinWaves + w];
+    int32_t q[kSU], qr[kSU];
+    if (L.pp.r_len <= lds_cap) {
+        int32_t k[RPT], r[RPT];
+        load_r<true, RPT>(rk + L.pp.r_off, rrp, L.pp.r_len, k, r);
+        load_s<true>(skp, srp, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, qr);
+        const LdsView v = lds_view(lds, lds_cap, true);
         const uint32_t log2H = floor_log2_min6(L.pp.r_len);
-        build_lds<true>(rk + L.pp.r_off, rrp, L.pp.r_len, log2H, v.bcnt, v.spare, v.skey, v.srid, v.ctot);
-        uint32_t lo[kSU];
-        probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, lo, hi, c, at);
-    } else {
-#pragma unroll
-        for (uint32_t u = 0; u < kSU; ++u) {
-            c[u] = 0;
-            at[u] = kNotFound;
-            if (wb + u * kWave + lane < we) {
-                at[u] = chain_find(region, region_slot(q[u], step.H), q[u], step);
-                if (at[u] != kNotFound) c[u] = chain_len(next, at[u]);
-            }
+        build_lds<true, RPT>(k, r, L.pp.r_len, log2H, v.bcnt, v.spare, v.skey, v.srid, v.ctot);
+        for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
+            const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
+            if (sb) load_s<true>(skp, srp, wb, we, q, qr);
+            uint32_t run[kSU], cf[kSU];
+            probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, run, cf);
+            const uint64_t pos0 = kOnePass ? block_reserve(lane_pairs_lds(cf), total, wtot, sb != 0) : base;
+            base = write_round_lds(v, q, qr, run, cf, pos0, capacity, out_r, out_s);
         }
-    }
-    uint64_t pos0;
-    if (kOnePass) {
-        uint64_t mine = 0;
-#pragma unroll
-        for (uint32_t u = 0; u < kSU; ++u) mine += c[u];
-        mine = wave_sum(mine);
-        if (lane == 0) wtot[w] = mine;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint64_t t = 0;
-            for (uint32_t i = 0; i < kJoinWaves; ++i) t += wtot[i];
-            wtot[kJoinWaves] = t ? atomicAdd(total, (unsigned long long)t) : 0ull;
-        }
-        __syncthreads();
-        pos0 = wtot[kJoinWaves];
-        for (uint32_t i = 0; i < w; ++i) pos0 += wtot[i];
     } else {
-        pos0 = wave_base[(uint64_t)L.item * kJoinWaves + w];
-    }
+        const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
+        const uint32_t* __restrict__ next = ovf_next + L.pp.r_off;
+        for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
+            const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
+            load_s<true>(skp, srp, wb, we, q, qr);
+            uint32_t c[kSU], at[kSU];
+            probe_hbm(region, next, 2u * L.pp.r_len, q, wb, we, c, at);
+            uint64_t mine = 0;
 #pragma unroll
-    for (uint32_t u = 0; u < kSU; ++u) {
-        uint64_t excl, wtotal;
-        wave_offsets(c[u], &excl, &wtotal);
-        uint64_t pos = pos0 + excl;
-        pos0 += wtotal;
-        if (c[u]) {
-            const int32_t key = q[u], rs = qr[u];
-            if (in_lds) {
-                write_lds_matches(v, key, rs, at[u], hi[u], c[u], pos, capacity, out_r, out_s);
-            } else {
-                uint32_t h = at[u];
-                while (true) {
-                    const uint32_t row = h & ~kLast;
-                    if (pos < capacity) {
-                        out_r[pos] = rrp[row];
-                        out_s[pos] = rs;
-                    }
-                    ++pos;
-                    if (h & kLast) break;
-                    h = next[row];
-                }
-            }
+            for (uint32_t u = 0; u < kSU; ++u) mine += c[u];
+            const uint64_t pos0 = kOnePass ? block_reserve(mine, total, wtot, sb != 0) : base;
+            base = write_round_hbm(next, rrp, qr, c, at, pos0, capacity, out_r, out_s);
         }
     }
 }
 
 // Joins whose whole R fits one LDS table, several jobs per launch: one
-// workgroup per (job, S chunk) builds the table over the job's R and writes
-// the chunk's pairs to the job's output with one-pass reservation.
+// workgroup per (job, chunk of up to kJoinChunk S tuples) builds the table over
+// the job's R and writes the chunk's pairs to the job's output with one-pass
+// reservation.
+template <uint32_t RPT>
 __global__ void __launch_bounds__(kJoinBlock) k_direct_join(const DirectJob* __restrict__ jobs,
                                                            const uint32_t* __restrict__ item_job,
                                                            uint32_t lds_cap) {
     extern __shared__ uint32_t lds[];
     __shared__ uint64_t wtot[kJoinWaves + 1];
     const uint32_t w = threadIdx.x / kWave;
-    const uint32_t lane = lane_id();
     const uint32_t item = xcd_remap(blockIdx.x, gridDim.x);
     const DirectJob J = jobs[item_job[item]];
     const uint32_t s_begin = (item - J.item0) * kJoinChunk;
     const uint32_t s_n = min(kJoinChunk, J.n_s - s_begin);
     const uint32_t r_len = min(J.n_r, lds_cap);  // the planner guarantees n_r <= lds_cap
-    const uint32_t wb = w * kSubJ;
-    const uint32_t we = min(wb + kSubJ, s_n);
+    const int32_t* __restrict__ skp = J.sk + s_begin;
+    const int32_t* __restrict__ srp = J.sr + s_begin;
+    int32_t k[RPT], r[RPT];
+    load_r<true, RPT>(J.rk, J.rr, r_len, k, r);
     int32_t q[kSU], qr[kSU];
-    load_s<true>(J.sk + s_begin, J.sr + s_begin, wb, we, q, qr);
+    load_s<true>(skp, srp, w * kSubJ, min(w * kSubJ + kSubJ, s_n), q, qr);
     const LdsView v = lds_view(lds, lds_cap, true);
     const uint32_t log2H = floor_log2_min6(r_len);
-    build_lds<true>(J.rk, J.rr, r_len, log2H, v.bcnt, v.spare, v.skey, v.srid, v.ctot);
-    uint32_t c[kSU], lo[kSU], hi[kSU], first[kSU];
-    probe_lds(v.bcnt, v.skey, log2H, r_len, q, wb, we, lo, hi, c, first);
-    uint64_t mine = 0;
-#pragma unroll
-    for (uint32_t u = 0; u < kSU; ++u) mine += c[u];
-    mine = wave_sum(mine);
-    if (lane == 0) wtot[w] = mine;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        for (uint32_t i = 0; i < kJoinWaves; ++i) t += wtot[i];
-        wtot[kJoinWaves] = t ? atomicAdd((unsigned long long*)J.count, (unsigned long long)t) : 0ull;
-    }
-    __syncthreads();
-    uint64_t pos0 = wtot[kJoinWaves];
-    for (uint32_t i = 0; i < w; ++i) pos0 += wtot[i];
-#pragma unroll
-    for (uint32_t u = 0; u < kSU; ++u) {
-        uint64_t excl, wtotal;
-        wave_offsets(c[u], &excl, &wtotal);
-        uint64_t pos = pos0 + excl;
-        pos0 += wtotal;
-        if (c[u]) write_lds_matches(v, q[u], qr[u], first[u], hi[u], c[u], pos, J.capacity, J.out_r, J.out_s);
+    build_lds<true, RPT>(k, r, r_len, log2H, v.bcnt, v.spare, v.skey, v.srid, v.ctot);
+    for (uint32_t sb = 0; sb < s_n; sb += kJoinSub) {
+        const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, s_n);
+        if (sb) load_s<true>(skp, srp, wb, we, q, qr);
+        uint32_t run[kSU], cf[kSU];
+        probe_lds(v.bcnt, v.skey, log2H, r_len, q, wb, we, run, cf);
+        const uint64_t pos0 = block_reserve(lane_pairs_lds(cf), (unsigned long long*)J.count, wtot, sb != 0);
+        write_round_lds(v, q, qr, run, cf, pos0, J.capacity, J.out_r, J.out_s);
     }
 }
 
@@ -558,16 +618,29 @@ void direct_zero(const DirectJob* jobs, uint32_t njobs, Recorder& rec) {
     rec.after();
 }
 
+static void allow_lds(const void* fn, size_t lds) {
+    if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <uint32_t RPT>
+void direct_join_t(const DirectJob* jobs, const uint32_t* item_job, uint32_t nitems, uint32_t lds_cap,
+                   Recorder& rec) {
+    const size_t lds = join_lds_bytes(lds_cap, true);
+    allow_lds((const void*)k_direct_join<RPT>, lds);
+    rec.before("direct_join");
+    hipLaunchKernelGGL(k_direct_join<RPT>, dim3(nitems), dim3(kJoinBlock), lds, rec.stream, jobs, item_job,
+                       lds_cap);
+    rec.after();
+}
+
 void direct_join(const DirectJob* jobs, const uint32_t* item_job, uint32_t nitems, uint32_t lds_cap,
                  Recorder& rec) {
     if (nitems == 0) return;
-    const size_t lds = join_lds_bytes(lds_cap, true);
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)k_direct_join, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-    rec.before("direct_join");
-    hipLaunchKernelGGL(k_direct_join, dim3(nitems), dim3(kJoinBlock), lds, rec.stream, jobs, item_job, lds_cap);
-    rec.after();
+    switch (join_rpt(lds_cap)) {
+        case kRptSmall: direct_join_t<kRptSmall>(jobs, item_job, nitems, lds_cap, rec); break;
+        case kRptMid: direct_join_t<kRptMid>(jobs, item_job, nitems, lds_cap, rec); break;
+        default: direct_join_t<kRptLarge>(jobs, item_job, nitems, lds_cap, rec); break;
+    }
 }
 
 void write_zero_count(uint64_t* d_count, Recorder& rec) {
@@ -612,20 +685,74 @@ void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint
     rec.after();
 }
 
+template <uint32_t RPT>
+void join_count_t(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+                  uint32_t grid, const int32_t* rk, const int32_t* sk, uint32_t lds_cap,
+                  const uint64_t* ovf_table, const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec) {
+    const size_t lds = join_lds_bytes(lds_cap, false);
+    allow_lds((const void*)k_join_count<RPT>, lds);
+    rec.before("join_count");
+    hipLaunchKernelGGL(k_join_count<RPT>, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin,
+                       item_part, P, rk, sk, lds_cap, ovf_table, ovf_next, wave_cnt);
+    rec.after();
+}
+
 void join_count(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
                 const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec) {
     if (grid == 0) return;
-    const size_t lds = join_lds_bytes(lds_cap, false);
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)k_join_count, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-    rec.before("join_count");
-    hipLaunchKernelGGL(k_join_count, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin,
-                       item_part, P,
-                       rk, sk, lds_cap, ovf_table, ovf_next, wave_cnt);
+    switch (join_rpt(lds_cap)) {
+        case kRptSmall:
+            join_count_t<kRptSmall>(pairs, item_begin, item_part, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
+                                    wave_cnt, rec);
+            break;
+        case kRptMid:
+            join_count_t<kRptMid>(pairs, item_begin, item_part, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
+                                  wave_cnt, rec);
+            break;
+        default:
+            join_count_t<kRptLarge>(pairs, item_begin, item_part, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
+                                    wave_cnt, rec);
+            break;
+    }
+}
+
+template <bool kOnePass, uint32_t RPT>
+void join_write_t(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+                  uint32_t grid, const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
+                  uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
+                  const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s, uint64_t capacity,
+                  Recorder& rec) {
+    const size_t lds = join_lds_bytes(lds_cap, true);
+    allow_lds((const void*)k_join_write<kOnePass, RPT>, lds);
+    rec.before(kOnePass ? "join_write_1pass" : "join_write");
+    hipLaunchKernelGGL((k_join_write<kOnePass, RPT>), dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs,
+                       item_begin, item_part, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, wave_base,
+                       (unsigned long long*)total, out_r, out_s, capacity);
     rec.after();
+}
+
+template <bool kOnePass>
+void join_write_p(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+                  uint32_t grid, const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
+                  uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
+                  const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s, uint64_t capacity,
+                  Recorder& rec) {
+    switch (join_rpt(lds_cap)) {
+        case kRptSmall:
+            join_write_t<kOnePass, kRptSmall>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap,
+                                              ovf_table, ovf_next, wave_base, total, out_r, out_s, capacity, rec);
+            break;
+        case kRptMid:
+            join_write_t<kOnePass, kRptMid>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap,
+                                            ovf_table, ovf_next, wave_base, total, out_r, out_s, capacity, rec);
+            break;
+        default:
+            join_write_t<kOnePass, kRptLarge>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap,
+                                              ovf_table, ovf_next, wave_base, total, out_r, out_s, capacity, rec);
+            break;
+    }
 }
 
 void join_write(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
@@ -635,20 +762,12 @@ void join_write(const PartPair* pairs, const uint32_t* item_begin, const uint32_
                 const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
                 uint64_t capacity, Recorder& rec) {
     if (grid == 0) return;
-    const size_t lds = join_lds_bytes(lds_cap, true);
-    const bool one_pass = wave_base == nullptr;
-    const void* fn = one_pass ? (const void*)k_join_write<true> : (const void*)k_join_write<false>;
-    if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    rec.before(one_pass ? "join_write_1pass" : "join_write");
-    if (one_pass)
-        hipLaunchKernelGGL(k_join_write<true>, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin,
-                           item_part, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, wave_base,
-                           (unsigned long long*)total, out_r, out_s, capacity);
+    if (wave_base == nullptr)
+        join_write_p<true>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
+                           wave_base, total, out_r, out_s, capacity, rec);
     else
-        hipLaunchKernelGGL(k_join_write<false>, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs,
-                           item_begin, item_part, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, wave_base,
-                           (unsigned long long*)total, out_r, out_s, capacity);
-    rec.after();
+        join_write_p<false>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
+                            wave_base, total, out_r, out_s, capacity, rec);
 }
 
 }  // namespace hj

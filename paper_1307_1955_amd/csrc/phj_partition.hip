@@ -78,8 +78,9 @@ __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restr
     constexpr uint32_t T = kPartBlock * IPT;
     uint32_t* cnt = lds;
     const uint32_t P = 1u << cfg.bits;
-    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= tile_begin[nseg]) return;
+    const uint32_t ntiles = tile_begin[nseg];
+    const uint32_t tile = live_remap(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
     const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
     const PartSeg sg = segs[t.seg];
     for (uint32_t i = threadIdx.x; i < P; i += kPartBlock) cnt[i] = 0;
@@ -127,8 +128,9 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     int32_t* skey = (int32_t*)(ctot + kScanScratch);  // [T]
     int32_t* srid = skey + T;                        // [T]
 
-    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    if (tile >= tile_begin[nseg]) return;
+    const uint32_t ntiles = tile_begin[nseg];
+    const uint32_t tile = live_remap(blockIdx.x, ntiles);
+    if (tile >= ntiles) return;
     const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
     const PartSeg sg = segs[t.seg];
     for (uint32_t i = threadIdx.x; i < Pp; i += kPartBlock) cnt[i] = 0;
