@@ -161,8 +161,10 @@ struct PhjWs {
     uint64_t* wave_cnt;
     uint64_t* ovf_table;
     uint32_t* ovf_next;
-    uint32_t* part32;
-    uint64_t* part64;
+    uint64_t* st1;     // scan states (cleared by the first kernel): pass-1 histogram,
+    uint64_t* st2;     //   pass-2 histogram,
+    uint64_t* stw;     //   per-wave match counts
+    uint64_t nzero;    // words from st1 on to clear
     uint64_t tiles1, tiles2_ub, items_ub, ovf_ub;
     size_t bytes;
 };
@@ -177,7 +179,6 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, void* base) {
     w.hist1 = c.take<uint32_t>(w.tiles1 * pl.P1);
     w.keyA = c.take<int32_t>(n);
     w.ridA = c.take<int32_t>(n);
-    uint64_t hist_max = w.tiles1 * pl.P1;
     if (pl.passes == 2) {
         w.tiles2_ub = cdiv(n, pl.tile) + 2ull * pl.P1;
         w.segs2 = c.take<hj::PartSeg>(2ull * pl.P1);
@@ -186,7 +187,6 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, void* base) {
         w.hist2 = c.take<uint32_t>(w.tiles2_ub * pl.P2);
         w.keyB = c.take<int32_t>(n);
         w.ridB = c.take<int32_t>(n);
-        hist_max = std::max<uint64_t>(hist_max, w.tiles2_ub * pl.P2);
     }
     w.pairs = c.take<hj::PartPair>(pl.P);
     w.item_begin = c.take<uint32_t>(pl.P + 1ull);
@@ -198,8 +198,13 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, void* base) {
     w.wave_cnt = c.take<uint64_t>(w.items_ub * hj::kJoinWaves);
     w.ovf_table = c.take<uint64_t>(2 * n_r);
     w.ovf_next = c.take<uint32_t>(n_r);
-    w.part32 = c.take<uint32_t>(hj::scan_partials(hist_max));
-    w.part64 = c.take<uint64_t>(hj::scan_partials(w.items_ub * hj::kJoinWaves));
+    const uint64_t n1 = hj::scan_state_words(w.tiles1 * pl.P1);
+    const uint64_t n2 = pl.passes == 2 ? hj::scan_state_words(w.tiles2_ub * pl.P2) : 0;
+    const uint64_t nw = hj::scan_state_words(w.items_ub * hj::kJoinWaves);
+    w.st1 = c.take<uint64_t>(n1 + n2 + nw);
+    w.st2 = w.st1 + n1;
+    w.stw = w.st2 + n2;
+    w.nzero = n1 + n2 + nw;
     w.bytes = c.off;
     return w;
 }
@@ -208,7 +213,8 @@ struct ShjWs {
     uint64_t* table;
     uint32_t* next;
     uint64_t* wave_cnt;
-    uint64_t* part64;
+    uint64_t* st;  // scan state of the per-wave counts
+    uint64_t nst;
     uint32_t log2_slots;
     uint64_t tiles;
     size_t bytes;
@@ -222,7 +228,8 @@ ShjWs shj_layout(uint64_t n_r, uint64_t n_s, void* base) {
     w.next = c.take<uint32_t>(n_r);
     w.tiles = cdiv(n_s, hj::kShjTile);
     w.wave_cnt = c.take<uint64_t>(w.tiles * hj::kShjWavesPerBlock);
-    w.part64 = c.take<uint64_t>(hj::scan_partials(w.tiles * hj::kShjWavesPerBlock));
+    w.nst = hj::scan_state_words(w.tiles * hj::kShjWavesPerBlock);
+    w.st = c.take<uint64_t>(w.nst);
     w.bytes = c.off;
     return w;
 }
@@ -295,7 +302,8 @@ void run_shj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
     hj::shj_build(R.key, R.n, w.table, w.next, w.log2_slots, rec);
     if (!pl.one_pass) {
         hj::shj_count(S.key, S.n, w.table, w.next, w.log2_slots, w.wave_cnt, rec);
-        hj::scan_u64(w.wave_cnt, w.wave_cnt, w.tiles * hj::kShjWavesPerBlock, w.part64, d_count, rec);
+        hj::zero_words(w.st, w.nst, rec);
+        hj::scan_u64(w.wave_cnt, w.wave_cnt, w.tiles * hj::kShjWavesPerBlock, w.st, d_count, rec);
     }
     hj::shj_write(S.key, S.rid, S.n, w.table, w.next, w.log2_slots, R.rid, pl.one_pass ? nullptr : w.wave_cnt,
                   d_count, out.rid_r, out.rid_s, out.capacity, rec);
@@ -305,10 +313,11 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
              uint64_t* d_count, hj::Recorder& rec) {
     PhjWs w = phj_layout(pl, R.n, S.n, ws);
     const uint32_t n_r = (uint32_t)R.n, n_s = (uint32_t)S.n;
-    hj::part_setup_pass1(w.segs1, w.tb1, R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, rec);
+    hj::part_setup_pass1(w.segs1, w.tb1, R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, w.st1, w.nzero,
+                         rec);
     hj::PassCfg c1{pl.b2, pl.b1, pl.hash, pl.tile};
     hj::part_hist(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, rec);
-    hj::scan_u32(w.hist1, w.hist1, w.tiles1 * pl.P1, w.part32, nullptr, rec);
+    hj::scan_u32(w.hist1, w.hist1, w.tiles1 * pl.P1, w.st1, nullptr, rec);
     hj::part_scatter(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, w.keyA, w.ridA, rec);
     const hj::PartSeg* segs = w.segs1;
     const uint32_t* tb = w.tb1;
@@ -320,7 +329,7 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
                              w.tb2, w.tseg2, rec);
         hj::PassCfg c2{0, pl.b2, pl.hash, pl.tile};
         hj::part_hist(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, rec);
-        hj::scan_u32(w.hist2, w.hist2, w.tiles2_ub * pl.P2, w.part32, nullptr, rec);
+        hj::scan_u32(w.hist2, w.hist2, w.tiles2_ub * pl.P2, w.st2, nullptr, rec);
         hj::part_scatter(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, w.keyB,
                          w.ridB, rec);
         segs = w.segs2;
@@ -339,7 +348,7 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
     if (!pl.one_pass) {
         hj::join_count(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, fk, fk + n_r, pl.lds_cap,
                        w.ovf_table, w.ovf_next, w.wave_cnt, rec);
-        hj::scan_u64(w.wave_cnt, w.wave_cnt, w.items_ub * hj::kJoinWaves, w.part64, d_count, rec);
+        hj::scan_u64(w.wave_cnt, w.wave_cnt, w.items_ub * hj::kJoinWaves, w.stw, d_count, rec);
     }
     hj::join_write(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, fk, fr, fk + n_r, fr + n_r,
                    pl.lds_cap, w.ovf_table, w.ovf_next, pl.one_pass ? nullptr : w.wave_cnt, d_count,

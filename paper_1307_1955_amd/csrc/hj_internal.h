@@ -39,12 +39,13 @@ struct Recorder {
 };
 
 // ---- scan.hip ----
-// Exclusive scans (reduce-then-scan).  `partials` needs scan_partials(n) entries.
-size_t scan_partials(uint64_t n);
-void scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* partials, uint32_t* total,
-              Recorder& rec);
-void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* partials, uint64_t* total,
-              Recorder& rec);
+// Exclusive scans in one launch.  `state` needs scan_state_words(n) words that
+// are zero when the scan starts (it leaves them non-zero).  `in` may equal `out`.
+size_t scan_state_words(uint64_t n);
+void scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint64_t* state, uint32_t* total, Recorder& rec);
+void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* state, uint64_t* total, Recorder& rec);
+// Clears n words.
+void zero_words(uint64_t* p, uint64_t n, Recorder& rec);
 
 // ---- shj.hip ----
 constexpr uint32_t kShjBlock = 256;
@@ -69,9 +70,10 @@ struct PassCfg {
     uint32_t tile;       // tuples per tile
 };
 // Pass-1 setup: writes the two segment descriptors (R, S) and tile_begin[0..2].
+// Also clears zero[0..nzero) (the join's scan states).
 void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, const int32_t* rr,
                       uint32_t n_r, const int32_t* sk, const int32_t* sr, uint32_t n_s,
-                      uint32_t tile, uint32_t bits, Recorder& rec);
+                      uint32_t tile, uint32_t bits, uint64_t* zero, uint64_t nzero, Recorder& rec);
 // tile_seg: segment of every tile (nullptr: binary search over tile_begin).
 void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec);
@@ -88,8 +90,8 @@ void part_setup_pass2(const uint32_t* hist1_scan, const uint32_t* tile_begin1, u
 // ---- phj_join.hip ----
 constexpr uint32_t kJoinBlock = 512;
 constexpr uint32_t kJoinWaves = kJoinBlock / 64;
-constexpr uint32_t kJoinChunk = 8192;   // S tuples per work item (probed kJoinSub at a time)
-constexpr uint32_t kJoinSub = 4096;     // S tuples per probe round of a work item (8 per lane)
+constexpr uint32_t kJoinSub = 4608;     // S tuples per probe round of a work item (9 per lane)
+constexpr uint32_t kJoinChunk = 2 * kJoinSub;  // S tuples per work item (probed kJoinSub at a time)
 constexpr uint32_t kMaxLdsCap = 8192;   // largest R partition held in LDS
 // R tuples per thread of the LDS build (a kernel template argument: the build
 // keeps them in registers), by lds_cap class.

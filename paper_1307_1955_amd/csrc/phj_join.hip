@@ -283,12 +283,11 @@ __device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const in
 // walked in lockstep (step i reads entry lo + i of every key's run, clamped to
 // a valid address), so each step keeps kSU LDS reads in flight and a wave runs
 // only as many steps as its longest run.  Per key, packed in 16-bit halves
-// (n <= kMaxLdsCap < 2^16): run[u] = lo | hi << 16, its bucket run clamped to
-// [0, n]; cf[u] = matches | first << 16, first = position of its first match
-// (meaningful when it has one).
+// (n <= kMaxLdsCap < 2^16): cf[u] = matches | first << 16, first = position of
+// its first match (meaningful when it has one).
 __device__ __forceinline__ void probe_lds(const uint32_t* bcnt, const int32_t* skey, uint32_t log2H, uint32_t n,
-                                          const int32_t* q, uint32_t wb, uint32_t we, uint32_t* run,
-                                          uint32_t* cf) {
+                                          const int32_t* q, uint32_t wb, uint32_t we, uint32_t* cf) {
+    uint32_t run[kSU];
     const uint32_t sh = 32 - log2H;
     uint32_t len = 0;
 #pragma unroll
@@ -341,26 +340,43 @@ __device__ __forceinline__ void probe_hbm(const uint64_t* __restrict__ region, c
     }
 }
 
+// End of the bucket run of `key` in the LDS table (clamped to n).
+__device__ __forceinline__ uint32_t bucket_end(const uint32_t* bcnt, int32_t key, uint32_t log2H, uint32_t n) {
+    return min(bcnt[(slot_hash(key) >> (32 - log2H)) + 1], n);
+}
+
 // Writes the c >= 1 matches of `key` found from position `first` of its bucket
-// run (ending at hi) to out[pos ...]; the common single match is one store.
+// run to o_r/o_s[p ...], slots below `room` only (o_r, o_s and room are the
+// wave's output window: uniform base pointers and the capacity left there).
+// The common single match is one store; the run's end is looked up only for
+// several matches.
 __device__ __forceinline__ void write_lds_matches(const LdsView& v, int32_t key, int32_t rs, uint32_t first,
-                                                  uint32_t hi, uint32_t c, uint64_t pos, uint64_t capacity,
-                                                  int32_t* __restrict__ out_r, int32_t* __restrict__ out_s) {
-    if (pos < capacity) {
-        out_r[pos] = v.srid[first];
-        out_s[pos] = rs;
+                                                  uint32_t c, uint32_t log2H, uint32_t n, uint32_t p,
+                                                  uint32_t room, int32_t* __restrict__ o_r,
+                                                  int32_t* __restrict__ o_s) {
+    if (p < room) {
+        o_r[p] = v.srid[first];
+        o_s[p] = rs;
     }
     if (c == 1) return;
-    ++pos;
+    ++p;
+    const uint32_t hi = bucket_end(v.bcnt, key, log2H, n);
     for (uint32_t x = first + 1; x < hi; ++x) {
         if (v.skey[x] == key) {
-            if (pos < capacity) {
-                out_r[pos] = v.srid[x];
-                out_s[pos] = rs;
+            if (p < room) {
+                o_r[p] = v.srid[x];
+                o_s[p] = rs;
             }
-            ++pos;
+            ++p;
         }
     }
+}
+
+// Wave-uniform copy of a 64-bit value held equal in every active lane.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Block-wide output reservation for one probe round (the block allocator of
@@ -398,20 +414,27 @@ __device__ __forceinline__ uint32_t lane_pairs_lds(const uint32_t* cf) {
 
 // Stores the round's pairs of this wave from output slot pos0 on (wave-compacted
 // by match counts); returns the slot after the wave's last pair.  LDS table.
-__device__ __forceinline__ uint64_t write_round_lds(const LdsView& v, const int32_t* q, const int32_t* qr,
-                                                    const uint32_t* run, const uint32_t* cf, uint64_t pos0,
+// A round of a wave has fewer than 2^32 pairs (kSubJ keys x kMaxLdsCap
+// matches), so slots are 32-bit offsets from the wave's uniform base.
+__device__ __forceinline__ uint64_t write_round_lds(const LdsView& v, uint32_t log2H, uint32_t n, const int32_t* q,
+                                                    const int32_t* qr, const uint32_t* cf, uint64_t pos0,
                                                     uint64_t capacity, int32_t* __restrict__ out_r,
                                                     int32_t* __restrict__ out_s) {
+    pos0 = uniform64(pos0);
+    const uint64_t left = capacity > pos0 ? capacity - pos0 : 0ull;
+    const uint32_t room = left > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)left;
+    int32_t* __restrict__ o_r = out_r + pos0;
+    int32_t* __restrict__ o_s = out_s + pos0;
+    uint32_t done = 0;  // pairs of the wave written so far
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
         const uint32_t c = cf[u] & 0xFFFFu;
         uint32_t excl, wtotal;
         wave_offsets32(c, &excl, &wtotal);
-        const uint64_t pos = pos0 + excl;
-        pos0 += wtotal;
-        if (c) write_lds_matches(v, q[u], qr[u], cf[u] >> 16, run[u] >> 16, c, pos, capacity, out_r, out_s);
+        if (c) write_lds_matches(v, q[u], qr[u], cf[u] >> 16, c, log2H, n, done + excl, room, o_r, o_s);
+        done += wtotal;
     }
-    return pos0;
+    return pos0 + done;
 }
 
 // The same for the partition-local HBM table: c[u] matches on the row chain
@@ -474,8 +497,8 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             if (sb) load_s<false>(skp, nullptr, wb, we, q, nullptr);
-            uint32_t run[kSU], cf[kSU];
-            probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, run, cf);
+            uint32_t cf[kSU];
+            probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, cf);
             cnt += lane_pairs_lds(cf);
         }
     } else {
@@ -524,10 +547,10 @@ k_join_write(
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             if (sb) load_s<true>(skp, srp, wb, we, q, qr);
-            uint32_t run[kSU], cf[kSU];
-            probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, run, cf);
+            uint32_t cf[kSU];
+            probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, cf);
             const uint64_t pos0 = kOnePass ? block_reserve(lane_pairs_lds(cf), total, wtot, sb != 0) : base;
-            base = write_round_lds(v, q, qr, run, cf, pos0, capacity, out_r, out_s);
+            base = write_round_lds(v, log2H, L.pp.r_len, q, qr, cf, pos0, capacity, out_r, out_s);
         }
     } else {
         const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
@@ -551,7 +574,8 @@ k_join_write(
 // the job's R and writes the chunk's pairs to the job's output with one-pass
 // reservation.
 template <uint32_t RPT>
-__global__ void __launch_bounds__(kJoinBlock) k_direct_join(const DirectJob* __restrict__ jobs,
+__global__ void __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(RPT > kRptMid ? 4 : 6)))
+k_direct_join(const DirectJob* __restrict__ jobs,
                                                            const uint32_t* __restrict__ item_job,
                                                            uint32_t lds_cap) {
     extern __shared__ uint32_t lds[];
@@ -574,10 +598,10 @@ __global__ void __launch_bounds__(kJoinBlock) k_direct_join(const DirectJob* __r
     for (uint32_t sb = 0; sb < s_n; sb += kJoinSub) {
         const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, s_n);
         if (sb) load_s<true>(skp, srp, wb, we, q, qr);
-        uint32_t run[kSU], cf[kSU];
-        probe_lds(v.bcnt, v.skey, log2H, r_len, q, wb, we, run, cf);
+        uint32_t cf[kSU];
+        probe_lds(v.bcnt, v.skey, log2H, r_len, q, wb, we, cf);
         const uint64_t pos0 = block_reserve(lane_pairs_lds(cf), (unsigned long long*)J.count, wtot, sb != 0);
-        write_round_lds(v, q, qr, run, cf, pos0, J.capacity, J.out_r, J.out_s);
+        write_round_lds(v, log2H, r_len, q, qr, cf, pos0, J.capacity, J.out_r, J.out_s);
     }
 }
 

@@ -203,10 +203,12 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     }
 }
 
-__global__ void k_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, const int32_t* rr,
-                              uint32_t n_r, const int32_t* sk, const int32_t* sr, uint32_t n_s,
-                              uint32_t tile, uint32_t bits) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(256) k_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk,
+                                                    const int32_t* rr, uint32_t n_r, const int32_t* sk,
+                                                    const int32_t* sr, uint32_t n_s, uint32_t tile, uint32_t bits,
+                                                    uint64_t* __restrict__ zero, uint64_t nzero) {
+    for (uint64_t i = threadIdx.x; i < nzero; i += blockDim.x) zero[i] = 0;
+    if (threadIdx.x != 0) return;
     const uint32_t nt_r = (n_r + tile - 1) / tile;
     const uint32_t nt_s = (n_s + tile - 1) / tile;
     PartSeg a;
@@ -318,10 +320,10 @@ size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile) {
 
 void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, const int32_t* rr,
                       uint32_t n_r, const int32_t* sk, const int32_t* sr, uint32_t n_s, uint32_t tile,
-                      uint32_t bits, Recorder& rec) {
+                      uint32_t bits, uint64_t* zero, uint64_t nzero, Recorder& rec) {
     rec.before("part_setup1");
-    hipLaunchKernelGGL(k_setup_pass1, dim3(1), dim3(64), 0, rec.stream, segs, tile_begin, rk, rr, n_r,
-                       sk, sr, n_s, tile, bits);
+    hipLaunchKernelGGL(k_setup_pass1, dim3(1), dim3(256), 0, rec.stream, segs, tile_begin, rk, rr, n_r,
+                       sk, sr, n_s, tile, bits, zero, nzero);
     rec.after();
 }
 

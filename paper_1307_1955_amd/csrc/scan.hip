@@ -1,9 +1,20 @@
-// Device-wide exclusive prefix scans (reduce-then-scan, three launches).
+// Device-wide exclusive prefix scans in one launch (chained scan with
+// decoupled look-back).
 //
 // Used for the partition histograms (uint32, modulo 2^32: consumers only take
 // differences inside one segment, which are exact) and for match counts
 // (uint64).  Replaces the paper's dynamic allocation of partition buckets and
 // output (Section 3.3, "Memory allocator") with counted, contiguous placement.
+//
+// Each workgroup takes the next tile from a ticket counter (so every tile's
+// predecessors were started before it and finish without waiting on it),
+// reduces the tile, publishes the tile sum as an "aggregate" status, then walks
+// back over its predecessors' statuses (one wave, 64 at a time), adding
+// aggregates until it meets an "inclusive" one, publishes its own inclusive
+// prefix and writes the tile's scanned values.  A status is one 64-bit word: flag in the top two bits, value
+// below, written and read with single-copy-atomic device-scope accesses.  The
+// state words must be zero before the launch (the callers clear them in the
+// first kernel of a join).
 #include "hj_device.h"
 #include "hj_internal.h"
 
@@ -14,52 +25,32 @@ namespace {
 constexpr uint32_t kScanBlock = 256;
 constexpr uint32_t kScanItems = 16;
 constexpr uint32_t kScanChunk = kScanBlock * kScanItems;
+constexpr uint64_t kFlagAggregate = 1ull << 62;
+constexpr uint64_t kFlagInclusive = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+// Bound on the polls of one predecessor's status: predecessors always finish
+// (see above), the bound only guarantees that the kernel ends.
+constexpr uint32_t kMaxPolls = 1u << 20;
 
+__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// state[0]: tile ticket; state[1 + t]: status of tile t.
 template <typename T>
-__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const T* __restrict__ in, uint64_t n,
-                                                          T* __restrict__ partials) {
-    const uint64_t base = (uint64_t)blockIdx.x * kScanChunk;
-    T s = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < kScanItems; ++k) {
-        const uint64_t i = base + (uint64_t)k * kScanBlock + threadIdx.x;
-        if (i < n) s += in[i];
-    }
-    s = wave_sum(s);
+__global__ void __launch_bounds__(kScanBlock) k_scan(const T* in, T* out, uint64_t n, uint64_t* state,
+                                                   uint32_t ntiles, T* __restrict__ total) {
     __shared__ T wt[kScanBlock / kWave];
-    if (lane_id() == 0) wt[threadIdx.x / kWave] = s;
+    __shared__ uint32_t s_tile;
+    __shared__ T s_prefix;
+    if (threadIdx.x == 0) s_tile = (uint32_t)atomicAdd((unsigned long long*)state, 1ull);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        T t = 0;
-        for (uint32_t w = 0; w < kScanBlock / kWave; ++w) t += wt[w];
-        partials[blockIdx.x] = t;
-    }
-}
-
-// One block scans the partials in place (exclusive) and writes the grand total.
-template <typename T>
-__global__ void __launch_bounds__(kScanBlock) k_scan_partials(T* __restrict__ partials, uint32_t nb,
-                                                            T* __restrict__ total) {
-    __shared__ T wt[kScanBlock / kWave];
-    T carry = 0;
-    for (uint32_t base = 0; base < nb; base += kScanBlock) {
-        const uint32_t i = base + threadIdx.x;
-        T v = i < nb ? partials[i] : T(0);
-        T tot;
-        T ex = block_excl_scan(v, wt, &tot);
-        if (i < nb) partials[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && total) *total = carry;
-}
-
-// Each block scans its chunk (items held per thread in consecutive order) and
-// adds its partial prefix.  `in` and `out` may alias.
-template <typename T>
-__global__ void __launch_bounds__(kScanBlock) k_scan_apply(const T* in, T* out, uint64_t n,
-                                                         const T* __restrict__ partials) {
-    __shared__ T wt[kScanBlock / kWave];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
+    const uint32_t tile = s_tile;
+    const uint64_t base = (uint64_t)tile * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
     T v[kScanItems];
     T s = 0;
 #pragma unroll
@@ -69,7 +60,35 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const T* in, T* out, 
         s += v[k];
     }
     T tot;
-    T run = block_excl_scan(s, wt, &tot) + partials[blockIdx.x];
+    T run = block_excl_scan(s, wt, &tot);
+    if (threadIdx.x < kWave) {  // wave 0: publish, then look back 64 predecessors at a time
+        const uint32_t lane = threadIdx.x;
+        uint64_t* st = state + 1;
+        if (lane == 0)
+            status_store(&st[tile], (tile == 0 ? kFlagInclusive : kFlagAggregate) | ((uint64_t)tot & kValueMask));
+        T prefix = 0;
+        int64_t j = (int64_t)tile - 1;
+        while (j >= 0) {
+            const int64_t idx = j - (int64_t)lane;  // lane 0 is the nearest predecessor
+            uint64_t w = idx >= 0 ? status_load(&st[idx]) : kFlagInclusive;  // nothing before tile 0
+            for (uint32_t polls = 0; __ballot((w >> 62) == 0) != 0 && polls < kMaxPolls; ++polls) {
+                if (polls > 8) __builtin_amdgcn_s_sleep(1);
+                if ((w >> 62) == 0) w = status_load(&st[idx]);
+            }
+            const uint64_t incl = __ballot((w >> 62) != 1);  // inclusive (or, past the poll bound, unset)
+            const uint32_t stop = incl ? (uint32_t)__ffsll((unsigned long long)incl) - 1 : kWave - 1;
+            prefix += wave_sum(lane <= stop ? (T)(w & kValueMask) : T(0));
+            if (incl) break;
+            j -= kWave;
+        }
+        if (lane == 0) {
+            if (tile != 0) status_store(&st[tile], kFlagInclusive | ((uint64_t)(prefix + tot) & kValueMask));
+            s_prefix = prefix;
+            if (tile == ntiles - 1 && total) *total = prefix + tot;
+        }
+    }
+    __syncthreads();
+    run += s_prefix;
 #pragma unroll
     for (uint32_t k = 0; k < kScanItems; ++k) {
         const uint64_t i = base + k;
@@ -79,42 +98,46 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const T* in, T* out, 
 }
 
 template <typename T>
-void scan_impl(const T* in, T* out, uint64_t n, T* partials, T* total, Recorder& rec,
-               const char* name) {
-    const uint64_t nb = (n + kScanChunk - 1) / kScanChunk;
-    if (nb == 0) {
-        rec.before(name);
-        hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(kScanBlock), 0, rec.stream, partials,
-                           0u, total);
-        rec.after();
-        return;
-    }
+__global__ void k_scan_empty(T* __restrict__ total) {
+    if (threadIdx.x == 0 && total) *total = 0;
+}
+
+__global__ void __launch_bounds__(256) k_zero_words(uint64_t* __restrict__ p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+template <typename T>
+void scan_impl(const T* in, T* out, uint64_t n, uint64_t* state, T* total, Recorder& rec, const char* name) {
+    const uint64_t nt = (n + kScanChunk - 1) / kScanChunk;
     rec.before(name);
-    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((uint32_t)nb), dim3(kScanBlock), 0, rec.stream, in,
-                       n, partials);
-    rec.after();
-    rec.before(name);
-    hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(kScanBlock), 0, rec.stream, partials,
-                       (uint32_t)nb, total);
-    rec.after();
-    rec.before(name);
-    hipLaunchKernelGGL(k_scan_apply<T>, dim3((uint32_t)nb), dim3(kScanBlock), 0, rec.stream, in,
-                       out, n, partials);
+    if (nt == 0)
+        hipLaunchKernelGGL(k_scan_empty<T>, dim3(1), dim3(64), 0, rec.stream, total);
+    else
+        hipLaunchKernelGGL(k_scan<T>, dim3((uint32_t)nt), dim3(kScanBlock), 0, rec.stream, in, out, n, state,
+                           (uint32_t)nt, total);
     rec.after();
 }
 
 }  // namespace
 
-size_t scan_partials(uint64_t n) { return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1; }
+size_t scan_state_words(uint64_t n) { return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1; }
 
-void scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* partials, uint32_t* total,
-              Recorder& rec) {
-    scan_impl<uint32_t>(in, out, n, partials, total, rec, "scan_u32");
+void scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint64_t* state, uint32_t* total, Recorder& rec) {
+    scan_impl<uint32_t>(in, out, n, state, total, rec, "scan_u32");
 }
 
-void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* partials, uint64_t* total,
-              Recorder& rec) {
-    scan_impl<uint64_t>(in, out, n, partials, total, rec, "scan_u64");
+void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* state, uint64_t* total, Recorder& rec) {
+    scan_impl<uint64_t>(in, out, n, state, total, rec, "scan_u64");
+}
+
+void zero_words(uint64_t* p, uint64_t n, Recorder& rec) {
+    if (n == 0) return;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    rec.before("zero_state");
+    hipLaunchKernelGGL(k_zero_words, dim3((uint32_t)blocks), dim3(256), 0, rec.stream, p, n);
+    rec.after();
 }
 
 }  // namespace hj
