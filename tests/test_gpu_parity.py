@@ -107,13 +107,15 @@ def test_cartesian_all_equal(kw):
 @pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="phj", passes=2, bits=(6, 6)),
                                 dict(algo="phj", passes=1, bits=(8,), hash="murmur2"),
                                 dict(algo="phj", passes=2, bits=(6, 6), one_pass=True)])
-def test_r_side_skew(kw):
-    """10% of R shares one key (a heavy partition that overflows the LDS budget)."""
+@pytest.mark.parametrize("frac", [0.10, 0.25])
+def test_r_side_skew(kw, frac):
+    """A fraction of R shares one key (the low/high skew sets of Section 5.1): a heavy
+    partition that overflows the LDS budget, and a many-to-many match."""
     n_r, n_s = 1 << 17, 1 << 18
     r, s = gen.unique_uniform(8, n_r, n_s, 2 * n_r)
     rk = r.key.copy()
     rng = np.random.default_rng(3)
-    rk[rng.choice(n_r, n_r // 10, replace=False)] = 12345
+    rk[rng.choice(n_r, int(n_r * frac), replace=False)] = 12345
     sk = s.key.copy()
     sk[:50] = 12345
     check_small(hj.params(**kw), rk, r.rid, sk, s.rid)
