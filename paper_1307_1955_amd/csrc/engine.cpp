@@ -163,7 +163,8 @@ struct PhjWs {
     uint32_t* ovf_next;
     uint64_t* st1;     // scan states (cleared by the first kernel): pass-1 histogram,
     uint64_t* st2;     //   pass-2 histogram,
-    uint64_t* stw;     //   per-wave match counts
+    uint64_t* stw;     //   per-wave match counts,
+    uint64_t* stp;     //   join plan
     uint64_t nzero;    // words from st1 on to clear
     uint64_t tiles1, tiles2_ub, items_ub, ovf_ub;
     size_t bytes;
@@ -201,10 +202,12 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, void* base) {
     const uint64_t n1 = hj::scan_state_words(w.tiles1 * pl.P1);
     const uint64_t n2 = pl.passes == 2 ? hj::scan_state_words(w.tiles2_ub * pl.P2) : 0;
     const uint64_t nw = hj::scan_state_words(w.items_ub * hj::kJoinWaves);
-    w.st1 = c.take<uint64_t>(n1 + n2 + nw);
+    const uint64_t np = hj::plan_state_words(pl.P);
+    w.st1 = c.take<uint64_t>(n1 + n2 + nw + np);
     w.st2 = w.st1 + n1;
     w.stw = w.st2 + n2;
-    w.nzero = n1 + n2 + nw;
+    w.stp = w.stw + nw;
+    w.nzero = n1 + n2 + nw + np;
     w.bytes = c.off;
     return w;
 }
@@ -342,7 +345,7 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
     }
     hj::JoinPlanOut po{w.pairs, w.item_begin, w.ovf_begin, w.item_part, w.ovf_part};
     hj::join_plan(segs, tb, nseg, bits_last, hist_last, n_r, n_s, pl.B, pl.lds_cap, po,
-                  pl.one_pass ? d_count : nullptr, rec);
+                  pl.one_pass ? d_count : nullptr, w.stp, rec);
     hj::join_ovf_build(w.pairs, w.ovf_begin, w.ovf_part, pl.P, (uint32_t)w.ovf_ub, fk, w.ovf_table, w.ovf_next,
                        rec);
     if (!pl.one_pass) {

@@ -288,6 +288,52 @@ __device__ __forceinline__ uint32_t live_remap(uint32_t b, uint32_t live) {
     return b < live ? xcd_remap(b, live) : b;
 }
 
+// ---- chained (decoupled look-back) scans across workgroups ----
+// A status word: flag in the top two bits (0 unset, 1 aggregate, 2 inclusive),
+// a value below 2^62.
+constexpr uint64_t kStatusAggregate = 1ull << 62;
+constexpr uint64_t kStatusInclusive = 2ull << 62;
+constexpr uint64_t kStatusValue = (1ull << 62) - 1;
+// Bound on the polls of one unset status: predecessors always publish (they
+// took their tickets earlier and wait on nothing later), the bound only
+// guarantees that a kernel ends.
+constexpr uint32_t kMaxStatusPolls = 1u << 20;
+
+__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by all 64 lanes of one wave of tile `tile` (tiles numbered by ticket):
+// publishes the tile's sum `tot` (< 2^62) in st[tile], walks back over the
+// predecessors' statuses 64 at a time, adding aggregates until it meets an
+// inclusive prefix, publishes its own inclusive prefix and returns the sum of
+// all predecessors.
+__device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint32_t tile, uint64_t tot) {
+    const uint32_t lane = lane_id();
+    if (lane == 0) status_store(&st[tile], (tile == 0 ? kStatusInclusive : kStatusAggregate) | (tot & kStatusValue));
+    uint64_t prefix = 0;
+    int64_t j = (int64_t)tile - 1;
+    while (j >= 0) {
+        const int64_t idx = j - (int64_t)lane;  // lane 0 is the nearest predecessor
+        uint64_t w = idx >= 0 ? status_load(&st[idx]) : kStatusInclusive;  // nothing before tile 0
+        for (uint32_t polls = 0; __ballot((w >> 62) == 0) != 0 && polls < kMaxStatusPolls; ++polls) {
+            if (polls > 8) __builtin_amdgcn_s_sleep(1);
+            if ((w >> 62) == 0) w = status_load(&st[idx]);
+        }
+        const uint64_t incl = __ballot((w >> 62) != 1);  // inclusive (or, past the poll bound, unset)
+        const uint32_t stop = incl ? (uint32_t)__ffsll((unsigned long long)incl) - 1 : kWave - 1;
+        prefix += wave_sum(lane <= stop ? (w & kStatusValue) : 0ull);
+        if (incl) break;
+        j -= kWave;
+    }
+    if (lane == 0 && tile != 0) status_store(&st[tile], kStatusInclusive | ((prefix + tot) & kStatusValue));
+    return prefix;
+}
+
 // Largest s in [0, n) with begin[s] <= v, for a nondecreasing begin[0..n].
 template <typename T>
 __device__ __forceinline__ uint32_t upper_index(const T* begin, uint32_t n, T v) {

@@ -107,10 +107,13 @@ struct JoinPlanOut {
     uint32_t* ovf_part;    // [ovf_grid] partition of every HBM-table build chunk
 };
 // Final partition table from the last pass's histogram scan, work-item and
-// overflow-chunk scans.  `segs`/`tile_begin`/`nseg` are the last pass's.
+// overflow-chunk scans and maps, in one launch.  `segs`/`tile_begin`/`nseg`
+// are the last pass's; `state` needs plan_state_words(2^total_bits) words that
+// are zero when it starts.
+size_t plan_state_words(uint32_t P);
 void join_plan(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t bits_last,
                const uint32_t* hist_scan, uint32_t n_r, uint32_t n_s, uint32_t total_bits,
-               uint32_t lds_cap, const JoinPlanOut& o, uint64_t* zero_total, Recorder& rec);
+               uint32_t lds_cap, const JoinPlanOut& o, uint64_t* zero_total, uint64_t* state, Recorder& rec);
 // Upper bounds of the HBM-table build items and of the join work items.
 uint32_t ovf_grid(uint32_t P, uint64_t n_r);
 uint32_t join_grid(uint32_t P, uint64_t n_s);

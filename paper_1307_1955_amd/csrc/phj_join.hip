@@ -24,8 +24,9 @@ namespace hj {
 namespace {
 
 constexpr uint32_t kOvfChunk = 4096;                  // R tuples per HBM-table build item
+constexpr uint32_t kOvfGrid = 1024;                   // workgroups of the HBM-table build launches
 constexpr uint32_t kSubJ = kJoinSub / kJoinWaves;     // S tuples per wave of a probe round
-constexpr uint32_t kPlanBlock = 1024;
+constexpr uint32_t kPlanBlock = 256;
 
 // Start of final partition i of one relation (positions relative to the relation).
 __device__ __forceinline__ uint32_t final_start(const PartSeg* __restrict__ segs,
@@ -50,64 +51,62 @@ __device__ __forceinline__ uint32_t ovf_chunks_of(const PartPair& pp, uint32_t l
     return (pp.r_len > lds_cap && pp.s_len) ? (pp.r_len + kOvfChunk - 1) / kOvfChunk : 0u;
 }
 
-// Plan, step 1 (one thread per partition pair): ranges of R_i and S_i from the
-// last pass's histogram scan, and the number of work items and of HBM-table
-// build chunks of the pair (temporarily in item_begin / ovf_begin).
-__global__ void __launch_bounds__(256) k_join_pairs(
+// Plan (one thread per partition pair, workgroups in ticket order): ranges of
+// R_i and S_i from the last pass's histogram scan, the pair's work items and
+// HBM-table build chunks, their exclusive scans over all pairs (one chained
+// scan of both counts packed in one word) and the item -> pair maps.
+// state[0]: ticket; state[1 + b]: status of workgroup b (cleared beforehand).
+__global__ void __launch_bounds__(kPlanBlock) k_join_plan(
     const PartSeg* __restrict__ segs, const uint32_t* __restrict__ tile_begin, uint32_t nseg,
     uint32_t bits_last, const uint32_t* __restrict__ hist_scan, uint32_t n_r, uint32_t n_s,
-    uint32_t total_bits, uint32_t lds_cap, PartPair* __restrict__ pairs, uint32_t* __restrict__ item_cnt,
-    uint32_t* __restrict__ ovf_cnt, uint64_t* __restrict__ zero_total) {
+    uint32_t total_bits, uint32_t lds_cap, PartPair* __restrict__ pairs, uint32_t* __restrict__ item_begin,
+    uint32_t* __restrict__ ovf_begin, uint32_t* __restrict__ item_part, uint32_t* __restrict__ ovf_part,
+    uint64_t* __restrict__ zero_total, uint64_t* state) {
+    __shared__ uint64_t wt[kPlanBlock / kWave];
+    __shared__ uint32_t s_blk;
+    __shared__ uint64_t s_prefix;
+    if (threadIdx.x == 0) s_blk = (uint32_t)atomicAdd((unsigned long long*)state, 1ull);
+    __syncthreads();
+    const uint32_t blk = s_blk;
     const uint32_t P = 1u << total_bits;
     const uint32_t nseg_rel = nseg / 2;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = blk * kPlanBlock + threadIdx.x;
     if (i == 0 && zero_total) *zero_total = 0;
-    if (i >= P) return;
-    const uint32_t r0 = min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i, n_r, 0, P), n_r);
-    const uint32_t s0 = min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i, n_s, n_r, P), n_s);
-    // clamped: a partition never extends past its relation or runs backwards
-    const uint32_t r1 = max(r0, min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i + 1, n_r, 0, P), n_r));
-    const uint32_t s1 = max(s0, min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i + 1, n_s, n_r, P), n_s));
-    PartPair pp;
-    pp.r_off = r0;
-    pp.r_len = r1 - r0;
-    pp.s_off = s0;
-    pp.s_len = s1 - s0;
-    pairs[i] = pp;
-    item_cnt[i] = items_of(pp);
-    ovf_cnt[i] = ovf_chunks_of(pp, lds_cap);
-}
-
-// Plan, step 2 (one block): exclusive scans of the per-pair counts (in place)
-// and the item -> pair maps.
-__global__ void __launch_bounds__(kPlanBlock) k_join_plan(uint32_t P, uint32_t* __restrict__ item_begin,
-                                                         uint32_t* __restrict__ ovf_begin,
-                                                         uint32_t* __restrict__ item_part,
-                                                         uint32_t* __restrict__ ovf_part) {
-    __shared__ uint32_t wt[kPlanBlock / kWave];
-    const uint32_t per = (P + kPlanBlock - 1) / kPlanBlock;
-    const uint32_t a = min(threadIdx.x * per, P);
-    const uint32_t b = min(a + per, P);
-    uint32_t items = 0, ovf = 0;
-    for (uint32_t i = a; i < b; ++i) {
-        items += item_begin[i];
-        ovf += ovf_begin[i];
+    PartPair pp{0, 0, 0, 0};
+    uint32_t ni = 0, no = 0;
+    if (i < P) {
+        const uint32_t r0 = min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i, n_r, 0, P), n_r);
+        const uint32_t s0 = min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i, n_s, n_r, P), n_s);
+        // clamped: a partition never extends past its relation or runs backwards
+        const uint32_t r1 = max(r0, min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i + 1, n_r, 0, P), n_r));
+        const uint32_t s1 = max(s0, min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i + 1, n_s, n_r, P), n_s));
+        pp.r_off = r0;
+        pp.r_len = r1 - r0;
+        pp.s_off = s0;
+        pp.s_len = s1 - s0;
+        ni = items_of(pp);
+        no = ovf_chunks_of(pp, lds_cap);
     }
-    uint32_t tot_items, tot_ovf;
-    uint32_t run_i = block_excl_scan(items, wt, &tot_items);
-    uint32_t run_o = block_excl_scan(ovf, wt, &tot_ovf);
-    for (uint32_t i = a; i < b; ++i) {
-        const uint32_t ni = item_begin[i], no = ovf_begin[i];
-        item_begin[i] = run_i;
-        ovf_begin[i] = run_o;
-        for (uint32_t x = 0; x < ni; ++x) item_part[run_i + x] = i;
-        for (uint32_t x = 0; x < no; ++x) ovf_part[run_o + x] = i;
-        run_i += ni;
-        run_o += no;
+    // items and chunks are each below 2^31: packed as items | chunks << 31
+    uint64_t tot;
+    const uint64_t excl = block_excl_scan((uint64_t)ni | ((uint64_t)no << 31), wt, &tot);
+    if (threadIdx.x < kWave) {
+        const uint64_t prefix = lookback_wave(state + 1, blk, tot);
+        if (threadIdx.x == 0) s_prefix = prefix;
     }
-    if (threadIdx.x == 0) {
-        item_begin[P] = tot_items;
-        ovf_begin[P] = tot_ovf;
+    __syncthreads();
+    const uint64_t run = s_prefix + excl;
+    const uint32_t ib = (uint32_t)(run & 0x7FFFFFFFu), ob = (uint32_t)(run >> 31);
+    if (i < P) {
+        pairs[i] = pp;
+        item_begin[i] = ib;
+        ovf_begin[i] = ob;
+        for (uint32_t x = 0; x < ni; ++x) item_part[ib + x] = i;
+        for (uint32_t x = 0; x < no; ++x) ovf_part[ob + x] = i;
+    }
+    if (i == P - 1) {  // the last pair also writes the totals
+        item_begin[P] = ib + ni;
+        ovf_begin[P] = ob + no;
     }
 }
 
@@ -119,15 +118,16 @@ __global__ void __launch_bounds__(256) k_ovf_clear(const PartPair* __restrict__ 
                                                   const uint32_t* __restrict__ ovf_begin,
                                                   const uint32_t* __restrict__ ovf_part, uint32_t P,
                                                   uint64_t* __restrict__ ovf_table) {
-    const uint32_t item = blockIdx.x;
-    if (item >= ovf_begin[P]) return;
-    const uint32_t i = ovf_part[item];
-    const uint32_t c = item - ovf_begin[i];
-    const PartPair pp = pairs[i];
-    uint64_t* region = ovf_table + 2ull * pp.r_off;
-    const uint64_t H = 2ull * pp.r_len;
-    const uint64_t end = min(2ull * (c + 1) * kOvfChunk, H);
-    for (uint64_t x = 2ull * c * kOvfChunk + threadIdx.x; x < end; x += blockDim.x) region[x] = kEmptySlot;
+    const uint32_t nitems = ovf_begin[P];
+    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const uint32_t i = ovf_part[item];
+        const uint32_t c = item - ovf_begin[i];
+        const PartPair pp = pairs[i];
+        uint64_t* region = ovf_table + 2ull * pp.r_off;
+        const uint64_t H = 2ull * pp.r_len;
+        const uint64_t end = min(2ull * (c + 1) * kOvfChunk, H);
+        for (uint64_t x = 2ull * c * kOvfChunk + threadIdx.x; x < end; x += blockDim.x) region[x] = kEmptySlot;
+    }
 }
 
 struct RegionStep {
@@ -141,18 +141,19 @@ __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ 
                                                   const int32_t* __restrict__ rk,
                                                   uint64_t* __restrict__ ovf_table,
                                                   uint32_t* __restrict__ ovf_next) {
-    const uint32_t item = blockIdx.x;
-    if (item >= ovf_begin[P]) return;
-    const uint32_t i = ovf_part[item];
-    const uint32_t c = item - ovf_begin[i];
-    const PartPair pp = pairs[i];
-    uint64_t* region = ovf_table + 2ull * pp.r_off;
-    uint32_t* next = ovf_next + pp.r_off;
-    const RegionStep step{2u * pp.r_len};
-    const uint32_t end = min((c + 1) * kOvfChunk, pp.r_len);
-    for (uint32_t j = c * kOvfChunk + threadIdx.x; j < end; j += blockDim.x) {
-        const int32_t k = rk[pp.r_off + j];
-        chain_insert(region, next, region_slot(k, step.H), k, j, step);
+    const uint32_t nitems = ovf_begin[P];
+    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const uint32_t i = ovf_part[item];
+        const uint32_t c = item - ovf_begin[i];
+        const PartPair pp = pairs[i];
+        uint64_t* region = ovf_table + 2ull * pp.r_off;
+        uint32_t* next = ovf_next + pp.r_off;
+        const RegionStep step{2u * pp.r_len};
+        const uint32_t end = min((c + 1) * kOvfChunk, pp.r_len);
+        for (uint32_t j = c * kOvfChunk + threadIdx.x; j < end; j += blockDim.x) {
+            const int32_t k = rk[pp.r_off + j];
+            chain_insert(region, next, region_slot(k, step.H), k, j, step);
+        }
     }
 }
 
@@ -673,18 +674,16 @@ void write_zero_count(uint64_t* d_count, Recorder& rec) {
     rec.after();
 }
 
+size_t plan_state_words(uint32_t P) { return 1 + (P + kPlanBlock - 1) / kPlanBlock; }
+
 void join_plan(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t bits_last,
                const uint32_t* hist_scan, uint32_t n_r, uint32_t n_s, uint32_t total_bits,
-               uint32_t lds_cap, const JoinPlanOut& o, uint64_t* zero_total, Recorder& rec) {
+               uint32_t lds_cap, const JoinPlanOut& o, uint64_t* zero_total, uint64_t* state, Recorder& rec) {
     const uint32_t P = 1u << total_bits;
-    rec.before("join_pairs");
-    hipLaunchKernelGGL(k_join_pairs, dim3((P + 255) / 256), dim3(256), 0, rec.stream, segs, tile_begin, nseg,
-                       bits_last, hist_scan, n_r, n_s, total_bits, lds_cap, o.pairs, o.item_begin, o.ovf_begin,
-                       zero_total);
-    rec.after();
     rec.before("join_plan");
-    hipLaunchKernelGGL(k_join_plan, dim3(1), dim3(kPlanBlock), 0, rec.stream, P, o.item_begin, o.ovf_begin,
-                       o.item_part, o.ovf_part);
+    hipLaunchKernelGGL(k_join_plan, dim3((P + kPlanBlock - 1) / kPlanBlock), dim3(kPlanBlock), 0, rec.stream,
+                       segs, tile_begin, nseg, bits_last, hist_scan, n_r, n_s, total_bits, lds_cap, o.pairs,
+                       o.item_begin, o.ovf_begin, o.item_part, o.ovf_part, zero_total, state);
     rec.after();
 }
 
@@ -699,6 +698,7 @@ uint32_t join_grid(uint32_t P, uint64_t n_s) {
 void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint32_t* ovf_part, uint32_t P,
                     uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, Recorder& rec) {
     if (grid == 0) return;
+    grid = grid < kOvfGrid ? grid : kOvfGrid;  // grid-stride: few chunks in the common case
     rec.before("ovf_clear");
     hipLaunchKernelGGL(k_ovf_clear, dim3(grid), dim3(256), 0, rec.stream, pairs, ovf_begin, ovf_part, P,
                        ovf_table);

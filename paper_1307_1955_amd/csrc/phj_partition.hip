@@ -224,6 +224,7 @@ __global__ void __launch_bounds__(256) k_setup_pass1(PartSeg* segs, uint32_t* ti
 }
 
 constexpr uint32_t kSetupBlock = 1024;
+constexpr uint32_t kSetupLdsSegs = 4096;  // segment table kept in LDS up to this many segments
 
 // Start of partition q of a pass-1 segment relative to the segment.
 __device__ __forceinline__ uint32_t seg_part_start(const uint32_t* __restrict__ hs_seg, uint32_t nt,
@@ -237,6 +238,7 @@ __global__ void __launch_bounds__(kSetupBlock) k_setup_pass2(
     uint32_t bits2, PartSeg* __restrict__ segs2, uint32_t* __restrict__ tile_begin2,
     uint32_t* __restrict__ tile_seg2) {
     __shared__ uint32_t wt[kSetupBlock / kWave];
+    __shared__ uint32_t tb[kSetupLdsSegs + 1];
     const uint32_t P1 = 1u << bits1;
     const uint32_t nseg = 2 * P1;
     const uint32_t per = (nseg + kSetupBlock - 1) / kSetupBlock;
@@ -265,6 +267,7 @@ __global__ void __launch_bounds__(kSetupBlock) k_setup_pass2(
     }
     uint32_t total;
     uint32_t run = block_excl_scan(ntiles, wt, &total);
+    const bool in_lds = nseg < kSetupLdsSegs;
     for (uint32_t s = a; s < b; ++s) {
         uint32_t off, len, base;
         seg_range(s, &off, &len, &base);
@@ -277,11 +280,21 @@ __global__ void __launch_bounds__(kSetupBlock) k_setup_pass2(
         g.pad = 0;
         segs2[s] = g;
         tile_begin2[s] = run;
+        if (in_lds) tb[s] = run;
         const uint32_t nt = (len + tile - 1) / tile;
-        for (uint32_t x = 0; x < nt; ++x) tile_seg2[run + x] = s;
+        if (!in_lds)
+            for (uint32_t x = 0; x < nt; ++x) tile_seg2[run + x] = s;
         run += nt;
     }
-    if (threadIdx.x == 0) tile_begin2[nseg] = total;
+    if (threadIdx.x == 0) {
+        tile_begin2[nseg] = total;
+        if (in_lds) tb[nseg] = total;
+    }
+    if (in_lds) {
+        // every thread maps its share of the tiles to segments (binary search in LDS)
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < total; t += kSetupBlock) tile_seg2[t] = upper_index(tb, nseg, t);
+    }
 }
 
 template <uint32_t IPT>

@@ -25,21 +25,6 @@ namespace {
 constexpr uint32_t kScanBlock = 256;
 constexpr uint32_t kScanItems = 16;
 constexpr uint32_t kScanChunk = kScanBlock * kScanItems;
-constexpr uint64_t kFlagAggregate = 1ull << 62;
-constexpr uint64_t kFlagInclusive = 2ull << 62;
-constexpr uint64_t kValueMask = (1ull << 62) - 1;
-// Bound on the polls of one predecessor's status: predecessors always finish
-// (see above), the bound only guarantees that the kernel ends.
-constexpr uint32_t kMaxPolls = 1u << 20;
-
-__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // state[0]: tile ticket; state[1 + t]: status of tile t.
 template <typename T>
 __global__ void __launch_bounds__(kScanBlock) k_scan(const T* in, T* out, uint64_t n, uint64_t* state,
@@ -61,28 +46,9 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(const T* in, T* out, uint64
     }
     T tot;
     T run = block_excl_scan(s, wt, &tot);
-    if (threadIdx.x < kWave) {  // wave 0: publish, then look back 64 predecessors at a time
-        const uint32_t lane = threadIdx.x;
-        uint64_t* st = state + 1;
-        if (lane == 0)
-            status_store(&st[tile], (tile == 0 ? kFlagInclusive : kFlagAggregate) | ((uint64_t)tot & kValueMask));
-        T prefix = 0;
-        int64_t j = (int64_t)tile - 1;
-        while (j >= 0) {
-            const int64_t idx = j - (int64_t)lane;  // lane 0 is the nearest predecessor
-            uint64_t w = idx >= 0 ? status_load(&st[idx]) : kFlagInclusive;  // nothing before tile 0
-            for (uint32_t polls = 0; __ballot((w >> 62) == 0) != 0 && polls < kMaxPolls; ++polls) {
-                if (polls > 8) __builtin_amdgcn_s_sleep(1);
-                if ((w >> 62) == 0) w = status_load(&st[idx]);
-            }
-            const uint64_t incl = __ballot((w >> 62) != 1);  // inclusive (or, past the poll bound, unset)
-            const uint32_t stop = incl ? (uint32_t)__ffsll((unsigned long long)incl) - 1 : kWave - 1;
-            prefix += wave_sum(lane <= stop ? (T)(w & kValueMask) : T(0));
-            if (incl) break;
-            j -= kWave;
-        }
-        if (lane == 0) {
-            if (tile != 0) status_store(&st[tile], kFlagInclusive | ((uint64_t)(prefix + tot) & kValueMask));
+    if (threadIdx.x < kWave) {  // wave 0: publish, then look back
+        const T prefix = (T)lookback_wave(state + 1, tile, (uint64_t)tot & kStatusValue);
+        if (threadIdx.x == 0) {
             s_prefix = prefix;
             if (tile == ntiles - 1 && total) *total = prefix + tot;
         }
