@@ -83,8 +83,6 @@ __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restr
     if (tile >= ntiles) return;
     const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
     const PartSeg sg = segs[t.seg];
-    for (uint32_t i = threadIdx.x; i < P; i += kPartBlock) cnt[i] = 0;
-    __syncthreads();
     const int32_t* __restrict__ kin = sg.key_in + t.start;
     int32_t keys[IPT];
 #pragma unroll
@@ -92,6 +90,9 @@ __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restr
         const uint32_t idx = k * kPartBlock + threadIdx.x;
         keys[k] = idx < t.len ? kin[idx] : 0;
     }
+    // counters cleared while the tile's loads are in flight
+    for (uint32_t i = threadIdx.x; i < P; i += kPartBlock) cnt[i] = 0;
+    __syncthreads();
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (uint32_t k = 0; k < IPT; ++k) {
@@ -133,9 +134,6 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     if (tile >= ntiles) return;
     const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
     const PartSeg sg = segs[t.seg];
-    for (uint32_t i = threadIdx.x; i < Pp; i += kPartBlock) cnt[i] = 0;
-    __syncthreads();
-
     const int32_t* __restrict__ kin = sg.key_in + t.start;
     const int32_t* __restrict__ rin = sg.rid_in + t.start;
     int32_t keys[IPT], rids[IPT];
@@ -147,6 +145,14 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
         keys[k] = valid ? kin[idx] : 0;
         rids[k] = valid ? rin[idx] : 0;
     }
+    // This tile's global partition offsets do not depend on the tile's data:
+    // fetched together with it (first kPartBlock partitions; the rest later).
+    const uint32_t* __restrict__ hs = hist_scan + sg.hist_base;
+    const uint32_t hs_own = threadIdx.x < P ? hs[(uint64_t)threadIdx.x * t.nt + t.tl] : 0u;
+    const uint32_t seg0 = hs[0];
+    // counters cleared while the loads are in flight
+    for (uint32_t i = threadIdx.x; i < Pp; i += kPartBlock) cnt[i] = 0;
+    __syncthreads();
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (uint32_t k = 0; k < IPT; ++k) {
@@ -170,10 +176,9 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     __syncthreads();
     lds_excl_scan(cnt, Pp, ctot);
     __syncthreads();
-    const uint32_t* __restrict__ hs = hist_scan + sg.hist_base;
-    const uint32_t seg0 = hs[0];
     for (uint32_t p = threadIdx.x; p < P; p += kPartBlock) {
-        const uint32_t rel = hs[(uint64_t)p * t.nt + t.tl] - seg0;  // exact: < segment length
+        const uint32_t g = p < kPartBlock ? hs_own : hs[(uint64_t)p * t.nt + t.tl];
+        const uint32_t rel = g - seg0;  // exact: < segment length
         delta[p] = rel - cnt[p];
     }
 #pragma unroll
