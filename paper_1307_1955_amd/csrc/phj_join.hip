@@ -161,9 +161,10 @@ constexpr uint32_t kSU = kSubJ / kWave;  // S tuples per lane of a probe round
 
 static_assert(kRptLarge * kJoinBlock == kMaxLdsCap, "largest build covers kMaxLdsCap");
 
-// Buckets of the LDS table for n tuples: largest power of two <= max(64, n).
-__device__ __forceinline__ uint32_t floor_log2_min6(uint32_t n) {
-    const uint32_t v = n < 64 ? 64u : n;
+// Heads of the LDS table for n tuples: the largest power of two <= max(64, n/2)
+// (chains of two tuples on average).
+__device__ __forceinline__ uint32_t table_log2H(uint32_t n) {
+    const uint32_t v = n < 128 ? 64u : n / 2;
     return 31u - (uint32_t)__clz(v);
 }
 
@@ -179,46 +180,57 @@ __device__ __forceinline__ void load_r(const int32_t* __restrict__ rk, const int
     }
 }
 
-// Builds the bucketed LDS table over the n <= RPT * kJoinBlock tuples held in
-// registers (k, r).  Afterwards bucket b holds skey/srid[bcnt[b] .. bcnt[b+1]);
-// H = 2^log2H buckets, bcnt has H + 1 entries.  The rank of a tuple inside its
-// bucket comes from the counting atomic and stays in a register until
-// placement.  Rounds past n are skipped as a whole (n is uniform over the
-// block); inside a round, lanes past n count into a private spare word so the
-// round's atomics are issued without branches.
+// LDS table of a work item: R_i's keys (and rids) at their row index j, and a
+// chain per bucket through next[] (the paper's bucket header + key/rid lists of
+// Section 3.1, with 16-bit row indices in place of pointers).  Layout:
+//   heads[cap/2 + 64] | spare[64] | skey[cap] | srid[cap] (write) | next[cap] (uint16)
+constexpr uint32_t kChainEnd = 0xFFFFu;  // end of a chain (cap <= kMaxLdsCap < 0xFFFF)
+struct LdsView {
+    uint32_t* heads;
+    uint32_t* spare;
+    int32_t* skey;
+    int32_t* srid;
+    uint16_t* next;
+};
+
+__device__ __forceinline__ LdsView lds_view(uint32_t* lds, uint32_t cap, bool rids) {
+    LdsView v;
+    v.heads = lds;
+    v.spare = lds + cap / 2 + kWave;
+    v.skey = (int32_t*)(v.spare + kWave);
+    v.srid = v.skey + cap;
+    v.next = (uint16_t*)(v.skey + (rids ? 2 : 1) * cap);
+    return v;
+}
+
+// Builds the table over the n <= RPT * kJoinBlock tuples held in registers
+// (k, r): b1-b2 bucket of the key, b3-b4 the tuple is stored at its row and
+// pushed on its bucket's chain with one LDS exchange (the latch of Section 3.3
+// is the exchange itself).  Rounds past n are skipped as a whole (n is uniform
+// over the block); inside a round, lanes past n exchange on a private spare
+// word so the round's exchanges are issued without branches.
 template <bool kRids, uint32_t RPT>
 __device__ __forceinline__ void build_lds(const int32_t* k, const int32_t* r, uint32_t n, uint32_t log2H,
-                                          uint32_t* bcnt, uint32_t* spare, int32_t* skey, int32_t* srid,
-                                          uint32_t* ctot) {
-    constexpr uint32_t kMaxE = RPT >= 16 ? 16 : (RPT >= 8 ? 8 : 4);  // H <= RPT * kJoinBlock buckets
+                                          const LdsView& v) {
     const uint32_t H = 1u << log2H;
     const uint32_t sh = 32 - log2H;
-    for (uint32_t x = threadIdx.x; x <= H; x += kJoinBlock) bcnt[x] = 0;
-    __syncthreads();
-    uint32_t br[RPT];
+    for (uint32_t x = threadIdx.x; x < H; x += kJoinBlock) v.heads[x] = kChainEnd;
 #pragma unroll
     for (uint32_t u = 0; u < RPT; ++u) {
-        br[u] = 0;
-        if (u * kJoinBlock < n) {
-            const uint32_t j = u * kJoinBlock + threadIdx.x;
-            const uint32_t b = slot_hash(k[u]) >> sh;
-            const uint32_t old = atomicAdd(j < n ? &bcnt[b] : &spare[lane_id()], 1u);
-            br[u] = (b << 16) | old;  // b < 2^13, rank < 2^13
+        const uint32_t j = u * kJoinBlock + threadIdx.x;
+        if (u * kJoinBlock < n && j < n) {
+            v.skey[j] = k[u];
+            if (kRids) v.srid[j] = r[u];
         }
     }
     __syncthreads();
-    lds_excl_scan_runs<kMaxE>(bcnt, H, ctot);
-    if (threadIdx.x == 0) bcnt[H] = n;
-    __syncthreads();
 #pragma unroll
     for (uint32_t u = 0; u < RPT; ++u) {
         if (u * kJoinBlock < n) {
             const uint32_t j = u * kJoinBlock + threadIdx.x;
-            const uint32_t pos = bcnt[br[u] >> 16] + (br[u] & 0xFFFFu);
-            if (j < n && pos < n) {  // pos < n always holds for a correct scan
-                skey[pos] = k[u];
-                if (kRids) srid[pos] = r[u];
-            }
+            const uint32_t b = slot_hash(k[u]) >> sh;
+            const uint32_t old = atomicExch(j < n ? &v.heads[b] : &v.spare[lane_id()], j);
+            if (j < n) v.next[j] = (uint16_t)old;
         }
     }
     __syncthreads();
@@ -247,26 +259,6 @@ __device__ __forceinline__ ItemLoc locate_item(const PartPair* __restrict__ pair
     return L;
 }
 
-// LDS layout of the join kernels:
-//   bcnt[cap + 64] | spare[64] | skey[cap] | srid[cap] (write) | ctot[kScanScratch]
-struct LdsView {
-    uint32_t* bcnt;
-    uint32_t* spare;
-    int32_t* skey;
-    int32_t* srid;
-    uint32_t* ctot;
-};
-
-__device__ __forceinline__ LdsView lds_view(uint32_t* lds, uint32_t cap, bool rids) {
-    LdsView v;
-    v.bcnt = lds;
-    v.spare = lds + cap + kWave;
-    v.skey = (int32_t*)(v.spare + kWave);
-    v.srid = v.skey + cap;
-    v.ctot = (uint32_t*)(v.skey + (rids ? 2 : 1) * cap);
-    return v;
-}
-
 // S keys (and rids) of this lane for the wave's range [wb, we) of the item.
 template <bool kRids>
 __device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const int32_t* __restrict__ srp,
@@ -280,47 +272,44 @@ __device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const in
 }
 
 // p1-p4 for the lane's kSU S keys against the LDS table, without branches per
-// key: the bucket bounds of all keys are read first, then the keys' runs are
-// walked in lockstep (step i reads entry lo + i of every key's run, clamped to
-// a valid address), so each step keeps kSU LDS reads in flight and a wave runs
-// only as many steps as its longest run.  Per key, packed in 16-bit halves
-// (n <= kMaxLdsCap < 2^16): cf[u] = matches | first << 16, first = position of
-// its first match (meaningful when it has one).
-__device__ __forceinline__ void probe_lds(const uint32_t* bcnt, const int32_t* skey, uint32_t log2H, uint32_t n,
-                                          const int32_t* q, uint32_t wb, uint32_t we, uint32_t* cf) {
-    uint32_t run[kSU];
+// key: the chain heads of all keys are read first, then the chains are walked
+// in lockstep (each step reads the current entry's key and link for every key
+// whose chain has not ended, at a clamped address), so each step keeps 2 kSU
+// LDS reads in flight and a wave runs only as many steps as its longest chain.
+// cf[u] = matches | first << 16 (16-bit halves: cap < 2^16), first = row of
+// the first match met (meaningful when there is one).
+__device__ __forceinline__ void probe_lds(const LdsView& v, uint32_t log2H, const int32_t* q, uint32_t wb,
+                                          uint32_t we, uint32_t* cf) {
     const uint32_t sh = 32 - log2H;
-    uint32_t len = 0;
-#pragma unroll
-    for (uint32_t u = 0; u < kSU; ++u) {
-        const uint32_t b = slot_hash(q[u]) >> sh;
-        const uint32_t lo = bcnt[b];
-        const uint32_t hi = bcnt[b + 1];
-        run[u] = lo | (hi << 16);
-    }
+    uint32_t h[kSU];
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
         const bool ok = wb + u * kWave + lane_id() < we;
-        const uint32_t hi = ok ? min(run[u] >> 16, n) : 0u;
-        const uint32_t lo = min(run[u] & 0xFFFFu, hi);
-        run[u] = lo | (hi << 16);
-        len = max(len, hi - lo);
+        const uint32_t head = v.heads[slot_hash(q[u]) >> sh];
+        h[u] = ok ? head : kChainEnd;
         cf[u] = 0;
     }
-    for (uint32_t i = 0; i < len; ++i) {
-        int32_t v[kSU];
+    while (true) {
+        bool live = false;
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) live |= h[u] != kChainEnd;
+        if (__ballot(live) == 0) break;
+        int32_t kk[kSU];
+        uint32_t nx[kSU];
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) {
-            const uint32_t x = (run[u] & 0xFFFFu) + i;
-            v[u] = skey[x < (run[u] >> 16) ? x : 0u];
+            const uint32_t x = h[u] != kChainEnd ? h[u] : 0u;
+            kk[u] = v.skey[x];
+            nx[u] = v.next[x];
         }
-        __builtin_amdgcn_sched_barrier(0);  // keep the kSU reads of a step together, in flight at once
+        __builtin_amdgcn_sched_barrier(0);  // keep the step's reads together, in flight at once
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) {
-            const uint32_t x = (run[u] & 0xFFFFu) + i;
-            const bool hit = x < (run[u] >> 16) && v[u] == q[u];
-            const uint32_t first = (cf[u] & 0xFFFFu) == 0 ? x << 16 : cf[u] & 0xFFFF0000u;
+            const bool on = h[u] != kChainEnd;
+            const bool hit = on && kk[u] == q[u];
+            const uint32_t first = (cf[u] & 0xFFFFu) == 0 ? h[u] << 16 : cf[u] & 0xFFFF0000u;
             cf[u] = hit ? first | ((cf[u] & 0xFFFFu) + 1u) : cf[u];
+            h[u] = on ? nx[u] : kChainEnd;
         }
     }
 }
@@ -341,28 +330,20 @@ __device__ __forceinline__ void probe_hbm(const uint64_t* __restrict__ region, c
     }
 }
 
-// End of the bucket run of `key` in the LDS table (clamped to n).
-__device__ __forceinline__ uint32_t bucket_end(const uint32_t* bcnt, int32_t key, uint32_t log2H, uint32_t n) {
-    return min(bcnt[(slot_hash(key) >> (32 - log2H)) + 1], n);
-}
-
-// Writes the c >= 1 matches of `key` found from position `first` of its bucket
-// run to o_r/o_s[p ...], slots below `room` only (o_r, o_s and room are the
-// wave's output window: uniform base pointers and the capacity left there).
-// The common single match is one store; the run's end is looked up only for
-// several matches.
+// Writes the c >= 1 matches of `key`, the first at row `first`, to
+// o_r/o_s[p ...], slots below `room` only (o_r, o_s and room are the wave's
+// output window: uniform base pointers and the capacity left there).  The
+// common single match is one store; further matches follow the chain.
 __device__ __forceinline__ void write_lds_matches(const LdsView& v, int32_t key, int32_t rs, uint32_t first,
-                                                  uint32_t c, uint32_t log2H, uint32_t n, uint32_t p,
-                                                  uint32_t room, int32_t* __restrict__ o_r,
-                                                  int32_t* __restrict__ o_s) {
+                                                  uint32_t c, uint32_t p, uint32_t room,
+                                                  int32_t* __restrict__ o_r, int32_t* __restrict__ o_s) {
     if (p < room) {
         o_r[p] = v.srid[first];
         o_s[p] = rs;
     }
     if (c == 1) return;
     ++p;
-    const uint32_t hi = bucket_end(v.bcnt, key, log2H, n);
-    for (uint32_t x = first + 1; x < hi; ++x) {
+    for (uint32_t x = v.next[first]; x != kChainEnd; x = v.next[x]) {
         if (v.skey[x] == key) {
             if (p < room) {
                 o_r[p] = v.srid[x];
@@ -417,7 +398,7 @@ __device__ __forceinline__ uint32_t lane_pairs_lds(const uint32_t* cf) {
 // by match counts); returns the slot after the wave's last pair.  LDS table.
 // A round of a wave has fewer than 2^32 pairs (kSubJ keys x kMaxLdsCap
 // matches), so slots are 32-bit offsets from the wave's uniform base.
-__device__ __forceinline__ uint64_t write_round_lds(const LdsView& v, uint32_t log2H, uint32_t n, const int32_t* q,
+__device__ __forceinline__ uint64_t write_round_lds(const LdsView& v, const int32_t* q,
                                                     const int32_t* qr, const uint32_t* cf, uint64_t pos0,
                                                     uint64_t capacity, int32_t* __restrict__ out_r,
                                                     int32_t* __restrict__ out_s) {
@@ -432,7 +413,7 @@ __device__ __forceinline__ uint64_t write_round_lds(const LdsView& v, uint32_t l
         const uint32_t c = cf[u] & 0xFFFFu;
         uint32_t excl, wtotal;
         wave_offsets32(c, &excl, &wtotal);
-        if (c) write_lds_matches(v, q[u], qr[u], cf[u] >> 16, c, log2H, n, done + excl, room, o_r, o_s);
+        if (c) write_lds_matches(v, q[u], qr[u], cf[u] >> 16, c, done + excl, room, o_r, o_s);
         done += wtotal;
     }
     return pos0 + done;
@@ -493,13 +474,13 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
         load_r<false, RPT>(rk + L.pp.r_off, nullptr, L.pp.r_len, k, nullptr);
         load_s<false>(skp, nullptr, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, nullptr);
         const LdsView v = lds_view(lds, lds_cap, false);
-        const uint32_t log2H = floor_log2_min6(L.pp.r_len);
-        build_lds<false, RPT>(k, nullptr, L.pp.r_len, log2H, v.bcnt, v.spare, v.skey, nullptr, v.ctot);
+        const uint32_t log2H = table_log2H(L.pp.r_len);
+        build_lds<false, RPT>(k, nullptr, L.pp.r_len, log2H, v);
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             if (sb) load_s<false>(skp, nullptr, wb, we, q, nullptr);
             uint32_t cf[kSU];
-            probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, cf);
+            probe_lds(v, log2H, q, wb, we, cf);
             cnt += lane_pairs_lds(cf);
         }
     } else {
@@ -543,15 +524,15 @@ k_join_write(
         load_r<true, RPT>(rk + L.pp.r_off, rrp, L.pp.r_len, k, r);
         load_s<true>(skp, srp, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, qr);
         const LdsView v = lds_view(lds, lds_cap, true);
-        const uint32_t log2H = floor_log2_min6(L.pp.r_len);
-        build_lds<true, RPT>(k, r, L.pp.r_len, log2H, v.bcnt, v.spare, v.skey, v.srid, v.ctot);
+        const uint32_t log2H = table_log2H(L.pp.r_len);
+        build_lds<true, RPT>(k, r, L.pp.r_len, log2H, v);
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             if (sb) load_s<true>(skp, srp, wb, we, q, qr);
             uint32_t cf[kSU];
-            probe_lds(v.bcnt, v.skey, log2H, L.pp.r_len, q, wb, we, cf);
+            probe_lds(v, log2H, q, wb, we, cf);
             const uint64_t pos0 = kOnePass ? block_reserve(lane_pairs_lds(cf), total, wtot, sb != 0) : base;
-            base = write_round_lds(v, log2H, L.pp.r_len, q, qr, cf, pos0, capacity, out_r, out_s);
+            base = write_round_lds(v, q, qr, cf, pos0, capacity, out_r, out_s);
         }
     } else {
         const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
@@ -594,15 +575,15 @@ k_direct_join(const DirectJob* __restrict__ jobs,
     int32_t q[kSU], qr[kSU];
     load_s<true>(skp, srp, w * kSubJ, min(w * kSubJ + kSubJ, s_n), q, qr);
     const LdsView v = lds_view(lds, lds_cap, true);
-    const uint32_t log2H = floor_log2_min6(r_len);
-    build_lds<true, RPT>(k, r, r_len, log2H, v.bcnt, v.spare, v.skey, v.srid, v.ctot);
+    const uint32_t log2H = table_log2H(r_len);
+    build_lds<true, RPT>(k, r, r_len, log2H, v);
     for (uint32_t sb = 0; sb < s_n; sb += kJoinSub) {
         const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, s_n);
         if (sb) load_s<true>(skp, srp, wb, we, q, qr);
         uint32_t cf[kSU];
-        probe_lds(v.bcnt, v.skey, log2H, r_len, q, wb, we, cf);
+        probe_lds(v, log2H, q, wb, we, cf);
         const uint64_t pos0 = block_reserve(lane_pairs_lds(cf), (unsigned long long*)J.count, wtot, sb != 0);
-        write_round_lds(v, log2H, r_len, q, qr, cf, pos0, J.capacity, J.out_r, J.out_s);
+        write_round_lds(v, q, qr, cf, pos0, J.capacity, J.out_r, J.out_s);
     }
 }
 
@@ -627,7 +608,8 @@ __global__ void k_write_zero(uint64_t* p) {
 }  // namespace
 
 size_t join_lds_bytes(uint32_t lds_cap, bool write) {
-    return sizeof(uint32_t) * ((size_t)lds_cap + 2 * kWave + (size_t)lds_cap * (write ? 2 : 1) + kScanScratch);
+    const size_t words = (size_t)lds_cap / 2 + 2 * kWave + (size_t)lds_cap * (write ? 2 : 1);
+    return sizeof(uint32_t) * words + ((sizeof(uint16_t) * lds_cap + 3) & ~(size_t)3);
 }
 
 void direct_setup_one(DirectJob* job, uint32_t* item_job, const DirectJob& j, uint32_t nitems, Recorder& rec) {
