@@ -161,68 +161,58 @@ constexpr uint32_t kSU = kSubJ / kWave;  // S tuples per lane of a probe round
 
 static_assert(kRptLarge * kJoinBlock == kMaxLdsCap, "largest build covers kMaxLdsCap");
 
-// Heads of the LDS table for n tuples: the largest power of two <= max(64, n/2)
-// (chains of two tuples on average).
+// Heads of the LDS table for n tuples: the largest power of two <= max(64, n)
+// (chains of one tuple on average).
 __device__ __forceinline__ uint32_t table_log2H(uint32_t n) {
-    const uint32_t v = n < 128 ? 64u : n / 2;
+    const uint32_t v = n < 64 ? 64u : n;
     return 31u - (uint32_t)__clz(v);
 }
 
-// R_i's keys (and rids) of this thread, n <= RPT * kJoinBlock.
-template <bool kRids, uint32_t RPT>
-__device__ __forceinline__ void load_r(const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
-                                       uint32_t n, int32_t* k, int32_t* r) {
+// R_i's keys of this thread, n <= RPT * kJoinBlock.
+template <uint32_t RPT>
+__device__ __forceinline__ void load_r(const int32_t* __restrict__ rk, uint32_t n, int32_t* k) {
 #pragma unroll
     for (uint32_t u = 0; u < RPT; ++u) {
         const uint32_t j = u * kJoinBlock + threadIdx.x;
         k[u] = j < n ? rk[j] : 0;
-        if (kRids) r[u] = j < n ? rr[j] : 0;
     }
 }
 
-// LDS table of a work item: R_i's keys (and rids) at their row index j, and a
-// chain per bucket through next[] (the paper's bucket header + key/rid lists of
-// Section 3.1, with 16-bit row indices in place of pointers).  Layout:
-//   heads[cap/2 + 64] | spare[64] | skey[cap] | srid[cap] (write) | next[cap] (uint16)
-constexpr uint32_t kChainEnd = 0xFFFFu;  // end of a chain (cap <= kMaxLdsCap < 0xFFFF)
+// LDS table of a work item: one 64-bit record per R_i tuple at its row j --
+// the key and the link to the next row of its bucket's chain -- and the chain
+// heads (the paper's bucket header + key list of Section 3.1, with row
+// indices in place of pointers).  The rid list stays in HBM: a match's rid is
+// read from R_i's rid column at its row when the pair is written.  Layout:
+//   heads[cap + 64] | spare[64] | rec[cap] (uint64: key | next << 32)
+constexpr uint32_t kChainEnd = 0xFFFFFFFFu;
 struct LdsView {
     uint32_t* heads;
     uint32_t* spare;
-    int32_t* skey;
-    int32_t* srid;
-    uint16_t* next;
+    uint64_t* rec;
 };
 
-__device__ __forceinline__ LdsView lds_view(uint32_t* lds, uint32_t cap, bool rids) {
+__device__ __forceinline__ LdsView lds_view(uint32_t* lds, uint32_t cap) {
     LdsView v;
     v.heads = lds;
-    v.spare = lds + cap / 2 + kWave;
-    v.skey = (int32_t*)(v.spare + kWave);
-    v.srid = v.skey + cap;
-    v.next = (uint16_t*)(v.skey + (rids ? 2 : 1) * cap);
+    v.spare = lds + cap + kWave;
+    v.rec = (uint64_t*)(v.spare + kWave);  // 8-byte aligned: cap is a multiple of 64
     return v;
 }
 
-// Builds the table over the n <= RPT * kJoinBlock tuples held in registers
-// (k, r): b1-b2 bucket of the key, b3-b4 the tuple is stored at its row and
-// pushed on its bucket's chain with one LDS exchange (the latch of Section 3.3
-// is the exchange itself).  Rounds past n are skipped as a whole (n is uniform
-// over the block); inside a round, lanes past n exchange on a private spare
-// word so the round's exchanges are issued without branches.
-template <bool kRids, uint32_t RPT>
-__device__ __forceinline__ void build_lds(const int32_t* k, const int32_t* r, uint32_t n, uint32_t log2H,
-                                          const LdsView& v) {
+__device__ __forceinline__ int32_t rec_key(uint64_t r) { return (int32_t)(uint32_t)r; }
+__device__ __forceinline__ uint32_t rec_next(uint64_t r) { return (uint32_t)(r >> 32); }
+
+// Builds the table over the n <= RPT * kJoinBlock keys held in registers: b1-b2
+// bucket of the key, b3-b4 the tuple is pushed on its bucket's chain with one
+// LDS exchange (the latch of Section 3.3 is the exchange itself) and its record
+// stored at its row.  Rounds past n are skipped as a whole (n is uniform over
+// the block); inside a round, lanes past n exchange on a private spare word so
+// the round's exchanges are issued without branches.
+template <uint32_t RPT>
+__device__ __forceinline__ void build_lds(const int32_t* k, uint32_t n, uint32_t log2H, const LdsView& v) {
     const uint32_t H = 1u << log2H;
     const uint32_t sh = 32 - log2H;
     for (uint32_t x = threadIdx.x; x < H; x += kJoinBlock) v.heads[x] = kChainEnd;
-#pragma unroll
-    for (uint32_t u = 0; u < RPT; ++u) {
-        const uint32_t j = u * kJoinBlock + threadIdx.x;
-        if (u * kJoinBlock < n && j < n) {
-            v.skey[j] = k[u];
-            if (kRids) v.srid[j] = r[u];
-        }
-    }
     __syncthreads();
 #pragma unroll
     for (uint32_t u = 0; u < RPT; ++u) {
@@ -230,7 +220,7 @@ __device__ __forceinline__ void build_lds(const int32_t* k, const int32_t* r, ui
             const uint32_t j = u * kJoinBlock + threadIdx.x;
             const uint32_t b = slot_hash(k[u]) >> sh;
             const uint32_t old = atomicExch(j < n ? &v.heads[b] : &v.spare[lane_id()], j);
-            if (j < n) v.next[j] = (uint16_t)old;
+            if (j < n) v.rec[j] = (uint64_t)(uint32_t)k[u] | ((uint64_t)old << 32);
         }
     }
     __syncthreads();
@@ -273,8 +263,8 @@ __device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const in
 
 // p1-p4 for the lane's kSU S keys against the LDS table, without branches per
 // key: the chain heads of all keys are read first, then the chains are walked
-// in lockstep (each step reads the current entry's key and link for every key
-// whose chain has not ended, at a clamped address), so each step keeps 2 kSU
+// in lockstep (each step reads the current record -- key and link -- for every
+// key whose chain has not ended, at a clamped address), so each step keeps kSU
 // LDS reads in flight and a wave runs only as many steps as its longest chain.
 // cf[u] = matches | first << 16 (16-bit halves: cap < 2^16), first = row of
 // the first match met (meaningful when there is one).
@@ -294,22 +284,17 @@ __device__ __forceinline__ void probe_lds(const LdsView& v, uint32_t log2H, cons
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) live |= h[u] != kChainEnd;
         if (__ballot(live) == 0) break;
-        int32_t kk[kSU];
-        uint32_t nx[kSU];
+        uint64_t rc[kSU];
 #pragma unroll
-        for (uint32_t u = 0; u < kSU; ++u) {
-            const uint32_t x = h[u] != kChainEnd ? h[u] : 0u;
-            kk[u] = v.skey[x];
-            nx[u] = v.next[x];
-        }
+        for (uint32_t u = 0; u < kSU; ++u) rc[u] = v.rec[h[u] != kChainEnd ? h[u] : 0u];
         __builtin_amdgcn_sched_barrier(0);  // keep the step's reads together, in flight at once
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) {
             const bool on = h[u] != kChainEnd;
-            const bool hit = on && kk[u] == q[u];
+            const bool hit = on && rec_key(rc[u]) == q[u];
             const uint32_t first = (cf[u] & 0xFFFFu) == 0 ? h[u] << 16 : cf[u] & 0xFFFF0000u;
             cf[u] = hit ? first | ((cf[u] & 0xFFFFu) + 1u) : cf[u];
-            h[u] = on ? nx[u] : kChainEnd;
+            h[u] = on ? rec_next(rc[u]) : kChainEnd;
         }
     }
 }
@@ -330,23 +315,25 @@ __device__ __forceinline__ void probe_hbm(const uint64_t* __restrict__ region, c
     }
 }
 
-// Writes the c >= 1 matches of `key`, the first at row `first`, to
-// o_r/o_s[p ...], slots below `room` only (o_r, o_s and room are the wave's
-// output window: uniform base pointers and the capacity left there).  The
-// common single match is one store; further matches follow the chain.
-__device__ __forceinline__ void write_lds_matches(const LdsView& v, int32_t key, int32_t rs, uint32_t first,
-                                                  uint32_t c, uint32_t p, uint32_t room,
-                                                  int32_t* __restrict__ o_r, int32_t* __restrict__ o_s) {
+// Writes the c >= 1 matches of `key` to o_r/o_s[p ...], slots below `room`
+// only (o_r, o_s and room are the wave's output window: uniform base pointers
+// and the capacity left there).  The first match is at row `first` and its
+// rid, rid0, was fetched already; further matches follow the chain and read
+// their rids from R_i's rid column `rrp`.
+__device__ __forceinline__ void write_lds_matches(const LdsView& v, const int32_t* __restrict__ rrp, int32_t key,
+                                                  int32_t rs, uint32_t first, int32_t rid0, uint32_t c, uint32_t p,
+                                                  uint32_t room, int32_t* __restrict__ o_r,
+                                                  int32_t* __restrict__ o_s) {
     if (p < room) {
-        o_r[p] = v.srid[first];
+        o_r[p] = rid0;
         o_s[p] = rs;
     }
     if (c == 1) return;
     ++p;
-    for (uint32_t x = v.next[first]; x != kChainEnd; x = v.next[x]) {
-        if (v.skey[x] == key) {
+    for (uint32_t x = rec_next(v.rec[first]); x != kChainEnd; x = rec_next(v.rec[x])) {
+        if (rec_key(v.rec[x]) == key) {
             if (p < room) {
-                o_r[p] = v.srid[x];
+                o_r[p] = rrp[x];
                 o_s[p] = rs;
             }
             ++p;
@@ -398,10 +385,10 @@ __device__ __forceinline__ uint32_t lane_pairs_lds(const uint32_t* cf) {
 // by match counts); returns the slot after the wave's last pair.  LDS table.
 // A round of a wave has fewer than 2^32 pairs (kSubJ keys x kMaxLdsCap
 // matches), so slots are 32-bit offsets from the wave's uniform base.
-__device__ __forceinline__ uint64_t write_round_lds(const LdsView& v, const int32_t* q,
-                                                    const int32_t* qr, const uint32_t* cf, uint64_t pos0,
-                                                    uint64_t capacity, int32_t* __restrict__ out_r,
-                                                    int32_t* __restrict__ out_s) {
+__device__ __forceinline__ uint64_t write_round_lds(const LdsView& v, const int32_t* __restrict__ rrp,
+                                                    const int32_t* q, const int32_t* qr, const uint32_t* cf,
+                                                    const int32_t* rid0, uint64_t pos0, uint64_t capacity,
+                                                    int32_t* __restrict__ out_r, int32_t* __restrict__ out_s) {
     pos0 = uniform64(pos0);
     const uint64_t left = capacity > pos0 ? capacity - pos0 : 0ull;
     const uint32_t room = left > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)left;
@@ -413,10 +400,17 @@ __device__ __forceinline__ uint64_t write_round_lds(const LdsView& v, const int3
         const uint32_t c = cf[u] & 0xFFFFu;
         uint32_t excl, wtotal;
         wave_offsets32(c, &excl, &wtotal);
-        if (c) write_lds_matches(v, q[u], qr[u], cf[u] >> 16, c, done + excl, room, o_r, o_s);
+        if (c) write_lds_matches(v, rrp, q[u], qr[u], cf[u] >> 16, rid0[u], c, done + excl, room, o_r, o_s);
         done += wtotal;
     }
     return pos0 + done;
+}
+
+// Rids of the first matches (issued right after the probe, so the loads are in
+// flight during the output reservation).
+__device__ __forceinline__ void fetch_first_rids(const int32_t* __restrict__ rrp, const uint32_t* cf, int32_t* rid0) {
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) rid0[u] = (cf[u] & 0xFFFFu) ? rrp[cf[u] >> 16] : 0;
 }
 
 // The same for the partition-local HBM table: c[u] matches on the row chain
@@ -471,11 +465,11 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
     int32_t q[kSU];
     if (L.pp.r_len <= lds_cap) {
         int32_t k[RPT];
-        load_r<false, RPT>(rk + L.pp.r_off, nullptr, L.pp.r_len, k, nullptr);
+        load_r<RPT>(rk + L.pp.r_off, L.pp.r_len, k);
         load_s<false>(skp, nullptr, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, nullptr);
-        const LdsView v = lds_view(lds, lds_cap, false);
+        const LdsView v = lds_view(lds, lds_cap);
         const uint32_t log2H = table_log2H(L.pp.r_len);
-        build_lds<false, RPT>(k, nullptr, L.pp.r_len, log2H, v);
+        build_lds<RPT>(k, L.pp.r_len, log2H, v);
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             if (sb) load_s<false>(skp, nullptr, wb, we, q, nullptr);
@@ -520,19 +514,21 @@ k_join_write(
     uint64_t base = kOnePass ? 0ull : wave_base[(uint64_t)L.item * kJoinWaves + w];
     int32_t q[kSU], qr[kSU];
     if (L.pp.r_len <= lds_cap) {
-        int32_t k[RPT], r[RPT];
-        load_r<true, RPT>(rk + L.pp.r_off, rrp, L.pp.r_len, k, r);
+        int32_t k[RPT];
+        load_r<RPT>(rk + L.pp.r_off, L.pp.r_len, k);
         load_s<true>(skp, srp, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, qr);
-        const LdsView v = lds_view(lds, lds_cap, true);
+        const LdsView v = lds_view(lds, lds_cap);
         const uint32_t log2H = table_log2H(L.pp.r_len);
-        build_lds<true, RPT>(k, r, L.pp.r_len, log2H, v);
+        build_lds<RPT>(k, L.pp.r_len, log2H, v);
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             if (sb) load_s<true>(skp, srp, wb, we, q, qr);
             uint32_t cf[kSU];
+            int32_t rid0[kSU];
             probe_lds(v, log2H, q, wb, we, cf);
+            fetch_first_rids(rrp, cf, rid0);
             const uint64_t pos0 = kOnePass ? block_reserve(lane_pairs_lds(cf), total, wtot, sb != 0) : base;
-            base = write_round_lds(v, q, qr, cf, pos0, capacity, out_r, out_s);
+            base = write_round_lds(v, rrp, q, qr, cf, rid0, pos0, capacity, out_r, out_s);
         }
     } else {
         const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
@@ -570,20 +566,22 @@ k_direct_join(const DirectJob* __restrict__ jobs,
     const uint32_t r_len = min(J.n_r, lds_cap);  // the planner guarantees n_r <= lds_cap
     const int32_t* __restrict__ skp = J.sk + s_begin;
     const int32_t* __restrict__ srp = J.sr + s_begin;
-    int32_t k[RPT], r[RPT];
-    load_r<true, RPT>(J.rk, J.rr, r_len, k, r);
+    int32_t k[RPT];
+    load_r<RPT>(J.rk, r_len, k);
     int32_t q[kSU], qr[kSU];
     load_s<true>(skp, srp, w * kSubJ, min(w * kSubJ + kSubJ, s_n), q, qr);
-    const LdsView v = lds_view(lds, lds_cap, true);
+    const LdsView v = lds_view(lds, lds_cap);
     const uint32_t log2H = table_log2H(r_len);
-    build_lds<true, RPT>(k, r, r_len, log2H, v);
+    build_lds<RPT>(k, r_len, log2H, v);
     for (uint32_t sb = 0; sb < s_n; sb += kJoinSub) {
         const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, s_n);
         if (sb) load_s<true>(skp, srp, wb, we, q, qr);
         uint32_t cf[kSU];
+        int32_t rid0[kSU];
         probe_lds(v, log2H, q, wb, we, cf);
+        fetch_first_rids(J.rr, cf, rid0);
         const uint64_t pos0 = block_reserve(lane_pairs_lds(cf), (unsigned long long*)J.count, wtot, sb != 0);
-        write_round_lds(v, q, qr, cf, pos0, J.capacity, J.out_r, J.out_s);
+        write_round_lds(v, J.rr, q, qr, cf, rid0, pos0, J.capacity, J.out_r, J.out_s);
     }
 }
 
@@ -607,9 +605,8 @@ __global__ void k_write_zero(uint64_t* p) {
 
 }  // namespace
 
-size_t join_lds_bytes(uint32_t lds_cap, bool write) {
-    const size_t words = (size_t)lds_cap / 2 + 2 * kWave + (size_t)lds_cap * (write ? 2 : 1);
-    return sizeof(uint32_t) * words + ((sizeof(uint16_t) * lds_cap + 3) & ~(size_t)3);
+size_t join_lds_bytes(uint32_t lds_cap, bool /*write*/) {
+    return sizeof(uint32_t) * ((size_t)lds_cap + 2 * kWave) + sizeof(uint64_t) * lds_cap;
 }
 
 void direct_setup_one(DirectJob* job, uint32_t* item_job, const DirectJob& j, uint32_t nitems, Recorder& rec) {
