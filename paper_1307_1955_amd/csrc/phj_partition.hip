@@ -68,6 +68,51 @@ __device__ __forceinline__ uint64_t match_mask(uint32_t p, uint32_t bits, bool v
     return valid ? m : 0ull;
 }
 
+// Loads the elements [0, len) of a tile (len <= kPartBlock * IPT) that starts
+// at `p` (4-byte aligned) with 16-byte vector loads: lane-contiguous 16-byte
+// chunks of the enclosing aligned window; thread t, slot k holds chunk
+// t + k * kPartBlock, i.e. v[4k + e] = window element 4 (t + k kPartBlock) + e,
+// tile element that minus the misalignment s = (p mod 16) / 4.  Only chunks lying
+// wholly inside the tile are read as vectors; the elements of the (at most two)
+// partial chunks are read one by one, and the up to 3 tile elements past the
+// window (when s > 0) go to `x` of threads 0..2.  Nothing outside the tile is
+// read.  Returns the validity mask: bit i for v[i], bit 4 IPT for x.  Element
+// order inside a tile is free: counts and ranks do not depend on it.
+template <uint32_t IPT>
+__device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ p, uint32_t len, int32_t* v,
+                                                  int32_t& x) {
+    static_assert(IPT % 4 == 0 && IPT <= 32, "vector tile slots");
+    const uint32_t s = (uint32_t)(((uintptr_t)p >> 2) & 3u);
+    const int32_t* __restrict__ q = p - s;  // 16-byte aligned
+    uint64_t valid = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < IPT / 4; ++k) {
+        const uint32_t c = threadIdx.x + k * kPartBlock;
+        const int32_t i0 = (int32_t)(4 * c) - (int32_t)s;  // tile index of the chunk's first element
+        if (i0 >= 0 && i0 + 4 <= (int32_t)len) {
+            const int4 w = *reinterpret_cast<const int4*>(q + 4 * c);
+            v[4 * k] = w.x;
+            v[4 * k + 1] = w.y;
+            v[4 * k + 2] = w.z;
+            v[4 * k + 3] = w.w;
+            valid |= 0xFull << (4 * k);
+        } else {
+#pragma unroll
+            for (uint32_t e = 0; e < 4; ++e) {
+                const int32_t i = i0 + (int32_t)e;
+                const bool ok = i >= 0 && i < (int32_t)len;
+                v[4 * k + e] = ok ? q[4 * c + e] : 0;
+                valid |= (uint64_t)ok << (4 * k + e);
+            }
+        }
+    }
+    const uint32_t xi = kPartBlock * IPT - s + threadIdx.x;  // past the window
+    const bool xok = threadIdx.x < s && xi < len;
+    x = xok ? p[xi] : 0;
+    valid |= (uint64_t)xok << IPT;
+    return valid;
+}
+
 template <uint32_t IPT>
 __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restrict__ segs,
                                                          const uint32_t* __restrict__ tile_begin,
@@ -84,28 +129,24 @@ __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restr
     const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
     const PartSeg sg = segs[t.seg];
     const int32_t* __restrict__ kin = sg.key_in + t.start;
-    int32_t keys[IPT];
-#pragma unroll
-    for (uint32_t k = 0; k < IPT; ++k) {
-        const uint32_t idx = k * kPartBlock + threadIdx.x;
-        keys[k] = idx < t.len ? kin[idx] : 0;
-    }
+    int32_t keys[IPT], kx;
+    const uint64_t valid = load_tile_vec<IPT>(kin, t.len, keys, kx);
     // counters cleared while the tile's loads are in flight
     for (uint32_t i = threadIdx.x; i < P; i += kPartBlock) cnt[i] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (uint32_t k = 0; k < IPT; ++k) {
-        const uint32_t idx = k * kPartBlock + threadIdx.x;
-        const bool valid = idx < t.len;
+        const bool ok = (valid >> k) & 1u;
         const uint32_t p = part_of(keys[k], cfg);
         if (cfg.bits <= kBallotMaxBits) {
-            const uint64_t m = match_mask(p, cfg.bits, valid);
-            if (valid && (m & lt) == 0) atomicAdd(&cnt[p], (uint32_t)__popcll(m));
-        } else if (valid) {
+            const uint64_t m = match_mask(p, cfg.bits, ok);
+            if (ok && (m & lt) == 0) atomicAdd(&cnt[p], (uint32_t)__popcll(m));
+        } else if (ok) {
             atomicAdd(&cnt[p], 1u);
         }
     }
+    if ((valid >> IPT) & 1u) atomicAdd(&cnt[part_of(kx, cfg)], 1u);
     __syncthreads();
     uint32_t* __restrict__ h = hist + sg.hist_base + t.tl;
     for (uint32_t p = threadIdx.x; p < P; p += kPartBlock) h[(uint64_t)p * t.nt] = cnt[p];
@@ -136,14 +177,23 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     const PartSeg sg = segs[t.seg];
     const int32_t* __restrict__ kin = sg.key_in + t.start;
     const int32_t* __restrict__ rin = sg.rid_in + t.start;
-    int32_t keys[IPT], rids[IPT];
+    int32_t keys[IPT], rids[IPT], kx, rx;
     uint32_t rank[IPT];
+    uint64_t valid;
+    if ((((uintptr_t)kin ^ (uintptr_t)rin) & 15u) == 0) {  // same misalignment: one vector pattern for both
+        valid = load_tile_vec<IPT>(kin, t.len, keys, kx);
+        load_tile_vec<IPT>(rin, t.len, rids, rx);
+    } else {
+        valid = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < IPT; ++k) {
-        const uint32_t idx = k * kPartBlock + threadIdx.x;
-        const bool valid = idx < t.len;
-        keys[k] = valid ? kin[idx] : 0;
-        rids[k] = valid ? rin[idx] : 0;
+        for (uint32_t k = 0; k < IPT; ++k) {
+            const uint32_t idx = k * kPartBlock + threadIdx.x;
+            const bool ok = idx < t.len;
+            keys[k] = ok ? kin[idx] : 0;
+            rids[k] = ok ? rin[idx] : 0;
+            valid |= (uint64_t)ok << k;
+        }
+        kx = rx = 0;
     }
     // This tile's global partition offsets do not depend on the tile's data:
     // fetched together with it (first kPartBlock partitions; the rest later).
@@ -156,23 +206,24 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (uint32_t k = 0; k < IPT; ++k) {
-        const uint32_t idx = k * kPartBlock + threadIdx.x;
-        const bool valid = idx < t.len;
+        const bool ok = (valid >> k) & 1u;
         const uint32_t p = part_of(keys[k], cfg);
         if (cfg.bits <= kBallotMaxBits) {
-            const uint64_t m = match_mask(p, cfg.bits, valid);
+            const uint64_t m = match_mask(p, cfg.bits, ok);
             const uint32_t below = (uint32_t)__popcll(m & lt);
             uint32_t old = 0;
-            if (valid && below == 0) old = atomicAdd(&cnt[p], (uint32_t)__popcll(m));
+            if (ok && below == 0) old = atomicAdd(&cnt[p], (uint32_t)__popcll(m));
             const uint32_t leader = m ? (uint32_t)(__ffsll((long long)m) - 1) : 0u;
             old = __shfl(old, (int)leader, kWave);
             rank[k] = old + below;
         } else {
             // the returned old value is the tuple's rank; lanes hitting the same
             // counter in one instruction get distinct values
-            rank[k] = valid ? atomicAdd(&cnt[p], 1u) : 0u;
+            rank[k] = ok ? atomicAdd(&cnt[p], 1u) : 0u;
         }
     }
+    const bool xok = (valid >> IPT) & 1u;
+    const uint32_t xrank = xok ? atomicAdd(&cnt[part_of(kx, cfg)], 1u) : 0u;
     __syncthreads();
     lds_excl_scan(cnt, Pp, ctot);
     __syncthreads();
@@ -183,12 +234,19 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     }
 #pragma unroll
     for (uint32_t k = 0; k < IPT; ++k) {
-        const uint32_t idx = k * kPartBlock + threadIdx.x;
-        if (idx < t.len) {
-            const uint32_t p = part_of(keys[k], cfg);
-            const uint32_t pos = cnt[p] + rank[k];
-            skey[pos] = keys[k];
-            srid[pos] = rids[k];
+        if ((valid >> k) & 1u) {
+            const uint32_t pos = cnt[part_of(keys[k], cfg)] + rank[k];
+            if (pos < T) {  // always true for consistent counts
+                skey[pos] = keys[k];
+                srid[pos] = rids[k];
+            }
+        }
+    }
+    if (xok) {
+        const uint32_t pos = cnt[part_of(kx, cfg)] + xrank;
+        if (pos < T) {
+            skey[pos] = kx;
+            srid[pos] = rx;
         }
     }
     __syncthreads();

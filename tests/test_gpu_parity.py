@@ -121,6 +121,29 @@ def test_r_side_skew(kw, frac):
     check_small(hj.params(**kw), rk, r.rid, sk, s.rid)
 
 
+def offset_view(a, off):
+    """Device copy of `a` that starts `off` int32 elements into a larger buffer
+    (input columns at every 4-byte alignment inside a 16-byte line)."""
+    buf = torch.zeros(len(a) + 8, dtype=torch.int32, device=DEV)
+    buf[off: off + len(a)] = torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(DEV)
+    return buf[off: off + len(a)]
+
+
+@pytest.mark.parametrize("offs", [(1, 1, 3, 3), (1, 2, 0, 3), (3, 0, 2, 2)])
+@pytest.mark.parametrize("kw", [dict(algo="phj", passes=2, bits=(6, 6)), dict(algo="phj", passes=1, bits=(7,)),
+                                dict(algo="phj", passes=2, bits=(5, 4), one_pass=True, tile=1024),
+                                dict(algo="shj")])
+def test_misaligned_columns(kw, offs):
+    """Key and rid columns at different offsets inside 16-byte lines (vector and
+    element-wise tile loads), ragged sizes."""
+    rk, rr, sk, sr = dup_relations(12, 70001, 130003, 90000)
+    cols = [offset_view(a, o) for a, o in zip((rk, rr, sk, sr), offs)]
+    want_r, want_s = oracle.join(rk, rr, sk, sr)
+    o_r, o_s, cnt = hj.join(*cols, p=hj.params(**kw))
+    assert cnt == len(want_r)
+    assert np.array_equal(oracle.canonical(o_r.cpu().numpy(), o_s.cpu().numpy()), oracle.canonical(want_r, want_s))
+
+
 @pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="phj", passes=2, bits=(6, 6)),
                                 dict(algo="phj", passes=1, bits=(3,)),
                                 dict(algo="phj", passes=2, bits=(6, 6), one_pass=True),
