@@ -10,6 +10,7 @@
 // Everything is enqueued on one stream; no host synchronisation, no
 // host<->device copy and no allocation happen here.
 #include "engine.h"
+#include "hj_side.h"
 
 #include <algorithm>
 #include <cmath>
@@ -316,36 +317,39 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
              uint64_t* d_count, hj::Recorder& rec) {
     PhjWs w = phj_layout(pl, R.n, S.n, ws);
     const uint32_t n_r = (uint32_t)R.n, n_s = (uint32_t)S.n;
+    const bool two = pl.passes == 2;
     hj::part_setup_pass1(w.segs1, w.tb1, R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, w.st1, w.nzero,
                          rec);
+    // the join plan rides on the last pass's scatter, the pass-2 setup on the first
+    hj::SideJob plan{};
+    plan.kind = hj::kSidePlan;
+    plan.blocks = hj::plan_blocks(pl.P);
+    plan.plan = hj::PlanArgs{two ? w.segs2 : w.segs1, two ? w.tb2 : w.tb1, two ? w.hist2 : w.hist1,
+                             two ? 2 * pl.P1 : 2u, two ? pl.b2 : pl.b1, n_r, n_s, pl.B, pl.lds_cap,
+                             w.pairs, w.item_begin, w.ovf_begin, w.item_part, w.ovf_part,
+                             pl.one_pass ? d_count : nullptr, w.stp};
+    hj::SideJob setup2{};
+    if (two) {
+        setup2.kind = hj::kSideSetup2;
+        setup2.blocks = 1;
+        setup2.setup2 = hj::Setup2Args{w.hist1, w.tb1, pl.b1, n_r, n_s, pl.tile, pl.b2, 0u, w.keyA, w.ridA,
+                                       w.segs2, w.tb2, w.tseg2};
+    }
     hj::PassCfg c1{pl.b2, pl.b1, pl.hash, pl.tile};
     hj::part_hist(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, rec);
     hj::scan_u32(w.hist1, w.hist1, w.tiles1 * pl.P1, w.st1, nullptr, rec);
-    hj::part_scatter(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, w.keyA, w.ridA, rec);
-    const hj::PartSeg* segs = w.segs1;
-    const uint32_t* tb = w.tb1;
-    uint32_t nseg = 2, bits_last = pl.b1;
-    const uint32_t* hist_last = w.hist1;
+    hj::part_scatter(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, w.keyA, w.ridA,
+                     two ? setup2 : plan, rec);
     int32_t *fk = w.keyA, *fr = w.ridA;
-    if (pl.passes == 2) {
-        hj::part_setup_pass2(w.hist1, w.tb1, pl.b1, n_r, n_s, w.keyA, w.ridA, pl.tile, pl.b2, w.segs2,
-                             w.tb2, w.tseg2, rec);
+    if (two) {
         hj::PassCfg c2{0, pl.b2, pl.hash, pl.tile};
         hj::part_hist(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, rec);
         hj::scan_u32(w.hist2, w.hist2, w.tiles2_ub * pl.P2, w.st2, nullptr, rec);
         hj::part_scatter(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, w.keyB,
-                         w.ridB, rec);
-        segs = w.segs2;
-        tb = w.tb2;
-        nseg = 2 * pl.P1;
-        bits_last = pl.b2;
-        hist_last = w.hist2;
+                         w.ridB, plan, rec);
         fk = w.keyB;
         fr = w.ridB;
     }
-    hj::JoinPlanOut po{w.pairs, w.item_begin, w.ovf_begin, w.item_part, w.ovf_part};
-    hj::join_plan(segs, tb, nseg, bits_last, hist_last, n_r, n_s, pl.B, pl.lds_cap, po,
-                  pl.one_pass ? d_count : nullptr, w.stp, rec);
     hj::join_ovf_build(w.pairs, w.ovf_begin, w.ovf_part, pl.P, (uint32_t)w.ovf_ub, fk, w.ovf_table, w.ovf_next,
                        rec);
     if (!pl.one_pass) {

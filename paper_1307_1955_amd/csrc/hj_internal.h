@@ -77,15 +77,12 @@ void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, co
 // tile_seg: segment of every tile (nullptr: binary search over tile_begin).
 void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec);
+// `side`: extra workgroups appended to the grid that run the next step's setup
+// (hj_side.h: the pass-2 segment table or the join plan).
+struct SideJob;
 void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                   uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
-                  int32_t* rid_out, Recorder& rec);
-// Pass-2 setup: one segment per pass-1 partition of R and of S, reading from
-// (key_in, rid_in) = pass-1 output.
-void part_setup_pass2(const uint32_t* hist1_scan, const uint32_t* tile_begin1, uint32_t bits1,
-                      uint32_t n_r, uint32_t n_s, const int32_t* key_in, const int32_t* rid_in,
-                      uint32_t tile, uint32_t bits2, PartSeg* segs2, uint32_t* tile_begin2,
-                      uint32_t* tile_seg2, Recorder& rec);
+                  int32_t* rid_out, const SideJob& side, Recorder& rec);
 
 // ---- phj_join.hip ----
 constexpr uint32_t kJoinBlock = 512;
@@ -106,14 +103,10 @@ struct JoinPlanOut {
     uint32_t* item_part;   // [join_grid] partition of every work item
     uint32_t* ovf_part;    // [ovf_grid] partition of every HBM-table build chunk
 };
-// Final partition table from the last pass's histogram scan, work-item and
-// overflow-chunk scans and maps, in one launch.  `segs`/`tile_begin`/`nseg`
-// are the last pass's; `state` needs plan_state_words(2^total_bits) words that
-// are zero when it starts.
+// The join plan (final partition table, work-item and overflow-chunk scans and
+// maps) runs as a side job of the last scatter (hj_side.h); its state needs
+// plan_state_words(2^total_bits) words that are zero when it starts.
 size_t plan_state_words(uint32_t P);
-void join_plan(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t bits_last,
-               const uint32_t* hist_scan, uint32_t n_r, uint32_t n_s, uint32_t total_bits,
-               uint32_t lds_cap, const JoinPlanOut& o, uint64_t* zero_total, uint64_t* state, Recorder& rec);
 // Upper bounds of the HBM-table build items and of the join work items.
 uint32_t ovf_grid(uint32_t P, uint64_t n_r);
 uint32_t join_grid(uint32_t P, uint64_t n_s);

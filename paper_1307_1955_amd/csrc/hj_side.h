@@ -1,0 +1,237 @@
+// Work that rides along with another launch ("side jobs"): extra workgroups
+// at the end of a radix-scatter grid run the next pass's setup or the join
+// plan.  Both only read data that was complete before the hosting launch
+// started (the histogram scan of the pass being scattered) and write tables
+// that only later launches read, so they need no ordering with the scatter's
+// own workgroups and cost no launch of their own.
+#pragma once
+
+#include "hj_device.h"
+#include "hj_internal.h"
+
+namespace hj {
+
+constexpr uint32_t kOvfChunk = 4096;  // R tuples per HBM-table build item
+constexpr uint32_t kPlanBlock = 256;  // threads of a join-plan workgroup
+
+// Everything the pass-2 setup reads and writes.
+struct Setup2Args {
+    const uint32_t* hist1_scan;
+    const uint32_t* tile_begin1;
+    uint32_t bits1, n_r, n_s, tile, bits2, pad;
+    const int32_t* key_in;
+    const int32_t* rid_in;
+    PartSeg* segs2;
+    uint32_t* tile_begin2;
+    uint32_t* tile_seg2;
+};
+
+// Everything the join plan reads and writes (see join_plan_block).
+struct PlanArgs {
+    const PartSeg* segs;
+    const uint32_t* tile_begin;
+    const uint32_t* hist_scan;
+    uint32_t nseg, bits_last, n_r, n_s, total_bits, lds_cap;
+    PartPair* pairs;
+    uint32_t* item_begin;
+    uint32_t* ovf_begin;
+    uint32_t* item_part;
+    uint32_t* ovf_part;
+    uint64_t* zero_total;
+    uint64_t* state;
+};
+
+enum SideKind : uint32_t { kSideNone = 0, kSideSetup2 = 1, kSidePlan = 2 };
+
+struct SideJob {
+    uint32_t kind;
+    uint32_t blocks;  // extra workgroups at the end of the grid
+    Setup2Args setup2;
+    PlanArgs plan;
+};
+
+inline uint32_t plan_blocks(uint32_t P) { return (P + kPlanBlock - 1) / kPlanBlock; }
+
+// Start of final partition i of one relation (positions relative to the relation).
+__device__ __forceinline__ uint32_t final_start(const PartSeg* __restrict__ segs,
+                                                const uint32_t* __restrict__ tile_begin,
+                                                const uint32_t* __restrict__ hist_scan, uint32_t rel,
+                                                uint32_t nseg_rel, uint32_t bits_last, uint32_t i,
+                                                uint32_t n_rel, uint32_t base_rel, uint32_t P) {
+    if (i >= P) return n_rel;
+    const uint32_t seg = rel * nseg_rel + (i >> bits_last);
+    const uint32_t p = i & ((1u << bits_last) - 1u);
+    const uint32_t nt = tile_begin[seg + 1] - tile_begin[seg];
+    const uint32_t* hs = hist_scan + segs[seg].hist_base;
+    const uint32_t r = nt ? hs[(uint64_t)p * nt] - hs[0] : 0u;
+    return (uint32_t)(segs[seg].out_base - base_rel) + r;
+}
+
+__device__ __forceinline__ uint32_t items_of(const PartPair& pp) {
+    return (pp.r_len && pp.s_len) ? (pp.s_len + kJoinChunk - 1) / kJoinChunk : 0u;
+}
+
+__device__ __forceinline__ uint32_t ovf_chunks_of(const PartPair& pp, uint32_t lds_cap) {
+    return (pp.r_len > lds_cap && pp.s_len) ? (pp.r_len + kOvfChunk - 1) / kOvfChunk : 0u;
+}
+
+// Plan (one thread per partition pair, workgroups in ticket order): ranges of
+// R_i and S_i from the last pass's histogram scan, the pair's work items and
+// HBM-table build chunks, their exclusive scans over all pairs (one chained
+// scan of both counts packed in one word) and the item -> pair maps.
+// state[0]: ticket; state[1 + b]: status of workgroup b (cleared beforehand).
+// Run by plan_blocks(P) workgroups of kPlanBlock threads.
+__device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
+    const PartSeg* __restrict__ segs = A.segs;
+    const uint32_t* __restrict__ tile_begin = A.tile_begin;
+    const uint32_t nseg = A.nseg, bits_last = A.bits_last, n_r = A.n_r, n_s = A.n_s;
+    const uint32_t total_bits = A.total_bits, lds_cap = A.lds_cap;
+    const uint32_t* __restrict__ hist_scan = A.hist_scan;
+    PartPair* __restrict__ pairs = A.pairs;
+    uint32_t* __restrict__ item_begin = A.item_begin;
+    uint32_t* __restrict__ ovf_begin = A.ovf_begin;
+    uint32_t* __restrict__ item_part = A.item_part;
+    uint32_t* __restrict__ ovf_part = A.ovf_part;
+    uint64_t* __restrict__ zero_total = A.zero_total;
+    uint64_t* state = A.state;
+    __shared__ uint64_t wt[kPlanBlock / kWave];
+    __shared__ uint32_t s_blk;
+    __shared__ uint64_t s_prefix;
+    if (threadIdx.x == 0) s_blk = (uint32_t)atomicAdd((unsigned long long*)state, 1ull);
+    __syncthreads();
+    const uint32_t blk = s_blk;
+    const uint32_t P = 1u << total_bits;
+    const uint32_t nseg_rel = nseg / 2;
+    const uint32_t i = blk * kPlanBlock + threadIdx.x;
+    if (i == 0 && zero_total) *zero_total = 0;
+    PartPair pp{0, 0, 0, 0};
+    uint32_t ni = 0, no = 0;
+    if (i < P) {
+        const uint32_t r0 = min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i, n_r, 0, P), n_r);
+        const uint32_t s0 = min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i, n_s, n_r, P), n_s);
+        // clamped: a partition never extends past its relation or runs backwards
+        const uint32_t r1 = max(r0, min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i + 1, n_r, 0, P), n_r));
+        const uint32_t s1 = max(s0, min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i + 1, n_s, n_r, P), n_s));
+        pp.r_off = r0;
+        pp.r_len = r1 - r0;
+        pp.s_off = s0;
+        pp.s_len = s1 - s0;
+        ni = items_of(pp);
+        no = ovf_chunks_of(pp, lds_cap);
+    }
+    // items and chunks are each below 2^31: packed as items | chunks << 31
+    uint64_t tot;
+    const uint64_t excl = block_excl_scan((uint64_t)ni | ((uint64_t)no << 31), wt, &tot);
+    if (threadIdx.x < kWave) {
+        const uint64_t prefix = lookback_wave(state + 1, blk, tot);
+        if (threadIdx.x == 0) s_prefix = prefix;
+    }
+    __syncthreads();
+    const uint64_t run = s_prefix + excl;
+    const uint32_t ib = (uint32_t)(run & 0x7FFFFFFFu), ob = (uint32_t)(run >> 31);
+    if (i < P) {
+        pairs[i] = pp;
+        item_begin[i] = ib;
+        ovf_begin[i] = ob;
+        for (uint32_t x = 0; x < ni; ++x) item_part[ib + x] = i;
+        for (uint32_t x = 0; x < no; ++x) ovf_part[ob + x] = i;
+    }
+    if (i == P - 1) {  // the last pair also writes the totals
+        item_begin[P] = ib + ni;
+        ovf_begin[P] = ob + no;
+    }
+}
+
+
+
+// Start of partition q of a pass-1 segment relative to the segment.
+__device__ __forceinline__ uint32_t seg_part_start(const uint32_t* __restrict__ hs_seg, uint32_t nt,
+                                                   uint32_t q) {
+    return nt ? hs_seg[(uint64_t)q * nt] - hs_seg[0] : 0u;
+}
+
+// Pass-2 segment table (every pass-1 partition of R and of S), its tile
+// offsets and the tile -> segment map, from the pass-1 histogram scan.  Run by
+// one workgroup of any size; `lds` holds lds_words scratch words (the segment
+// tile offsets are kept there for the tile map when they fit).
+__device__ __forceinline__ void setup_pass2_block(const Setup2Args& A, uint32_t* lds, uint32_t lds_words) {
+    const uint32_t* __restrict__ hist1_scan = A.hist1_scan;
+    const uint32_t* __restrict__ tile_begin1 = A.tile_begin1;
+    const uint32_t bits1 = A.bits1, n_r = A.n_r, n_s = A.n_s, tile = A.tile, bits2 = A.bits2;
+    const int32_t* key_in = A.key_in;
+    const int32_t* rid_in = A.rid_in;
+    PartSeg* __restrict__ segs2 = A.segs2;
+    uint32_t* __restrict__ tile_begin2 = A.tile_begin2;
+    uint32_t* __restrict__ tile_seg2 = A.tile_seg2;
+    uint32_t* wt = lds;                   // [kScanScratch]
+    uint32_t* tb = lds + kScanScratch;    // [nseg + 1] when it fits
+    const uint32_t P1 = 1u << bits1;
+    const uint32_t nseg = 2 * P1;
+    const uint32_t per = (nseg + blockDim.x - 1) / blockDim.x;
+    const uint32_t a = threadIdx.x * per;
+    const uint32_t b = min(a + per, nseg);
+    const uint32_t nt_r = tile_begin1[1], nt_s = tile_begin1[2] - tile_begin1[1];
+    // pass 1 used hist_base = 0 for R and nt_r << bits1 for S
+    auto seg_range = [&](uint32_t s, uint32_t* off, uint32_t* len, uint32_t* base) {
+        const uint32_t rel = s >= P1;
+        const uint32_t q = s - rel * P1;
+        const uint32_t nt = rel ? nt_s : nt_r;
+        const uint32_t* hs = hist1_scan + (rel ? ((uint64_t)nt_r << bits1) : 0ull);
+        const uint32_t n = rel ? n_s : n_r;
+        // clamped so a segment always lies inside its relation
+        const uint32_t st = min(seg_part_start(hs, nt, q), n);
+        const uint32_t en = max(st, q + 1 < P1 ? min(seg_part_start(hs, nt, q + 1), n) : n);
+        *off = st;
+        *len = en - st;
+        *base = rel ? n_r : 0u;
+    };
+    uint32_t ntiles = 0;
+    for (uint32_t s = a; s < b; ++s) {
+        uint32_t off, len, base;
+        seg_range(s, &off, &len, &base);
+        ntiles += (len + tile - 1) / tile;
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(ntiles, wt, &total);
+    const bool in_lds = nseg + 1 + kScanScratch <= lds_words;
+    for (uint32_t s = a; s < b; ++s) {
+        uint32_t off, len, base;
+        seg_range(s, &off, &len, &base);
+        PartSeg g;
+        g.key_in = key_in + base + off;
+        g.rid_in = rid_in + base + off;
+        g.out_base = (uint64_t)base + off;
+        g.hist_base = (uint64_t)run << bits2;
+        g.n = len;
+        g.pad = 0;
+        segs2[s] = g;
+        tile_begin2[s] = run;
+        if (in_lds) tb[s] = run;
+        const uint32_t nt = (len + tile - 1) / tile;
+        if (!in_lds)
+            for (uint32_t x = 0; x < nt; ++x) tile_seg2[run + x] = s;
+        run += nt;
+    }
+    if (threadIdx.x == 0) {
+        tile_begin2[nseg] = total;
+        if (in_lds) tb[nseg] = total;
+    }
+    if (in_lds) {
+        // every thread maps its share of the tiles to segments (binary search in LDS)
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < total; t += blockDim.x) tile_seg2[t] = upper_index(tb, nseg, t);
+    }
+}
+
+
+// Runs the side job on workgroup `b` of its extra workgroups.  `lds`: the
+// hosting kernel's dynamic LDS (lds_words words).
+__device__ __forceinline__ void run_side_job(const SideJob& J, uint32_t b, uint32_t* lds, uint32_t lds_words) {
+    if (J.kind == kSideSetup2) {
+        if (b == 0) setup_pass2_block(J.setup2, lds, lds_words);
+    } else if (J.kind == kSidePlan) {
+        join_plan_block(J.plan);
+    }
+}
+
+}  // namespace hj

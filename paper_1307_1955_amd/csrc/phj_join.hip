@@ -18,97 +18,14 @@
 // dynamic output allocation replaced by counting).
 #include "hj_device.h"
 #include "hj_internal.h"
+#include "hj_side.h"
 
 namespace hj {
 
 namespace {
 
-constexpr uint32_t kOvfChunk = 4096;                  // R tuples per HBM-table build item
 constexpr uint32_t kOvfGrid = 1024;                   // workgroups of the HBM-table build launches
 constexpr uint32_t kSubJ = kJoinSub / kJoinWaves;     // S tuples per wave of a probe round
-constexpr uint32_t kPlanBlock = 256;
-
-// Start of final partition i of one relation (positions relative to the relation).
-__device__ __forceinline__ uint32_t final_start(const PartSeg* __restrict__ segs,
-                                                const uint32_t* __restrict__ tile_begin,
-                                                const uint32_t* __restrict__ hist_scan, uint32_t rel,
-                                                uint32_t nseg_rel, uint32_t bits_last, uint32_t i,
-                                                uint32_t n_rel, uint32_t base_rel, uint32_t P) {
-    if (i >= P) return n_rel;
-    const uint32_t seg = rel * nseg_rel + (i >> bits_last);
-    const uint32_t p = i & ((1u << bits_last) - 1u);
-    const uint32_t nt = tile_begin[seg + 1] - tile_begin[seg];
-    const uint32_t* hs = hist_scan + segs[seg].hist_base;
-    const uint32_t r = nt ? hs[(uint64_t)p * nt] - hs[0] : 0u;
-    return (uint32_t)(segs[seg].out_base - base_rel) + r;
-}
-
-__device__ __forceinline__ uint32_t items_of(const PartPair& pp) {
-    return (pp.r_len && pp.s_len) ? (pp.s_len + kJoinChunk - 1) / kJoinChunk : 0u;
-}
-
-__device__ __forceinline__ uint32_t ovf_chunks_of(const PartPair& pp, uint32_t lds_cap) {
-    return (pp.r_len > lds_cap && pp.s_len) ? (pp.r_len + kOvfChunk - 1) / kOvfChunk : 0u;
-}
-
-// Plan (one thread per partition pair, workgroups in ticket order): ranges of
-// R_i and S_i from the last pass's histogram scan, the pair's work items and
-// HBM-table build chunks, their exclusive scans over all pairs (one chained
-// scan of both counts packed in one word) and the item -> pair maps.
-// state[0]: ticket; state[1 + b]: status of workgroup b (cleared beforehand).
-__global__ void __launch_bounds__(kPlanBlock) k_join_plan(
-    const PartSeg* __restrict__ segs, const uint32_t* __restrict__ tile_begin, uint32_t nseg,
-    uint32_t bits_last, const uint32_t* __restrict__ hist_scan, uint32_t n_r, uint32_t n_s,
-    uint32_t total_bits, uint32_t lds_cap, PartPair* __restrict__ pairs, uint32_t* __restrict__ item_begin,
-    uint32_t* __restrict__ ovf_begin, uint32_t* __restrict__ item_part, uint32_t* __restrict__ ovf_part,
-    uint64_t* __restrict__ zero_total, uint64_t* state) {
-    __shared__ uint64_t wt[kPlanBlock / kWave];
-    __shared__ uint32_t s_blk;
-    __shared__ uint64_t s_prefix;
-    if (threadIdx.x == 0) s_blk = (uint32_t)atomicAdd((unsigned long long*)state, 1ull);
-    __syncthreads();
-    const uint32_t blk = s_blk;
-    const uint32_t P = 1u << total_bits;
-    const uint32_t nseg_rel = nseg / 2;
-    const uint32_t i = blk * kPlanBlock + threadIdx.x;
-    if (i == 0 && zero_total) *zero_total = 0;
-    PartPair pp{0, 0, 0, 0};
-    uint32_t ni = 0, no = 0;
-    if (i < P) {
-        const uint32_t r0 = min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i, n_r, 0, P), n_r);
-        const uint32_t s0 = min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i, n_s, n_r, P), n_s);
-        // clamped: a partition never extends past its relation or runs backwards
-        const uint32_t r1 = max(r0, min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i + 1, n_r, 0, P), n_r));
-        const uint32_t s1 = max(s0, min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i + 1, n_s, n_r, P), n_s));
-        pp.r_off = r0;
-        pp.r_len = r1 - r0;
-        pp.s_off = s0;
-        pp.s_len = s1 - s0;
-        ni = items_of(pp);
-        no = ovf_chunks_of(pp, lds_cap);
-    }
-    // items and chunks are each below 2^31: packed as items | chunks << 31
-    uint64_t tot;
-    const uint64_t excl = block_excl_scan((uint64_t)ni | ((uint64_t)no << 31), wt, &tot);
-    if (threadIdx.x < kWave) {
-        const uint64_t prefix = lookback_wave(state + 1, blk, tot);
-        if (threadIdx.x == 0) s_prefix = prefix;
-    }
-    __syncthreads();
-    const uint64_t run = s_prefix + excl;
-    const uint32_t ib = (uint32_t)(run & 0x7FFFFFFFu), ob = (uint32_t)(run >> 31);
-    if (i < P) {
-        pairs[i] = pp;
-        item_begin[i] = ib;
-        ovf_begin[i] = ob;
-        for (uint32_t x = 0; x < ni; ++x) item_part[ib + x] = i;
-        for (uint32_t x = 0; x < no; ++x) ovf_part[ob + x] = i;
-    }
-    if (i == P - 1) {  // the last pair also writes the totals
-        item_begin[P] = ib + ni;
-        ovf_begin[P] = ob + no;
-    }
-}
 
 __device__ __forceinline__ uint64_t region_slot(int32_t key, uint32_t H) {
     return ((uint64_t)slot_hash(key) * H) >> 32;
@@ -653,18 +570,7 @@ void write_zero_count(uint64_t* d_count, Recorder& rec) {
     rec.after();
 }
 
-size_t plan_state_words(uint32_t P) { return 1 + (P + kPlanBlock - 1) / kPlanBlock; }
-
-void join_plan(const PartSeg* segs, const uint32_t* tile_begin, uint32_t nseg, uint32_t bits_last,
-               const uint32_t* hist_scan, uint32_t n_r, uint32_t n_s, uint32_t total_bits,
-               uint32_t lds_cap, const JoinPlanOut& o, uint64_t* zero_total, uint64_t* state, Recorder& rec) {
-    const uint32_t P = 1u << total_bits;
-    rec.before("join_plan");
-    hipLaunchKernelGGL(k_join_plan, dim3((P + kPlanBlock - 1) / kPlanBlock), dim3(kPlanBlock), 0, rec.stream,
-                       segs, tile_begin, nseg, bits_last, hist_scan, n_r, n_s, total_bits, lds_cap, o.pairs,
-                       o.item_begin, o.ovf_begin, o.item_part, o.ovf_part, zero_total, state);
-    rec.after();
-}
+size_t plan_state_words(uint32_t P) { return 1 + plan_blocks(P); }
 
 uint32_t ovf_grid(uint32_t P, uint64_t n_r) {
     return (uint32_t)(P + (n_r + kOvfChunk - 1) / kOvfChunk);

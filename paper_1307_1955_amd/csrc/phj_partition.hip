@@ -19,6 +19,7 @@
 // (Section 3.1, Section 3.3) become contiguous partitions at counted offsets.
 #include "hj_device.h"
 #include "hj_internal.h"
+#include "hj_side.h"
 
 namespace hj {
 
@@ -159,8 +160,13 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
                                                             uint32_t nseg, PassCfg cfg,
                                                             const uint32_t* __restrict__ hist_scan,
                                                             int32_t* __restrict__ key_out,
-                                                            int32_t* __restrict__ rid_out) {
+                                                            int32_t* __restrict__ rid_out, SideJob side,
+                                                            uint32_t lds_words) {
     extern __shared__ uint32_t lds[];
+    if (blockIdx.x >= gridDim.x - side.blocks) {  // extra workgroups: the side job
+        run_side_job(side, blockIdx.x - (gridDim.x - side.blocks), lds, lds_words);
+        return;
+    }
     constexpr uint32_t T = kPartBlock * IPT;
     const uint32_t P = 1u << cfg.bits;
     const uint32_t Pp = P < kWave ? kWave : P;  // scan length, a multiple of 64
@@ -286,80 +292,6 @@ __global__ void __launch_bounds__(256) k_setup_pass1(PartSeg* segs, uint32_t* ti
     tile_begin[2] = nt_r + nt_s;
 }
 
-constexpr uint32_t kSetupBlock = 1024;
-constexpr uint32_t kSetupLdsSegs = 4096;  // segment table kept in LDS up to this many segments
-
-// Start of partition q of a pass-1 segment relative to the segment.
-__device__ __forceinline__ uint32_t seg_part_start(const uint32_t* __restrict__ hs_seg, uint32_t nt,
-                                                   uint32_t q) {
-    return nt ? hs_seg[(uint64_t)q * nt] - hs_seg[0] : 0u;
-}
-
-__global__ void __launch_bounds__(kSetupBlock) k_setup_pass2(
-    const uint32_t* __restrict__ hist1_scan, const uint32_t* __restrict__ tile_begin1, uint32_t bits1,
-    uint32_t n_r, uint32_t n_s, const int32_t* key_in, const int32_t* rid_in, uint32_t tile,
-    uint32_t bits2, PartSeg* __restrict__ segs2, uint32_t* __restrict__ tile_begin2,
-    uint32_t* __restrict__ tile_seg2) {
-    __shared__ uint32_t wt[kSetupBlock / kWave];
-    __shared__ uint32_t tb[kSetupLdsSegs + 1];
-    const uint32_t P1 = 1u << bits1;
-    const uint32_t nseg = 2 * P1;
-    const uint32_t per = (nseg + kSetupBlock - 1) / kSetupBlock;
-    const uint32_t a = threadIdx.x * per;
-    const uint32_t b = min(a + per, nseg);
-    const uint32_t nt_r = tile_begin1[1], nt_s = tile_begin1[2] - tile_begin1[1];
-    // pass 1 used hist_base = 0 for R and nt_r << bits1 for S
-    auto seg_range = [&](uint32_t s, uint32_t* off, uint32_t* len, uint32_t* base) {
-        const uint32_t rel = s >= P1;
-        const uint32_t q = s - rel * P1;
-        const uint32_t nt = rel ? nt_s : nt_r;
-        const uint32_t* hs = hist1_scan + (rel ? ((uint64_t)nt_r << bits1) : 0ull);
-        const uint32_t n = rel ? n_s : n_r;
-        // clamped so a segment always lies inside its relation
-        const uint32_t st = min(seg_part_start(hs, nt, q), n);
-        const uint32_t en = max(st, q + 1 < P1 ? min(seg_part_start(hs, nt, q + 1), n) : n);
-        *off = st;
-        *len = en - st;
-        *base = rel ? n_r : 0u;
-    };
-    uint32_t ntiles = 0;
-    for (uint32_t s = a; s < b; ++s) {
-        uint32_t off, len, base;
-        seg_range(s, &off, &len, &base);
-        ntiles += (len + tile - 1) / tile;
-    }
-    uint32_t total;
-    uint32_t run = block_excl_scan(ntiles, wt, &total);
-    const bool in_lds = nseg < kSetupLdsSegs;
-    for (uint32_t s = a; s < b; ++s) {
-        uint32_t off, len, base;
-        seg_range(s, &off, &len, &base);
-        PartSeg g;
-        g.key_in = key_in + base + off;
-        g.rid_in = rid_in + base + off;
-        g.out_base = (uint64_t)base + off;
-        g.hist_base = (uint64_t)run << bits2;
-        g.n = len;
-        g.pad = 0;
-        segs2[s] = g;
-        tile_begin2[s] = run;
-        if (in_lds) tb[s] = run;
-        const uint32_t nt = (len + tile - 1) / tile;
-        if (!in_lds)
-            for (uint32_t x = 0; x < nt; ++x) tile_seg2[run + x] = s;
-        run += nt;
-    }
-    if (threadIdx.x == 0) {
-        tile_begin2[nseg] = total;
-        if (in_lds) tb[nseg] = total;
-    }
-    if (in_lds) {
-        // every thread maps its share of the tiles to segments (binary search in LDS)
-        __syncthreads();
-        for (uint32_t t = threadIdx.x; t < total; t += kSetupBlock) tile_seg2[t] = upper_index(tb, nseg, t);
-    }
-}
-
 template <uint32_t IPT>
 void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                  uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
@@ -373,16 +305,22 @@ void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t
 template <uint32_t IPT>
 void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                     uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
-                    int32_t* rid_out, Recorder& rec) {
+                    int32_t* rid_out, const SideJob& side, Recorder& rec) {
     const size_t P = (size_t)1 << cfg.bits;
     const size_t Pp = P < kWave ? kWave : P;
-    const size_t lds = sizeof(uint32_t) * (2 * Pp + kScanScratch) + sizeof(int32_t) * 2 * kPartBlock * IPT;
+    size_t lds = sizeof(uint32_t) * (2 * Pp + kScanScratch) + sizeof(int32_t) * 2 * kPartBlock * IPT;
+    if (side.kind == kSideSetup2) {
+        // room for the pass-2 segment tile offsets (else the setup fills the tile map from HBM)
+        const size_t want = sizeof(uint32_t) * (kScanScratch + 2 * ((size_t)1 << side.setup2.bits1) + 1);
+        if (want > lds && want <= 65536) lds = want;
+    }
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_part_scatter<IPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
     rec.before("part_scatter");
-    hipLaunchKernelGGL(k_part_scatter<IPT>, dim3(grid), dim3(kPartBlock), lds, rec.stream, segs,
-                       tile_begin, tile_seg, nseg, cfg, hist_scan, key_out, rid_out);
+    hipLaunchKernelGGL(k_part_scatter<IPT>, dim3(grid + side.blocks), dim3(kPartBlock), lds, rec.stream, segs,
+                       tile_begin, tile_seg, nseg, cfg, hist_scan, key_out, rid_out, side,
+                       (uint32_t)(lds / sizeof(uint32_t)));
     rec.after();
 }
 
@@ -403,16 +341,6 @@ void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, co
     rec.after();
 }
 
-void part_setup_pass2(const uint32_t* hist1_scan, const uint32_t* tile_begin1, uint32_t bits1,
-                      uint32_t n_r, uint32_t n_s, const int32_t* key_in, const int32_t* rid_in,
-                      uint32_t tile, uint32_t bits2, PartSeg* segs2, uint32_t* tile_begin2,
-                      uint32_t* tile_seg2, Recorder& rec) {
-    rec.before("part_setup2");
-    hipLaunchKernelGGL(k_setup_pass2, dim3(1), dim3(kSetupBlock), 0, rec.stream, hist1_scan,
-                       tile_begin1, bits1, n_r, n_s, key_in, rid_in, tile, bits2, segs2, tile_begin2,
-                       tile_seg2);
-    rec.after();
-}
 
 void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
@@ -427,10 +355,10 @@ void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* 
 
 void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                   uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
-                  int32_t* rid_out, Recorder& rec) {
-    if (grid == 0) return;
+                  int32_t* rid_out, const SideJob& side, Recorder& rec) {
+    if (grid + side.blocks == 0) return;
 #define HJ_SCATTER(IPT) \
-    launch_scatter<IPT>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist_scan, key_out, rid_out, rec)
+    launch_scatter<IPT>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist_scan, key_out, rid_out, side, rec)
     switch (cfg.tile) {
         case 1024: HJ_SCATTER(4); break;
         case 2048: HJ_SCATTER(8); break;
