@@ -25,15 +25,16 @@ from dataclasses import dataclass
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(PKG, "tuning", "mi355x.json")
 
-# Calibration on MI355X (16M x 16M PHJ, 6+6 bits): histogram read 4 B/tuple in
-# 31 us per pass; scatter 16 B/tuple in 116 us per pass; LDS join write
-# (8 B/tuple + 8 B/pair) 186 us for 4096 work items; SHJ build 16M tuples in
-# 0.79 ms into a 256 MB table, probe 0.35 ms per pass.
+# Calibration on MI355X (rocprofv3 kernel times, 16M x 16M PHJ, 6+6 bits):
+# histogram read 4 B/tuple in 31 us per pass; scatter 16 B/tuple in 110 us per
+# pass; one-pass LDS join write (8 B/tuple + 8 B/pair) 95 us for 4096 work
+# items of ~17 us each; SHJ build 16M tuples in 0.78 ms into a 256 MB table,
+# probe 0.35 ms per pass.
 CALIB = {
     "bw_hist": 4.3e12,          # B/s, streaming key read
-    "bw_scatter": 4.6e12,       # B/s, read 8 + write 8 per tuple
-    "bw_join": 1.8e12,          # B/s, LDS-table join passes
-    "item_lat": 30e-6,          # s, one join work item start to finish
+    "bw_scatter": 4.9e12,       # B/s, read 8 + write 8 per tuple
+    "bw_join": 3.5e12,          # B/s, LDS-table join passes
+    "item_lat": 17e-6,          # s, one join work item start to finish
     "launch": 4e-6,             # s, per kernel launch
     "shj_build_hbm": 47e-9,     # s per R tuple, table beyond the caches
     "shj_build_cache": 4e-9,    # s per R tuple, table resident in L2 / MALL
@@ -51,17 +52,19 @@ class Candidate:
     passes: int          # PHJ: 0 (direct), 1, 2
     bits: tuple = (0, 0)
     one_pass: bool = True
+    tile: int = 0        # partition tile (0: the library default, 4096)
 
     def params(self):
         from . import hj
-        return hj.params(self.algo, self.passes, self.bits, one_pass=self.one_pass)
+        return hj.params(self.algo, self.passes, self.bits, tile=self.tile, one_pass=self.one_pass)
 
     def as_dict(self) -> dict:
-        return {"algo": self.algo, "passes": self.passes, "bits": list(self.bits), "one_pass": self.one_pass}
+        return {"algo": self.algo, "passes": self.passes, "bits": list(self.bits), "one_pass": self.one_pass,
+                "tile": self.tile}
 
     @staticmethod
     def from_dict(d: dict) -> "Candidate":
-        return Candidate(d["algo"], int(d["passes"]), tuple(d["bits"]), bool(d["one_pass"]))
+        return Candidate(d["algo"], int(d["passes"]), tuple(d["bits"]), bool(d["one_pass"]), int(d.get("tile", 0)))
 
 
 def _bits_for(n_r: int, target: int = 4096) -> int:
@@ -79,6 +82,8 @@ def candidates(n_r: int, n_s: int) -> list[Candidate]:
     for b in {max(1, B - 1), max(1, B), B + 1}:
         if b <= 8:
             out.append(Candidate("phj", 1, (b, 0)))
+        if 7 <= b <= 11:  # wider fan-out: larger tiles keep the scatter's runs long
+            out.append(Candidate("phj", 1, (b, 0), tile=8192))
         if 2 <= b <= 16:
             out.append(Candidate("phj", 2, ((b + 1) // 2, b // 2)))
             out.append(Candidate("phj", 2, ((b + 1) // 2, b // 2), one_pass=False))
@@ -103,14 +108,18 @@ def predict(c: Candidate, n_r: int, n_s: int, m: float, cal: dict = CALIB) -> fl
         waves = math.ceil(items / conc)
         return waves * cal["item_lat"] + (8 * n + 8 * m) / cal["bw_join"] + 2 * cal["launch"]
     t = 0.0
-    for _ in range(c.passes):
-        t += 4 * n / cal["bw_hist"] + 16 * n / cal["bw_scatter"] + 5 * cal["launch"]
+    tile = c.tile or 4096
+    for b in c.bits[: c.passes]:
+        # scatter runs shorter than ~64 tuples waste write bandwidth
+        runs = tile / (1 << b)
+        eff = min(1.0, runs / 64.0)
+        t += 4 * n / cal["bw_hist"] + 16 * n / (cal["bw_scatter"] * max(eff, 0.25)) + 3 * cal["launch"]
     P = 1 << sum(c.bits[: c.passes])
     items = P + math.ceil(n_s / 4096)
     waves = math.ceil(items / conc)
     join_bytes = (8 * n + 8 * m) + (0 if c.one_pass else 4 * n)
     t += max(waves * cal["item_lat"], join_bytes / cal["bw_join"]) * (1 if c.one_pass else 1.6)
-    t += (5 if c.one_pass else 9) * cal["launch"]
+    t += (4 if c.one_pass else 6) * cal["launch"]
     r_part = n_r / P
     if r_part > 8192:  # partitions beyond the LDS budget take the HBM-table path
         t += n * cal["shj_probe_hbm"]
