@@ -82,8 +82,6 @@ def candidates(n_r: int, n_s: int) -> list[Candidate]:
     for b in {max(1, B - 1), max(1, B), B + 1}:
         if b <= 8:
             out.append(Candidate("phj", 1, (b, 0)))
-        if 7 <= b <= 11:  # wider fan-out: larger tiles keep the scatter's runs long
-            out.append(Candidate("phj", 1, (b, 0), tile=8192))
         if 2 <= b <= 16:
             out.append(Candidate("phj", 2, ((b + 1) // 2, b // 2)))
             out.append(Candidate("phj", 2, ((b + 1) // 2, b // 2), one_pass=False))
