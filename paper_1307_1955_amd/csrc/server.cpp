@@ -176,6 +176,8 @@ void dispatcher(hj_server* sv) {
             sv->cv.notify_all();
         }
         // admit waiting requests into idle slots
+        bool rejected_any = false;
+        std::vector<Slot*> to_launch;
         for (Slot& s : sv->slots) {
             if (s.busy || sv->pending.empty()) continue;
             size_t pipe_ws = 0;
@@ -187,6 +189,7 @@ void dispatcher(hj_server* sv) {
                     sv->done.push_back(d);
                     ++sv->rejected;
                     sv->pending.pop_front();
+                    rejected_any = true;
                     continue;
                 }
                 if (sv->used + r.footprint > sv->cfg.mem_cap_bytes) break;  // wait for memory
@@ -201,9 +204,25 @@ void dispatcher(hj_server* sv) {
             sv->inflight += s.reqs.size();
             ++sv->batches;
             s.busy = true;
-            hj_status st = launch_slot(sv, s);
-            if (st != HJ_OK && sv->fatal == HJ_OK) sv->fatal = st;
+            to_launch.push_back(&s);
             any_busy = true;
+        }
+        // a rejection can leave nothing pending or in flight: wake drain()
+        if (rejected_any) sv->cv.notify_all();
+        if (!to_launch.empty()) {
+            // Slots are touched by this thread only; submitters need not wait
+            // for the launches.
+            lk.unlock();
+            hj_status st = HJ_OK;
+            for (Slot* s : to_launch) {
+                const hj_status e = launch_slot(sv, *s);
+                if (st == HJ_OK) st = e;
+            }
+            lk.lock();
+            if (st != HJ_OK && sv->fatal == HJ_OK) {
+                sv->fatal = st;
+                sv->cv.notify_all();
+            }
         }
         if (sv->stop && sv->pending.empty() && !any_busy) break;
         if (any_busy) {

@@ -117,3 +117,22 @@ def test_many_small_requests():
     ref = oracle.canonical(*oracle.join(r.key, r.rid, s.key, s.rid))
     for i in (0, n // 2, n - 1):
         assert np.array_equal(oracle.canonical(outs[i, 0].cpu().numpy(), outs[i, 1].cpu().numpy()), ref)
+
+
+def test_drain_after_only_rejections():
+    """drain() returns when the only requests were rejected at admission (nothing
+    ever ran, so no finished batch wakes it)."""
+    r, s = gen.unique_uniform(31, 2048, 4096, 3000)
+    rk, rr, sk, sr = (torch.from_numpy(a).to(DEV) for a in (r.key, r.rid, s.key, s.rid))
+    o = torch.empty((2, 4096), dtype=torch.int32, device=DEV)
+    counts = torch.zeros(2, dtype=torch.int64, device=DEV)
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device=DEV)
+    sv = hj.Server(ws, mem_cap_bytes=1 << 20, slots=2, max_batch_jobs=4)
+    p = hj.params("phj", 0, (0, 0))
+    t = [sv.submit(rk, rr, sk, sr, o[0], o[1], counts[i:i + 1], p, 2 << 20) for i in range(2)]
+    sv.drain()
+    done = {x[0]: x[1] for x in sv.poll()}
+    assert done == {t[0]: hj.HJ_ERR_CAPACITY, t[1]: hj.HJ_ERR_CAPACITY}
+    st = sv.stats()
+    assert st["rejected"] == 2 and st["completed"] == 0 and st["bytes_in_use"] == 0
+    sv.close()
