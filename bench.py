@@ -321,6 +321,7 @@ def main():
     bits = tuple(int(b) for b in args.bits.split(","))
     one_pass = not args.two_pass
     p = hj.params("phj", args.passes, bits, hash=args.hash, tile=args.tile, one_pass=one_pass)
+    rp = hj.hj_resolve_params(p, n, n)  # tile and LDS table capacity as the library chooses them
     print("bench: generating 16M x 16M inputs on the device", file=sys.stderr, flush=True)
     t = dgen.config_c2(n=n, device=dev)
     n_r, n_s = n, n
@@ -355,7 +356,7 @@ def main():
             "workload": "PHJ 16M x 16M: |R| = |S| = %d int32 (key, rid); R keys a permutation of 1..|R|, "
                         "S keys uniform over 1..2|R| (~50%% match)" % n,
             "algo": "phj", "passes": args.passes, "bits": list(bits), "hash": args.hash,
-            "tile": p.tile or 4096, "output": "one-pass (block reservation)" if one_pass else
+            "tile": rp.tile, "lds_cap": rp.lds_cap, "output": "one-pass (block reservation)" if one_pass else
             "two-pass (count, scan, write)", "matches": m,
         },
         "roofline": {
@@ -392,11 +393,12 @@ def main():
             for passes, bb in configs:
                 if sum(bb) < 8 or sum(bb) > 14 or max(bb) > 13:
                     continue
-                for tile in (0, 8192) if passes == 1 else (0,):
+                for tile in (0, 4096) if passes == 1 else (0,):
                     q = hj.params("phj", passes, bb, hash=args.hash, tile=tile, one_pass=one)
                     wq = hj.workspace(q, n_r, n_s, dev)
                     msq = time_steps(lambda: hj.hj_join(q, *t, out_r, out_s, wq, d_count), 5, 2, torch)
-                    sweep.append({"passes": passes, "bits": list(bb), "tile": tile or 4096, "one_pass": one,
+                    sweep.append({"passes": passes, "bits": list(bb), "tile": hj.hj_resolve_params(q, n_r, n_s).tile,
+                                  "one_pass": one,
                                   "ms": round(msq, 4), "tuples_per_s": (n_r + n_s) / (msq * 1e-3)})
                     print("bench: sweep %s" % sweep[-1], file=sys.stderr, flush=True)
                     del wq

@@ -99,8 +99,8 @@ typedef struct hj_out {
            2^B partitions are the values of the B low bits of the hash; pass 1
            splits on the high bits[0] of them, pass 2 on the low bits[1].
    hash    an hj_hash value.
-   tile    tuples per partitioning tile: 0 (default 4096) or a power of two
-           in 1024..8192.
+   tile    tuples per partitioning tile: a power of two in 1024..8192, or 0
+           = chosen from the sizes (8192 when |R| + |S| >= 2^24, else 4096).
    lds_cap largest R partition (tuples) joined from an LDS-resident table:
            0 = chosen from |R| and B; else a multiple of 64 in 256..8192.
            Larger partitions take the HBM-table path.
@@ -115,8 +115,15 @@ typedef struct hj_params {
     uint32_t flags;
 } hj_params;
 
-/* Fills `p` with the library defaults: PHJ, 2 passes of 6 bits, identity hash. */
+/* Fills `p` with the library defaults: PHJ, 2 passes of 6 bits, identity hash,
+   tile and lds_cap chosen from the sizes, two-pass output. */
 void hj_default_params(hj_params* p);
+
+/* Copies `p` into `out` with every value the library chooses from the sizes
+   filled in, as hj_join would use it for |R| = n_r, |S| = n_s: PHJ tile and
+   lds_cap (and HJ_FLAG_ONE_PASS for passes == 0, which always writes its output
+   in one pass).  Host only.  Returns HJ_ERR_INVALID for invalid parameters. */
+hj_status hj_resolve_params(const hj_params* p, uint64_t n_r, uint64_t n_s, hj_params* out);
 
 /* Bytes of device workspace hj_join needs for these parameters and sizes.
    Returns 0 if the parameters are invalid (hj_last_error() says why). */

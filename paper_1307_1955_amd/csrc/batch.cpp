@@ -186,7 +186,7 @@ hj_status hj_batch_plan_create(uint32_t njobs, const hj_job* jobs, const hj_para
         hj_params p;
         if (params) p = params[i]; else default_params(j, &p);
         Plan pl;
-        st = check_params(&p, j.R.n, &pl);
+        st = check_params(&p, j.R.n, j.S.n, &pl);
         if (st != HJ_OK) {
             free_plan(b);
             return fail(st, "job %u: %s", i, last_error());

@@ -89,13 +89,13 @@ uint32_t auto_lds_cap(uint64_t n_r, uint32_t P) {
     return cap;
 }
 
-hj_status check_params(const hj_params* p, uint64_t n_r, Plan* pl) {
+hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl) {
     if (!p) return fail(HJ_ERR_INVALID, "params is NULL");
     if (p->flags & ~HJ_FLAG_ONE_PASS) return fail(HJ_ERR_INVALID, "unknown flags 0x%x", p->flags);
     if (p->algo != HJ_SHJ && p->algo != HJ_PHJ) return fail(HJ_ERR_INVALID, "unknown algo %u", p->algo);
     if (p->hash != HJ_HASH_IDENTITY && p->hash != HJ_HASH_MURMUR2)
         return fail(HJ_ERR_INVALID, "unknown hash %u", p->hash);
-    const uint32_t tile = p->tile ? p->tile : 4096;
+    const uint32_t tile = p->tile ? p->tile : hj::default_tile(n_r, n_s);
     if (tile != 1024 && tile != 2048 && tile != 4096 && tile != 8192)
         return fail(HJ_ERR_INVALID, "tile must be 0 or a power of two in 1024..8192 (got %u)", p->tile);
     pl->phj = p->algo == HJ_PHJ;
@@ -283,7 +283,7 @@ void run_direct(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& 
 hj_status check_call(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,
                      size_t ws_bytes, uint64_t* d_count, Plan* pl) {
     if (!R || !S || !out) return fail(HJ_ERR_INVALID, "R, S and out must not be NULL");
-    hj_status st = check_params(p, R->n, pl);
+    hj_status st = check_params(p, R->n, S->n, pl);
     if (st != HJ_OK) return st;
     if (R->n > kMaxRows || S->n > kMaxRows)
         return fail(HJ_ERR_INVALID, "relations must have fewer than 2^31 tuples");
@@ -323,7 +323,7 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
     // the join plan rides on the last pass's scatter, the pass-2 setup on the first
     hj::SideJob plan{};
     plan.kind = hj::kSidePlan;
-    plan.blocks = hj::plan_blocks(pl.P);
+    plan.blocks = hj::plan_blocks(pl.P, hj::part_block(pl.tile));
     plan.plan = hj::PlanArgs{two ? w.segs2 : w.segs1, two ? w.tb2 : w.tb1, two ? w.hist2 : w.hist1,
                              two ? 2 * pl.P1 : 2u, two ? pl.b2 : pl.b1, n_r, n_s, pl.B, pl.lds_cap,
                              w.pairs, w.item_begin, w.ovf_begin, w.item_part, w.ovf_part,

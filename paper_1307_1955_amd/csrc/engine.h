@@ -31,7 +31,7 @@ struct Plan {
 
 // Default LDS table capacity for |R| = n_r split into P partitions.
 uint32_t auto_lds_cap(uint64_t n_r, uint32_t P);
-hj_status check_params(const hj_params* p, uint64_t n_r, Plan* pl);
+hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl);
 hj_status check_call(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,
                      size_t ws_bytes, uint64_t* d_count, Plan* pl);
 size_t ws_bytes_for(const Plan& pl, uint64_t n_r, uint64_t n_s);

@@ -48,19 +48,36 @@ void hj_default_params(hj_params* p) {
     p->bits[0] = 6;
     p->bits[1] = 6;
     p->hash = HJ_HASH_IDENTITY;
-    p->tile = 4096;
+    p->tile = 0;
     p->lds_cap = 0;
     p->flags = 0;
 }
 
 size_t hj_workspace_bytes(const hj_params* p, uint64_t n_r, uint64_t n_s) {
     Plan pl;
-    if (check_params(p, n_r, &pl) != HJ_OK) return 0;
+    if (check_params(p, n_r, n_s, &pl) != HJ_OK) return 0;
     if (n_r > kMaxRows || n_s > kMaxRows) {
         fail(HJ_ERR_INVALID, "relations must have fewer than 2^31 tuples");
         return 0;
     }
     return ws_bytes_for(pl, n_r, n_s);
+}
+
+hj_status hj_resolve_params(const hj_params* p, uint64_t n_r, uint64_t n_s, hj_params* out) {
+    if (!out) return fail(HJ_ERR_INVALID, "out is NULL");
+    Plan pl;
+    const hj_status st = check_params(p, n_r, n_s, &pl);
+    if (st != HJ_OK) return st;
+    if (n_r > kMaxRows || n_s > kMaxRows) return fail(HJ_ERR_INVALID, "relations must have fewer than 2^31 tuples");
+    *out = *p;
+    if (pl.phj) {
+        out->passes = pl.passes;
+        out->tile = pl.tile;
+        out->lds_cap = pl.lds_cap;
+        if (pl.passes == 0) out->flags |= HJ_FLAG_ONE_PASS;
+    }
+    clear_error();
+    return HJ_OK;
 }
 
 hj_status hj_join(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,

@@ -12,7 +12,7 @@
 namespace hj {
 
 constexpr uint32_t kOvfChunk = 4096;  // R tuples per HBM-table build item
-constexpr uint32_t kPlanBlock = 256;  // threads of a join-plan workgroup
+constexpr uint32_t kMaxPlanWaves = 16;  // waves of the largest workgroup that runs the join plan
 
 // Everything the pass-2 setup reads and writes.
 struct Setup2Args {
@@ -50,7 +50,8 @@ struct SideJob {
     PlanArgs plan;
 };
 
-inline uint32_t plan_blocks(uint32_t P) { return (P + kPlanBlock - 1) / kPlanBlock; }
+// Join-plan workgroups of `block` threads (one partition pair per thread).
+inline uint32_t plan_blocks(uint32_t P, uint32_t block) { return (P + block - 1) / block; }
 
 // Start of final partition i of one relation (positions relative to the relation).
 __device__ __forceinline__ uint32_t final_start(const PartSeg* __restrict__ segs,
@@ -80,7 +81,7 @@ __device__ __forceinline__ uint32_t ovf_chunks_of(const PartPair& pp, uint32_t l
 // HBM-table build chunks, their exclusive scans over all pairs (one chained
 // scan of both counts packed in one word) and the item -> pair maps.
 // state[0]: ticket; state[1 + b]: status of workgroup b (cleared beforehand).
-// Run by plan_blocks(P) workgroups of kPlanBlock threads.
+// Run by plan_blocks(P, blockDim.x) workgroups.
 __device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
     const PartSeg* __restrict__ segs = A.segs;
     const uint32_t* __restrict__ tile_begin = A.tile_begin;
@@ -94,7 +95,7 @@ __device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
     uint32_t* __restrict__ ovf_part = A.ovf_part;
     uint64_t* __restrict__ zero_total = A.zero_total;
     uint64_t* state = A.state;
-    __shared__ uint64_t wt[kPlanBlock / kWave];
+    __shared__ uint64_t wt[kMaxPlanWaves];
     __shared__ uint32_t s_blk;
     __shared__ uint64_t s_prefix;
     if (threadIdx.x == 0) s_blk = (uint32_t)atomicAdd((unsigned long long*)state, 1ull);
@@ -102,7 +103,7 @@ __device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
     const uint32_t blk = s_blk;
     const uint32_t P = 1u << total_bits;
     const uint32_t nseg_rel = nseg / 2;
-    const uint32_t i = blk * kPlanBlock + threadIdx.x;
+    const uint32_t i = blk * blockDim.x + threadIdx.x;
     if (i == 0 && zero_total) *zero_total = 0;
     PartPair pp{0, 0, 0, 0};
     uint32_t ni = 0, no = 0;

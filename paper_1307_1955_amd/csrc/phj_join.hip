@@ -570,7 +570,8 @@ void write_zero_count(uint64_t* d_count, Recorder& rec) {
     rec.after();
 }
 
-size_t plan_state_words(uint32_t P) { return 1 + plan_blocks(P); }
+// (an upper bound: the plan runs in workgroups of at least kMinPartBlock threads)
+size_t plan_state_words(uint32_t P) { return 1 + plan_blocks(P, kMinPartBlock); }
 
 uint32_t ovf_grid(uint32_t P, uint64_t n_r) {
     return (uint32_t)(P + (n_r + kOvfChunk - 1) / kOvfChunk);

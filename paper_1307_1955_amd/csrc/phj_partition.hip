@@ -25,7 +25,6 @@ namespace hj {
 
 namespace {
 
-constexpr uint32_t kPartBlock = 256;
 // Up to this many radix bits (8 partitions) the lanes of a wave that share a
 // partition are grouped with ballots and one leader atomic per group: at such
 // low fan-out most lanes of a wave hit the same few LDS counters.  Above it,
@@ -69,17 +68,17 @@ __device__ __forceinline__ uint64_t match_mask(uint32_t p, uint32_t bits, bool v
     return valid ? m : 0ull;
 }
 
-// Loads the elements [0, len) of a tile (len <= kPartBlock * IPT) that starts
+// Loads the elements [0, len) of a tile (len <= BLOCK * IPT) that starts
 // at `p` (4-byte aligned) with 16-byte vector loads: lane-contiguous 16-byte
 // chunks of the enclosing aligned window; thread t, slot k holds chunk
-// t + k * kPartBlock, i.e. v[4k + e] = window element 4 (t + k kPartBlock) + e,
+// t + k * BLOCK, i.e. v[4k + e] = window element 4 (t + k BLOCK) + e,
 // tile element that minus the misalignment s = (p mod 16) / 4.  Only chunks lying
 // wholly inside the tile are read as vectors; the elements of the (at most two)
 // partial chunks are read one by one, and the up to 3 tile elements past the
 // window (when s > 0) go to `x` of threads 0..2.  Nothing outside the tile is
 // read.  Returns the validity mask: bit i for v[i], bit 4 IPT for x.  Element
 // order inside a tile is free: counts and ranks do not depend on it.
-template <uint32_t IPT>
+template <uint32_t BLOCK, uint32_t IPT>
 __device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ p, uint32_t len, int32_t* v,
                                                   int32_t& x) {
     static_assert(IPT % 4 == 0 && IPT <= 32, "vector tile slots");
@@ -88,7 +87,7 @@ __device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ p,
     uint64_t valid = 0;
 #pragma unroll
     for (uint32_t k = 0; k < IPT / 4; ++k) {
-        const uint32_t c = threadIdx.x + k * kPartBlock;
+        const uint32_t c = threadIdx.x + k * BLOCK;
         const int32_t i0 = (int32_t)(4 * c) - (int32_t)s;  // tile index of the chunk's first element
         if (i0 >= 0 && i0 + 4 <= (int32_t)len) {
             const int4 w = *reinterpret_cast<const int4*>(q + 4 * c);
@@ -107,21 +106,21 @@ __device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ p,
             }
         }
     }
-    const uint32_t xi = kPartBlock * IPT - s + threadIdx.x;  // past the window
+    const uint32_t xi = BLOCK * IPT - s + threadIdx.x;  // past the window
     const bool xok = threadIdx.x < s && xi < len;
     x = xok ? p[xi] : 0;
     valid |= (uint64_t)xok << IPT;
     return valid;
 }
 
-template <uint32_t IPT>
-__global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restrict__ segs,
+template <uint32_t BLOCK, uint32_t IPT>
+__global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__ segs,
                                                          const uint32_t* __restrict__ tile_begin,
                                                          const uint32_t* __restrict__ tile_seg,
                                                          uint32_t nseg, PassCfg cfg,
                                                          uint32_t* __restrict__ hist) {
     extern __shared__ uint32_t lds[];
-    constexpr uint32_t T = kPartBlock * IPT;
+    constexpr uint32_t T = BLOCK * IPT;
     uint32_t* cnt = lds;
     const uint32_t P = 1u << cfg.bits;
     const uint32_t ntiles = tile_begin[nseg];
@@ -131,9 +130,9 @@ __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restr
     const PartSeg sg = segs[t.seg];
     const int32_t* __restrict__ kin = sg.key_in + t.start;
     int32_t keys[IPT], kx;
-    const uint64_t valid = load_tile_vec<IPT>(kin, t.len, keys, kx);
+    const uint64_t valid = load_tile_vec<BLOCK, IPT>(kin, t.len, keys, kx);
     // counters cleared while the tile's loads are in flight
-    for (uint32_t i = threadIdx.x; i < P; i += kPartBlock) cnt[i] = 0;
+    for (uint32_t i = threadIdx.x; i < P; i += BLOCK) cnt[i] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
 #pragma unroll
@@ -150,11 +149,11 @@ __global__ void __launch_bounds__(kPartBlock) k_part_hist(const PartSeg* __restr
     if ((valid >> IPT) & 1u) atomicAdd(&cnt[part_of(kx, cfg)], 1u);
     __syncthreads();
     uint32_t* __restrict__ h = hist + sg.hist_base + t.tl;
-    for (uint32_t p = threadIdx.x; p < P; p += kPartBlock) h[(uint64_t)p * t.nt] = cnt[p];
+    for (uint32_t p = threadIdx.x; p < P; p += BLOCK) h[(uint64_t)p * t.nt] = cnt[p];
 }
 
-template <uint32_t IPT>
-__global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __restrict__ segs,
+template <uint32_t BLOCK, uint32_t IPT>
+__global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restrict__ segs,
                                                             const uint32_t* __restrict__ tile_begin,
                                                             const uint32_t* __restrict__ tile_seg,
                                                             uint32_t nseg, PassCfg cfg,
@@ -167,7 +166,7 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
         run_side_job(side, blockIdx.x - (gridDim.x - side.blocks), lds, lds_words);
         return;
     }
-    constexpr uint32_t T = kPartBlock * IPT;
+    constexpr uint32_t T = BLOCK * IPT;
     const uint32_t P = 1u << cfg.bits;
     const uint32_t Pp = P < kWave ? kWave : P;  // scan length, a multiple of 64
     uint32_t* cnt = lds;                         // [Pp]  counts, then local starts
@@ -187,13 +186,13 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     uint32_t rank[IPT];
     uint64_t valid;
     if ((((uintptr_t)kin ^ (uintptr_t)rin) & 15u) == 0) {  // same misalignment: one vector pattern for both
-        valid = load_tile_vec<IPT>(kin, t.len, keys, kx);
-        load_tile_vec<IPT>(rin, t.len, rids, rx);
+        valid = load_tile_vec<BLOCK, IPT>(kin, t.len, keys, kx);
+        load_tile_vec<BLOCK, IPT>(rin, t.len, rids, rx);
     } else {
         valid = 0;
 #pragma unroll
         for (uint32_t k = 0; k < IPT; ++k) {
-            const uint32_t idx = k * kPartBlock + threadIdx.x;
+            const uint32_t idx = k * BLOCK + threadIdx.x;
             const bool ok = idx < t.len;
             keys[k] = ok ? kin[idx] : 0;
             rids[k] = ok ? rin[idx] : 0;
@@ -202,12 +201,12 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
         kx = rx = 0;
     }
     // This tile's global partition offsets do not depend on the tile's data:
-    // fetched together with it (first kPartBlock partitions; the rest later).
+    // fetched together with it (first BLOCK partitions; the rest later).
     const uint32_t* __restrict__ hs = hist_scan + sg.hist_base;
     const uint32_t hs_own = threadIdx.x < P ? hs[(uint64_t)threadIdx.x * t.nt + t.tl] : 0u;
     const uint32_t seg0 = hs[0];
     // counters cleared while the loads are in flight
-    for (uint32_t i = threadIdx.x; i < Pp; i += kPartBlock) cnt[i] = 0;
+    for (uint32_t i = threadIdx.x; i < Pp; i += BLOCK) cnt[i] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
 #pragma unroll
@@ -233,8 +232,8 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     __syncthreads();
     lds_excl_scan(cnt, Pp, ctot);
     __syncthreads();
-    for (uint32_t p = threadIdx.x; p < P; p += kPartBlock) {
-        const uint32_t g = p < kPartBlock ? hs_own : hs[(uint64_t)p * t.nt + t.tl];
+    for (uint32_t p = threadIdx.x; p < P; p += BLOCK) {
+        const uint32_t g = p < BLOCK ? hs_own : hs[(uint64_t)p * t.nt + t.tl];
         const uint32_t rel = g - seg0;  // exact: < segment length
         delta[p] = rel - cnt[p];
     }
@@ -260,7 +259,7 @@ __global__ void __launch_bounds__(kPartBlock) k_part_scatter(const PartSeg* __re
     int32_t* __restrict__ rout = rid_out + sg.out_base;
 #pragma unroll
     for (uint32_t k = 0; k < IPT; ++k) {
-        const uint32_t j = k * kPartBlock + threadIdx.x;
+        const uint32_t j = k * BLOCK + threadIdx.x;
         if (j < t.len) {
             const int32_t key = skey[j];
             const uint32_t dst = delta[part_of(key, cfg)] + j;
@@ -292,33 +291,39 @@ __global__ void __launch_bounds__(256) k_setup_pass1(PartSeg* segs, uint32_t* ti
     tile_begin[2] = nt_r + nt_s;
 }
 
-template <uint32_t IPT>
+template <uint32_t BLOCK, uint32_t IPT>
 void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                  uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
     const size_t lds = sizeof(uint32_t) * ((size_t)1 << cfg.bits);
     rec.before("part_hist");
-    hipLaunchKernelGGL(k_part_hist<IPT>, dim3(grid), dim3(kPartBlock), lds, rec.stream, segs, tile_begin,
+    static_assert(BLOCK * IPT >= 1024 && BLOCK * IPT <= 8192 && BLOCK / kWave <= kScanScratch, "tile shape");
+    hipLaunchKernelGGL((k_part_hist<BLOCK, IPT>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs, tile_begin,
                        tile_seg, nseg, cfg, hist);
     rec.after();
 }
 
-template <uint32_t IPT>
+template <uint32_t BLOCK, uint32_t IPT>
 void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                     uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
                     int32_t* rid_out, const SideJob& side, Recorder& rec) {
+    if (part_block(cfg.tile) != BLOCK) {  // side-job workgroups are sized with part_block()
+        if (rec.err == hipSuccess) rec.err = hipErrorInvalidConfiguration;
+        return;
+    }
     const size_t P = (size_t)1 << cfg.bits;
     const size_t Pp = P < kWave ? kWave : P;
-    size_t lds = sizeof(uint32_t) * (2 * Pp + kScanScratch) + sizeof(int32_t) * 2 * kPartBlock * IPT;
+    size_t lds = sizeof(uint32_t) * (2 * Pp + kScanScratch) + sizeof(int32_t) * 2 * BLOCK * IPT;
     if (side.kind == kSideSetup2) {
         // room for the pass-2 segment tile offsets (else the setup fills the tile map from HBM)
         const size_t want = sizeof(uint32_t) * (kScanScratch + 2 * ((size_t)1 << side.setup2.bits1) + 1);
         if (want > lds && want <= 65536) lds = want;
     }
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)k_part_scatter<IPT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)k_part_scatter<BLOCK, IPT>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
     rec.before("part_scatter");
-    hipLaunchKernelGGL(k_part_scatter<IPT>, dim3(grid + side.blocks), dim3(kPartBlock), lds, rec.stream, segs,
+    hipLaunchKernelGGL((k_part_scatter<BLOCK, IPT>), dim3(grid + side.blocks), dim3(BLOCK), lds, rec.stream, segs,
                        tile_begin, tile_seg, nseg, cfg, hist_scan, key_out, rid_out, side,
                        (uint32_t)(lds / sizeof(uint32_t)));
     rec.after();
@@ -345,11 +350,12 @@ void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, co
 void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
     if (grid == 0) return;
+    // workgroup size by tile: part_block()
     switch (cfg.tile) {
-        case 1024: launch_hist<4>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
-        case 2048: launch_hist<8>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
-        case 4096: launch_hist<16>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
-        default: launch_hist<32>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
+        case 1024: launch_hist<256, 4>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
+        case 2048: launch_hist<256, 8>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
+        case 4096: launch_hist<512, 8>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
+        default: launch_hist<512, 16>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
     }
 }
 
@@ -357,13 +363,13 @@ void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_
                   uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
                   int32_t* rid_out, const SideJob& side, Recorder& rec) {
     if (grid + side.blocks == 0) return;
-#define HJ_SCATTER(IPT) \
-    launch_scatter<IPT>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist_scan, key_out, rid_out, side, rec)
-    switch (cfg.tile) {
-        case 1024: HJ_SCATTER(4); break;
-        case 2048: HJ_SCATTER(8); break;
-        case 4096: HJ_SCATTER(16); break;
-        default: HJ_SCATTER(32); break;
+#define HJ_SCATTER(BLOCK, IPT) \
+    launch_scatter<BLOCK, IPT>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist_scan, key_out, rid_out, side, rec)
+    switch (cfg.tile) {  // workgroup size by tile: part_block()
+        case 1024: HJ_SCATTER(256, 4); break;
+        case 2048: HJ_SCATTER(256, 8); break;
+        case 4096: HJ_SCATTER(512, 8); break;
+        default: HJ_SCATTER(512, 16); break;
     }
 #undef HJ_SCATTER
 }

@@ -306,7 +306,7 @@ hj_status hj_server_submit(hj_server* sv, const hj_job* job, const hj_params* pa
         return fail(HJ_ERR_INVALID, "out has capacity but a NULL array");
     if (!job->d_count) return fail(HJ_ERR_INVALID, "d_count is NULL");
     Request r;
-    hj_status st = check_params(params, job->R.n, &r.plan);
+    hj_status st = check_params(params, job->R.n, job->S.n, &r.plan);
     if (st != HJ_OK) return st;
     r.job = *job;
     r.footprint = footprint;

@@ -34,7 +34,7 @@ HJ_BATCH_NO_GRAPH = 1
 
 # Every symbol include/hj.h declares.
 EXPORTED = (
-    "hj_default_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
+    "hj_default_params", "hj_resolve_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
     "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_run",
     "hj_batch_plan_destroy", "hj_server_create", "hj_server_submit", "hj_server_poll", "hj_server_drain",
     "hj_server_stats", "hj_server_destroy", "hj_status_str", "hj_last_error", "hj_version",
@@ -95,6 +95,8 @@ def load() -> ctypes.CDLL:
             vp = ctypes.c_void_p
             lib.hj_default_params.restype = None
             lib.hj_default_params.argtypes = [P(HjParams)]
+            lib.hj_resolve_params.restype = ctypes.c_int
+            lib.hj_resolve_params.argtypes = [P(HjParams), ctypes.c_uint64, ctypes.c_uint64, P(HjParams)]
             lib.hj_workspace_bytes.restype = ctypes.c_size_t
             lib.hj_workspace_bytes.argtypes = [P(HjParams), ctypes.c_uint64, ctypes.c_uint64]
             lib.hj_join.restype = ctypes.c_int
@@ -174,6 +176,13 @@ def params(algo: str = "phj", passes: int = 2, bits=(6, 6), hash: str = "identit
     p.lds_cap = lds_cap
     p.flags = HJ_FLAG_ONE_PASS if one_pass else 0
     return p
+
+
+def hj_resolve_params(p: HjParams, n_r: int, n_s: int) -> HjParams:
+    """The parameters as hj_join uses them for these sizes (tile, lds_cap filled in)."""
+    q = HjParams()
+    _check(load().hj_resolve_params(ctypes.byref(p), n_r, n_s, ctypes.byref(q)))
+    return q
 
 
 def hj_workspace_bytes(p: HjParams, n_r: int, n_s: int) -> int:

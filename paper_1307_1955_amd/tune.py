@@ -52,11 +52,11 @@ class Candidate:
     passes: int          # PHJ: 0 (direct), 1, 2
     bits: tuple = (0, 0)
     one_pass: bool = True
-    tile: int = 0        # partition tile (0: the library default, 4096)
+    tile: int = 0        # partition tile (0: 4096, the tile the stored table was measured with)
 
     def params(self):
         from . import hj
-        return hj.params(self.algo, self.passes, self.bits, tile=self.tile, one_pass=self.one_pass)
+        return hj.params(self.algo, self.passes, self.bits, tile=self.tile or 4096, one_pass=self.one_pass)
 
     def as_dict(self) -> dict:
         return {"algo": self.algo, "passes": self.passes, "bits": list(self.bits), "one_pass": self.one_pass,

@@ -53,6 +53,28 @@ def test_version_and_status_strings(hj):
 def test_default_params(hj):
     p = hj.hj_default_params()
     assert p.algo == hj.HJ_PHJ and p.passes == 2 and tuple(p.bits) == (6, 6) and p.flags == 0
+    assert p.tile == 0 and p.lds_cap == 0  # chosen from the sizes
+
+
+def test_resolve_params(hj):
+    p = hj.hj_default_params()
+    small = hj.hj_resolve_params(p, 1 << 22, 1 << 22)
+    big = hj.hj_resolve_params(p, 1 << 23, 1 << 23)
+    assert (small.tile, big.tile) == (4096, 8192)
+    for q in (small, big):
+        assert q.lds_cap % 64 == 0 and 256 <= q.lds_cap <= 8192
+        assert (q.algo, q.passes, tuple(q.bits), q.flags) == (p.algo, p.passes, tuple(p.bits), p.flags)
+        # the resolved parameters describe the same join: same workspace
+        assert hj.hj_workspace_bytes(q, 1 << 22, 1 << 22) > 0
+    assert hj.hj_workspace_bytes(big, 1 << 23, 1 << 23) == hj.hj_workspace_bytes(p, 1 << 23, 1 << 23)
+    assert hj.hj_workspace_bytes(small, 1 << 22, 1 << 22) == hj.hj_workspace_bytes(p, 1 << 22, 1 << 22)
+    # an explicit tile is kept
+    e = hj.hj_resolve_params(hj.params("phj", 2, (6, 6), tile=2048), 1 << 23, 1 << 23)
+    assert e.tile == 2048
+    d = hj.hj_resolve_params(hj.params("phj", 0, (0, 0)), 1000, 5000)
+    assert d.passes == 0 and d.lds_cap == 1024 and d.flags & hj.HJ_FLAG_ONE_PASS
+    with pytest.raises(hj.HJError):
+        hj.hj_resolve_params(hj.params("phj", 2, (6, 6), tile=3000), 10, 10)
 
 
 @pytest.mark.parametrize("kw", [

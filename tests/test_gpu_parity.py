@@ -59,6 +59,9 @@ CASES = [
     ("phj1_b4", dict(algo="phj", passes=1, bits=(4,))),
     ("phj1_b8_t1024", dict(algo="phj", passes=1, bits=(8,), tile=1024)),
     ("phj1_b13_t8192", dict(algo="phj", passes=1, bits=(13,), tile=8192)),
+    ("phj1_b10_t4096", dict(algo="phj", passes=1, bits=(10,), tile=4096)),
+    ("phj2_2_3_t8192", dict(algo="phj", passes=2, bits=(2, 3), tile=8192)),
+    ("phj2_6_6_t8192_1pass", dict(algo="phj", passes=2, bits=(6, 6), tile=8192, one_pass=True)),
     ("phj2_3_3", dict(algo="phj", passes=2, bits=(3, 3))),
     ("phj2_6_6", dict(algo="phj", passes=2, bits=(6, 6))),
     ("phj2_7_5_t2048", dict(algo="phj", passes=2, bits=(7, 5), tile=2048)),
@@ -132,6 +135,7 @@ def offset_view(a, off):
 @pytest.mark.parametrize("offs", [(1, 1, 3, 3), (1, 2, 0, 3), (3, 0, 2, 2)])
 @pytest.mark.parametrize("kw", [dict(algo="phj", passes=2, bits=(6, 6)), dict(algo="phj", passes=1, bits=(7,)),
                                 dict(algo="phj", passes=2, bits=(5, 4), one_pass=True, tile=1024),
+                                dict(algo="phj", passes=2, bits=(6, 5), tile=8192),
                                 dict(algo="shj")])
 def test_misaligned_columns(kw, offs):
     """Key and rid columns at different offsets inside 16-byte lines (vector and
