@@ -55,7 +55,11 @@ typedef enum hj_status {
     HJ_ERR_UNSUPPORTED = 5  /* a parameter combination this build does not implement */
 } hj_status;
 
-typedef enum hj_algo { HJ_SHJ = 0, HJ_PHJ = 1 } hj_algo;
+/* HJ_AUTO: the library picks PHJ parameters from |R| (no partitioning up to
+   4416 R tuples, else about 4096 R tuples per partition: one pass up to 6
+   radix bits, two passes above); hash, tile, lds_cap and flags are kept.
+   hj_resolve_params shows the choice. */
+typedef enum hj_algo { HJ_SHJ = 0, HJ_PHJ = 1, HJ_AUTO = 2 } hj_algo;
 
 /* Hash applied to a key before its radix bits are taken (Section 3.1 partitions
    on the low bits of the integer hash value).  The join result does not depend
@@ -90,7 +94,7 @@ typedef struct hj_out {
 #define HJ_FLAG_ONE_PASS 1u
 
 /* Join parameters.
-   algo    HJ_SHJ or HJ_PHJ.
+   algo    HJ_SHJ, HJ_PHJ or HJ_AUTO.
    passes  PHJ: number of radix passes, 1 or 2; or 0 = no partitioning, for
            |R| <= 8192: R is one LDS-resident table probed by every S chunk
            (ignored by SHJ).
@@ -153,6 +157,51 @@ hj_status hj_join_timed(const hj_params* p, const hj_rel* R, const hj_rel* S, co
                         const char** names, float* ms, uint32_t max_launches,
                         uint32_t* n_launches);
 
+/* ---- Build once, probe many times -----------------------------------------
+   The two phases of Algorithm 1 as separate calls: hj_build makes R's
+   build-side structure once, and any number of hj_probe calls join relations
+   S against it (concurrently too, each with its own workspace).  For SHJ the
+   table is the hash table over R (steps b1-b4); for PHJ with 1 or 2 passes it
+   is R partitioned with the radix passes of Algorithm 2 plus the range of
+   every partition, so a probe partitions only S and joins the partition
+   pairs (each R partition's LDS table is rebuilt inside the join kernel, as
+   in hj_join); for PHJ with passes 0 nothing is stored and probes read R.
+   The result of a probe is the result hj_join would give for (R, S) with the
+   table's parameters. */
+
+/* A table over R, filled in by hj_build.  The caller keeps the structure, its
+   build workspace and (for SHJ and for PHJ with passes 0) R's arrays alive
+   and unmodified while probes may use it. */
+typedef struct hj_table {
+    hj_params params;      /* as run: HJ_AUTO and the size-dependent choices resolved */
+    uint64_t n_r;          /* tuples of R */
+    const int32_t* r_key;  /* R's columns as given to hj_build (SHJ probes read */
+    const int32_t* r_rid;  /*   r_rid; PHJ probes with passes 0 read both) */
+    void* ws;              /* the build workspace that holds the table */
+    size_t ws_bytes;
+} hj_table;
+
+/* Bytes of device workspace hj_build needs for a table over n_r tuples (the
+   table lives there).  0 if the parameters are invalid. */
+size_t hj_table_bytes(const hj_params* p, uint64_t n_r);
+
+/* Builds the table over R into ws (256-byte aligned, >= hj_table_bytes) and
+   fills *table.  Size-dependent parameters (tile 0, lds_cap 0, HJ_AUTO) are
+   chosen from |R| alone.  Asynchronous on `stream`; probes must be ordered
+   after it (same stream, or an event). */
+hj_status hj_build(const hj_params* p, const hj_rel* R, void* ws, size_t ws_bytes, void* stream,
+                   hj_table* table);
+
+/* Bytes of device workspace hj_probe needs for a probe of n_s tuples. */
+size_t hj_probe_workspace_bytes(const hj_table* table, uint64_t n_s);
+
+/* Joins S against the table: output, count and capacity behaviour as in
+   hj_join.  ws: >= hj_probe_workspace_bytes(table, S->n) bytes, 256-byte
+   aligned, not used by any other call in flight (the table itself is only
+   read).  Asynchronous on `stream`. */
+hj_status hj_probe(const hj_table* table, const hj_rel* S, const hj_out* out, void* ws, size_t ws_bytes,
+                   uint64_t* d_count, void* stream);
+
 /* ---- Batched joins ------------------------------------------------------
    Many independent joins of uneven sizes enqueued together.  A plan fixes the
    jobs (pointers and sizes) and the per-job parameters; running it enqueues
@@ -197,6 +246,13 @@ uint32_t hj_batch_direct_jobs(const hj_batch_plan* plan);
 hj_status hj_batch_run(hj_batch_plan* plan, void* ws, size_t ws_bytes, void* stream);
 
 void hj_batch_plan_destroy(hj_batch_plan* plan);
+
+/* One-shot batch: the plan of hj_batch_plan_create run once without a graph
+   (params as there), then freed.  Synchronises `stream` before returning.
+   ws: >= hj_batch_bytes(njobs, jobs, params) bytes, 256-byte aligned. */
+size_t hj_batch_bytes(uint32_t njobs, const hj_job* jobs, const hj_params* params);
+hj_status hj_batch(uint32_t njobs, const hj_job* jobs, const hj_params* params, void* ws, size_t ws_bytes,
+                   void* stream);
 
 /* ---- Serving ------------------------------------------------------------
    A server accepts join requests as they arrive (from any thread) and runs

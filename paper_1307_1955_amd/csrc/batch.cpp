@@ -34,9 +34,6 @@ using namespace hj::eng;
 namespace {
 
 constexpr uint32_t kLanes = 4;
-// Largest |R| the size rule sends to the multi-job direct kernel, and the LDS
-// capacity that kernel is launched with (three workgroups per CU).
-constexpr uint32_t kDirectCap = 4416;
 
 struct LaneJob {
     uint32_t job;
@@ -72,25 +69,11 @@ struct hj_batch_plan {
 
 namespace {
 
+// The size rule (HJ_AUTO's) with one-pass output.
 void default_params(const hj_job& j, hj_params* p) {
     hj_default_params(p);
     p->flags = HJ_FLAG_ONE_PASS;
-    if (j.R.n <= kDirectCap) {
-        p->algo = HJ_PHJ;
-        p->passes = 0;
-        return;
-    }
-    uint32_t B = 0;
-    while (B < 16 && (j.R.n >> B) > 4096) ++B;
-    if (B <= 6) {
-        p->passes = 1;
-        p->bits[0] = B;
-        p->bits[1] = 0;
-    } else {
-        p->passes = 2;
-        p->bits[0] = (B + 1) / 2;
-        p->bits[1] = B / 2;
-    }
+    auto_params(j.R.n, p);
 }
 
 void free_plan(hj_batch_plan* b) {
@@ -161,10 +144,50 @@ hj_status enqueue(hj_batch_plan* b, char* ws, hipStream_t stream) {
 
 }  // namespace
 
+namespace {
+// Plans the batch; sizing_only: stops after the workspace layout (no pinned
+// staging, streams or events).
+hj_status create_plan(uint32_t njobs, const hj_job* jobs, const hj_params* params, uint32_t flags,
+                      bool sizing_only, hj_batch_plan** plan);
+}  // namespace
+
 extern "C" {
 
 hj_status hj_batch_plan_create(uint32_t njobs, const hj_job* jobs, const hj_params* params, uint32_t flags,
                                hj_batch_plan** plan) {
+    return create_plan(njobs, jobs, params, flags, false, plan);
+}
+
+size_t hj_batch_bytes(uint32_t njobs, const hj_job* jobs, const hj_params* params) {
+    hj_batch_plan* b = nullptr;
+    if (create_plan(njobs, jobs, params, HJ_BATCH_NO_GRAPH, true, &b) != HJ_OK) return 0;
+    const size_t n = b->ws_bytes;
+    free_plan(b);
+    clear_error();
+    return n;
+}
+
+hj_status hj_batch(uint32_t njobs, const hj_job* jobs, const hj_params* params, void* ws, size_t ws_bytes,
+                   void* stream) {
+    hj_batch_plan* b = nullptr;
+    hj_status st = create_plan(njobs, jobs, params, HJ_BATCH_NO_GRAPH, false, &b);
+    if (st != HJ_OK) return st;
+    st = hj_batch_run(b, ws, ws_bytes, stream);
+    // the job table is copied from the plan's pinned staging: wait before freeing it
+    const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    free_plan(b);
+    if (st != HJ_OK) return st;
+    if (e != hipSuccess) return fail(HJ_ERR_DEVICE, "batch failed: %s", hipGetErrorString(e));
+    clear_error();
+    return HJ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hj_status create_plan(uint32_t njobs, const hj_job* jobs, const hj_params* params, uint32_t flags,
+                      bool sizing_only, hj_batch_plan** plan) {
     if (!plan) return fail(HJ_ERR_INVALID, "plan is NULL");
     *plan = nullptr;
     if (njobs && !jobs) return fail(HJ_ERR_INVALID, "jobs is NULL");
@@ -208,7 +231,7 @@ hj_status hj_batch_plan_create(uint32_t njobs, const hj_job* jobs, const hj_para
         return fail(HJ_ERR_INVALID, "too many direct work items");
     }
     b->direct_items = (uint32_t)items;
-    if (b->ndirect) {
+    if (b->ndirect && !sizing_only) {
         hipError_t e = hipHostMalloc((void**)&b->h_djobs, sizeof(hj::DirectJob) * b->ndirect, hipHostMallocDefault);
         if (e == hipSuccess && b->direct_items)
             e = hipHostMalloc((void**)&b->h_item_job, sizeof(uint32_t) * b->direct_items, hipHostMallocDefault);
@@ -262,6 +285,10 @@ hj_status hj_batch_plan_create(uint32_t njobs, const hj_job* jobs, const hj_para
         off += align_up(b->lane_bytes[l]);
     }
     b->ws_bytes = off;
+    if (sizing_only) {
+        *plan = b;
+        return HJ_OK;
+    }
     // lane streams and events (default priority)
     hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
@@ -277,6 +304,10 @@ hj_status hj_batch_plan_create(uint32_t njobs, const hj_job* jobs, const hj_para
     clear_error();
     return HJ_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 size_t hj_batch_workspace_bytes(const hj_batch_plan* plan) { return plan ? plan->ws_bytes : 0; }
 

@@ -89,8 +89,49 @@ uint32_t auto_lds_cap(uint64_t n_r, uint32_t P) {
     return cap;
 }
 
+void auto_params(uint64_t n_r, hj_params* p) {
+    p->algo = HJ_PHJ;
+    if (n_r <= kAutoDirectMax) {
+        p->passes = 0;
+        p->bits[0] = p->bits[1] = 0;
+        return;
+    }
+    uint32_t B = 0;
+    while (B < 16 && (n_r >> B) > 4096) ++B;
+    if (B <= 6) {
+        p->passes = 1;
+        p->bits[0] = B;
+        p->bits[1] = 0;
+    } else {
+        p->passes = 2;
+        p->bits[0] = (B + 1) / 2;
+        p->bits[1] = B / 2;
+    }
+}
+
+namespace {
+// The parameters a plan runs with, every size-dependent choice filled in.
+void fill_resolved(const hj_params* p, Plan* pl) {
+    hj_params& r = pl->res;
+    r = *p;
+    r.algo = pl->phj ? HJ_PHJ : HJ_SHJ;
+    r.tile = pl->tile;
+    if (!pl->phj) return;
+    r.passes = pl->passes;
+    r.bits[0] = pl->b1;
+    r.bits[1] = pl->b2;
+    r.lds_cap = pl->lds_cap;
+    if (pl->one_pass) r.flags |= HJ_FLAG_ONE_PASS;
+}
+}  // namespace
+
 hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl) {
     if (!p) return fail(HJ_ERR_INVALID, "params is NULL");
+    if (p->algo == HJ_AUTO) {
+        hj_params q = *p;
+        auto_params(n_r, &q);
+        return check_params(&q, n_r, n_s, pl);
+    }
     if (p->flags & ~HJ_FLAG_ONE_PASS) return fail(HJ_ERR_INVALID, "unknown flags 0x%x", p->flags);
     if (p->algo != HJ_SHJ && p->algo != HJ_PHJ) return fail(HJ_ERR_INVALID, "unknown algo %u", p->algo);
     if (p->hash != HJ_HASH_IDENTITY && p->hash != HJ_HASH_MURMUR2)
@@ -106,7 +147,10 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
     pl->b1 = pl->b2 = pl->B = 0;
     pl->P1 = pl->P2 = pl->P = 1;
     pl->lds_cap = 0;
-    if (!pl->phj) return HJ_OK;
+    if (!pl->phj) {
+        fill_resolved(p, pl);
+        return HJ_OK;
+    }
     if (p->passes == 0) {
         // no partitioning: R must fit one LDS table
         if (n_r > hj::kMaxLdsCap)
@@ -117,6 +161,7 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
         const uint32_t need = (uint32_t)std::max<uint64_t>(256, (n_r + 63) / 64 * 64);
         pl->lds_cap = p->lds_cap ? std::max(p->lds_cap, need) : need;
         if (pl->lds_cap > hj::kMaxLdsCap) return fail(HJ_ERR_INVALID, "lds_cap above %u", hj::kMaxLdsCap);
+        fill_resolved(p, pl);
         return HJ_OK;
     }
     if (p->passes != 1 && p->passes != 2)
@@ -140,6 +185,7 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
     } else {
         pl->lds_cap = auto_lds_cap(n_r, pl->P);
     }
+    fill_resolved(p, pl);
     return HJ_OK;
 }
 
@@ -171,7 +217,10 @@ struct PhjWs {
     size_t bytes;
 };
 
-PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, void* base) {
+// n_r, n_s: tuples partitioned by this call (either may be 0 for a table
+// build or a probe); n_r_tab: tuples of the R that is joined (sizes the HBM
+// tables of oversized R partitions).
+PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, void* base) {
     PhjWs w{};
     Carver c(base);
     const uint64_t n = n_r + n_s;
@@ -194,12 +243,12 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, void* base) {
     w.item_begin = c.take<uint32_t>(pl.P + 1ull);
     w.ovf_begin = c.take<uint32_t>(pl.P + 1ull);
     w.items_ub = hj::join_grid(pl.P, n_s);
-    w.ovf_ub = hj::ovf_grid(pl.P, n_r);
+    w.ovf_ub = hj::ovf_grid(pl.P, n_r_tab);
     w.item_part = c.take<uint32_t>(w.items_ub);
     w.ovf_part = c.take<uint32_t>(w.ovf_ub);
     w.wave_cnt = c.take<uint64_t>(w.items_ub * hj::kJoinWaves);
-    w.ovf_table = c.take<uint64_t>(2 * n_r);
-    w.ovf_next = c.take<uint32_t>(n_r);
+    w.ovf_table = c.take<uint64_t>(2 * n_r_tab);
+    w.ovf_next = c.take<uint32_t>(n_r_tab);
     const uint64_t n1 = hj::scan_state_words(w.tiles1 * pl.P1);
     const uint64_t n2 = pl.passes == 2 ? hj::scan_state_words(w.tiles2_ub * pl.P2) : 0;
     const uint64_t nw = hj::scan_state_words(w.items_ub * hj::kJoinWaves);
@@ -213,29 +262,45 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, void* base) {
     return w;
 }
 
-struct ShjWs {
+// SHJ: the table over R (slots and row chains), then the probe's per-wave counts.
+struct ShjTableWs {
     uint64_t* table;
     uint32_t* next;
-    uint64_t* wave_cnt;
-    uint64_t* st;  // scan state of the per-wave counts
-    uint64_t nst;
     uint32_t log2_slots;
-    uint64_t tiles;
     size_t bytes;
 };
 
-ShjWs shj_layout(uint64_t n_r, uint64_t n_s, void* base) {
-    ShjWs w{};
+ShjTableWs shj_table_layout(uint64_t n_r, void* base) {
+    ShjTableWs w{};
     Carver c(base);
     w.log2_slots = std::max<uint32_t>(1, ceil_log2(2 * std::max<uint64_t>(n_r, 1)));
     w.table = c.take<uint64_t>(1ull << w.log2_slots);
     w.next = c.take<uint32_t>(n_r);
+    w.bytes = c.off;
+    return w;
+}
+
+struct ShjProbeWs {
+    uint64_t* wave_cnt;
+    uint64_t* st;  // scan state of the per-wave counts
+    uint64_t nst;
+    uint64_t tiles;
+    size_t bytes;
+};
+
+ShjProbeWs shj_probe_layout(uint64_t n_s, void* base) {
+    ShjProbeWs w{};
+    Carver c(base);
     w.tiles = cdiv(n_s, hj::kShjTile);
     w.wave_cnt = c.take<uint64_t>(w.tiles * hj::kShjWavesPerBlock);
     w.nst = hj::scan_state_words(w.tiles * hj::kShjWavesPerBlock);
     w.st = c.take<uint64_t>(w.nst);
     w.bytes = c.off;
     return w;
+}
+
+size_t shj_bytes(uint64_t n_r, uint64_t n_s) {
+    return shj_table_layout(n_r, nullptr).bytes + shj_probe_layout(n_s, nullptr).bytes;
 }
 
 // Direct join (PHJ with no partitioning pass): one job descriptor and the item map.
@@ -258,7 +323,17 @@ DirectWs direct_layout(uint64_t n_s, void* base) {
 
 size_t ws_bytes_for(const Plan& pl, uint64_t n_r, uint64_t n_s) {
     if (pl.phj && pl.passes == 0) return direct_layout(n_s, nullptr).bytes;
-    return pl.phj ? phj_layout(pl, n_r, n_s, nullptr).bytes : shj_layout(n_r, n_s, nullptr).bytes;
+    return pl.phj ? phj_layout(pl, n_r, n_s, n_r, nullptr).bytes : shj_bytes(n_r, n_s);
+}
+
+size_t table_bytes_for(const Plan& pl, uint64_t n_r) {
+    if (pl.phj && pl.passes == 0) return kAlign;  // the table is R itself (nothing is stored)
+    return pl.phj ? phj_layout(pl, n_r, 0, 0, nullptr).bytes : shj_table_layout(n_r, nullptr).bytes;
+}
+
+size_t probe_bytes_for(const Plan& pl, uint64_t n_r, uint64_t n_s) {
+    if (pl.phj && pl.passes == 0) return direct_layout(n_s, nullptr).bytes;
+    return pl.phj ? phj_layout(pl, 0, n_s, n_r, nullptr).bytes : shj_probe_layout(n_s, nullptr).bytes;
 }
 
 void run_direct(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
@@ -299,23 +374,39 @@ hj_status check_call(const hj_params* p, const hj_rel* R, const hj_rel* S, const
     return HJ_OK;
 }
 
-void run_shj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
-             uint64_t* d_count, hj::Recorder& rec) {
-    ShjWs w = shj_layout(R.n, S.n, ws);
-    hj::shj_fill(w.table, 1ull << w.log2_slots, pl.one_pass ? d_count : nullptr, rec);
-    hj::shj_build(R.key, R.n, w.table, w.next, w.log2_slots, rec);
+// SHJ build (Algorithm 1, b1-b4): empty slots, then R inserted.
+// zero_total (optional) is cleared by the fill.
+void shj_build_table(const hj_rel& R, const ShjTableWs& t, uint64_t* zero_total, hj::Recorder& rec) {
+    hj::shj_fill(t.table, 1ull << t.log2_slots, zero_total, rec);
+    hj::shj_build(R.key, R.n, t.table, t.next, t.log2_slots, rec);
+}
+
+// SHJ probe (Algorithm 1, p1-p4) of a built table; r_rid: R's rid column.
+void shj_probe_table(const Plan& pl, const ShjTableWs& t, const int32_t* r_rid, const hj_rel& S,
+                     const hj_out& out, const ShjProbeWs& w, uint64_t* d_count, hj::Recorder& rec) {
     if (!pl.one_pass) {
-        hj::shj_count(S.key, S.n, w.table, w.next, w.log2_slots, w.wave_cnt, rec);
+        hj::shj_count(S.key, S.n, t.table, t.next, t.log2_slots, w.wave_cnt, rec);
         hj::zero_words(w.st, w.nst, rec);
         hj::scan_u64(w.wave_cnt, w.wave_cnt, w.tiles * hj::kShjWavesPerBlock, w.st, d_count, rec);
     }
-    hj::shj_write(S.key, S.rid, S.n, w.table, w.next, w.log2_slots, R.rid, pl.one_pass ? nullptr : w.wave_cnt,
+    hj::shj_write(S.key, S.rid, S.n, t.table, t.next, t.log2_slots, r_rid, pl.one_pass ? nullptr : w.wave_cnt,
                   d_count, out.rid_r, out.rid_s, out.capacity, rec);
 }
 
-void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
+void run_shj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
              uint64_t* d_count, hj::Recorder& rec) {
-    PhjWs w = phj_layout(pl, R.n, S.n, ws);
+    const ShjTableWs t = shj_table_layout(R.n, ws);
+    const ShjProbeWs w = shj_probe_layout(S.n, (char*)ws + t.bytes);
+    shj_build_table(R, t, pl.one_pass ? d_count : nullptr, rec);
+    shj_probe_table(pl, t, R.rid, S, out, w, d_count, rec);
+}
+
+// PHJ partitioning (Algorithm 2, n1-n3) of R and S (either may be empty) into
+// w, with the join plan of the partition pairs riding on the last scatter.
+// r_pairs: R's partition ranges from a built table (R is then empty here).
+// The partitioned arrays are returned in *fk / *fr (R first, S from n_r on).
+void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs& w, const hj::PartPair* r_pairs,
+                   uint64_t* zero_total, int32_t** fk, int32_t** fr, hj::Recorder& rec) {
     const uint32_t n_r = (uint32_t)R.n, n_s = (uint32_t)S.n;
     const bool two = pl.passes == 2;
     hj::part_setup_pass1(w.segs1, w.tb1, R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, w.st1, w.nzero,
@@ -326,8 +417,8 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
     plan.blocks = hj::plan_blocks(pl.P, hj::part_block(pl.tile));
     plan.plan = hj::PlanArgs{two ? w.segs2 : w.segs1, two ? w.tb2 : w.tb1, two ? w.hist2 : w.hist1,
                              two ? 2 * pl.P1 : 2u, two ? pl.b2 : pl.b1, n_r, n_s, pl.B, pl.lds_cap,
-                             w.pairs, w.item_begin, w.ovf_begin, w.item_part, w.ovf_part,
-                             pl.one_pass ? d_count : nullptr, w.stp};
+                             w.pairs, w.item_begin, w.ovf_begin, w.item_part, w.ovf_part, zero_total, w.stp,
+                             r_pairs};
     hj::SideJob setup2{};
     if (two) {
         setup2.kind = hj::kSideSetup2;
@@ -340,26 +431,42 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
     hj::scan_u32(w.hist1, w.hist1, w.tiles1 * pl.P1, w.st1, nullptr, rec);
     hj::part_scatter(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, w.keyA, w.ridA,
                      two ? setup2 : plan, rec);
-    int32_t *fk = w.keyA, *fr = w.ridA;
+    *fk = w.keyA;
+    *fr = w.ridA;
     if (two) {
         hj::PassCfg c2{0, pl.b2, pl.hash, pl.tile};
         hj::part_hist(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, rec);
         hj::scan_u32(w.hist2, w.hist2, w.tiles2_ub * pl.P2, w.st2, nullptr, rec);
         hj::part_scatter(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, w.keyB,
                          w.ridB, plan, rec);
-        fk = w.keyB;
-        fr = w.ridB;
+        *fk = w.keyB;
+        *fr = w.ridB;
     }
-    hj::join_ovf_build(w.pairs, w.ovf_begin, w.ovf_part, pl.P, (uint32_t)w.ovf_ub, fk, w.ovf_table, w.ovf_next,
+}
+
+// PHJ join of the planned partition pairs (Algorithm 1 per pair): HBM tables
+// for oversized R partitions, then count -> scan -> write (or one-pass write).
+// rk/rr: partitioned R, sk/sr: partitioned S.
+void phj_join_pairs(const Plan& pl, const PhjWs& w, const int32_t* rk, const int32_t* rr, const int32_t* sk,
+                    const int32_t* sr, const hj_out& out, uint64_t* d_count, hj::Recorder& rec) {
+    hj::join_ovf_build(w.pairs, w.ovf_begin, w.ovf_part, pl.P, (uint32_t)w.ovf_ub, rk, w.ovf_table, w.ovf_next,
                        rec);
     if (!pl.one_pass) {
-        hj::join_count(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, fk, fk + n_r, pl.lds_cap,
+        hj::join_count(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, rk, sk, pl.lds_cap,
                        w.ovf_table, w.ovf_next, w.wave_cnt, rec);
         hj::scan_u64(w.wave_cnt, w.wave_cnt, w.items_ub * hj::kJoinWaves, w.stw, d_count, rec);
     }
-    hj::join_write(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, fk, fr, fk + n_r, fr + n_r,
-                   pl.lds_cap, w.ovf_table, w.ovf_next, pl.one_pass ? nullptr : w.wave_cnt, d_count,
-                   out.rid_r, out.rid_s, out.capacity, rec);
+    hj::join_write(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, rk, rr, sk, sr, pl.lds_cap,
+                   w.ovf_table, w.ovf_next, pl.one_pass ? nullptr : w.wave_cnt, d_count, out.rid_r, out.rid_s,
+                   out.capacity, rec);
+}
+
+void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
+             uint64_t* d_count, hj::Recorder& rec) {
+    const PhjWs w = phj_layout(pl, R.n, S.n, R.n, ws);
+    int32_t *fk, *fr;
+    phj_partition(pl, R, S, w, nullptr, pl.one_pass ? d_count : nullptr, &fk, &fr, rec);
+    phj_join_pairs(pl, w, fk, fr, fk + R.n, fr + R.n, out, d_count, rec);
 }
 
 void run_join(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
@@ -372,6 +479,42 @@ void run_join(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& ou
         run_phj(pl, R, S, out, ws, d_count, rec);
     } else {
         run_shj(pl, R, S, out, ws, d_count, rec);
+    }
+}
+
+void run_build(const Plan& pl, const hj_rel& R, void* ws, hj::Recorder& rec) {
+    if (R.n == 0 || (pl.phj && pl.passes == 0)) return;  // passes 0: the table is R itself
+    if (!pl.phj) {
+        shj_build_table(R, shj_table_layout(R.n, ws), nullptr, rec);
+        return;
+    }
+    const PhjWs w = phj_layout(pl, R.n, 0, 0, ws);
+    const hj_rel none{nullptr, nullptr, 0};
+    int32_t *fk, *fr;
+    phj_partition(pl, R, none, w, nullptr, nullptr, &fk, &fr, rec);
+}
+
+void run_probe(const Plan& pl, const hj_table& t, const hj_rel& S, const hj_out& out, void* ws,
+               uint64_t* d_count, hj::Recorder& rec) {
+    const hj_rel R{t.r_key, t.r_rid, t.n_r};
+    if (t.n_r == 0 || S.n == 0) {
+        hj::write_zero_count(d_count, rec);
+    } else if (pl.phj && pl.passes == 0) {
+        run_direct(pl, R, S, out, ws, d_count, rec);
+    } else if (!pl.phj) {
+        const ShjTableWs tw = shj_table_layout(t.n_r, t.ws);
+        const ShjProbeWs w = shj_probe_layout(S.n, ws);
+        if (pl.one_pass) hj::write_zero_count(d_count, rec);
+        shj_probe_table(pl, tw, t.r_rid, S, out, w, d_count, rec);
+    } else {
+        // R's partitions and pair ranges are in the table; only S is partitioned here
+        const PhjWs tw = phj_layout(pl, t.n_r, 0, 0, t.ws);
+        const PhjWs w = phj_layout(pl, 0, S.n, t.n_r, ws);
+        const hj_rel none{nullptr, nullptr, 0};
+        int32_t *fk, *fr;
+        phj_partition(pl, none, S, w, tw.pairs, pl.one_pass ? d_count : nullptr, &fk, &fr, rec);
+        const bool two = pl.passes == 2;
+        phj_join_pairs(pl, w, two ? tw.keyB : tw.keyA, two ? tw.ridB : tw.ridA, fk, fr, out, d_count, rec);
     }
 }
 

@@ -27,7 +27,16 @@ uint64_t cdiv(uint64_t a, uint64_t b);
 struct Plan {
     bool phj, one_pass;
     uint32_t passes, b1, b2, B, P1, P2, P, tile, hash, lds_cap;
+    hj_params res;  // the parameters as run (HJ_AUTO and size-dependent choices resolved)
 };
+
+// HJ_AUTO: the largest |R| joined from one LDS table without partitioning
+// (the direct kernel then runs three workgroups per CU).
+constexpr uint32_t kAutoDirectMax = 4416;
+// The size rule of HJ_AUTO: PHJ with no partitioning up to kAutoDirectMax R
+// tuples, else about 4096 R tuples per partition (one pass up to 6 radix bits,
+// two passes above).  Keeps hash, tile, lds_cap and flags.
+void auto_params(uint64_t n_r, hj_params* p);
 
 // Default LDS table capacity for |R| = n_r split into P partitions.
 uint32_t auto_lds_cap(uint64_t n_r, uint32_t P);
@@ -35,6 +44,14 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
 hj_status check_call(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,
                      size_t ws_bytes, uint64_t* d_count, Plan* pl);
 size_t ws_bytes_for(const Plan& pl, uint64_t n_r, uint64_t n_s);
+// Split join (hj_build / hj_probe): build and probe workspace bytes.
+size_t table_bytes_for(const Plan& pl, uint64_t n_r);
+size_t probe_bytes_for(const Plan& pl, uint64_t n_r, uint64_t n_s);
+// Enqueues the build of R's table into ws (table_bytes_for bytes).
+void run_build(const Plan& pl, const hj_rel& R, void* ws, Recorder& rec);
+// Enqueues a probe of table t (built with plan pl) by S.
+void run_probe(const Plan& pl, const hj_table& t, const hj_rel& S, const hj_out& out, void* ws,
+               uint64_t* d_count, Recorder& rec);
 
 // Enqueues one validated join on rec.stream (ws must hold ws_bytes_for bytes).
 void run_join(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,

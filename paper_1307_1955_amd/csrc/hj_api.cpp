@@ -69,13 +69,98 @@ hj_status hj_resolve_params(const hj_params* p, uint64_t n_r, uint64_t n_s, hj_p
     const hj_status st = check_params(p, n_r, n_s, &pl);
     if (st != HJ_OK) return st;
     if (n_r > kMaxRows || n_s > kMaxRows) return fail(HJ_ERR_INVALID, "relations must have fewer than 2^31 tuples");
-    *out = *p;
-    if (pl.phj) {
-        out->passes = pl.passes;
-        out->tile = pl.tile;
-        out->lds_cap = pl.lds_cap;
-        if (pl.passes == 0) out->flags |= HJ_FLAG_ONE_PASS;
+    *out = pl.res;
+    clear_error();
+    return HJ_OK;
+}
+
+size_t hj_table_bytes(const hj_params* p, uint64_t n_r) {
+    Plan pl;
+    if (check_params(p, n_r, n_r, &pl) != HJ_OK) return 0;
+    if (n_r > kMaxRows) {
+        fail(HJ_ERR_INVALID, "relations must have fewer than 2^31 tuples");
+        return 0;
     }
+    return table_bytes_for(pl, n_r);
+}
+
+hj_status hj_build(const hj_params* p, const hj_rel* R, void* ws, size_t ws_bytes, void* stream,
+                   hj_table* table) {
+    if (!R || !table) return fail(HJ_ERR_INVALID, "R and table must not be NULL");
+    Plan pl;
+    hj_status st = check_params(p, R->n, R->n, &pl);
+    if (st != HJ_OK) return st;
+    if (R->n > kMaxRows) return fail(HJ_ERR_INVALID, "relations must have fewer than 2^31 tuples");
+    if (R->n && (!R->key || !R->rid)) return fail(HJ_ERR_INVALID, "R has tuples but a NULL array");
+    const size_t need = table_bytes_for(pl, R->n);
+    if (!ws || ws_bytes < need)
+        return fail(HJ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
+    if ((uintptr_t)ws % kAlign) return fail(HJ_ERR_INVALID, "workspace must be 256-byte aligned");
+    hj::Recorder rec;
+    rec.stream = (hipStream_t)stream;
+    (void)hipGetLastError();
+    run_build(pl, *R, ws, rec);
+    if (rec.err != hipSuccess) return fail(HJ_ERR_DEVICE, "launch failed: %s", hipGetErrorString(rec.err));
+    hj_table t{};
+    t.params = pl.res;
+    t.n_r = R->n;
+    t.r_key = R->key;
+    t.r_rid = R->rid;
+    t.ws = ws;
+    t.ws_bytes = ws_bytes;
+    *table = t;
+    clear_error();
+    return HJ_OK;
+}
+
+namespace {
+// The plan a table was built with, after checking the table's own fields.
+hj_status table_plan(const hj_table* t, uint64_t n_s, Plan* pl) {
+    if (!t) return fail(HJ_ERR_INVALID, "table is NULL");
+    if (t->n_r > kMaxRows) return fail(HJ_ERR_INVALID, "table: relations must have fewer than 2^31 tuples");
+    hj_status st = check_params(&t->params, t->n_r, n_s, pl);
+    if (st != HJ_OK) return st;
+    if (t->params.algo == HJ_AUTO || (pl->phj && t->params.tile == 0))
+        return fail(HJ_ERR_INVALID, "table parameters are not the ones hj_build filled in");
+    if (!t->ws || t->ws_bytes < table_bytes_for(*pl, t->n_r))
+        return fail(HJ_ERR_INVALID, "table: build workspace missing or too small");
+    const bool reads_r = !pl->phj || pl->passes == 0;
+    if (t->n_r && reads_r && (!t->r_rid || (pl->phj && !t->r_key)))
+        return fail(HJ_ERR_INVALID, "table: R's arrays are needed by this probe");
+    return HJ_OK;
+}
+}  // namespace
+
+size_t hj_probe_workspace_bytes(const hj_table* table, uint64_t n_s) {
+    Plan pl;
+    if (table_plan(table, n_s, &pl) != HJ_OK) return 0;
+    if (n_s > kMaxRows) {
+        fail(HJ_ERR_INVALID, "relations must have fewer than 2^31 tuples");
+        return 0;
+    }
+    return probe_bytes_for(pl, table->n_r, n_s);
+}
+
+hj_status hj_probe(const hj_table* table, const hj_rel* S, const hj_out* out, void* ws, size_t ws_bytes,
+                   uint64_t* d_count, void* stream) {
+    if (!S || !out) return fail(HJ_ERR_INVALID, "S and out must not be NULL");
+    Plan pl;
+    hj_status st = table_plan(table, S->n, &pl);
+    if (st != HJ_OK) return st;
+    if (S->n > kMaxRows) return fail(HJ_ERR_INVALID, "relations must have fewer than 2^31 tuples");
+    if (S->n && (!S->key || !S->rid)) return fail(HJ_ERR_INVALID, "S has tuples but a NULL array");
+    if (out->capacity && (!out->rid_r || !out->rid_s))
+        return fail(HJ_ERR_INVALID, "out has capacity but a NULL array");
+    if (!d_count) return fail(HJ_ERR_INVALID, "d_count is NULL");
+    const size_t need = probe_bytes_for(pl, table->n_r, S->n);
+    if (!ws || ws_bytes < need)
+        return fail(HJ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
+    if ((uintptr_t)ws % kAlign) return fail(HJ_ERR_INVALID, "workspace must be 256-byte aligned");
+    hj::Recorder rec;
+    rec.stream = (hipStream_t)stream;
+    (void)hipGetLastError();
+    run_probe(pl, *table, *S, *out, ws, d_count, rec);
+    if (rec.err != hipSuccess) return fail(HJ_ERR_DEVICE, "launch failed: %s", hipGetErrorString(rec.err));
     clear_error();
     return HJ_OK;
 }

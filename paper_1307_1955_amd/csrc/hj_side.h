@@ -39,6 +39,9 @@ struct PlanArgs {
     uint32_t* ovf_part;
     uint64_t* zero_total;
     uint64_t* state;
+    // R's partition ranges from an earlier build (hj_build); nullptr: from the
+    // histogram scan like S's
+    const PartPair* r_pairs;
 };
 
 enum SideKind : uint32_t { kSideNone = 0, kSideSetup2 = 1, kSidePlan = 2 };
@@ -108,13 +111,19 @@ __device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
     PartPair pp{0, 0, 0, 0};
     uint32_t ni = 0, no = 0;
     if (i < P) {
-        const uint32_t r0 = min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i, n_r, 0, P), n_r);
         const uint32_t s0 = min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i, n_s, n_r, P), n_s);
         // clamped: a partition never extends past its relation or runs backwards
-        const uint32_t r1 = max(r0, min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i + 1, n_r, 0, P), n_r));
         const uint32_t s1 = max(s0, min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i + 1, n_s, n_r, P), n_s));
-        pp.r_off = r0;
-        pp.r_len = r1 - r0;
+        if (A.r_pairs) {
+            const PartPair q = A.r_pairs[i];
+            pp.r_off = q.r_off;
+            pp.r_len = q.r_len;
+        } else {
+            const uint32_t r0 = min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i, n_r, 0, P), n_r);
+            const uint32_t r1 = max(r0, min(final_start(segs, tile_begin, hist_scan, 0, nseg_rel, bits_last, i + 1, n_r, 0, P), n_r));
+            pp.r_off = r0;
+            pp.r_len = r1 - r0;
+        }
         pp.s_off = s0;
         pp.s_len = s1 - s0;
         ni = items_of(pp);

@@ -26,6 +26,7 @@ HJ_ERR_UNSUPPORTED = 5
 
 HJ_SHJ = 0
 HJ_PHJ = 1
+HJ_AUTO = 2
 HJ_HASH_IDENTITY = 0
 HJ_HASH_MURMUR2 = 1
 HJ_FLAG_ONE_PASS = 1
@@ -36,7 +37,8 @@ HJ_BATCH_NO_GRAPH = 1
 EXPORTED = (
     "hj_default_params", "hj_resolve_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
     "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_run",
-    "hj_batch_plan_destroy", "hj_server_create", "hj_server_submit", "hj_server_poll", "hj_server_drain",
+    "hj_batch_plan_destroy", "hj_batch_bytes", "hj_batch", "hj_table_bytes", "hj_build",
+    "hj_probe_workspace_bytes", "hj_probe", "hj_server_create", "hj_server_submit", "hj_server_poll", "hj_server_drain",
     "hj_server_stats", "hj_server_destroy", "hj_status_str", "hj_last_error", "hj_version",
 )
 
@@ -58,8 +60,13 @@ class HjParams(ctypes.Structure):
 
     def __repr__(self) -> str:
         return ("HjParams(algo=%s, passes=%d, bits=(%d, %d), hash=%d, tile=%d, lds_cap=%d, flags=%d)" % (
-            "phj" if self.algo == HJ_PHJ else "shj", self.passes, self.bits[0], self.bits[1],
-            self.hash, self.tile, self.lds_cap, self.flags))
+            {HJ_SHJ: "shj", HJ_PHJ: "phj", HJ_AUTO: "auto"}.get(self.algo, str(self.algo)), self.passes,
+            self.bits[0], self.bits[1], self.hash, self.tile, self.lds_cap, self.flags))
+
+
+class HjTable(ctypes.Structure):
+    _fields_ = [("params", HjParams), ("n_r", ctypes.c_uint64), ("r_key", ctypes.c_void_p),
+                ("r_rid", ctypes.c_void_p), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 
 class HjJob(ctypes.Structure):
@@ -108,6 +115,18 @@ def load() -> ctypes.CDLL:
             lib.hj_join_timed.argtypes = [P(HjParams), P(HjRel), P(HjRel), P(HjOut), vp, ctypes.c_size_t, vp,
                                           vp, P(ctypes.c_char_p), P(ctypes.c_float), ctypes.c_uint32,
                                           P(ctypes.c_uint32)]
+            lib.hj_table_bytes.restype = ctypes.c_size_t
+            lib.hj_table_bytes.argtypes = [P(HjParams), ctypes.c_uint64]
+            lib.hj_build.restype = ctypes.c_int
+            lib.hj_build.argtypes = [P(HjParams), P(HjRel), vp, ctypes.c_size_t, vp, P(HjTable)]
+            lib.hj_probe_workspace_bytes.restype = ctypes.c_size_t
+            lib.hj_probe_workspace_bytes.argtypes = [P(HjTable), ctypes.c_uint64]
+            lib.hj_probe.restype = ctypes.c_int
+            lib.hj_probe.argtypes = [P(HjTable), P(HjRel), P(HjOut), vp, ctypes.c_size_t, vp, vp]
+            lib.hj_batch_bytes.restype = ctypes.c_size_t
+            lib.hj_batch_bytes.argtypes = [ctypes.c_uint32, P(HjJob), P(HjParams)]
+            lib.hj_batch.restype = ctypes.c_int
+            lib.hj_batch.argtypes = [ctypes.c_uint32, P(HjJob), P(HjParams), vp, ctypes.c_size_t, vp]
             lib.hj_status_str.restype = ctypes.c_char_p
             lib.hj_status_str.argtypes = [ctypes.c_int]
             lib.hj_last_error.restype = ctypes.c_char_p
@@ -164,10 +183,10 @@ def hj_default_params() -> HjParams:
 
 def params(algo: str = "phj", passes: int = 2, bits=(6, 6), hash: str = "identity", tile: int = 0,
            lds_cap: int = 0, one_pass: bool = False) -> HjParams:
-    """Builds an ``hj_params``.  ``algo`` is "shj" or "phj"; ``hash`` "identity" or "murmur2";
+    """Builds an ``hj_params``.  ``algo`` is "shj", "phj" or "auto"; ``hash`` "identity" or "murmur2";
     ``one_pass`` selects the single-pass PHJ output (HJ_FLAG_ONE_PASS)."""
     p = HjParams()
-    p.algo = {"shj": HJ_SHJ, "phj": HJ_PHJ}[algo]
+    p.algo = {"shj": HJ_SHJ, "phj": HJ_PHJ, "auto": HJ_AUTO}[algo]
     p.passes = passes
     b = tuple(bits) + (0,) * (2 - len(tuple(bits)))
     p.bits[0], p.bits[1] = int(b[0]), int(b[1])
@@ -301,8 +320,119 @@ def join(r_key, r_rid, s_key, s_rid, p: HjParams | None = None, capacity: int | 
 
 
 # ---------------------------------------------------------------------------
+# Build once, probe many times
+# ---------------------------------------------------------------------------
+
+
+def hj_table_bytes(p: HjParams, n_r: int) -> int:
+    v = load().hj_table_bytes(ctypes.byref(p), n_r)
+    if v == 0:
+        raise HJError(HJ_ERR_INVALID, load().hj_last_error().decode())
+    return int(v)
+
+
+def hj_build(p: HjParams, r_key, r_rid, ws: torch.Tensor, stream=None) -> HjTable:
+    """Enqueues the build of R's table into ``ws``; returns the ``hj_table``."""
+    R = _rel(r_key, r_rid, "R")
+    wp, wb = _ws(ws)
+    t = HjTable()
+    _check(load().hj_build(ctypes.byref(p), ctypes.byref(R), wp, wb, _stream(stream), ctypes.byref(t)))
+    return t
+
+
+def hj_probe_workspace_bytes(t: HjTable, n_s: int) -> int:
+    v = load().hj_probe_workspace_bytes(ctypes.byref(t), n_s)
+    if v == 0:
+        raise HJError(HJ_ERR_INVALID, load().hj_last_error().decode())
+    return int(v)
+
+
+def hj_probe(t: HjTable, s_key, s_rid, out_r, out_s, ws: torch.Tensor, d_count: torch.Tensor,
+             stream=None) -> None:
+    """Enqueues a probe of table ``t`` by S on ``stream``."""
+    if d_count.dtype != torch.int64 or not d_count.is_cuda or d_count.numel() < 1:
+        raise ValueError("d_count must be an int64 CUDA tensor with at least one element")
+    S, O = _rel(s_key, s_rid, "S"), _out(out_r, out_s)
+    wp, wb = _ws(ws)
+    _check(load().hj_probe(ctypes.byref(t), ctypes.byref(S), ctypes.byref(O), wp, wb, d_count.data_ptr(),
+                           _stream(stream)))
+
+
+class Table:
+    """A table over R (``hj_build``) with its device workspace; keeps R's
+    tensors alive for probes that read them.  ``probe`` joins S against it."""
+
+    def __init__(self, r_key, r_rid, p: HjParams | None = None, stream=None):
+        if p is None:
+            p = hj_default_params()
+        self.r_key, self.r_rid = r_key, r_rid
+        self.ws = torch.empty(max(hj_table_bytes(p, r_key.numel()), 1), dtype=torch.uint8, device=r_key.device)
+        self.t = hj_build(p, r_key, r_rid, self.ws, stream)
+
+    @property
+    def params(self) -> HjParams:
+        return self.t.params
+
+    def probe_workspace(self, n_s: int) -> torch.Tensor:
+        return torch.empty(max(hj_probe_workspace_bytes(self.t, n_s), 1), dtype=torch.uint8,
+                           device=self.r_key.device)
+
+    def probe(self, s_key, s_rid, capacity: int | None = None, stream=None):
+        """Returns ``(rid_r, rid_s, count)`` trimmed to ``count`` (rerun once with
+        the exact size when ``capacity``, default ``len(S)``, is too small)."""
+        dev = s_key.device
+        ws = self.probe_workspace(s_key.numel())
+        d_count = torch.zeros(1, dtype=torch.int64, device=dev)
+        cap = s_key.numel() if capacity is None else int(capacity)
+        for attempt in range(2):
+            out_r = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            out_s = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            hj_probe(self.t, s_key, s_rid, out_r[:cap], out_s[:cap], ws, d_count, stream)
+            (stream or torch.cuda.current_stream()).synchronize()
+            cnt = int(d_count.item())
+            if cnt <= cap:
+                return out_r[:cnt], out_s[:cnt], cnt
+            cap = cnt
+        raise AssertionError("probe count changed between runs")
+
+
+# ---------------------------------------------------------------------------
 # Batches
 # ---------------------------------------------------------------------------
+
+
+def _job_array(jobs, d_counts: torch.Tensor, params):
+    if d_counts.dtype != torch.int64 or not d_counts.is_cuda or d_counts.numel() < len(jobs):
+        raise ValueError("d_counts must be an int64 CUDA tensor with one element per job")
+    n = len(jobs)
+    arr = (HjJob * max(n, 1))()
+    base = d_counts.data_ptr()
+    for j, (rk, rr, sk, sr, o_r, o_s) in enumerate(jobs):
+        arr[j].R = _rel(rk, rr, "R")
+        arr[j].S = _rel(sk, sr, "S")
+        arr[j].out = _out(o_r, o_s)
+        arr[j].d_count = base + 8 * j
+    pp = None
+    if params is not None:
+        if len(params) != n:
+            raise ValueError("one HjParams per job")
+        pp = (HjParams * max(n, 1))(*params)
+    return n, arr, pp
+
+
+def hj_batch_bytes(jobs, d_counts: torch.Tensor, params=None) -> int:
+    n, arr, pp = _job_array(jobs, d_counts, params)
+    v = load().hj_batch_bytes(n, arr, pp)
+    if v == 0:
+        raise HJError(HJ_ERR_INVALID, load().hj_last_error().decode())
+    return int(v)
+
+
+def hj_batch(jobs, d_counts: torch.Tensor, ws: torch.Tensor, params=None, stream=None) -> None:
+    """One-shot batch (``hj_batch``): plans, runs and synchronises ``stream``."""
+    n, arr, pp = _job_array(jobs, d_counts, params)
+    wp, wb = _ws(ws)
+    _check(load().hj_batch(n, arr, pp, wp, wb, _stream(stream)))
 
 
 class BatchPlan:
@@ -315,23 +445,8 @@ class BatchPlan:
     The tensors must stay alive while the plan is used."""
 
     def __init__(self, jobs, d_counts: torch.Tensor, params=None, graph: bool = True):
-        if d_counts.dtype != torch.int64 or not d_counts.is_cuda or d_counts.numel() < len(jobs):
-            raise ValueError("d_counts must be an int64 CUDA tensor with one element per job")
-        n = len(jobs)
+        n, arr, pp = _job_array(jobs, d_counts, params)
         self._keep = (jobs, d_counts)
-        arr = (HjJob * max(n, 1))()
-        base = d_counts.data_ptr()
-        for j, (rk, rr, sk, sr, o_r, o_s) in enumerate(jobs):
-            arr[j].R = _rel(rk, rr, "R")
-            arr[j].S = _rel(sk, sr, "S")
-            arr[j].out = _out(o_r, o_s)
-            arr[j].d_count = base + 8 * j
-        pp = None
-        if params is not None:
-            if len(params) != n:
-                raise ValueError("one HjParams per job")
-            parr = (HjParams * max(n, 1))(*params)
-            pp = parr
         h = ctypes.c_void_p()
         _check(load().hj_batch_plan_create(n, arr, pp, 0 if graph else HJ_BATCH_NO_GRAPH, ctypes.byref(h)))
         self._h = h

@@ -155,3 +155,114 @@ def test_validation_before_launch(hj):
                        None) == hj.HJ_ERR_INVALID
     assert lib.hj_join(ctypes.byref(p), None, ctypes.byref(R), ctypes.byref(O), 1 << 20, need, 8,
                        None) == hj.HJ_ERR_INVALID
+
+
+@pytest.mark.parametrize("n_r,want", [
+    (0, (0, (0, 0))), (1000, (0, (0, 0))), (4416, (0, (0, 0))), (4417, (1, (1, 0))),
+    (100000, (1, (5, 0))), (1 << 20, (2, (4, 4))), (1 << 24, (2, (6, 6))), (3 << 24, (2, (7, 7))),
+])
+def test_auto_params(hj, n_r, want):
+    """HJ_AUTO: no partitioning up to 4416 R tuples, else ~4096 R tuples per partition
+    (B = smallest with |R| >> B <= 4096; one pass up to 6 bits, else split (B+1)/2, B/2)."""
+    for flags in (0, hj.HJ_FLAG_ONE_PASS):
+        p = hj.params("auto", one_pass=bool(flags))
+        q = hj.hj_resolve_params(p, n_r, 1000)
+        assert q.algo == hj.HJ_PHJ
+        assert (q.passes, tuple(q.bits)) == want
+        # passes 0 always writes its output in one pass; otherwise the caller's flag is kept
+        assert q.flags == (hj.HJ_FLAG_ONE_PASS if want[0] == 0 else flags)
+        assert hj.hj_workspace_bytes(p, n_r, 1000) == hj.hj_workspace_bytes(q, n_r, 1000)
+
+
+def test_table_and_probe_sizes(hj):
+    n = 1 << 20
+    for p in (hj.params("shj"), hj.params("phj", 1, (8,)), hj.params("phj", 2, (5, 5)),
+              hj.params("phj", 0, (0, 0)), hj.params("auto")):
+        n_r = 4000 if p.passes == 0 and p.algo == hj.HJ_PHJ else n
+        tb = hj.hj_table_bytes(p, n_r)
+        assert tb > 0
+        t = hj.HjTable()
+        t.params = hj.hj_resolve_params(p, n_r, n_r)
+        t.n_r, t.r_key, t.r_rid, t.ws, t.ws_bytes = n_r, 256, 256, 1 << 20, tb
+        pb = hj.hj_probe_workspace_bytes(t, n)
+        assert pb > 0
+        if t.params.algo == hj.HJ_PHJ and t.params.passes > 0:
+            # build (R) + probe (S) hold what one join holds, minus nothing it needs twice
+            assert tb + pb >= hj.hj_workspace_bytes(t.params, n_r, n)
+    # SHJ table: 2^ceil(log2 2|R|) 8-byte slots plus a 4-byte link per R row
+    tb = hj.hj_table_bytes(hj.params("shj"), 1 << 24)
+    assert 8 * 2 * (1 << 24) + 4 * (1 << 24) <= tb < 8 * 2 * (1 << 24) + 4 * (1 << 24) + (1 << 20)
+    with pytest.raises(hj.HJError):
+        hj.hj_table_bytes(hj.params("phj", 0, (0, 0)), 9000)  # passes 0 needs |R| <= 8192
+    with pytest.raises(hj.HJError):
+        hj.hj_table_bytes(hj.params("phj", 2, (6, 6)), 1 << 31)
+
+
+def test_build_probe_validation_before_launch(hj):
+    """Rejected build/probe calls return before touching the device (runs without a GPU)."""
+    lib = hj.load()
+    p = hj.params("phj", 2, (6, 6))
+    R = hj.HjRel(256, 256, 1000)
+    t = hj.HjTable()
+    tb = hj.hj_table_bytes(p, 1000)
+    # build: NULL table, NULL or small or misaligned workspace, NULL R arrays
+    assert lib.hj_build(ctypes.byref(p), ctypes.byref(R), 1 << 20, tb, None, None) == hj.HJ_ERR_INVALID
+    assert lib.hj_build(ctypes.byref(p), ctypes.byref(R), None, tb, None, ctypes.byref(t)) == hj.HJ_ERR_WORKSPACE
+    assert lib.hj_build(ctypes.byref(p), ctypes.byref(R), 1 << 20, tb - 1, None, ctypes.byref(t)) == \
+        hj.HJ_ERR_WORKSPACE
+    assert lib.hj_build(ctypes.byref(p), ctypes.byref(R), (1 << 20) + 8, tb, None, ctypes.byref(t)) == \
+        hj.HJ_ERR_INVALID
+    Rn = hj.HjRel(None, 256, 1000)
+    assert lib.hj_build(ctypes.byref(p), ctypes.byref(Rn), 1 << 20, tb, None, ctypes.byref(t)) == \
+        hj.HJ_ERR_INVALID
+    # probe: a table whose parameters were not resolved, or without its workspace
+    t.params = hj.hj_resolve_params(p, 1000, 1000)
+    t.n_r, t.r_key, t.r_rid, t.ws, t.ws_bytes = 1000, 256, 256, 1 << 20, tb
+    S = hj.HjRel(256, 256, 500)
+    O = hj.HjOut(256, 256, 500)
+    pb = hj.hj_probe_workspace_bytes(t, 500)
+    probe = lambda tt, ws=1 << 22, wb=pb, d=8, o=O: lib.hj_probe(  # noqa: E731
+        ctypes.byref(tt), ctypes.byref(S), ctypes.byref(o), ws, wb, d, None)
+    assert probe(t, d=None) == hj.HJ_ERR_INVALID
+    assert probe(t, wb=pb - 1) == hj.HJ_ERR_WORKSPACE
+    assert probe(t, o=hj.HjOut(None, 256, 5)) == hj.HJ_ERR_INVALID
+    bad = hj.HjTable.from_buffer_copy(t)
+    bad.params.tile = 0
+    assert probe(bad) == hj.HJ_ERR_INVALID
+    bad = hj.HjTable.from_buffer_copy(t)
+    bad.params.algo = hj.HJ_AUTO
+    assert probe(bad) == hj.HJ_ERR_INVALID
+    bad = hj.HjTable.from_buffer_copy(t)
+    bad.ws = None
+    assert probe(bad) == hj.HJ_ERR_INVALID
+    bad = hj.HjTable.from_buffer_copy(t)
+    bad.ws_bytes = tb - 1
+    assert probe(bad) == hj.HJ_ERR_INVALID
+    # SHJ probes read R's rids through the table
+    ps = hj.params("shj")
+    ts = hj.HjTable()
+    ts.params = hj.hj_resolve_params(ps, 1000, 1000)
+    ts.n_r, ts.r_key, ts.r_rid, ts.ws, ts.ws_bytes = 1000, 256, None, 1 << 20, hj.hj_table_bytes(ps, 1000)
+    assert lib.hj_probe_workspace_bytes(ctypes.byref(ts), 500) == 0
+
+
+def test_batch_bytes_on_host(hj):
+    """hj_batch_bytes plans on the host only (no device calls): fake device pointers suffice."""
+    lib = hj.load()
+    jobs = (hj.HjJob * 3)()
+    sizes = [(1000, 5000), (200000, 400000), (3 << 20, 1 << 20)]
+    for j, (nr, ns) in enumerate(sizes):
+        jobs[j].R = hj.HjRel(256, 256, nr)
+        jobs[j].S = hj.HjRel(256, 256, ns)
+        jobs[j].out = hj.HjOut(256, 256, ns)
+        jobs[j].d_count = 256 + 8 * j
+    a = lib.hj_batch_bytes(3, jobs, None)
+    assert a > 0
+    # at least the largest pipelined job's own workspace (its lane slice)
+    q = hj.HjParams()
+    lib.hj_default_params(ctypes.byref(q))
+    q.algo = hj.HJ_AUTO
+    q.flags = hj.HJ_FLAG_ONE_PASS
+    assert a >= hj.hj_workspace_bytes(q, 3 << 20, 1 << 20)
+    jobs[1].d_count = None
+    assert lib.hj_batch_bytes(3, jobs, None) == 0
