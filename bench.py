@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--no-shj", action="store_true", help="skip the SHJ line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="also time every radix configuration")
+    ap.add_argument("--sweeps", action="store_true",
+                    help="also time a build-size sweep (|R| 2^16..2^24 against |S| = 2^24, 50%% match) and a "
+                         "selectivity sweep (12.5/50/100%% of S matching, 16M x 16M)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the Zipf-skewed 16M x 64M workload")
     ap.add_argument("--batch-jobs", type=int, default=4096, help="jobs of the batched workload (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=12288, help="requests per served level (0: skip)")
@@ -272,6 +276,82 @@ def measure_phj(hj, torch, p, t, out_r, out_s, d_count, n_r, n_s, steps, warmup,
             "path_frac": round(total_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def bench_build_probe(hj, torch, p, t, out_r, out_s, d_count, steps, warmup) -> dict:
+    """The split join on the same inputs: R's table built once (hj_build), then
+    S probed against it (hj_probe); a probe partitions only S."""
+    rk, rr, sk, sr = t
+    tab_ws = torch.empty(hj.hj_table_bytes(p, rk.numel()), dtype=torch.uint8, device=rk.device)
+    build_ms = time_steps(lambda: hj.hj_build(p, rk, rr, tab_ws), steps, warmup, torch)
+    tab = hj.hj_build(p, rk, rr, tab_ws)
+    pws = torch.empty(hj.hj_probe_workspace_bytes(tab, sk.numel()), dtype=torch.uint8, device=rk.device)
+    probe_ms = time_steps(lambda: hj.hj_probe(tab, sk, sr, out_r, out_s, pws, d_count), steps, warmup, torch)
+    return {"params": repr(tab.params), "build_ms": round(build_ms, 4), "probe_ms": round(probe_ms, 4),
+            "build_tuples_per_s": rk.numel() / (build_ms * 1e-3), "probe_tuples_per_s": sk.numel() / (probe_ms * 1e-3),
+            "matches": int(d_count.item())}
+
+
+def bench_c3(hj, torch, dev, steps, warmup) -> dict:
+    """R = permutation of 1..2^24, S = 2^26 Zipf draws over R's keys (every S tuple
+    matches once; at theta 1 the most frequent key holds ~5.8% of S)."""
+    from paper_1307_1955_amd.gen import device as dgen
+    out = {}
+    for theta in (0.5, 1.0):
+        t = dgen.config_c3(theta=theta, device=dev)
+        n_r, n_s = t[0].numel(), t[2].numel()
+        o_r = torch.empty(n_s, dtype=torch.int32, device=dev)
+        o_s = torch.empty(n_s, dtype=torch.int32, device=dev)
+        d = torch.zeros(1, dtype=torch.int64, device=dev)
+        row = {}
+        for name, q in (("phj", hj.params("phj", 2, (6, 6), one_pass=True)), ("shj", hj.params("shj", one_pass=True))):
+            ws = hj.workspace(q, n_r, n_s, dev)
+            ms = time_steps(lambda: hj.hj_join(q, *t, o_r, o_s, ws, d), steps, warmup, torch)
+            row[name] = {"ms": round(ms, 4), "tuples_per_s": (n_r + n_s) / (ms * 1e-3), "matches": int(d.item())}
+            del ws
+        out["theta_%g" % theta] = row
+        del t, o_r, o_s
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_sweeps(hj, torch, dev, steps, warmup) -> dict:
+    """Build-size sweep (|R| = 2^16..2^24, |S| = 2^24 uniform over 1..2|R|) and
+    selectivity sweep (16M x 16M, S uniform over 1..|R|/f for a match fraction f)."""
+    from paper_1307_1955_amd.gen import device as dgen
+    n_s = 1 << 24
+    o_r = torch.empty(n_s, dtype=torch.int32, device=dev)
+    o_s = torch.empty(n_s, dtype=torch.int32, device=dev)
+    d = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def run(t):
+        row = {}
+        n_r = t[0].numel()
+        for name, q in (("phj_auto", hj.params("auto", one_pass=True)), ("shj", hj.params("shj", one_pass=True))):
+            ws = hj.workspace(q, n_r, n_s, dev)
+            ms = time_steps(lambda: hj.hj_join(q, *t, o_r, o_s, ws, d), steps, warmup, torch)
+            row[name] = {"ms": round(ms, 4), "tuples_per_s": (n_r + n_s) / (ms * 1e-3), "matches": int(d.item())}
+            if name == "phj_auto":
+                row[name]["params"] = repr(hj.hj_resolve_params(q, n_r, n_s))
+            del ws
+        return row
+
+    build = []
+    for lg in (16, 18, 20, 22, 24):
+        n_r = 1 << lg
+        t = dgen.unique_uniform(7, n_r, n_s, 2 * n_r, dev)
+        build.append({"n_r": n_r, "n_s": n_s, **run(t)})
+        print("bench: build-size sweep %s" % build[-1], file=sys.stderr, flush=True)
+        del t
+    sel = []
+    for f in (0.125, 0.5, 1.0):
+        n_r = 1 << 24
+        t = dgen.unique_uniform(8, n_r, n_s, int(n_r / f), dev)
+        sel.append({"match_fraction": f, **run(t)})
+        print("bench: selectivity sweep %s" % sel[-1], file=sys.stderr, flush=True)
+        del t
+    torch.cuda.empty_cache()
+    return {"build_size": build, "selectivity": sel}
+
+
 PROFILE = os.path.join(ROOT, "profiles", "phj_16m_x_16m_hbm.json")
 KERNEL_OF_PHASE = {"part_hist": "k_part_hist", "part_scatter": "k_part_scatter", "join_count": "k_join_count",
                    "join_write": "k_join_write<false>", "join_write_1pass": "k_join_write<true>"}
@@ -368,6 +448,8 @@ def main():
         "path_frac": head["path_frac"],
         "kernels": phases,
     }
+    print("bench: build once, probe (split join)", file=sys.stderr, flush=True)
+    result["build_probe"] = bench_build_probe(hj, torch, p, t, out_r, out_s, d_count, args.steps, args.warmup)
     # the other output materialisation on the same inputs (both give the same multiset)
     q = hj.params("phj", args.passes, bits, hash=args.hash, tile=args.tile, one_pass=not one_pass)
     alt = measure_phj(hj, torch, q, t, out_r, out_s, d_count, n_r, n_s, args.steps, args.warmup, args.passes,
@@ -403,9 +485,14 @@ def main():
                     print("bench: sweep %s" % sweep[-1], file=sys.stderr, flush=True)
                     del wq
         result["sweep"] = sweep
+    del out_r, out_s, t
+    torch.cuda.empty_cache()
+    if not args.no_c3:
+        print("bench: Zipf-skewed 16M x 64M (C3)", file=sys.stderr, flush=True)
+        result["c3"] = bench_c3(hj, torch, dev, min(args.steps, 10), min(args.warmup, 3))
+    if args.sweeps:
+        result["sweeps"] = bench_sweeps(hj, torch, dev, min(args.steps, 10), min(args.warmup, 3))
     if args.batch_jobs:
-        del out_r, out_s, t
-        torch.cuda.empty_cache()
         from paper_1307_1955_amd import tune, workloads
         print("bench: building the batched workload (%d jobs) in HBM" % args.batch_jobs, file=sys.stderr, flush=True)
         wl = workloads.batch_workload(njobs=args.batch_jobs)

@@ -56,7 +56,7 @@ typedef enum hj_status {
 } hj_status;
 
 /* HJ_AUTO: the library picks PHJ parameters from |R| (no partitioning up to
-   4416 R tuples, else about 4096 R tuples per partition: one pass up to 6
+   4416 R tuples, else about 4096 R tuples per partition: one pass up to 10
    radix bits, two passes above); hash, tile, lds_cap and flags are kept.
    hj_resolve_params shows the choice. */
 typedef enum hj_algo { HJ_SHJ = 0, HJ_PHJ = 1, HJ_AUTO = 2 } hj_algo;
@@ -104,7 +104,8 @@ typedef struct hj_out {
            splits on the high bits[0] of them, pass 2 on the low bits[1].
    hash    an hj_hash value.
    tile    tuples per partitioning tile: a power of two in 1024..8192, or 0
-           = chosen from the sizes (8192 when |R| + |S| >= 2^24, else 4096).
+           = chosen from the sizes (8192 when |R| + |S| >= 2^25, or >= 2^24
+           with one pass of 8 or more bits; else 4096).
    lds_cap largest R partition (tuples) joined from an LDS-resident table:
            0 = chosen from |R| and B; else a multiple of 64 in 256..8192.
            Larger partitions take the HBM-table path.

@@ -98,7 +98,7 @@ void auto_params(uint64_t n_r, hj_params* p) {
     }
     uint32_t B = 0;
     while (B < 16 && (n_r >> B) > 4096) ++B;
-    if (B <= 6) {
+    if (B <= kAutoOnePassMaxBits) {
         p->passes = 1;
         p->bits[0] = B;
         p->bits[1] = 0;
@@ -136,12 +136,11 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
     if (p->algo != HJ_SHJ && p->algo != HJ_PHJ) return fail(HJ_ERR_INVALID, "unknown algo %u", p->algo);
     if (p->hash != HJ_HASH_IDENTITY && p->hash != HJ_HASH_MURMUR2)
         return fail(HJ_ERR_INVALID, "unknown hash %u", p->hash);
-    const uint32_t tile = p->tile ? p->tile : hj::default_tile(n_r, n_s);
-    if (tile != 1024 && tile != 2048 && tile != 4096 && tile != 8192)
+    if (p->tile != 0 && p->tile != 1024 && p->tile != 2048 && p->tile != 4096 && p->tile != 8192)
         return fail(HJ_ERR_INVALID, "tile must be 0 or a power of two in 1024..8192 (got %u)", p->tile);
     pl->phj = p->algo == HJ_PHJ;
     pl->one_pass = (p->flags & HJ_FLAG_ONE_PASS) != 0;
-    pl->tile = tile;
+    pl->tile = p->tile ? p->tile : 4096;  // PHJ with partitioning: chosen below
     pl->hash = p->hash;
     pl->passes = 0;
     pl->b1 = pl->b2 = pl->B = 0;
@@ -185,6 +184,7 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
     } else {
         pl->lds_cap = auto_lds_cap(n_r, pl->P);
     }
+    if (!p->tile) pl->tile = hj::default_tile(n_r, n_s, pl->passes, pl->b1);
     fill_resolved(p, pl);
     return HJ_OK;
 }

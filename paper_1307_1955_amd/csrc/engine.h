@@ -33,9 +33,14 @@ struct Plan {
 // HJ_AUTO: the largest |R| joined from one LDS table without partitioning
 // (the direct kernel then runs three workgroups per CU).
 constexpr uint32_t kAutoDirectMax = 4416;
+// Radix bits HJ_AUTO still takes in one pass (measured on MI355X against
+// |S| = 2^24: one pass of 8-10 bits with 8192-tuple tiles beats two passes by
+// 10-35%; from 11 bits two passes win).
+constexpr uint32_t kAutoOnePassMaxBits = 10;
 // The size rule of HJ_AUTO: PHJ with no partitioning up to kAutoDirectMax R
-// tuples, else about 4096 R tuples per partition (one pass up to 6 radix bits,
-// two passes above).  Keeps hash, tile, lds_cap and flags.
+// tuples, else about 4096 R tuples per partition (one pass up to
+// kAutoOnePassMaxBits radix bits, two passes above).  Keeps hash, tile,
+// lds_cap and flags.
 void auto_params(uint64_t n_r, hj_params* p);
 
 // Default LDS table capacity for |R| = n_r split into P partitions.

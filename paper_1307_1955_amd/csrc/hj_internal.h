@@ -69,9 +69,14 @@ void shj_write(const int32_t* s_key, const int32_t* s_rid, uint64_t n_s, const u
 // 4% faster), 256 below (the vector tile loads need >= 4 tuples per thread).
 constexpr uint32_t kMinPartBlock = 256;
 inline uint32_t part_block(uint32_t tile) { return tile >= 4096 ? 512u : kMinPartBlock; }
-// Default partitioning tile: 8192 tuples once a join has enough tuples to fill
-// the chip several times over with such tiles, else 4096.
-inline uint32_t default_tile(uint64_t n_r, uint64_t n_s) { return n_r + n_s >= (1ull << 24) ? 8192u : 4096u; }
+// Default partitioning tile: 8192 tuples when the join has enough tuples to
+// fill the chip several times over with such tiles and needs the longer
+// partition runs they give (2^25 tuples or more, or 2^24 or more in one pass of
+// 8 or more radix bits), else 4096 (measured on MI355X).
+inline uint32_t default_tile(uint64_t n_r, uint64_t n_s, uint32_t passes, uint32_t bits1) {
+    const uint64_t n = n_r + n_s;
+    return (n >= (1ull << 25) || (n >= (1ull << 24) && passes == 1 && bits1 >= 8)) ? 8192u : 4096u;
+}
 struct PassCfg {
     uint32_t shift;      // radix bits taken from (hash >> shift)
     uint32_t bits;       // partitions = 1 << bits

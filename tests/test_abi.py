@@ -58,16 +58,21 @@ def test_default_params(hj):
 
 def test_resolve_params(hj):
     p = hj.hj_default_params()
-    small = hj.hj_resolve_params(p, 1 << 22, 1 << 22)
-    big = hj.hj_resolve_params(p, 1 << 23, 1 << 23)
+    small = hj.hj_resolve_params(p, 1 << 23, 1 << 23)
+    big = hj.hj_resolve_params(p, 1 << 24, 1 << 24)
     assert (small.tile, big.tile) == (4096, 8192)
+    # one pass of 8+ bits takes 8192-tuple tiles from 2^24 tuples on
+    one = hj.params("phj", 1, (8,))
+    assert hj.hj_resolve_params(one, 1 << 20, (1 << 24) - (1 << 20)).tile == 8192
+    assert hj.hj_resolve_params(one, 1 << 20, (1 << 23)).tile == 4096
+    assert hj.hj_resolve_params(hj.params("phj", 1, (7,)), 1 << 20, 1 << 24).tile == 4096
     for q in (small, big):
         assert q.lds_cap % 64 == 0 and 256 <= q.lds_cap <= 8192
         assert (q.algo, q.passes, tuple(q.bits), q.flags) == (p.algo, p.passes, tuple(p.bits), p.flags)
         # the resolved parameters describe the same join: same workspace
         assert hj.hj_workspace_bytes(q, 1 << 22, 1 << 22) > 0
-    assert hj.hj_workspace_bytes(big, 1 << 23, 1 << 23) == hj.hj_workspace_bytes(p, 1 << 23, 1 << 23)
-    assert hj.hj_workspace_bytes(small, 1 << 22, 1 << 22) == hj.hj_workspace_bytes(p, 1 << 22, 1 << 22)
+    assert hj.hj_workspace_bytes(big, 1 << 24, 1 << 24) == hj.hj_workspace_bytes(p, 1 << 24, 1 << 24)
+    assert hj.hj_workspace_bytes(small, 1 << 23, 1 << 23) == hj.hj_workspace_bytes(p, 1 << 23, 1 << 23)
     # an explicit tile is kept
     e = hj.hj_resolve_params(hj.params("phj", 2, (6, 6), tile=2048), 1 << 23, 1 << 23)
     assert e.tile == 2048
@@ -159,11 +164,12 @@ def test_validation_before_launch(hj):
 
 @pytest.mark.parametrize("n_r,want", [
     (0, (0, (0, 0))), (1000, (0, (0, 0))), (4416, (0, (0, 0))), (4417, (1, (1, 0))),
-    (100000, (1, (5, 0))), (1 << 20, (2, (4, 4))), (1 << 24, (2, (6, 6))), (3 << 24, (2, (7, 7))),
+    (100000, (1, (5, 0))), (1 << 20, (1, (8, 0))), (1 << 22, (1, (10, 0))), ((1 << 22) + (1 << 12), (2, (6, 5))),
+    (1 << 24, (2, (6, 6))), (3 << 24, (2, (7, 7))),
 ])
 def test_auto_params(hj, n_r, want):
     """HJ_AUTO: no partitioning up to 4416 R tuples, else ~4096 R tuples per partition
-    (B = smallest with |R| >> B <= 4096; one pass up to 6 bits, else split (B+1)/2, B/2)."""
+    (B = smallest with |R| >> B <= 4096; one pass up to 10 bits, else split (B+1)/2, B/2)."""
     for flags in (0, hj.HJ_FLAG_ONE_PASS):
         p = hj.params("auto", one_pass=bool(flags))
         q = hj.hj_resolve_params(p, n_r, 1000)

@@ -295,3 +295,28 @@ def test_c3_zipf_full(theta, kw):
     r_key, s_key, rows = check_full(hj.params(**kw), rk, rr, sk, sr, seed=3)
     cdf = gen.zipf_cdf(1 << 24, theta)
     assert np.array_equal(s_key[rows[:2000]], gen.zipf_ranks_at(3, gen.STREAM_S_KEYS, rows[:2000], cdf))
+
+
+@pytest.mark.parametrize("n_r,n_s", [(1 << 21, 1 << 24), (1 << 22, (1 << 24) - (1 << 22))])
+def test_auto_one_pass_wide(n_r, n_s):
+    """HJ_AUTO's one-pass range at its widest (9 and 10 radix bits, 8192-tuple
+    tiles in 512-thread workgroups): every S row against the closed form, a
+    sample of S rows against the oracle."""
+    p = hj.params("auto", one_pass=True)
+    q = hj.hj_resolve_params(p, n_r, n_s)
+    assert q.passes == 1 and q.bits[0] >= 9 and q.tile == 8192
+    rk, rr, sk, sr = dgen.unique_uniform(50, n_r, n_s, 2 * n_r)
+    o_r, o_s, cnt = hj.join(rk, rr, sk, sr, p=p)
+    s_key = sk.cpu().numpy()
+    assert cnt == int((s_key <= n_r).sum())
+    m = oracle.match_of(o_r.cpu().numpy(), o_s.cpu().numpy(), n_s)
+    r_key = rk.cpu().numpy()
+    inv = np.empty(n_r + 1, dtype=np.int64)
+    inv[r_key.astype(np.int64)] = np.arange(n_r)
+    want = np.where(s_key <= n_r, inv[np.minimum(s_key, n_r).astype(np.int64)], -1)
+    assert np.array_equal(m, want)
+    rows = np.sort(np.random.default_rng(51).choice(n_s, size=1 << 15, replace=False))
+    w_r, w_s = oracle.join(r_key, np.arange(n_r, dtype=np.int32), s_key[rows], rows.astype(np.int32))
+    got = np.stack([m[rows], rows], axis=1)
+    got = got[got[:, 0] >= 0]
+    assert np.array_equal(oracle.canonical(got[:, 0], got[:, 1]), oracle.canonical(w_r, w_s))
