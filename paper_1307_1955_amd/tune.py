@@ -48,7 +48,7 @@ CALIB = {
 
 @dataclass(frozen=True)
 class Candidate:
-    algo: str            # "shj" | "phj"
+    algo: str            # "shj" | "phj" | "auto" (the library's HJ_AUTO choice for the job's own sizes)
     passes: int          # PHJ: 0 (direct), 1, 2
     bits: tuple = (0, 0)
     one_pass: bool = True
@@ -56,6 +56,8 @@ class Candidate:
 
     def params(self):
         from . import hj
+        if self.algo == "auto":  # parameters and tile as the library chooses them
+            return hj.params("auto", tile=self.tile, one_pass=self.one_pass)
         return hj.params(self.algo, self.passes, self.bits, tile=self.tile or 4096, one_pass=self.one_pass)
 
     def as_dict(self) -> dict:
@@ -74,13 +76,30 @@ def _bits_for(n_r: int, target: int = 4096) -> int:
     return b
 
 
+# HJ_AUTO's rule (the library's auto_params), for the cost model: no
+# partitioning up to AUTO_DIRECT_MAX R tuples, else ~4096 R tuples per
+# partition, one pass up to AUTO_ONE_PASS_MAX_BITS radix bits.
+AUTO_DIRECT_MAX = 4416
+AUTO_ONE_PASS_MAX_BITS = 10
+
+
+def auto_candidate(n_r: int) -> Candidate:
+    """The concrete candidate HJ_AUTO picks for |R| = n_r (tile left to the library)."""
+    if n_r <= AUTO_DIRECT_MAX:
+        return Candidate("phj", 0)
+    b = _bits_for(n_r)
+    if b <= AUTO_ONE_PASS_MAX_BITS:
+        return Candidate("phj", 1, (b, 0))
+    return Candidate("phj", 2, ((b + 1) // 2, b // 2))
+
+
 def candidates(n_r: int, n_s: int) -> list[Candidate]:
-    out = [Candidate("shj", 0), Candidate("shj", 0, one_pass=False)]
+    out = [Candidate("shj", 0), Candidate("shj", 0, one_pass=False), Candidate("auto", 0)]
     if n_r <= 8192:
         out.append(Candidate("phj", 0))
     B = _bits_for(n_r)
     for b in {max(1, B - 1), max(1, B), B + 1}:
-        if b <= 8:
+        if b <= AUTO_ONE_PASS_MAX_BITS:
             out.append(Candidate("phj", 1, (b, 0)))
         if 2 <= b <= 16:
             out.append(Candidate("phj", 2, ((b + 1) // 2, b // 2)))
@@ -90,6 +109,11 @@ def candidates(n_r: int, n_s: int) -> list[Candidate]:
 
 def predict(c: Candidate, n_r: int, n_s: int, m: float, cal: dict = CALIB) -> float:
     """Cost-model time (s) of candidate c on |R| = n_r, |S| = n_s with m pairs."""
+    if c.algo == "auto":
+        a = auto_candidate(n_r)
+        tile = 8192 if (n_r + n_s >= 1 << 25 or (n_r + n_s >= 1 << 24 and a.passes == 1 and a.bits[0] >= 8)) \
+            else 4096
+        return predict(Candidate(a.algo, a.passes, a.bits, c.one_pass, tile), n_r, n_s, m, cal)
     n = n_r + n_s
     conc = cal["cus"] * cal["join_blocks_per_cu"]
     if c.algo == "shj":
@@ -193,6 +217,11 @@ def load_table(path: str = DEFAULT_TABLE) -> dict | None:
 def choose(n_r: int, n_s: int, table: dict | None) -> Candidate:
     """Tuned candidate for a job (nearest bucket), or the model's pick without a table."""
     if table:
+        # from this |R| on, the library's own HJ_AUTO choice (set where timing the
+        # whole batch, not single joins, found it faster)
+        af = table.get("auto_from_log2")
+        if af is not None and n_r >= (1 << int(af)):
+            return Candidate("auto", 0)
         lr, rb = bucket_key(n_r, n_s)
         lrs = sorted({int(k.split(":")[0]) for k in table["buckets"]})
         lr = min(lrs, key=lambda x: abs(x - lr))
@@ -212,8 +241,26 @@ def main():
     ap.add_argument("--min-log2", type=int, default=10)
     ap.add_argument("--max-log2", type=int, default=22)
     ap.add_argument("--top", type=int, default=4)
+    ap.add_argument("--merge", action="store_true",
+                    help="keep the buckets of the existing table outside the tuned range")
+    ap.add_argument("--set-auto-from-log2", type=int, default=None, metavar="L",
+                    help="no tuning: mark the existing table so jobs with |R| >= 2^L take HJ_AUTO's choice")
+    ap.add_argument("--note", default="", help="why (stored with --set-auto-from-log2)")
     a = ap.parse_args()
+    if a.set_auto_from_log2 is not None:
+        table = load_table(a.out)
+        table["auto_from_log2"] = a.set_auto_from_log2
+        table["auto_note"] = a.note
+        with open(a.out, "w") as f:
+            json.dump(table, f, indent=1)
+        print(a.out)
+        return
     table = tune(range(a.min_log2, a.max_log2 + 1), top=a.top)
+    old = load_table(a.out) if a.merge else None
+    if old:
+        for k, v in old["buckets"].items():
+            table["buckets"].setdefault(k, v)
+        table["buckets"] = dict(sorted(table["buckets"].items(), key=lambda kv: tuple(map(int, kv[0].split(":")))))
     os.makedirs(os.path.dirname(a.out), exist_ok=True)
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1)
