@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=12288, help="requests per served level (0: skip)")
     ap.add_argument("--serve-warmup", type=int, default=2048)
+    ap.add_argument("--serve-slots", type=int, default=16, help="concurrent batches of the server (1..16)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
@@ -169,7 +170,7 @@ def bench_served(args, torch, hj, wl, params, qps_levels) -> dict:
     n = args.serve_requests
     warm = min(args.serve_warmup, n // 2)
     ws_max = max(hj.hj_workspace_bytes(q, sp.n_r, sp.n_s) for q, sp in zip(params, wl.specs))
-    slots = 4
+    slots = args.serve_slots
     pool = torch.empty(slots * (ws_max + (64 << 20)), dtype=torch.uint8, device="cuda")
     jobs = [hj.make_job(*wl.jobs[j], wl.d_counts.data_ptr() + 8 * j) for j in range(njobs)]
     fps = [8 * (sp.n_r + sp.n_s) + 8 * e + hj.hj_workspace_bytes(q, sp.n_r, sp.n_s)

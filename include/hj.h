@@ -208,7 +208,7 @@ hj_status hj_probe(const hj_table* table, const hj_rel* S, const hj_out* out, vo
    jobs (pointers and sizes) and the per-job parameters; running it enqueues
    every job on the given stream.  Jobs with PHJ and passes == 0 (R fits one
    LDS table) run together in one multi-job kernel; the others run their own
-   launch sequences on four concurrent lanes whose workspace slices are reused
+   launch sequences on 16 concurrent lanes whose workspace slices are reused
    job after job.  Unless HJ_BATCH_NO_GRAPH is set, the first run with a given
    workspace captures the whole batch into one HIP graph (on a stream of the
    plan) and every run launches that graph on the caller's stream. */
