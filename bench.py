@@ -44,6 +44,8 @@ def parse():
                     help="also time a build-size sweep (|R| 2^16..2^24 against |S| = 2^24, 50%% match) and a "
                          "selectivity sweep (12.5/50/100%% of S matching, 16M x 16M)")
     ap.add_argument("--no-c3", action="store_true", help="skip the Zipf-skewed 16M x 64M workload")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the 16M x 16M PHJ and SHJ lines (no build/probe, no C3), e.g. under a profiler")
     ap.add_argument("--batch-jobs", type=int, default=4096, help="jobs of the batched workload (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=12288, help="requests per served level (0: skip)")
@@ -449,8 +451,9 @@ def main():
         "path_frac": head["path_frac"],
         "kernels": phases,
     }
-    print("bench: build once, probe (split join)", file=sys.stderr, flush=True)
-    result["build_probe"] = bench_build_probe(hj, torch, p, t, out_r, out_s, d_count, args.steps, args.warmup)
+    if not args.no_extras:
+        print("bench: build once, probe (split join)", file=sys.stderr, flush=True)
+        result["build_probe"] = bench_build_probe(hj, torch, p, t, out_r, out_s, d_count, args.steps, args.warmup)
     # the other output materialisation on the same inputs (both give the same multiset)
     q = hj.params("phj", args.passes, bits, hash=args.hash, tile=args.tile, one_pass=not one_pass)
     alt = measure_phj(hj, torch, q, t, out_r, out_s, d_count, n_r, n_s, args.steps, args.warmup, args.passes,
@@ -488,7 +491,7 @@ def main():
         result["sweep"] = sweep
     del out_r, out_s, t
     torch.cuda.empty_cache()
-    if not args.no_c3:
+    if not args.no_c3 and not args.no_extras:
         print("bench: Zipf-skewed 16M x 64M (C3)", file=sys.stderr, flush=True)
         result["c3"] = bench_c3(hj, torch, dev, min(args.steps, 10), min(args.warmup, 3))
     if args.sweeps:
