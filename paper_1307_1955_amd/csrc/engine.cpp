@@ -409,8 +409,8 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
                    uint64_t* zero_total, int32_t** fk, int32_t** fr, hj::Recorder& rec) {
     const uint32_t n_r = (uint32_t)R.n, n_s = (uint32_t)S.n;
     const bool two = pl.passes == 2;
-    hj::part_setup_pass1(w.segs1, w.tb1, R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, w.st1, w.nzero,
-                         rec);
+    const hj::Pass1 p1 = hj::make_pass1(R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, w.segs1, w.tb1,
+                                        w.st1, w.nzero);
     // the join plan rides on the last pass's scatter, the pass-2 setup on the first
     hj::SideJob plan{};
     plan.kind = hj::kSidePlan;
@@ -427,7 +427,7 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
                                        w.segs2, w.tb2, w.tseg2};
     }
     hj::PassCfg c1{pl.b2, pl.b1, pl.hash, pl.tile};
-    hj::part_hist(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, rec);
+    hj::part_hist_pass1(p1, c1, w.hist1, rec);  // also writes segs1/tb1 and clears the scan states
     hj::scan_u32(w.hist1, w.hist1, w.tiles1 * pl.P1, w.st1, nullptr, rec);
     hj::part_scatter(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, w.keyA, w.ridA,
                      two ? setup2 : plan, rec);

@@ -83,12 +83,31 @@ struct PassCfg {
     uint32_t hash_kind;  // hj_hash
     uint32_t tile;       // tuples per tile
 };
-// Pass-1 setup: writes the two segment descriptors (R, S) and tile_begin[0..2].
-// Also clears zero[0..nzero) (the join's scan states).
-void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, const int32_t* rr,
-                      uint32_t n_r, const int32_t* sk, const int32_t* sr, uint32_t n_s,
-                      uint32_t tile, uint32_t bits, uint64_t* zero, uint64_t nzero, Recorder& rec);
-// tile_seg: segment of every tile (nullptr: binary search over tile_begin).
+// Pass 1 of a join: R and S are its two segments (tiles numbered R first).
+// The pass-1 histogram takes them from here, as plain launch arguments, and
+// its first workgroup writes what later launches read from memory: the two
+// segment descriptors (segs[0..1]), tile_begin[0..2] = {0, nt_r, nt_r + nt_s},
+// and zero[0..nzero) cleared (the join's scan states).
+struct Pass1 {
+    const int32_t* rk;
+    const int32_t* rr;
+    const int32_t* sk;
+    const int32_t* sr;
+    uint32_t n_r, n_s;
+    uint32_t nt_r, ntiles;
+    uint64_t hist_s;  // first histogram entry of S: nt_r << bits
+    PartSeg* segs;
+    uint32_t* tile_begin;
+    uint64_t* zero;
+    uint64_t nzero;
+};
+Pass1 make_pass1(const int32_t* rk, const int32_t* rr, uint32_t n_r, const int32_t* sk, const int32_t* sr,
+                 uint32_t n_s, uint32_t tile, uint32_t bits, PartSeg* segs, uint32_t* tile_begin, uint64_t* zero,
+                 uint64_t nzero);
+// Pass-1 histogram (and the pass's set-up, see Pass1).
+void part_hist_pass1(const Pass1& p1, const PassCfg& cfg, uint32_t* hist, Recorder& rec);
+// Histogram of a later pass over the segments in memory; tile_seg: segment of
+// every tile (nullptr: binary search over tile_begin).
 void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec);
 // `side`: extra workgroups appended to the grid that run the next step's setup

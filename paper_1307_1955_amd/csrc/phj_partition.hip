@@ -113,24 +113,61 @@ __device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ p,
     return valid;
 }
 
-template <uint32_t BLOCK, uint32_t IPT>
+// The pass-1 set-up that later launches read (see Pass1), by one workgroup.
+__device__ __forceinline__ void pass1_setup(const Pass1& A) {
+    for (uint64_t i = threadIdx.x; i < A.nzero; i += blockDim.x) A.zero[i] = 0;
+    if (threadIdx.x == 0) {
+        PartSeg a;
+        a.key_in = A.rk; a.rid_in = A.rr; a.out_base = 0; a.hist_base = 0; a.n = A.n_r; a.pad = 0;
+        PartSeg b;
+        b.key_in = A.sk; b.rid_in = A.sr; b.out_base = A.n_r; b.hist_base = A.hist_s; b.n = A.n_s; b.pad = 0;
+        A.segs[0] = a;
+        A.segs[1] = b;
+        A.tile_begin[0] = 0;
+        A.tile_begin[1] = A.nt_r;
+        A.tile_begin[2] = A.ntiles;
+    }
+}
+
+// kPass1: the tiles of R and S from the launch arguments (p1), and workgroup 0
+// also does the pass's set-up; else the segments in memory.
+template <uint32_t BLOCK, uint32_t IPT, bool kPass1>
 __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__ segs,
                                                          const uint32_t* __restrict__ tile_begin,
                                                          const uint32_t* __restrict__ tile_seg,
                                                          uint32_t nseg, PassCfg cfg,
-                                                         uint32_t* __restrict__ hist) {
+                                                         uint32_t* __restrict__ hist, Pass1 p1) {
     extern __shared__ uint32_t lds[];
     constexpr uint32_t T = BLOCK * IPT;
     uint32_t* cnt = lds;
     const uint32_t P = 1u << cfg.bits;
-    const uint32_t ntiles = tile_begin[nseg];
-    const uint32_t tile = live_remap(blockIdx.x, ntiles);
-    if (tile >= ntiles) return;
-    const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
-    const PartSeg sg = segs[t.seg];
-    const int32_t* __restrict__ kin = sg.key_in + t.start;
+    const int32_t* __restrict__ kin;
+    uint32_t len, tl, nt;
+    uint64_t hist_base;
+    if (kPass1) {
+        if (blockIdx.x == 0) pass1_setup(p1);
+        const uint32_t tile = live_remap(blockIdx.x, p1.ntiles);
+        if (tile >= p1.ntiles) return;
+        const bool s1 = tile >= p1.nt_r;  // field by field: no dynamic index into the arguments
+        tl = s1 ? tile - p1.nt_r : tile;
+        nt = s1 ? p1.ntiles - p1.nt_r : p1.nt_r;
+        len = min(T, (s1 ? p1.n_s : p1.n_r) - tl * T);
+        kin = (s1 ? p1.sk : p1.rk) + tl * T;
+        hist_base = s1 ? p1.hist_s : 0ull;
+    } else {
+        const uint32_t ntiles = tile_begin[nseg];
+        const uint32_t tile = live_remap(blockIdx.x, ntiles);
+        if (tile >= ntiles) return;
+        const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
+        const PartSeg sg = segs[t.seg];
+        kin = sg.key_in + t.start;
+        len = t.len;
+        tl = t.tl;
+        nt = t.nt;
+        hist_base = sg.hist_base;
+    }
     int32_t keys[IPT], kx;
-    const uint64_t valid = load_tile_vec<BLOCK, IPT>(kin, t.len, keys, kx);
+    const uint64_t valid = load_tile_vec<BLOCK, IPT>(kin, len, keys, kx);
     // counters cleared while the tile's loads are in flight
     for (uint32_t i = threadIdx.x; i < P; i += BLOCK) cnt[i] = 0;
     __syncthreads();
@@ -148,8 +185,8 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
     }
     if ((valid >> IPT) & 1u) atomicAdd(&cnt[part_of(kx, cfg)], 1u);
     __syncthreads();
-    uint32_t* __restrict__ h = hist + sg.hist_base + t.tl;
-    for (uint32_t p = threadIdx.x; p < P; p += BLOCK) h[(uint64_t)p * t.nt] = cnt[p];
+    uint32_t* __restrict__ h = hist + hist_base + tl;
+    for (uint32_t p = threadIdx.x; p < P; p += BLOCK) h[(uint64_t)p * nt] = cnt[p];
 }
 
 template <uint32_t BLOCK, uint32_t IPT>
@@ -271,35 +308,31 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
     }
 }
 
-__global__ void __launch_bounds__(256) k_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk,
-                                                    const int32_t* rr, uint32_t n_r, const int32_t* sk,
-                                                    const int32_t* sr, uint32_t n_s, uint32_t tile, uint32_t bits,
-                                                    uint64_t* __restrict__ zero, uint64_t nzero) {
-    for (uint64_t i = threadIdx.x; i < nzero; i += blockDim.x) zero[i] = 0;
-    if (threadIdx.x != 0) return;
-    const uint32_t nt_r = (n_r + tile - 1) / tile;
-    const uint32_t nt_s = (n_s + tile - 1) / tile;
-    PartSeg a;
-    a.key_in = rk; a.rid_in = rr; a.out_base = 0; a.hist_base = 0; a.n = n_r; a.pad = 0;
-    PartSeg b;
-    b.key_in = sk; b.rid_in = sr; b.out_base = n_r; b.hist_base = (uint64_t)nt_r << bits; b.n = n_s;
-    b.pad = 0;
-    segs[0] = a;
-    segs[1] = b;
-    tile_begin[0] = 0;
-    tile_begin[1] = nt_r;
-    tile_begin[2] = nt_r + nt_s;
-}
-
+// p1 != nullptr: pass 1 (tiles from *p1; grid >= 1 so the set-up always runs).
 template <uint32_t BLOCK, uint32_t IPT>
 void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
-                 uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
+                 uint32_t grid, const PassCfg& cfg, uint32_t* hist, const Pass1* p1, Recorder& rec) {
     const size_t lds = sizeof(uint32_t) * ((size_t)1 << cfg.bits);
     rec.before("part_hist");
     static_assert(BLOCK * IPT >= 1024 && BLOCK * IPT <= 8192 && BLOCK / kWave <= kScanScratch, "tile shape");
-    hipLaunchKernelGGL((k_part_hist<BLOCK, IPT>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs, tile_begin,
-                       tile_seg, nseg, cfg, hist);
+    if (p1)
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
+                           tile_begin, tile_seg, nseg, cfg, hist, *p1);
+    else
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, false>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
+                           tile_begin, tile_seg, nseg, cfg, hist, Pass1{});
     rec.after();
+}
+
+void hist_dispatch(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
+                   uint32_t grid, const PassCfg& cfg, uint32_t* hist, const Pass1* p1, Recorder& rec) {
+    // workgroup size by tile: part_block()
+    switch (cfg.tile) {
+        case 1024: launch_hist<256, 4>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, p1, rec); break;
+        case 2048: launch_hist<256, 8>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, p1, rec); break;
+        case 4096: launch_hist<512, 8>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, p1, rec); break;
+        default: launch_hist<512, 16>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, p1, rec); break;
+    }
 }
 
 template <uint32_t BLOCK, uint32_t IPT>
@@ -337,26 +370,34 @@ size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile) {
     return sizeof(uint32_t) * (2 * Pp + kScanScratch) + sizeof(int32_t) * 2 * tile;
 }
 
-void part_setup_pass1(PartSeg* segs, uint32_t* tile_begin, const int32_t* rk, const int32_t* rr,
-                      uint32_t n_r, const int32_t* sk, const int32_t* sr, uint32_t n_s, uint32_t tile,
-                      uint32_t bits, uint64_t* zero, uint64_t nzero, Recorder& rec) {
-    rec.before("part_setup1");
-    hipLaunchKernelGGL(k_setup_pass1, dim3(1), dim3(256), 0, rec.stream, segs, tile_begin, rk, rr, n_r,
-                       sk, sr, n_s, tile, bits, zero, nzero);
-    rec.after();
+Pass1 make_pass1(const int32_t* rk, const int32_t* rr, uint32_t n_r, const int32_t* sk, const int32_t* sr,
+                 uint32_t n_s, uint32_t tile, uint32_t bits, PartSeg* segs, uint32_t* tile_begin, uint64_t* zero,
+                 uint64_t nzero) {
+    Pass1 a{};
+    a.rk = rk;
+    a.rr = rr;
+    a.sk = sk;
+    a.sr = sr;
+    a.n_r = n_r;
+    a.n_s = n_s;
+    a.nt_r = (n_r + tile - 1) / tile;
+    a.ntiles = a.nt_r + (n_s + tile - 1) / tile;
+    a.hist_s = (uint64_t)a.nt_r << bits;
+    a.segs = segs;
+    a.tile_begin = tile_begin;
+    a.zero = zero;
+    a.nzero = nzero;
+    return a;
 }
 
+void part_hist_pass1(const Pass1& p1, const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
+    hist_dispatch(p1.segs, p1.tile_begin, nullptr, 2, p1.ntiles ? p1.ntiles : 1u, cfg, hist, &p1, rec);
+}
 
 void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec) {
     if (grid == 0) return;
-    // workgroup size by tile: part_block()
-    switch (cfg.tile) {
-        case 1024: launch_hist<256, 4>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
-        case 2048: launch_hist<256, 8>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
-        case 4096: launch_hist<512, 8>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
-        default: launch_hist<512, 16>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, rec); break;
-    }
+    hist_dispatch(segs, tile_begin, tile_seg, nseg, grid, cfg, hist, nullptr, rec);
 }
 
 void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
