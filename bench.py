@@ -264,6 +264,38 @@ def cpu_baseline(n: int, min_seconds: float = 10.0, max_reps: int = 6) -> dict:
                       % (len(times), len(r), len(s), pairs, el)}
 
 
+def host_threads() -> int:
+    """Host threads this process may use (its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return max(1, min(n, cap) if cap > 0 else n)
+
+
+def cpu_baseline_all_cores(n: int, min_seconds: float = 10.0, max_reps: int = 6) -> dict:
+    """The oracle with its probe split over S chunks on every host thread
+    (single-threaded build, then a concurrent read-only probe), 16M x 16M."""
+    import oracle
+    from paper_1307_1955_amd import gen
+    r, s = gen.config_c2(n=n)
+    threads = host_threads()
+    times, build = [], []
+    pairs = 0
+    while len(times) < max_reps and sum(times) < min_seconds:
+        t0 = time.perf_counter()
+        with oracle.Table(r.key, r.rid) as tb:
+            t1 = time.perf_counter()
+            o_r, o_s = tb.probe_threads(s.key, s.rid, threads)
+        times.append(time.perf_counter() - t0)
+        build.append(t1 - t0)
+        pairs = len(o_r)
+    el = sum(times) / len(times)
+    return {"value": (len(r) + len(s)) / el, "unit": "tuples/s", "cores": threads, "kind": "oracle",
+            "sample": "%d full %d x %d joins on %d threads (single-threaded build %.2f s, then the probe split "
+                      "over S; %d pairs), %.2f s each on average"
+                      % (len(times), len(r), len(s), threads, sum(build) / len(build), pairs, el)}
+
+
 def measure_phj(hj, torch, p, t, out_r, out_s, d_count, n_r, n_s, steps, warmup, passes, one_pass):
     """Throughput of one PHJ configuration plus its per-kernel breakdown."""
     ws = hj.workspace(p, n_r, n_s)
@@ -511,6 +543,8 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(n)
+        print("bench: CPU oracle baseline, all host threads", file=sys.stderr, flush=True)
+        result["cpu_baseline_all_cores"] = cpu_baseline_all_cores(n)
     print(json.dumps(result), flush=True)
 
 

@@ -133,6 +133,34 @@ class Table:
         return out_r, out_s
 
 
+    def probe_threads(self, s_key, s_rid, threads: int) -> tuple[np.ndarray, np.ndarray]:
+        """``probe`` with S cut into ``threads`` contiguous chunks probed
+        concurrently against the (read-only) table; the chunks' pairs are
+        concatenated in chunk order, so the result equals ``probe``'s."""
+        from concurrent.futures import ThreadPoolExecutor
+        s_key = _arr(s_key)
+        s_rid = _arr(s_rid)
+        if s_key.shape != s_rid.shape:
+            raise ValueError("S key and rid lengths differ")
+        threads = max(1, int(threads))
+        cuts = np.linspace(0, len(s_key), threads + 1).astype(np.int64)
+
+        def chunk(i):  # the C calls release the interpreter lock
+            k = np.ascontiguousarray(s_key[cuts[i]:cuts[i + 1]])
+            r = np.ascontiguousarray(s_rid[cuts[i]:cuts[i + 1]])
+            n = int(self._lib.oracle_probe_count(self._h, _ptr(k), len(k)))
+            o_r = np.empty(n, dtype=np.int32)
+            o_s = np.empty(n, dtype=np.int32)
+            got = int(self._lib.oracle_probe_emit(self._h, _ptr(k), _ptr(r), len(k), _ptr(o_r), _ptr(o_s), n))
+            assert got == n
+            return o_r, o_s
+
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            parts = list(ex.map(chunk, range(threads)))
+        return (np.concatenate([p[0] for p in parts]) if parts else np.empty(0, np.int32),
+                np.concatenate([p[1] for p in parts]) if parts else np.empty(0, np.int32))
+
+
 def join(r_key, r_rid, s_key, s_rid) -> tuple[np.ndarray, np.ndarray]:
     """J(R, S): every (rid_R, rid_S) with equal keys, R the build side."""
     with Table(r_key, r_rid) as t:

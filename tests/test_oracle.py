@@ -202,3 +202,20 @@ def test_build_side_is_r_even_when_larger():
     sk = np.array([1], dtype=np.int32)
     o_r, o_s = oracle.join(rk, np.arange(5), sk, np.array([99]))
     assert sorted(o_r.tolist()) == [0, 1, 2] and o_s.tolist() == [99, 99, 99]
+
+
+def test_threaded_probe_equals_probe():
+    """The probe split over S chunks on several threads (the all-cores CPU
+    baseline) returns exactly the single-threaded probe's pairs, in order."""
+    rng = np.random.default_rng(77)
+    rk = rng.integers(-500, 500, size=3000).astype(np.int32)
+    sk = rng.integers(-600, 600, size=7001).astype(np.int32)
+    rr = np.arange(3000, dtype=np.int32)
+    sr = np.arange(7001, dtype=np.int32) * 5
+    with oracle.Table(rk, rr) as t:
+        a_r, a_s = t.probe(sk, sr)
+        for threads in (1, 3, 8):
+            b_r, b_s = t.probe_threads(sk, sr, threads)
+            assert np.array_equal(a_r, b_r) and np.array_equal(a_s, b_s)
+        e_r, e_s = t.probe_threads(sk[:0], sr[:0], 4)
+        assert len(e_r) == 0 and len(e_s) == 0
