@@ -99,7 +99,7 @@ typedef struct hj_out {
            |R| <= 8192: R is one LDS-resident table probed by every S chunk
            (ignored by SHJ).
    bits    PHJ: radix bits of pass 1 and pass 2.  B = bits[0] (+ bits[1] when
-           passes == 2) must be in 1..16 and each used entry in 1..13.  The
+           passes == 2) must be in 1..20 and each used entry in 1..13.  The
            2^B partitions are the values of the B low bits of the hash; pass 1
            splits on the high bits[0] of them, pass 2 on the low bits[1].
    hash    an hj_hash value.

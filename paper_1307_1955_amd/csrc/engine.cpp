@@ -97,7 +97,7 @@ void auto_params(uint64_t n_r, hj_params* p) {
         return;
     }
     uint32_t B = 0;
-    while (B < 16 && (n_r >> B) > 4096) ++B;
+    while (B < kMaxRadixBits && (n_r >> B) > 4096) ++B;
     if (B <= kAutoOnePassMaxBits) {
         p->passes = 1;
         p->bits[0] = B;
@@ -172,7 +172,8 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
     if (p->passes == 2 && (pl->b2 < 1 || pl->b2 > 13))
         return fail(HJ_ERR_INVALID, "bits[1] must be in 1..13 (got %u)", pl->b2);
     pl->B = pl->b1 + pl->b2;
-    if (pl->B > 16) return fail(HJ_ERR_INVALID, "total radix bits must be <= 16 (got %u)", pl->B);
+    if (pl->B > kMaxRadixBits)
+        return fail(HJ_ERR_INVALID, "total radix bits must be <= %u (got %u)", kMaxRadixBits, pl->B);
     pl->P1 = 1u << pl->b1;
     pl->P2 = 1u << pl->b2;
     pl->P = 1u << pl->B;

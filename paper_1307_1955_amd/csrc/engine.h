@@ -30,6 +30,9 @@ struct Plan {
     hj_params res;  // the parameters as run (HJ_AUTO and size-dependent choices resolved)
 };
 
+// Most radix bits over all passes: 2^20 partitions keep ~4096 R tuples per
+// partition (one LDS table) up to |R| = 2^31 - 1.
+constexpr uint32_t kMaxRadixBits = 20;
 // HJ_AUTO: the largest |R| joined from one LDS table without partitioning
 // (the direct kernel then runs three workgroups per CU).
 constexpr uint32_t kAutoDirectMax = 4416;

@@ -69,9 +69,12 @@ class Candidate:
         return Candidate(d["algo"], int(d["passes"]), tuple(d["bits"]), bool(d["one_pass"]), int(d.get("tile", 0)))
 
 
+MAX_RADIX_BITS = 20  # the library's limit on the radix bits of all passes
+
+
 def _bits_for(n_r: int, target: int = 4096) -> int:
     b = 0
-    while b < 16 and (n_r >> b) > target:
+    while b < MAX_RADIX_BITS and (n_r >> b) > target:
         b += 1
     return b
 

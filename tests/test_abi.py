@@ -86,7 +86,7 @@ def test_resolve_params(hj):
     dict(algo="phj", passes=3, bits=(6, 6)),
     dict(algo="phj", passes=1, bits=(0,)),
     dict(algo="phj", passes=1, bits=(14,)),
-    dict(algo="phj", passes=2, bits=(9, 8)),
+    dict(algo="phj", passes=2, bits=(13, 8)),
     dict(algo="phj", passes=2, bits=(6, 0)),
     dict(algo="phj", passes=2, bits=(6, 6), tile=3000),
     dict(algo="phj", passes=2, bits=(6, 6), lds_cap=100),
@@ -165,7 +165,7 @@ def test_validation_before_launch(hj):
 @pytest.mark.parametrize("n_r,want", [
     (0, (0, (0, 0))), (1000, (0, (0, 0))), (4416, (0, (0, 0))), (4417, (1, (1, 0))),
     (100000, (1, (5, 0))), (1 << 20, (1, (8, 0))), (1 << 22, (1, (10, 0))), ((1 << 22) + (1 << 12), (2, (6, 5))),
-    (1 << 24, (2, (6, 6))), (3 << 24, (2, (7, 7))),
+    (1 << 24, (2, (6, 6))), (3 << 24, (2, (7, 7))), (1 << 30, (2, (9, 9))), ((1 << 31) - 1, (2, (10, 9))),
 ])
 def test_auto_params(hj, n_r, want):
     """HJ_AUTO: no partitioning up to 4416 R tuples, else ~4096 R tuples per partition

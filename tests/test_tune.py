@@ -15,7 +15,8 @@ def hj():
     return m
 
 
-SIZES = [1, 4416, 4417, 9000, 65536, 100000, 1 << 20, (1 << 22) - 1, 1 << 22, (1 << 22) + 4096, 1 << 24, 3 << 24]
+SIZES = [1, 4416, 4417, 9000, 65536, 100000, 1 << 20, (1 << 22) - 1, 1 << 22, (1 << 22) + 4096, 1 << 24, 3 << 24,
+         1 << 30, (1 << 31) - 1]
 
 
 @pytest.mark.parametrize("n_r", SIZES)
