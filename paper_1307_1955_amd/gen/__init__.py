@@ -214,8 +214,18 @@ def perm_keys(seed: int, stream: int, n: int) -> np.ndarray:
     return (permutation(seed, stream, n) + 1).astype(np.int32)
 
 
+INT32_MAX = (1 << 31) - 1
+
+
+def check_key_domain(domain: int) -> None:
+    """Keys 1..domain must be int32 values."""
+    if not 1 <= domain <= INT32_MAX:
+        raise ValueError("key domain 1..%d does not fit int32 keys" % domain)
+
+
 def uniform_keys(seed: int, stream: int, count: int, domain: int) -> np.ndarray:
-    """Keys drawn uniformly from ``1..domain``."""
+    """Keys drawn uniformly from ``1..domain`` (domain <= 2^31 - 1)."""
+    check_key_domain(domain)
     return uniform_int(seed, stream, 0, count, 1, domain).astype(np.int32)
 
 

@@ -13,7 +13,7 @@ import threading
 import numpy as np
 import torch
 
-from . import (STREAM_R_KEYS, STREAM_S_KEYS, JobSpec, feistel_half_bits, feistel_round_keys,
+from . import (STREAM_R_KEYS, STREAM_S_KEYS, JobSpec, check_key_domain, feistel_half_bits, feistel_round_keys,
                stream_key, zipf_cdf)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "libhjgen.so")
@@ -60,6 +60,7 @@ def perm_keys(seed: int, stream: int, n: int, device="cuda", out: torch.Tensor |
 
 def uniform_keys(seed: int, stream: int, count: int, domain: int, device="cuda",
                  out: torch.Tensor | None = None) -> torch.Tensor:
+    check_key_domain(domain)
     out = torch.empty(count, dtype=torch.int32, device=device) if out is None else out
     if count:
         _ok(load().hjgen_uniform(out.data_ptr(), count, stream_key(seed, stream), 1, domain, _s()))

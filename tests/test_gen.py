@@ -108,3 +108,10 @@ def test_poisson_arrivals():
     gaps = np.diff(np.concatenate([[0.0], t]))
     assert np.all(gaps >= 0)
     assert abs(gaps.mean() - 1 / 50.0) < 6 * (1 / 50.0) / math.sqrt(len(gaps))
+
+
+def test_key_domain_fits_int32():
+    gen.check_key_domain((1 << 31) - 1)
+    for bad in (0, 1 << 31, 3 << 30):
+        with pytest.raises(ValueError):
+            gen.uniform_keys(1, 2, 10, bad)
