@@ -56,8 +56,9 @@ typedef enum hj_status {
 } hj_status;
 
 /* HJ_AUTO: the library picks PHJ parameters from |R| (no partitioning up to
-   4416 R tuples, else about 4096 R tuples per partition: one pass up to 10
-   radix bits, two passes above); hash, tile, lds_cap and flags are kept.
+   4416 R tuples, else about 4096 R tuples per partition -- up to 5120 when
+   that takes more than 16 radix bits -- in one pass up to 10 radix bits, two
+   passes above); hash, tile, lds_cap and flags are kept.
    hj_resolve_params shows the choice. */
 typedef enum hj_algo { HJ_SHJ = 0, HJ_PHJ = 1, HJ_AUTO = 2 } hj_algo;
 

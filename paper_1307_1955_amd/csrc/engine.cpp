@@ -98,6 +98,12 @@ void auto_params(uint64_t n_r, hj_params* p) {
     }
     uint32_t B = 0;
     while (B < kMaxRadixBits && (n_r >> B) > 4096) ++B;
+    if (B > kAutoWideFromBits) {
+        // with this many bits the partitioning passes lose more than a bigger
+        // LDS table costs the join: allow up to 5120 R tuples per partition
+        B = 0;
+        while (B < kMaxRadixBits && (n_r >> B) > 5120) ++B;
+    }
     if (B <= kAutoOnePassMaxBits) {
         p->passes = 1;
         p->bits[0] = B;

@@ -84,6 +84,7 @@ def _bits_for(n_r: int, target: int = 4096) -> int:
 # partition, one pass up to AUTO_ONE_PASS_MAX_BITS radix bits.
 AUTO_DIRECT_MAX = 4416
 AUTO_ONE_PASS_MAX_BITS = 10
+AUTO_WIDE_FROM_BITS = 16  # above this, partitions of up to 5120 R tuples
 
 
 def auto_candidate(n_r: int) -> Candidate:
@@ -91,6 +92,8 @@ def auto_candidate(n_r: int) -> Candidate:
     if n_r <= AUTO_DIRECT_MAX:
         return Candidate("phj", 0)
     b = _bits_for(n_r)
+    if b > AUTO_WIDE_FROM_BITS:
+        b = _bits_for(n_r, 5120)
     if b <= AUTO_ONE_PASS_MAX_BITS:
         return Candidate("phj", 1, (b, 0))
     return Candidate("phj", 2, ((b + 1) // 2, b // 2))

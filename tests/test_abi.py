@@ -166,10 +166,12 @@ def test_validation_before_launch(hj):
     (0, (0, (0, 0))), (1000, (0, (0, 0))), (4416, (0, (0, 0))), (4417, (1, (1, 0))),
     (100000, (1, (5, 0))), (1 << 20, (1, (8, 0))), (1 << 22, (1, (10, 0))), ((1 << 22) + (1 << 12), (2, (6, 5))),
     (1 << 24, (2, (6, 6))), (3 << 24, (2, (7, 7))), (1 << 30, (2, (9, 9))), ((1 << 31) - 1, (2, (10, 9))),
+    (300_000_000, (2, (8, 8))), (1_200_000_000, (2, (9, 9))), (80_000_000, (2, (8, 7))),
 ])
 def test_auto_params(hj, n_r, want):
     """HJ_AUTO: no partitioning up to 4416 R tuples, else ~4096 R tuples per partition
-    (B = smallest with |R| >> B <= 4096; one pass up to 10 bits, else split (B+1)/2, B/2)."""
+    (B = smallest with |R| >> B <= 4096, or <= 5120 when that B exceeds 16; one pass up
+    to 10 bits, else split (B+1)/2, B/2)."""
     for flags in (0, hj.HJ_FLAG_ONE_PASS):
         p = hj.params("auto", one_pass=bool(flags))
         q = hj.hj_resolve_params(p, n_r, 1000)

@@ -16,7 +16,7 @@ def hj():
 
 
 SIZES = [1, 4416, 4417, 9000, 65536, 100000, 1 << 20, (1 << 22) - 1, 1 << 22, (1 << 22) + 4096, 1 << 24, 3 << 24,
-         1 << 30, (1 << 31) - 1]
+         1 << 30, (1 << 31) - 1, 80_000_000, 300_000_000, 1_200_000_000]
 
 
 @pytest.mark.parametrize("n_r", SIZES)
