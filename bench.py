@@ -261,7 +261,21 @@ def cpu_baseline(n: int, min_seconds: float = 10.0, max_reps: int = 6) -> dict:
     el = sum(times) / len(times)
     return {"value": (len(r) + len(s)) / el, "unit": "tuples/s", "cores": 1, "kind": "oracle",
             "sample": "%d full %d x %d joins (build + probe + emit %d pairs), %.2f s each on average"
-                      % (len(times), len(r), len(s), pairs, el)}
+                      % (len(times), len(r), len(s), pairs, el), "host": host_cpu()}
+
+
+def host_cpu() -> str:
+    """The host CPU model and logical CPU count, for the CPU baseline record."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%s, %d logical CPUs (%d usable here)" % (model or "unknown CPU", os.cpu_count() or 0, host_threads())
 
 
 def host_threads() -> int:
@@ -293,7 +307,8 @@ def cpu_baseline_all_cores(n: int, min_seconds: float = 10.0, max_reps: int = 6)
     return {"value": (len(r) + len(s)) / el, "unit": "tuples/s", "cores": threads, "kind": "oracle",
             "sample": "%d full %d x %d joins on %d threads (single-threaded build %.2f s, then the probe split "
                       "over S; %d pairs), %.2f s each on average"
-                      % (len(times), len(r), len(s), threads, sum(build) / len(build), pairs, el)}
+                      % (len(times), len(r), len(s), threads, sum(build) / len(build), pairs, el),
+            "host": host_cpu()}
 
 
 def measure_phj(hj, torch, p, t, out_r, out_s, d_count, n_r, n_s, steps, warmup, passes, one_pass):
