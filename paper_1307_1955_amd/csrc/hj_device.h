@@ -232,41 +232,6 @@ __device__ __forceinline__ uint32_t lds_excl_scan(uint32_t* a, uint32_t n, uint3
     return total;
 }
 
-// In-place exclusive scan of an LDS array a[0..n) by the whole block, for
-// n <= blockDim.x * kMaxE: thread t owns the run [t*E, t*E + E), E =
-// ceil(n / blockDim.x), which it sums in registers; one wave scan of the run
-// sums and one exchange of wave totals (through `wave_tot`, >= blockDim/64
-// entries) give every run its offset.  One barrier inside; callers sync before
-// reading `a`.  Returns the total.
-template <uint32_t kMaxE>
-__device__ __forceinline__ uint32_t lds_excl_scan_runs(uint32_t* a, uint32_t n, uint32_t* wave_tot) {
-    const uint32_t E = (n + blockDim.x - 1) / blockDim.x;
-    const uint32_t b = threadIdx.x * E;
-    const uint32_t w = threadIdx.x / kWave;
-    uint32_t v[kMaxE];
-    uint32_t s = 0;
-#pragma unroll
-    for (uint32_t e = 0; e < kMaxE; ++e) {
-        v[e] = (e < E && b + e < n) ? a[b + e] : 0u;
-        s += v[e];
-    }
-    const uint32_t incl = wave_incl_scan(s);
-    if (lane_id() == kWave - 1) wave_tot[w] = incl;
-    __syncthreads();
-    uint32_t off = incl - s, total = 0;
-    for (uint32_t i = 0; i < blockDim.x / kWave; ++i) {
-        const uint32_t t = wave_tot[i];
-        off += i < w ? t : 0u;
-        total += t;
-    }
-#pragma unroll
-    for (uint32_t e = 0; e < kMaxE; ++e) {
-        if (e < E && b + e < n) a[b + e] = off;
-        off += v[e];
-    }
-    return total;
-}
-
 // Scratch entries `lds_excl_scan` needs (one per wave of the largest block).
 constexpr uint32_t kScanScratch = 16;
 
