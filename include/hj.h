@@ -289,6 +289,14 @@ hj_status hj_server_create(const hj_server_config* cfg, void* ws, size_t ws_byte
 hj_status hj_server_submit(hj_server* server, const hj_job* job, const hj_params* params, uint64_t footprint,
                            uint64_t* ticket);
 
+/* Queues a probe of a resident table (hj_build) by S (thread-safe, returns at
+   once): the request runs hj_probe on a slot, so relations and their tables
+   built once stay on the device and serve many requests.  The table and
+   everything it points to must stay alive until the request has finished.
+   footprint: as for hj_server_submit (S, output and probe workspace). */
+hj_status hj_server_submit_probe(hj_server* server, const hj_table* table, const hj_rel* S, const hj_out* out,
+                                 uint64_t* d_count, uint64_t footprint, uint64_t* ticket);
+
 /* Moves up to `max` finished requests out of the server: ticket, status
    (HJ_OK, HJ_ERR_CAPACITY if rejected by admission, HJ_ERR_DEVICE), seconds
    from submission to completion and from submission to admission.  *n gets

@@ -59,6 +59,9 @@ size_t ws_bytes_for(const Plan& pl, uint64_t n_r, uint64_t n_s);
 // Split join (hj_build / hj_probe): build and probe workspace bytes.
 size_t table_bytes_for(const Plan& pl, uint64_t n_r);
 size_t probe_bytes_for(const Plan& pl, uint64_t n_r, uint64_t n_s);
+// The plan a table was built with (hj_build), after checking the table's own
+// fields, for a probe of n_s tuples.
+hj_status table_plan(const hj_table* t, uint64_t n_s, Plan* pl);
 // Enqueues the build of R's table into ws (table_bytes_for bytes).
 void run_build(const Plan& pl, const hj_rel& R, void* ws, Recorder& rec);
 // Enqueues a probe of table t (built with plan pl) by S.

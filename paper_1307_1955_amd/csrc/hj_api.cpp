@@ -113,23 +113,6 @@ hj_status hj_build(const hj_params* p, const hj_rel* R, void* ws, size_t ws_byte
     return HJ_OK;
 }
 
-namespace {
-// The plan a table was built with, after checking the table's own fields.
-hj_status table_plan(const hj_table* t, uint64_t n_s, Plan* pl) {
-    if (!t) return fail(HJ_ERR_INVALID, "table is NULL");
-    if (t->n_r > kMaxRows) return fail(HJ_ERR_INVALID, "table: relations must have fewer than 2^31 tuples");
-    hj_status st = check_params(&t->params, t->n_r, n_s, pl);
-    if (st != HJ_OK) return st;
-    if (t->params.algo == HJ_AUTO || (pl->phj && t->params.tile == 0))
-        return fail(HJ_ERR_INVALID, "table parameters are not the ones hj_build filled in");
-    if (!t->ws || t->ws_bytes < table_bytes_for(*pl, t->n_r))
-        return fail(HJ_ERR_INVALID, "table: build workspace missing or too small");
-    const bool reads_r = !pl->phj || pl->passes == 0;
-    if (t->n_r && reads_r && (!t->r_rid || (pl->phj && !t->r_key)))
-        return fail(HJ_ERR_INVALID, "table: R's arrays are needed by this probe");
-    return HJ_OK;
-}
-}  // namespace
 
 size_t hj_probe_workspace_bytes(const hj_table* table, uint64_t n_s) {
     Plan pl;

@@ -41,6 +41,8 @@ using Clock = std::chrono::steady_clock;
 struct Request {
     uint64_t ticket;
     hj_job job;
+    bool probe = false;  // a probe of `table` by job.S (else a join of job.R and job.S)
+    hj_table table{};
     Plan plan;
     uint64_t footprint;
     size_t ws;
@@ -98,7 +100,7 @@ hj_status launch_slot(hj_server* sv, Slot& s) {
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         const Request& r = s.reqs[i];
         const uint32_t it = (r.job.R.n && r.job.S.n) ? (uint32_t)cdiv(r.job.S.n, hj::kJoinChunk) : 0u;
-        if (r.plan.phj && r.plan.passes == 0 && items + it <= sv->cfg.max_batch_jobs * kItemsPerJob) {
+        if (!r.probe && r.plan.phj && r.plan.passes == 0 && items + it <= sv->cfg.max_batch_jobs * kItemsPerJob) {
             hj::DirectJob& d = s.h_djobs[nd];
             std::memset(&d, 0, sizeof d);
             d.rk = r.job.R.key;
@@ -136,7 +138,10 @@ hj_status launch_slot(hj_server* sv, Slot& s) {
     }
     for (size_t i : piped) {
         const Request& r = s.reqs[i];
-        run_join(r.plan, r.job.R, r.job.S, r.job.out, s.ws + sv->slot_pipe_off, r.job.d_count, rec);
+        if (r.probe)
+            run_probe(r.plan, r.table, r.job.S, r.job.out, s.ws + sv->slot_pipe_off, r.job.d_count, rec);
+        else
+            run_join(r.plan, r.job.R, r.job.S, r.job.out, s.ws + sv->slot_pipe_off, r.job.d_count, rec);
     }
     if (rec.err != hipSuccess) return fail(HJ_ERR_DEVICE, "server launch failed: %s", hipGetErrorString(rec.err));
     hipError_t e = hipEventRecord(s.done, s.stream);
@@ -311,6 +316,38 @@ hj_status hj_server_submit(hj_server* sv, const hj_job* job, const hj_params* pa
     r.job = *job;
     r.footprint = footprint;
     r.ws = ws_bytes_for(r.plan, job->R.n, job->S.n);
+    r.arrival = Clock::now();
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        if (sv->fatal != HJ_OK) return fail(sv->fatal, "server stopped after a device error");
+        r.ticket = sv->next_ticket++;
+        *ticket = r.ticket;
+        sv->pending.push_back(r);
+    }
+    sv->cv.notify_all();
+    clear_error();
+    return HJ_OK;
+}
+
+hj_status hj_server_submit_probe(hj_server* sv, const hj_table* table, const hj_rel* S, const hj_out* out,
+                                 uint64_t* d_count, uint64_t footprint, uint64_t* ticket) {
+    if (!sv || !table || !S || !out || !d_count || !ticket)
+        return fail(HJ_ERR_INVALID, "server, table, S, out, d_count and ticket must be given");
+    if (S->n > kMaxRows) return fail(HJ_ERR_INVALID, "relations must have < 2^31 tuples");
+    if (S->n && (!S->key || !S->rid)) return fail(HJ_ERR_INVALID, "S has tuples but a NULL array");
+    if (out->capacity && (!out->rid_r || !out->rid_s))
+        return fail(HJ_ERR_INVALID, "out has capacity but a NULL array");
+    Request r;
+    hj_status st = table_plan(table, S->n, &r.plan);
+    if (st != HJ_OK) return st;
+    r.probe = true;
+    r.table = *table;
+    r.job.R = hj_rel{table->r_key, table->r_rid, table->n_r};
+    r.job.S = *S;
+    r.job.out = *out;
+    r.job.d_count = d_count;
+    r.footprint = footprint;
+    r.ws = probe_bytes_for(r.plan, table->n_r, S->n);
     r.arrival = Clock::now();
     {
         std::lock_guard<std::mutex> g(sv->mu);

@@ -38,7 +38,7 @@ EXPORTED = (
     "hj_default_params", "hj_resolve_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
     "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_run",
     "hj_batch_plan_destroy", "hj_batch_bytes", "hj_batch", "hj_table_bytes", "hj_build",
-    "hj_probe_workspace_bytes", "hj_probe", "hj_server_create", "hj_server_submit", "hj_server_poll", "hj_server_drain",
+    "hj_probe_workspace_bytes", "hj_probe", "hj_server_create", "hj_server_submit", "hj_server_submit_probe", "hj_server_poll", "hj_server_drain",
     "hj_server_stats", "hj_server_destroy", "hj_status_str", "hj_last_error", "hj_version",
 )
 
@@ -149,6 +149,9 @@ def load() -> ctypes.CDLL:
             lib.hj_server_submit.restype = ctypes.c_int
             lib.hj_server_submit.argtypes = [ctypes.c_void_p, P(HjJob), P(HjParams), ctypes.c_uint64,
                                              P(ctypes.c_uint64)]
+            lib.hj_server_submit_probe.restype = ctypes.c_int
+            lib.hj_server_submit_probe.argtypes = [ctypes.c_void_p, P(HjTable), P(HjRel), P(HjOut), vp,
+                                                   ctypes.c_uint64, P(ctypes.c_uint64)]
             lib.hj_server_poll.restype = ctypes.c_int
             lib.hj_server_poll.argtypes = [ctypes.c_void_p, P(ctypes.c_uint64), P(ctypes.c_int32),
                                            P(ctypes.c_double), P(ctypes.c_double), ctypes.c_uint32,
@@ -519,6 +522,16 @@ class Server:
                footprint: int) -> int:
         job = make_job(r_key, r_rid, s_key, s_rid, out_r, out_s, d_count.data_ptr())
         return self.submit_job(job, params, footprint, keep=(r_key, r_rid, s_key, s_rid, out_r, out_s, d_count))
+
+    def submit_probe(self, table: "Table", s_key, s_rid, out_r, out_s, d_count: torch.Tensor,
+                     footprint: int) -> int:
+        """Queues a probe of a resident ``Table`` by S; the table must outlive the request."""
+        S, O = _rel(s_key, s_rid, "S"), _out(out_r, out_s)
+        t = ctypes.c_uint64(0)
+        _check(load().hj_server_submit_probe(self._h, ctypes.byref(table.t), ctypes.byref(S), ctypes.byref(O),
+                                             d_count.data_ptr(), footprint, ctypes.byref(t)))
+        self._keep[t.value] = (table, s_key, s_rid, out_r, out_s, d_count)
+        return int(t.value)
 
     def poll(self, max_n: int = 4096):
         """Finished requests: list of (ticket, status, latency_s, queue_s)."""

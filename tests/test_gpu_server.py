@@ -136,3 +136,42 @@ def test_drain_after_only_rejections():
     st = sv.stats()
     assert st["rejected"] == 2 and st["completed"] == 0 and st["bytes_in_use"] == 0
     sv.close()
+
+
+def test_resident_tables_serve_probes():
+    """Tables built once stay on the device and serve probe requests mixed with
+    full joins; every probe equals the oracle's join of the table's R with its S."""
+    r1, _ = gen.unique_uniform(32, 60000, 10, 1)
+    r2, _ = gen.unique_uniform(33, 3000, 10, 1)
+    tabs = [hj.Table(*(torch.from_numpy(a).to(DEV) for a in (r.key, r.rid)), p=p)
+            for r, p in ((r1, hj.params("phj", 2, (4, 3), one_pass=True)), (r2, hj.params("shj")))]
+    rels = [r1, r2]
+    torch.cuda.synchronize()
+    reqs = requests(34, 12, r_max=1 << 15)
+    ws = torch.empty(1 << 29, dtype=torch.uint8, device=DEV)
+    sv = hj.Server(ws, mem_cap_bytes=16 << 30, slots=4, max_batch_jobs=8)
+    counts = torch.zeros(len(reqs) + 20, dtype=torch.int64, device=DEV)
+    probes = []
+    for i in range(20):
+        k = i % 2
+        _, s = gen.unique_uniform(100 + i, 10, 5000 + 997 * i, 2 * len(rels[k]))
+        sk, sr = (torch.from_numpy(a).to(DEV) for a in (s.key, s.rid))
+        o = torch.full((2, len(s)), -1, dtype=torch.int32, device=DEV)
+        c = counts[len(reqs) + i: len(reqs) + i + 1]
+        probes.append((k, s, o, c, sv.submit_probe(tabs[k], sk, sr, o[0], o[1], c, 1 << 20)))
+        if i < len(reqs):
+            r = reqs[i]
+            sv.submit(*r["t"], counts[i:i + 1], r["p"], r["fp"])
+    sv.drain()
+    done = {t: st for t, st, _, _ in sv.poll()}
+    assert all(st == hj.HJ_OK for st in done.values()) and len(done) == 20 + min(20, len(reqs))
+    sv.close()
+    for k, s, o, c, t in probes:
+        n = int(c.item())
+        w_r, w_s = oracle.join(rels[k].key, rels[k].rid, s.key, s.rid)
+        assert n == len(w_r)
+        assert np.array_equal(oracle.canonical(o[0, :n].cpu().numpy(), o[1, :n].cpu().numpy()),
+                              oracle.canonical(w_r, w_s))
+    got = counts[: len(reqs)].cpu().numpy()
+    for i, r in enumerate(reqs):
+        assert int(got[i]) == r["cap"]
