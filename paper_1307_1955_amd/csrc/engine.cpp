@@ -210,7 +210,7 @@ struct PhjWs {
     hj::PartPair* pairs;
     uint32_t* item_begin;
     uint32_t* ovf_begin;
-    uint32_t* item_part;
+    hj::ItemRec* item_rec;
     uint32_t* ovf_part;
     uint64_t* wave_cnt;
     uint64_t* ovf_table;
@@ -251,7 +251,7 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, v
     w.ovf_begin = c.take<uint32_t>(pl.P + 1ull);
     w.items_ub = hj::join_grid(pl.P, n_s);
     w.ovf_ub = hj::ovf_grid(pl.P, n_r_tab);
-    w.item_part = c.take<uint32_t>(w.items_ub);
+    w.item_rec = c.take<hj::ItemRec>(w.items_ub);
     w.ovf_part = c.take<uint32_t>(w.ovf_ub);
     w.wave_cnt = c.take<uint64_t>(w.items_ub * hj::kJoinWaves);
     w.ovf_table = c.take<uint64_t>(2 * n_r_tab);
@@ -424,7 +424,7 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
     plan.blocks = hj::plan_blocks(pl.P, hj::part_block(pl.tile));
     plan.plan = hj::PlanArgs{two ? w.segs2 : w.segs1, two ? w.tb2 : w.tb1, two ? w.hist2 : w.hist1,
                              two ? 2 * pl.P1 : 2u, two ? pl.b2 : pl.b1, n_r, n_s, pl.B, pl.lds_cap,
-                             w.pairs, w.item_begin, w.ovf_begin, w.item_part, w.ovf_part, zero_total, w.stp,
+                             w.pairs, w.item_begin, w.ovf_begin, w.item_rec, w.ovf_part, zero_total, w.stp,
                              r_pairs};
     hj::SideJob setup2{};
     if (two) {
@@ -459,11 +459,11 @@ void phj_join_pairs(const Plan& pl, const PhjWs& w, const int32_t* rk, const int
     hj::join_ovf_build(w.pairs, w.ovf_begin, w.ovf_part, pl.P, (uint32_t)w.ovf_ub, rk, w.ovf_table, w.ovf_next,
                        rec);
     if (!pl.one_pass) {
-        hj::join_count(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, rk, sk, pl.lds_cap,
+        hj::join_count(w.pairs, w.item_begin, w.item_rec, pl.P, (uint32_t)w.items_ub, rk, sk, pl.lds_cap,
                        w.ovf_table, w.ovf_next, w.wave_cnt, rec);
         hj::scan_u64(w.wave_cnt, w.wave_cnt, w.items_ub * hj::kJoinWaves, w.stw, d_count, rec);
     }
-    hj::join_write(w.pairs, w.item_begin, w.item_part, pl.P, (uint32_t)w.items_ub, rk, rr, sk, sr, pl.lds_cap,
+    hj::join_write(w.pairs, w.item_begin, w.item_rec, pl.P, (uint32_t)w.items_ub, rk, rr, sk, sr, pl.lds_cap,
                    w.ovf_table, w.ovf_next, pl.one_pass ? nullptr : w.wave_cnt, d_count, out.rid_r, out.rid_s,
                    out.capacity, rec);
 }

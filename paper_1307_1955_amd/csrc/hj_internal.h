@@ -19,6 +19,13 @@ struct PartSeg {
     uint32_t pad;
 };
 
+// One join work item: an R partition and a chunk of its S partition
+// (positions relative to each relation's base in the scratch arrays).
+struct ItemRec {
+    uint32_t r_off, r_len;
+    uint32_t s_begin, s_n;
+};
+
 // One final partition pair of a PHJ: ranges in the partitioned R and S arrays
 // (positions relative to each relation's base in the scratch arrays).
 struct PartPair {
@@ -133,7 +140,7 @@ struct JoinPlanOut {
     PartPair* pairs;       // [P]
     uint32_t* item_begin;  // [P + 1] exclusive scan of work items per partition
     uint32_t* ovf_begin;   // [P + 1] exclusive scan of HBM-table build chunks per partition
-    uint32_t* item_part;   // [join_grid] partition of every work item
+    ItemRec* item_rec;     // [join_grid] every work item's R range and S chunk
     uint32_t* ovf_part;    // [ovf_grid] partition of every HBM-table build chunk
 };
 // The join plan (final partition table, work-item and overflow-chunk scans and
@@ -148,12 +155,12 @@ size_t join_lds_bytes(uint32_t lds_cap, bool write);
 size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile);
 void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint32_t* ovf_part, uint32_t P,
                     uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, Recorder& rec);
-// item_begin/item_part come from join_plan (JoinPlanOut).
-void join_count(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+// item_begin/item_rec come from the join plan (JoinPlanOut).
+void join_count(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
                 const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec);
-void join_write(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+void join_write(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                 uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,

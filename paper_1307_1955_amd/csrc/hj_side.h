@@ -35,7 +35,7 @@ struct PlanArgs {
     PartPair* pairs;
     uint32_t* item_begin;
     uint32_t* ovf_begin;
-    uint32_t* item_part;
+    ItemRec* item_rec;
     uint32_t* ovf_part;
     uint64_t* zero_total;
     uint64_t* state;
@@ -82,7 +82,8 @@ __device__ __forceinline__ uint32_t ovf_chunks_of(const PartPair& pp, uint32_t l
 // Plan (one thread per partition pair, workgroups in ticket order): ranges of
 // R_i and S_i from the last pass's histogram scan, the pair's work items and
 // HBM-table build chunks, their exclusive scans over all pairs (one chained
-// scan of both counts packed in one word) and the item -> pair maps.
+// scan of both counts packed in one word), the work-item records and the
+// chunk -> pair map.
 // state[0]: ticket; state[1 + b]: status of workgroup b (cleared beforehand).
 // Run by plan_blocks(P, blockDim.x) workgroups.
 __device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
@@ -94,7 +95,7 @@ __device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
     PartPair* __restrict__ pairs = A.pairs;
     uint32_t* __restrict__ item_begin = A.item_begin;
     uint32_t* __restrict__ ovf_begin = A.ovf_begin;
-    uint32_t* __restrict__ item_part = A.item_part;
+    ItemRec* __restrict__ item_rec = A.item_rec;
     uint32_t* __restrict__ ovf_part = A.ovf_part;
     uint64_t* __restrict__ zero_total = A.zero_total;
     uint64_t* state = A.state;
@@ -143,7 +144,9 @@ __device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
         pairs[i] = pp;
         item_begin[i] = ib;
         ovf_begin[i] = ob;
-        for (uint32_t x = 0; x < ni; ++x) item_part[ib + x] = i;
+        for (uint32_t x = 0; x < ni; ++x)
+            item_rec[ib + x] = ItemRec{pp.r_off, pp.r_len, pp.s_off + x * kJoinChunk,
+                                       min(kJoinChunk, pp.s_len - x * kJoinChunk)};
         for (uint32_t x = 0; x < no; ++x) ovf_part[ob + x] = i;
     }
     if (i == P - 1) {  // the last pair also writes the totals

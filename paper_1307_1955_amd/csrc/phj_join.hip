@@ -146,23 +146,24 @@ __device__ __forceinline__ void build_lds(const int32_t* k, uint32_t n, uint32_t
 struct ItemLoc {
     uint32_t item;
     bool live;
-    PartPair pp;
+    uint32_t r_off, r_len;
     uint32_t s_begin, s_n;
 };
 
-__device__ __forceinline__ ItemLoc locate_item(const PartPair* __restrict__ pairs,
-                                               const uint32_t* __restrict__ item_begin,
-                                               const uint32_t* __restrict__ item_part, uint32_t P) {
+// The work item of this workgroup (items spread over the XCDs in proportion to
+// live work): two dependent loads, the live count and the item's record.
+__device__ __forceinline__ ItemLoc locate_item(const uint32_t* __restrict__ item_begin,
+                                               const ItemRec* __restrict__ item_rec, uint32_t P) {
     ItemLoc L;
     const uint32_t live = item_begin[P];
     L.item = live_remap(blockIdx.x, live);
     L.live = L.item < live;
     if (!L.live) return L;
-    const uint32_t i = item_part[L.item];
-    const uint32_t c = L.item - item_begin[i];
-    L.pp = pairs[i];
-    L.s_begin = L.pp.s_off + c * kJoinChunk;
-    L.s_n = min(kJoinChunk, L.pp.s_len - c * kJoinChunk);
+    const ItemRec r = item_rec[L.item];
+    L.r_off = r.r_off;
+    L.r_len = r.r_len;
+    L.s_begin = r.s_begin;
+    L.s_n = r.s_n;
     return L;
 }
 
@@ -363,7 +364,7 @@ __device__ __forceinline__ uint64_t write_round_hbm(const uint32_t* __restrict__
 template <uint32_t RPT>
 __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __restrict__ pairs,
                                                           const uint32_t* __restrict__ item_begin,
-                                                          const uint32_t* __restrict__ item_part,
+                                                          const ItemRec* __restrict__ item_rec,
                                                           uint32_t P, const int32_t* __restrict__ rk,
                                                           const int32_t* __restrict__ sk, uint32_t lds_cap,
                                                           const uint64_t* __restrict__ ovf_table,
@@ -372,7 +373,7 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
     extern __shared__ uint32_t lds[];
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
-    const ItemLoc L = locate_item(pairs, item_begin, item_part, P);
+    const ItemLoc L = locate_item(item_begin, item_rec, P);
     if (!L.live) {
         if (lane == 0) wave_cnt[(uint64_t)L.item * kJoinWaves + w] = 0;
         return;
@@ -380,13 +381,13 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
     const int32_t* __restrict__ skp = sk + L.s_begin;
     uint64_t cnt = 0;
     int32_t q[kSU];
-    if (L.pp.r_len <= lds_cap) {
+    if (L.r_len <= lds_cap) {
         int32_t k[RPT];
-        load_r<RPT>(rk + L.pp.r_off, L.pp.r_len, k);
+        load_r<RPT>(rk + L.r_off, L.r_len, k);
         load_s<false>(skp, nullptr, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, nullptr);
         const LdsView v = lds_view(lds, lds_cap);
-        const uint32_t log2H = table_log2H(L.pp.r_len);
-        build_lds<RPT>(k, L.pp.r_len, log2H, v);
+        const uint32_t log2H = table_log2H(L.r_len);
+        build_lds<RPT>(k, L.r_len, log2H, v);
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             if (sb) load_s<false>(skp, nullptr, wb, we, q, nullptr);
@@ -399,7 +400,7 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             load_s<false>(skp, nullptr, wb, we, q, nullptr);
             uint32_t c[kSU], at[kSU];
-            probe_hbm(ovf_table + 2ull * L.pp.r_off, ovf_next + L.pp.r_off, 2u * L.pp.r_len, q, wb, we, c, at);
+            probe_hbm(ovf_table + 2ull * L.r_off, ovf_next + L.r_off, 2u * L.r_len, q, wb, we, c, at);
 #pragma unroll
             for (uint32_t u = 0; u < kSU; ++u) cnt += c[u];
         }
@@ -414,7 +415,7 @@ template <bool kOnePass, uint32_t RPT>
 __global__ void __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(RPT > kRptMid ? 4 : 6)))
 k_join_write(
     const PartPair* __restrict__ pairs, const uint32_t* __restrict__ item_begin,
-    const uint32_t* __restrict__ item_part, uint32_t P, const int32_t* __restrict__ rk,
+    const ItemRec* __restrict__ item_rec, uint32_t P, const int32_t* __restrict__ rk,
     const int32_t* __restrict__ rr, const int32_t* __restrict__ sk, const int32_t* __restrict__ sr,
     uint32_t lds_cap, const uint64_t* __restrict__ ovf_table,
     const uint32_t* __restrict__ ovf_next, const uint64_t* __restrict__ wave_base,
@@ -423,20 +424,20 @@ k_join_write(
     extern __shared__ uint32_t lds[];
     __shared__ uint64_t wtot[kJoinWaves + 1];
     const uint32_t w = threadIdx.x / kWave;
-    const ItemLoc L = locate_item(pairs, item_begin, item_part, P);
+    const ItemLoc L = locate_item(item_begin, item_rec, P);
     if (!L.live) return;
-    const int32_t* __restrict__ rrp = rr + L.pp.r_off;
+    const int32_t* __restrict__ rrp = rr + L.r_off;
     const int32_t* __restrict__ skp = sk + L.s_begin;
     const int32_t* __restrict__ srp = sr + L.s_begin;
     uint64_t base = kOnePass ? 0ull : wave_base[(uint64_t)L.item * kJoinWaves + w];
     int32_t q[kSU], qr[kSU];
-    if (L.pp.r_len <= lds_cap) {
+    if (L.r_len <= lds_cap) {
         int32_t k[RPT];
-        load_r<RPT>(rk + L.pp.r_off, L.pp.r_len, k);
+        load_r<RPT>(rk + L.r_off, L.r_len, k);
         load_s<true>(skp, srp, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, qr);
         const LdsView v = lds_view(lds, lds_cap);
-        const uint32_t log2H = table_log2H(L.pp.r_len);
-        build_lds<RPT>(k, L.pp.r_len, log2H, v);
+        const uint32_t log2H = table_log2H(L.r_len);
+        build_lds<RPT>(k, L.r_len, log2H, v);
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             if (sb) load_s<true>(skp, srp, wb, we, q, qr);
@@ -448,13 +449,13 @@ k_join_write(
             base = write_round_lds(v, rrp, q, qr, cf, rid0, pos0, capacity, out_r, out_s);
         }
     } else {
-        const uint64_t* __restrict__ region = ovf_table + 2ull * L.pp.r_off;
-        const uint32_t* __restrict__ next = ovf_next + L.pp.r_off;
+        const uint64_t* __restrict__ region = ovf_table + 2ull * L.r_off;
+        const uint32_t* __restrict__ next = ovf_next + L.r_off;
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
             load_s<true>(skp, srp, wb, we, q, qr);
             uint32_t c[kSU], at[kSU];
-            probe_hbm(region, next, 2u * L.pp.r_len, q, wb, we, c, at);
+            probe_hbm(region, next, 2u * L.r_len, q, wb, we, c, at);
             uint64_t mine = 0;
 #pragma unroll
             for (uint32_t u = 0; u < kSU; ++u) mine += c[u];
@@ -596,40 +597,40 @@ void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint
 }
 
 template <uint32_t RPT>
-void join_count_t(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+void join_count_t(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                   uint32_t grid, const int32_t* rk, const int32_t* sk, uint32_t lds_cap,
                   const uint64_t* ovf_table, const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec) {
     const size_t lds = join_lds_bytes(lds_cap, false);
     allow_lds((const void*)k_join_count<RPT>, lds);
     rec.before("join_count");
     hipLaunchKernelGGL(k_join_count<RPT>, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin,
-                       item_part, P, rk, sk, lds_cap, ovf_table, ovf_next, wave_cnt);
+                       item_rec, P, rk, sk, lds_cap, ovf_table, ovf_next, wave_cnt);
     rec.after();
 }
 
-void join_count(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+void join_count(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
                 const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec) {
     if (grid == 0) return;
     switch (join_rpt(lds_cap)) {
         case kRptSmall:
-            join_count_t<kRptSmall>(pairs, item_begin, item_part, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
+            join_count_t<kRptSmall>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
                                     wave_cnt, rec);
             break;
         case kRptMid:
-            join_count_t<kRptMid>(pairs, item_begin, item_part, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
+            join_count_t<kRptMid>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
                                   wave_cnt, rec);
             break;
         default:
-            join_count_t<kRptLarge>(pairs, item_begin, item_part, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
+            join_count_t<kRptLarge>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
                                     wave_cnt, rec);
             break;
     }
 }
 
 template <bool kOnePass, uint32_t RPT>
-void join_write_t(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+void join_write_t(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                   uint32_t grid, const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                   uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
                   const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s, uint64_t capacity,
@@ -638,34 +639,34 @@ void join_write_t(const PartPair* pairs, const uint32_t* item_begin, const uint3
     allow_lds((const void*)k_join_write<kOnePass, RPT>, lds);
     rec.before(kOnePass ? "join_write_1pass" : "join_write");
     hipLaunchKernelGGL((k_join_write<kOnePass, RPT>), dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs,
-                       item_begin, item_part, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, wave_base,
+                       item_begin, item_rec, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, wave_base,
                        (unsigned long long*)total, out_r, out_s, capacity);
     rec.after();
 }
 
 template <bool kOnePass>
-void join_write_p(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+void join_write_p(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                   uint32_t grid, const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                   uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
                   const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s, uint64_t capacity,
                   Recorder& rec) {
     switch (join_rpt(lds_cap)) {
         case kRptSmall:
-            join_write_t<kOnePass, kRptSmall>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap,
+            join_write_t<kOnePass, kRptSmall>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
                                               ovf_table, ovf_next, wave_base, total, out_r, out_s, capacity, rec);
             break;
         case kRptMid:
-            join_write_t<kOnePass, kRptMid>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap,
+            join_write_t<kOnePass, kRptMid>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
                                             ovf_table, ovf_next, wave_base, total, out_r, out_s, capacity, rec);
             break;
         default:
-            join_write_t<kOnePass, kRptLarge>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap,
+            join_write_t<kOnePass, kRptLarge>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
                                               ovf_table, ovf_next, wave_base, total, out_r, out_s, capacity, rec);
             break;
     }
 }
 
-void join_write(const PartPair* pairs, const uint32_t* item_begin, const uint32_t* item_part, uint32_t P,
+void join_write(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                 uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
@@ -673,10 +674,10 @@ void join_write(const PartPair* pairs, const uint32_t* item_begin, const uint32_
                 uint64_t capacity, Recorder& rec) {
     if (grid == 0) return;
     if (wave_base == nullptr)
-        join_write_p<true>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
+        join_write_p<true>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
                            wave_base, total, out_r, out_s, capacity, rec);
     else
-        join_write_p<false>(pairs, item_begin, item_part, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
+        join_write_p<false>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
                             wave_base, total, out_r, out_s, capacity, rec);
 }
 
