@@ -67,14 +67,14 @@ __device__ __forceinline__ void chain_insert(uint64_t* table, uint32_t* next, ui
             if (cur == kEmptySlot) return;
         }
         if ((uint32_t)cur == (uint32_t)k) {
-            // Key present: push the row in front of its chain.
-            while (true) {
-                next[row] = (uint32_t)(cur >> 32);
-                const uint64_t prev = atomicCAS((unsigned long long*)&table[s], (unsigned long long)cur,
-                                                (unsigned long long)chain_slot(k, row));
-                if (prev == cur) return;
-                cur = prev;
-            }
+            // Key present: push the row in front of its chain with one exchange,
+            // which cannot fail (a claimed slot keeps its key), so duplicates of a
+            // heavy key cost one atomic each instead of compare-and-swap retries
+            // that grow with the contention.  The row's link is written after
+            // the exchange: tables are read only after the build launch ends.
+            const uint64_t prev = atomicExch((unsigned long long*)&table[s], (unsigned long long)chain_slot(k, row));
+            next[row] = (uint32_t)(prev >> 32);
+            return;
         }
         s = step(s);
     }
