@@ -217,18 +217,132 @@ __device__ __forceinline__ void probe_lds(const LdsView& v, uint32_t log2H, cons
     }
 }
 
-// Matches of the lane's kSU S keys in the partition-local HBM table.
+// Keys whose row chain is longer than heavy_limit(r_len) are "heavy" (the
+// duplicate-heavy keys of a skewed R): instead of one lane walking the chain,
+// the whole workgroup scans the partition's keys for them (Section 3.3's
+// remedy for workload divergence: work of very different size is not left to
+// single lanes of one wave).  The scan takes about 2 r_len / kJoinBlock block
+// steps (count and write), the walk c dependent loads, so a chain is heavy
+// only when it is longer than both kHeavyChain and r_len / 256.
+constexpr uint32_t kHeavyChain = 64;
+__device__ __forceinline__ uint32_t heavy_limit(uint32_t r_len) { return max(kHeavyChain, r_len >> 8); }
+// Heavy keys a workgroup handles cooperatively per probe round; more fall back
+// to walking their chains.
+constexpr uint32_t kMaxHeavy = 32;
+// In c[u]: a registered heavy entry, its index in the low bits (counts stay
+// below 2^31: R_i has fewer than 2^31 tuples).
+constexpr uint32_t kHeavyBit = 0x80000000u;
+__device__ __forceinline__ bool is_heavy(uint32_t c) { return (c & kHeavyBit) != 0; }
+
+// The heavy entries of a probe round (LDS).
+struct HeavySet {
+    uint32_t n;                  // entries registered (may exceed kMaxHeavy: the rest walk)
+    int32_t key[kMaxHeavy];
+    int32_t srid[kMaxHeavy];
+    uint32_t cnt[kMaxHeavy];     // exact match counts
+    uint64_t pos[kMaxHeavy];     // first output slot (one-pass: absolute; two-pass: absolute too)
+    uint32_t wsum[kJoinWaves];   // scratch for block reductions / ranks
+};
+
+// Length of the chain at head field h, or lim + 1 if longer.
+__device__ __forceinline__ uint32_t chain_len_bounded(const uint32_t* __restrict__ next, uint32_t h, uint32_t lim) {
+    uint32_t c = 1;
+    while (!(h & kLast) && c <= lim) {
+        h = next[h];
+        ++c;
+    }
+    return c;
+}
+
+// Matches of the lane's kSU S keys in the partition-local HBM table (H = 2
+// r_len slots).  A key with a chain longer than heavy_limit(r_len) is
+// registered in `hs` (c[u] = kHeavyBit | its index) when there is room, else
+// counted by walking.
+// hs->n must be zero and visible to the block before the call.
 __device__ __forceinline__ void probe_hbm(const uint64_t* __restrict__ region, const uint32_t* __restrict__ next,
-                                          uint32_t H, const int32_t* q, uint32_t wb, uint32_t we, uint32_t* c,
-                                          uint32_t* at) {
+                                          uint32_t H, const int32_t* q, const int32_t* qr, uint32_t wb,
+                                          uint32_t we, uint32_t* c, uint32_t* at, HeavySet* hs) {
     const RegionStep step{H};
+    const uint32_t lim = heavy_limit(H / 2);
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
         c[u] = 0;
         at[u] = kNotFound;
         if (wb + u * kWave + lane_id() < we) {
             at[u] = chain_find(region, region_slot(q[u], H), q[u], step);
-            if (at[u] != kNotFound) c[u] = chain_len(next, at[u]);
+            if (at[u] != kNotFound) {
+                c[u] = chain_len_bounded(next, at[u], lim);
+                if (c[u] > lim) {
+                    const uint32_t e = atomicAdd(&hs->n, 1u);
+                    if (e < kMaxHeavy) {
+                        hs->key[e] = q[u];
+                        hs->srid[e] = qr ? qr[u] : 0;
+                        c[u] = kHeavyBit | e;
+                    } else {
+                        c[u] = chain_len(next, at[u]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Exact counts of the registered heavy keys: the workgroup scans R_i's keys
+// once per entry (coalesced, ballot counts per wave).  All threads call it.
+__device__ __forceinline__ void heavy_counts(const int32_t* __restrict__ rk_i, uint32_t r_len, HeavySet* hs) {
+    __syncthreads();  // registrations done
+    const uint32_t ne = min(hs->n, kMaxHeavy);
+    const uint32_t w = threadIdx.x / kWave;
+    for (uint32_t e = 0; e < ne; ++e) {
+        const int32_t k = hs->key[e];
+        uint32_t m = 0;
+        for (uint32_t j = threadIdx.x; j < r_len; j += kJoinBlock) m += rk_i[j] == k;
+        m = wave_sum(m);
+        if (lane_id() == 0) hs->wsum[w] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (uint32_t i = 0; i < kJoinWaves; ++i) t += hs->wsum[i];
+            hs->cnt[e] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Writes the matches of every registered heavy key from its slot hs->pos[e]
+// on: the workgroup scans R_i in order and ranks the matches block-wide.
+// Slots at or past `capacity` are not written.  All threads call it.
+__device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk_i, const int32_t* __restrict__ rr_i,
+                                             uint32_t r_len, HeavySet* hs, uint64_t capacity,
+                                             int32_t* __restrict__ out_r, int32_t* __restrict__ out_s) {
+    __syncthreads();  // positions published
+    const uint32_t ne = min(hs->n, kMaxHeavy);
+    const uint32_t w = threadIdx.x / kWave;
+    for (uint32_t e = 0; e < ne; ++e) {
+        const int32_t k = hs->key[e];
+        const int32_t rs = hs->srid[e];
+        uint64_t pos = hs->pos[e];
+        for (uint32_t j0 = 0; j0 < r_len; j0 += kJoinBlock) {
+            const uint32_t j = j0 + threadIdx.x;
+            const bool hit = j < r_len && rk_i[j] == k;
+            const uint64_t mask = __ballot(hit);
+            if (lane_id() == 0) hs->wsum[w] = (uint32_t)__popcll(mask);
+            __syncthreads();
+            uint32_t before = 0, all = 0;
+            for (uint32_t i = 0; i < kJoinWaves; ++i) {
+                const uint32_t t = hs->wsum[i];
+                before += i < w ? t : 0u;
+                all += t;
+            }
+            if (hit) {
+                const uint64_t at = pos + before + (uint32_t)__popcll(mask & lanemask_lt());
+                if (at < capacity) {
+                    out_r[at] = rr_i[j];
+                    out_s[at] = rs;
+                }
+            }
+            pos += all;
+            __syncthreads();  // wsum reused
         }
     }
 }
@@ -333,18 +447,24 @@ __device__ __forceinline__ void fetch_first_rids(const int32_t* __restrict__ rrp
 
 // The same for the partition-local HBM table: c[u] matches on the row chain
 // that starts at at[u].
+// Heavy entries (is_heavy(c[u])) take their count from hs and only publish
+// their first slot in hs->pos; heavy_writes writes them.
 __device__ __forceinline__ uint64_t write_round_hbm(const uint32_t* __restrict__ next,
                                                     const int32_t* __restrict__ rrp, const int32_t* qr,
-                                                    const uint32_t* c, const uint32_t* at, uint64_t pos0,
-                                                    uint64_t capacity, int32_t* __restrict__ out_r,
-                                                    int32_t* __restrict__ out_s) {
+                                                    const uint32_t* c, const uint32_t* at,
+                                                    HeavySet* hs, uint64_t pos0, uint64_t capacity,
+                                                    int32_t* __restrict__ out_r, int32_t* __restrict__ out_s) {
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
+        const bool heavy = is_heavy(c[u]);
+        const uint32_t cu = heavy ? hs->cnt[c[u] & ~kHeavyBit] : c[u];
         uint64_t excl, wtotal;
-        wave_offsets(c[u], &excl, &wtotal);
+        wave_offsets(cu, &excl, &wtotal);
         uint64_t pos = pos0 + excl;
         pos0 += wtotal;
-        if (c[u]) {
+        if (heavy) {
+            hs->pos[c[u] & ~kHeavyBit] = pos;
+        } else if (cu) {
             uint32_t h = at[u];
             while (true) {
                 const uint32_t row = h & ~kLast;
@@ -359,6 +479,32 @@ __device__ __forceinline__ uint64_t write_round_hbm(const uint32_t* __restrict__
         }
     }
     return pos0;
+}
+
+// Count pass over a partition whose R exceeds the LDS table: probes the
+// partition-local HBM table and returns this lane's pair count.  hs takes the
+// LDS the table would have used.  Inlined: a call would give the kernel a
+// stack, and the LDS path measured a few percent slower with one.
+__device__ __forceinline__ uint64_t join_count_hbm(const ItemLoc L, uint32_t w,
+                                                             const int32_t* __restrict__ rk,
+                                                             const int32_t* __restrict__ skp,
+                                                             const uint64_t* __restrict__ ovf_table,
+                                                             const uint32_t* __restrict__ ovf_next, HeavySet* hs) {
+    uint64_t cnt = 0;
+    int32_t q[kSU];
+    for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
+        const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
+        load_s<false>(skp, nullptr, wb, we, q, nullptr);
+        if (threadIdx.x == 0) hs->n = 0;
+        __syncthreads();
+        uint32_t c[kSU], at[kSU];
+        probe_hbm(ovf_table + 2ull * L.r_off, ovf_next + L.r_off, 2u * L.r_len, q, nullptr, wb, we, c, at, hs);
+        heavy_counts(rk + L.r_off, L.r_len, hs);
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) cnt += is_heavy(c[u]) ? hs->cnt[c[u] & ~kHeavyBit] : c[u];
+        __syncthreads();  // the set is reused by the next round
+    }
+    return cnt;
 }
 
 template <uint32_t RPT>
@@ -396,17 +542,39 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
             cnt += lane_pairs_lds(cf);
         }
     } else {
-        for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
-            const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
-            load_s<false>(skp, nullptr, wb, we, q, nullptr);
-            uint32_t c[kSU], at[kSU];
-            probe_hbm(ovf_table + 2ull * L.r_off, ovf_next + L.r_off, 2u * L.r_len, q, wb, we, c, at);
-#pragma unroll
-            for (uint32_t u = 0; u < kSU; ++u) cnt += c[u];
-        }
+        cnt = join_count_hbm(L, w, rk, skp, ovf_table, ovf_next, reinterpret_cast<HeavySet*>(lds));
     }
     cnt = wave_sum(cnt);
     if (lane == 0) wave_cnt[(uint64_t)L.item * kJoinWaves + w] = cnt;
+}
+
+// Write pass over a partition whose R exceeds the LDS table (see
+// join_count_hbm).
+template <bool kOnePass>
+__device__ __forceinline__ void join_write_hbm(
+    const ItemLoc L, uint32_t w, const int32_t* __restrict__ rk, const int32_t* __restrict__ rrp,
+    const int32_t* __restrict__ skp, const int32_t* __restrict__ srp, const uint64_t* __restrict__ ovf_table,
+    const uint32_t* __restrict__ ovf_next, uint64_t base, unsigned long long* __restrict__ total, uint64_t* wtot,
+    int32_t* __restrict__ out_r, int32_t* __restrict__ out_s, uint64_t capacity, HeavySet* hs) {
+    const uint64_t* __restrict__ region = ovf_table + 2ull * L.r_off;
+    const uint32_t* __restrict__ next = ovf_next + L.r_off;
+    int32_t q[kSU], qr[kSU];
+    for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
+        const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
+        load_s<true>(skp, srp, wb, we, q, qr);
+        if (threadIdx.x == 0) hs->n = 0;
+        __syncthreads();
+        uint32_t c[kSU], at[kSU];
+        probe_hbm(region, next, 2u * L.r_len, q, qr, wb, we, c, at, hs);
+        heavy_counts(rk + L.r_off, L.r_len, hs);
+        uint64_t mine = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < kSU; ++u) mine += is_heavy(c[u]) ? hs->cnt[c[u] & ~kHeavyBit] : c[u];
+        const uint64_t pos0 = kOnePass ? block_reserve(mine, total, wtot, sb != 0) : base;
+        base = write_round_hbm(next, rrp, qr, c, at, hs, pos0, capacity, out_r, out_s);
+        heavy_writes(rk + L.r_off, rrp, L.r_len, hs, capacity, out_r, out_s);
+        __syncthreads();  // the set is reused by the next round
+    }
 }
 
 // Write pass.  kOnePass: instead of reading a scanned per-wave offset, each
@@ -449,19 +617,8 @@ k_join_write(
             base = write_round_lds(v, rrp, q, qr, cf, rid0, pos0, capacity, out_r, out_s);
         }
     } else {
-        const uint64_t* __restrict__ region = ovf_table + 2ull * L.r_off;
-        const uint32_t* __restrict__ next = ovf_next + L.r_off;
-        for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
-            const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
-            load_s<true>(skp, srp, wb, we, q, qr);
-            uint32_t c[kSU], at[kSU];
-            probe_hbm(region, next, 2u * L.r_len, q, wb, we, c, at);
-            uint64_t mine = 0;
-#pragma unroll
-            for (uint32_t u = 0; u < kSU; ++u) mine += c[u];
-            const uint64_t pos0 = kOnePass ? block_reserve(mine, total, wtot, sb != 0) : base;
-            base = write_round_hbm(next, rrp, qr, c, at, pos0, capacity, out_r, out_s);
-        }
+        join_write_hbm<kOnePass>(L, w, rk, rrp, skp, srp, ovf_table, ovf_next, base, total, wtot, out_r, out_s,
+                                 capacity, reinterpret_cast<HeavySet*>(lds));
     }
 }
 
@@ -524,6 +681,8 @@ __global__ void k_write_zero(uint64_t* p) {
 }  // namespace
 
 size_t join_lds_bytes(uint32_t lds_cap, bool /*write*/) {
+    static_assert(sizeof(HeavySet) <= sizeof(uint32_t) * (256 + 2 * kWave) + sizeof(uint64_t) * 256,
+                  "the heavy-key set fits the smallest table area");
     return sizeof(uint32_t) * ((size_t)lds_cap + 2 * kWave) + sizeof(uint64_t) * lds_cap;
 }
 

@@ -124,6 +124,54 @@ def test_r_side_skew(kw, frac):
     check_small(hj.params(**kw), rk, r.rid, sk, s.rid)
 
 
+@pytest.mark.parametrize("kw", [dict(algo="phj", passes=2, bits=(4, 4), lds_cap=256),
+                                dict(algo="phj", passes=2, bits=(4, 4), lds_cap=256, one_pass=True),
+                                dict(algo="phj", passes=1, bits=(5,), one_pass=True)])
+def test_heavy_keys_hbm_path(kw):
+    """Partitions beyond the LDS budget (identity hash: the partition is the key's low
+    bits) with chains of very different length.  Partition 146 (mod 256) holds one key
+    with 30000 R duplicates and 64 keys with 100 each, below that partition's heavy
+    limit (r_len / 256), so those are walked; partition 239 holds a key with 3000
+    duplicates and 16 keys with 100 each, all heavy there.  S matches them from many
+    work items and rounds, 40 tuples of one key in one round (more than a round's
+    heavy set holds)."""
+    rng = np.random.default_rng(21)
+    n_r, n_s = 60001, 150001
+    special = np.concatenate([np.full(30000, 4242), np.repeat((1 << 21) + 146 + 256 * np.arange(64), 100),
+                              np.full(3000, -17), np.repeat((1 << 22) + 239 + 256 * np.arange(16), 100)])
+    rk = np.concatenate([special, rng.integers(0, 1 << 20, size=n_r - len(special))]).astype(np.int32)
+    rk = rk[rng.permutation(n_r)]
+    sk = rng.integers(0, 1 << 20, size=n_s).astype(np.int32)
+    sk[rng.choice(n_s, 60, replace=False)] = 4242
+    sk[rng.choice(n_s, 500, replace=False)] = (1 << 21) + 146 + 256 * rng.integers(0, 64, size=500)
+    sk[rng.choice(n_s, 200, replace=False)] = (1 << 22) + 239 + 256 * rng.integers(0, 16, size=200)
+    sk[:40] = -17
+    assert 4242 % 256 == 146 and (-17) % 256 == 239
+    rr = rng.permutation(n_r).astype(np.int32)
+    sr = rng.permutation(n_s).astype(np.int32) + 7
+    check_small(hj.params(**kw), rk, rr, sk, sr)
+    # a too-small output: the full count, only valid pairs below capacity, nothing past it
+    want_r, want_s = oracle.join(rk, rr, sk, sr)
+    want = len(want_r)
+    cap = want // 2
+    p = hj.params(**kw)
+    buf_r = torch.full((want,), -9, dtype=torch.int32, device=DEV)
+    buf_s = torch.full((want,), -9, dtype=torch.int32, device=DEV)
+    ws = hj.workspace(p, n_r, n_s)
+    d = torch.zeros(1, dtype=torch.int64, device=DEV)
+    hj.hj_join(p, *to_dev(rk, rr, sk, sr), buf_r[:cap], buf_s[:cap], ws, d)
+    torch.cuda.synchronize()
+    assert int(d.item()) == want
+    assert torch.all(buf_r[cap:] == -9) and torch.all(buf_s[cap:] == -9)
+    got = oracle.canonical(buf_r[:cap].cpu().numpy(), buf_s[:cap].cpu().numpy())
+    allp = oracle.canonical(want_r, want_s)
+    # every written pair is a pair of the join, and no pair is written twice
+    key = lambda a: a[:, 0].astype(np.int64) * (1 << 32) + a[:, 1].astype(np.int64) + (1 << 31)
+    g, a = key(got), key(allp)
+    assert len(np.unique(g)) == cap
+    assert np.isin(g, a).all()
+
+
 def offset_view(a, off):
     """Device copy of `a` that starts `off` int32 elements into a larger buffer
     (input columns at every 4-byte alignment inside a 16-byte line)."""
