@@ -364,8 +364,9 @@ def bench_c3(hj, torch, dev, steps, warmup) -> dict:
 
 
 def bench_sweeps(hj, torch, dev, steps, warmup) -> dict:
-    """Build-size sweep (|R| = 2^16..2^24, |S| = 2^24 uniform over 1..2|R|) and
-    selectivity sweep (16M x 16M, S uniform over 1..|R|/f for a match fraction f)."""
+    """Build-size sweep (|R| = 2^16..2^24, |S| = 2^24 uniform over 1..2|R|),
+    selectivity sweep (16M x 16M, S uniform over 1..|R|/f for a match fraction f)
+    and the low/high-skew sets (10% / 25% of R on one key) at three build sizes."""
     from paper_1307_1955_amd.gen import device as dgen
     n_s = 1 << 24
     o_r = torch.empty(n_s, dtype=torch.int32, device=dev)
@@ -398,8 +399,16 @@ def bench_sweeps(hj, torch, dev, steps, warmup) -> dict:
         sel.append({"match_fraction": f, **run(t)})
         print("bench: selectivity sweep %s" % sel[-1], file=sys.stderr, flush=True)
         del t
+    skew = []
+    for frac in (0.10, 0.25):
+        for lg in (16, 20, 24):
+            n_r = 1 << lg
+            t = dgen.skewed_r(9, n_r, n_s, 2 * n_r, frac, dev)
+            skew.append({"skew": frac, "n_r": n_r, "n_s": n_s, **run(t)})
+            print("bench: skew sweep %s" % skew[-1], file=sys.stderr, flush=True)
+            del t
     torch.cuda.empty_cache()
-    return {"build_size": build, "selectivity": sel}
+    return {"build_size": build, "selectivity": sel, "skew": skew}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "phj_16m_x_16m_hbm.json")

@@ -388,16 +388,16 @@ void shj_build_table(const hj_rel& R, const ShjTableWs& t, uint64_t* zero_total,
     hj::shj_build(R.key, R.n, t.table, t.next, t.log2_slots, rec);
 }
 
-// SHJ probe (Algorithm 1, p1-p4) of a built table; r_rid: R's rid column.
-void shj_probe_table(const Plan& pl, const ShjTableWs& t, const int32_t* r_rid, const hj_rel& S,
+// SHJ probe (Algorithm 1, p1-p4) of a table built over R.
+void shj_probe_table(const Plan& pl, const ShjTableWs& t, const hj_rel& R, const hj_rel& S,
                      const hj_out& out, const ShjProbeWs& w, uint64_t* d_count, hj::Recorder& rec) {
     if (!pl.one_pass) {
-        hj::shj_count(S.key, S.n, t.table, t.next, t.log2_slots, w.wave_cnt, rec);
+        hj::shj_count(S.key, S.n, t.table, t.next, t.log2_slots, R.key, R.n, w.wave_cnt, rec);
         hj::zero_words(w.st, w.nst, rec);
         hj::scan_u64(w.wave_cnt, w.wave_cnt, w.tiles * hj::kShjWavesPerBlock, w.st, d_count, rec);
     }
-    hj::shj_write(S.key, S.rid, S.n, t.table, t.next, t.log2_slots, r_rid, pl.one_pass ? nullptr : w.wave_cnt,
-                  d_count, out.rid_r, out.rid_s, out.capacity, rec);
+    hj::shj_write(S.key, S.rid, S.n, t.table, t.next, t.log2_slots, R.key, R.rid, R.n,
+                  pl.one_pass ? nullptr : w.wave_cnt, d_count, out.rid_r, out.rid_s, out.capacity, rec);
 }
 
 void run_shj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
@@ -405,7 +405,7 @@ void run_shj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
     const ShjTableWs t = shj_table_layout(R.n, ws);
     const ShjProbeWs w = shj_probe_layout(S.n, (char*)ws + t.bytes);
     shj_build_table(R, t, pl.one_pass ? d_count : nullptr, rec);
-    shj_probe_table(pl, t, R.rid, S, out, w, d_count, rec);
+    shj_probe_table(pl, t, R, S, out, w, d_count, rec);
 }
 
 // PHJ partitioning (Algorithm 2, n1-n3) of R and S (either may be empty) into
@@ -512,7 +512,7 @@ void run_probe(const Plan& pl, const hj_table& t, const hj_rel& S, const hj_out&
         const ShjTableWs tw = shj_table_layout(t.n_r, t.ws);
         const ShjProbeWs w = shj_probe_layout(S.n, ws);
         if (pl.one_pass) hj::write_zero_count(d_count, rec);
-        shj_probe_table(pl, tw, t.r_rid, S, out, w, d_count, rec);
+        shj_probe_table(pl, tw, R, S, out, w, d_count, rec);
     } else {
         // R's partitions and pair ranges are in the table; only S is partitioned here
         const PhjWs tw = phj_layout(pl, t.n_r, 0, 0, t.ws);

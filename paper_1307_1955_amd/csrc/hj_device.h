@@ -67,13 +67,32 @@ __device__ __forceinline__ void chain_insert(uint64_t* table, uint32_t* next, ui
             if (cur == kEmptySlot) return;
         }
         if ((uint32_t)cur == (uint32_t)k) {
-            // Key present: push the row in front of its chain with one exchange,
+            // Key present: push the row in front of its chain with an exchange,
             // which cannot fail (a claimed slot keeps its key), so duplicates of a
-            // heavy key cost one atomic each instead of compare-and-swap retries
-            // that grow with the contention.  The row's link is written after
-            // the exchange: tables are read only after the build launch ends.
-            const uint64_t prev = atomicExch((unsigned long long*)&table[s], (unsigned long long)chain_slot(k, row));
-            next[row] = (uint32_t)(prev >> 32);
+            // heavy key cost no compare-and-swap retries.  Lanes of the wave that
+            // push onto the same slot now are linked among themselves first
+            // (lowest lane in front, each to the next higher one) and their
+            // lowest lane makes the one exchange; the highest links to the old
+            // head.  Links are written after the exchange: tables are read only
+            // after the build launch ends.
+            const uint32_t lane = __lane_id();
+            uint64_t todo = __ballot(1);
+            while (todo) {
+                const int lead = __ffsll((unsigned long long)todo) - 1;
+                const uint64_t ls = __shfl(s, lead);
+                const uint64_t peers = __ballot(s == ls) & todo;
+                todo &= ~peers;
+                if (s == ls) {
+                    uint64_t prev = 0;
+                    if ((int)lane == lead)
+                        prev = atomicExch((unsigned long long*)&table[s], (unsigned long long)chain_slot(k, row));
+                    prev = __shfl(prev, lead);
+                    const uint64_t after = peers & ~((2ull << lane) - 1ull);
+                    const int succ = after ? __ffsll((unsigned long long)after) - 1 : (int)lane;
+                    const uint32_t succ_row = __shfl(row, succ);
+                    next[row] = after ? succ_row : (uint32_t)(prev >> 32);
+                }
+            }
             return;
         }
         s = step(s);

@@ -62,11 +62,13 @@ constexpr uint32_t kShjWavesPerBlock = kShjBlock / 64;
 void shj_fill(uint64_t* table, uint64_t nslots, uint64_t* zero_total, Recorder& rec);
 void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint32_t log2_slots,
                Recorder& rec);
+// The probe kernels read R's columns (r_key, r_rid, n_r rows, the ones the
+// table was built from) for keys with long chains.
 void shj_count(const int32_t* s_key, uint64_t n_s, const uint64_t* table, const uint32_t* next,
-               uint32_t log2_slots, uint64_t* wave_cnt, Recorder& rec);
+               uint32_t log2_slots, const int32_t* r_key, uint64_t n_r, uint64_t* wave_cnt, Recorder& rec);
 void shj_write(const int32_t* s_key, const int32_t* s_rid, uint64_t n_s, const uint64_t* table,
-               const uint32_t* next, uint32_t log2_slots, const int32_t* r_rid,
-               const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
+               const uint32_t* next, uint32_t log2_slots, const int32_t* r_key, const int32_t* r_rid,
+               uint64_t n_r, const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
                uint64_t capacity, Recorder& rec);  // wave_base == nullptr: one-pass output into *total
 
 // ---- phj_partition.hip ----

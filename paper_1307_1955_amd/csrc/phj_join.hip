@@ -17,6 +17,7 @@
 // the same item and stores its pairs at the scanned offset (Section 3.3's
 // dynamic output allocation replaced by counting).
 #include "hj_device.h"
+#include "hj_heavy.h"
 #include "hj_internal.h"
 #include "hj_side.h"
 
@@ -217,43 +218,6 @@ __device__ __forceinline__ void probe_lds(const LdsView& v, uint32_t log2H, cons
     }
 }
 
-// Keys whose row chain is longer than heavy_limit(r_len) are "heavy" (the
-// duplicate-heavy keys of a skewed R): instead of one lane walking the chain,
-// the whole workgroup scans the partition's keys for them (Section 3.3's
-// remedy for workload divergence: work of very different size is not left to
-// single lanes of one wave).  The scan takes about 2 r_len / kJoinBlock block
-// steps (count and write), the walk c dependent loads, so a chain is heavy
-// only when it is longer than both kHeavyChain and r_len / 256.
-constexpr uint32_t kHeavyChain = 64;
-__device__ __forceinline__ uint32_t heavy_limit(uint32_t r_len) { return max(kHeavyChain, r_len >> 8); }
-// Heavy keys a workgroup handles cooperatively per probe round; more fall back
-// to walking their chains.
-constexpr uint32_t kMaxHeavy = 32;
-// In c[u]: a registered heavy entry, its index in the low bits (counts stay
-// below 2^31: R_i has fewer than 2^31 tuples).
-constexpr uint32_t kHeavyBit = 0x80000000u;
-__device__ __forceinline__ bool is_heavy(uint32_t c) { return (c & kHeavyBit) != 0; }
-
-// The heavy entries of a probe round (LDS).
-struct HeavySet {
-    uint32_t n;                  // entries registered (may exceed kMaxHeavy: the rest walk)
-    int32_t key[kMaxHeavy];
-    int32_t srid[kMaxHeavy];
-    uint32_t cnt[kMaxHeavy];     // exact match counts
-    uint64_t pos[kMaxHeavy];     // first output slot (one-pass: absolute; two-pass: absolute too)
-    uint32_t wsum[kJoinWaves];   // scratch for block reductions / ranks
-};
-
-// Length of the chain at head field h, or lim + 1 if longer.
-__device__ __forceinline__ uint32_t chain_len_bounded(const uint32_t* __restrict__ next, uint32_t h, uint32_t lim) {
-    uint32_t c = 1;
-    while (!(h & kLast) && c <= lim) {
-        h = next[h];
-        ++c;
-    }
-    return c;
-}
-
 // Matches of the lane's kSU S keys in the partition-local HBM table (H = 2
 // r_len slots).  A key with a chain longer than heavy_limit(r_len) is
 // registered in `hs` (c[u] = kHeavyBit | its index) when there is room, else
@@ -271,78 +235,8 @@ __device__ __forceinline__ void probe_hbm(const uint64_t* __restrict__ region, c
         if (wb + u * kWave + lane_id() < we) {
             at[u] = chain_find(region, region_slot(q[u], H), q[u], step);
             if (at[u] != kNotFound) {
-                c[u] = chain_len_bounded(next, at[u], lim);
-                if (c[u] > lim) {
-                    const uint32_t e = atomicAdd(&hs->n, 1u);
-                    if (e < kMaxHeavy) {
-                        hs->key[e] = q[u];
-                        hs->srid[e] = qr ? qr[u] : 0;
-                        c[u] = kHeavyBit | e;
-                    } else {
-                        c[u] = chain_len(next, at[u]);
-                    }
-                }
+                c[u] = heavy_or_len(next, at[u], lim, q[u], qr ? qr[u] : 0, hs);
             }
-        }
-    }
-}
-
-// Exact counts of the registered heavy keys: the workgroup scans R_i's keys
-// once per entry (coalesced, ballot counts per wave).  All threads call it.
-__device__ __forceinline__ void heavy_counts(const int32_t* __restrict__ rk_i, uint32_t r_len, HeavySet* hs) {
-    __syncthreads();  // registrations done
-    const uint32_t ne = min(hs->n, kMaxHeavy);
-    const uint32_t w = threadIdx.x / kWave;
-    for (uint32_t e = 0; e < ne; ++e) {
-        const int32_t k = hs->key[e];
-        uint32_t m = 0;
-        for (uint32_t j = threadIdx.x; j < r_len; j += kJoinBlock) m += rk_i[j] == k;
-        m = wave_sum(m);
-        if (lane_id() == 0) hs->wsum[w] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (uint32_t i = 0; i < kJoinWaves; ++i) t += hs->wsum[i];
-            hs->cnt[e] = t;
-        }
-        __syncthreads();
-    }
-}
-
-// Writes the matches of every registered heavy key from its slot hs->pos[e]
-// on: the workgroup scans R_i in order and ranks the matches block-wide.
-// Slots at or past `capacity` are not written.  All threads call it.
-__device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk_i, const int32_t* __restrict__ rr_i,
-                                             uint32_t r_len, HeavySet* hs, uint64_t capacity,
-                                             int32_t* __restrict__ out_r, int32_t* __restrict__ out_s) {
-    __syncthreads();  // positions published
-    const uint32_t ne = min(hs->n, kMaxHeavy);
-    const uint32_t w = threadIdx.x / kWave;
-    for (uint32_t e = 0; e < ne; ++e) {
-        const int32_t k = hs->key[e];
-        const int32_t rs = hs->srid[e];
-        uint64_t pos = hs->pos[e];
-        for (uint32_t j0 = 0; j0 < r_len; j0 += kJoinBlock) {
-            const uint32_t j = j0 + threadIdx.x;
-            const bool hit = j < r_len && rk_i[j] == k;
-            const uint64_t mask = __ballot(hit);
-            if (lane_id() == 0) hs->wsum[w] = (uint32_t)__popcll(mask);
-            __syncthreads();
-            uint32_t before = 0, all = 0;
-            for (uint32_t i = 0; i < kJoinWaves; ++i) {
-                const uint32_t t = hs->wsum[i];
-                before += i < w ? t : 0u;
-                all += t;
-            }
-            if (hit) {
-                const uint64_t at = pos + before + (uint32_t)__popcll(mask & lanemask_lt());
-                if (at < capacity) {
-                    out_r[at] = rr_i[j];
-                    out_s[at] = rs;
-                }
-            }
-            pos += all;
-            __syncthreads();  // wsum reused
         }
     }
 }
@@ -499,7 +393,7 @@ __device__ __forceinline__ uint64_t join_count_hbm(const ItemLoc L, uint32_t w,
         __syncthreads();
         uint32_t c[kSU], at[kSU];
         probe_hbm(ovf_table + 2ull * L.r_off, ovf_next + L.r_off, 2u * L.r_len, q, nullptr, wb, we, c, at, hs);
-        heavy_counts(rk + L.r_off, L.r_len, hs);
+        heavy_counts<kJoinBlock, kHeavyMaxV>(rk + L.r_off, L.r_len, hs);
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) cnt += is_heavy(c[u]) ? hs->cnt[c[u] & ~kHeavyBit] : c[u];
         __syncthreads();  // the set is reused by the next round
@@ -566,13 +460,13 @@ __device__ __forceinline__ void join_write_hbm(
         __syncthreads();
         uint32_t c[kSU], at[kSU];
         probe_hbm(region, next, 2u * L.r_len, q, qr, wb, we, c, at, hs);
-        heavy_counts(rk + L.r_off, L.r_len, hs);
+        heavy_counts<kJoinBlock, kHeavyMaxV>(rk + L.r_off, L.r_len, hs);
         uint64_t mine = 0;
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) mine += is_heavy(c[u]) ? hs->cnt[c[u] & ~kHeavyBit] : c[u];
         const uint64_t pos0 = kOnePass ? block_reserve(mine, total, wtot, sb != 0) : base;
         base = write_round_hbm(next, rrp, qr, c, at, hs, pos0, capacity, out_r, out_s);
-        heavy_writes(rk + L.r_off, rrp, L.r_len, hs, capacity, out_r, out_s);
+        heavy_writes<kJoinBlock, kHeavyMaxV>(rk + L.r_off, rrp, L.r_len, hs, capacity, out_r, out_s);
         __syncthreads();  // the set is reused by the next round
     }
 }

@@ -16,6 +16,7 @@
 // Output is materialised in two passes (count -> scan -> write), so nothing is
 // allocated on the device and the result lands contiguously.
 #include "hj_device.h"
+#include "hj_heavy.h"
 #include "hj_internal.h"
 
 namespace hj {
@@ -61,11 +62,14 @@ __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ k
 constexpr uint32_t kSub = kShjTile / kShjWavesPerBlock;
 constexpr uint32_t kSU = kSub / kWave;
 
+// An S tuple whose chain is longer than heavy_limit(|R|) is registered in hs
+// and counted and written by the whole block (cooperative scan of R).
+// hs->n must be zero and visible to the block before the call.
 template <bool kRids>
 __device__ __forceinline__ void shj_probe(const int32_t* __restrict__ s_key, const int32_t* __restrict__ s_rid,
                                           uint64_t begin, uint64_t n_s, const uint64_t* __restrict__ table,
-                                          const uint32_t* __restrict__ next, uint32_t log2_slots, int32_t* q,
-                                          int32_t* qr, uint32_t* head, uint32_t* cnt) {
+                                          const uint32_t* __restrict__ next, uint32_t log2_slots, uint32_t lim,
+                                          HeavySet* hs, int32_t* q, int32_t* qr, uint32_t* head, uint32_t* cnt) {
     const PowStep step{(1ull << log2_slots) - 1};
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
@@ -78,24 +82,32 @@ __device__ __forceinline__ void shj_probe(const int32_t* __restrict__ s_key, con
             q[u] = s_key[j];
             if (kRids) qr[u] = s_rid[j];
             head[u] = chain_find(table, home_slot(q[u], log2_slots), q[u], step);
-            if (head[u] != kNotFound) cnt[u] = chain_len(next, head[u]);
+            if (head[u] != kNotFound) cnt[u] = heavy_or_len(next, head[u], lim, q[u], kRids ? qr[u] : 0, hs);
         }
     }
+}
+
+__device__ __forceinline__ uint32_t count_of(uint32_t c, const HeavySet* hs) {
+    return is_heavy(c) ? hs->cnt[c & ~kHeavyBit] : c;
 }
 
 __global__ void __launch_bounds__(kShjBlock) k_shj_count(const int32_t* __restrict__ s_key, uint64_t n_s,
                                                         const uint64_t* __restrict__ table,
                                                         const uint32_t* __restrict__ next,
-                                                        uint32_t log2_slots,
-                                                        uint64_t* __restrict__ wave_cnt) {
+                                                        uint32_t log2_slots, const int32_t* __restrict__ r_key,
+                                                        uint64_t n_r, uint64_t* __restrict__ wave_cnt) {
+    __shared__ HeavySet hs;
     const uint32_t w = threadIdx.x / kWave;
     const uint64_t begin = (uint64_t)blockIdx.x * kShjTile + (uint64_t)w * kSub;
+    if (threadIdx.x == 0) hs.n = 0;
+    __syncthreads();
     int32_t q[kSU], qr[kSU];
     uint32_t head[kSU], c[kSU];
-    shj_probe<false>(s_key, nullptr, begin, n_s, table, next, log2_slots, q, qr, head, c);
+    shj_probe<false>(s_key, nullptr, begin, n_s, table, next, log2_slots, heavy_limit(n_r), &hs, q, qr, head, c);
+    heavy_counts<kShjBlock, kHeavyMaxV>(r_key, n_r, &hs);
     uint64_t cnt = 0;
 #pragma unroll
-    for (uint32_t u = 0; u < kSU; ++u) cnt += c[u];
+    for (uint32_t u = 0; u < kSU; ++u) cnt += count_of(c[u], &hs);
     cnt = wave_sum(cnt);
     if (lane_id() == 0) wave_cnt[(uint64_t)blockIdx.x * kShjWavesPerBlock + w] = cnt;
 }
@@ -106,21 +118,25 @@ template <bool kOnePass>
 __global__ void __launch_bounds__(kShjBlock) k_shj_write(
     const int32_t* __restrict__ s_key, const int32_t* __restrict__ s_rid, uint64_t n_s,
     const uint64_t* __restrict__ table, const uint32_t* __restrict__ next, uint32_t log2_slots,
-    const int32_t* __restrict__ r_rid, const uint64_t* __restrict__ wave_base,
-    unsigned long long* __restrict__ total, int32_t* __restrict__ out_r, int32_t* __restrict__ out_s,
-    uint64_t capacity) {
+    const int32_t* __restrict__ r_key, const int32_t* __restrict__ r_rid, uint64_t n_r,
+    const uint64_t* __restrict__ wave_base, unsigned long long* __restrict__ total, int32_t* __restrict__ out_r,
+    int32_t* __restrict__ out_s, uint64_t capacity) {
     __shared__ uint64_t wtot[kShjWavesPerBlock + 1];
+    __shared__ HeavySet hs;
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
     const uint64_t begin = (uint64_t)blockIdx.x * kShjTile + (uint64_t)w * kSub;
+    if (threadIdx.x == 0) hs.n = 0;
+    __syncthreads();
     int32_t q[kSU], qr[kSU];
     uint32_t head[kSU], c[kSU];
-    shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, q, qr, head, c);
+    shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, heavy_limit(n_r), &hs, q, qr, head, c);
+    heavy_counts<kShjBlock, kHeavyMaxV>(r_key, n_r, &hs);
     uint64_t pos0;
     if (kOnePass) {
         uint64_t mine = 0;
 #pragma unroll
-        for (uint32_t u = 0; u < kSU; ++u) mine += c[u];
+        for (uint32_t u = 0; u < kSU; ++u) mine += count_of(c[u], &hs);
         mine = wave_sum(mine);
         if (lane == 0) wtot[w] = mine;
         __syncthreads();
@@ -137,11 +153,14 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_write(
     }
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
+        const uint32_t cu = count_of(c[u], &hs);
         uint64_t excl, wtotal;
-        wave_offsets(c[u], &excl, &wtotal);
+        wave_offsets(cu, &excl, &wtotal);
         uint64_t pos = pos0 + excl;
         pos0 += wtotal;
-        if (c[u]) {
+        if (is_heavy(c[u])) {
+            hs.pos[c[u] & ~kHeavyBit] = pos;
+        } else if (cu) {
             uint32_t h = head[u];
             while (true) {
                 const uint32_t row = h & ~kLast;
@@ -155,6 +174,7 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_write(
             }
         }
     }
+    heavy_writes<kShjBlock, kHeavyMaxV>(r_key, r_rid, n_r, &hs, capacity, out_r, out_s);
 }
 
 __global__ void k_zero_u64(uint64_t* p) {
@@ -190,30 +210,30 @@ void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, 
 }
 
 void shj_count(const int32_t* s_key, uint64_t n_s, const uint64_t* table, const uint32_t* next,
-               uint32_t log2_slots, uint64_t* wave_cnt, Recorder& rec) {
+               uint32_t log2_slots, const int32_t* r_key, uint64_t n_r, uint64_t* wave_cnt, Recorder& rec) {
     const uint64_t tiles = (n_s + kShjTile - 1) / kShjTile;
     if (tiles == 0) return;
     rec.before("shj_count");
     hipLaunchKernelGGL(k_shj_count, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key, n_s,
-                       table, next, log2_slots, wave_cnt);
+                       table, next, log2_slots, r_key, n_r, wave_cnt);
     rec.after();
 }
 
 void shj_write(const int32_t* s_key, const int32_t* s_rid, uint64_t n_s, const uint64_t* table,
-               const uint32_t* next, uint32_t log2_slots, const int32_t* r_rid,
-               const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
+               const uint32_t* next, uint32_t log2_slots, const int32_t* r_key, const int32_t* r_rid,
+               uint64_t n_r, const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
                uint64_t capacity, Recorder& rec) {
     const uint64_t tiles = (n_s + kShjTile - 1) / kShjTile;
     if (tiles == 0) return;
     if (wave_base == nullptr) {
         rec.before("shj_write_1pass");
         hipLaunchKernelGGL(k_shj_write<true>, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key,
-                           s_rid, n_s, table, next, log2_slots, r_rid, wave_base, (unsigned long long*)total,
+                           s_rid, n_s, table, next, log2_slots, r_key, r_rid, n_r, wave_base, (unsigned long long*)total,
                            out_r, out_s, capacity);
     } else {
         rec.before("shj_write");
         hipLaunchKernelGGL(k_shj_write<false>, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key,
-                           s_rid, n_s, table, next, log2_slots, r_rid, wave_base, (unsigned long long*)total,
+                           s_rid, n_s, table, next, log2_slots, r_key, r_rid, n_r, wave_base, (unsigned long long*)total,
                            out_r, out_s, capacity);
     }
     rec.after();

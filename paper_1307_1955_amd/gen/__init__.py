@@ -43,6 +43,7 @@ STREAM_JOB_SIZE = 3
 STREAM_JOB_FACTOR = 4
 STREAM_JOB_MATCH = 5
 STREAM_ARRIVALS = 6
+STREAM_SKEW_ROWS = 7
 
 
 def mix64(z: np.ndarray) -> np.ndarray:
@@ -233,6 +234,28 @@ def unique_uniform(seed: int, n_r: int, n_s: int, s_domain: int) -> tuple[Relati
     """R keys a permutation of 1..n_r, rid = row; S keys uniform over 1..s_domain."""
     r = Relation(perm_keys(seed, STREAM_R_KEYS, n_r), rows(n_r))
     s = Relation(uniform_keys(seed, STREAM_S_KEYS, n_s, s_domain), rows(n_s))
+    return r, s
+
+
+SKEW_KEY = 1
+
+
+def skew_rows(n_r: int, frac: float) -> int:
+    """Rows of an n_r-tuple R that carry the one duplicated key at fraction frac."""
+    if not 0.0 <= frac <= 1.0:
+        raise ValueError("skew fraction must lie in [0, 1]")
+    return int(round(frac * n_r))
+
+
+def skewed_r(seed: int, n_r: int, n_s: int, s_domain: int, frac: float) -> tuple[Relation, Relation]:
+    """The skewed sets of Section 5.1: ``unique_uniform`` with a fraction ``frac``
+    of R's rows (the rows whose index under a seeded permutation is below
+    ``round(frac * n_r)``) set to the one key ``SKEW_KEY``; every other R key
+    stays unique.  Low skew is frac = 0.10, high skew 0.25."""
+    r, s = unique_uniform(seed, n_r, n_s, s_domain)
+    m = skew_rows(n_r, frac)
+    if m:
+        r.key[permutation(seed, STREAM_SKEW_ROWS, n_r) < m] = SKEW_KEY
     return r, s
 
 

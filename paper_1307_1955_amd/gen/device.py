@@ -13,8 +13,8 @@ import threading
 import numpy as np
 import torch
 
-from . import (STREAM_R_KEYS, STREAM_S_KEYS, JobSpec, check_key_domain, feistel_half_bits, feistel_round_keys,
-               stream_key, zipf_cdf)
+from . import (SKEW_KEY, STREAM_R_KEYS, STREAM_S_KEYS, STREAM_SKEW_ROWS, JobSpec, check_key_domain,
+               feistel_half_bits, feistel_round_keys, skew_rows, stream_key, zipf_cdf)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "libhjgen.so")
 _lock = threading.Lock()
@@ -88,6 +88,17 @@ def unique_uniform(seed: int, n_r: int, n_s: int, s_domain: int, device="cuda"):
     """Device tensors (r_key, r_rid, s_key, s_rid) equal to ``gen.unique_uniform``."""
     return (perm_keys(seed, STREAM_R_KEYS, n_r, device), rows(n_r, device),
             uniform_keys(seed, STREAM_S_KEYS, n_s, s_domain, device), rows(n_s, device))
+
+
+def skewed_r(seed: int, n_r: int, n_s: int, s_domain: int, frac: float, device="cuda"):
+    """Device tensors equal to ``gen.skewed_r``."""
+    rk, rr, sk, sr = unique_uniform(seed, n_r, n_s, s_domain, device)
+    m = skew_rows(n_r, frac)
+    if m:
+        sel = perm_keys(seed, STREAM_SKEW_ROWS, n_r, device)  # 1 + the row's permuted index
+        rk.masked_fill_(sel <= m, SKEW_KEY)
+        del sel
+    return rk, rr, sk, sr
 
 
 def config_c1(seed: int = 1, n: int = 1 << 20, device="cuda"):

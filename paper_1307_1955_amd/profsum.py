@@ -23,7 +23,7 @@ import re
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/phj_partition.hip", "csrc/phj_join.hip", "csrc/shj.hip", "csrc/scan.hip", "csrc/hj_side.h",
-                  "csrc/hj_device.h", "csrc/hj_internal.h"]
+                  "csrc/hj_device.h", "csrc/hj_heavy.h", "csrc/hj_internal.h"]
 
 
 def sources_hash() -> str:

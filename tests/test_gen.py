@@ -115,3 +115,23 @@ def test_key_domain_fits_int32():
     for bad in (0, 1 << 31, 3 << 30):
         with pytest.raises(ValueError):
             gen.uniform_keys(1, 2, 10, bad)
+
+
+@pytest.mark.parametrize("frac", [0.0, 0.10, 0.25])
+def test_skewed_r(frac):
+    """Section 5.1's skew sets: exactly round(frac * n) R rows carry the one
+    duplicated key, every other key stays unique, S is untouched."""
+    n = 10007
+    r, s = gen.skewed_r(5, n, 3 * n, 2 * n, frac)
+    base_r, base_s = gen.unique_uniform(5, n, 3 * n, 2 * n)
+    m = gen.skew_rows(n, frac)
+    changed = r.key != base_r.key
+    assert np.array_equal(s.key, base_s.key) and np.array_equal(r.rid, base_r.rid)
+    # rows set to the key (one of them may have held it already)
+    on_key = r.key == gen.SKEW_KEY
+    assert on_key.sum() in (m, m + 1) if m else on_key.sum() == 1
+    assert changed.sum() in (m, m - 1) if m else changed.sum() == 0
+    rest = r.key[~on_key]
+    assert len(np.unique(rest)) == len(rest)
+    with pytest.raises(ValueError):
+        gen.skew_rows(n, 1.5)

@@ -159,9 +159,11 @@ def test_probe_capacity_guard(kw):
     assert torch.all(buf_r[cap:] == -7) and torch.all(buf_s[cap:] == -7)
 
 
-def test_r_side_skew_overflow():
-    """A quarter of R shares one key: an R partition beyond the LDS budget takes
-    the HBM-table path inside the probe."""
+@pytest.mark.parametrize("algo", ["phj", "shj"])
+def test_r_side_skew_overflow(algo):
+    """A quarter of R shares one key: for PHJ an R partition beyond the LDS budget
+    takes the HBM-table path inside the probe; for SHJ the key's chain is long
+    enough for the block-wide scan of R."""
     n_r, n_s = 1 << 17, 1 << 18
     r, s = gen.unique_uniform(48, n_r, n_s, 2 * n_r)
     rk = r.key.copy()
@@ -169,7 +171,8 @@ def test_r_side_skew_overflow():
     rk[rng.choice(n_r, n_r // 4, replace=False)] = 999
     sk = s.key.copy()
     sk[:40] = 999
-    tab = hj.Table(*to_dev(rk, r.rid), p=hj.params("phj", 2, (6, 6), one_pass=True))
+    p = hj.params("phj", 2, (6, 6), one_pass=True) if algo == "phj" else hj.params("shj", one_pass=True)
+    tab = hj.Table(*to_dev(rk, r.rid), p=p)
     o_r, o_s, cnt = tab.probe(*to_dev(sk, s.rid))
     want_r, want_s = oracle.join(rk, r.rid, sk, s.rid)
     assert cnt == len(want_r)

@@ -126,7 +126,8 @@ def test_r_side_skew(kw, frac):
 
 @pytest.mark.parametrize("kw", [dict(algo="phj", passes=2, bits=(4, 4), lds_cap=256),
                                 dict(algo="phj", passes=2, bits=(4, 4), lds_cap=256, one_pass=True),
-                                dict(algo="phj", passes=1, bits=(5,), one_pass=True)])
+                                dict(algo="phj", passes=1, bits=(5,), one_pass=True),
+                                dict(algo="shj"), dict(algo="shj", one_pass=True)])
 def test_heavy_keys_hbm_path(kw):
     """Partitions beyond the LDS budget (identity hash: the partition is the key's low
     bits) with chains of very different length.  Partition 146 (mod 256) holds one key
@@ -134,7 +135,8 @@ def test_heavy_keys_hbm_path(kw):
     limit (r_len / 256), so those are walked; partition 239 holds a key with 3000
     duplicates and 16 keys with 100 each, all heavy there.  S matches them from many
     work items and rounds, 40 tuples of one key in one round (more than a round's
-    heavy set holds)."""
+    heavy set holds).  For SHJ (one table over all 60001 rows, limit 234) the two
+    big keys are heavy and the 100-long chains are walked."""
     rng = np.random.default_rng(21)
     n_r, n_s = 60001, 150001
     special = np.concatenate([np.full(30000, 4242), np.repeat((1 << 21) + 146 + 256 * np.arange(64), 100),
@@ -268,11 +270,33 @@ def test_device_generator_matches_host():
     rk, rr, sk, sr = dgen.config_c1(seed=1, n=1 << 16)
     assert np.array_equal(rk.cpu().numpy(), r_host.key) and np.array_equal(sk.cpu().numpy(), s_host.key)
     assert np.array_equal(rr.cpu().numpy(), r_host.rid) and np.array_equal(sr.cpu().numpy(), s_host.rid)
+    r_host, s_host = gen.skewed_r(4, 1 << 16, 1 << 17, 1 << 17, 0.25)
+    rk, rr, sk, sr = dgen.skewed_r(4, 1 << 16, 1 << 17, 1 << 17, 0.25)
+    assert np.array_equal(rk.cpu().numpy(), r_host.key) and np.array_equal(sk.cpu().numpy(), s_host.key)
 
 
 # ---------------------------------------------------------------------------
 # Full-size workloads
 # ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("frac", [0.10, 0.25])
+def test_paper_skew_sets_16m(frac):
+    """Section 5.1's low- and high-skew sets at 16M x 16M (R: a fraction frac of the
+    rows on one key, S uniform over 1..2^25), with three S tuples forced onto the
+    skewed key so the probe meets its chain: PHJ (library choice) and SHJ, every
+    pair against the oracle."""
+    n = 1 << 24
+    r, s = gen.skewed_r(31, n, n, 2 * n, frac)
+    s.key[[5, n // 2, n - 1]] = gen.SKEW_KEY
+    want_r, want_s = oracle.join(r.key, r.rid, s.key, s.rid)
+    want = oracle.canonical(want_r, want_s)
+    del want_r, want_s
+    t = to_dev(r.key, r.rid, s.key, s.rid)
+    for p in (hj.params("auto", one_pass=True), hj.params("shj")):
+        got_r, got_s, cnt = gpu_join(p, *t, capacity=len(want))
+        assert cnt == len(want)
+        assert np.array_equal(oracle.canonical(got_r, got_s), want)
 
 
 def closed_form_unique(r_key, s_key):
