@@ -413,7 +413,7 @@ def bench_sweeps(hj, torch, dev, steps, warmup) -> dict:
 
 PROFILE = os.path.join(ROOT, "profiles", "phj_16m_x_16m_hbm.json")
 KERNEL_OF_PHASE = {"part_hist": "k_part_hist", "part_scatter": "k_part_scatter", "join_count": "k_join_count",
-                   "join_write": "k_join_write<false>", "join_write_1pass": "k_join_write<true>"}
+                   "join_write": "k_join_write<false", "join_write_1pass": "k_join_write<true"}
 
 
 def counter_traffic(phase: str):

@@ -24,7 +24,7 @@ constexpr uint32_t kMaxHeavy = 32;
 // (counts stay below 2^31).
 constexpr uint32_t kHeavyBit = 0x80000000u;
 constexpr uint32_t kHeavyMaxWaves = 16;  // largest block: 1024 threads
-constexpr uint32_t kHeavyMaxV = 8;       // most R keys per thread per scan step
+constexpr uint32_t kHeavyV = 8;          // R keys per thread per scan step (more costs the callers' registers)
 
 __device__ __forceinline__ uint32_t heavy_limit(uint64_t r_len) {
     const uint64_t l = r_len >> 8;
@@ -41,7 +41,7 @@ struct HeavySet {
     uint32_t rep[kMaxHeavy];     // first entry with the same key (its scan serves both)
     uint32_t cnt[kMaxHeavy];     // exact match counts
     uint64_t pos[kMaxHeavy];     // first output slot of each entry
-    uint32_t wsum[kHeavyMaxWaves * kHeavyMaxV];  // per-wave hit counts of one scan step
+    uint32_t wsum[kHeavyMaxWaves * kHeavyV];  // per-wave hit counts of one scan step
 };
 
 // Length of the chain at head field h, or lim + 1 if longer.
@@ -74,7 +74,7 @@ __device__ __forceinline__ uint32_t heavy_or_len(const uint32_t* __restrict__ ne
 template <uint32_t kBlock, uint32_t kV, typename Len>
 __device__ __forceinline__ void heavy_counts(const int32_t* __restrict__ rk, Len r_len, HeavySet* hs) {
     constexpr uint32_t kWaves = kBlock / kWave;
-    static_assert(kWaves <= kHeavyMaxWaves && kV <= kHeavyMaxV, "block or step too large for the heavy set");
+    static_assert(kWaves <= kHeavyMaxWaves, "block too large for the heavy set");
     __syncthreads();  // registrations done
     const uint32_t ne = min(hs->n, kMaxHeavy);
     if (threadIdx.x < ne) {
@@ -117,15 +117,19 @@ __device__ __forceinline__ void heavy_counts(const int32_t* __restrict__ rk, Len
 }
 
 // Writes the matches of every registered tuple from its slot hs->pos[e] on,
-// in R's row order: one scan of R per distinct key, kV keys per thread per
-// step, hits ranked block-wide.  Slots at or past `capacity` are not
-// written.  All threads of the block call it, after the positions are set.
+// in R's row order: one scan of R per distinct key, kV (<= 32) keys per
+// thread per step held as hit bits; after one barrier per step every hit is
+// ranked by (element, wave, lane) from per-wave counts in LDS and a ballot,
+// so consecutive lanes write consecutive slots.  Slots at or past `capacity`
+// are not written.  All threads of the block call it, after the positions
+// are set.
 template <uint32_t kBlock, uint32_t kV, typename Len>
 __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
                                              Len r_len, HeavySet* hs, uint64_t capacity,
                                              int32_t* __restrict__ out_r, int32_t* __restrict__ out_s) {
     constexpr uint32_t kWaves = kBlock / kWave;
     constexpr Len kStep = (Len)kV * kBlock;
+    static_assert(kV <= 32 && kV * kWaves <= sizeof(hs->wsum) / sizeof(uint32_t), "step too large");
     __syncthreads();  // positions published
     const uint32_t ne = min(hs->n, kMaxHeavy);
     const uint32_t w = threadIdx.x / kWave;
@@ -135,31 +139,29 @@ __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, con
         Len done = 0;  // matches written before this step
         for (Len j0 = 0; j0 < r_len; j0 += kStep) {
             // element u of the thread: row j0 + u * kBlock + threadIdx.x
-            bool hit[kV];
-            uint64_t mask[kV];
+            uint32_t bits = 0;
 #pragma unroll
             for (uint32_t u = 0; u < kV; ++u) {
                 const Len j = j0 + (Len)u * kBlock + threadIdx.x;
-                hit[u] = j < r_len && rk[j] == k;
+                bits |= (j < r_len && rk[j] == k) ? 1u << u : 0u;
             }
 #pragma unroll
             for (uint32_t u = 0; u < kV; ++u) {
-                mask[u] = __ballot(hit[u]);
-                if (lane_id() == 0) hs->wsum[u * kWaves + w] = (uint32_t)__popcll(mask[u]);
+                const uint32_t n = (uint32_t)__popcll(__ballot((bits >> u) & 1u));
+                if (lane_id() == 0) hs->wsum[u * kWaves + w] = n;
             }
             __syncthreads();
-            // rank order: (u, wave, lane)
-            uint32_t base_u = 0;
-#pragma unroll
+            Len base = done;
             for (uint32_t u = 0; u < kV; ++u) {
-                uint32_t wb = 0, tu = 0;
+                uint32_t before = 0, all = 0;
                 for (uint32_t i = 0; i < kWaves; ++i) {
                     const uint32_t t = hs->wsum[u * kWaves + i];
-                    wb += i < w ? t : 0u;
-                    tu += t;
+                    before += i < w ? t : 0u;
+                    all += t;
                 }
-                if (hit[u]) {
-                    const Len rank = done + base_u + wb + (uint32_t)__popcll(mask[u] & lanemask_lt());
+                const uint64_t m = __ballot((bits >> u) & 1u);
+                if ((bits >> u) & 1u) {
+                    const Len rank = base + before + (uint32_t)__popcll(m & lanemask_lt());
                     const int32_t rid = rr[j0 + (Len)u * kBlock + threadIdx.x];
                     for (uint32_t e2 = e; e2 < ne; ++e2) {
                         if (hs->rep[e2] != e) continue;
@@ -170,9 +172,9 @@ __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, con
                         }
                     }
                 }
-                base_u += tu;
+                base += all;
             }
-            done += base_u;
+            done = base;
             __syncthreads();  // wsum reused by the next step
         }
     }
