@@ -53,10 +53,14 @@ __device__ __forceinline__ uint64_t chain_slot(int32_t key, uint32_t head) {
     return ((uint64_t)head << 32) | (uint32_t)key;
 }
 
-// Inserts `row` under key `k`, probing from slot `s` with `step(s)`.
+constexpr uint64_t kClaimed = ~0ull;  // chain_claim: the row took an empty slot
+
+// Finds key k's slot, probing from slot s with step(s).  A row whose key is
+// new claims an empty slot with one compare-and-swap and is done (kClaimed);
+// otherwise the key's slot is returned and the row still has to be pushed
+// onto its chain (WavePush).
 template <typename Step>
-__device__ __forceinline__ void chain_insert(uint64_t* table, uint32_t* next, uint64_t s, int32_t k,
-                                             uint32_t row, Step step) {
+__device__ __forceinline__ uint64_t chain_claim(uint64_t* table, uint64_t s, int32_t k, uint32_t row, Step step) {
     while (true) {
         // Read first and CAS only a free slot (faster on MI355X than an
         // unconditional CAS: the read brings the line in, the CAS then hits it).
@@ -64,40 +68,76 @@ __device__ __forceinline__ void chain_insert(uint64_t* table, uint32_t* next, ui
         if (cur == kEmptySlot) {
             cur = atomicCAS((unsigned long long*)&table[s], (unsigned long long)kEmptySlot,
                             (unsigned long long)chain_slot(k, row | kLast));
-            if (cur == kEmptySlot) return;
+            if (cur == kEmptySlot) return kClaimed;
         }
-        if ((uint32_t)cur == (uint32_t)k) {
-            // Key present: push the row in front of its chain with an exchange,
-            // which cannot fail (a claimed slot keeps its key), so duplicates of a
-            // heavy key cost no compare-and-swap retries.  Lanes of the wave that
-            // push onto the same slot now are linked among themselves first
-            // (lowest lane in front, each to the next higher one) and their
-            // lowest lane makes the one exchange; the highest links to the old
-            // head.  Links are written after the exchange: tables are read only
-            // after the build launch ends.
-            const uint32_t lane = __lane_id();
-            uint64_t todo = __ballot(1);
-            while (todo) {
-                const int lead = __ffsll((unsigned long long)todo) - 1;
-                const uint64_t ls = __shfl(s, lead);
-                const uint64_t peers = __ballot(s == ls) & todo;
-                todo &= ~peers;
-                if (s == ls) {
-                    uint64_t prev = 0;
-                    if ((int)lane == lead)
-                        prev = atomicExch((unsigned long long*)&table[s], (unsigned long long)chain_slot(k, row));
-                    prev = __shfl(prev, lead);
-                    const uint64_t after = peers & ~((2ull << lane) - 1ull);
-                    const int succ = after ? __ffsll((unsigned long long)after) - 1 : (int)lane;
-                    const uint32_t succ_row = __shfl(row, succ);
-                    next[row] = after ? succ_row : (uint32_t)(prev >> 32);
-                }
-            }
-            return;
-        }
+        if ((uint32_t)cur == (uint32_t)k) return s;
         s = step(s);
     }
 }
+
+// Pushes of duplicate keys by one wave.  A row is pushed in front of its key's
+// chain by exchanging the slot's head, which cannot fail (a claimed slot keeps
+// its key), so a heavy key costs no compare-and-swap retries.  Exchanges are
+// saved twice over: lanes pushing onto the same slot in one call are linked
+// among themselves (lowest lane in front), and the wave keeps that run as a
+// pending chain (slot, key, head row, tail row) that later runs onto the same
+// slot extend, with one exchange when the wave moves to another slot or
+// flushes.  Links are written before the exchange publishes them; tables are
+// read only after the build launch ends.  Every lane of the wave calls add()
+// and flush() (wave-uniform control flow); the pending fields are uniform.
+struct WavePush {
+    uint64_t slot = kClaimed;
+    int32_t key = 0;
+    uint32_t head = 0, tail = 0;
+    // The slot of the last key the wave pushed: a row with that key can skip
+    // chain_claim (a claimed slot never moves), which keeps a heavy key's rows
+    // off its slot's cache line.
+    uint64_t hot_slot = kClaimed;
+    int32_t hot_key = 0;
+
+    __device__ __forceinline__ bool hot(int32_t k) const { return hot_slot != kClaimed && k == hot_key; }
+
+    __device__ __forceinline__ void flush(uint64_t* table, uint32_t* next) {
+        if (slot != kClaimed) {
+            if (__lane_id() == 0) {
+                const uint64_t prev =
+                    atomicExch((unsigned long long*)&table[slot], (unsigned long long)chain_slot(key, head));
+                next[tail] = (uint32_t)(prev >> 32);
+            }
+            slot = kClaimed;
+        }
+    }
+
+    // s: the lane's slot from chain_claim (kClaimed: nothing to push).
+    __device__ __forceinline__ void add(uint64_t* table, uint32_t* next, uint64_t s, int32_t k, uint32_t row) {
+        const uint32_t lane = __lane_id();
+        uint64_t todo = __ballot(s != kClaimed);
+        while (todo) {
+            const int lead = __ffsll((unsigned long long)todo) - 1;
+            const uint64_t ls = __shfl(s, lead);
+            const int32_t lk = __shfl(k, lead);
+            const uint64_t peers = __ballot(s == ls) & todo;
+            todo &= ~peers;
+            const int last = 63 - __clzll((long long)peers);
+            const uint32_t first_row = __shfl(row, lead);
+            const uint32_t last_row = __shfl(row, last);
+            const uint64_t after = peers & ~((2ull << lane) - 1ull);
+            const int succ = after ? __ffsll((unsigned long long)after) - 1 : (int)lane;
+            const uint32_t succ_row = __shfl(row, succ);
+            if (s == ls && after) next[row] = succ_row;
+            if (ls == slot) {
+                if ((int)lane == last) next[row] = head;  // the run goes in front of the pending chain
+                head = first_row;
+            } else {
+                flush(table, next);
+                slot = hot_slot = ls;
+                key = hot_key = lk;
+                head = first_row;
+                tail = last_row;
+            }
+        }
+    }
+};
 
 // Head field of key `k`'s chain, or kNotFound.
 template <typename Step>

@@ -68,10 +68,18 @@ __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ 
         uint32_t* next = ovf_next + pp.r_off;
         const RegionStep step{2u * pp.r_len};
         const uint32_t end = min((c + 1) * kOvfChunk, pp.r_len);
-        for (uint32_t j = c * kOvfChunk + threadIdx.x; j < end; j += blockDim.x) {
-            const int32_t k = rk[pp.r_off + j];
-            chain_insert(region, next, region_slot(k, step.H), k, j, step);
+        WavePush push;
+        for (uint32_t j0 = c * kOvfChunk; j0 < end; j0 += blockDim.x) {  // uniform trip count
+            const uint32_t j = j0 + threadIdx.x;
+            int32_t k = 0;
+            uint64_t s = kClaimed;
+            if (j < end) {
+                k = rk[pp.r_off + j];
+                s = push.hot(k) ? push.hot_slot : chain_claim(region, region_slot(k, step.H), k, j, step);
+            }
+            push.add(region, next, s, k, j);
         }
+        push.flush(region, next);
     }
 }
 
@@ -393,7 +401,7 @@ __device__ __forceinline__ uint64_t join_count_hbm(const ItemLoc L, uint32_t w,
         __syncthreads();
         uint32_t c[kSU], at[kSU];
         probe_hbm(ovf_table + 2ull * L.r_off, ovf_next + L.r_off, 2u * L.r_len, q, nullptr, wb, we, c, at, hs);
-        heavy_counts<kJoinBlock, kHeavyMaxV>(rk + L.r_off, L.r_len, hs);
+        heavy_counts<kJoinBlock, kHeavyV>(rk + L.r_off, L.r_len, hs);
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) cnt += is_heavy(c[u]) ? hs->cnt[c[u] & ~kHeavyBit] : c[u];
         __syncthreads();  // the set is reused by the next round
@@ -460,13 +468,13 @@ __device__ __forceinline__ void join_write_hbm(
         __syncthreads();
         uint32_t c[kSU], at[kSU];
         probe_hbm(region, next, 2u * L.r_len, q, qr, wb, we, c, at, hs);
-        heavy_counts<kJoinBlock, kHeavyMaxV>(rk + L.r_off, L.r_len, hs);
+        heavy_counts<kJoinBlock, kHeavyV>(rk + L.r_off, L.r_len, hs);
         uint64_t mine = 0;
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) mine += is_heavy(c[u]) ? hs->cnt[c[u] & ~kHeavyBit] : c[u];
         const uint64_t pos0 = kOnePass ? block_reserve(mine, total, wtot, sb != 0) : base;
         base = write_round_hbm(next, rrp, qr, c, at, hs, pos0, capacity, out_r, out_s);
-        heavy_writes<kJoinBlock, kHeavyMaxV>(rk + L.r_off, rrp, L.r_len, hs, capacity, out_r, out_s);
+        heavy_writes<kJoinBlock, kHeavyV>(rk + L.r_off, rrp, L.r_len, hs, capacity, out_r, out_s);
         __syncthreads();  // the set is reused by the next round
     }
 }

@@ -48,10 +48,18 @@ __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ k
                                                   uint32_t log2_slots) {
     const PowStep step{(1ull << log2_slots) - 1};
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int32_t k = key[i];
-        chain_insert(table, next, home_slot(k, log2_slots), k, (uint32_t)i, step);
+    WavePush push;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {  // uniform trip count
+        const uint64_t i = i0 + threadIdx.x;
+        int32_t k = 0;
+        uint64_t s = kClaimed;
+        if (i < n) {
+            k = key[i];
+            s = push.hot(k) ? push.hot_slot : chain_claim(table, home_slot(k, log2_slots), k, (uint32_t)i, step);
+        }
+        push.add(table, next, s, k, (uint32_t)i);
     }
+    push.flush(table, next);
 }
 
 // Probe tiles: tile t covers S rows [t*kShjTile, ...); wave w of the block takes
@@ -104,7 +112,7 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_count(const int32_t* __restri
     int32_t q[kSU], qr[kSU];
     uint32_t head[kSU], c[kSU];
     shj_probe<false>(s_key, nullptr, begin, n_s, table, next, log2_slots, heavy_limit(n_r), &hs, q, qr, head, c);
-    heavy_counts<kShjBlock, kHeavyMaxV>(r_key, n_r, &hs);
+    heavy_counts<kShjBlock, kHeavyV>(r_key, n_r, &hs);
     uint64_t cnt = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) cnt += count_of(c[u], &hs);
@@ -131,7 +139,7 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_write(
     int32_t q[kSU], qr[kSU];
     uint32_t head[kSU], c[kSU];
     shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, heavy_limit(n_r), &hs, q, qr, head, c);
-    heavy_counts<kShjBlock, kHeavyMaxV>(r_key, n_r, &hs);
+    heavy_counts<kShjBlock, kHeavyV>(r_key, n_r, &hs);
     uint64_t pos0;
     if (kOnePass) {
         uint64_t mine = 0;
@@ -174,7 +182,7 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_write(
             }
         }
     }
-    heavy_writes<kShjBlock, kHeavyMaxV>(r_key, r_rid, n_r, &hs, capacity, out_r, out_s);
+    heavy_writes<kShjBlock, kHeavyV>(r_key, r_rid, n_r, &hs, capacity, out_r, out_s);
 }
 
 __global__ void k_zero_u64(uint64_t* p) {
@@ -201,7 +209,7 @@ void shj_fill(uint64_t* table, uint64_t nslots, uint64_t* zero_total, Recorder& 
 void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint32_t log2_slots,
                Recorder& rec) {
     uint64_t blocks = (n + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
+    if (blocks > 16384) blocks = 16384;  // grid-stride: a wave's pending push chain spans its rows
     if (blocks == 0) return;
     rec.before("shj_build");
     hipLaunchKernelGGL(k_shj_build, dim3((uint32_t)blocks), dim3(256), 0, rec.stream, key, n, table, next,
