@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--sweeps", action="store_true",
                     help="also time a build-size sweep (|R| 2^16..2^24 against |S| = 2^24, 50%% match) and a "
                          "selectivity sweep (12.5/50/100%% of S matching, 16M x 16M)")
-    ap.add_argument("--no-c3", action="store_true", help="skip the Zipf-skewed 16M x 64M workload")
+    ap.add_argument("--no-c3", action="store_true", help="skip the Zipf-skewed 16M x 64M workload and the skewed-R sets")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the 16M x 16M PHJ and SHJ lines (no build/probe, no C3), e.g. under a profiler")
     ap.add_argument("--batch-jobs", type=int, default=4096, help="jobs of the batched workload (0: skip)")
@@ -399,16 +399,36 @@ def bench_sweeps(hj, torch, dev, steps, warmup) -> dict:
         sel.append({"match_fraction": f, **run(t)})
         print("bench: selectivity sweep %s" % sel[-1], file=sys.stderr, flush=True)
         del t
-    skew = []
+    del o_r, o_s
+    torch.cuda.empty_cache()
+    return {"build_size": build, "selectivity": sel, "skew": bench_skew(hj, torch, dev, steps, warmup, (16, 20, 24))}
+
+
+def bench_skew(hj, torch, dev, steps, warmup, log2_sizes=(24,)) -> list:
+    """The skewed sets of Section 5.1: |S| = 2^24 uniform over 1..2|R|, a fraction
+    s = 10% (low) or 25% (high) of R's rows on one key, PHJ (`HJ_AUTO`) and SHJ."""
+    from paper_1307_1955_amd.gen import device as dgen
+    n_s = 1 << 24
+    o_r = torch.empty(n_s, dtype=torch.int32, device=dev)
+    o_s = torch.empty(n_s, dtype=torch.int32, device=dev)
+    d = torch.zeros(1, dtype=torch.int64, device=dev)
+    rows = []
     for frac in (0.10, 0.25):
-        for lg in (16, 20, 24):
+        for lg in log2_sizes:
             n_r = 1 << lg
             t = dgen.skewed_r(9, n_r, n_s, 2 * n_r, frac, dev)
-            skew.append({"skew": frac, "n_r": n_r, "n_s": n_s, **run(t)})
-            print("bench: skew sweep %s" % skew[-1], file=sys.stderr, flush=True)
+            row = {"skew": frac, "n_r": n_r, "n_s": n_s}
+            for name, q in (("phj_auto", hj.params("auto", one_pass=True)), ("shj", hj.params("shj", one_pass=True))):
+                ws = hj.workspace(q, n_r, n_s, dev)
+                ms = time_steps(lambda: hj.hj_join(q, *t, o_r, o_s, ws, d), steps, warmup, torch)
+                row[name] = {"ms": round(ms, 4), "tuples_per_s": (n_r + n_s) / (ms * 1e-3), "matches": int(d.item())}
+                del ws
+            rows.append(row)
+            print("bench: skew set %s" % row, file=sys.stderr, flush=True)
             del t
+    del o_r, o_s
     torch.cuda.empty_cache()
-    return {"build_size": build, "selectivity": sel, "skew": skew}
+    return rows
 
 
 PROFILE = os.path.join(ROOT, "profiles", "phj_16m_x_16m_hbm.json")
@@ -550,6 +570,8 @@ def main():
     if not args.no_c3 and not args.no_extras:
         print("bench: Zipf-skewed 16M x 64M (C3)", file=sys.stderr, flush=True)
         result["c3"] = bench_c3(hj, torch, dev, min(args.steps, 10), min(args.warmup, 3))
+        print("bench: skewed R (10% / 25% on one key), 16M x 16M", file=sys.stderr, flush=True)
+        result["skew"] = bench_skew(hj, torch, dev, min(args.steps, 10), min(args.warmup, 3))
     if args.sweeps:
         result["sweeps"] = bench_sweeps(hj, torch, dev, min(args.steps, 10), min(args.warmup, 3))
     if args.batch_jobs:
