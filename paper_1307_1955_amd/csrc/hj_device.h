@@ -108,6 +108,40 @@ struct WavePush {
         }
     }
 
+    // The block's last step: the waves' pending runs onto one slot are joined
+    // (lower wave in front) and go in with one exchange, so a heavy key costs
+    // one exchange per block, not per wave.  Every thread of the block calls
+    // it; `runs` is LDS for one run per wave, reusable when it returns.
+    struct Run {
+        uint64_t slot;
+        int32_t key;
+        uint32_t head, tail;
+    };
+    template <uint32_t kWaves>
+    __device__ __forceinline__ void flush_block(uint64_t* table, uint32_t* next, Run* runs) {
+        if (__lane_id() == 0) runs[threadIdx.x / kWave] = Run{slot, key, head, tail};
+        slot = kClaimed;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (uint32_t i = 0; i < kWaves; ++i) {
+                const Run a = runs[i];
+                if (a.slot == kClaimed) continue;
+                uint32_t t = a.tail;
+                for (uint32_t j = i + 1; j < kWaves; ++j) {
+                    if (runs[j].slot == a.slot) {
+                        next[t] = runs[j].head;
+                        t = runs[j].tail;
+                        runs[j].slot = kClaimed;
+                    }
+                }
+                const uint64_t prev =
+                    atomicExch((unsigned long long*)&table[a.slot], (unsigned long long)chain_slot(a.key, a.head));
+                next[t] = (uint32_t)(prev >> 32);
+            }
+        }
+        __syncthreads();
+    }
+
     // s: the lane's slot from chain_claim (kClaimed: nothing to push).
     __device__ __forceinline__ void add(uint64_t* table, uint32_t* next, uint64_t s, int32_t k, uint32_t row) {
         const uint32_t lane = __lane_id();

@@ -11,7 +11,7 @@
 
 namespace hj {
 
-constexpr uint32_t kOvfChunk = 4096;  // R tuples per HBM-table build item
+constexpr uint32_t kOvfChunk = 16384;  // R tuples per HBM-table build item (a heavy key: one exchange each)
 constexpr uint32_t kMaxPlanWaves = 16;  // waves of the largest workgroup that runs the join plan
 
 // Everything the pass-2 setup reads and writes.

@@ -59,6 +59,8 @@ __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ 
                                                   const int32_t* __restrict__ rk,
                                                   uint64_t* __restrict__ ovf_table,
                                                   uint32_t* __restrict__ ovf_next) {
+    constexpr uint32_t kWaves = 256 / kWave;
+    __shared__ WavePush::Run runs[kWaves];
     const uint32_t nitems = ovf_begin[P];
     for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
         const uint32_t i = ovf_part[item];
@@ -79,7 +81,7 @@ __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ 
             }
             push.add(region, next, s, k, j);
         }
-        push.flush(region, next);
+        push.flush_block<kWaves>(region, next, runs);
     }
 }
 
@@ -387,11 +389,10 @@ __device__ __forceinline__ uint64_t write_round_hbm(const uint32_t* __restrict__
 // partition-local HBM table and returns this lane's pair count.  hs takes the
 // LDS the table would have used.  Inlined: a call would give the kernel a
 // stack, and the LDS path measured a few percent slower with one.
-__device__ __forceinline__ uint64_t join_count_hbm(const ItemLoc L, uint32_t w,
-                                                             const int32_t* __restrict__ rk,
-                                                             const int32_t* __restrict__ skp,
-                                                             const uint64_t* __restrict__ ovf_table,
-                                                             const uint32_t* __restrict__ ovf_next, HeavySet* hs) {
+__device__ __forceinline__ uint64_t join_count_hbm(const ItemLoc L, uint32_t w, const int32_t* __restrict__ rk,
+                                                   const int32_t* __restrict__ skp,
+                                                   const uint64_t* __restrict__ ovf_table,
+                                                   const uint32_t* __restrict__ ovf_next, HeavySet* hs) {
     uint64_t cnt = 0;
     int32_t q[kSU];
     for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {

@@ -46,6 +46,8 @@ __device__ __forceinline__ uint64_t home_slot(int32_t k, uint32_t log2_slots) {
 __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ key, uint64_t n,
                                                   uint64_t* __restrict__ table, uint32_t* __restrict__ next,
                                                   uint32_t log2_slots) {
+    constexpr uint32_t kWaves = 256 / kWave;
+    __shared__ WavePush::Run runs[kWaves];
     const PowStep step{(1ull << log2_slots) - 1};
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     WavePush push;
@@ -59,7 +61,7 @@ __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ k
         }
         push.add(table, next, s, k, (uint32_t)i);
     }
-    push.flush(table, next);
+    push.flush_block<kWaves>(table, next, runs);
 }
 
 // Probe tiles: tile t covers S rows [t*kShjTile, ...); wave w of the block takes
