@@ -174,6 +174,28 @@ def test_heavy_keys_hbm_path(kw):
     assert np.isin(g, a).all()
 
 
+@pytest.mark.parametrize("kw", [dict(algo="shj"), dict(algo="shj", one_pass=True),
+                                dict(algo="phj", passes=2, bits=(4, 4), lds_cap=256, one_pass=True),
+                                dict(algo="phj", passes=1, bits=(3,))])
+def test_interleaved_heavy_keys(kw):
+    """Several heavy keys interleaved row by row (runs onto different slots inside
+    one wave, pending chains flushed and restarted at every row), among them the
+    int32 extremes and -1 (the empty slot's key bits), plus unique keys; S hits
+    each heavy key a few times."""
+    n_r, n_s = 50000, 90001
+    heavy = np.array([-1, -(2 ** 31), 2 ** 31 - 1, 7, 7 + 8, 7 + 16], dtype=np.int64)
+    rk = np.arange(n_r, dtype=np.int64) * 64 + 1000          # unique keys, outside the heavy set
+    rows = np.arange(0, 36000)
+    rk[rows] = heavy[rows % len(heavy)]                       # 6000 rows per heavy key, interleaved
+    rng = np.random.default_rng(23)
+    sk = rng.integers(0, n_r * 64 + 1000, size=n_s)
+    for i, k in enumerate(heavy):
+        sk[rng.choice(n_s, 3, replace=False)] = k
+    rr = rng.permutation(n_r).astype(np.int32)
+    sr = rng.permutation(n_s).astype(np.int32)
+    check_small(hj.params(**kw), rk.astype(np.int32), rr, sk.astype(np.int32), sr)
+
+
 def offset_view(a, off):
     """Device copy of `a` that starts `off` int32 elements into a larger buffer
     (input columns at every 4-byte alignment inside a 16-byte line)."""
