@@ -273,6 +273,7 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, v
 struct ShjTableWs {
     uint64_t* table;
     uint32_t* next;
+    hj::HotKeys* hot;
     uint32_t log2_slots;
     size_t bytes;
 };
@@ -283,11 +284,13 @@ ShjTableWs shj_table_layout(uint64_t n_r, void* base) {
     w.log2_slots = std::max<uint32_t>(1, ceil_log2(2 * std::max<uint64_t>(n_r, 1)));
     w.table = c.take<uint64_t>(1ull << w.log2_slots);
     w.next = c.take<uint32_t>(n_r);
+    w.hot = c.take<hj::HotKeys>(1);
     w.bytes = c.off;
     return w;
 }
 
 struct ShjProbeWs {
+    hj::HeavyQueue* heavy;  // one-pass: heavy S tuples shared by all workgroups
     uint64_t* wave_cnt;
     uint64_t* st;  // scan state of the per-wave counts
     uint64_t nst;
@@ -299,6 +302,7 @@ ShjProbeWs shj_probe_layout(uint64_t n_s, void* base) {
     ShjProbeWs w{};
     Carver c(base);
     w.tiles = cdiv(n_s, hj::kShjTile);
+    w.heavy = c.take<hj::HeavyQueue>(1);
     w.wave_cnt = c.take<uint64_t>(w.tiles * hj::kShjWavesPerBlock);
     w.nst = hj::scan_state_words(w.tiles * hj::kShjWavesPerBlock);
     w.st = c.take<uint64_t>(w.nst);
@@ -382,29 +386,31 @@ hj_status check_call(const hj_params* p, const hj_rel* R, const hj_rel* S, const
 }
 
 // SHJ build (Algorithm 1, b1-b4): empty slots, then R inserted.
-// zero_total (optional) is cleared by the fill.
-void shj_build_table(const hj_rel& R, const ShjTableWs& t, uint64_t* zero_total, hj::Recorder& rec) {
-    hj::shj_fill(t.table, 1ull << t.log2_slots, zero_total, rec);
-    hj::shj_build(R.key, R.n, t.table, t.next, t.log2_slots, rec);
+void shj_build_table(const hj_rel& R, const ShjTableWs& t, hj::Recorder& rec) {
+    hj::shj_fill(t.table, 1ull << t.log2_slots, t.hot, rec);
+    hj::shj_build(R.key, R.n, t.table, t.next, t.log2_slots, t.hot, rec);
 }
 
 // SHJ probe (Algorithm 1, p1-p4) of a table built over R.
 void shj_probe_table(const Plan& pl, const ShjTableWs& t, const hj_rel& R, const hj_rel& S,
                      const hj_out& out, const ShjProbeWs& w, uint64_t* d_count, hj::Recorder& rec) {
     if (!pl.one_pass) {
-        hj::shj_count(S.key, S.n, t.table, t.next, t.log2_slots, R.key, R.n, w.wave_cnt, rec);
+        hj::shj_count(S.key, S.n, t.table, t.next, t.log2_slots, R.key, R.n, t.hot, w.wave_cnt, rec);
         hj::zero_words(w.st, w.nst, rec);
         hj::scan_u64(w.wave_cnt, w.wave_cnt, w.tiles * hj::kShjWavesPerBlock, w.st, d_count, rec);
+    } else {
+        hj::shj_zero_one_pass(d_count, w.heavy, rec);
     }
-    hj::shj_write(S.key, S.rid, S.n, t.table, t.next, t.log2_slots, R.key, R.rid, R.n,
-                  pl.one_pass ? nullptr : w.wave_cnt, d_count, out.rid_r, out.rid_s, out.capacity, rec);
+    hj::shj_write(S.key, S.rid, S.n, t.table, t.next, t.log2_slots, R.key, R.rid, R.n, t.hot,
+                  pl.one_pass ? nullptr : w.wave_cnt, d_count, pl.one_pass ? w.heavy : nullptr, out.rid_r,
+                  out.rid_s, out.capacity, rec);
 }
 
 void run_shj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
              uint64_t* d_count, hj::Recorder& rec) {
     const ShjTableWs t = shj_table_layout(R.n, ws);
     const ShjProbeWs w = shj_probe_layout(S.n, (char*)ws + t.bytes);
-    shj_build_table(R, t, pl.one_pass ? d_count : nullptr, rec);
+    shj_build_table(R, t, rec);
     shj_probe_table(pl, t, R, S, out, w, d_count, rec);
 }
 
@@ -492,7 +498,7 @@ void run_join(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& ou
 void run_build(const Plan& pl, const hj_rel& R, void* ws, hj::Recorder& rec) {
     if (R.n == 0 || (pl.phj && pl.passes == 0)) return;  // passes 0: the table is R itself
     if (!pl.phj) {
-        shj_build_table(R, shj_table_layout(R.n, ws), nullptr, rec);
+        shj_build_table(R, shj_table_layout(R.n, ws), rec);
         return;
     }
     const PhjWs w = phj_layout(pl, R.n, 0, 0, ws);
@@ -511,7 +517,6 @@ void run_probe(const Plan& pl, const hj_table& t, const hj_rel& S, const hj_out&
     } else if (!pl.phj) {
         const ShjTableWs tw = shj_table_layout(t.n_r, t.ws);
         const ShjProbeWs w = shj_probe_layout(S.n, ws);
-        if (pl.one_pass) hj::write_zero_count(d_count, rec);
         shj_probe_table(pl, tw, R, S, out, w, d_count, rec);
     } else {
         // R's partitions and pair ranges are in the table; only S is partitioned here

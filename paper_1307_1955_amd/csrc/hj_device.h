@@ -75,6 +75,26 @@ __device__ __forceinline__ uint64_t chain_claim(uint64_t* table, uint64_t s, int
     }
 }
 
+// Keys that a build workgroup pushed kHotRun or more times in one run (the
+// heavy keys of a skewed R), recorded by the SHJ build so that its probes can
+// hand such tuples over without walking their chains first.  n may exceed
+// kHotKeys; the keys beyond are not recorded.
+constexpr uint32_t kHotKeys = 63;
+constexpr uint32_t kHotRun = 16;
+struct HotKeys {
+    uint32_t n;
+    int32_t key[kHotKeys];
+};
+
+__device__ __forceinline__ void record_hot(HotKeys* hot, int32_t key) {
+    // a key may land twice when two workgroups record it at once: harmless
+    const uint32_t n = min(__hip_atomic_load(&hot->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), kHotKeys);
+    for (uint32_t i = 0; i < n; ++i)
+        if (hot->key[i] == key) return;
+    const uint32_t idx = atomicAdd(&hot->n, 1u);
+    if (idx < kHotKeys) hot->key[idx] = key;
+}
+
 // Pushes of duplicate keys by one wave.  A row is pushed in front of its key's
 // chain by exchanging the slot's head, which cannot fail (a claimed slot keeps
 // its key), so a heavy key costs no compare-and-swap retries.  Exchanges are
@@ -89,6 +109,8 @@ struct WavePush {
     uint64_t slot = kClaimed;
     int32_t key = 0;
     uint32_t head = 0, tail = 0;
+    uint32_t len = 0;          // rows in the pending run
+    HotKeys* hot_keys = nullptr;  // where runs of kHotRun or more rows record their key
     // The slot of the last key the wave pushed: a row with that key can skip
     // chain_claim (a claimed slot never moves), which keeps a heavy key's rows
     // off its slot's cache line.
@@ -103,6 +125,7 @@ struct WavePush {
                 const uint64_t prev =
                     atomicExch((unsigned long long*)&table[slot], (unsigned long long)chain_slot(key, head));
                 next[tail] = (uint32_t)(prev >> 32);
+                if (hot_keys && len >= kHotRun) record_hot(hot_keys, key);
             }
             slot = kClaimed;
         }
@@ -115,28 +138,30 @@ struct WavePush {
     struct Run {
         uint64_t slot;
         int32_t key;
-        uint32_t head, tail;
+        uint32_t head, tail, len;
     };
     template <uint32_t kWaves>
     __device__ __forceinline__ void flush_block(uint64_t* table, uint32_t* next, Run* runs) {
-        if (__lane_id() == 0) runs[threadIdx.x / kWave] = Run{slot, key, head, tail};
+        if (__lane_id() == 0) runs[threadIdx.x / kWave] = Run{slot, key, head, tail, len};
         slot = kClaimed;
         __syncthreads();
         if (threadIdx.x == 0) {
             for (uint32_t i = 0; i < kWaves; ++i) {
                 const Run a = runs[i];
                 if (a.slot == kClaimed) continue;
-                uint32_t t = a.tail;
+                uint32_t t = a.tail, rows = a.len;
                 for (uint32_t j = i + 1; j < kWaves; ++j) {
                     if (runs[j].slot == a.slot) {
                         next[t] = runs[j].head;
                         t = runs[j].tail;
+                        rows += runs[j].len;
                         runs[j].slot = kClaimed;
                     }
                 }
                 const uint64_t prev =
                     atomicExch((unsigned long long*)&table[a.slot], (unsigned long long)chain_slot(a.key, a.head));
                 next[t] = (uint32_t)(prev >> 32);
+                if (hot_keys && rows >= kHotRun) record_hot(hot_keys, a.key);
             }
         }
         __syncthreads();
@@ -158,16 +183,19 @@ struct WavePush {
             const uint64_t after = peers & ~((2ull << lane) - 1ull);
             const int succ = after ? __ffsll((unsigned long long)after) - 1 : (int)lane;
             const uint32_t succ_row = __shfl(row, succ);
+            const uint32_t rows = (uint32_t)__popcll(peers);
             if (s == ls && after) next[row] = succ_row;
             if (ls == slot) {
                 if ((int)lane == last) next[row] = head;  // the run goes in front of the pending chain
                 head = first_row;
+                len += rows;
             } else {
                 flush(table, next);
                 slot = hot_slot = ls;
                 key = hot_key = lk;
                 head = first_row;
                 tail = last_row;
+                len = rows;
             }
         }
     }

@@ -36,6 +36,7 @@ __device__ __forceinline__ bool is_heavy(uint32_t c) { return (c & kHeavyBit) !=
 // The heavy tuples of one probe round (LDS).
 struct HeavySet {
     uint32_t n;                  // tuples registered (may exceed kMaxHeavy: the rest walk)
+    uint32_t queued;             // bit e: entry e was handed to other workgroups (count 0 here)
     int32_t key[kMaxHeavy];
     int32_t srid[kMaxHeavy];
     uint32_t rep[kMaxHeavy];     // first entry with the same key (its scan serves both)
@@ -55,12 +56,10 @@ __device__ __forceinline__ uint32_t chain_len_bounded(const uint32_t* __restrict
     return c;
 }
 
-// Count word of an S tuple whose chain starts at head field h: the chain
-// length, or kHeavyBit | entry when the tuple is registered in hs.
-__device__ __forceinline__ uint32_t heavy_or_len(const uint32_t* __restrict__ next, uint32_t h, uint32_t lim,
-                                                 int32_t key, int32_t srid, HeavySet* hs) {
-    const uint32_t c = chain_len_bounded(next, h, lim);
-    if (c <= lim) return c;
+// Registers an S tuple whose chain starts at head field h in hs: returns
+// kHeavyBit | entry, or the chain length when the set is full.
+__device__ __forceinline__ uint32_t register_heavy(const uint32_t* __restrict__ next, uint32_t h, int32_t key,
+                                                   int32_t srid, HeavySet* hs) {
     const uint32_t e = atomicAdd(&hs->n, 1u);
     if (e >= kMaxHeavy) return chain_len(next, h);
     hs->key[e] = key;
@@ -68,19 +67,31 @@ __device__ __forceinline__ uint32_t heavy_or_len(const uint32_t* __restrict__ ne
     return kHeavyBit | e;
 }
 
+// Count word of an S tuple whose chain starts at head field h: the chain
+// length, or kHeavyBit | entry when the tuple is registered in hs.
+__device__ __forceinline__ uint32_t heavy_or_len(const uint32_t* __restrict__ next, uint32_t h, uint32_t lim,
+                                                 int32_t key, int32_t srid, HeavySet* hs) {
+    const uint32_t c = chain_len_bounded(next, h, lim);
+    if (c <= lim) return c;
+    return register_heavy(next, h, key, srid, hs);
+}
+
 // Exact counts of the registered tuples: one scan of R's keys per distinct
 // key, kV keys per thread per step (Len: an index type that holds r_len).
-// All threads of the block call it, after the registrations.
-template <uint32_t kBlock, uint32_t kV, typename Len>
+// kQueued: entries marked in hs->queued are skipped (count 0).  All threads of
+// the block call it, after the registrations.
+template <uint32_t kBlock, uint32_t kV, bool kQueued = false, typename Len>
 __device__ __forceinline__ void heavy_counts(const int32_t* __restrict__ rk, Len r_len, HeavySet* hs) {
     constexpr uint32_t kWaves = kBlock / kWave;
     static_assert(kWaves <= kHeavyMaxWaves, "block too large for the heavy set");
     __syncthreads();  // registrations done
     const uint32_t ne = min(hs->n, kMaxHeavy);
     if (threadIdx.x < ne) {
-        uint32_t r = threadIdx.x;
-        for (uint32_t i = 0; i < threadIdx.x; ++i) {
-            if (hs->key[i] == hs->key[threadIdx.x]) {
+        // queued entries are nobody's representative and have none
+        const uint32_t queued = kQueued ? hs->queued : 0u;
+        uint32_t r = (queued >> threadIdx.x) & 1u ? kMaxHeavy : threadIdx.x;
+        for (uint32_t i = 0; i < threadIdx.x && r != kMaxHeavy; ++i) {
+            if (!((queued >> i) & 1u) && hs->key[i] == hs->key[threadIdx.x]) {
                 r = i;
                 break;
             }
@@ -112,7 +123,8 @@ __device__ __forceinline__ void heavy_counts(const int32_t* __restrict__ rk, Len
         }
         __syncthreads();
     }
-    if (threadIdx.x < ne) hs->cnt[threadIdx.x] = hs->cnt[hs->rep[threadIdx.x]];
+    if (threadIdx.x < ne)
+        hs->cnt[threadIdx.x] = !kQueued || hs->rep[threadIdx.x] < kMaxHeavy ? hs->cnt[hs->rep[threadIdx.x]] : 0u;
     __syncthreads();
 }
 

@@ -58,18 +58,42 @@ void zero_words(uint64_t* p, uint64_t n, Recorder& rec);
 constexpr uint32_t kShjBlock = 256;
 constexpr uint32_t kShjTile = 2048;  // S tuples per probe tile
 constexpr uint32_t kShjWavesPerBlock = kShjBlock / 64;
-// Fills the table with empty slots; zero_total (optional) is set to 0.
-void shj_fill(uint64_t* table, uint64_t nslots, uint64_t* zero_total, Recorder& rec);
+struct HotKeys;  // keys the build saw in long push runs (hj_device.h)
+// Fills the table with empty slots and clears the hot-key record.
+void shj_fill(uint64_t* table, uint64_t nslots, HotKeys* hot, Recorder& rec);
 void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint32_t log2_slots,
-               Recorder& rec);
+               HotKeys* hot, Recorder& rec);
+// Heavy S tuples of a one-pass SHJ probe are handed to a device-wide queue:
+// any workgroup that has finished its own tile claims chunks of R and writes
+// their matches (one 64-byte record per tuple; the queue is zeroed before each
+// probe).
+constexpr uint32_t kHeavyJobs = 64;
+constexpr uint32_t kHelpChunk = 1u << 16;  // R rows per claimed chunk
+struct HeavyJob {
+    int32_t key, srid;
+    uint32_t valid;        // 1 once key and srid are written
+    uint32_t write_next;   // next chunk to claim
+    uint32_t pad[12];
+};
+struct HeavyQueue {
+    uint32_t n;            // tuples handed in (may exceed kHeavyJobs: the rest stay with their workgroup)
+    uint32_t pad[15];
+    HeavyJob job[kHeavyJobs];
+};
+static_assert(sizeof(HeavyJob) == 64 && sizeof(HeavyQueue) % 8 == 0, "queue layout");
+// Sets *d_count to zero and empties the queue (one-pass SHJ probes).
+void shj_zero_one_pass(uint64_t* d_count, HeavyQueue* q, Recorder& rec);
+
 // The probe kernels read R's columns (r_key, r_rid, n_r rows, the ones the
 // table was built from) for keys with long chains.
 void shj_count(const int32_t* s_key, uint64_t n_s, const uint64_t* table, const uint32_t* next,
-               uint32_t log2_slots, const int32_t* r_key, uint64_t n_r, uint64_t* wave_cnt, Recorder& rec);
+               uint32_t log2_slots, const int32_t* r_key, uint64_t n_r, const HotKeys* hot, uint64_t* wave_cnt,
+               Recorder& rec);
 void shj_write(const int32_t* s_key, const int32_t* s_rid, uint64_t n_s, const uint64_t* table,
                const uint32_t* next, uint32_t log2_slots, const int32_t* r_key, const int32_t* r_rid,
-               uint64_t n_r, const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
-               uint64_t capacity, Recorder& rec);  // wave_base == nullptr: one-pass output into *total
+               uint64_t n_r, const HotKeys* hot, const uint64_t* wave_base, uint64_t* total, HeavyQueue* heavy,
+               int32_t* out_r, int32_t* out_s, uint64_t capacity,
+               Recorder& rec);  // wave_base == nullptr: one-pass output into *total
 
 // ---- phj_partition.hip ----
 // Threads of a partitioning workgroup for a given tile: 512 from 4096 tuples on

@@ -23,7 +23,10 @@ namespace hj {
 
 namespace {
 
-__global__ void __launch_bounds__(256) k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
+__global__ void __launch_bounds__(256) k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v,
+                                                 uint32_t* __restrict__ zero, uint32_t zero_words) {
+    if (blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < zero_words; i += blockDim.x) zero[i] = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 2;
     for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; i < n; i += stride) {
         if (i + 1 < n) {
@@ -45,12 +48,13 @@ __device__ __forceinline__ uint64_t home_slot(int32_t k, uint32_t log2_slots) {
 
 __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ key, uint64_t n,
                                                   uint64_t* __restrict__ table, uint32_t* __restrict__ next,
-                                                  uint32_t log2_slots) {
+                                                  uint32_t log2_slots, HotKeys* hot) {
     constexpr uint32_t kWaves = 256 / kWave;
     __shared__ WavePush::Run runs[kWaves];
     const PowStep step{(1ull << log2_slots) - 1};
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     WavePush push;
+    push.hot_keys = hot;
     for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {  // uniform trip count
         const uint64_t i = i0 + threadIdx.x;
         int32_t k = 0;
@@ -72,14 +76,15 @@ __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ k
 constexpr uint32_t kSub = kShjTile / kShjWavesPerBlock;
 constexpr uint32_t kSU = kSub / kWave;
 
-// An S tuple whose chain is longer than heavy_limit(|R|) is registered in hs
-// and counted and written by the whole block (cooperative scan of R).
+// An S tuple whose chain is longer than lim, or whose key the build recorded
+// as hot (hk[0..nhk), LDS), is registered in hs as heavy.
 // hs->n must be zero and visible to the block before the call.
 template <bool kRids>
 __device__ __forceinline__ void shj_probe(const int32_t* __restrict__ s_key, const int32_t* __restrict__ s_rid,
                                           uint64_t begin, uint64_t n_s, const uint64_t* __restrict__ table,
                                           const uint32_t* __restrict__ next, uint32_t log2_slots, uint32_t lim,
-                                          HeavySet* hs, int32_t* q, int32_t* qr, uint32_t* head, uint32_t* cnt) {
+                                          const int32_t* hk, uint32_t nhk, HeavySet* hs, int32_t* q, int32_t* qr,
+                                          uint32_t* head, uint32_t* cnt) {
     const PowStep step{(1ull << log2_slots) - 1};
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
@@ -92,9 +97,22 @@ __device__ __forceinline__ void shj_probe(const int32_t* __restrict__ s_key, con
             q[u] = s_key[j];
             if (kRids) qr[u] = s_rid[j];
             head[u] = chain_find(table, home_slot(q[u], log2_slots), q[u], step);
-            if (head[u] != kNotFound) cnt[u] = heavy_or_len(next, head[u], lim, q[u], kRids ? qr[u] : 0, hs);
+            if (head[u] != kNotFound) {
+                bool hot = false;
+                if (!(head[u] & kLast))  // a chain of one row is never heavy
+                    for (uint32_t i = 0; i < nhk; ++i) hot |= hk[i] == q[u];
+                cnt[u] = hot ? register_heavy(next, head[u], q[u], kRids ? qr[u] : 0, hs)
+                             : heavy_or_len(next, head[u], lim, q[u], kRids ? qr[u] : 0, hs);
+            }
         }
     }
+}
+
+// The build's hot keys into LDS (before the barrier that publishes hs->n = 0).
+__device__ __forceinline__ void load_hot(const HotKeys* hot, int32_t* hk, uint32_t* nhk) {
+    const uint32_t n = min(hot->n, kHotKeys);
+    if (threadIdx.x == 0) *nhk = n;
+    if (threadIdx.x < n) hk[threadIdx.x] = hot->key[threadIdx.x];
 }
 
 __device__ __forceinline__ uint32_t count_of(uint32_t c, const HeavySet* hs) {
@@ -105,15 +123,20 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_count(const int32_t* __restri
                                                         const uint64_t* __restrict__ table,
                                                         const uint32_t* __restrict__ next,
                                                         uint32_t log2_slots, const int32_t* __restrict__ r_key,
-                                                        uint64_t n_r, uint64_t* __restrict__ wave_cnt) {
+                                                        uint64_t n_r, const HotKeys* __restrict__ hot,
+                                                        uint64_t* __restrict__ wave_cnt) {
     __shared__ HeavySet hs;
+    __shared__ int32_t hk[kHotKeys];
+    __shared__ uint32_t nhk;
     const uint32_t w = threadIdx.x / kWave;
     const uint64_t begin = (uint64_t)blockIdx.x * kShjTile + (uint64_t)w * kSub;
-    if (threadIdx.x == 0) hs.n = 0;
+    load_hot(hot, hk, &nhk);
+    if (threadIdx.x == 0) hs.n = hs.queued = 0;
     __syncthreads();
     int32_t q[kSU], qr[kSU];
     uint32_t head[kSU], c[kSU];
-    shj_probe<false>(s_key, nullptr, begin, n_s, table, next, log2_slots, heavy_limit(n_r), &hs, q, qr, head, c);
+    shj_probe<false>(s_key, nullptr, begin, n_s, table, next, log2_slots, heavy_limit(n_r), hk, nhk, &hs, q, qr,
+                     head, c);
     heavy_counts<kShjBlock, kHeavyV>(r_key, n_r, &hs);
     uint64_t cnt = 0;
 #pragma unroll
@@ -122,26 +145,164 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_count(const int32_t* __restri
     if (lane_id() == 0) wave_cnt[(uint64_t)blockIdx.x * kShjWavesPerBlock + w] = cnt;
 }
 
+// ---- Heavy S tuples shared by all workgroups (one-pass output) ----
+// A workgroup hands the heavy tuples it registered to the queue (hand_off);
+// every workgroup, once its tile is written, runs help_heavy: for each queued
+// tuple it claims chunks of R and writes the tuple's matches in them, each
+// scan step reserving its slots on the running total (one-pass output has no
+// fixed order, so no count is needed first).  Nothing waits: a workgroup
+// takes what is unclaimed and leaves; the workgroup that queued a tuple runs
+// help_heavy too, so every chunk is written before the launch ends.
+
+// Moves this block's registered heavy tuples to the queue while it has room
+// (marked in hs->queued); a tuple that finds the queue full is walked by its
+// lane after all (c[u] becomes its chain length, also marked in hs->queued,
+// so nothing is left for the block-local heavy path).  All threads call it
+// after the registrations.
+__device__ __forceinline__ void hand_off(HeavyQueue* Q, HeavySet* hs, const uint32_t* __restrict__ next,
+                                         const uint32_t* head, uint32_t* c) {
+    __syncthreads();  // registrations done
+    const uint32_t ne = min(hs->n, kMaxHeavy);
+    if (threadIdx.x < ne) {
+        const uint32_t idx = atomicAdd(&Q->n, 1u);
+        if (idx < kHeavyJobs) {
+            HeavyJob* J = &Q->job[idx];
+            J->key = hs->key[threadIdx.x];
+            J->srid = hs->srid[threadIdx.x];
+            __hip_atomic_store(&J->valid, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        atomicOr(&hs->queued, (idx < kHeavyJobs ? 1u : 0u) << threadIdx.x);
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t u = 0; u < kSU; ++u) {
+        if (is_heavy(c[u])) {
+            const uint32_t e = c[u] & ~kHeavyBit;
+            if (!((hs->queued >> e) & 1u)) {
+                c[u] = chain_len(next, head[u]);
+                atomicOr(&hs->queued, 1u << e);
+            }
+        }
+    }
+}
+
+// A one-pass probe hands a tuple to the queue once its chain is longer than
+// this: a lane walking further would hold its workgroup past the others
+// (~240 ns per step), while a queued tuple costs one scan of R shared by the
+// workgroups that are still running.
+constexpr uint32_t kQueueWalk = 1024;
+
+// Claims the next chunk of a phase for the block (thread 0 takes it, LDS
+// broadcasts it).  sh: LDS scratch.
+__device__ __forceinline__ uint32_t claim_chunk(uint32_t* counter, uint32_t* sh) {
+    __syncthreads();  // sh free
+    if (threadIdx.x == 0) sh[0] = atomicAdd(counter, 1u);
+    __syncthreads();
+    return sh[0];
+}
+
+template <uint32_t kBlock>
+__device__ __forceinline__ void help_heavy(HeavyQueue* Q, const int32_t* __restrict__ rk,
+                                           const int32_t* __restrict__ rr, uint64_t n_r,
+                                           unsigned long long* __restrict__ total, uint64_t capacity,
+                                           int32_t* __restrict__ out_r, int32_t* __restrict__ out_s, uint32_t* sh) {
+    constexpr uint32_t kWaves = kBlock / kWave;
+    constexpr uint32_t kV = kHeavyV;
+    uint32_t* cnt = sh + 8;  // kV * kWaves per-wave hit counts of a step
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t nchunks = (uint32_t)((n_r + kHelpChunk - 1) / kHelpChunk);
+    __syncthreads();
+    if (threadIdx.x == 0) sh[1] = min(__hip_atomic_load(&Q->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), kHeavyJobs);
+    __syncthreads();
+    const uint32_t nj = sh[1];
+    for (uint32_t e = 0; e < nj; ++e) {
+        HeavyJob* J = &Q->job[e];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sh[1] = __hip_atomic_load(&J->valid, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            sh[2] = (uint32_t)J->key;
+            sh[3] = (uint32_t)J->srid;
+        }
+        __syncthreads();
+        if (!sh[1]) continue;
+        const int32_t k = (int32_t)sh[2], srid = (int32_t)sh[3];
+        while (true) {
+            const uint32_t c = claim_chunk(&J->write_next, sh);
+            if (c >= nchunks) break;
+            const uint64_t lo = (uint64_t)c * kHelpChunk, hi = min(lo + kHelpChunk, n_r);
+            for (uint64_t j0 = lo; j0 < hi; j0 += (uint64_t)kV * kBlock) {
+                // element u of the thread: row j0 + u * kBlock + threadIdx.x
+                uint32_t bits = 0;
+#pragma unroll
+                for (uint32_t u = 0; u < kV; ++u) {
+                    const uint64_t j = j0 + (uint64_t)u * kBlock + threadIdx.x;
+                    bits |= (j < hi && rk[j] == k) ? 1u << u : 0u;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kV; ++u) {
+                    const uint32_t nh = (uint32_t)__popcll(__ballot((bits >> u) & 1u));
+                    if (lane_id() == 0) cnt[u * kWaves + w] = nh;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    uint32_t t = 0;
+                    for (uint32_t i = 0; i < kV * kWaves; ++i) t += cnt[i];
+                    const unsigned long long b = t ? atomicAdd(total, (unsigned long long)t) : 0ull;
+                    sh[4] = (uint32_t)b;
+                    sh[5] = (uint32_t)(b >> 32);
+                }
+                __syncthreads();
+                uint64_t base = (uint64_t)sh[4] | ((uint64_t)sh[5] << 32);
+                for (uint32_t u = 0; u < kV; ++u) {
+                    uint32_t before = 0, all = 0;
+                    for (uint32_t i = 0; i < kWaves; ++i) {
+                        const uint32_t t = cnt[u * kWaves + i];
+                        before += i < w ? t : 0u;
+                        all += t;
+                    }
+                    const uint64_t mk = __ballot((bits >> u) & 1u);
+                    if ((bits >> u) & 1u) {
+                        const uint64_t at = base + before + (uint32_t)__popcll(mk & lanemask_lt());
+                        if (at < capacity) {
+                            out_r[at] = rr[j0 + (uint64_t)u * kBlock + threadIdx.x];
+                            out_s[at] = srid;
+                        }
+                    }
+                    base += all;
+                }
+                __syncthreads();  // cnt and sh reused
+            }
+        }
+    }
+}
+
 // Write pass; kOnePass reserves the block's output with one atomic add on the
 // running total instead of reading a scanned offset (see HJ_FLAG_ONE_PASS).
 template <bool kOnePass>
-__global__ void __launch_bounds__(kShjBlock) k_shj_write(
+__global__ void __launch_bounds__(kShjBlock) __attribute__((amdgpu_waves_per_eu(8))) k_shj_write(
     const int32_t* __restrict__ s_key, const int32_t* __restrict__ s_rid, uint64_t n_s,
     const uint64_t* __restrict__ table, const uint32_t* __restrict__ next, uint32_t log2_slots,
     const int32_t* __restrict__ r_key, const int32_t* __restrict__ r_rid, uint64_t n_r,
-    const uint64_t* __restrict__ wave_base, unsigned long long* __restrict__ total, int32_t* __restrict__ out_r,
+    const HotKeys* __restrict__ hot, const uint64_t* __restrict__ wave_base,
+    unsigned long long* __restrict__ total, HeavyQueue* heavy, int32_t* __restrict__ out_r,
     int32_t* __restrict__ out_s, uint64_t capacity) {
     __shared__ uint64_t wtot[kShjWavesPerBlock + 1];
     __shared__ HeavySet hs;
+    __shared__ int32_t hk[kHotKeys];
+    __shared__ uint32_t nhk;
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
     const uint64_t begin = (uint64_t)blockIdx.x * kShjTile + (uint64_t)w * kSub;
-    if (threadIdx.x == 0) hs.n = 0;
+    load_hot(hot, hk, &nhk);
+    if (threadIdx.x == 0) hs.n = hs.queued = 0;
     __syncthreads();
     int32_t q[kSU], qr[kSU];
     uint32_t head[kSU], c[kSU];
-    shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, heavy_limit(n_r), &hs, q, qr, head, c);
-    heavy_counts<kShjBlock, kHeavyV>(r_key, n_r, &hs);
+    // one-pass: a chain is heavy from kQueueWalk rows on (handed to every workgroup)
+    const uint32_t lim = kOnePass ? min(heavy_limit(n_r), kQueueWalk) : heavy_limit(n_r);
+    shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, lim, hk, nhk, &hs, q, qr, head, c);
+    if (kOnePass) hand_off(heavy, &hs, next, head, c);
+    heavy_counts<kShjBlock, kHeavyV, kOnePass>(r_key, n_r, &hs);
     uint64_t pos0;
     if (kOnePass) {
         uint64_t mine = 0;
@@ -185,66 +346,70 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_write(
         }
     }
     heavy_writes<kShjBlock, kHeavyV>(r_key, r_rid, n_r, &hs, capacity, out_r, out_s);
+    if (kOnePass) help_heavy<kShjBlock>(heavy, r_key, r_rid, n_r, total, capacity, out_r, out_s, hs.wsum);
 }
 
-__global__ void k_zero_u64(uint64_t* p) {
-    if (threadIdx.x == 0) *p = 0;
+__global__ void __launch_bounds__(256) k_zero_one_pass(uint64_t* __restrict__ total, uint64_t* __restrict__ q) {
+    if (threadIdx.x == 0) *total = 0;
+    for (uint32_t i = threadIdx.x; i < sizeof(HeavyQueue) / 8; i += blockDim.x) q[i] = 0;
 }
 
 }  // namespace
 
-void shj_fill(uint64_t* table, uint64_t nslots, uint64_t* zero_total, Recorder& rec) {
+void shj_fill(uint64_t* table, uint64_t nslots, HotKeys* hot, Recorder& rec) {
     uint64_t blocks = (nslots / 2 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks == 0) blocks = 1;
     rec.before("shj_fill");
     hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)blocks), dim3(256), 0, rec.stream, table, nslots,
-                       kEmptySlot);
+                       kEmptySlot, reinterpret_cast<uint32_t*>(hot), (uint32_t)(sizeof(HotKeys) / 4));
     rec.after();
-    if (zero_total) {
-        rec.before("zero_count");
-        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, rec.stream, zero_total);
-        rec.after();
-    }
+}
+
+void shj_zero_one_pass(uint64_t* d_count, HeavyQueue* q, Recorder& rec) {
+    rec.before("zero_count");
+    hipLaunchKernelGGL(k_zero_one_pass, dim3(1), dim3(256), 0, rec.stream, d_count, reinterpret_cast<uint64_t*>(q));
+    rec.after();
 }
 
 void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint32_t log2_slots,
-               Recorder& rec) {
+               HotKeys* hot, Recorder& rec) {
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;  // grid-stride: a wave's pending push chain spans its rows
     if (blocks == 0) return;
     rec.before("shj_build");
     hipLaunchKernelGGL(k_shj_build, dim3((uint32_t)blocks), dim3(256), 0, rec.stream, key, n, table, next,
-                       log2_slots);
+                       log2_slots, hot);
     rec.after();
 }
 
 void shj_count(const int32_t* s_key, uint64_t n_s, const uint64_t* table, const uint32_t* next,
-               uint32_t log2_slots, const int32_t* r_key, uint64_t n_r, uint64_t* wave_cnt, Recorder& rec) {
+               uint32_t log2_slots, const int32_t* r_key, uint64_t n_r, const HotKeys* hot, uint64_t* wave_cnt,
+               Recorder& rec) {
     const uint64_t tiles = (n_s + kShjTile - 1) / kShjTile;
     if (tiles == 0) return;
     rec.before("shj_count");
     hipLaunchKernelGGL(k_shj_count, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key, n_s,
-                       table, next, log2_slots, r_key, n_r, wave_cnt);
+                       table, next, log2_slots, r_key, n_r, hot, wave_cnt);
     rec.after();
 }
 
 void shj_write(const int32_t* s_key, const int32_t* s_rid, uint64_t n_s, const uint64_t* table,
                const uint32_t* next, uint32_t log2_slots, const int32_t* r_key, const int32_t* r_rid,
-               uint64_t n_r, const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
-               uint64_t capacity, Recorder& rec) {
+               uint64_t n_r, const HotKeys* hot, const uint64_t* wave_base, uint64_t* total, HeavyQueue* heavy,
+               int32_t* out_r, int32_t* out_s, uint64_t capacity, Recorder& rec) {
     const uint64_t tiles = (n_s + kShjTile - 1) / kShjTile;
     if (tiles == 0) return;
     if (wave_base == nullptr) {
         rec.before("shj_write_1pass");
         hipLaunchKernelGGL(k_shj_write<true>, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key,
-                           s_rid, n_s, table, next, log2_slots, r_key, r_rid, n_r, wave_base, (unsigned long long*)total,
-                           out_r, out_s, capacity);
+                           s_rid, n_s, table, next, log2_slots, r_key, r_rid, n_r, hot, wave_base,
+                           (unsigned long long*)total, heavy, out_r, out_s, capacity);
     } else {
         rec.before("shj_write");
         hipLaunchKernelGGL(k_shj_write<false>, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key,
-                           s_rid, n_s, table, next, log2_slots, r_key, r_rid, n_r, wave_base, (unsigned long long*)total,
-                           out_r, out_s, capacity);
+                           s_rid, n_s, table, next, log2_slots, r_key, r_rid, n_r, hot, wave_base,
+                           (unsigned long long*)total, heavy, out_r, out_s, capacity);
     }
     rec.after();
 }

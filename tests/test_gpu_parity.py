@@ -307,7 +307,8 @@ def test_paper_skew_sets_16m(frac):
     """Section 5.1's low- and high-skew sets at 16M x 16M (R: a fraction frac of the
     rows on one key, S uniform over 1..2^25), with three S tuples forced onto the
     skewed key so the probe meets its chain: PHJ (library choice) and SHJ, every
-    pair against the oracle."""
+    pair against the oracle (one-pass SHJ hands the heavy tuples to the device-wide
+    queue that every workgroup helps with)."""
     n = 1 << 24
     r, s = gen.skewed_r(31, n, n, 2 * n, frac)
     s.key[[5, n // 2, n - 1]] = gen.SKEW_KEY
@@ -315,7 +316,7 @@ def test_paper_skew_sets_16m(frac):
     want = oracle.canonical(want_r, want_s)
     del want_r, want_s
     t = to_dev(r.key, r.rid, s.key, s.rid)
-    for p in (hj.params("auto", one_pass=True), hj.params("shj")):
+    for p in (hj.params("auto", one_pass=True), hj.params("shj"), hj.params("shj", one_pass=True)):
         got_r, got_s, cnt = gpu_join(p, *t, capacity=len(want))
         assert cnt == len(want)
         assert np.array_equal(oracle.canonical(got_r, got_s), want)
