@@ -67,7 +67,7 @@ void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, 
 // any workgroup that has finished its own tile claims chunks of R and writes
 // their matches (one 64-byte record per tuple; the queue is zeroed before each
 // probe).
-constexpr uint32_t kHeavyJobs = 64;
+constexpr uint32_t kHeavyJobs = 256;
 constexpr uint32_t kHelpChunk = 1u << 16;  // R rows per claimed chunk
 struct HeavyJob {
     int32_t key, srid;

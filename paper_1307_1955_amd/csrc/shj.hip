@@ -155,12 +155,10 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_count(const int32_t* __restri
 // help_heavy too, so every chunk is written before the launch ends.
 
 // Moves this block's registered heavy tuples to the queue while it has room
-// (marked in hs->queued); a tuple that finds the queue full is walked by its
-// lane after all (c[u] becomes its chain length, also marked in hs->queued,
-// so nothing is left for the block-local heavy path).  All threads call it
+// (marked in hs->queued); a tuple that finds the queue full stays with the
+// block's own scan of R (heavy_counts / heavy_writes).  All threads call it
 // after the registrations.
-__device__ __forceinline__ void hand_off(HeavyQueue* Q, HeavySet* hs, const uint32_t* __restrict__ next,
-                                         const uint32_t* head, uint32_t* c) {
+__device__ __forceinline__ void hand_off(HeavyQueue* Q, HeavySet* hs) {
     __syncthreads();  // registrations done
     const uint32_t ne = min(hs->n, kMaxHeavy);
     if (threadIdx.x < ne) {
@@ -170,18 +168,7 @@ __device__ __forceinline__ void hand_off(HeavyQueue* Q, HeavySet* hs, const uint
             J->key = hs->key[threadIdx.x];
             J->srid = hs->srid[threadIdx.x];
             __hip_atomic_store(&J->valid, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        atomicOr(&hs->queued, (idx < kHeavyJobs ? 1u : 0u) << threadIdx.x);
-    }
-    __syncthreads();
-#pragma unroll
-    for (uint32_t u = 0; u < kSU; ++u) {
-        if (is_heavy(c[u])) {
-            const uint32_t e = c[u] & ~kHeavyBit;
-            if (!((hs->queued >> e) & 1u)) {
-                c[u] = chain_len(next, head[u]);
-                atomicOr(&hs->queued, 1u << e);
-            }
+            atomicOr(&hs->queued, 1u << threadIdx.x);
         }
     }
 }
@@ -208,6 +195,7 @@ __device__ __forceinline__ void help_heavy(HeavyQueue* Q, const int32_t* __restr
                                            int32_t* __restrict__ out_r, int32_t* __restrict__ out_s, uint32_t* sh) {
     constexpr uint32_t kWaves = kBlock / kWave;
     constexpr uint32_t kV = kHeavyV;
+    static_assert(kHeavyJobs <= kBlock, "one thread per queued tuple looks for open work");
     uint32_t* cnt = sh + 8;  // kV * kWaves per-wave hit counts of a step
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t nchunks = (uint32_t)((n_r + kHelpChunk - 1) / kHelpChunk);
@@ -215,16 +203,29 @@ __device__ __forceinline__ void help_heavy(HeavyQueue* Q, const int32_t* __restr
     if (threadIdx.x == 0) sh[1] = min(__hip_atomic_load(&Q->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), kHeavyJobs);
     __syncthreads();
     const uint32_t nj = sh[1];
-    for (uint32_t e = 0; e < nj; ++e) {
+    if (nj == 0) return;
+    while (true) {
+        // the lowest queued tuple that still has unclaimed chunks (one thread looks at each)
+        __syncthreads();
+        if (threadIdx.x == 0) sh[6] = ~0u;
+        __syncthreads();
+        if (threadIdx.x < nj) {
+            HeavyJob* J = &Q->job[threadIdx.x];
+            if (__hip_atomic_load(&J->valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+                __hip_atomic_load(&J->write_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nchunks)
+                atomicMin(&sh[6], threadIdx.x);
+        }
+        __syncthreads();
+        const uint32_t e = sh[6];
+        if (e == ~0u) return;
         HeavyJob* J = &Q->job[e];
         __syncthreads();
         if (threadIdx.x == 0) {
-            sh[1] = __hip_atomic_load(&J->valid, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            (void)__hip_atomic_load(&J->valid, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);  // orders the reads below
             sh[2] = (uint32_t)J->key;
             sh[3] = (uint32_t)J->srid;
         }
         __syncthreads();
-        if (!sh[1]) continue;
         const int32_t k = (int32_t)sh[2], srid = (int32_t)sh[3];
         while (true) {
             const uint32_t c = claim_chunk(&J->write_next, sh);
@@ -301,7 +302,7 @@ __global__ void __launch_bounds__(kShjBlock) __attribute__((amdgpu_waves_per_eu(
     // one-pass: a chain is heavy from kQueueWalk rows on (handed to every workgroup)
     const uint32_t lim = kOnePass ? min(heavy_limit(n_r), kQueueWalk) : heavy_limit(n_r);
     shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, lim, hk, nhk, &hs, q, qr, head, c);
-    if (kOnePass) hand_off(heavy, &hs, next, head, c);
+    if (kOnePass) hand_off(heavy, &hs);
     heavy_counts<kShjBlock, kHeavyV, kOnePass>(r_key, n_r, &hs);
     uint64_t pos0;
     if (kOnePass) {
