@@ -302,7 +302,8 @@ __global__ void __launch_bounds__(kShjBlock) __attribute__((amdgpu_waves_per_eu(
     // one-pass: a chain is heavy from kQueueWalk rows on (handed to every workgroup)
     const uint32_t lim = kOnePass ? min(heavy_limit(n_r), kQueueWalk) : heavy_limit(n_r);
     shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, lim, hk, nhk, &hs, q, qr, head, c);
-    if (kOnePass) hand_off(heavy, &hs);
+    // with R in one chunk the queue adds no workgroups to a tuple: keep the block's own scan
+    if (kOnePass && n_r > kHelpChunk) hand_off(heavy, &hs);
     heavy_counts<kShjBlock, kHeavyV, kOnePass>(r_key, n_r, &hs);
     uint64_t pos0;
     if (kOnePass) {
