@@ -196,6 +196,23 @@ def test_interleaved_heavy_keys(kw):
     check_small(hj.params(**kw), rk.astype(np.int32), rr, sk.astype(np.int32), sr)
 
 
+@pytest.mark.parametrize("one_pass", [True, False])
+def test_shj_heavy_queue_overflow(one_pass):
+    """One-pass SHJ hands heavy S tuples to a 256-entry queue that every workgroup
+    helps with; here 400 S tuples hit one heavy key of an R spanning several 64K-row
+    chunks, so the queue fills and the rest stay with their workgroups' own scans
+    (two-pass SHJ: all of them block-local).  Every pair against the oracle."""
+    n_r, n_s = 150001, 200003
+    rng = np.random.default_rng(29)
+    rk = rng.permutation(n_r).astype(np.int64) + 1
+    rk[rng.choice(n_r, 15000, replace=False)] = 77
+    sk = rng.integers(1, 2 * n_r, size=n_s)
+    sk[rng.choice(n_s, 400, replace=False)] = 77
+    rr = rng.permutation(n_r).astype(np.int32)
+    sr = rng.permutation(n_s).astype(np.int32)
+    check_small(hj.params("shj", one_pass=one_pass), rk.astype(np.int32), rr, sk.astype(np.int32), sr)
+
+
 def offset_view(a, off):
     """Device copy of `a` that starts `off` int32 elements into a larger buffer
     (input columns at every 4-byte alignment inside a 16-byte line)."""
