@@ -3,19 +3,22 @@
 //
 // Work item = (partition pair i, chunk of up to kJoinChunk S tuples of S_i),
 // probed kJoinSub tuples at a time.  One workgroup per item:
-//  * |R_i| <= lds_cap: R_i becomes a bucketed table in LDS.  The paper's
-//    bucket header + key list + rid list (Section 3.1) is laid out without
-//    pointers: bucket counts (LDS atomics, the latch of Section 3.3), an
-//    in-LDS exclusive scan, then R_i's keys (and rids) placed bucket by bucket,
-//    so bucket b is the contiguous run [end[b-1], end[b]).  Probing walks that
-//    run (p3) and compares keys (p4).
+//  * |R_i| <= lds_cap: R_i becomes a chained table in LDS.  The paper's
+//    bucket header + key list + rid list (Section 3.1) is laid out without an
+//    allocator: one head word per bucket and one 64-bit record (key, link)
+//    per R tuple at its own row; a tuple is pushed on its bucket's chain with
+//    one LDS exchange (the latch of Section 3.3).  Probing walks the chain
+//    (p3) and compares keys (p4); rids are read from HBM for matches only.
 //  * |R_i| > lds_cap (few, large partitions: low radix bits, duplicate-heavy
 //    R): the pair is joined through a partition-local open-addressing table
 //    in HBM (2 |R_i| slots at twice R_i's offset, plus per-key row chains),
-//    built by separate clear/build launches with 64-bit compare-and-swap.
+//    built by separate clear/build launches (compare-and-swap for a new key,
+//    exchange pushes for duplicates); S tuples on very long chains are
+//    counted and written by the whole workgroup (hj_heavy.h).
 // Output: count pass -> per-wave counts -> scan -> write pass, which re-runs
-// the same item and stores its pairs at the scanned offset (Section 3.3's
-// dynamic output allocation replaced by counting).
+// the same item and stores its pairs at the scanned offset, or one pass that
+// reserves each round's pairs on a running total (Section 3.3's dynamic
+// output allocation replaced by counting or by block reservation).
 #include "hj_device.h"
 #include "hj_heavy.h"
 #include "hj_internal.h"

@@ -10,11 +10,14 @@
 //     duplicates cost one push each instead of lengthening probe sequences.
 // build  b1: slot = mix(key); b2/b3: probe to the key's slot or claim an empty
 //        one with a 64-bit compare-and-swap (the latch of Section 3.3 becomes
-//        one HBM atomic per tuple); b4: push the row onto the key's chain.
+//        one HBM atomic per new key); b4: push the row onto the key's chain
+//        (exchange pushes, joined per wave and per workgroup; WavePush).
 // probe  p1-p3: probe to the key's slot or the first empty slot; p4: every
-//        row of the chain is one output pair.
-// Output is materialised in two passes (count -> scan -> write), so nothing is
-// allocated on the device and the result lands contiguously.
+//        row of the chain is one output pair.  Tuples on very long chains are
+//        handled by whole workgroups (below, and hj_heavy.h).
+// Output is materialised in two passes (count -> scan -> write) or in one
+// (block reservation on a running total); nothing is allocated on the device
+// and the result lands contiguously.
 #include "hj_device.h"
 #include "hj_heavy.h"
 #include "hj_internal.h"
@@ -175,8 +178,8 @@ __device__ __forceinline__ void hand_off(HeavyQueue* Q, HeavySet* hs) {
 
 // A one-pass probe hands a tuple to the queue once its chain is longer than
 // this: a lane walking further would hold its workgroup past the others
-// (~240 ns per step), while a queued tuple costs one scan of R shared by the
-// workgroups that are still running.
+// (every step a dependent load), while a queued tuple costs one scan of R
+// shared by the workgroups that are still running.
 constexpr uint32_t kQueueWalk = 1024;
 
 // Claims the next chunk of a phase for the block (thread 0 takes it, LDS
