@@ -128,52 +128,47 @@ __device__ __forceinline__ void heavy_counts(const int32_t* __restrict__ rk, Len
     __syncthreads();
 }
 
-// Writes the matches of every registered tuple from its slot hs->pos[e] on,
-// in R's row order: one scan of R per distinct key, kV (<= 32) keys per
-// thread per step held as hit bits; after one barrier per step every hit is
-// ranked by (element, wave, lane) from per-wave counts in LDS and a ballot,
-// so consecutive lanes write consecutive slots.  Slots at or past `capacity`
-// are not written.  All threads of the block call it, after the positions
-// are set.
+// Writes the matches of every registered tuple into its slots hs->pos[e] ..
+// hs->pos[e] + cnt - 1, in no particular order: one scan of R per distinct
+// key, kV (<= 32) keys per thread per step; each wave takes slots for its hits
+// of an element with one LDS atomic on the key's fill counter (no barrier in
+// the scan), and consecutive hit lanes write consecutive slots.  Slots at or
+// past `capacity` are not written.  All threads of the block call it, after
+// the positions are set.
 template <uint32_t kBlock, uint32_t kV, typename Len>
 __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
                                              Len r_len, HeavySet* hs, uint64_t capacity,
                                              int32_t* __restrict__ out_r, int32_t* __restrict__ out_s) {
-    constexpr uint32_t kWaves = kBlock / kWave;
     constexpr Len kStep = (Len)kV * kBlock;
-    static_assert(kV <= 32 && kV * kWaves <= sizeof(hs->wsum) / sizeof(uint32_t), "step too large");
+    static_assert(kV <= 32 && kMaxHeavy <= sizeof(hs->wsum) / sizeof(uint32_t), "fill counters fit wsum");
+    uint32_t* fill = hs->wsum;  // per representative entry
     __syncthreads();  // positions published
     const uint32_t ne = min(hs->n, kMaxHeavy);
-    const uint32_t w = threadIdx.x / kWave;
+    if (threadIdx.x < ne) fill[threadIdx.x] = 0;
+    __syncthreads();
     for (uint32_t e = 0; e < ne; ++e) {
         if (hs->rep[e] != e) continue;
         const int32_t k = hs->key[e];
-        Len done = 0;  // matches written before this step
         for (Len j0 = 0; j0 < r_len; j0 += kStep) {
-            // element u of the thread: row j0 + u * kBlock + threadIdx.x
+            // element u of the thread: row j0 + u * kBlock + threadIdx.x; rows
+            // past the end read the last row (all loads issue together) and
+            // do not count
+            int32_t v[kV];
+#pragma unroll
+            for (uint32_t u = 0; u < kV; ++u) v[u] = rk[min(j0 + (Len)u * kBlock + threadIdx.x, r_len - 1)];
             uint32_t bits = 0;
 #pragma unroll
+            for (uint32_t u = 0; u < kV; ++u)
+                bits |= (j0 + (Len)u * kBlock + threadIdx.x < r_len && v[u] == k) ? 1u << u : 0u;
             for (uint32_t u = 0; u < kV; ++u) {
-                const Len j = j0 + (Len)u * kBlock + threadIdx.x;
-                bits |= (j < r_len && rk[j] == k) ? 1u << u : 0u;
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kV; ++u) {
-                const uint32_t n = (uint32_t)__popcll(__ballot((bits >> u) & 1u));
-                if (lane_id() == 0) hs->wsum[u * kWaves + w] = n;
-            }
-            __syncthreads();
-            Len base = done;
-            for (uint32_t u = 0; u < kV; ++u) {
-                uint32_t before = 0, all = 0;
-                for (uint32_t i = 0; i < kWaves; ++i) {
-                    const uint32_t t = hs->wsum[u * kWaves + i];
-                    before += i < w ? t : 0u;
-                    all += t;
-                }
                 const uint64_t m = __ballot((bits >> u) & 1u);
+                if (m == 0) continue;  // uniform over the wave
+                const int lead = __ffsll((unsigned long long)m) - 1;
+                uint32_t base = 0;
+                if ((int)lane_id() == lead) base = atomicAdd(&fill[e], (uint32_t)__popcll(m));
+                base = __shfl(base, lead);
                 if ((bits >> u) & 1u) {
-                    const Len rank = base + before + (uint32_t)__popcll(m & lanemask_lt());
+                    const uint32_t rank = base + (uint32_t)__popcll(m & lanemask_lt());
                     const int32_t rid = rr[j0 + (Len)u * kBlock + threadIdx.x];
                     for (uint32_t e2 = e; e2 < ne; ++e2) {
                         if (hs->rep[e2] != e) continue;
@@ -184,10 +179,7 @@ __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, con
                         }
                     }
                 }
-                base += all;
             }
-            done = base;
-            __syncthreads();  // wsum reused by the next step
         }
     }
 }

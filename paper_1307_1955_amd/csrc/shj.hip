@@ -235,13 +235,16 @@ __device__ __forceinline__ void help_heavy(HeavyQueue* Q, const int32_t* __restr
             if (c >= nchunks) break;
             const uint64_t lo = (uint64_t)c * kHelpChunk, hi = min(lo + kHelpChunk, n_r);
             for (uint64_t j0 = lo; j0 < hi; j0 += (uint64_t)kV * kBlock) {
-                // element u of the thread: row j0 + u * kBlock + threadIdx.x
+                // element u of the thread: row j0 + u * kBlock + threadIdx.x; rows
+                // past the chunk read its last row (all loads issue together) and
+                // do not count
+                int32_t v[kV];
+#pragma unroll
+                for (uint32_t u = 0; u < kV; ++u) v[u] = rk[min(j0 + (uint64_t)u * kBlock + threadIdx.x, hi - 1)];
                 uint32_t bits = 0;
 #pragma unroll
-                for (uint32_t u = 0; u < kV; ++u) {
-                    const uint64_t j = j0 + (uint64_t)u * kBlock + threadIdx.x;
-                    bits |= (j < hi && rk[j] == k) ? 1u << u : 0u;
-                }
+                for (uint32_t u = 0; u < kV; ++u)
+                    bits |= (j0 + (uint64_t)u * kBlock + threadIdx.x < hi && v[u] == k) ? 1u << u : 0u;
 #pragma unroll
                 for (uint32_t u = 0; u < kV; ++u) {
                     const uint32_t nh = (uint32_t)__popcll(__ballot((bits >> u) & 1u));
