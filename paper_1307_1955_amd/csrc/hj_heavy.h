@@ -134,8 +134,9 @@ __device__ __forceinline__ void heavy_counts(const int32_t* __restrict__ rk, Len
 // of an element with one LDS atomic on the key's fill counter (no barrier in
 // the scan), and consecutive hit lanes write consecutive slots.  Slots at or
 // past `capacity` are not written.  All threads of the block call it, after
-// the positions are set.
-template <uint32_t kBlock, uint32_t kV, typename Len>
+// the positions are set.  kRids: the step's rids are loaded with its keys
+// (more registers, no dependent load per hit).
+template <uint32_t kBlock, uint32_t kV, bool kRids = false, typename Len>
 __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
                                              Len r_len, HeavySet* hs, uint64_t capacity,
                                              int32_t* __restrict__ out_r, int32_t* __restrict__ out_s) {
@@ -153,9 +154,13 @@ __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, con
             // element u of the thread: row j0 + u * kBlock + threadIdx.x; rows
             // past the end read the last row (all loads issue together) and
             // do not count
-            int32_t v[kV];
+            int32_t v[kV], rid[kRids ? kV : 1];
 #pragma unroll
-            for (uint32_t u = 0; u < kV; ++u) v[u] = rk[min(j0 + (Len)u * kBlock + threadIdx.x, r_len - 1)];
+            for (uint32_t u = 0; u < kV; ++u) {
+                const Len j = min(j0 + (Len)u * kBlock + threadIdx.x, r_len - 1);
+                v[u] = rk[j];
+                if (kRids) rid[u] = rr[j];
+            }
             uint32_t bits = 0;
 #pragma unroll
             for (uint32_t u = 0; u < kV; ++u)
@@ -169,12 +174,12 @@ __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, con
                 base = __shfl(base, lead);
                 if ((bits >> u) & 1u) {
                     const uint32_t rank = base + (uint32_t)__popcll(m & lanemask_lt());
-                    const int32_t rid = rr[j0 + (Len)u * kBlock + threadIdx.x];
+                    const int32_t r = kRids ? rid[kRids ? u : 0] : rr[j0 + (Len)u * kBlock + threadIdx.x];
                     for (uint32_t e2 = e; e2 < ne; ++e2) {
                         if (hs->rep[e2] != e) continue;
                         const uint64_t at = hs->pos[e2] + rank;
                         if (at < capacity) {
-                            out_r[at] = rid;
+                            out_r[at] = r;
                             out_s[at] = hs->srid[e2];
                         }
                     }

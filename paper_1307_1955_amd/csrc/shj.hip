@@ -353,7 +353,7 @@ __global__ void __launch_bounds__(kShjBlock) __attribute__((amdgpu_waves_per_eu(
             }
         }
     }
-    heavy_writes<kShjBlock, kHeavyV>(r_key, r_rid, n_r, &hs, capacity, out_r, out_s);
+    heavy_writes<kShjBlock, kHeavyV, true>(r_key, r_rid, n_r, &hs, capacity, out_r, out_s);
     if (kOnePass) help_heavy<kShjBlock>(heavy, r_key, r_rid, n_r, total, capacity, out_r, out_s, hs.wsum);
 }
 
