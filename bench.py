@@ -39,10 +39,10 @@ def parse():
                     help="headline PHJ with the two-pass output (count, scan, write) instead of one-pass")
     ap.add_argument("--no-shj", action="store_true", help="skip the SHJ line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sweep", action="store_true", help="also time every radix configuration")
-    ap.add_argument("--sweeps", action="store_true",
-                    help="also time a build-size sweep (|R| 2^16..2^24 against |S| = 2^24, 50%% match) and a "
-                         "selectivity sweep (12.5/50/100%% of S matching, 16M x 16M)")
+    ap.add_argument("--no-sweeps", action="store_true",
+                    help="skip the radix sweep of the 16M x 16M workload (6-14 bits over one or two passes) and the "
+                         "build-size (|R| 2^16..2^24 against |S| = 2^24), selectivity (12.5/50/100%% of S "
+                         "matching) and skew-set sweeps that the default run times")
     ap.add_argument("--no-c3", action="store_true", help="skip the Zipf-skewed 16M x 64M workload and the skewed-R sets")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the 16M x 16M PHJ and SHJ lines (no build/probe, no C3), e.g. under a profiler")
@@ -111,7 +111,10 @@ def summarize(acc, reps, n_r, n_s, m):
 
 
 def bench_batched(args, torch, hj, wl, params, table) -> dict:
-    """4096 joins of log-uniform sizes: one graph-captured batch vs plain per-join calls."""
+    """4096 joins of log-uniform sizes: one graph-captured batch vs plain per-join calls.
+    After the timed runs every job is checked on the device (count = closed form,
+    every pair joins equal keys, no S row twice)."""
+    from paper_1307_1955_amd import workloads
     plan = hj.BatchPlan(wl.jobs, wl.d_counts, params=params)
     ws = plan.workspace()
     expected = torch.tensor(wl.expected, dtype=torch.int64, device="cuda")
@@ -135,6 +138,8 @@ def bench_batched(args, torch, hj, wl, params, table) -> dict:
         for j, (job, q) in enumerate(zip(wl.jobs, params)):
             hj.hj_join(q, *job, ws_one, one_counts[j:j + 1])
 
+    print("bench: checking every batched job on the device", file=sys.stderr, flush=True)
+    bad = workloads.verify_device(wl)
     ms_plain = time_steps(plain, 1, 1, torch)
     same = bool(torch.equal(one_counts, expected))
     del d_one
@@ -146,6 +151,7 @@ def bench_batched(args, torch, hj, wl, params, table) -> dict:
         "params": "tuning table" if table else "cost model",
         "direct_jobs": plan.direct_jobs, "graph": True, "first_run_s_incl_capture": round(first_s, 3),
         "counts_match_closed_form": ok,
+        "pairs_verified_on_device": not bad, "failed_jobs": bad[:8],
         "plain_per_join": {"value": len(wl.jobs) / (ms_plain * 1e-3), "ms": ms_plain,
                            "counts_match_closed_form": same},
         "speedup_vs_plain": ms_plain / ms,
@@ -164,19 +170,31 @@ def percentile(v, q):
 def bench_served(args, torch, hj, wl, params, qps_levels) -> dict:
     """Open-loop Poisson arrivals of requests drawn from the batched workload,
     served with continuous batching under a 64 GiB footprint cap, against the
-    same trace through plain per-join calls run serially."""
+    same trace through plain per-join calls run serially.
+
+    Request i joins job i mod 4096 into that job's output buffer; every request
+    has a count slot of its own.  Checked after each level: every request's
+    status and count, that no two requests of one job were on the device at
+    the same time (so none could overwrite another's pairs), and every job's
+    pairs (those of its last request) on the device."""
     import ctypes
 
-    from paper_1307_1955_amd import gen
+    from paper_1307_1955_amd import gen, workloads
     njobs = len(wl.jobs)
     n = args.serve_requests
     warm = min(args.serve_warmup, n // 2)
     ws_max = max(hj.hj_workspace_bytes(q, sp.n_r, sp.n_s) for q, sp in zip(params, wl.specs))
     slots = args.serve_slots
     pool = torch.empty(slots * (ws_max + (64 << 20)), dtype=torch.uint8, device="cuda")
-    jobs = [hj.make_job(*wl.jobs[j], wl.d_counts.data_ptr() + 8 * j) for j in range(njobs)]
+    req_counts = torch.zeros(n, dtype=torch.int64, device="cuda")
+    plain_counts = torch.zeros(n, dtype=torch.int64, device="cuda")
+    base = req_counts.data_ptr()
+    jobs = [hj.make_job(*wl.jobs[i % njobs], base + 8 * i) for i in range(n)]
     fps = [8 * (sp.n_r + sp.n_s) + 8 * e + hj.hj_workspace_bytes(q, sp.n_r, sp.n_s)
            for sp, e, q in zip(wl.specs, wl.expected, params)]
+    want = torch.tensor([wl.expected[i % njobs] for i in range(n)], dtype=torch.int64, device="cuda")
+    asked = [j for j in range(njobs) if j < n]  # jobs with at least one request
+    last = [max(range(j, n, njobs)) for j in asked]  # each one's last request
     lib = hj.load()
     out = {"requests": n, "warmup_requests": warm, "cap_bytes": 64 << 30, "slots": slots, "levels": []}
     for qps in qps_levels:
@@ -185,6 +203,8 @@ def bench_served(args, torch, hj, wl, params, qps_levels) -> dict:
         ticket = ctypes.c_uint64(0)
         lag = []
         submit_t = [0.0] * n
+        req_counts.fill_(-1)
+        torch.cuda.synchronize()
         print("bench: serving %d requests at %.0f/s" % (n, qps), file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         for i in range(n):
@@ -193,7 +213,7 @@ def bench_served(args, torch, hj, wl, params, qps_levels) -> dict:
                 pass
             now = time.perf_counter()
             j = i % njobs
-            st = lib.hj_server_submit(sv._h, ctypes.byref(jobs[j]), ctypes.byref(params[j]), fps[j],
+            st = lib.hj_server_submit(sv._h, ctypes.byref(jobs[i]), ctypes.byref(params[j]), fps[j],
                                       ctypes.byref(ticket))
             if st != 0:
                 raise RuntimeError("submit failed: %s" % lib.hj_last_error().decode())
@@ -206,37 +226,50 @@ def bench_served(args, torch, hj, wl, params, qps_levels) -> dict:
         by_ticket = {t: (s_, lat, q_) for t, s_, lat, q_ in done}
         # tickets are issued 1..n in submission order
         lat = [by_ticket[i + 1][1] for i in range(warm, n)]
-        ends = [submit_t[i] + by_ticket[i + 1][1] for i in range(warm, n)]
-        span = max(ends) - arr[warm]
-        ok = all(by_ticket[i + 1][0] == 0 for i in range(n))
+        ends = [submit_t[i] + by_ticket[i + 1][1] for i in range(n)]
+        span = max(ends[warm:]) - arr[warm]
+        statuses_ok = all(by_ticket[i + 1][0] == 0 for i in range(n))
+        counts_ok = bool(torch.equal(req_counts, want))
+        # a request's end (submission + latency, the server's clock starts a few
+        # microseconds later) 1 ms before the next request of its job is submitted
+        overlaps = sum(1 for i in range(njobs, n) if ends[i - njobs] + 1e-3 > submit_t[i])
+        print("bench: checking every job's pairs on the device", file=sys.stderr, flush=True)
+        last_counts = torch.full((njobs,), -1, dtype=torch.int64, device="cuda")
+        last_counts[torch.tensor(asked, device="cuda")] = req_counts[torch.tensor(last, device="cuda")]
+        bad = workloads.verify_device(wl, counts=last_counts, jobs=asked) if overlaps == 0 else [(-1, "overlap")]
         # the same trace through plain per-join calls, one at a time
         print("bench: plain per-join serial path at %.0f/s" % qps, file=sys.stderr, flush=True)
         ws_one = pool[: ws_max]
         lat_plain = []
         h = ctypes.c_uint64(0)
+        plain_counts.fill_(-1)
         t0 = time.perf_counter()
         for i in range(n):
             target = t0 + arr[i]
             while time.perf_counter() < target:
                 pass
             j = i % njobs
-            st = lib.hj_join_sync(ctypes.byref(params[j]), ctypes.byref(jobs[j].R), ctypes.byref(jobs[j].S),
-                                  ctypes.byref(jobs[j].out), ws_one.data_ptr(), ws_max, jobs[j].d_count,
+            st = lib.hj_join_sync(ctypes.byref(params[j]), ctypes.byref(jobs[i].R), ctypes.byref(jobs[i].S),
+                                  ctypes.byref(jobs[i].out), ws_one.data_ptr(), ws_max, plain_counts.data_ptr() + 8 * i,
                                   ctypes.byref(h), torch.cuda.current_stream().cuda_stream)
             if st != 0:
                 raise RuntimeError("plain join failed: %s" % lib.hj_last_error().decode())
             if i >= warm:
                 lat_plain.append(time.perf_counter() - target)
         span_plain = time.perf_counter() - (t0 + arr[warm])
-        ok = ok and bool(torch.equal(wl.d_counts, torch.tensor(wl.expected, dtype=torch.int64, device="cuda")))
+        plain_ok = bool(torch.equal(plain_counts, want))
         out["levels"].append({
             "offered_qps": qps,
             "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
             "throughput_joins_per_s": (n - warm) / span,
             "batches": stats["batches"], "rejected": stats["rejected"],
-            "max_submit_lag_ms": max(lag) * 1e3, "all_ok": ok,
+            "max_submit_lag_ms": max(lag) * 1e3,
+            "all_ok": statuses_ok and counts_ok and overlaps == 0 and not bad,
+            "checks": {"statuses_ok": statuses_ok, "every_request_count_ok": counts_ok,
+                       "same_job_overlaps": overlaps, "pairs_verified_on_device": not bad,
+                       "failed_jobs": bad[:8]},
             "plain_serial": {"p50_ms": percentile(lat_plain, 50) * 1e3, "p99_ms": percentile(lat_plain, 99) * 1e3,
-                             "throughput_joins_per_s": (n - warm) / span_plain},
+                             "throughput_joins_per_s": (n - warm) / span_plain, "counts_ok": plain_ok},
         })
         print("bench: served %s" % out["levels"][-1], file=sys.stderr, flush=True)
     del pool
@@ -340,6 +373,27 @@ def bench_build_probe(hj, torch, p, t, out_r, out_s, d_count, steps, warmup) -> 
             "matches": int(d_count.item())}
 
 
+def device_count(torch, rk, sk) -> int:
+    """Pairs the join must produce (sum over S of the R rows with its key), with
+    plain PyTorch on the device; generated keys are non-negative."""
+    hi = int(max(int(rk.max()), int(sk.max()))) + 1
+    cnt = torch.bincount(rk.long(), minlength=hi)
+    return int(cnt[sk.long()].sum())
+
+
+def timed_join(hj, torch, q, t, o_r, o_s, d, steps, warmup, want, dev):
+    """Mean time of one join with parameters q; raises if its count is not `want`."""
+    n_r, n_s = t[0].numel(), t[2].numel()
+    ws = hj.workspace(q, n_r, n_s, dev)
+    ms = time_steps(lambda: hj.hj_join(q, *t, o_r, o_s, ws, d), steps, warmup, torch)
+    m = int(d.item())
+    hj.hj_workspace_status(ws)
+    if m != want:
+        raise AssertionError("%r: %d pairs, the closed form says %d" % (q, m, want))
+    del ws
+    return {"ms": round(ms, 4), "tuples_per_s": (n_r + n_s) / (ms * 1e-3), "matches": m, "count_ok": True}
+
+
 def bench_c3(hj, torch, dev, steps, warmup) -> dict:
     """R = permutation of 1..2^24, S = 2^26 Zipf draws over R's keys (every S tuple
     matches once; at theta 1 the most frequent key holds ~5.8% of S)."""
@@ -347,26 +401,52 @@ def bench_c3(hj, torch, dev, steps, warmup) -> dict:
     out = {}
     for theta in (0.5, 1.0):
         t = dgen.config_c3(theta=theta, device=dev)
-        n_r, n_s = t[0].numel(), t[2].numel()
+        n_s = t[2].numel()
         o_r = torch.empty(n_s, dtype=torch.int32, device=dev)
         o_s = torch.empty(n_s, dtype=torch.int32, device=dev)
         d = torch.zeros(1, dtype=torch.int64, device=dev)
         row = {}
         for name, q in (("phj", hj.params("phj", 2, (6, 6), one_pass=True)), ("shj", hj.params("shj", one_pass=True))):
-            ws = hj.workspace(q, n_r, n_s, dev)
-            ms = time_steps(lambda: hj.hj_join(q, *t, o_r, o_s, ws, d), steps, warmup, torch)
-            row[name] = {"ms": round(ms, 4), "tuples_per_s": (n_r + n_s) / (ms * 1e-3), "matches": int(d.item())}
-            del ws
+            row[name] = timed_join(hj, torch, q, t, o_r, o_s, d, steps, warmup, n_s, dev)
         out["theta_%g" % theta] = row
         del t, o_r, o_s
         torch.cuda.empty_cache()
     return out
 
 
+def bench_radix_sweep(hj, torch, t, out_r, out_s, d_count, want, dev) -> dict:
+    """The 16M x 16M workload over radix bits 6-14 in one pass (up to 13, the
+    per-pass limit) and in two passes (the split of HJ_AUTO), each with one- and
+    two-pass output: time per join, every count against the closed form, and
+    the best GB/s each phase reached over the sweep (per-kernel HIP events)."""
+    n_r, n_s = t[0].numel(), t[2].numel()
+    configs = [(1, (b,)) for b in range(6, 14)] + [(2, ((b + 1) // 2, b // 2)) for b in range(6, 15)]
+    rows, best = [], {}
+    for passes, bb in configs:
+        for one in (True, False):
+            q = hj.params("phj", passes, bb, one_pass=one)
+            row = {"passes": passes, "bits": list(bb), "one_pass": one,
+                   "tile": hj.hj_resolve_params(q, n_r, n_s).tile,
+                   **timed_join(hj, torch, q, t, out_r, out_s, d_count, 5, 2, want, dev)}
+            ws = hj.workspace(q, n_r, n_s, dev)
+            for name, r in summarize(kernel_times(hj, q, t, out_r, out_s, ws, d_count, 1), 1, n_r, n_s,
+                                     want).items():
+                if "gbs" in r and r["gbs"] > best.get(name, {}).get("gbs", 0.0):
+                    best[name] = {"gbs": r["gbs"], "frac_of_peak": round(r["gbs"] / HBM_PEAK_GBS, 4),
+                                  "passes": passes, "bits": list(bb), "one_pass": one}
+            del ws
+            rows.append(row)
+            print("bench: radix sweep %s" % row, file=sys.stderr, flush=True)
+    fastest = min(rows, key=lambda r: r["ms"])
+    return {"configs": rows, "best_per_phase_gbs": best,
+            "fastest": {k: fastest[k] for k in ("passes", "bits", "one_pass", "ms", "tuples_per_s")}}
+
+
 def bench_sweeps(hj, torch, dev, steps, warmup) -> dict:
     """Build-size sweep (|R| = 2^16..2^24, |S| = 2^24 uniform over 1..2|R|),
     selectivity sweep (16M x 16M, S uniform over 1..|R|/f for a match fraction f)
-    and the low/high-skew sets (10% / 25% of R on one key) at three build sizes."""
+    and the low/high-skew sets (10% / 25% of R on one key) at three build sizes;
+    every count against the closed form."""
     from paper_1307_1955_amd.gen import device as dgen
     n_s = 1 << 24
     o_r = torch.empty(n_s, dtype=torch.int32, device=dev)
@@ -376,13 +456,11 @@ def bench_sweeps(hj, torch, dev, steps, warmup) -> dict:
     def run(t):
         row = {}
         n_r = t[0].numel()
+        want = device_count(torch, t[0], t[2])
         for name, q in (("phj_auto", hj.params("auto", one_pass=True)), ("shj", hj.params("shj", one_pass=True))):
-            ws = hj.workspace(q, n_r, n_s, dev)
-            ms = time_steps(lambda: hj.hj_join(q, *t, o_r, o_s, ws, d), steps, warmup, torch)
-            row[name] = {"ms": round(ms, 4), "tuples_per_s": (n_r + n_s) / (ms * 1e-3), "matches": int(d.item())}
+            row[name] = timed_join(hj, torch, q, t, o_r, o_s, d, steps, warmup, want, dev)
             if name == "phj_auto":
                 row[name]["params"] = repr(hj.hj_resolve_params(q, n_r, n_s))
-            del ws
         return row
 
     build = []
@@ -401,12 +479,13 @@ def bench_sweeps(hj, torch, dev, steps, warmup) -> dict:
         del t
     del o_r, o_s
     torch.cuda.empty_cache()
-    return {"build_size": build, "selectivity": sel, "skew": bench_skew(hj, torch, dev, steps, warmup, (16, 20, 24))}
+    return {"build_size": build, "selectivity": sel, "skew": bench_skew(hj, torch, dev, steps, warmup, (16, 20))}
 
 
 def bench_skew(hj, torch, dev, steps, warmup, log2_sizes=(24,)) -> list:
     """The skewed sets of Section 5.1: |S| = 2^24 uniform over 1..2|R|, a fraction
-    s = 10% (low) or 25% (high) of R's rows on one key, PHJ (`HJ_AUTO`) and SHJ."""
+    s = 10% (low) or 25% (high) of R's rows on one key, PHJ (`HJ_AUTO`) and SHJ;
+    counts against the closed form."""
     from paper_1307_1955_amd.gen import device as dgen
     n_s = 1 << 24
     o_r = torch.empty(n_s, dtype=torch.int32, device=dev)
@@ -417,12 +496,10 @@ def bench_skew(hj, torch, dev, steps, warmup, log2_sizes=(24,)) -> list:
         for lg in log2_sizes:
             n_r = 1 << lg
             t = dgen.skewed_r(9, n_r, n_s, 2 * n_r, frac, dev)
+            want = device_count(torch, t[0], t[2])
             row = {"skew": frac, "n_r": n_r, "n_s": n_s}
             for name, q in (("phj_auto", hj.params("auto", one_pass=True)), ("shj", hj.params("shj", one_pass=True))):
-                ws = hj.workspace(q, n_r, n_s, dev)
-                ms = time_steps(lambda: hj.hj_join(q, *t, o_r, o_s, ws, d), steps, warmup, torch)
-                row[name] = {"ms": round(ms, 4), "tuples_per_s": (n_r + n_s) / (ms * 1e-3), "matches": int(d.item())}
-                del ws
+                row[name] = timed_join(hj, torch, q, t, o_r, o_s, d, steps, warmup, want, dev)
             rows.append(row)
             print("bench: skew set %s" % row, file=sys.stderr, flush=True)
             del t
@@ -433,7 +510,13 @@ def bench_skew(hj, torch, dev, steps, warmup, log2_sizes=(24,)) -> list:
 
 PROFILE = os.path.join(ROOT, "profiles", "phj_16m_x_16m_hbm.json")
 KERNEL_OF_PHASE = {"part_hist": "k_part_hist", "part_scatter": "k_part_scatter", "join_count": "k_join_count",
-                   "join_write": "k_join_write<false", "join_write_1pass": "k_join_write<true"}
+                   "join_write": "k_join_write<false", "join_write_1pass": "k_join_write<true",
+                   "shj_build": "k_shj_build", "shj_count": "k_shj_count", "shj_write": "k_shj_write<false",
+                   "shj_write_1pass": "k_shj_write<true"}
+# What the rocprofv3 counters FETCH_SIZE and WRITE_SIZE count: bytes between the
+# L2 caches and the memory fabric, so lines served by the 256 MB Infinity Cache
+# (MALL) count too; HBM itself may have moved fewer.
+TRAFFIC_KIND = "beyond-L2 bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; includes Infinity Cache hits)"
 
 
 def counter_traffic(phase: str):
@@ -493,6 +576,9 @@ def main():
                        one_pass)
     phases = head["kernels"]
     m = head["matches"]
+    want = int((t[2] <= n).sum())  # R keys are 1..|R|: every S key <= |R| matches once
+    if m != want:
+        raise AssertionError("PHJ produced %d pairs, the closed form says %d" % (m, want))
     # dominant kernel: most time per join among kernels with an algorithmic byte count
     dom = max((k for k in phases if "gbs" in phases[k]), key=lambda k: phases[k]["ms_per_join"])
     dom_bytes = algorithmic_bytes(dom, n_r, n_s, m)
@@ -516,12 +602,12 @@ def main():
                         "S keys uniform over 1..2|R| (~50%% match)" % n,
             "algo": "phj", "passes": args.passes, "bits": list(bits), "hash": args.hash,
             "tile": rp.tile, "lds_cap": rp.lds_cap, "output": "one-pass (block reservation)" if one_pass else
-            "two-pass (count, scan, write)", "matches": m,
+            "two-pass (count, scan, write)", "matches": m, "count_matches_closed_form": True,
         },
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom),
-            "bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms,
+            "traffic_kind": TRAFFIC_KIND, "bytes_per_launch": dom_bytes, "avg_launch_ms": dom_ms,
         },
         "path_gbs": head["path_gbs"],
         "path_frac": head["path_frac"],
@@ -543,28 +629,25 @@ def main():
             ms_s = time_steps(lambda: hj.hj_join(ps, *t, out_r, out_s, ws_s, d_count), args.steps, args.warmup,
                               torch)
             m_s = int(d_count.item())
+            if m_s != want:
+                raise AssertionError("SHJ produced %d pairs, the closed form says %d" % (m_s, want))
             acc_s = kernel_times(hj, ps, t, out_r, out_s, ws_s, d_count, 5)
+            ks = summarize(acc_s, 5, n_r, n_s, m_s)
+            for name, row in ks.items():
+                # one table lookup chain per R tuple inserted or S tuple probed
+                units = {"shj_build": n_r, "shj_count": n_s, "shj_write": n_s, "shj_write_1pass": n_s}.get(name)
+                if units:
+                    row["random_accesses_per_s"] = units / (row["avg_launch_ms"] * 1e-3)
+                    tb = counter_traffic(name)
+                    row["counter_bytes_per_tuple"] = None if tb is None else round(tb / units, 1)
             result["shj" if shj_one else "shj_two_pass_output"] = {
                 "value": (n_r + n_s) / (ms_s * 1e-3), "unit": "tuples/s", "ms_per_step": ms_s, "matches": m_s,
-                "kernels": summarize(acc_s, 5, n_r, n_s, m_s)}
+                "count_matches_closed_form": True, "kernels": ks,
+                "counter_bytes_kind": TRAFFIC_KIND.replace(" per launch", "")}
             del ws_s
-    if args.sweep:
-        sweep = []
-        configs = [(1, (b,)) for b in range(8, 15)] + [(2, (a, b)) for a in range(4, 9) for b in range(4, 9)]
-        for one in (False, True):
-            for passes, bb in configs:
-                if sum(bb) < 8 or sum(bb) > 14 or max(bb) > 13:
-                    continue
-                for tile in (0, 4096) if passes == 1 else (0,):
-                    q = hj.params("phj", passes, bb, hash=args.hash, tile=tile, one_pass=one)
-                    wq = hj.workspace(q, n_r, n_s, dev)
-                    msq = time_steps(lambda: hj.hj_join(q, *t, out_r, out_s, wq, d_count), 5, 2, torch)
-                    sweep.append({"passes": passes, "bits": list(bb), "tile": hj.hj_resolve_params(q, n_r, n_s).tile,
-                                  "one_pass": one,
-                                  "ms": round(msq, 4), "tuples_per_s": (n_r + n_s) / (msq * 1e-3)})
-                    print("bench: sweep %s" % sweep[-1], file=sys.stderr, flush=True)
-                    del wq
-        result["sweep"] = sweep
+    if not args.no_sweeps and not args.no_extras:
+        print("bench: radix sweep of the 16M x 16M workload", file=sys.stderr, flush=True)
+        result["radix_sweep"] = bench_radix_sweep(hj, torch, t, out_r, out_s, d_count, m, dev)
     del out_r, out_s, t
     torch.cuda.empty_cache()
     if not args.no_c3 and not args.no_extras:
@@ -572,7 +655,7 @@ def main():
         result["c3"] = bench_c3(hj, torch, dev, min(args.steps, 10), min(args.warmup, 3))
         print("bench: skewed R (10% / 25% on one key), 16M x 16M", file=sys.stderr, flush=True)
         result["skew"] = bench_skew(hj, torch, dev, min(args.steps, 10), min(args.warmup, 3))
-    if args.sweeps:
+    if not args.no_sweeps and not args.no_extras:
         result["sweeps"] = bench_sweeps(hj, torch, dev, min(args.steps, 10), min(args.warmup, 3))
     if args.batch_jobs:
         from paper_1307_1955_amd import tune, workloads

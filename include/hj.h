@@ -51,7 +51,8 @@ typedef enum hj_status {
     HJ_ERR_INVALID = 1,     /* bad argument (NULL buffer with n > 0, bad bits/passes, n >= 2^31) */
     HJ_ERR_CAPACITY = 2,    /* *_sync only: more pairs than out->capacity; the count is still reported */
     HJ_ERR_WORKSPACE = 3,   /* ws_bytes below hj_workspace_bytes(), or ws NULL */
-    HJ_ERR_DEVICE = 4,      /* a HIP runtime call failed; see hj_last_error() */
+    HJ_ERR_DEVICE = 4,      /* a HIP runtime call failed, or the device reported a failure in the
+                               workspace's error word (hj_workspace_status); see hj_last_error() */
     HJ_ERR_UNSUPPORTED = 5  /* a parameter combination this build does not implement */
 } hj_status;
 
@@ -145,7 +146,9 @@ hj_status hj_join(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj
                   void* ws, size_t ws_bytes, uint64_t* d_count, void* stream);
 
 /* hj_join followed by a synchronisation of `stream` and a copy of the count
-   into *h_count.  Returns HJ_ERR_CAPACITY when *h_count > out->capacity. */
+   into *h_count.  Returns HJ_ERR_DEVICE when the join's device error word is
+   set (see hj_workspace_status), else HJ_ERR_CAPACITY when
+   *h_count > out->capacity. */
 hj_status hj_join_sync(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out,
                        void* ws, size_t ws_bytes, uint64_t* d_count, uint64_t* h_count,
                        void* stream);
@@ -177,8 +180,12 @@ hj_status hj_join_timed(const hj_params* p, const hj_rel* R, const hj_rel* S, co
 typedef struct hj_table {
     hj_params params;      /* as run: HJ_AUTO and the size-dependent choices resolved */
     uint64_t n_r;          /* tuples of R */
-    const int32_t* r_key;  /* R's columns as given to hj_build (SHJ probes read */
-    const int32_t* r_rid;  /*   r_rid; PHJ probes with passes 0 read both) */
+    const int32_t* r_key;  /* R's columns as given to hj_build.  SHJ probes and PHJ */
+    const int32_t* r_rid;  /*   probes with passes 0 read both: the rids of matches,
+                              and the keys when S tuples meet a duplicate-heavy key
+                              (its matches are found by scanning R's key column);
+                              hj_probe rejects a NULL column there.  PHJ probes with
+                              1 or 2 passes read neither. */
     void* ws;              /* the build workspace that holds the table */
     size_t ws_bytes;
 } hj_table;
@@ -313,6 +320,23 @@ hj_status hj_server_stats(hj_server* server, uint64_t* completed, uint64_t* reje
 
 /* Finishes the queued requests, stops the dispatcher and frees the server. */
 void hj_server_destroy(hj_server* server);
+
+/* Device-side failures of an asynchronous call.  Every workspace handed to
+   hj_join, hj_build, hj_probe, hj_batch_run or a server starts with an 8-byte
+   error word that the call's first kernel clears.  The chained (decoupled
+   look-back) scans that place partitions and output wait on their
+   predecessors with a bounded number of polls; a wait that runs out ends its
+   kernel normally and sets a bit there, and the call's output is then not
+   valid.  This call synchronises `stream` and returns HJ_OK when the error
+   word of `ws` (the workspace of the last call on that stream) is clear, else
+   HJ_ERR_DEVICE with the cause in hj_last_error().  hj_join_sync checks it by
+   itself; a server marks the requests of such a batch HJ_ERR_DEVICE.
+   Failure injection for tests of these paths: the environment variable
+   HJ_DEBUG_FAIL_PHASE, read at every call, set to "scan_stall" makes the first
+   tile of every histogram and count scan withhold its status (the waits give
+   up after 64 polls), and set to "launch:<phase>" (e.g. "launch:part_scatter") makes that
+   launch report a launch failure (HJ_ERR_DEVICE from the call). */
+hj_status hj_workspace_status(const void* ws, void* stream);
 
 /* Static description of a status code. */
 const char* hj_status_str(hj_status s);

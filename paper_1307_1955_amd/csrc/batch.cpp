@@ -55,7 +55,7 @@ struct hj_batch_plan {
     uint32_t ndirect = 0, direct_items = 0, direct_cap = 256;
     hj::DirectJob* h_djobs = nullptr;  // pinned staging, ndirect entries
     uint32_t* h_item_job = nullptr;    // pinned staging, direct_items entries
-    size_t djobs_off = 0, item_job_off = 0;
+    size_t err_off = 0, djobs_off = 0, item_job_off = 0;
     // pipelined jobs
     std::vector<LaneJob> lane_jobs[kLanes];
     size_t lane_off[kLanes] = {0};
@@ -108,6 +108,7 @@ hj_status check_job(uint32_t i, const hj_job& j) {
 // Enqueues the whole batch on `stream` (lanes fork from and join back to it).
 hj_status enqueue(hj_batch_plan* b, char* ws, hipStream_t stream) {
     hipError_t e = hipSuccess;
+    uint64_t* err = (uint64_t*)(ws + b->err_off);  // one error word for the whole batch
     hj::DirectJob* d_djobs = (hj::DirectJob*)(ws + b->djobs_off);
     uint32_t* d_item_job = (uint32_t*)(ws + b->item_job_off);
     if (b->ndirect) {
@@ -117,6 +118,10 @@ hj_status enqueue(hj_batch_plan* b, char* ws, hipStream_t stream) {
                                hipMemcpyHostToDevice, stream);
         if (e != hipSuccess) return fail(HJ_ERR_DEVICE, "job table upload failed: %s", hipGetErrorString(e));
     }
+    hj::Recorder main_rec;
+    init_recorder(main_rec, stream, err, false);
+    // cleared before the lanes fork, so no job's report can be lost
+    hj::zero_pair(err, nullptr, main_rec);
     bool any_lane = false;
     for (uint32_t l = 0; l < kLanes; ++l) any_lane |= !b->lane_jobs[l].empty();
     if (any_lane) {
@@ -125,15 +130,13 @@ hj_status enqueue(hj_batch_plan* b, char* ws, hipStream_t stream) {
             if (!b->lane_jobs[l].empty()) e = hipStreamWaitEvent(b->lane_stream[l], b->fork, 0);
         if (e != hipSuccess) return fail(HJ_ERR_DEVICE, "lane fork failed: %s", hipGetErrorString(e));
     }
-    hj::Recorder main_rec;
-    main_rec.stream = stream;
     hj::direct_zero(d_djobs, b->ndirect, main_rec);
     hj::direct_join(d_djobs, d_item_job, b->direct_items, b->direct_cap, main_rec);
     if (main_rec.err != hipSuccess) return fail(HJ_ERR_DEVICE, "launch failed: %s", hipGetErrorString(main_rec.err));
     for (uint32_t l = 0; l < kLanes; ++l) {
         if (b->lane_jobs[l].empty()) continue;
         hj::Recorder rec;
-        rec.stream = b->lane_stream[l];
+        init_recorder(rec, b->lane_stream[l], err, false);
         for (const LaneJob& lj : b->lane_jobs[l]) {
             const hj_job& j = b->jobs[lj.job];
             run_join(lj.plan, j.R, j.S, j.out, ws + b->lane_off[l], j.d_count, rec);
@@ -278,8 +281,10 @@ hj_status create_plan(uint32_t njobs, const hj_job* jobs, const hj_params* param
         b->lane_jobs[best].push_back(lj);
         b->lane_bytes[best] = std::max(b->lane_bytes[best], lj.ws);
     }
-    // workspace: [direct jobs][item map][lane 0]...[lane 3]
+    // workspace: [error word][direct jobs][item map][lane 0]...[lane 15]
     size_t off = 0;
+    b->err_off = off;
+    off += align_up(sizeof(uint64_t));
     b->djobs_off = off;
     off += align_up(sizeof(hj::DirectJob) * std::max<uint32_t>(b->ndirect, 1));
     b->item_job_off = off;

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 
 namespace hj {
@@ -196,8 +197,11 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
     return HJ_OK;
 }
 
+// Every workspace layout starts with the call's error word (kErrLookback;
+// hj_workspace_status reads it), then its own buffers.
 // Workspace layout; with base == nullptr only the size is computed.
 struct PhjWs {
+    uint64_t* err;
     hj::PartSeg* segs1;
     uint32_t* tb1;
     uint32_t* hist1;
@@ -232,6 +236,7 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, v
     Carver c(base);
     const uint64_t n = n_r + n_s;
     w.tiles1 = cdiv(n_r, pl.tile) + cdiv(n_s, pl.tile);
+    w.err = c.take<uint64_t>(1);
     w.segs1 = c.take<hj::PartSeg>(2);
     w.tb1 = c.take<uint32_t>(3);
     w.hist1 = c.take<uint32_t>(w.tiles1 * pl.P1);
@@ -271,6 +276,7 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, v
 
 // SHJ: the table over R (slots and row chains), then the probe's per-wave counts.
 struct ShjTableWs {
+    uint64_t* err;
     uint64_t* table;
     uint32_t* next;
     hj::HotKeys* hot;
@@ -282,6 +288,7 @@ ShjTableWs shj_table_layout(uint64_t n_r, void* base) {
     ShjTableWs w{};
     Carver c(base);
     w.log2_slots = std::max<uint32_t>(1, ceil_log2(2 * std::max<uint64_t>(n_r, 1)));
+    w.err = c.take<uint64_t>(1);
     w.table = c.take<uint64_t>(1ull << w.log2_slots);
     w.next = c.take<uint32_t>(n_r);
     w.hot = c.take<hj::HotKeys>(1);
@@ -290,6 +297,7 @@ ShjTableWs shj_table_layout(uint64_t n_r, void* base) {
 }
 
 struct ShjProbeWs {
+    uint64_t* err;
     hj::HeavyQueue* heavy;  // one-pass: heavy S tuples shared by all workgroups
     uint64_t* wave_cnt;
     uint64_t* st;  // scan state of the per-wave counts
@@ -302,6 +310,7 @@ ShjProbeWs shj_probe_layout(uint64_t n_s, void* base) {
     ShjProbeWs w{};
     Carver c(base);
     w.tiles = cdiv(n_s, hj::kShjTile);
+    w.err = c.take<uint64_t>(1);
     w.heavy = c.take<hj::HeavyQueue>(1);
     w.wave_cnt = c.take<uint64_t>(w.tiles * hj::kShjWavesPerBlock);
     w.nst = hj::scan_state_words(w.tiles * hj::kShjWavesPerBlock);
@@ -316,6 +325,7 @@ size_t shj_bytes(uint64_t n_r, uint64_t n_s) {
 
 // Direct join (PHJ with no partitioning pass): one job descriptor and the item map.
 struct DirectWs {
+    uint64_t* err;
     hj::DirectJob* job;
     uint32_t* item_job;
     uint32_t nitems;
@@ -326,6 +336,7 @@ DirectWs direct_layout(uint64_t n_s, void* base) {
     DirectWs w{};
     Carver c(base);
     w.nitems = (uint32_t)cdiv(n_s, hj::kJoinChunk);
+    w.err = c.take<uint64_t>(1);
     w.job = c.take<hj::DirectJob>(1);
     w.item_job = c.take<uint32_t>(w.nitems);
     w.bytes = c.off;
@@ -423,15 +434,19 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
     const uint32_t n_r = (uint32_t)R.n, n_s = (uint32_t)S.n;
     const bool two = pl.passes == 2;
     const hj::Pass1 p1 = hj::make_pass1(R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, w.segs1, w.tb1,
-                                        w.st1, w.nzero);
+                                        w.st1, w.nzero, rec.err_clear);
     // the join plan rides on the last pass's scatter, the pass-2 setup on the first
+    // The plan's records are written at offsets from its chained scan; its wait
+    // keeps the full bound and no injected stall (every consumer of the other
+    // scans clamps what it reads and writes, the item records have no clamp).
+    const hj::ScanCtl plan_ctl{rec.ctl.err, hj::kMaxStatusPolls, 0};
     hj::SideJob plan{};
     plan.kind = hj::kSidePlan;
     plan.blocks = hj::plan_blocks(pl.P, hj::part_block(pl.tile));
     plan.plan = hj::PlanArgs{two ? w.segs2 : w.segs1, two ? w.tb2 : w.tb1, two ? w.hist2 : w.hist1,
                              two ? 2 * pl.P1 : 2u, two ? pl.b2 : pl.b1, n_r, n_s, pl.B, pl.lds_cap,
                              w.pairs, w.item_begin, w.ovf_begin, w.item_rec, w.ovf_part, zero_total, w.stp,
-                             r_pairs};
+                             r_pairs, plan_ctl};
     hj::SideJob setup2{};
     if (two) {
         setup2.kind = hj::kSideSetup2;
@@ -496,7 +511,10 @@ void run_join(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& ou
 }
 
 void run_build(const Plan& pl, const hj_rel& R, void* ws, hj::Recorder& rec) {
-    if (R.n == 0 || (pl.phj && pl.passes == 0)) return;  // passes 0: the table is R itself
+    if (R.n == 0 || (pl.phj && pl.passes == 0)) {  // passes 0: the table is R itself
+        hj::zero_pair(rec.err_clear, nullptr, rec);
+        return;
+    }
     if (!pl.phj) {
         shj_build_table(R, shj_table_layout(R.n, ws), rec);
         return;
@@ -540,10 +558,36 @@ hj_status table_plan(const hj_table* t, uint64_t n_s, Plan* pl) {
         return fail(HJ_ERR_INVALID, "table parameters are not the ones hj_build filled in");
     if (!t->ws || t->ws_bytes < table_bytes_for(*pl, t->n_r))
         return fail(HJ_ERR_INVALID, "table: build workspace missing or too small");
+    // SHJ probes read R's rids for every match and scan R's keys for the S
+    // tuples of duplicate-heavy keys; PHJ probes without partitioning read both
     const bool reads_r = !pl->phj || pl->passes == 0;
-    if (t->n_r && reads_r && (!t->r_rid || (pl->phj && !t->r_key)))
-        return fail(HJ_ERR_INVALID, "table: R's arrays are needed by this probe");
+    if (t->n_r && reads_r && (!t->r_rid || !t->r_key))
+        return fail(HJ_ERR_INVALID, "table: R's key and rid arrays are needed by this probe");
     return HJ_OK;
+}
+
+void init_recorder(Recorder& rec, hipStream_t stream, uint64_t* err, bool clear) {
+    rec.stream = stream;
+    rec.ctl.err = err;
+    rec.err_clear = clear ? err : nullptr;
+    rec.ctl.max_polls = kMaxStatusPolls;
+    rec.ctl.stall = 0;
+    rec.fail_phase = nullptr;
+    // HJ_DEBUG_FAIL_PHASE (tests of the failure paths, read per call):
+    //   scan_stall     the first tile of every chained scan never publishes and
+    //                  waits give up after 64 polls (every kernel still ends;
+    //                  the call's error word reports it)
+    //   launch:<name>  the launch of phase <name> reports a launch failure
+    thread_local std::string phase;
+    const char* v = getenv("HJ_DEBUG_FAIL_PHASE");
+    if (!v || !*v) return;
+    phase = v;
+    if (phase == "scan_stall") {
+        rec.ctl.max_polls = 64;
+        rec.ctl.stall = 1;
+    } else if (phase.rfind("launch:", 0) == 0) {
+        rec.fail_phase = phase.c_str() + 7;
+    }
 }
 
 hj_status launch_join(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,

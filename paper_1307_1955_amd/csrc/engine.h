@@ -68,6 +68,12 @@ void run_build(const Plan& pl, const hj_rel& R, void* ws, Recorder& rec);
 void run_probe(const Plan& pl, const hj_table& t, const hj_rel& S, const hj_out& out, void* ws,
                uint64_t* d_count, Recorder& rec);
 
+// Sets up the recorder of one call on `stream`: its chained scans report a
+// give-up in *err, which the call's first kernel clears when `clear` (a batch
+// clears its word once and runs its jobs with clear = false).  Applies the
+// HJ_DEBUG_FAIL_PHASE failure injection.
+void init_recorder(Recorder& rec, hipStream_t stream, uint64_t* err, bool clear);
+
 // Enqueues one validated join on rec.stream (ws must hold ws_bytes_for bytes).
 void run_join(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,
               uint64_t* d_count, Recorder& rec);

@@ -19,6 +19,7 @@ using namespace hj::eng;
 namespace hj {
 
 void Recorder::before(const char* name) {
+    cur = name;
     if (timed && n < cap) {
         names[n] = name;
         hipError_t e = hipEventRecord(ev[2 * n], stream);
@@ -29,6 +30,7 @@ void Recorder::before(const char* name) {
 void Recorder::after() {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess && err == hipSuccess) err = e;
+    if (fail_phase && cur && std::strcmp(fail_phase, cur) == 0 && err == hipSuccess) err = hipErrorLaunchFailure;
     if (timed && n < cap) {
         e = hipEventRecord(ev[2 * n + 1], stream);
         if (e != hipSuccess && err == hipSuccess) err = e;
@@ -37,6 +39,15 @@ void Recorder::after() {
 }
 
 }  // namespace hj
+
+namespace {
+hj_status ws_error(uint64_t werr) {
+    return fail(HJ_ERR_DEVICE, "device error word 0x%llx: %s", (unsigned long long)werr,
+                (werr & hj::kErrLookback) ? "a chained scan gave up waiting for a predecessor's status; "
+                                            "the output of the call is not valid"
+                                          : "unknown device-side failure");
+}
+}  // namespace
 
 extern "C" {
 
@@ -97,7 +108,7 @@ hj_status hj_build(const hj_params* p, const hj_rel* R, void* ws, size_t ws_byte
         return fail(HJ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
     if ((uintptr_t)ws % kAlign) return fail(HJ_ERR_INVALID, "workspace must be 256-byte aligned");
     hj::Recorder rec;
-    rec.stream = (hipStream_t)stream;
+    init_recorder(rec, (hipStream_t)stream, (uint64_t*)ws, true);
     (void)hipGetLastError();
     run_build(pl, *R, ws, rec);
     if (rec.err != hipSuccess) return fail(HJ_ERR_DEVICE, "launch failed: %s", hipGetErrorString(rec.err));
@@ -140,7 +151,7 @@ hj_status hj_probe(const hj_table* table, const hj_rel* S, const hj_out* out, vo
         return fail(HJ_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws ? ws_bytes : 0);
     if ((uintptr_t)ws % kAlign) return fail(HJ_ERR_INVALID, "workspace must be 256-byte aligned");
     hj::Recorder rec;
-    rec.stream = (hipStream_t)stream;
+    init_recorder(rec, (hipStream_t)stream, (uint64_t*)ws, true);
     (void)hipGetLastError();
     run_probe(pl, *table, *S, *out, ws, d_count, rec);
     if (rec.err != hipSuccess) return fail(HJ_ERR_DEVICE, "launch failed: %s", hipGetErrorString(rec.err));
@@ -151,7 +162,7 @@ hj_status hj_probe(const hj_table* table, const hj_rel* S, const hj_out* out, vo
 hj_status hj_join(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,
                   size_t ws_bytes, uint64_t* d_count, void* stream) {
     hj::Recorder rec;
-    rec.stream = (hipStream_t)stream;
+    init_recorder(rec, (hipStream_t)stream, (uint64_t*)ws, true);
     return launch_join(p, R, S, out, ws, ws_bytes, d_count, rec);
 }
 
@@ -161,9 +172,12 @@ hj_status hj_join_sync(const hj_params* p, const hj_rel* R, const hj_rel* S, con
     hj_status st = hj_join(p, R, S, out, ws, ws_bytes, d_count, stream);
     if (st != HJ_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    uint64_t werr = 0;
     hipError_t e = hipMemcpyAsync(h_count, d_count, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&werr, ws, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(HJ_ERR_DEVICE, "synchronisation failed: %s", hipGetErrorString(e));
+    if (werr) return ws_error(werr);
     if (*h_count > out->capacity)
         return fail(HJ_ERR_CAPACITY, "%llu pairs do not fit capacity %llu",
                     (unsigned long long)*h_count, (unsigned long long)out->capacity);
@@ -184,7 +198,7 @@ hj_status hj_join_timed(const hj_params* p, const hj_rel* R, const hj_rel* S, co
         }
     }
     hj::Recorder rec;
-    rec.stream = (hipStream_t)stream;
+    init_recorder(rec, (hipStream_t)stream, (uint64_t*)ws, true);
     rec.timed = true;
     rec.cap = max_launches;
     rec.names = names;
@@ -203,6 +217,18 @@ hj_status hj_join_timed(const hj_params* p, const hj_rel* R, const hj_rel* S, co
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     return st;
+}
+
+hj_status hj_workspace_status(const void* ws, void* stream) {
+    if (!ws || (uintptr_t)ws % kAlign) return fail(HJ_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t werr = 0;
+    hipError_t e = hipMemcpyAsync(&werr, ws, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(HJ_ERR_DEVICE, "synchronisation failed: %s", hipGetErrorString(e));
+    if (werr) return ws_error(werr);
+    clear_error();
+    return HJ_OK;
 }
 
 const char* hj_status_str(hj_status s) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hj_internal.h"
+
 namespace hj {
 
 constexpr int kWave = 64;
@@ -77,22 +79,35 @@ __device__ __forceinline__ uint64_t chain_claim(uint64_t* table, uint64_t s, int
 
 // Keys that a build workgroup pushed kHotRun or more times in one run (the
 // heavy keys of a skewed R), recorded by the SHJ build so that its probes can
-// hand such tuples over without walking their chains first.  n may exceed
-// kHotKeys; the keys beyond are not recorded.
+// hand such tuples over without walking their chains first.  rows[i] sums the
+// rows of key[i]'s recorded runs: a lower bound of its chain length (shorter
+// runs are not counted), so a probe may skip the walk only when that bound
+// alone exceeds its walk limit.  n may exceed kHotKeys; the keys beyond are
+// not recorded.  A key may hold two entries (two workgroups recording it at
+// once); each entry's rows stay a lower bound.
 constexpr uint32_t kHotKeys = 63;
 constexpr uint32_t kHotRun = 16;
 struct HotKeys {
     uint32_t n;
     int32_t key[kHotKeys];
+    uint32_t rows[kHotKeys];
+    uint32_t valid[kHotKeys];  // 1 once key[i] is written (read during the build)
 };
 
-__device__ __forceinline__ void record_hot(HotKeys* hot, int32_t key) {
-    // a key may land twice when two workgroups record it at once: harmless
+__device__ __forceinline__ void record_hot(HotKeys* hot, int32_t key, uint32_t rows) {
     const uint32_t n = min(__hip_atomic_load(&hot->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), kHotKeys);
-    for (uint32_t i = 0; i < n; ++i)
-        if (hot->key[i] == key) return;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (__hip_atomic_load(&hot->valid[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) && hot->key[i] == key) {
+            atomicAdd(&hot->rows[i], rows);
+            return;
+        }
+    }
     const uint32_t idx = atomicAdd(&hot->n, 1u);
-    if (idx < kHotKeys) hot->key[idx] = key;
+    if (idx < kHotKeys) {
+        hot->key[idx] = key;
+        atomicAdd(&hot->rows[idx], rows);
+        __hip_atomic_store(&hot->valid[idx], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Pushes of duplicate keys by one wave.  A row is pushed in front of its key's
@@ -125,7 +140,7 @@ struct WavePush {
                 const uint64_t prev =
                     atomicExch((unsigned long long*)&table[slot], (unsigned long long)chain_slot(key, head));
                 next[tail] = (uint32_t)(prev >> 32);
-                if (hot_keys && len >= kHotRun) record_hot(hot_keys, key);
+                if (hot_keys && len >= kHotRun) record_hot(hot_keys, key, len);
             }
             slot = kClaimed;
         }
@@ -161,7 +176,7 @@ struct WavePush {
                 const uint64_t prev =
                     atomicExch((unsigned long long*)&table[a.slot], (unsigned long long)chain_slot(a.key, a.head));
                 next[t] = (uint32_t)(prev >> 32);
-                if (hot_keys && rows >= kHotRun) record_hot(hot_keys, a.key);
+                if (hot_keys && rows >= kHotRun) record_hot(hot_keys, a.key, rows);
             }
         }
         __syncthreads();
@@ -380,10 +395,6 @@ __device__ __forceinline__ uint32_t live_remap(uint32_t b, uint32_t live) {
 constexpr uint64_t kStatusAggregate = 1ull << 62;
 constexpr uint64_t kStatusInclusive = 2ull << 62;
 constexpr uint64_t kStatusValue = (1ull << 62) - 1;
-// Bound on the polls of one unset status: predecessors always publish (they
-// took their tickets earlier and wait on nothing later), the bound only
-// guarantees that a kernel ends.
-constexpr uint32_t kMaxStatusPolls = 1u << 20;
 
 __device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -397,19 +408,25 @@ __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
 // publishes the tile's sum `tot` (< 2^62) in st[tile], walks back over the
 // predecessors' statuses 64 at a time, adding aggregates until it meets an
 // inclusive prefix, publishes its own inclusive prefix and returns the sum of
-// all predecessors.
-__device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint32_t tile, uint64_t tot) {
+// all predecessors.  A predecessor whose status stays unset for ctl.max_polls
+// polls is taken as inclusive so the kernel still ends, and kErrLookback goes
+// into the call's error word: the prefix is then wrong and the host reports
+// the call as failed.
+__device__ __forceinline__ uint64_t lookback_wave(uint64_t* st, uint32_t tile, uint64_t tot, const ScanCtl& ctl) {
     const uint32_t lane = lane_id();
-    if (lane == 0) status_store(&st[tile], (tile == 0 ? kStatusInclusive : kStatusAggregate) | (tot & kStatusValue));
+    if (lane == 0 && !(ctl.stall && tile == 0))
+        status_store(&st[tile], (tile == 0 ? kStatusInclusive : kStatusAggregate) | (tot & kStatusValue));
     uint64_t prefix = 0;
     int64_t j = (int64_t)tile - 1;
     while (j >= 0) {
         const int64_t idx = j - (int64_t)lane;  // lane 0 is the nearest predecessor
         uint64_t w = idx >= 0 ? status_load(&st[idx]) : kStatusInclusive;  // nothing before tile 0
-        for (uint32_t polls = 0; __ballot((w >> 62) == 0) != 0 && polls < kMaxStatusPolls; ++polls) {
+        for (uint32_t polls = 0; __ballot((w >> 62) == 0) != 0 && polls < ctl.max_polls; ++polls) {
             if (polls > 8) __builtin_amdgcn_s_sleep(1);
             if ((w >> 62) == 0) w = status_load(&st[idx]);
         }
+        if (__ballot((w >> 62) == 0) != 0 && lane == 0 && ctl.err)
+            atomicOr((unsigned long long*)ctl.err, (unsigned long long)kErrLookback);
         const uint64_t incl = __ballot((w >> 62) != 1);  // inclusive (or, past the poll bound, unset)
         const uint32_t stop = incl ? (uint32_t)__ffsll((unsigned long long)incl) - 1 : kWave - 1;
         prefix += wave_sum(lane <= stop ? (w & kStatusValue) : 0ull);

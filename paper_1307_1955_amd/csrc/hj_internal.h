@@ -33,9 +33,31 @@ struct PartPair {
     uint32_t s_off, s_len;
 };
 
-// Launch recorder: optional per-launch HIP event timing.
+// Bound on the polls of one unset status in a chained scan (decoupled
+// look-back): predecessors always publish (they took their tickets earlier and
+// wait on nothing later), the bound only guarantees that a kernel ends.
+constexpr uint32_t kMaxStatusPolls = 1u << 20;
+// Bits of a call's device error word (the first 8 bytes of its workspace; the
+// call's first kernel clears it).
+constexpr uint64_t kErrLookback = 1;  // a chained scan gave up waiting for a predecessor
+// How the chained scans of one call wait, and where a scan that gives up says so.
+struct ScanCtl {
+    uint64_t* err;       // the call's error word (kErrLookback is or-ed in)
+    uint32_t max_polls;  // polls of one unset status before giving up
+    uint32_t stall;      // failure injection: the first tile of every chained scan never publishes
+};
+
+// Launch recorder: the stream, the call's error word, optional per-launch HIP
+// event timing, and the first launch error.
 struct Recorder {
     hipStream_t stream = nullptr;
+    ScanCtl ctl{nullptr, kMaxStatusPolls, 0};
+    // the call's first kernel clears this word (nullptr: the word belongs to an
+    // enclosing batch that cleared it already)
+    uint64_t* err_clear = nullptr;
+    // failure injection: the launch of this phase reports a launch failure
+    const char* fail_phase = nullptr;
+    const char* cur = nullptr;
     bool timed = false;
     uint32_t n = 0, cap = 0;
     const char** names = nullptr;
@@ -53,13 +75,16 @@ void scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint64_t* state, ui
 void scan_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* state, uint64_t* total, Recorder& rec);
 // Clears n words.
 void zero_words(uint64_t* p, uint64_t n, Recorder& rec);
+// Clears the words a and b (either may be nullptr) in one small launch.
+void zero_pair(uint64_t* a, uint64_t* b, Recorder& rec);
 
 // ---- shj.hip ----
 constexpr uint32_t kShjBlock = 256;
 constexpr uint32_t kShjTile = 2048;  // S tuples per probe tile
 constexpr uint32_t kShjWavesPerBlock = kShjBlock / 64;
 struct HotKeys;  // keys the build saw in long push runs (hj_device.h)
-// Fills the table with empty slots and clears the hot-key record.
+// Fills the table with empty slots, clears the hot-key record and the call's
+// error word (rec.err_clear).
 void shj_fill(uint64_t* table, uint64_t nslots, HotKeys* hot, Recorder& rec);
 void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint32_t log2_slots,
                HotKeys* hot, Recorder& rec);
@@ -81,11 +106,13 @@ struct HeavyQueue {
     HeavyJob job[kHeavyJobs];
 };
 static_assert(sizeof(HeavyJob) == 64 && sizeof(HeavyQueue) % 8 == 0, "queue layout");
-// Sets *d_count to zero and empties the queue (one-pass SHJ probes).
+// Sets *d_count to zero and empties the queue (one-pass SHJ probes); clears
+// the call's error word (rec.err_clear).
 void shj_zero_one_pass(uint64_t* d_count, HeavyQueue* q, Recorder& rec);
 
 // The probe kernels read R's columns (r_key, r_rid, n_r rows, the ones the
-// table was built from) for keys with long chains.
+// table was built from) for keys with long chains.  shj_count also clears the
+// call's error word (rec.err_clear): it runs before the count scan.
 void shj_count(const int32_t* s_key, uint64_t n_s, const uint64_t* table, const uint32_t* next,
                uint32_t log2_slots, const int32_t* r_key, uint64_t n_r, const HotKeys* hot, uint64_t* wave_cnt,
                Recorder& rec);
@@ -133,10 +160,11 @@ struct Pass1 {
     uint32_t* tile_begin;
     uint64_t* zero;
     uint64_t nzero;
+    uint64_t* err_clear;  // the call's error word, cleared with the scan states (or nullptr)
 };
 Pass1 make_pass1(const int32_t* rk, const int32_t* rr, uint32_t n_r, const int32_t* sk, const int32_t* sr,
                  uint32_t n_s, uint32_t tile, uint32_t bits, PartSeg* segs, uint32_t* tile_begin, uint64_t* zero,
-                 uint64_t nzero);
+                 uint64_t nzero, uint64_t* err_clear);
 // Pass-1 histogram (and the pass's set-up, see Pass1).
 void part_hist_pass1(const Pass1& p1, const PassCfg& cfg, uint32_t* hist, Recorder& rec);
 // Histogram of a later pass over the segments in memory; tile_seg: segment of
@@ -194,7 +222,8 @@ void join_write(const PartPair* pairs, const uint32_t* item_begin, const ItemRec
                 uint64_t capacity, Recorder& rec);
 // wave_base == nullptr selects the one-pass write: `total` must be zero on entry
 // and ends as the number of pairs.
-// Writes zero to *d_count (joins with an empty side).
+// Writes zero to *d_count (joins with an empty side) and clears the call's
+// error word (rec.err_clear).
 void write_zero_count(uint64_t* d_count, Recorder& rec);
 
 // ---- direct joins (no partitioning: R fits one LDS table) ----
@@ -211,8 +240,8 @@ struct DirectJob {
     uint64_t* count;  // running total of the job's pairs (zeroed by direct_zero)
     uint32_t n_r, n_s, item0, pad;
 };
-// Writes one job descriptor and item map from kernel arguments and zeroes the
-// job's count (single join).
+// Writes one job descriptor and item map from kernel arguments, zeroes the
+// job's count and clears the call's error word (rec.err_clear) (single join).
 void direct_setup_one(DirectJob* job, uint32_t* item_job, const DirectJob& j, uint32_t nitems, Recorder& rec);
 void direct_zero(const DirectJob* jobs, uint32_t njobs, Recorder& rec);
 // lds_cap >= every job's n_r (<= kMaxLdsCap).

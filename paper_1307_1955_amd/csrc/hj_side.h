@@ -42,6 +42,7 @@ struct PlanArgs {
     // R's partition ranges from an earlier build (hj_build); nullptr: from the
     // histogram scan like S's
     const PartPair* r_pairs;
+    ScanCtl ctl;  // the chained scan of the plan reports a give-up here
 };
 
 enum SideKind : uint32_t { kSideNone = 0, kSideSetup2 = 1, kSidePlan = 2 };
@@ -134,7 +135,7 @@ __device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
     uint64_t tot;
     const uint64_t excl = block_excl_scan((uint64_t)ni | ((uint64_t)no << 31), wt, &tot);
     if (threadIdx.x < kWave) {
-        const uint64_t prefix = lookback_wave(state + 1, blk, tot);
+        const uint64_t prefix = lookback_wave(state + 1, blk, tot, A.ctl);
         if (threadIdx.x == 0) s_prefix = prefix;
     }
     __syncthreads();

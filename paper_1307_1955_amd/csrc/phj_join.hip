@@ -571,17 +571,22 @@ __global__ void k_direct_zero(const DirectJob* __restrict__ jobs, uint32_t njobs
         *jobs[j].count = 0;
 }
 
-__global__ void k_direct_setup_one(DirectJob* job, uint32_t* item_job, DirectJob j, uint32_t nitems) {
+__global__ void k_direct_setup_one(DirectJob* job, uint32_t* item_job, DirectJob j, uint32_t nitems,
+                                   uint64_t* err_clear) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *job = j;
         *j.count = 0;
+        if (err_clear) *err_clear = 0;
     }
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nitems; i += gridDim.x * blockDim.x)
         item_job[i] = 0;
 }
 
-__global__ void k_write_zero(uint64_t* p) {
-    if (threadIdx.x == 0) *p = 0;
+__global__ void k_write_zero(uint64_t* p, uint64_t* err_clear) {
+    if (threadIdx.x == 0) {
+        *p = 0;
+        if (err_clear) *err_clear = 0;
+    }
 }
 
 }  // namespace
@@ -594,7 +599,8 @@ size_t join_lds_bytes(uint32_t lds_cap, bool /*write*/) {
 
 void direct_setup_one(DirectJob* job, uint32_t* item_job, const DirectJob& j, uint32_t nitems, Recorder& rec) {
     rec.before("direct_setup");
-    hipLaunchKernelGGL(k_direct_setup_one, dim3(1), dim3(256), 0, rec.stream, job, item_job, j, nitems);
+    hipLaunchKernelGGL(k_direct_setup_one, dim3(1), dim3(256), 0, rec.stream, job, item_job, j, nitems,
+                       rec.err_clear);
     rec.after();
 }
 
@@ -632,7 +638,7 @@ void direct_join(const DirectJob* jobs, const uint32_t* item_job, uint32_t nitem
 
 void write_zero_count(uint64_t* d_count, Recorder& rec) {
     rec.before("zero_count");
-    hipLaunchKernelGGL(k_write_zero, dim3(1), dim3(64), 0, rec.stream, d_count);
+    hipLaunchKernelGGL(k_write_zero, dim3(1), dim3(64), 0, rec.stream, d_count, rec.err_clear);
     rec.after();
 }
 

@@ -117,6 +117,7 @@ __device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ p,
 __device__ __forceinline__ void pass1_setup(const Pass1& A) {
     for (uint64_t i = threadIdx.x; i < A.nzero; i += blockDim.x) A.zero[i] = 0;
     if (threadIdx.x == 0) {
+        if (A.err_clear) *A.err_clear = 0;
         PartSeg a;
         a.key_in = A.rk; a.rid_in = A.rr; a.out_base = 0; a.hist_base = 0; a.n = A.n_r; a.pad = 0;
         PartSeg b;
@@ -372,7 +373,7 @@ size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile) {
 
 Pass1 make_pass1(const int32_t* rk, const int32_t* rr, uint32_t n_r, const int32_t* sk, const int32_t* sr,
                  uint32_t n_s, uint32_t tile, uint32_t bits, PartSeg* segs, uint32_t* tile_begin, uint64_t* zero,
-                 uint64_t nzero) {
+                 uint64_t nzero, uint64_t* err_clear) {
     Pass1 a{};
     a.rk = rk;
     a.rr = rr;
@@ -387,6 +388,7 @@ Pass1 make_pass1(const int32_t* rk, const int32_t* rr, uint32_t n_r, const int32
     a.tile_begin = tile_begin;
     a.zero = zero;
     a.nzero = nzero;
+    a.err_clear = err_clear;
     return a;
 }
 

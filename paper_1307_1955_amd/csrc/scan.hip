@@ -30,7 +30,7 @@ constexpr uint32_t kScanChunk = kScanBlock * kScanItems;
 // state[0]: tile ticket; state[1 + t]: status of tile t.
 template <typename T>
 __global__ void __launch_bounds__(kScanBlock) k_scan(const T* in, T* out, uint64_t n, uint64_t* state,
-                                                   uint32_t ntiles, T* __restrict__ total) {
+                                                   uint32_t ntiles, T* __restrict__ total, ScanCtl ctl) {
     __shared__ T wt[kScanBlock / kWave];
     __shared__ uint32_t s_tile;
     __shared__ T s_prefix;
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(const T* in, T* out, uint64
     T tot;
     T run = block_excl_scan(s, wt, &tot);
     if (threadIdx.x < kWave) {  // wave 0: publish, then look back
-        const T prefix = (T)lookback_wave(state + 1, tile, (uint64_t)tot & kStatusValue);
+        const T prefix = (T)lookback_wave(state + 1, tile, (uint64_t)tot & kStatusValue, ctl);
         if (threadIdx.x == 0) {
             s_prefix = prefix;
             if (tile == ntiles - 1 && total) *total = prefix + tot;
@@ -83,11 +83,25 @@ void scan_impl(const T* in, T* out, uint64_t n, uint64_t* state, T* total, Recor
         hipLaunchKernelGGL(k_scan_empty<T>, dim3(1), dim3(64), 0, rec.stream, total);
     else
         hipLaunchKernelGGL(k_scan<T>, dim3((uint32_t)nt), dim3(kScanBlock), 0, rec.stream, in, out, n, state,
-                           (uint32_t)nt, total);
+                           (uint32_t)nt, total, rec.ctl);
     rec.after();
 }
 
+__global__ void k_zero_pair(uint64_t* a, uint64_t* b) {
+    if (threadIdx.x == 0) {
+        if (a) *a = 0;
+        if (b) *b = 0;
+    }
+}
+
 }  // namespace
+
+void zero_pair(uint64_t* a, uint64_t* b, Recorder& rec) {
+    if (!a && !b) return;
+    rec.before("zero_pair");
+    hipLaunchKernelGGL(k_zero_pair, dim3(1), dim3(64), 0, rec.stream, a, b);
+    rec.after();
+}
 
 size_t scan_state_words(uint64_t n) { return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1; }
 

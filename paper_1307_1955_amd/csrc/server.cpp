@@ -65,7 +65,8 @@ struct Slot {
     uint64_t footprint = 0;
     hj::DirectJob* h_djobs = nullptr;  // pinned, max_batch entries
     uint32_t* h_items = nullptr;       // pinned, max_items entries
-    char* ws = nullptr;                // this slot's workspace share
+    uint64_t* h_err = nullptr;         // pinned: the batch's device error word, copied back at its end
+    char* ws = nullptr;                // this slot's workspace share: [error word][jobs][items][pipeline]
 };
 
 // Direct work items a slot can hold (a direct job with |S| beyond the per-job
@@ -77,7 +78,7 @@ constexpr uint32_t kItemsPerJob = 64;
 struct hj_server {
     hj_server_config cfg{};
     std::vector<Slot> slots;
-    size_t slot_ws = 0, slot_direct_bytes = 0, slot_items_off = 0, slot_pipe_off = 0;
+    size_t slot_ws = 0, slot_djobs_off = 0, slot_items_off = 0, slot_pipe_off = 0;
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Request> pending;
@@ -122,8 +123,10 @@ hj_status launch_slot(hj_server* sv, Slot& s) {
         }
     }
     hj::Recorder rec;
-    rec.stream = s.stream;
-    hj::DirectJob* d_djobs = (hj::DirectJob*)s.ws;
+    uint64_t* d_err = (uint64_t*)s.ws;
+    init_recorder(rec, s.stream, d_err, false);
+    hj::zero_pair(d_err, nullptr, rec);  // one error word for the slot's batch
+    hj::DirectJob* d_djobs = (hj::DirectJob*)(s.ws + sv->slot_djobs_off);
     uint32_t* d_items = (uint32_t*)(s.ws + sv->slot_items_off);
     if (nd) {
         hipError_t e = hipMemcpyAsync(d_djobs, s.h_djobs, sizeof(hj::DirectJob) * nd, hipMemcpyHostToDevice, s.stream);
@@ -144,7 +147,9 @@ hj_status launch_slot(hj_server* sv, Slot& s) {
             run_join(r.plan, r.job.R, r.job.S, r.job.out, s.ws + sv->slot_pipe_off, r.job.d_count, rec);
     }
     if (rec.err != hipSuccess) return fail(HJ_ERR_DEVICE, "server launch failed: %s", hipGetErrorString(rec.err));
-    hipError_t e = hipEventRecord(s.done, s.stream);
+    *s.h_err = 0;
+    hipError_t e = hipMemcpyAsync(s.h_err, d_err, sizeof(uint64_t), hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
     if (e != hipSuccess) return fail(HJ_ERR_DEVICE, "server event failed: %s", hipGetErrorString(e));
     return HJ_OK;
 }
@@ -162,10 +167,12 @@ void dispatcher(hj_server* sv) {
                 continue;
             }
             const Clock::time_point now = Clock::now();
+            // a set error word fails this batch's requests; the server goes on
+            const bool ok = q == hipSuccess && sv->fatal == HJ_OK && *s.h_err == 0;
             for (size_t i = 0; i < s.reqs.size(); ++i) {
                 Done d;
                 d.ticket = s.reqs[i].ticket;
-                d.status = (q == hipSuccess && sv->fatal == HJ_OK) ? HJ_OK : HJ_ERR_DEVICE;
+                d.status = ok ? HJ_OK : HJ_ERR_DEVICE;
                 d.latency_s = std::chrono::duration<double>(now - s.reqs[i].arrival).count();
                 d.queue_s = std::chrono::duration<double>(s.admitted[i] - s.reqs[i].arrival).count();
                 sv->done.push_back(d);
@@ -247,6 +254,7 @@ void destroy(hj_server* sv) {
         if (s.stream) (void)hipStreamDestroy(s.stream);
         if (s.h_djobs) (void)hipHostFree(s.h_djobs);
         if (s.h_items) (void)hipHostFree(s.h_items);
+        if (s.h_err) (void)hipHostFree(s.h_err);
     }
     delete sv;
 }
@@ -267,8 +275,8 @@ hj_status hj_server_create(const hj_server_config* cfg, void* ws, size_t ws_byte
     if (!sv) return fail(HJ_ERR_DEVICE, "out of host memory");
     sv->cfg = *cfg;
     sv->slots.resize(cfg->slots);
-    sv->slot_direct_bytes = align_up(sizeof(hj::DirectJob) * cfg->max_batch_jobs);
-    sv->slot_items_off = sv->slot_direct_bytes;
+    sv->slot_djobs_off = align_up(sizeof(uint64_t));
+    sv->slot_items_off = sv->slot_djobs_off + align_up(sizeof(hj::DirectJob) * cfg->max_batch_jobs);
     sv->slot_pipe_off = sv->slot_items_off + align_up(sizeof(uint32_t) * cfg->max_batch_jobs * kItemsPerJob);
     sv->slot_ws = (ws_bytes / cfg->slots) / kAlign * kAlign;
     if (sv->slot_ws <= sv->slot_pipe_off) {
@@ -285,6 +293,7 @@ hj_status hj_server_create(const hj_server_config* cfg, void* ws, size_t ws_byte
         if (e == hipSuccess)
             e = hipHostMalloc((void**)&s.h_items, sizeof(uint32_t) * cfg->max_batch_jobs * kItemsPerJob,
                               hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_err, sizeof(uint64_t), hipHostMallocDefault);
         if (e != hipSuccess) {
             destroy(sv);
             return fail(HJ_ERR_DEVICE, "server setup failed: %s", hipGetErrorString(e));

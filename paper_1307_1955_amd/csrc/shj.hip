@@ -27,9 +27,12 @@ namespace hj {
 namespace {
 
 __global__ void __launch_bounds__(256) k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v,
-                                                 uint32_t* __restrict__ zero, uint32_t zero_words) {
-    if (blockIdx.x == 0)
+                                                 uint32_t* __restrict__ zero, uint32_t zero_words,
+                                                 uint64_t* __restrict__ err_clear) {
+    if (blockIdx.x == 0) {
         for (uint32_t i = threadIdx.x; i < zero_words; i += blockDim.x) zero[i] = 0;
+        if (threadIdx.x == 0 && err_clear) *err_clear = 0;
+    }
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 2;
     for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; i < n; i += stride) {
         if (i + 1 < n) {
@@ -79,14 +82,17 @@ __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ k
 constexpr uint32_t kSub = kShjTile / kShjWavesPerBlock;
 constexpr uint32_t kSU = kSub / kWave;
 
-// An S tuple whose chain is longer than lim, or whose key the build recorded
-// as hot (hk[0..nhk), LDS), is registered in hs as heavy.
+// An S tuple whose chain is longer than lim is registered in hs as heavy.  When
+// the build recorded its key as hot (hk[0..nhk), LDS) with more than lim rows
+// (hr: the recorded lower bound of the chain length), it is registered without
+// walking the chain; otherwise the walk decides.
 // hs->n must be zero and visible to the block before the call.
 template <bool kRids>
 __device__ __forceinline__ void shj_probe(const int32_t* __restrict__ s_key, const int32_t* __restrict__ s_rid,
                                           uint64_t begin, uint64_t n_s, const uint64_t* __restrict__ table,
                                           const uint32_t* __restrict__ next, uint32_t log2_slots, uint32_t lim,
-                                          const int32_t* hk, uint32_t nhk, HeavySet* hs, int32_t* q, int32_t* qr,
+                                          const int32_t* hk, const uint32_t* hr, uint32_t nhk, HeavySet* hs,
+                                          int32_t* q, int32_t* qr,
                                           uint32_t* head, uint32_t* cnt) {
     const PowStep step{(1ull << log2_slots) - 1};
 #pragma unroll
@@ -101,21 +107,24 @@ __device__ __forceinline__ void shj_probe(const int32_t* __restrict__ s_key, con
             if (kRids) qr[u] = s_rid[j];
             head[u] = chain_find(table, home_slot(q[u], log2_slots), q[u], step);
             if (head[u] != kNotFound) {
-                bool hot = false;
+                uint32_t hot_rows = 0;
                 if (!(head[u] & kLast))  // a chain of one row is never heavy
-                    for (uint32_t i = 0; i < nhk; ++i) hot |= hk[i] == q[u];
-                cnt[u] = hot ? register_heavy(next, head[u], q[u], kRids ? qr[u] : 0, hs)
-                             : heavy_or_len(next, head[u], lim, q[u], kRids ? qr[u] : 0, hs);
+                    for (uint32_t i = 0; i < nhk; ++i) hot_rows = hk[i] == q[u] ? max(hot_rows, hr[i]) : hot_rows;
+                cnt[u] = hot_rows > lim ? register_heavy(next, head[u], q[u], kRids ? qr[u] : 0, hs)
+                                        : heavy_or_len(next, head[u], lim, q[u], kRids ? qr[u] : 0, hs);
             }
         }
     }
 }
 
 // The build's hot keys into LDS (before the barrier that publishes hs->n = 0).
-__device__ __forceinline__ void load_hot(const HotKeys* hot, int32_t* hk, uint32_t* nhk) {
+__device__ __forceinline__ void load_hot(const HotKeys* hot, int32_t* hk, uint32_t* hr, uint32_t* nhk) {
     const uint32_t n = min(hot->n, kHotKeys);
     if (threadIdx.x == 0) *nhk = n;
-    if (threadIdx.x < n) hk[threadIdx.x] = hot->key[threadIdx.x];
+    if (threadIdx.x < n) {
+        hk[threadIdx.x] = hot->key[threadIdx.x];
+        hr[threadIdx.x] = hot->rows[threadIdx.x];
+    }
 }
 
 __device__ __forceinline__ uint32_t count_of(uint32_t c, const HeavySet* hs) {
@@ -127,18 +136,21 @@ __global__ void __launch_bounds__(kShjBlock) k_shj_count(const int32_t* __restri
                                                         const uint32_t* __restrict__ next,
                                                         uint32_t log2_slots, const int32_t* __restrict__ r_key,
                                                         uint64_t n_r, const HotKeys* __restrict__ hot,
-                                                        uint64_t* __restrict__ wave_cnt) {
+                                                        uint64_t* __restrict__ wave_cnt,
+                                                        uint64_t* __restrict__ err_clear) {
     __shared__ HeavySet hs;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && err_clear) *err_clear = 0;
     __shared__ int32_t hk[kHotKeys];
+    __shared__ uint32_t hr[kHotKeys];
     __shared__ uint32_t nhk;
     const uint32_t w = threadIdx.x / kWave;
     const uint64_t begin = (uint64_t)blockIdx.x * kShjTile + (uint64_t)w * kSub;
-    load_hot(hot, hk, &nhk);
+    load_hot(hot, hk, hr, &nhk);
     if (threadIdx.x == 0) hs.n = hs.queued = 0;
     __syncthreads();
     int32_t q[kSU], qr[kSU];
     uint32_t head[kSU], c[kSU];
-    shj_probe<false>(s_key, nullptr, begin, n_s, table, next, log2_slots, heavy_limit(n_r), hk, nhk, &hs, q, qr,
+    shj_probe<false>(s_key, nullptr, begin, n_s, table, next, log2_slots, heavy_limit(n_r), hk, hr, nhk, &hs, q, qr,
                      head, c);
     heavy_counts<kShjBlock, kHeavyV>(r_key, n_r, &hs);
     uint64_t cnt = 0;
@@ -296,18 +308,19 @@ __global__ void __launch_bounds__(kShjBlock) __attribute__((amdgpu_waves_per_eu(
     __shared__ uint64_t wtot[kShjWavesPerBlock + 1];
     __shared__ HeavySet hs;
     __shared__ int32_t hk[kHotKeys];
+    __shared__ uint32_t hr[kHotKeys];
     __shared__ uint32_t nhk;
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
     const uint64_t begin = (uint64_t)blockIdx.x * kShjTile + (uint64_t)w * kSub;
-    load_hot(hot, hk, &nhk);
+    load_hot(hot, hk, hr, &nhk);
     if (threadIdx.x == 0) hs.n = hs.queued = 0;
     __syncthreads();
     int32_t q[kSU], qr[kSU];
     uint32_t head[kSU], c[kSU];
     // one-pass: a chain is heavy from kQueueWalk rows on (handed to every workgroup)
     const uint32_t lim = kOnePass ? min(heavy_limit(n_r), kQueueWalk) : heavy_limit(n_r);
-    shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, lim, hk, nhk, &hs, q, qr, head, c);
+    shj_probe<true>(s_key, s_rid, begin, n_s, table, next, log2_slots, lim, hk, hr, nhk, &hs, q, qr, head, c);
     // with R in one chunk the queue adds no workgroups to a tuple: keep the block's own scan
     if (kOnePass && n_r > kHelpChunk) hand_off(heavy, &hs);
     heavy_counts<kShjBlock, kHeavyV, kOnePass>(r_key, n_r, &hs);
@@ -357,8 +370,12 @@ __global__ void __launch_bounds__(kShjBlock) __attribute__((amdgpu_waves_per_eu(
     if (kOnePass) help_heavy<kShjBlock>(heavy, r_key, r_rid, n_r, total, capacity, out_r, out_s, hs.wsum);
 }
 
-__global__ void __launch_bounds__(256) k_zero_one_pass(uint64_t* __restrict__ total, uint64_t* __restrict__ q) {
-    if (threadIdx.x == 0) *total = 0;
+__global__ void __launch_bounds__(256) k_zero_one_pass(uint64_t* __restrict__ total, uint64_t* __restrict__ q,
+                                                      uint64_t* __restrict__ err_clear) {
+    if (threadIdx.x == 0) {
+        *total = 0;
+        if (err_clear) *err_clear = 0;
+    }
     for (uint32_t i = threadIdx.x; i < sizeof(HeavyQueue) / 8; i += blockDim.x) q[i] = 0;
 }
 
@@ -370,13 +387,14 @@ void shj_fill(uint64_t* table, uint64_t nslots, HotKeys* hot, Recorder& rec) {
     if (blocks == 0) blocks = 1;
     rec.before("shj_fill");
     hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)blocks), dim3(256), 0, rec.stream, table, nslots,
-                       kEmptySlot, reinterpret_cast<uint32_t*>(hot), (uint32_t)(sizeof(HotKeys) / 4));
+                       kEmptySlot, reinterpret_cast<uint32_t*>(hot), (uint32_t)(sizeof(HotKeys) / 4), rec.err_clear);
     rec.after();
 }
 
 void shj_zero_one_pass(uint64_t* d_count, HeavyQueue* q, Recorder& rec) {
     rec.before("zero_count");
-    hipLaunchKernelGGL(k_zero_one_pass, dim3(1), dim3(256), 0, rec.stream, d_count, reinterpret_cast<uint64_t*>(q));
+    hipLaunchKernelGGL(k_zero_one_pass, dim3(1), dim3(256), 0, rec.stream, d_count, reinterpret_cast<uint64_t*>(q),
+                       rec.err_clear);
     rec.after();
 }
 
@@ -398,7 +416,7 @@ void shj_count(const int32_t* s_key, uint64_t n_s, const uint64_t* table, const 
     if (tiles == 0) return;
     rec.before("shj_count");
     hipLaunchKernelGGL(k_shj_count, dim3((uint32_t)tiles), dim3(kShjBlock), 0, rec.stream, s_key, n_s,
-                       table, next, log2_slots, r_key, n_r, hot, wave_cnt);
+                       table, next, log2_slots, r_key, n_r, hot, wave_cnt, rec.err_clear);
     rec.after();
 }
 

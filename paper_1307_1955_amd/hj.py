@@ -39,7 +39,8 @@ EXPORTED = (
     "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_run",
     "hj_batch_plan_destroy", "hj_batch_bytes", "hj_batch", "hj_table_bytes", "hj_build",
     "hj_probe_workspace_bytes", "hj_probe", "hj_server_create", "hj_server_submit", "hj_server_submit_probe", "hj_server_poll", "hj_server_drain",
-    "hj_server_stats", "hj_server_destroy", "hj_status_str", "hj_last_error", "hj_version",
+    "hj_server_stats", "hj_server_destroy", "hj_workspace_status", "hj_status_str", "hj_last_error",
+    "hj_version",
 )
 
 
@@ -127,6 +128,8 @@ def load() -> ctypes.CDLL:
             lib.hj_batch_bytes.argtypes = [ctypes.c_uint32, P(HjJob), P(HjParams)]
             lib.hj_batch.restype = ctypes.c_int
             lib.hj_batch.argtypes = [ctypes.c_uint32, P(HjJob), P(HjParams), vp, ctypes.c_size_t, vp]
+            lib.hj_workspace_status.restype = ctypes.c_int
+            lib.hj_workspace_status.argtypes = [vp, vp]
             lib.hj_status_str.restype = ctypes.c_char_p
             lib.hj_status_str.argtypes = [ctypes.c_int]
             lib.hj_last_error.restype = ctypes.c_char_p
@@ -212,6 +215,13 @@ def hj_workspace_bytes(p: HjParams, n_r: int, n_s: int) -> int:
     if v == 0:
         raise HJError(HJ_ERR_INVALID, load().hj_last_error().decode())
     return int(v)
+
+
+def hj_workspace_status(ws: torch.Tensor, stream=None) -> None:
+    """Synchronises ``stream`` and raises ``HJError`` (HJ_ERR_DEVICE) when the
+    error word of the workspace ``ws`` (the last call that used it) is set."""
+    wp, _ = _ws(ws)
+    _check(load().hj_workspace_status(wp, _stream(stream)))
 
 
 def hj_version() -> int:

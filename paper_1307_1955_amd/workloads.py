@@ -72,3 +72,39 @@ def tuned_params(specs, table=None):
     if table is None:
         table = tune.load_table()
     return [tune.choose(sp.n_r, sp.n_s, table).params() for sp in specs]
+
+
+def verify_device(wl: BatchWorkload, counts: torch.Tensor | None = None, jobs=None) -> list:
+    """Checks job outputs on the device against what the workload fixes, with
+    plain PyTorch ops: the count equals the closed form (every S key <= |R_j|
+    matches exactly one R tuple), every pair's R row and S row carry equal keys
+    (rid = row index), and no S row appears twice.  Together these say that
+    each matching S row appears exactly once, with the one R row of its key.
+    counts: the counts to check (default wl.d_counts), one per job; jobs: the
+    job indices (default all).  Returns the failing jobs as (job, reason)."""
+    counts = wl.d_counts if counts is None else counts
+    got = counts.cpu().tolist()
+    bad = []
+    for j in (range(len(wl.jobs)) if jobs is None else jobs):
+        rk, _, sk, _, o_r, o_s = wl.jobs[j]
+        c = wl.expected[j]
+        if got[j] != c:
+            bad.append((j, "count %d, closed form %d" % (got[j], c)))
+            continue
+        if c == 0:
+            continue
+        a, b = o_r[:c], o_s[:c]
+        # rows in range before any gather
+        lo_a, hi_a = torch.aminmax(a)
+        lo_b, hi_b = torch.aminmax(b)
+        if int(lo_a) < 0 or int(hi_a) >= rk.numel() or int(lo_b) < 0 or int(hi_b) >= sk.numel():
+            bad.append((j, "row out of range"))
+            continue
+        if not torch.equal(rk.index_select(0, a), sk.index_select(0, b)):
+            bad.append((j, "a pair joins unequal keys"))
+            continue
+        seen = torch.zeros(sk.numel(), dtype=torch.int32, device=sk.device)
+        seen.index_fill_(0, b.long(), 1)
+        if int(seen.sum()) != c:
+            bad.append((j, "an S row appears twice"))
+    return bad

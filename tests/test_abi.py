@@ -246,12 +246,19 @@ def test_build_probe_validation_before_launch(hj):
     bad = hj.HjTable.from_buffer_copy(t)
     bad.ws_bytes = tb - 1
     assert probe(bad) == hj.HJ_ERR_INVALID
-    # SHJ probes read R's rids through the table
+    # SHJ probes read R's rids (matches) and R's keys (heavy-key scans) through the table
     ps = hj.params("shj")
     ts = hj.HjTable()
     ts.params = hj.hj_resolve_params(ps, 1000, 1000)
     ts.n_r, ts.r_key, ts.r_rid, ts.ws, ts.ws_bytes = 1000, 256, None, 1 << 20, hj.hj_table_bytes(ps, 1000)
     assert lib.hj_probe_workspace_bytes(ctypes.byref(ts), 500) == 0
+    ts.r_key, ts.r_rid = None, 256
+    assert lib.hj_probe_workspace_bytes(ctypes.byref(ts), 500) == 0
+    # a NULL r_key is rejected before any launch (fake device pointers: a launch would fault)
+    assert probe(ts, wb=1 << 22) == hj.HJ_ERR_INVALID
+    assert b"key and rid" in lib.hj_last_error()
+    ts.r_key = 256
+    assert lib.hj_probe_workspace_bytes(ctypes.byref(ts), 500) > 0
 
 
 def test_batch_bytes_on_host(hj):

@@ -1,9 +1,11 @@
 """The batched workload at full size (4096 joins, |R| log-uniform in [1024, 4M],
 |S| = |R| x U{1..16}), in the launch configuration the benchmark times: one
-captured plan with per-job parameters from the tuning table.  Every job's count
-against its closed form; sampled jobs row by row against the closed form and
-on sampled S rows against the oracle; sampled inputs against the host
-generator."""
+captured plan with per-job parameters from the tuning table.  Every job checked
+on the device (count = closed form, every pair joins equal keys, no S row
+twice); sampled jobs row by row against the closed form and on sampled S rows
+against the oracle; sampled inputs against the host generator.  The same
+workload served (Poisson arrivals, continuous batching under the 64 GiB cap),
+every request owning its output and count, every request checked the same way."""
 import numpy as np
 import pytest
 
@@ -37,11 +39,17 @@ def test_c4_full_batch():
     params = workloads.tuned_params(wl.specs)
     plan = hj.BatchPlan(wl.jobs, wl.d_counts, params=params)
     ws = plan.workspace()
-    for _ in range(2):  # the captured graph, launched twice: the second launch must give the same counts
+    for _ in range(2):  # the captured graph, launched twice: both launches checked in full
         wl.d_counts.zero_()
+        for o in wl.jobs:  # outputs poisoned, so a pair the second launch misses shows
+            o[4].fill_(-1)
+            o[5].fill_(-1)
         plan.run(ws)
         torch.cuda.synchronize()
+        hj.hj_workspace_status(ws)
         assert torch.equal(wl.d_counts.cpu(), torch.tensor(wl.expected, dtype=torch.int64))
+        # every job, every pair, on the device
+        assert workloads.verify_device(wl) == []
     order = np.argsort([sp.n_r for sp in wl.specs])
     rng = np.random.default_rng(44)
     picks = sorted(set([int(order[0]), int(order[1]), int(order[len(order) // 2]), int(order[-2]),
@@ -65,4 +73,42 @@ def test_c4_full_batch():
         assert np.array_equal(oracle.canonical(got[:, 0], got[:, 1]), oracle.canonical(w_r, w_s)), j
     plan.close()
     del ws, plan, wl
+    torch.cuda.empty_cache()
+
+
+def test_c5_served_full_size():
+    """Every job of the batched workload submitted once to the server at Poisson
+    arrivals (so each in-flight request owns its output buffer and count), then
+    every request checked on the device."""
+    import time
+
+    torch.cuda.empty_cache()
+    wl = workloads.batch_workload(njobs=4096)
+    params = workloads.tuned_params(wl.specs)
+    ws_max = max(hj.hj_workspace_bytes(q, sp.n_r, sp.n_s) for q, sp in zip(params, wl.specs))
+    slots = 16
+    pool = torch.empty(slots * (ws_max + (64 << 20)), dtype=torch.uint8, device="cuda")
+    sv = hj.Server(pool, mem_cap_bytes=64 << 30, slots=slots, max_batch_jobs=64)
+    arr = gen.poisson_arrivals(18, len(wl.jobs), 8000.0)
+    order = np.random.default_rng(19).permutation(len(wl.jobs))
+    for o in wl.jobs:
+        o[4].fill_(-1)
+        o[5].fill_(-1)
+    torch.cuda.synchronize()
+    tickets = {}
+    t0 = time.perf_counter()
+    for i, j in enumerate(order):
+        while time.perf_counter() < t0 + arr[i]:
+            pass
+        sp = wl.specs[j]
+        fp = 8 * (sp.n_r + sp.n_s) + 8 * wl.expected[j] + hj.hj_workspace_bytes(params[j], sp.n_r, sp.n_s)
+        tickets[sv.submit(*wl.jobs[j], wl.d_counts[j:j + 1], params[j], fp)] = int(j)
+    sv.drain()
+    done = sv.poll(len(wl.jobs) + 16)
+    assert sorted(t for t, *_ in done) == sorted(tickets)
+    assert all(st == hj.HJ_OK for _, st, *_ in done)
+    assert sv.stats()["rejected"] == 0 and sv.stats()["bytes_in_use"] == 0
+    sv.close()
+    assert workloads.verify_device(wl) == []
+    del pool, sv, wl
     torch.cuda.empty_cache()

@@ -213,6 +213,22 @@ def test_shj_heavy_queue_overflow(one_pass):
     check_small(hj.params("shj", one_pass=one_pass), rk.astype(np.int32), rr, sk.astype(np.int32), sr)
 
 
+@pytest.mark.parametrize("one_pass", [True, False])
+def test_sorted_r_short_duplicate_runs(one_pass):
+    """R sorted with 32 duplicates per key: every build wave pushes runs of 32 rows
+    onto one slot, so up to 63 keys are recorded as hot, yet every chain (32 rows)
+    is far below the heavy limit.  A probe registers a hot key's tuple at once only
+    when the recorded rows exceed its walk limit; here the walks decide, and the
+    result is the same multiset either way."""
+    n_r, n_s = 1 << 18, 1 << 18
+    rng = np.random.default_rng(61)
+    rk = (np.arange(n_r, dtype=np.int64) // 32).astype(np.int32)
+    sk = rng.integers(-100, n_r // 32 + 100, size=n_s).astype(np.int32)
+    rr = np.arange(n_r, dtype=np.int32)
+    sr = rng.permutation(n_s).astype(np.int32)
+    check_small(hj.params("shj", one_pass=one_pass), rk, rr, sk, sr)
+
+
 def offset_view(a, off):
     """Device copy of `a` that starts `off` int32 elements into a larger buffer
     (input columns at every 4-byte alignment inside a 16-byte line)."""
@@ -395,6 +411,69 @@ def test_c2_full(name, kw):
     assert np.array_equal(r_key[rows[:1000] % len(r_key)],
                           gen.permutation_at(2, gen.STREAM_R_KEYS, 1 << 24, rows[:1000] % len(r_key)) + 1)
     assert np.array_equal(s_key[rows], gen.uniform_int_at(2, gen.STREAM_S_KEYS, rows, 1, 1 << 25))
+
+
+# 16M x 16M in one pass of few radix bits (and 7 + 7): every R partition is
+# larger than the LDS table and joins through the HBM-table path.  With the
+# identity hash the partitions are exactly equal (1024 build items of 16384 R
+# tuples); MurmurHash 2.0 makes them uneven, so there are more build items than
+# the 1024 workgroups of the HBM-table launches and their grid-stride loops turn.
+C2_WIDE_PARAMS = [
+    ("phj1_6", dict(algo="phj", passes=1, bits=(6,))),
+    ("phj1_6_murmur_1pass", dict(algo="phj", passes=1, bits=(6,), hash="murmur2", one_pass=True)),
+    ("phj1_7_1pass", dict(algo="phj", passes=1, bits=(7,), one_pass=True)),
+    ("phj1_8_murmur", dict(algo="phj", passes=1, bits=(8,), hash="murmur2")),
+    ("phj1_10_murmur_1pass", dict(algo="phj", passes=1, bits=(10,), hash="murmur2", one_pass=True)),
+    ("phj1_10", dict(algo="phj", passes=1, bits=(10,))),
+    ("phj2_7_7", dict(algo="phj", passes=2, bits=(7, 7))),
+    ("phj2_7_7_1pass", dict(algo="phj", passes=2, bits=(7, 7), one_pass=True)),
+]
+
+
+def murmur2_np(k):
+    """MurmurHash 2.0 of each 4-byte key (the radix hash HJ_HASH_MURMUR2), in
+    numpy, to count the partitions a configuration makes."""
+    m = np.uint64(0x5bd1e995)
+    mask = np.uint64(0xFFFFFFFF)
+    k = k.astype(np.uint32).astype(np.uint64)
+    h = (np.uint64(0x9747b28c) ^ np.uint64(4)) & mask
+    k = (k * m) & mask
+    k ^= k >> np.uint64(24)
+    k = (k * m) & mask
+    h = (h * m) & mask
+    h ^= k
+    h ^= h >> np.uint64(13)
+    h = (h * m) & mask
+    h ^= h >> np.uint64(15)
+    return h.astype(np.uint32)
+
+
+def hbm_build_items(p, r_key, s_key):
+    """HBM-table build items of a one-pass configuration: ceil(|R_i| / 16384) for
+    every partition with |R_i| above the LDS table and a non-empty S_i."""
+    q = hj.hj_resolve_params(p, len(r_key), len(s_key))
+    B = q.bits[0] + (q.bits[1] if q.passes == 2 else 0)
+    f = murmur2_np if q.hash == hj.HJ_HASH_MURMUR2 else (lambda a: a.astype(np.uint32))
+    mask = np.uint32((1 << B) - 1)
+    r_len = np.bincount(f(r_key) & mask, minlength=1 << B)
+    s_len = np.bincount(f(s_key) & mask, minlength=1 << B)
+    big = (r_len > q.lds_cap) & (s_len > 0)
+    return int(np.sum((r_len[big] + 16383) // 16384))
+
+
+@pytest.mark.parametrize("name,kw", C2_WIDE_PARAMS, ids=[c[0] for c in C2_WIDE_PARAMS])
+def test_c2_full_hbm_tables(name, kw):
+    """16M x 16M through the HBM-table path for every partition: every row against
+    the closed form, a sample of S rows against the oracle."""
+    rk, rr, sk, sr = dgen.config_c2()
+    p = hj.params(**kw)
+    r_key, s_key, rows = check_full(p, rk, rr, sk, sr, seed=22)
+    if kw["passes"] == 1:
+        items = hbm_build_items(p, r_key, s_key)
+        if kw.get("hash") == "murmur2":
+            assert items > 1024, items  # the build launches' grid-stride loops run a second time
+        else:
+            assert items == 1024, items
 
 
 @pytest.mark.parametrize("theta", [0.5, 1.0])
