@@ -162,6 +162,21 @@ hj_status hj_join_timed(const hj_params* p, const hj_rel* R, const hj_rel* S, co
                         const char** names, float* ms, uint32_t max_launches,
                         uint32_t* n_launches);
 
+/* hj_join without a workspace argument, for callers that cannot allocate device
+   memory (code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc).  The workspace is a fixed array of this library in device
+   memory: 64 MiB (67,108,864 bytes) on every GPU the library runs on, held from
+   the first call on that GPU until the process ends.  Arguments, result and
+   asynchrony as hj_join; nothing is allocated.  Returns HJ_ERR_WORKSPACE,
+   before touching the device, when hj_workspace_bytes(p, R->n, S->n) exceeds
+   the array (e.g. HJ_AUTO up to about |R| = |S| = 1.7M tuples, SHJ up to about
+   3M + 3M).  All calls on one GPU share its array: calls that overlap on one
+   GPU (two streams, two threads) race; serialise them.  The call's device
+   error word (hj_workspace_status) sits in the array and is not reachable by
+   the caller. */
+hj_status hj_join_noalloc(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out,
+                          uint64_t* d_count, void* stream);
+
 /* ---- Build once, probe many times -----------------------------------------
    The two phases of Algorithm 1 as separate calls: hj_build makes R's
    build-side structure once, and any number of hj_probe calls join relations

@@ -36,6 +36,7 @@ HJ_BATCH_NO_GRAPH = 1
 # Every symbol include/hj.h declares.
 EXPORTED = (
     "hj_default_params", "hj_resolve_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
+    "hj_join_noalloc",
     "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_run",
     "hj_batch_plan_destroy", "hj_batch_bytes", "hj_batch", "hj_table_bytes", "hj_build",
     "hj_probe_workspace_bytes", "hj_probe", "hj_server_create", "hj_server_submit", "hj_server_submit_probe", "hj_server_poll", "hj_server_drain",
@@ -116,6 +117,8 @@ def load() -> ctypes.CDLL:
             lib.hj_join_timed.argtypes = [P(HjParams), P(HjRel), P(HjRel), P(HjOut), vp, ctypes.c_size_t, vp,
                                           vp, P(ctypes.c_char_p), P(ctypes.c_float), ctypes.c_uint32,
                                           P(ctypes.c_uint32)]
+            lib.hj_join_noalloc.restype = ctypes.c_int
+            lib.hj_join_noalloc.argtypes = [P(HjParams), P(HjRel), P(HjRel), P(HjOut), vp, vp]
             lib.hj_table_bytes.restype = ctypes.c_size_t
             lib.hj_table_bytes.argtypes = [P(HjParams), ctypes.c_uint64]
             lib.hj_build.restype = ctypes.c_int
@@ -304,6 +307,17 @@ def hj_join_timed(p: HjParams, r_key, r_rid, s_key, s_rid, out_r, out_s, ws: tor
                                 d_count.data_ptr(), _stream(stream), names, ms, max_launches,
                                 ctypes.byref(n)))
     return [(names[i].decode(), float(ms[i])) for i in range(min(n.value, max_launches))]
+
+
+def hj_join_noalloc(p: HjParams, r_key, r_rid, s_key, s_rid, out_r, out_s, d_count: torch.Tensor,
+                    stream=None) -> None:
+    """Enqueues the join on the library's fixed device workspace (no workspace
+    argument, nothing allocated; see include/hj.h for its size limit)."""
+    if d_count.dtype != torch.int64 or not d_count.is_cuda or d_count.numel() < 1:
+        raise ValueError("d_count must be an int64 CUDA tensor with at least one element")
+    R, S, O = _rel(r_key, r_rid, "R"), _rel(s_key, s_rid, "S"), _out(out_r, out_s)
+    _check(load().hj_join_noalloc(ctypes.byref(p), ctypes.byref(R), ctypes.byref(S), ctypes.byref(O),
+                                  d_count.data_ptr(), _stream(stream)))
 
 
 def join(r_key, r_rid, s_key, s_rid, p: HjParams | None = None, capacity: int | None = None,

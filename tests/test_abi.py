@@ -281,3 +281,19 @@ def test_batch_bytes_on_host(hj):
     assert a >= hj.hj_workspace_bytes(q, 3 << 20, 1 << 20)
     jobs[1].d_count = None
     assert lib.hj_batch_bytes(3, jobs, None) == 0
+
+
+def test_noalloc_rejects_sizes_beyond_its_array(hj):
+    """hj_join_noalloc checks its fixed 64 MiB workspace against the sizes on the
+    host, before any device call (runs without a GPU; fake device pointers)."""
+    lib = hj.load()
+    p = hj.params("phj", 2, (6, 6))
+    R = hj.HjRel(256, 256, 1 << 24)
+    S = hj.HjRel(256, 256, 1 << 24)
+    O = hj.HjOut(256, 256, 1 << 24)
+    assert lib.hj_join_noalloc(ctypes.byref(p), ctypes.byref(R), ctypes.byref(S), ctypes.byref(O), 256,
+                               None) == hj.HJ_ERR_WORKSPACE
+    assert b"fixed" in lib.hj_last_error()
+    assert lib.hj_join_noalloc(None, ctypes.byref(R), ctypes.byref(S), ctypes.byref(O), 256,
+                               None) == hj.HJ_ERR_INVALID
+    assert hj.hj_workspace_bytes(p, 1 << 24, 1 << 24) > 64 << 20
