@@ -56,11 +56,11 @@ typedef enum hj_status {
     HJ_ERR_UNSUPPORTED = 5  /* a parameter combination this build does not implement */
 } hj_status;
 
-/* HJ_AUTO: the library picks PHJ parameters from |R| (no partitioning up to
-   4416 R tuples, else about 4096 R tuples per partition -- up to 5120 when
-   that takes more than 16 radix bits -- in one pass up to 10 radix bits, two
-   passes above); hash, tile, lds_cap and flags are kept.
-   hj_resolve_params shows the choice. */
+/* HJ_AUTO: the library evaluates its cost model (hj_model_seconds) for SHJ, for
+   PHJ without partitioning (|R| <= 8192), and for PHJ in one or two radix
+   passes around 4096 R tuples per partition with both partitioning tiles (one
+   tile when p->tile is set), and runs the plan with the least modelled time;
+   hash, lds_cap and flags are kept.  hj_resolve_params shows the choice. */
 typedef enum hj_algo { HJ_SHJ = 0, HJ_PHJ = 1, HJ_AUTO = 2 } hj_algo;
 
 /* Hash applied to a key before its radix bits are taken (Section 3.1 partitions
@@ -131,6 +131,17 @@ void hj_default_params(hj_params* p);
    lds_cap (and HJ_FLAG_ONE_PASS for passes == 0, which always writes its output
    in one pass).  Host only.  Returns HJ_ERR_INVALID for invalid parameters. */
 hj_status hj_resolve_params(const hj_params* p, uint64_t n_r, uint64_t n_s, hj_params* out);
+
+/* The cost model of Section 4 (Eq. 2-3) as calibrated on MI355X: the predicted
+   elapsed time of hj_join with parameters p (HJ_AUTO resolved first) for
+   |R| = n_r, |S| = n_s and `pairs` output pairs, in seconds.  Every kernel
+   launch of the plan is one step, timed as the delay of a dependent launch,
+   the kernel's ramp-up and drain, and the larger of its memory time
+   (algorithmic bytes over the bandwidth of its access pattern) and its
+   workgroup latency (rounds of resident workgroups times one workgroup's
+   duration).  Host only; the constants come from per-kernel timings of a grid
+   of joins on the device. */
+hj_status hj_model_seconds(const hj_params* p, uint64_t n_r, uint64_t n_s, uint64_t pairs, double* seconds);
 
 /* Bytes of device workspace hj_join needs for these parameters and sizes.
    Returns 0 if the parameters are invalid (hj_last_error() says why). */
@@ -335,6 +346,43 @@ hj_status hj_server_stats(hj_server* server, uint64_t* completed, uint64_t* reje
 
 /* Finishes the queued requests, stops the dispatcher and frees the server. */
 void hj_server_destroy(hj_server* server);
+
+/* ---- Relations in host memory, larger than the device ---------------------
+   The paper's joins of datasets beyond its zero-copy buffer (appendix "More
+   Experimental Results", "Large datasets that cannot fit into the zero copy
+   buffer"), as an external-memory hash join with device memory as the main
+   memory: R, then S, streams through the device in chunks that are split into
+   2^k partitions on k high bits of the key's MurmurHash 2.0 (the radix passes
+   of Algorithm 2) and copied back to host memory; the partitions of all chunks
+   are linked into partition pairs, and each pair is copied to the device and
+   joined with `p` (any hj_params, HJ_AUTO recommended); its pairs are copied to
+   the host output.  k is the smallest fan-out whose expected largest pair fits
+   the workspace (k = 0: no partition pass, the whole join runs on the device).
+   An S partition too large for the device with its R partition, or whose pairs
+   overflow the device output room, is joined in pieces against the whole R
+   partition.  Result as hj_join (multiset of pairs, count in *h_count,
+   HJ_ERR_CAPACITY when it exceeds out->capacity, nothing written past it).
+   R, S and out are HOST pointers (pinned memory from hipHostMalloc copies
+   asynchronously; pageable memory works, more slowly).  ws: device workspace
+   of at least 64 MiB, 256-byte aligned; its size bounds the device memory the
+   call uses.  Synchronous: returns when the output is in host memory.
+   Allocates a pinned host buffer of 8 (|R| + |S|) bytes for the partitions and
+   two streams for the call's duration; no device memory.  Returns
+   HJ_ERR_WORKSPACE when one R partition with its join does not fit the
+   workspace (a key with that many duplicates). */
+typedef struct hj_external_info {
+    uint32_t fanout_bits;   /* partitions of the out-of-core pass: 2^fanout_bits (0: none) */
+    uint32_t pieces;        /* device joins run (partition pairs, or pieces of them) */
+    uint64_t chunk_tuples;  /* tuples per chunk of the partition pass */
+    double partition_s;     /* wall time of the partition pass, copies included */
+    double join_s;          /* wall time of joining the partition pairs, copies included */
+    double total_s;         /* wall time of the call */
+    uint64_t h2d_bytes;     /* bytes copied host -> device */
+    uint64_t d2h_bytes;     /* bytes copied device -> host */
+} hj_external_info;
+
+hj_status hj_join_external(const hj_params* p, const hj_rel* R, const hj_rel* S, const hj_out* out, void* ws,
+                           size_t ws_bytes, uint64_t* h_count, hj_external_info* info);
 
 /* Device-side failures of an asynchronous call.  Every workspace handed to
    hj_join, hj_build, hj_probe, hj_batch_run or a server starts with an 8-byte

@@ -27,7 +27,7 @@ FLAGS = [
 ]
 
 LIBS = {
-    "libhj.so": ("csrc", ["scan.hip", "shj.hip", "phj_partition.hip", "phj_join.hip", "engine.cpp", "hj_api.cpp", "batch.cpp", "server.cpp", "noalloc.hip"]),
+    "libhj.so": ("csrc", ["scan.hip", "shj.hip", "phj_partition.hip", "phj_join.hip", "engine.cpp", "costmodel.cpp", "hj_api.cpp", "batch.cpp", "server.cpp", "external.cpp", "noalloc.hip"]),
     "libhjgen.so": ("gen", ["gen.hip"]),
 }
 

@@ -9,9 +9,8 @@
 //    engine) on one of kLanes streams; jobs go to lanes longest-first onto the
 //    least loaded lane, and each lane reuses one workspace slice sized for its
 //    largest job, so the workspace is bounded by the lanes, not the batch;
-//  * without explicit per-job parameters a size rule picks them (direct if
-//    |R| fits the LDS budget, else PHJ with about 4K R tuples per partition,
-//    one pass up to 6 radix bits, one-pass output).
+//  * without explicit per-job parameters HJ_AUTO picks them: the plan with the
+//    least time under the calibrated cost model (costmodel.cpp), one-pass output.
 // Running: the job table is copied from pinned host memory into the
 // workspace, lanes fork from the issuing stream through events and join back
 // to it.  The first run with a given workspace captures all of it (on a
@@ -73,11 +72,11 @@ struct hj_batch_plan {
 
 namespace {
 
-// The size rule (HJ_AUTO's) with one-pass output.
+// HJ_AUTO's plan (the cost model's choice) with one-pass output.
 void default_params(const hj_job& j, hj_params* p) {
     hj_default_params(p);
     p->flags = HJ_FLAG_ONE_PASS;
-    auto_params(j.R.n, p);
+    auto_params(j.R.n, j.S.n, p);
 }
 
 void free_plan(hj_batch_plan* b) {

@@ -90,32 +90,6 @@ uint32_t auto_lds_cap(uint64_t n_r, uint32_t P) {
     return cap;
 }
 
-void auto_params(uint64_t n_r, hj_params* p) {
-    p->algo = HJ_PHJ;
-    if (n_r <= kAutoDirectMax) {
-        p->passes = 0;
-        p->bits[0] = p->bits[1] = 0;
-        return;
-    }
-    uint32_t B = 0;
-    while (B < kMaxRadixBits && (n_r >> B) > 4096) ++B;
-    if (B > kAutoWideFromBits) {
-        // with this many bits the partitioning passes lose more than a bigger
-        // LDS table costs the join: allow up to 5120 R tuples per partition
-        B = 0;
-        while (B < kMaxRadixBits && (n_r >> B) > 5120) ++B;
-    }
-    if (B <= kAutoOnePassMaxBits) {
-        p->passes = 1;
-        p->bits[0] = B;
-        p->bits[1] = 0;
-    } else {
-        p->passes = 2;
-        p->bits[0] = (B + 1) / 2;
-        p->bits[1] = B / 2;
-    }
-}
-
 namespace {
 // The parameters a plan runs with, every size-dependent choice filled in.
 void fill_resolved(const hj_params* p, Plan* pl) {
@@ -136,7 +110,7 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
     if (!p) return fail(HJ_ERR_INVALID, "params is NULL");
     if (p->algo == HJ_AUTO) {
         hj_params q = *p;
-        auto_params(n_r, &q);
+        auto_params(n_r, n_s, &q);
         return check_params(&q, n_r, n_s, pl);
     }
     if (p->flags & ~HJ_FLAG_ONE_PASS) return fail(HJ_ERR_INVALID, "unknown flags 0x%x", p->flags);
@@ -219,11 +193,14 @@ struct PhjWs {
     uint64_t* wave_cnt;
     uint64_t* ovf_table;
     uint32_t* ovf_next;
+    hj::HeavyQueue* heavy;  // one-pass heavy-tuple queue (cleared with the scan states)
+    hj::HotKeys* hot;       // hot keys of the HBM-table build (cleared with the scan states)
     uint64_t* st1;     // scan states (cleared by the first kernel): pass-1 histogram,
     uint64_t* st2;     //   pass-2 histogram,
     uint64_t* stw;     //   per-wave match counts,
     uint64_t* stp;     //   join plan
-    uint64_t nzero;    // words from st1 on to clear
+    uint64_t* zero;    // the queue and the scan states, cleared by the first kernel
+    uint64_t nzero;    // words from `zero` on to clear
     uint64_t tiles1, tiles2_ub, items_ub, ovf_ub;
     size_t bytes;
 };
@@ -265,11 +242,17 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, v
     const uint64_t n2 = pl.passes == 2 ? hj::scan_state_words(w.tiles2_ub * pl.P2) : 0;
     const uint64_t nw = hj::scan_state_words(w.items_ub * hj::kJoinWaves);
     const uint64_t np = hj::plan_state_words(pl.P);
-    w.st1 = c.take<uint64_t>(n1 + n2 + nw + np);
+    static_assert(sizeof(hj::HotKeys) % sizeof(uint64_t) == 0, "hot keys in whole words");
+    const uint64_t nq = sizeof(hj::HeavyQueue) / sizeof(uint64_t) + sizeof(hj::HotKeys) / sizeof(uint64_t);
+    uint64_t* zero = c.take<uint64_t>(nq + n1 + n2 + nw + np);
+    w.heavy = reinterpret_cast<hj::HeavyQueue*>(zero);
+    w.hot = zero ? reinterpret_cast<hj::HotKeys*>(zero + sizeof(hj::HeavyQueue) / sizeof(uint64_t)) : nullptr;
+    w.st1 = zero ? zero + nq : nullptr;
     w.st2 = w.st1 + n1;
     w.stw = w.st2 + n2;
     w.stp = w.stw + nw;
-    w.nzero = n1 + n2 + nw + np;
+    w.zero = zero;
+    w.nzero = nq + n1 + n2 + nw + np;
     w.bytes = c.off;
     return w;
 }
@@ -280,16 +263,16 @@ struct ShjTableWs {
     uint64_t* table;
     uint32_t* next;
     hj::HotKeys* hot;
-    uint32_t log2_slots;
+    uint64_t nslots;
     size_t bytes;
 };
 
 ShjTableWs shj_table_layout(uint64_t n_r, void* base) {
     ShjTableWs w{};
     Carver c(base);
-    w.log2_slots = std::max<uint32_t>(1, ceil_log2(2 * std::max<uint64_t>(n_r, 1)));
+    w.nslots = hj::shj_slots(n_r);
     w.err = c.take<uint64_t>(1);
-    w.table = c.take<uint64_t>(1ull << w.log2_slots);
+    w.table = c.take<uint64_t>(w.nslots);
     w.next = c.take<uint32_t>(n_r);
     w.hot = c.take<hj::HotKeys>(1);
     w.bytes = c.off;
@@ -398,21 +381,21 @@ hj_status check_call(const hj_params* p, const hj_rel* R, const hj_rel* S, const
 
 // SHJ build (Algorithm 1, b1-b4): empty slots, then R inserted.
 void shj_build_table(const hj_rel& R, const ShjTableWs& t, hj::Recorder& rec) {
-    hj::shj_fill(t.table, 1ull << t.log2_slots, t.hot, rec);
-    hj::shj_build(R.key, R.n, t.table, t.next, t.log2_slots, t.hot, rec);
+    hj::shj_fill(t.table, t.nslots, t.hot, rec);
+    hj::shj_build(R.key, R.n, t.table, t.next, t.nslots, t.hot, rec);
 }
 
 // SHJ probe (Algorithm 1, p1-p4) of a table built over R.
 void shj_probe_table(const Plan& pl, const ShjTableWs& t, const hj_rel& R, const hj_rel& S,
                      const hj_out& out, const ShjProbeWs& w, uint64_t* d_count, hj::Recorder& rec) {
     if (!pl.one_pass) {
-        hj::shj_count(S.key, S.n, t.table, t.next, t.log2_slots, R.key, R.n, t.hot, w.wave_cnt, rec);
+        hj::shj_count(S.key, S.n, t.table, t.next, t.nslots, R.key, R.n, t.hot, w.wave_cnt, rec);
         hj::zero_words(w.st, w.nst, rec);
         hj::scan_u64(w.wave_cnt, w.wave_cnt, w.tiles * hj::kShjWavesPerBlock, w.st, d_count, rec);
     } else {
         hj::shj_zero_one_pass(d_count, w.heavy, rec);
     }
-    hj::shj_write(S.key, S.rid, S.n, t.table, t.next, t.log2_slots, R.key, R.rid, R.n, t.hot,
+    hj::shj_write(S.key, S.rid, S.n, t.table, t.next, t.nslots, R.key, R.rid, R.n, t.hot,
                   pl.one_pass ? nullptr : w.wave_cnt, d_count, pl.one_pass ? w.heavy : nullptr, out.rid_r,
                   out.rid_s, out.capacity, rec);
 }
@@ -434,7 +417,7 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
     const uint32_t n_r = (uint32_t)R.n, n_s = (uint32_t)S.n;
     const bool two = pl.passes == 2;
     const hj::Pass1 p1 = hj::make_pass1(R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, w.segs1, w.tb1,
-                                        w.st1, w.nzero, rec.err_clear);
+                                        w.zero, w.nzero, rec.err_clear);
     // the join plan rides on the last pass's scatter, the pass-2 setup on the first
     // The plan's records are written at offsets from its chained scan; its wait
     // keeps the full bound and no injected stall (every consumer of the other
@@ -478,15 +461,15 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
 void phj_join_pairs(const Plan& pl, const PhjWs& w, const int32_t* rk, const int32_t* rr, const int32_t* sk,
                     const int32_t* sr, const hj_out& out, uint64_t* d_count, hj::Recorder& rec) {
     hj::join_ovf_build(w.pairs, w.ovf_begin, w.ovf_part, pl.P, (uint32_t)w.ovf_ub, rk, w.ovf_table, w.ovf_next,
-                       rec);
+                       w.hot, pl.one_pass ? w.heavy : nullptr, rec);
     if (!pl.one_pass) {
         hj::join_count(w.pairs, w.item_begin, w.item_rec, pl.P, (uint32_t)w.items_ub, rk, sk, pl.lds_cap,
-                       w.ovf_table, w.ovf_next, w.wave_cnt, rec);
+                       w.ovf_table, w.ovf_next, w.hot, w.wave_cnt, rec);
         hj::scan_u64(w.wave_cnt, w.wave_cnt, w.items_ub * hj::kJoinWaves, w.stw, d_count, rec);
     }
     hj::join_write(w.pairs, w.item_begin, w.item_rec, pl.P, (uint32_t)w.items_ub, rk, rr, sk, sr, pl.lds_cap,
                    w.ovf_table, w.ovf_next, pl.one_pass ? nullptr : w.wave_cnt, d_count, out.rid_r, out.rid_s,
-                   out.capacity, rec);
+                   w.hot, out.capacity, pl.one_pass ? w.heavy : nullptr, rec);
 }
 
 void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,

@@ -33,22 +33,14 @@ struct Plan {
 // Most radix bits over all passes: 2^20 partitions keep ~4096 R tuples per
 // partition (one LDS table) up to |R| = 2^31 - 1.
 constexpr uint32_t kMaxRadixBits = 20;
-// HJ_AUTO: the largest |R| joined from one LDS table without partitioning
-// (the direct kernel then runs three workgroups per CU).
-constexpr uint32_t kAutoDirectMax = 4416;
-// Radix bits HJ_AUTO still takes in one pass (measured on MI355X against
-// |S| = 2^24: one pass of 8-10 bits with 8192-tuple tiles beats two passes by
-// 10-35%; from 11 bits two passes win).
-constexpr uint32_t kAutoOnePassMaxBits = 10;
-// Above this many radix bits HJ_AUTO takes partitions of up to 5120 R tuples
-// instead of 4096 (measured on MI355X: 300M x 300M 8% and 1.2G x 1.2G 10%
-// faster with one bit less; at 80M x 80M 1% slower, so only from 17 bits).
-constexpr uint32_t kAutoWideFromBits = 16;
-// The size rule of HJ_AUTO: PHJ with no partitioning up to kAutoDirectMax R
-// tuples, else about 4096 R tuples per partition (up to 5120 above
-// kAutoWideFromBits bits), in one pass up to kAutoOnePassMaxBits radix bits
-// and two passes above.  Keeps hash, tile, lds_cap and flags.
-void auto_params(uint64_t n_r, hj_params* p);
+// HJ_AUTO (costmodel.cpp): the plan with the least modelled time among SHJ,
+// the direct LDS join and PHJ in one or two radix passes (and both tiles when
+// p->tile is 0); keeps hash, lds_cap and flags.
+void auto_params(uint64_t n_r, uint64_t n_s, hj_params* p);
+
+// Struct Plan is below; the cost model of a plan (costmodel.cpp).
+struct Plan;
+double model_seconds(const Plan& pl, uint64_t n_r, uint64_t n_s, double pairs);
 
 // Default LDS table capacity for |R| = n_r split into P partitions.
 uint32_t auto_lds_cap(uint64_t n_r, uint32_t P);

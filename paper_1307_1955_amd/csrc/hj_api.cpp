@@ -219,6 +219,17 @@ hj_status hj_join_timed(const hj_params* p, const hj_rel* R, const hj_rel* S, co
     return st;
 }
 
+hj_status hj_model_seconds(const hj_params* p, uint64_t n_r, uint64_t n_s, uint64_t pairs, double* seconds) {
+    if (!seconds) return fail(HJ_ERR_INVALID, "seconds is NULL");
+    Plan pl;
+    const hj_status st = check_params(p, n_r, n_s, &pl);
+    if (st != HJ_OK) return st;
+    if (n_r > kMaxRows || n_s > kMaxRows) return fail(HJ_ERR_INVALID, "relations must have fewer than 2^31 tuples");
+    *seconds = model_seconds(pl, n_r, n_s, (double)pairs);
+    clear_error();
+    return HJ_OK;
+}
+
 hj_status hj_workspace_status(const void* ws, void* stream) {
     if (!ws || (uintptr_t)ws % kAlign) return fail(HJ_ERR_INVALID, "workspace must be non-NULL and 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;

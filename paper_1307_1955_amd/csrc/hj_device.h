@@ -78,11 +78,11 @@ __device__ __forceinline__ uint64_t chain_claim(uint64_t* table, uint64_t s, int
 }
 
 // Keys that a build workgroup pushed kHotRun or more times in one run (the
-// heavy keys of a skewed R), recorded by the SHJ build so that its probes can
-// hand such tuples over without walking their chains first.  rows[i] sums the
-// rows of key[i]'s recorded runs: a lower bound of its chain length (shorter
-// runs are not counted), so a probe may skip the walk only when that bound
-// alone exceeds its walk limit.  n may exceed kHotKeys; the keys beyond are
+// heavy keys of a skewed R), recorded by the SHJ build and the PHJ HBM-table
+// build so that their probes can hand such tuples over without walking their
+// chains first.  rows[i] sums the rows of key[i]'s recorded runs: a lower
+// bound of its chain length (shorter runs are not counted), so a probe may
+// skip the walk only when that bound alone exceeds its walk limit.  n may exceed kHotKeys; the keys beyond are
 // not recorded.  A key may hold two entries (two workgroups recording it at
 // once); each entry's rows stay a lower bound.
 constexpr uint32_t kHotKeys = 63;
@@ -108,6 +108,24 @@ __device__ __forceinline__ void record_hot(HotKeys* hot, int32_t key, uint32_t r
         atomicAdd(&hot->rows[idx], rows);
         __hip_atomic_store(&hot->valid[idx], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// The build's hot keys into LDS, for a probe that registers their tuples as
+// heavy without walking (needs a barrier before the arrays are read).
+__device__ __forceinline__ void load_hot(const HotKeys* hot, int32_t* hk, uint32_t* hr, uint32_t* nhk) {
+    const uint32_t n = min(hot->n, kHotKeys);
+    if (threadIdx.x == 0) *nhk = n;
+    if (threadIdx.x < n) {
+        hk[threadIdx.x] = hot->key[threadIdx.x];
+        hr[threadIdx.x] = hot->rows[threadIdx.x];
+    }
+}
+
+// Rows the build recorded for key q (0 if it is not among the hot keys).
+__device__ __forceinline__ uint32_t hot_rows_of(int32_t q, const int32_t* hk, const uint32_t* hr, uint32_t nhk) {
+    uint32_t rows = 0;
+    for (uint32_t i = 0; i < nhk; ++i) rows = hk[i] == q ? max(rows, hr[i]) : rows;
+    return rows;
 }
 
 // Pushes of duplicate keys by one wave.  A row is pushed in front of its key's

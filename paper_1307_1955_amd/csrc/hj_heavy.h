@@ -189,4 +189,151 @@ __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, con
     }
 }
 
+// ---- Heavy S tuples shared by all workgroups (one-pass output) ----
+// A workgroup hands the heavy tuples it registered to the queue (hand_off);
+// every workgroup, once its own work is written, runs help_heavy: for each
+// queued tuple it claims chunks of the tuple's R rows and writes its matches
+// in them, each
+// scan step reserving its slots on the running total (one-pass output has no
+// fixed order, so no count is needed first).  Nothing waits: a workgroup
+// takes what is unclaimed and leaves; the workgroup that queued a tuple runs
+// help_heavy too, so every chunk is written before the launch ends.
+
+// Moves this block's registered heavy tuples to the queue while it has room
+// (marked in hs->queued); a tuple that finds the queue full stays with the
+// block's own scan of R (heavy_counts / heavy_writes).  All threads call it
+// after the registrations.
+__device__ __forceinline__ void hand_off(HeavyQueue* Q, HeavySet* hs, uint32_t r_off, uint32_t r_len) {
+    __syncthreads();  // registrations done
+    const uint32_t ne = min(hs->n, kMaxHeavy);
+    if (threadIdx.x < ne) {
+        const uint32_t idx = atomicAdd(&Q->n, 1u);
+        if (idx < kHeavyJobs) {
+            HeavyJob* J = &Q->job[idx];
+            J->key = hs->key[threadIdx.x];
+            J->srid = hs->srid[threadIdx.x];
+            J->r_off = r_off;
+            J->r_len = r_len;
+            __hip_atomic_store(&J->valid, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            atomicOr(&hs->queued, 1u << threadIdx.x);
+        }
+    }
+}
+
+// A one-pass probe hands a tuple to the queue once its chain is longer than
+// this: a lane walking further would hold its workgroup past the others
+// (every step a dependent load), while a queued tuple costs one scan of R
+// shared by the workgroups that are still running.
+constexpr uint32_t kQueueWalk = 1024;
+
+// Claims the next chunk of a phase for the block (thread 0 takes it, LDS
+// broadcasts it).  sh: LDS scratch.
+__device__ __forceinline__ uint32_t claim_chunk(uint32_t* counter, uint32_t* sh) {
+    __syncthreads();  // sh free
+    if (threadIdx.x == 0) sh[0] = atomicAdd(counter, 1u);
+    __syncthreads();
+    return sh[0];
+}
+
+// rk, rr: the columns the queued tuples' R rows index (job rows r_off ..
+// r_off + r_len - 1).  sh: LDS scratch of 9 + kHeavyV * kBlock / 64 words.
+template <uint32_t kBlock>
+__device__ __forceinline__ void help_heavy(HeavyQueue* Q, const int32_t* __restrict__ rk,
+                                           const int32_t* __restrict__ rr,
+                                           unsigned long long* __restrict__ total, uint64_t capacity,
+                                           int32_t* __restrict__ out_r, int32_t* __restrict__ out_s, uint32_t* sh) {
+    constexpr uint32_t kWaves = kBlock / kWave;
+    constexpr uint32_t kV = kHeavyV;
+    static_assert(kHeavyJobs <= kBlock, "one thread per queued tuple looks for open work");
+    uint32_t* cnt = sh + 8;  // kV * kWaves per-wave hit counts of a step
+    const uint32_t w = threadIdx.x / kWave;
+    __syncthreads();
+    if (threadIdx.x == 0) sh[1] = min(__hip_atomic_load(&Q->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), kHeavyJobs);
+    __syncthreads();
+    const uint32_t nj = sh[1];
+    if (nj == 0) return;
+    while (true) {
+        // the lowest queued tuple that still has unclaimed chunks (one thread looks at each)
+        __syncthreads();
+        if (threadIdx.x == 0) sh[6] = ~0u;
+        __syncthreads();
+        // relaxed: a hint only (an acquire would drop cache lines that the
+        // running workgroups use at every look); the job taken is read after
+        // an acquire of its flag below
+        if (threadIdx.x < nj) {
+            HeavyJob* J = &Q->job[threadIdx.x];
+            if (__hip_atomic_load(&J->valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+                __hip_atomic_load(&J->write_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                    (J->r_len + kHelpChunk - 1) / kHelpChunk)
+                atomicMin(&sh[6], threadIdx.x);
+        }
+        __syncthreads();
+        const uint32_t e = sh[6];
+        if (e == ~0u) return;
+        HeavyJob* J = &Q->job[e];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            (void)__hip_atomic_load(&J->valid, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);  // orders the reads below
+            sh[2] = (uint32_t)J->key;
+            sh[3] = (uint32_t)J->srid;
+            sh[7] = J->r_off;
+            sh[8 + kV * kWaves] = J->r_len;
+        }
+        __syncthreads();
+        const int32_t k = (int32_t)sh[2], srid = (int32_t)sh[3];
+        const uint64_t r_off = sh[7], r_len = sh[8 + kV * kWaves];
+        const uint32_t nchunks = (uint32_t)((r_len + kHelpChunk - 1) / kHelpChunk);
+        while (true) {
+            const uint32_t c = claim_chunk(&J->write_next, sh);
+            if (c >= nchunks) break;
+            const uint64_t lo = r_off + (uint64_t)c * kHelpChunk, hi = r_off + min((uint64_t)(c + 1) * kHelpChunk, r_len);
+            for (uint64_t j0 = lo; j0 < hi; j0 += (uint64_t)kV * kBlock) {
+                // element u of the thread: row j0 + u * kBlock + threadIdx.x; rows
+                // past the chunk read its last row (all loads issue together) and
+                // do not count
+                int32_t v[kV];
+#pragma unroll
+                for (uint32_t u = 0; u < kV; ++u) v[u] = rk[min(j0 + (uint64_t)u * kBlock + threadIdx.x, hi - 1)];
+                uint32_t bits = 0;
+#pragma unroll
+                for (uint32_t u = 0; u < kV; ++u)
+                    bits |= (j0 + (uint64_t)u * kBlock + threadIdx.x < hi && v[u] == k) ? 1u << u : 0u;
+#pragma unroll
+                for (uint32_t u = 0; u < kV; ++u) {
+                    const uint32_t nh = (uint32_t)__popcll(__ballot((bits >> u) & 1u));
+                    if (lane_id() == 0) cnt[u * kWaves + w] = nh;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    uint32_t t = 0;
+                    for (uint32_t i = 0; i < kV * kWaves; ++i) t += cnt[i];
+                    const unsigned long long b = t ? atomicAdd(total, (unsigned long long)t) : 0ull;
+                    sh[4] = (uint32_t)b;
+                    sh[5] = (uint32_t)(b >> 32);
+                }
+                __syncthreads();
+                uint64_t base = (uint64_t)sh[4] | ((uint64_t)sh[5] << 32);
+                for (uint32_t u = 0; u < kV; ++u) {
+                    uint32_t before = 0, all = 0;
+                    for (uint32_t i = 0; i < kWaves; ++i) {
+                        const uint32_t t = cnt[u * kWaves + i];
+                        before += i < w ? t : 0u;
+                        all += t;
+                    }
+                    const uint64_t mk = __ballot((bits >> u) & 1u);
+                    if ((bits >> u) & 1u) {
+                        const uint64_t at = base + before + (uint32_t)__popcll(mk & lanemask_lt());
+                        if (at < capacity) {
+                            out_r[at] = rr[j0 + (uint64_t)u * kBlock + threadIdx.x];
+                            out_s[at] = srid;
+                        }
+                    }
+                    base += all;
+                }
+                __syncthreads();  // cnt and sh reused
+            }
+        }
+    }
+}
+
 }  // namespace hj

@@ -82,27 +82,42 @@ void zero_pair(uint64_t* a, uint64_t* b, Recorder& rec);
 constexpr uint32_t kShjBlock = 256;
 constexpr uint32_t kShjTile = 2048;  // S tuples per probe tile
 constexpr uint32_t kShjWavesPerBlock = kShjBlock / 64;
+// Slots of the SHJ table per R row (linear probing, load factor 1 / this).
+constexpr double kShjSlotsPerRow = 2.0;
+// Slots of the SHJ table over n_r rows: kShjSlotsPerRow per row, rounded up to
+// whole 128-byte lines.
+inline uint64_t shj_slots(uint64_t n_r) {
+    const uint64_t s = (uint64_t)(kShjSlotsPerRow * (double)(n_r < 1 ? 1 : n_r) + 0.999999);
+    return (s + 15) / 16 * 16;
+}
 struct HotKeys;  // keys the build saw in long push runs (hj_device.h)
 // Fills the table with empty slots, clears the hot-key record and the call's
 // error word (rec.err_clear).
 void shj_fill(uint64_t* table, uint64_t nslots, HotKeys* hot, Recorder& rec);
-void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint32_t log2_slots,
+void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint64_t nslots,
                HotKeys* hot, Recorder& rec);
-// Heavy S tuples of a one-pass SHJ probe are handed to a device-wide queue:
-// any workgroup that has finished its own tile claims chunks of R and writes
-// their matches (one 64-byte record per tuple; the queue is zeroed before each
-// probe).
+// Heavy S tuples of a one-pass probe (SHJ, and the HBM-table partitions of
+// PHJ) are handed to a device-wide queue: any workgroup that has finished its
+// own work claims chunks of the tuple's R rows and writes their matches (one
+// 64-byte record per tuple; the queue is zeroed before each probe).
 constexpr uint32_t kHeavyJobs = 256;
 constexpr uint32_t kHelpChunk = 1u << 16;  // R rows per claimed chunk
 struct HeavyJob {
     int32_t key, srid;
-    uint32_t valid;        // 1 once key and srid are written
+    uint32_t valid;        // 1 once the fields below are written
     uint32_t write_next;   // next chunk to claim
-    uint32_t pad[12];
+    uint32_t r_off, r_len; // the R rows that hold the tuple's matches (SHJ: all of R)
+    uint32_t pad[10];
 };
 struct HeavyQueue {
     uint32_t n;            // tuples handed in (may exceed kHeavyJobs: the rest stay with their workgroup)
-    uint32_t pad[15];
+    // PHJ one-pass write: set by the HBM-table build when a partition can hand
+    // tuples in; the write's workgroups then claim their items from item_next
+    // and, with none left, help the queue until items_done reaches the count
+    uint32_t wait;
+    uint32_t item_next;
+    uint32_t items_done;
+    uint32_t pad[12];
     HeavyJob job[kHeavyJobs];
 };
 static_assert(sizeof(HeavyJob) == 64 && sizeof(HeavyQueue) % 8 == 0, "queue layout");
@@ -114,10 +129,10 @@ void shj_zero_one_pass(uint64_t* d_count, HeavyQueue* q, Recorder& rec);
 // table was built from) for keys with long chains.  shj_count also clears the
 // call's error word (rec.err_clear): it runs before the count scan.
 void shj_count(const int32_t* s_key, uint64_t n_s, const uint64_t* table, const uint32_t* next,
-               uint32_t log2_slots, const int32_t* r_key, uint64_t n_r, const HotKeys* hot, uint64_t* wave_cnt,
+               uint64_t nslots, const int32_t* r_key, uint64_t n_r, const HotKeys* hot, uint64_t* wave_cnt,
                Recorder& rec);
 void shj_write(const int32_t* s_key, const int32_t* s_rid, uint64_t n_s, const uint64_t* table,
-               const uint32_t* next, uint32_t log2_slots, const int32_t* r_key, const int32_t* r_rid,
+               const uint32_t* next, uint64_t nslots, const int32_t* r_key, const int32_t* r_rid,
                uint64_t n_r, const HotKeys* hot, const uint64_t* wave_base, uint64_t* total, HeavyQueue* heavy,
                int32_t* out_r, int32_t* out_s, uint64_t capacity,
                Recorder& rec);  // wave_base == nullptr: one-pass output into *total
@@ -171,6 +186,10 @@ void part_hist_pass1(const Pass1& p1, const PassCfg& cfg, uint32_t* hist, Record
 // every tile (nullptr: binary search over tile_begin).
 void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                uint32_t grid, const PassCfg& cfg, uint32_t* hist, Recorder& rec);
+// Partition boundaries of a one-segment pass (R only, segment at position 0):
+// starts[p] for p < 2^bits from the pass's histogram scan, starts[2^bits] = n.
+void part_starts(const uint32_t* hist_scan, uint32_t ntiles, uint32_t bits, uint32_t n, uint32_t* starts,
+                 Recorder& rec);
 // `side`: extra workgroups appended to the grid that run the next step's setup
 // (hj_side.h: the pass-2 segment table or the join plan).
 struct SideJob;
@@ -183,6 +202,16 @@ constexpr uint32_t kJoinBlock = 512;
 constexpr uint32_t kJoinWaves = kJoinBlock / 64;
 constexpr uint32_t kJoinSub = 4608;     // S tuples per probe round of a work item (9 per lane)
 constexpr uint32_t kJoinChunk = 2 * kJoinSub;  // S tuples per work item (probed kJoinSub at a time)
+// R tuples per HBM-table build item: 8 rounds of a workgroup, or 64 in a
+// partition of more than kOvfBigPart tuples.  Small items keep the build's
+// latency low; in a large partition, which is large because a key is heavy as
+// often as not, each item's pushes of that key end in one exchange on its
+// slot, and those exchanges serialize.
+constexpr uint32_t kOvfChunk = 2048;
+constexpr uint32_t kOvfChunkBig = 16384;
+constexpr uint32_t kOvfBigPart = 1u << 16;
+constexpr uint32_t kOvfGrid = 2048;  // workgroups of the HBM-table build launches (8 per CU)
+__host__ __device__ inline uint32_t ovf_chunk(uint32_t r_len) { return r_len > kOvfBigPart ? kOvfChunkBig : kOvfChunk; }
 constexpr uint32_t kMaxLdsCap = 8192;   // largest R partition held in LDS
 // R tuples per thread of the LDS build (a kernel template argument: the build
 // keeps them in registers), by lds_cap class.
@@ -207,21 +236,27 @@ uint32_t join_grid(uint32_t P, uint64_t n_s);
 // Dynamic LDS bytes of the join kernels for a given lds_cap.
 size_t join_lds_bytes(uint32_t lds_cap, bool write);
 size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile);
+// hot: where the build records its hot keys (zeroed before); heavy: the
+// one-pass queue (nullptr for count -> scan -> write), whose `wait` it sets.
 void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint32_t* ovf_part, uint32_t P,
-                    uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, Recorder& rec);
+                    uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, HotKeys* hot,
+                    HeavyQueue* heavy, Recorder& rec);
 // item_begin/item_rec come from the join plan (JoinPlanOut).
 void join_count(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
-                const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec);
+                const uint32_t* ovf_next, const HotKeys* hot, uint64_t* wave_cnt, Recorder& rec);
 void join_write(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                 uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
                 const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
-                uint64_t capacity, Recorder& rec);
+                const HotKeys* hot, uint64_t capacity, HeavyQueue* heavy, Recorder& rec);
 // wave_base == nullptr selects the one-pass write: `total` must be zero on entry
-// and ends as the number of pairs.
+// and ends as the number of pairs; `heavy` (one-pass only, zeroed before the
+// HBM-table build, or nullptr) takes the heavy S tuples of HBM-table
+// partitions that span several kHelpChunk-row chunks.  `hot`: the keys the
+// HBM-table build recorded (their S tuples skip the chain walk).
 // Writes zero to *d_count (joins with an empty side) and clears the call's
 // error word (rec.err_clear).
 void write_zero_count(uint64_t* d_count, Recorder& rec);

@@ -11,7 +11,6 @@
 
 namespace hj {
 
-constexpr uint32_t kOvfChunk = 16384;  // R tuples per HBM-table build item (a heavy key: one exchange each)
 constexpr uint32_t kMaxPlanWaves = 16;  // waves of the largest workgroup that runs the join plan
 
 // Everything the pass-2 setup reads and writes.
@@ -77,7 +76,8 @@ __device__ __forceinline__ uint32_t items_of(const PartPair& pp) {
 }
 
 __device__ __forceinline__ uint32_t ovf_chunks_of(const PartPair& pp, uint32_t lds_cap) {
-    return (pp.r_len > lds_cap && pp.s_len) ? (pp.r_len + kOvfChunk - 1) / kOvfChunk : 0u;
+    const uint32_t chunk = ovf_chunk(pp.r_len);
+    return (pp.r_len > lds_cap && pp.s_len) ? (pp.r_len + chunk - 1) / chunk : 0u;
 }
 
 // Plan (one thread per partition pair, workgroups in ticket order): ranges of

@@ -28,7 +28,6 @@ namespace hj {
 
 namespace {
 
-constexpr uint32_t kOvfGrid = 1024;                   // workgroups of the HBM-table build launches
 constexpr uint32_t kSubJ = kJoinSub / kJoinWaves;     // S tuples per wave of a probe round
 
 __device__ __forceinline__ uint64_t region_slot(int32_t key, uint32_t H) {
@@ -46,8 +45,9 @@ __global__ void __launch_bounds__(256) k_ovf_clear(const PartPair* __restrict__ 
         const PartPair pp = pairs[i];
         uint64_t* region = ovf_table + 2ull * pp.r_off;
         const uint64_t H = 2ull * pp.r_len;
-        const uint64_t end = min(2ull * (c + 1) * kOvfChunk, H);
-        for (uint64_t x = 2ull * c * kOvfChunk + threadIdx.x; x < end; x += blockDim.x) region[x] = kEmptySlot;
+        const uint32_t chunk = ovf_chunk(pp.r_len);
+        const uint64_t end = min(2ull * (c + 1) * chunk, H);
+        for (uint64_t x = 2ull * c * chunk + threadIdx.x; x < end; x += blockDim.x) region[x] = kEmptySlot;
     }
 }
 
@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ 
                                                   const uint32_t* __restrict__ ovf_part, uint32_t P,
                                                   const int32_t* __restrict__ rk,
                                                   uint64_t* __restrict__ ovf_table,
-                                                  uint32_t* __restrict__ ovf_next) {
+                                                  uint32_t* __restrict__ ovf_next, HotKeys* hot,
+                                                  HeavyQueue* heavy) {
     constexpr uint32_t kWaves = 256 / kWave;
     __shared__ WavePush::Run runs[kWaves];
     const uint32_t nitems = ovf_begin[P];
@@ -72,9 +73,13 @@ __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ 
         uint64_t* region = ovf_table + 2ull * pp.r_off;
         uint32_t* next = ovf_next + pp.r_off;
         const RegionStep step{2u * pp.r_len};
-        const uint32_t end = min((c + 1) * kOvfChunk, pp.r_len);
+        const uint32_t chunk = ovf_chunk(pp.r_len);
+        const uint32_t end = min((c + 1) * chunk, pp.r_len);
+        // a partition the one-pass write may queue tuples of: its workgroups stay to help
+        if (heavy && c == 0 && threadIdx.x == 0 && pp.r_len > kHelpChunk) heavy->wait = 1;
         WavePush push;
-        for (uint32_t j0 = c * kOvfChunk; j0 < end; j0 += blockDim.x) {  // uniform trip count
+        push.hot_keys = hot;
+        for (uint32_t j0 = c * chunk; j0 < end; j0 += blockDim.x) {  // uniform trip count
             const uint32_t j = j0 + threadIdx.x;
             int32_t k = 0;
             uint64_t s = kClaimed;
@@ -231,16 +236,24 @@ __device__ __forceinline__ void probe_lds(const LdsView& v, uint32_t log2H, cons
     }
 }
 
+// LDS of a work item whose R partition has an HBM table: the heavy set of a
+// probe round and the hot keys the table's build recorded.
+struct HbmLds {
+    HeavySet hs;
+    int32_t hk[kHotKeys];
+    uint32_t hr[kHotKeys];
+    uint32_t nhk;
+};
+
 // Matches of the lane's kSU S keys in the partition-local HBM table (H = 2
-// r_len slots).  A key with a chain longer than heavy_limit(r_len) is
-// registered in `hs` (c[u] = kHeavyBit | its index) when there is room, else
-// counted by walking.
-// hs->n must be zero and visible to the block before the call.
+// r_len slots).  A key with a chain longer than lim is registered in `hs`
+// (c[u] = kHeavyBit | its index) when there is room, else counted by walking;
+// a hot key whose recorded rows alone exceed lim is registered without the
+// walk.  hs->n must be zero and visible to the block before the call.
 __device__ __forceinline__ void probe_hbm(const uint64_t* __restrict__ region, const uint32_t* __restrict__ next,
-                                          uint32_t H, const int32_t* q, const int32_t* qr, uint32_t wb,
-                                          uint32_t we, uint32_t* c, uint32_t* at, HeavySet* hs) {
+                                          uint32_t H, uint32_t lim, const int32_t* q, const int32_t* qr, uint32_t wb,
+                                          uint32_t we, uint32_t* c, uint32_t* at, HbmLds* sh) {
     const RegionStep step{H};
-    const uint32_t lim = heavy_limit(H / 2);
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
         c[u] = 0;
@@ -248,7 +261,9 @@ __device__ __forceinline__ void probe_hbm(const uint64_t* __restrict__ region, c
         if (wb + u * kWave + lane_id() < we) {
             at[u] = chain_find(region, region_slot(q[u], H), q[u], step);
             if (at[u] != kNotFound) {
-                c[u] = heavy_or_len(next, at[u], lim, q[u], qr ? qr[u] : 0, hs);
+                const uint32_t hot = (at[u] & kLast) ? 0u : hot_rows_of(q[u], sh->hk, sh->hr, sh->nhk);
+                c[u] = hot > lim ? register_heavy(next, at[u], q[u], qr ? qr[u] : 0, &sh->hs)
+                                 : heavy_or_len(next, at[u], lim, q[u], qr ? qr[u] : 0, &sh->hs);
             }
         }
     }
@@ -395,16 +410,20 @@ __device__ __forceinline__ uint64_t write_round_hbm(const uint32_t* __restrict__
 __device__ __forceinline__ uint64_t join_count_hbm(const ItemLoc L, uint32_t w, const int32_t* __restrict__ rk,
                                                    const int32_t* __restrict__ skp,
                                                    const uint64_t* __restrict__ ovf_table,
-                                                   const uint32_t* __restrict__ ovf_next, HeavySet* hs) {
+                                                   const uint32_t* __restrict__ ovf_next, const HotKeys* hot,
+                                                   HbmLds* sh) {
+    HeavySet* hs = &sh->hs;
     uint64_t cnt = 0;
     int32_t q[kSU];
+    load_hot(hot, sh->hk, sh->hr, &sh->nhk);  // read after the round's barrier
     for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
         const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
         load_s<false>(skp, nullptr, wb, we, q, nullptr);
         if (threadIdx.x == 0) hs->n = 0;
         __syncthreads();
         uint32_t c[kSU], at[kSU];
-        probe_hbm(ovf_table + 2ull * L.r_off, ovf_next + L.r_off, 2u * L.r_len, q, nullptr, wb, we, c, at, hs);
+        probe_hbm(ovf_table + 2ull * L.r_off, ovf_next + L.r_off, 2u * L.r_len, heavy_limit(L.r_len), q, nullptr, wb,
+                  we, c, at, sh);
         heavy_counts<kJoinBlock, kHeavyV>(rk + L.r_off, L.r_len, hs);
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) cnt += is_heavy(c[u]) ? hs->cnt[c[u] & ~kHeavyBit] : c[u];
@@ -421,6 +440,7 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
                                                           const int32_t* __restrict__ sk, uint32_t lds_cap,
                                                           const uint64_t* __restrict__ ovf_table,
                                                           const uint32_t* __restrict__ ovf_next,
+                                                          const HotKeys* __restrict__ hot,
                                                           uint64_t* __restrict__ wave_cnt) {
     extern __shared__ uint32_t lds[];
     const uint32_t w = threadIdx.x / kWave;
@@ -448,31 +468,42 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
             cnt += lane_pairs_lds(cf);
         }
     } else {
-        cnt = join_count_hbm(L, w, rk, skp, ovf_table, ovf_next, reinterpret_cast<HeavySet*>(lds));
+        cnt = join_count_hbm(L, w, rk, skp, ovf_table, ovf_next, hot, reinterpret_cast<HbmLds*>(lds));
     }
     cnt = wave_sum(cnt);
     if (lane == 0) wave_cnt[(uint64_t)L.item * kJoinWaves + w] = cnt;
 }
 
 // Write pass over a partition whose R exceeds the LDS table (see
-// join_count_hbm).
+// join_count_hbm).  One-pass output with `heavy`: a heavy S tuple of a
+// partition that spans more than one kHelpChunk-row chunk is registered after
+// a walk of at most kQueueWalk rows (none for a recorded hot key) and handed
+// to the device-wide queue, whose chunks every workgroup of the launch helps
+// write (help_heavy); tuples the queue has no room for stay with this
+// workgroup's own scans.
 template <bool kOnePass>
 __device__ __forceinline__ void join_write_hbm(
     const ItemLoc L, uint32_t w, const int32_t* __restrict__ rk, const int32_t* __restrict__ rrp,
     const int32_t* __restrict__ skp, const int32_t* __restrict__ srp, const uint64_t* __restrict__ ovf_table,
-    const uint32_t* __restrict__ ovf_next, uint64_t base, unsigned long long* __restrict__ total, uint64_t* wtot,
-    int32_t* __restrict__ out_r, int32_t* __restrict__ out_s, uint64_t capacity, HeavySet* hs) {
+    const uint32_t* __restrict__ ovf_next, const HotKeys* hot, uint64_t base, unsigned long long* __restrict__ total,
+    uint64_t* wtot, int32_t* __restrict__ out_r, int32_t* __restrict__ out_s, uint64_t capacity, HbmLds* sh,
+    HeavyQueue* heavy) {
+    HeavySet* hs = &sh->hs;
     const uint64_t* __restrict__ region = ovf_table + 2ull * L.r_off;
     const uint32_t* __restrict__ next = ovf_next + L.r_off;
+    const bool queue = kOnePass && heavy && L.r_len > kHelpChunk;  // uniform
+    const uint32_t lim = queue ? min(heavy_limit(L.r_len), kQueueWalk) : heavy_limit(L.r_len);
     int32_t q[kSU], qr[kSU];
+    load_hot(hot, sh->hk, sh->hr, &sh->nhk);  // read after the round's barrier
     for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
         const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
         load_s<true>(skp, srp, wb, we, q, qr);
-        if (threadIdx.x == 0) hs->n = 0;
+        if (threadIdx.x == 0) hs->n = hs->queued = 0;
         __syncthreads();
         uint32_t c[kSU], at[kSU];
-        probe_hbm(region, next, 2u * L.r_len, q, qr, wb, we, c, at, hs);
-        heavy_counts<kJoinBlock, kHeavyV>(rk + L.r_off, L.r_len, hs);
+        probe_hbm(region, next, 2u * L.r_len, lim, q, qr, wb, we, c, at, sh);
+        if (queue) hand_off(heavy, hs, L.r_off, L.r_len);
+        heavy_counts<kJoinBlock, kHeavyV, kOnePass>(rk + L.r_off, L.r_len, hs);
         uint64_t mine = 0;
 #pragma unroll
         for (uint32_t u = 0; u < kSU; ++u) mine += is_heavy(c[u]) ? hs->cnt[c[u] & ~kHeavyBit] : c[u];
@@ -483,27 +514,19 @@ __device__ __forceinline__ void join_write_hbm(
     }
 }
 
-// Write pass.  kOnePass: instead of reading a scanned per-wave offset, each
-// probe round reserves its pairs' output slots with block_reserve.
+// The pairs of one work item (R_i in an LDS table, or its HBM table).
 template <bool kOnePass, uint32_t RPT>
-__global__ void __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(RPT > kRptMid ? 4 : 6)))
-k_join_write(
-    const PartPair* __restrict__ pairs, const uint32_t* __restrict__ item_begin,
-    const ItemRec* __restrict__ item_rec, uint32_t P, const int32_t* __restrict__ rk,
-    const int32_t* __restrict__ rr, const int32_t* __restrict__ sk, const int32_t* __restrict__ sr,
-    uint32_t lds_cap, const uint64_t* __restrict__ ovf_table,
-    const uint32_t* __restrict__ ovf_next, const uint64_t* __restrict__ wave_base,
-    unsigned long long* __restrict__ total, int32_t* __restrict__ out_r, int32_t* __restrict__ out_s,
-    uint64_t capacity) {
-    extern __shared__ uint32_t lds[];
-    __shared__ uint64_t wtot[kJoinWaves + 1];
-    const uint32_t w = threadIdx.x / kWave;
-    const ItemLoc L = locate_item(item_begin, item_rec, P);
-    if (!L.live) return;
+__device__ __forceinline__ void write_item(const ItemLoc L, uint32_t w, uint32_t* lds, uint64_t* wtot,
+                                           const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
+                                           const int32_t* __restrict__ sk, const int32_t* __restrict__ sr,
+                                           uint32_t lds_cap, const uint64_t* __restrict__ ovf_table,
+                                           const uint32_t* __restrict__ ovf_next, const HotKeys* hot,
+                                           uint64_t base, unsigned long long* __restrict__ total,
+                                           int32_t* __restrict__ out_r, int32_t* __restrict__ out_s,
+                                           uint64_t capacity, HeavyQueue* heavy) {
     const int32_t* __restrict__ rrp = rr + L.r_off;
     const int32_t* __restrict__ skp = sk + L.s_begin;
     const int32_t* __restrict__ srp = sr + L.s_begin;
-    uint64_t base = kOnePass ? 0ull : wave_base[(uint64_t)L.item * kJoinWaves + w];
     int32_t q[kSU], qr[kSU];
     if (L.r_len <= lds_cap) {
         int32_t k[RPT];
@@ -523,8 +546,93 @@ k_join_write(
             base = write_round_lds(v, rrp, q, qr, cf, rid0, pos0, capacity, out_r, out_s);
         }
     } else {
-        join_write_hbm<kOnePass>(L, w, rk, rrp, skp, srp, ovf_table, ovf_next, base, total, wtot, out_r, out_s,
-                                 capacity, reinterpret_cast<HeavySet*>(lds));
+        join_write_hbm<kOnePass>(L, w, rk, rrp, skp, srp, ovf_table, ovf_next, hot, base, total, wtot, out_r,
+                                 out_s, capacity, reinterpret_cast<HbmLds*>(lds), heavy);
+    }
+}
+
+// Workgroups of a one-pass write beyond its items that help with queued heavy
+// tuples until every item is done (when a partition may queue tuples), and
+// the polls of the item count after which such a workgroup leaves anyway (its
+// help is only a speed-up: every queued chunk is also taken by the workgroup
+// that queued it).
+constexpr uint32_t kWaitHelpers = 256;
+constexpr uint32_t kHelpWaitPolls = 1u << 20;
+
+// Write pass.  kOnePass: instead of reading a scanned per-wave offset, each
+// probe round reserves its pairs' output slots with block_reserve.  One-pass
+// with `heavy` (the grid then has kWaitHelpers workgroups beyond the items'
+// bound): every workgroup helps with the queued heavy tuples once its own item
+// is written.  When the HBM-table build set heavy->wait (a partition may queue
+// tuples), each workgroup takes its item by ticket (the order the workgroups
+// start in) instead of by its index, and the workgroups whose tickets are past
+// the last item keep helping until every item is done, so that a tuple queued
+// by the last items still finds helpers.
+template <bool kOnePass, uint32_t RPT>
+__global__ void __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(RPT > kRptMid ? 4 : 6)))
+k_join_write(
+    const PartPair* __restrict__ pairs, const uint32_t* __restrict__ item_begin,
+    const ItemRec* __restrict__ item_rec, uint32_t P, const int32_t* __restrict__ rk,
+    const int32_t* __restrict__ rr, const int32_t* __restrict__ sk, const int32_t* __restrict__ sr,
+    uint32_t lds_cap, const uint64_t* __restrict__ ovf_table,
+    const uint32_t* __restrict__ ovf_next, const HotKeys* __restrict__ hot, const uint64_t* __restrict__ wave_base,
+    unsigned long long* __restrict__ total, int32_t* __restrict__ out_r, int32_t* __restrict__ out_s,
+    uint64_t capacity, HeavyQueue* heavy) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint64_t wtot[kJoinWaves + 1];
+    __shared__ uint32_t s_word;
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t live = item_begin[P];
+    const bool claim = kOnePass && heavy && heavy->wait;  // written by an earlier launch: uniform
+    uint32_t item;
+    if (claim) {
+        if (threadIdx.x == 0) s_word = atomicAdd(&heavy->item_next, 1u);
+        __syncthreads();
+        item = s_word;
+    } else {
+        item = live_remap(blockIdx.x, live);
+        if (item >= live) return;
+    }
+    if (item < live) {
+        const ItemRec r = item_rec[item];
+        ItemLoc L;
+        L.item = item;
+        L.live = true;
+        L.r_off = r.r_off;
+        L.r_len = r.r_len;
+        L.s_begin = r.s_begin;
+        L.s_n = r.s_n;
+        const uint64_t base = kOnePass ? 0ull : wave_base[(uint64_t)item * kJoinWaves + w];
+        write_item<kOnePass, RPT>(L, w, lds, wtot, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, hot, base, total,
+                                  out_r, out_s, capacity, heavy);
+        if (claim) {
+            __syncthreads();  // the item's hand-offs are made
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_add(&heavy->items_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // one-pass: help with the heavy tuples any workgroup queued (the LDS
+    // tables are free now and give the scratch); with tickets, the first
+    // kWaitHelpers workgroups past the last item keep helping until every item
+    // is done.  Only those wait: their tickets come after every item's, so
+    // every item is then held by a workgroup that is running, while a
+    // workgroup that waited after its own item could keep one that has not
+    // started off the device.
+    if (kOnePass && heavy) {
+        const bool wait = claim && item >= live && item - live < kWaitHelpers;
+        for (uint32_t polls = 0;; ++polls) {
+            bool all_done = true;
+            if (wait) {
+                __syncthreads();  // s_word free
+                if (threadIdx.x == 0)  // relaxed: the queue's own flags order what is read from it
+                    s_word = __hip_atomic_load(&heavy->items_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                all_done = s_word >= live;
+            }
+            help_heavy<kJoinBlock>(heavy, rk, rr, total, capacity, out_r, out_s, lds);
+            if (all_done || polls >= kHelpWaitPolls) break;
+            __builtin_amdgcn_s_sleep(32);
+        }
     }
 }
 
@@ -592,8 +700,8 @@ __global__ void k_write_zero(uint64_t* p, uint64_t* err_clear) {
 }  // namespace
 
 size_t join_lds_bytes(uint32_t lds_cap, bool /*write*/) {
-    static_assert(sizeof(HeavySet) <= sizeof(uint32_t) * (256 + 2 * kWave) + sizeof(uint64_t) * 256,
-                  "the heavy-key set fits the smallest table area");
+    static_assert(sizeof(HbmLds) <= sizeof(uint32_t) * (256 + 2 * kWave) + sizeof(uint64_t) * 256,
+                  "the heavy-key set and the hot keys fit the smallest table area");
     return sizeof(uint32_t) * ((size_t)lds_cap + 2 * kWave) + sizeof(uint64_t) * lds_cap;
 }
 
@@ -646,7 +754,7 @@ void write_zero_count(uint64_t* d_count, Recorder& rec) {
 size_t plan_state_words(uint32_t P) { return 1 + plan_blocks(P, kMinPartBlock); }
 
 uint32_t ovf_grid(uint32_t P, uint64_t n_r) {
-    return (uint32_t)(P + (n_r + kOvfChunk - 1) / kOvfChunk);
+    return (uint32_t)(P + (n_r + kOvfChunk - 1) / kOvfChunk);  // the smaller chunk bounds both
 }
 
 uint32_t join_grid(uint32_t P, uint64_t n_s) {
@@ -654,7 +762,8 @@ uint32_t join_grid(uint32_t P, uint64_t n_s) {
 }
 
 void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint32_t* ovf_part, uint32_t P,
-                    uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, Recorder& rec) {
+                    uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, HotKeys* hot,
+                    HeavyQueue* heavy, Recorder& rec) {
     if (grid == 0) return;
     grid = grid < kOvfGrid ? grid : kOvfGrid;  // grid-stride: few chunks in the common case
     rec.before("ovf_clear");
@@ -663,39 +772,39 @@ void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint
     rec.after();
     rec.before("ovf_build");
     hipLaunchKernelGGL(k_ovf_build, dim3(grid), dim3(256), 0, rec.stream, pairs, ovf_begin, ovf_part, P, rk,
-                       ovf_table, ovf_next);
+                       ovf_table, ovf_next, hot, heavy);
     rec.after();
 }
 
 template <uint32_t RPT>
 void join_count_t(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
-                  uint32_t grid, const int32_t* rk, const int32_t* sk, uint32_t lds_cap,
-                  const uint64_t* ovf_table, const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec) {
+                  uint32_t grid, const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
+                  const uint32_t* ovf_next, const HotKeys* hot, uint64_t* wave_cnt, Recorder& rec) {
     const size_t lds = join_lds_bytes(lds_cap, false);
     allow_lds((const void*)k_join_count<RPT>, lds);
     rec.before("join_count");
     hipLaunchKernelGGL(k_join_count<RPT>, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin,
-                       item_rec, P, rk, sk, lds_cap, ovf_table, ovf_next, wave_cnt);
+                       item_rec, P, rk, sk, lds_cap, ovf_table, ovf_next, hot, wave_cnt);
     rec.after();
 }
 
 void join_count(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
-                const uint32_t* ovf_next, uint64_t* wave_cnt, Recorder& rec) {
+                const uint32_t* ovf_next, const HotKeys* hot, uint64_t* wave_cnt, Recorder& rec) {
     if (grid == 0) return;
     switch (join_rpt(lds_cap)) {
         case kRptSmall:
             join_count_t<kRptSmall>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
-                                    wave_cnt, rec);
+                                    hot, wave_cnt, rec);
             break;
         case kRptMid:
             join_count_t<kRptMid>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
-                                  wave_cnt, rec);
+                                  hot, wave_cnt, rec);
             break;
         default:
             join_count_t<kRptLarge>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
-                                    wave_cnt, rec);
+                                    hot, wave_cnt, rec);
             break;
     }
 }
@@ -703,36 +812,37 @@ void join_count(const PartPair* pairs, const uint32_t* item_begin, const ItemRec
 template <bool kOnePass, uint32_t RPT>
 void join_write_t(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                   uint32_t grid, const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
-                  uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
+                  uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next, const HotKeys* hot,
                   const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s, uint64_t capacity,
-                  Recorder& rec) {
+                  HeavyQueue* heavy, Recorder& rec) {
     const size_t lds = join_lds_bytes(lds_cap, true);
     allow_lds((const void*)k_join_write<kOnePass, RPT>, lds);
     rec.before(kOnePass ? "join_write_1pass" : "join_write");
+    if (kOnePass && heavy) grid += kWaitHelpers;
     hipLaunchKernelGGL((k_join_write<kOnePass, RPT>), dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs,
-                       item_begin, item_rec, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, wave_base,
-                       (unsigned long long*)total, out_r, out_s, capacity);
+                       item_begin, item_rec, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, hot, wave_base,
+                       (unsigned long long*)total, out_r, out_s, capacity, heavy);
     rec.after();
 }
 
 template <bool kOnePass>
 void join_write_p(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                   uint32_t grid, const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
-                  uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
+                  uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next, const HotKeys* hot,
                   const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s, uint64_t capacity,
-                  Recorder& rec) {
+                  HeavyQueue* heavy, Recorder& rec) {
     switch (join_rpt(lds_cap)) {
         case kRptSmall:
             join_write_t<kOnePass, kRptSmall>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
-                                              ovf_table, ovf_next, wave_base, total, out_r, out_s, capacity, rec);
+                                              ovf_table, ovf_next, hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
             break;
         case kRptMid:
             join_write_t<kOnePass, kRptMid>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
-                                            ovf_table, ovf_next, wave_base, total, out_r, out_s, capacity, rec);
+                                            ovf_table, ovf_next, hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
             break;
         default:
             join_write_t<kOnePass, kRptLarge>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
-                                              ovf_table, ovf_next, wave_base, total, out_r, out_s, capacity, rec);
+                                              ovf_table, ovf_next, hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
             break;
     }
 }
@@ -742,14 +852,14 @@ void join_write(const PartPair* pairs, const uint32_t* item_begin, const ItemRec
                 const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                 uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
                 const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
-                uint64_t capacity, Recorder& rec) {
+                const HotKeys* hot, uint64_t capacity, HeavyQueue* heavy, Recorder& rec) {
     if (grid == 0) return;
     if (wave_base == nullptr)
         join_write_p<true>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
-                           wave_base, total, out_r, out_s, capacity, rec);
+                           hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
     else
         join_write_p<false>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
-                            wave_base, total, out_r, out_s, capacity, rec);
+                            hot, wave_base, total, out_r, out_s, capacity, nullptr, rec);
 }
 
 }  // namespace hj

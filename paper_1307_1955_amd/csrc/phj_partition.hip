@@ -363,7 +363,24 @@ void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint3
     rec.after();
 }
 
+// starts[p] = first position of partition p in a one-segment pass (segment at
+// output position 0, ntiles tiles, partition-major histogram scan), starts[P] = n.
+__global__ void __launch_bounds__(256) k_part_starts(const uint32_t* __restrict__ hist_scan, uint32_t ntiles,
+                                                    uint32_t P, uint32_t n, uint32_t* __restrict__ starts) {
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p <= P; p += gridDim.x * blockDim.x)
+        starts[p] = (p == P || ntiles == 0) ? (p == P ? n : 0u) : min(hist_scan[(uint64_t)p * ntiles] - hist_scan[0], n);
+}
+
 }  // namespace
+
+void part_starts(const uint32_t* hist_scan, uint32_t ntiles, uint32_t bits, uint32_t n, uint32_t* starts,
+                 Recorder& rec) {
+    const uint32_t P = 1u << bits;
+    rec.before("part_starts");
+    hipLaunchKernelGGL(k_part_starts, dim3((P + 256) / 256), dim3(256), 0, rec.stream, hist_scan, ntiles, P, n,
+                       starts);
+    rec.after();
+}
 
 size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile) {
     const size_t P = (size_t)1 << bits;

@@ -149,6 +149,33 @@ def permutation_at(seed: int, stream: int, n: int, idx) -> np.ndarray:
     return y.astype(np.int64)
 
 
+def permutation_index_of(seed: int, stream: int, n: int, values) -> np.ndarray:
+    """Inverse of ``permutation_at``: the index at which the permutation of
+    ``[0, n)`` holds each of ``values`` (the Feistel rounds run backwards, with
+    the same cycle walking until the result lies in ``[0, n)``)."""
+    y = np.asarray(values, dtype=np.uint64)
+    if n <= 0 or y.size == 0:
+        return np.zeros(0, dtype=np.int64)
+    h = _feistel_half_bits(n)
+    mask = np.uint64((1 << h) - 1)
+    rk = [np.uint64(k) for k in feistel_round_keys(seed, stream)]
+
+    def dec(v: np.ndarray) -> np.ndarray:
+        left = v >> np.uint64(h)
+        right = v & mask
+        for r in range(3, -1, -1):
+            f = mix64(rk[r] ^ left) & mask
+            left, right = right ^ f, left
+        return (left << np.uint64(h)) | right
+
+    x = dec(y)
+    bad = x >= np.uint64(n)
+    while bad.any():
+        x[bad] = dec(x[bad])
+        bad = x >= np.uint64(n)
+    return x.astype(np.int64)
+
+
 def permutation(seed: int, stream: int, n: int, start: int = 0, count: int | None = None) -> np.ndarray:
     """Elements ``start .. start+count-1`` of a pseudo-random permutation of ``[0, n)``."""
     if count is None:

@@ -36,7 +36,7 @@ HJ_BATCH_NO_GRAPH = 1
 # Every symbol include/hj.h declares.
 EXPORTED = (
     "hj_default_params", "hj_resolve_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
-    "hj_join_noalloc",
+    "hj_join_noalloc", "hj_join_external", "hj_model_seconds",
     "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_run",
     "hj_batch_plan_destroy", "hj_batch_bytes", "hj_batch", "hj_table_bytes", "hj_build",
     "hj_probe_workspace_bytes", "hj_probe", "hj_server_create", "hj_server_submit", "hj_server_submit_probe", "hj_server_poll", "hj_server_drain",
@@ -80,6 +80,15 @@ class HjServerConfig(ctypes.Structure):
                 ("max_batch_jobs", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
+class HjExternalInfo(ctypes.Structure):
+    _fields_ = [("fanout_bits", ctypes.c_uint32), ("pieces", ctypes.c_uint32), ("chunk_tuples", ctypes.c_uint64),
+                ("partition_s", ctypes.c_double), ("join_s", ctypes.c_double), ("total_s", ctypes.c_double),
+                ("h2d_bytes", ctypes.c_uint64), ("d2h_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class HJError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("%s (status %d): %s" % (_status_name(status), status, message))
@@ -119,6 +128,12 @@ def load() -> ctypes.CDLL:
                                           P(ctypes.c_uint32)]
             lib.hj_join_noalloc.restype = ctypes.c_int
             lib.hj_join_noalloc.argtypes = [P(HjParams), P(HjRel), P(HjRel), P(HjOut), vp, vp]
+            lib.hj_model_seconds.restype = ctypes.c_int
+            lib.hj_model_seconds.argtypes = [P(HjParams), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                             P(ctypes.c_double)]
+            lib.hj_join_external.restype = ctypes.c_int
+            lib.hj_join_external.argtypes = [P(HjParams), P(HjRel), P(HjRel), P(HjOut), vp, ctypes.c_size_t,
+                                             P(ctypes.c_uint64), P(HjExternalInfo)]
             lib.hj_table_bytes.restype = ctypes.c_size_t
             lib.hj_table_bytes.argtypes = [P(HjParams), ctypes.c_uint64]
             lib.hj_build.restype = ctypes.c_int
@@ -211,6 +226,13 @@ def hj_resolve_params(p: HjParams, n_r: int, n_s: int) -> HjParams:
     q = HjParams()
     _check(load().hj_resolve_params(ctypes.byref(p), n_r, n_s, ctypes.byref(q)))
     return q
+
+
+def hj_model_seconds(p: HjParams, n_r: int, n_s: int, pairs: int) -> float:
+    """The library's cost-model prediction of hj_join's time (seconds)."""
+    v = ctypes.c_double(0.0)
+    _check(load().hj_model_seconds(ctypes.byref(p), n_r, n_s, pairs, ctypes.byref(v)))
+    return float(v.value)
 
 
 def hj_workspace_bytes(p: HjParams, n_r: int, n_s: int) -> int:
@@ -344,6 +366,37 @@ def join(r_key, r_rid, s_key, s_rid, p: HjParams | None = None, capacity: int | 
         cnt2 = hj_join_sync(p, r_key, r_rid, s_key, s_rid, out_r, out_s, ws, d_count, stream)
         assert cnt2 == cnt
     return out_r[:cnt], out_s[:cnt], cnt
+
+
+def _host_i32(a, name: str) -> int:
+    """Address of a host int32 array: a contiguous CPU torch tensor (pinned or
+    not) or a numpy array."""
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.int32 or a.is_cuda or not a.is_contiguous() or a.dim() != 1:
+            raise ValueError("%s must be a contiguous 1-D int32 CPU tensor" % name)
+        return a.data_ptr()
+    import numpy as np
+    if not isinstance(a, np.ndarray) or a.dtype != np.int32 or not a.flags.c_contiguous or a.ndim != 1:
+        raise ValueError("%s must be a contiguous 1-D int32 array" % name)
+    return a.ctypes.data
+
+
+def hj_join_external(p: HjParams, r_key, r_rid, s_key, s_rid, out_r, out_s, ws: torch.Tensor):
+    """Joins relations held in HOST memory through the device workspace ``ws``
+    (see include/hj.h); the pairs land in the host arrays ``out_r``/``out_s``.
+    Returns ``(count, info)``; raises on errors, also when the count exceeds the
+    output length (HJ_ERR_CAPACITY; the count is in the exception's message)."""
+    if len(r_key) != len(r_rid) or len(s_key) != len(s_rid) or len(out_r) != len(out_s):
+        raise ValueError("column lengths differ")
+    R = HjRel(_host_i32(r_key, "r_key"), _host_i32(r_rid, "r_rid"), len(r_key))
+    S = HjRel(_host_i32(s_key, "s_key"), _host_i32(s_rid, "s_rid"), len(s_key))
+    O = HjOut(_host_i32(out_r, "out_r"), _host_i32(out_s, "out_s"), len(out_r))
+    wp, wb = _ws(ws)
+    h = ctypes.c_uint64(0)
+    info = HjExternalInfo()
+    _check(load().hj_join_external(ctypes.byref(p), ctypes.byref(R), ctypes.byref(S), ctypes.byref(O), wp, wb,
+                                   ctypes.byref(h), ctypes.byref(info)))
+    return int(h.value), info.as_dict()
 
 
 # ---------------------------------------------------------------------------

@@ -67,10 +67,9 @@ def batch_workload(seed: int = 4, njobs: int = 4096, r_min: int = gen.JOB_R_MIN,
 
 
 def tuned_params(specs, table=None):
-    """Per-job hj_params from the tuning table (or the cost model without one)."""
+    """Per-job hj_params: the cost model's choice (HJ_AUTO, one-pass output), or
+    a tuned table's bucket when a table is given."""
     from . import tune
-    if table is None:
-        table = tune.load_table()
     return [tune.choose(sp.n_r, sp.n_s, table).params() for sp in specs]
 
 

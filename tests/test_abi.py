@@ -162,24 +162,100 @@ def test_validation_before_launch(hj):
                        None) == hj.HJ_ERR_INVALID
 
 
-@pytest.mark.parametrize("n_r,want", [
-    (0, (0, (0, 0))), (1000, (0, (0, 0))), (4416, (0, (0, 0))), (4417, (1, (1, 0))),
-    (100000, (1, (5, 0))), (1 << 20, (1, (8, 0))), (1 << 22, (1, (10, 0))), ((1 << 22) + (1 << 12), (2, (6, 5))),
-    (1 << 24, (2, (6, 6))), (3 << 24, (2, (7, 7))), (1 << 30, (2, (9, 9))), ((1 << 31) - 1, (2, (10, 9))),
-    (300_000_000, (2, (8, 8))), (1_200_000_000, (2, (9, 9))), (80_000_000, (2, (8, 7))),
-])
-def test_auto_params(hj, n_r, want):
-    """HJ_AUTO: no partitioning up to 4416 R tuples, else ~4096 R tuples per partition
-    (B = smallest with |R| >> B <= 4096, or <= 5120 when that B exceeds 16; one pass up
-    to 10 bits, else split (B+1)/2, B/2)."""
+def auto_candidates(hj, n_r, flags, tile=0):
+    """The plans HJ_AUTO weighs (csrc/costmodel.cpp), built independently here."""
+    c = [hj.params("shj", one_pass=bool(flags))]
+    if n_r <= 8192:
+        c.append(hj.params("phj", 0, (0, 0), one_pass=bool(flags)))
+    B = 0
+    while B < 20 and (n_r >> B) > 4096:
+        B += 1
+    for b in range(max(1, B - 2), min(B + 2, 20) + 1):
+        for t in ((tile,) if tile else (4096, 8192)):
+            if b <= 13:
+                c.append(hj.params("phj", 1, (b,), tile=t, one_pass=bool(flags)))
+            if b >= 2:
+                for b1 in range(max(1, b // 2 - 1), min(13, b // 2 + 2) + 1):
+                    if 1 <= b - b1 <= 13:
+                        c.append(hj.params("phj", 2, (b1, b - b1), tile=t, one_pass=bool(flags)))
+    return c
+
+
+@pytest.mark.parametrize("n_r,n_s", [(0, 1000), (1000, 1000), (4416, 50000), (9000, 9000), (100000, 400000),
+                                     (1 << 20, 1 << 20), (1 << 22, 1 << 24), (1 << 24, 1 << 24), (3 << 24, 3 << 24),
+                                     (1 << 30, 1 << 30), ((1 << 31) - 1, 1 << 20)])
+def test_auto_params_are_the_models_choice(hj, n_r, n_s):
+    """HJ_AUTO runs the candidate with the least modelled time (hj_model_seconds)."""
     for flags in (0, hj.HJ_FLAG_ONE_PASS):
-        p = hj.params("auto", one_pass=bool(flags))
-        q = hj.hj_resolve_params(p, n_r, 1000)
-        assert q.algo == hj.HJ_PHJ
-        assert (q.passes, tuple(q.bits)) == want
-        # passes 0 always writes its output in one pass; otherwise the caller's flag is kept
-        assert q.flags == (hj.HJ_FLAG_ONE_PASS if want[0] == 0 else flags)
-        assert hj.hj_workspace_bytes(p, n_r, 1000) == hj.hj_workspace_bytes(q, n_r, 1000)
+        for tile in (0, 8192):
+            p = hj.params("auto", tile=tile, one_pass=bool(flags))
+            q = hj.hj_resolve_params(p, n_r, n_s)
+            t_auto = hj.hj_model_seconds(q, n_r, n_s, n_s)
+            ts = []
+            for c in auto_candidates(hj, n_r, flags, tile):
+                try:
+                    ts.append(hj.hj_model_seconds(c, n_r, n_s, n_s))
+                except hj.HJError:
+                    pass
+            assert t_auto == pytest.approx(min(ts), rel=1e-12)
+            assert hj.hj_workspace_bytes(p, n_r, n_s) == hj.hj_workspace_bytes(q, n_r, n_s)
+            if q.algo == hj.HJ_PHJ and q.passes == 0:
+                assert q.flags == hj.HJ_FLAG_ONE_PASS  # the direct join always writes in one pass
+            else:
+                assert q.flags == flags
+
+
+def test_model_twins_agree(hj):
+    """The library's compiled cost model and its Python twin (used to fit the
+    constants and to validate them) give the same predictions."""
+    from paper_1307_1955_amd import costmodel
+    c = costmodel.load()
+    for n_r, n_s in [(1000, 1000), (5000, 80000), (100000, 400000), (1 << 20, 1 << 22), (1 << 24, 1 << 24),
+                     (3 << 24, 1 << 26), (1 << 28, 1 << 28)]:
+        for p in auto_candidates(hj, n_r, 0) + auto_candidates(hj, n_r, 1):
+            try:
+                want = hj.hj_model_seconds(p, n_r, n_s, n_s // 2)
+            except hj.HJError:
+                continue
+            q = hj.hj_resolve_params(p, n_r, n_s)
+            got = costmodel.join_seconds(costmodel.plan_of(q), n_r, n_s, n_s // 2, c)
+            assert got == pytest.approx(want, rel=1e-9), (repr(q), n_r, n_s)
+
+
+def test_model_constants_match_the_calibration():
+    """csrc/calib_mi355x.inc is generated from tuning/mi355x_calib.json."""
+    import re
+
+    from paper_1307_1955_amd import costmodel
+    c = costmodel.load()
+    inc = open(costmodel.CALIB_INC).read()
+    got = {m.group(1): float(m.group(2)) for m in re.finditer(r"k_(\w+) = ([-+0-9.eE]+);", inc)}
+    assert set(got) == set(costmodel.PARAMS)
+    for k in costmodel.PARAMS:
+        assert got[k] == pytest.approx(c[k], rel=1e-15)
+
+
+def test_model_geometry_matches_the_kernels():
+    """The Python twin's launch geometry (chunk, tile and grid sizes) is the
+    one the kernels are compiled with (csrc/hj_internal.h)."""
+    import re
+
+    from paper_1307_1955_amd import costmodel
+    hdr = open(os.path.join(os.path.dirname(costmodel.__file__), "csrc", "hj_internal.h")).read()
+
+    def const(name):
+        m = re.search(r"constexpr \w+ %s = ([^;]+);" % name, hdr)
+        assert m, name
+        return m.group(1)
+
+    assert int(const("kOvfChunk")) == costmodel.OVF_CHUNK
+    assert int(const("kOvfChunkBig")) == costmodel.OVF_CHUNK_BIG
+    assert const("kOvfBigPart") == "1u << 16" and costmodel.OVF_BIG_PART == 1 << 16
+    assert int(const("kOvfGrid")) == costmodel.OVF_GRID
+    assert int(const("kShjTile")) == costmodel.SHJ_TILE
+    assert float(const("kShjSlotsPerRow")) == costmodel.SHJ_SLOTS_PER_ROW
+    sub = re.search(r"constexpr uint32_t kJoinSub = (\d+)", hdr)
+    assert sub and 2 * int(sub.group(1)) == costmodel.JOIN_CHUNK
 
 
 def test_table_and_probe_sizes(hj):
@@ -297,3 +373,23 @@ def test_noalloc_rejects_sizes_beyond_its_array(hj):
     assert lib.hj_join_noalloc(None, ctypes.byref(R), ctypes.byref(S), ctypes.byref(O), 256,
                                None) == hj.HJ_ERR_INVALID
     assert hj.hj_workspace_bytes(p, 1 << 24, 1 << 24) > 64 << 20
+
+
+def test_external_validation_before_device(hj):
+    """hj_join_external rejects bad arguments before any device call (no GPU here;
+    fake pointers)."""
+    lib = hj.load()
+    p = hj.params("auto", one_pass=True)
+    R = hj.HjRel(256, 256, 1000)
+    S = hj.HjRel(256, 256, 1000)
+    O = hj.HjOut(256, 256, 1000)
+    h = ctypes.c_uint64(0)
+    info = hj.HjExternalInfo()
+    call = lambda ws, wb, r=R, o=O, cnt=ctypes.byref(h): lib.hj_join_external(  # noqa: E731
+        ctypes.byref(p), ctypes.byref(r), ctypes.byref(S), ctypes.byref(o), ws, wb, cnt, ctypes.byref(info))
+    assert call(1 << 20, (64 << 20) - 1) == hj.HJ_ERR_WORKSPACE
+    assert call(None, 64 << 20) == hj.HJ_ERR_WORKSPACE
+    assert call((1 << 20) + 8, 64 << 20) == hj.HJ_ERR_INVALID
+    assert call(1 << 20, 64 << 20, r=hj.HjRel(None, 256, 5)) == hj.HJ_ERR_INVALID
+    assert call(1 << 20, 64 << 20, o=hj.HjOut(None, 256, 5)) == hj.HJ_ERR_INVALID
+    assert call(1 << 20, 64 << 20, cnt=None) == hj.HJ_ERR_INVALID

@@ -135,3 +135,13 @@ def test_skewed_r(frac):
     assert len(np.unique(rest)) == len(rest)
     with pytest.raises(ValueError):
         gen.skew_rows(n, 1.5)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 1000, (1 << 20) + 17, 1 << 30])
+def test_permutation_index_of_inverts(n):
+    rng = np.random.default_rng(n)
+    idx = rng.integers(0, n, size=min(n, 5000))
+    v = gen.permutation_at(5, 3, n, idx)
+    assert np.array_equal(gen.permutation_index_of(5, 3, n, v), idx)
+    full = gen.permutation(7, 1, min(n, 4096))
+    assert np.array_equal(gen.permutation_index_of(7, 1, min(n, 4096), full), np.arange(min(n, 4096)))

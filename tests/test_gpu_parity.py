@@ -213,6 +213,26 @@ def test_shj_heavy_queue_overflow(one_pass):
     check_small(hj.params("shj", one_pass=one_pass), rk.astype(np.int32), rr, sk.astype(np.int32), sr)
 
 
+@pytest.mark.parametrize("kw", [dict(algo="phj", passes=2, bits=(6, 6), one_pass=True),
+                                dict(algo="phj", passes=1, bits=(8,), one_pass=True),
+                                dict(algo="phj", passes=2, bits=(6, 6))], ids=["6_6_1pass", "8_1pass", "6_6"])
+@pytest.mark.parametrize("n_heavy_s", [40, 300])
+def test_phj_heavy_queue(kw, n_heavy_s):
+    """One-pass PHJ hands the heavy S tuples of an HBM-table partition larger than
+    one 64K-row chunk (70000 R rows on key 77) to the device-wide queue every
+    workgroup helps with; 300 such tuples overflow its 256 entries and the rest
+    stay with their workgroups' own scans.  Two-pass output keeps the
+    workgroup-local scans.  Every pair against the oracle."""
+    n_r, n_s = 1 << 19, 1 << 20
+    r, s = gen.unique_uniform(33, n_r, n_s, 2 * n_r)
+    rng = np.random.default_rng(34)
+    rk = r.key.copy()
+    rk[rng.choice(n_r, 70000, replace=False)] = 77
+    sk = s.key.copy()
+    sk[rng.choice(n_s, n_heavy_s, replace=False)] = 77
+    check_small(hj.params(**kw), rk, r.rid, sk, s.rid)
+
+
 @pytest.mark.parametrize("one_pass", [True, False])
 def test_sorted_r_short_duplicate_runs(one_pass):
     """R sorted with 32 duplicates per key: every build wave pushes runs of 32 rows
@@ -488,14 +508,14 @@ def test_c3_zipf_full(theta, kw):
     assert np.array_equal(s_key[rows[:2000]], gen.zipf_ranks_at(3, gen.STREAM_S_KEYS, rows[:2000], cdf))
 
 
-@pytest.mark.parametrize("n_r,n_s", [(1 << 21, 1 << 24), (1 << 22, (1 << 24) - (1 << 22))])
-def test_auto_one_pass_wide(n_r, n_s):
-    """HJ_AUTO's one-pass range at its widest (9 and 10 radix bits, 8192-tuple
-    tiles in 512-thread workgroups): every S row against the closed form, a
-    sample of S rows against the oracle."""
-    p = hj.params("auto", one_pass=True)
+@pytest.mark.parametrize("n_r,n_s,bits", [(1 << 21, 1 << 24, 9), (1 << 22, (1 << 24) - (1 << 22), 10)])
+def test_one_pass_wide(n_r, n_s, bits):
+    """One pass of 9 and 10 radix bits with 8192-tuple tiles in 512-thread
+    workgroups (partitions of 4096 R tuples): every S row against the closed
+    form, a sample of S rows against the oracle."""
+    p = hj.params("phj", 1, (bits,), tile=8192, one_pass=True)
     q = hj.hj_resolve_params(p, n_r, n_s)
-    assert q.passes == 1 and q.bits[0] >= 9 and q.tile == 8192
+    assert q.passes == 1 and q.bits[0] == bits and q.tile == 8192
     rk, rr, sk, sr = dgen.unique_uniform(50, n_r, n_s, 2 * n_r)
     o_r, o_s, cnt = hj.join(rk, rr, sk, sr, p=p)
     s_key = sk.cpu().numpy()
