@@ -318,7 +318,10 @@ hj_status hj_server_create(const hj_server_config* cfg, void* ws, size_t ws_byte
 
 /* Queues one request (thread-safe, returns at once).  footprint: the bytes the
    request holds on the device while admitted (inputs, output, workspace), as
-   the caller accounts them.  *ticket identifies it in hj_server_poll. */
+   the caller accounts them; admission uses the larger of that and the bytes
+   the server accounts itself: 8 per tuple of R and S, 8 per output slot of
+   out.capacity, the count and the request's workspace (hj_workspace_bytes).
+   *ticket identifies it in hj_server_poll. */
 hj_status hj_server_submit(hj_server* server, const hj_job* job, const hj_params* params, uint64_t footprint,
                            uint64_t* ticket);
 
@@ -326,7 +329,8 @@ hj_status hj_server_submit(hj_server* server, const hj_job* job, const hj_params
    once): the request runs hj_probe on a slot, so relations and their tables
    built once stay on the device and serve many requests.  The table and
    everything it points to must stay alive until the request has finished.
-   footprint: as for hj_server_submit (S, output and probe workspace). */
+   footprint: as for hj_server_submit, with the server's own account over S,
+   the output and the probe workspace (the table is the caller's). */
 hj_status hj_server_submit_probe(hj_server* server, const hj_table* table, const hj_rel* S, const hj_out* out,
                                  uint64_t* d_count, uint64_t footprint, uint64_t* ticket);
 

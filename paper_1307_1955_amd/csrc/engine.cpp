@@ -247,10 +247,12 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, v
     uint64_t* zero = c.take<uint64_t>(nq + n1 + n2 + nw + np);
     w.heavy = reinterpret_cast<hj::HeavyQueue*>(zero);
     w.hot = zero ? reinterpret_cast<hj::HotKeys*>(zero + sizeof(hj::HeavyQueue) / sizeof(uint64_t)) : nullptr;
-    w.st1 = zero ? zero + nq : nullptr;
-    w.st2 = w.st1 + n1;
-    w.stw = w.st2 + n2;
-    w.stp = w.stw + nw;
+    if (zero) {  // (sizing only when there is no base: no arithmetic on a null pointer)
+        w.st1 = zero + nq;
+        w.st2 = w.st1 + n1;
+        w.stw = w.st2 + n2;
+        w.stp = w.stw + nw;
+    }
     w.zero = zero;
     w.nzero = nq + n1 + n2 + nw + np;
     w.bytes = c.off;

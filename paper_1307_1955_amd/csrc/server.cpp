@@ -14,7 +14,9 @@
 // footprint and records each request's completion time, so requests that
 // arrive while others are on the GPU are admitted as soon as a slot and memory
 // free up.  A request whose footprint alone exceeds the cap, or whose
-// workspace exceeds a slot, is rejected.
+// workspace exceeds a slot, is rejected.  The admission policy itself lives in
+// server_core.h (no device state), which a host test drives with a virtual
+// clock; this file runs its batches on HIP streams.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +33,7 @@
 #include "../../include/hj.h"
 #include "engine.h"
 #include "hj_internal.h"
+#include "server_core.h"
 
 using namespace hj::eng;
 
@@ -38,36 +41,26 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// What the device needs of a request (the core keeps its ticket, footprint,
+// workspace need and arrival).
 struct Request {
-    uint64_t ticket;
     hj_job job;
     bool probe = false;  // a probe of `table` by job.S (else a join of job.R and job.S)
     hj_table table{};
     Plan plan;
-    uint64_t footprint;
-    size_t ws;
-    Clock::time_point arrival;
 };
 
-struct Done {
-    uint64_t ticket;
-    hj_status status;
-    double latency_s;   // arrival -> completion observed
-    double queue_s;     // arrival -> admission
-};
-
-struct Slot {
+// Device resources of a slot (its admission state is the core's).
+struct SlotDev {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    bool busy = false;
-    std::vector<Request> reqs;
-    std::vector<Clock::time_point> admitted;
-    uint64_t footprint = 0;
     hj::DirectJob* h_djobs = nullptr;  // pinned, max_batch entries
     uint32_t* h_items = nullptr;       // pinned, max_items entries
     uint64_t* h_err = nullptr;         // pinned: the batch's device error word, copied back at its end
     char* ws = nullptr;                // this slot's workspace share: [error word][jobs][items][pipeline]
 };
+
+using Core = hj::srv::Core<Request>;
 
 // Direct work items a slot can hold (a direct job with |S| beyond the per-job
 // share of this runs through the pipeline path instead).
@@ -77,29 +70,27 @@ constexpr uint32_t kItemsPerJob = 64;
 
 struct hj_server {
     hj_server_config cfg{};
-    std::vector<Slot> slots;
+    std::vector<SlotDev> slots;
     size_t slot_ws = 0, slot_djobs_off = 0, slot_items_off = 0, slot_pipe_off = 0;
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<Request> pending;
-    std::vector<Done> done;
-    uint64_t next_ticket = 1;
-    uint64_t used = 0;      // footprint on the device
-    uint64_t inflight = 0;  // admitted, not finished
-    uint64_t rejected = 0, completed = 0, batches = 0;
+    Core* core = nullptr;  // guarded by mu
+    Clock::time_point t0;
     bool stop = false;
     hj_status fatal = HJ_OK;
     std::thread worker;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
 
 namespace {
 
-// Enqueues the slot's admitted requests on its stream.
-hj_status launch_slot(hj_server* sv, Slot& s) {
+// Enqueues a slot's admitted requests (reqs) on its stream.
+hj_status launch_slot(hj_server* sv, SlotDev& s, const std::vector<Core::Req>& reqs) {
     uint32_t nd = 0, items = 0;
     std::vector<size_t> piped;
-    for (size_t i = 0; i < s.reqs.size(); ++i) {
-        const Request& r = s.reqs[i];
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        const Request& r = reqs[i].payload;
         const uint32_t it = (r.job.R.n && r.job.S.n) ? (uint32_t)cdiv(r.job.S.n, hj::kJoinChunk) : 0u;
         if (!r.probe && r.plan.phj && r.plan.passes == 0 && items + it <= sv->cfg.max_batch_jobs * kItemsPerJob) {
             hj::DirectJob& d = s.h_djobs[nd];
@@ -134,13 +125,13 @@ hj_status launch_slot(hj_server* sv, Slot& s) {
             e = hipMemcpyAsync(d_items, s.h_items, sizeof(uint32_t) * items, hipMemcpyHostToDevice, s.stream);
         if (e != hipSuccess) return fail(HJ_ERR_DEVICE, "server upload failed: %s", hipGetErrorString(e));
         uint32_t cap = 256;
-        for (const Request& r : s.reqs)
-            if (r.plan.phj && r.plan.passes == 0) cap = std::max(cap, r.plan.lds_cap);
+        for (const Core::Req& q : reqs)
+            if (q.payload.plan.phj && q.payload.plan.passes == 0) cap = std::max(cap, q.payload.plan.lds_cap);
         hj::direct_zero(d_djobs, nd, rec);
         hj::direct_join(d_djobs, d_items, items, cap, rec);
     }
     for (size_t i : piped) {
-        const Request& r = s.reqs[i];
+        const Request& r = reqs[i].payload;
         if (r.probe)
             run_probe(r.plan, r.table, r.job.S, r.job.out, s.ws + sv->slot_pipe_off, r.job.d_count, rec);
         else
@@ -156,78 +147,38 @@ hj_status launch_slot(hj_server* sv, Slot& s) {
 
 void dispatcher(hj_server* sv) {
     std::unique_lock<std::mutex> lk(sv->mu);
+    Core& c = *sv->core;
     while (true) {
         // retire finished batches
         bool any_busy = false;
-        for (Slot& s : sv->slots) {
-            if (!s.busy) continue;
+        for (uint32_t i = 0; i < sv->slots.size(); ++i) {
+            if (!c.slots[i].busy) continue;
+            SlotDev& s = sv->slots[i];
             hipError_t q = hipEventQuery(s.done);
             if (q == hipErrorNotReady) {
                 any_busy = true;
                 continue;
             }
-            const Clock::time_point now = Clock::now();
             // a set error word fails this batch's requests; the server goes on
             const bool ok = q == hipSuccess && sv->fatal == HJ_OK && *s.h_err == 0;
-            for (size_t i = 0; i < s.reqs.size(); ++i) {
-                Done d;
-                d.ticket = s.reqs[i].ticket;
-                d.status = ok ? HJ_OK : HJ_ERR_DEVICE;
-                d.latency_s = std::chrono::duration<double>(now - s.reqs[i].arrival).count();
-                d.queue_s = std::chrono::duration<double>(s.admitted[i] - s.reqs[i].arrival).count();
-                sv->done.push_back(d);
-            }
-            sv->used -= s.footprint;
-            sv->inflight -= s.reqs.size();
-            sv->completed += s.reqs.size();
-            s.reqs.clear();
-            s.admitted.clear();
-            s.footprint = 0;
-            s.busy = false;
+            c.retire(i, ok, sv->now(), HJ_ERR_DEVICE);
             if (q != hipSuccess && sv->fatal == HJ_OK) sv->fatal = HJ_ERR_DEVICE;
             sv->cv.notify_all();
         }
         // admit waiting requests into idle slots
         bool rejected_any = false;
-        std::vector<Slot*> to_launch;
-        for (Slot& s : sv->slots) {
-            if (s.busy || sv->pending.empty()) continue;
-            size_t pipe_ws = 0;
-            const Clock::time_point now = Clock::now();
-            while (!sv->pending.empty() && s.reqs.size() < sv->cfg.max_batch_jobs) {
-                Request& r = sv->pending.front();
-                if (r.footprint > sv->cfg.mem_cap_bytes || r.ws > sv->slot_ws - sv->slot_pipe_off) {
-                    Done d{r.ticket, HJ_ERR_CAPACITY, 0.0, 0.0};
-                    sv->done.push_back(d);
-                    ++sv->rejected;
-                    sv->pending.pop_front();
-                    rejected_any = true;
-                    continue;
-                }
-                if (sv->used + r.footprint > sv->cfg.mem_cap_bytes) break;  // wait for memory
-                pipe_ws = std::max(pipe_ws, r.ws);
-                sv->used += r.footprint;
-                s.footprint += r.footprint;
-                s.reqs.push_back(r);
-                s.admitted.push_back(now);
-                sv->pending.pop_front();
-            }
-            if (s.reqs.empty()) continue;
-            sv->inflight += s.reqs.size();
-            ++sv->batches;
-            s.busy = true;
-            to_launch.push_back(&s);
-            any_busy = true;
-        }
+        const std::vector<uint32_t> to_launch = c.admit(sv->now(), &rejected_any);
+        if (!to_launch.empty()) any_busy = true;
         // a rejection can leave nothing pending or in flight: wake drain()
         if (rejected_any) sv->cv.notify_all();
         if (!to_launch.empty()) {
-            // Slots are touched by this thread only; submitters need not wait
+            // A busy slot's requests change only when this thread retires it,
+            // so they can be read without the lock; submitters need not wait
             // for the launches.
             lk.unlock();
             hj_status st = HJ_OK;
-            for (Slot* s : to_launch) {
-                const hj_status e = launch_slot(sv, *s);
+            for (uint32_t i : to_launch) {
+                const hj_status e = launch_slot(sv, sv->slots[i], c.slots[i].reqs);
                 if (st == HJ_OK) st = e;
             }
             lk.lock();
@@ -236,26 +187,27 @@ void dispatcher(hj_server* sv) {
                 sv->cv.notify_all();
             }
         }
-        if (sv->stop && sv->pending.empty() && !any_busy) break;
+        if (sv->stop && c.pending.empty() && !any_busy) break;
         if (any_busy) {
             lk.unlock();
             std::this_thread::yield();
             lk.lock();
         } else {
             sv->cv.wait_for(lk, std::chrono::microseconds(200),
-                            [&] { return sv->stop || !sv->pending.empty(); });
+                            [&] { return sv->stop || !c.pending.empty(); });
         }
     }
 }
 
 void destroy(hj_server* sv) {
-    for (Slot& s : sv->slots) {
+    for (SlotDev& s : sv->slots) {
         if (s.done) (void)hipEventDestroy(s.done);
         if (s.stream) (void)hipStreamDestroy(s.stream);
         if (s.h_djobs) (void)hipHostFree(s.h_djobs);
         if (s.h_items) (void)hipHostFree(s.h_items);
         if (s.h_err) (void)hipHostFree(s.h_err);
     }
+    delete sv->core;
     delete sv;
 }
 
@@ -283,8 +235,15 @@ hj_status hj_server_create(const hj_server_config* cfg, void* ws, size_t ws_byte
         destroy(sv);
         return fail(HJ_ERR_WORKSPACE, "workspace too small for %u slots", cfg->slots);
     }
+    sv->core = new (std::nothrow)
+        Core(hj::srv::CoreConfig{cfg->slots, cfg->max_batch_jobs, cfg->mem_cap_bytes, sv->slot_ws - sv->slot_pipe_off});
+    if (!sv->core) {
+        destroy(sv);
+        return fail(HJ_ERR_DEVICE, "out of host memory");
+    }
+    sv->t0 = Clock::now();
     for (uint32_t i = 0; i < cfg->slots; ++i) {
-        Slot& s = sv->slots[i];
+        SlotDev& s = sv->slots[i];
         s.ws = (char*)ws + i * sv->slot_ws;
         hipError_t e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
@@ -323,15 +282,13 @@ hj_status hj_server_submit(hj_server* sv, const hj_job* job, const hj_params* pa
     hj_status st = check_params(params, job->R.n, job->S.n, &r.plan);
     if (st != HJ_OK) return st;
     r.job = *job;
-    r.footprint = footprint;
-    r.ws = ws_bytes_for(r.plan, job->R.n, job->S.n);
-    r.arrival = Clock::now();
+    const size_t ws = ws_bytes_for(r.plan, job->R.n, job->S.n);
+    // the bytes the request holds on the device are at least its own arrays and workspace
+    footprint = std::max(footprint, hj::srv::least_footprint(job->R.n, job->S.n, job->out.capacity, ws));
     {
         std::lock_guard<std::mutex> g(sv->mu);
         if (sv->fatal != HJ_OK) return fail(sv->fatal, "server stopped after a device error");
-        r.ticket = sv->next_ticket++;
-        *ticket = r.ticket;
-        sv->pending.push_back(r);
+        *ticket = sv->core->submit(footprint, ws, sv->now(), r);
     }
     sv->cv.notify_all();
     clear_error();
@@ -355,15 +312,13 @@ hj_status hj_server_submit_probe(hj_server* sv, const hj_table* table, const hj_
     r.job.S = *S;
     r.job.out = *out;
     r.job.d_count = d_count;
-    r.footprint = footprint;
-    r.ws = probe_bytes_for(r.plan, table->n_r, S->n);
-    r.arrival = Clock::now();
+    const size_t ws = probe_bytes_for(r.plan, table->n_r, S->n);
+    // the table stays resident and is the caller's; S, the output and the workspace are the request's
+    footprint = std::max(footprint, hj::srv::least_footprint(0, S->n, out->capacity, ws));
     {
         std::lock_guard<std::mutex> g(sv->mu);
         if (sv->fatal != HJ_OK) return fail(sv->fatal, "server stopped after a device error");
-        r.ticket = sv->next_ticket++;
-        *ticket = r.ticket;
-        sv->pending.push_back(r);
+        *ticket = sv->core->submit(footprint, ws, sv->now(), r);
     }
     sv->cv.notify_all();
     clear_error();
@@ -375,14 +330,15 @@ hj_status hj_server_poll(hj_server* sv, uint64_t* tickets, int32_t* status, doub
     if (!sv || !n || (max && (!tickets || !status || !latency_s || !queue_s)))
         return fail(HJ_ERR_INVALID, "bad poll arguments");
     std::lock_guard<std::mutex> g(sv->mu);
-    const uint32_t k = (uint32_t)std::min<size_t>(max, sv->done.size());
+    std::vector<hj::srv::Finished>& done = sv->core->done;
+    const uint32_t k = (uint32_t)std::min<size_t>(max, done.size());
     for (uint32_t i = 0; i < k; ++i) {
-        tickets[i] = sv->done[i].ticket;
-        status[i] = sv->done[i].status;
-        latency_s[i] = sv->done[i].latency_s;
-        queue_s[i] = sv->done[i].queue_s;
+        tickets[i] = done[i].ticket;
+        status[i] = done[i].status;
+        latency_s[i] = done[i].latency_s;
+        queue_s[i] = done[i].queue_s;
     }
-    sv->done.erase(sv->done.begin(), sv->done.begin() + k);
+    done.erase(done.begin(), done.begin() + k);
     *n = k;
     return sv->fatal;
 }
@@ -390,7 +346,7 @@ hj_status hj_server_poll(hj_server* sv, uint64_t* tickets, int32_t* status, doub
 hj_status hj_server_drain(hj_server* sv) {
     if (!sv) return fail(HJ_ERR_INVALID, "server is NULL");
     std::unique_lock<std::mutex> lk(sv->mu);
-    sv->cv.wait(lk, [&] { return (sv->pending.empty() && sv->inflight == 0) || sv->fatal != HJ_OK; });
+    sv->cv.wait(lk, [&] { return sv->core->idle() || sv->fatal != HJ_OK; });
     return sv->fatal;
 }
 
@@ -398,10 +354,10 @@ hj_status hj_server_stats(hj_server* sv, uint64_t* completed, uint64_t* rejected
                           uint64_t* bytes_in_use) {
     if (!sv) return fail(HJ_ERR_INVALID, "server is NULL");
     std::lock_guard<std::mutex> g(sv->mu);
-    if (completed) *completed = sv->completed;
-    if (rejected) *rejected = sv->rejected;
-    if (batches) *batches = sv->batches;
-    if (bytes_in_use) *bytes_in_use = sv->used;
+    if (completed) *completed = sv->core->completed;
+    if (rejected) *rejected = sv->core->rejected;
+    if (batches) *batches = sv->core->batches;
+    if (bytes_in_use) *bytes_in_use = sv->core->used;
     return HJ_OK;
 }
 
@@ -413,7 +369,7 @@ void hj_server_destroy(hj_server* sv) {
     }
     sv->cv.notify_all();
     if (sv->worker.joinable()) sv->worker.join();
-    for (Slot& s : sv->slots)
+    for (SlotDev& s : sv->slots)
         if (s.stream) (void)hipStreamSynchronize(s.stream);
     destroy(sv);
 }
