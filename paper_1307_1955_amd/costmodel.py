@@ -50,6 +50,7 @@ PARAMS = [
     "t_scan_entry",
     "bw_join", "l_join0", "l_join_r", "l_join_s",
     "f_count", "f_1pass",  # a work item's latency in the count pass and the one-pass write, against the write pass
+    "p_join",              # the join kernels overlap memory and latency imperfectly: (M^p + W^p)^(1/p)
     "l_hbm0", "l_hbm_s", "t_ovf_insert", "l_ovf_round",
     "bw_fill",
     # random table accesses: throughput n * t * (table MiB)^gamma, at least a
@@ -103,6 +104,14 @@ def join_slots(cap: int) -> int:
 
 def _nonempty(mean: float) -> float:
     return 1.0 - math.exp(-mean) if mean < 30 else 1.0
+
+
+def _smooth_max(a: float, b: float, p: float) -> float:
+    """(a^p + b^p)^(1/p): max(a, b) as p grows, more than it when a and b are close."""
+    m = max(a, b)
+    if m <= 0.0:
+        return 0.0
+    return m * ((a / m) ** p + (b / m) ** p) ** (1.0 / p)
 
 
 def _table_factor(table_bytes: float, gamma: float, base: float = 1 << 20) -> float:
@@ -200,7 +209,7 @@ def kernel_seconds(name: str, f: dict, c: dict) -> float:
             lat = c["l_join0"] + c["l_join_r"] * f["r"] + c["l_join_s"] * f["s"]
         lat *= c["f_count"] if name == "join_count" else c["f_1pass"] if name == "join_write_1pass" else 1.0
         rounds = math.ceil(max(f["items"], 1) / join_slots(f["cap"]))
-        return d + max(f["bytes"] / c["bw_join"], rounds * lat)
+        return d + _smooth_max(f["bytes"] / c["bw_join"], rounds * lat, c["p_join"])
     if name == "ovf_clear":
         return d + f["bytes"] / c["bw_fill"]
     if name == "ovf_build":
@@ -230,7 +239,7 @@ def join_seconds(plan: dict, n_r: int, n_s: int, m: float, c: dict) -> float:
 START = {
     "d_gap": 2e-6, "d_kernel": 3e-6, "bw_hist": 4.5e12, "t_hist_tile": 5e-6, "bw_scatter": 5.2e12, "run_half": 8.0,
     "t_scatter_tile": 12e-6, "t_scan_entry": 2e-12, "bw_join": 4e12, "l_join0": 4e-6, "l_join_r": 1e-9,
-    "l_join_s": 5e-10, "f_count": 0.8, "f_1pass": 1.2, "l_hbm0": 8e-6, "l_hbm_s": 2e-9, "t_ovf_insert": 1e-10, "l_ovf_round": 4e-6,
+    "l_join_s": 5e-10, "f_count": 0.8, "f_1pass": 1.2, "p_join": 4.0, "l_hbm0": 8e-6, "l_hbm_s": 2e-9, "t_ovf_insert": 1e-10, "l_ovf_round": 4e-6,
     "bw_fill": 5e12, "t_ins": 1e-10, "gamma_ins": -0.2, "t_bround": 1e-5, "gamma_bround": 0.1,
     "t_probe": 3e-11, "gamma_probe": 0.0, "t_pround": 2e-5, "gamma_pround": 0.1, "t_match": 1e-11,
 }

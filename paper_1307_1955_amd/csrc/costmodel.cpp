@@ -76,10 +76,17 @@ double scatter_s(double n, double tiles, uint32_t tile, uint32_t bits) {
 
 double scan_s(double entries) { return k_d_kernel + entries * k_t_scan_entry; }
 
+// (a^p + b^p)^(1/p): max(a, b) as p grows, more than it when a and b are close.
+double smooth_max(double a, double b, double p) {
+    const double m = std::max(a, b);
+    if (m <= 0) return 0;
+    return m * std::pow(std::pow(a / m, p) + std::pow(b / m, p), 1.0 / p);
+}
+
 // f: the kernel's work-item latency against the write pass (k_f_count, k_f_1pass, or 1)
 double join_s(double items, double r, double s, uint32_t cap, bool hbm, double bytes, double f) {
     const double lat = f * (hbm ? k_l_hbm0 + k_l_hbm_s * s : k_l_join0 + k_l_join_r * r + k_l_join_s * s);
-    return k_d_kernel + std::max(bytes / k_bw_join, rounds(items, join_slots(cap)) * lat);
+    return k_d_kernel + smooth_max(bytes / k_bw_join, rounds(items, join_slots(cap)) * lat, k_p_join);
 }
 
 }  // namespace

@@ -103,8 +103,35 @@ def bucket_key(n_r: int, n_s: int) -> tuple[int, int]:
 RATIO_OF_BUCKET = {0: 1, 1: 4, 2: 16}
 
 
+def steady_join_ms(run, reps: int = 3, warm_ms: float = 2.0, span_ms: float = 1.0, cap: int = 200) -> float:
+    """Mean device time (ms) of run() (one join enqueued on the current stream)
+    at steady clocks: joins are run until at least warm_ms of device time has
+    passed (the clocks ramp up under load), then at least `reps` joins covering
+    at least span_ms are timed between two events."""
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    done, spent, last = 0, 0.0, 0.0
+    while done < cap and (done < 2 or spent < warm_ms):
+        a.record()
+        run()
+        b.record()
+        torch.cuda.synchronize()
+        last = a.elapsed_time(b)
+        spent += last
+        done += 1
+    k = max(reps, min(cap, int(math.ceil(span_ms / max(last, 1e-3)))))
+    a.record()
+    for _ in range(k):
+        run()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / k
+
+
 def measure(c: Candidate, n_r: int, n_s: int, domain: int, reps: int = 5, seed: int = 11, t=None) -> float:
-    """Mean device time (s) of one hj_join with candidate c (events around the calls)."""
+    """Mean device time (s) of one hj_join with candidate c at steady clocks
+    (steady_join_ms)."""
     import torch
 
     from . import hj
@@ -116,17 +143,7 @@ def measure(c: Candidate, n_r: int, n_s: int, domain: int, reps: int = 5, seed: 
     out_r = torch.empty(max(1, n_s), dtype=torch.int32, device="cuda")
     out_s = torch.empty_like(out_r)
     d = torch.zeros(1, dtype=torch.int64, device="cuda")
-    for _ in range(2):
-        hj.hj_join(p, *t, out_r, out_s, ws, d)
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        hj.hj_join(p, *t, out_r, out_s, ws, d)
-    b.record()
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps * 1e-3
+    return steady_join_ms(lambda: hj.hj_join(p, *t, out_r, out_s, ws, d), reps) * 1e-3
 
 
 def tune(log2_r=range(10, 23), ratios=(0, 1, 2), top: int = 4, match: float = 0.625, verbose=True) -> dict:
@@ -185,16 +202,19 @@ def main():
     ap.add_argument("--collect", metavar="OUT", default=None,
                     help="time every kernel of the calibration grid and write the raw records to OUT")
     ap.add_argument("--quick", action="store_true", help="with --collect: every 7th setting only")
-    ap.add_argument("--fit", metavar="RAW", default=None,
-                    help="fit the cost model to RAW (from --collect); writes tuning/mi355x_calib.json and the "
-                         "library's include")
+    ap.add_argument("--random", type=int, default=0, metavar="N",
+                    help="with --collect: N random settings drawn like the validation's instead of the grid")
+    ap.add_argument("--seed", type=int, default=7, help="with --collect --random: the draw's seed")
+    ap.add_argument("--fit", metavar="RAW", nargs="+", default=None,
+                    help="fit the cost model to the RAW files (from --collect); writes tuning/mi355x_calib.json "
+                         "and the library's include")
     ap.add_argument("--validate", metavar="OUT", default=None,
                     help="Monte-Carlo validation of the library's model on random settings; writes OUT (JSON) "
                          "and OUT with .md")
     ap.add_argument("--runs", type=int, default=1000, help="with --validate: random settings")
     a = ap.parse_args()
     if a.collect:
-        collect(a.collect, quick=a.quick)
+        collect(a.collect, quick=a.quick, settings=calibration_random(a.random, a.seed) if a.random else None)
         return
     if a.fit:
         fit_calibration(a.fit)
@@ -248,15 +268,34 @@ def calibration_grid(quick: bool = False) -> list[dict]:
     return g[::7] if quick else g
 
 
-def collect(out_path: str, reps: int = 3, quick: bool = False) -> None:
-    """Times every kernel of every setting of the calibration grid (reps joins
-    each, HIP events per launch) and writes the raw records as JSON."""
+def calibration_random(n: int, seed: int) -> list[dict]:
+    """Join settings drawn the way the Monte-Carlo validation draws them (sizes,
+    match rate and parameters at random), for calibrating on more than the
+    regular grid; a different seed than the validation's keeps the two apart."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    g = []
+    for _ in range(n):
+        n_r = int(round(1024 * 4096 ** rng.random()))
+        n_s = n_r * int(rng.integers(1, 17))
+        match = float(rng.uniform(0.25, 1.0))
+        c = random_setting(rng, n_r)
+        bits = tuple(c.bits) if c.algo == "phj" and c.passes else (0, 0)
+        g.append(dict(n_r=n_r, n_s=n_s, match=match, algo=c.algo, passes=c.passes, bits=bits,
+                      tile=c.tile if c.algo == "phj" and c.passes else 0, one_pass=c.one_pass))
+    return g
+
+
+def collect(out_path: str, reps: int = 3, quick: bool = False, settings: list | None = None) -> None:
+    """Times every kernel of every setting (the calibration grid unless given;
+    reps joins each, HIP events per launch, after steady_join_ms has warmed the
+    clocks and timed the whole join) and writes the raw records as JSON."""
     import torch
 
     from . import hj
     from .gen import device as dgen
     recs = []
-    grid = calibration_grid(quick)
+    grid = settings if settings is not None else calibration_grid(quick)
     cache = {}
     for i, c in enumerate(grid):
         key = (c["n_r"], c["n_s"], c["match"])
@@ -273,18 +312,10 @@ def collect(out_path: str, reps: int = 3, quick: bool = False) -> None:
         q = hj.hj_resolve_params(p, c["n_r"], c["n_s"])
         ws = hj.workspace(p, c["n_r"], c["n_s"])
         d = torch.zeros(1, dtype=torch.int64, device="cuda")
-        hj.hj_join(p, *t, out_r, out_s, ws, d)  # warm-up
-        torch.cuda.synchronize()
+        join_ms = steady_join_ms(lambda: hj.hj_join(p, *t, out_r, out_s, ws, d), reps)
         launches = []
         for _ in range(reps):
             launches.append(hj.hj_join_timed(p, *t, out_r, out_s, ws, d))
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            hj.hj_join(p, *t, out_r, out_s, ws, d)
-        b.record()
-        torch.cuda.synchronize()
         if int(d.item()) != m:
             raise AssertionError("calibration join %r gave %d pairs, expected %d" % (c, int(d.item()), m))
         names = [n for n, _ in launches[0]]
@@ -292,7 +323,7 @@ def collect(out_path: str, reps: int = 3, quick: bool = False) -> None:
         recs.append({"cfg": {**c, "bits": list(c["bits"])}, "resolved": {
             "algo": q.algo, "passes": q.passes, "bits": [q.bits[0], q.bits[1]], "tile": q.tile,
             "lds_cap": q.lds_cap, "one_pass": bool(q.flags & hj.HJ_FLAG_ONE_PASS)},
-            "pairs": m, "kernels": list(zip(names, ms)), "join_ms": a.elapsed_time(b) / reps})
+            "pairs": m, "kernels": list(zip(names, ms)), "join_ms": join_ms})
         del ws
         if i % 25 == 0:
             print("collect %d/%d %s %.4f ms" % (i, len(grid), c, recs[-1]["join_ms"]), file=sys.stderr, flush=True)
@@ -301,12 +332,19 @@ def collect(out_path: str, reps: int = 3, quick: bool = False) -> None:
     print(out_path)
 
 
-def fit_calibration(raw_path: str) -> None:
-    """Fits the model to raw per-kernel times and writes the calibration JSON
-    and the C++ include (the library must be rebuilt afterwards)."""
+def fit_calibration(raw_paths) -> None:
+    """Fits the model to raw per-kernel times (one or more --collect files) and
+    writes the calibration JSON and the C++ include (the library must be
+    rebuilt afterwards)."""
     from . import costmodel
-    with open(raw_path) as f:
-        raw = json.load(f)
+    if isinstance(raw_paths, str):
+        raw_paths = [raw_paths]
+    raw = {"records": []}
+    for path in raw_paths:
+        with open(path) as f:
+            r = json.load(f)
+        raw.setdefault("device", r.get("device"))
+        raw["records"] += r["records"]
     params, report = costmodel.fit(raw)
     rec = {"device": raw.get("device", "MI355X"), "source": "tune.py --fit of %d joins (%d launches)" % (
         report["joins"], report["launches"]), "params": params, "fit": report}
@@ -419,7 +457,8 @@ def validation_markdown(res: dict) -> str:
     lines = ["# Cost model against measurement on MI355X (Monte Carlo, %d random settings)" % s["runs"], "",
              "Command: `python -m paper_1307_1955_amd.tune --validate <out>.json` (settings: |R| log-uniform in "
              "[1024, 4194304], |S| = |R| x U{1..16}, match rate U[0.25, 1], random algorithm, passes, radix bits, "
-             "tile and output mode; each timed as the mean of 3 joins after 2 warm-ups, predicted by "
+             "tile and output mode; each timed at steady clocks (at least 2 ms of warm-up joins, then at least 3 joins "
+             "and 1 ms timed), predicted by "
              "`hj_model_seconds` with the true pair count).", "",
              "Within 15%% of the measured time: **%.1f%%** of the settings; median signed error %+.1f%%." % (
                  100 * s["within_15pct"], 100 * s["signed_err_median"]), "",

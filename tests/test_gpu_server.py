@@ -32,7 +32,8 @@ def requests(seed, n, r_max=1 << 17):
         o_r = torch.full((max(cap, 1),), -1, dtype=torch.int32, device=DEV)
         o_s = torch.full((max(cap, 1),), -1, dtype=torch.int32, device=DEV)
         p = tune.choose(sp.n_r, sp.n_s, table).params()
-        fp = 8 * (sp.n_r + sp.n_s) + 8 * cap + hj.hj_workspace_bytes(p, sp.n_r, sp.n_s)
+        # the server's own account: relations, output slots, the count, the workspace
+        fp = 8 * (sp.n_r + sp.n_s) + 8 * cap + 8 + hj.hj_workspace_bytes(p, sp.n_r, sp.n_s)
         reqs.append(dict(spec=sp, t=[rk, rr, sk, sr, o_r[:cap], o_s[:cap]], cap=cap, p=p, fp=fp))
     return reqs
 
@@ -93,6 +94,24 @@ def test_admission_cap_and_rejection():
     got = counts.cpu().numpy()
     for i, r in enumerate(reqs[1:], start=1):
         assert int(got[i]) == r["cap"]
+
+
+def test_footprint_floor():
+    """A request declared smaller than its own arrays and workspace is admitted by
+    the server's account of it: rejected under a cap below that account, run
+    under a cap at it."""
+    reqs = requests(23, 2)
+    r = reqs[1]
+    counts = torch.zeros(2, dtype=torch.int64, device=DEV)
+    ws = torch.empty(1 << 28, dtype=torch.uint8, device=DEV)
+    for cap, want in ((r["fp"] - 1, hj.HJ_ERR_CAPACITY), (r["fp"], hj.HJ_OK)):
+        sv = hj.Server(ws, mem_cap_bytes=cap, slots=1, max_batch_jobs=4)
+        t = sv.submit(*r["t"], counts[0:1], r["p"], 0)  # declared footprint 0
+        sv.drain()
+        done = {tk: st for tk, st, _, _ in sv.poll()}
+        assert done[t] == want, (cap, done)
+        sv.close()
+    assert int(counts[0].item()) == r["cap"]
 
 
 def test_many_small_requests():
