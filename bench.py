@@ -149,7 +149,8 @@ def bench_batched(args, torch, hj, wl, params, table) -> dict:
         "config": "4096 joins, |R| log-uniform in [1024, 4194304], |S| = |R| x U{1..16}, 25-100%% match; "
                   "sum |R|+|S| = %d tuples, %d pairs" % (wl.tuples, wl.pairs),
         "params": "tuning table" if table else "cost model",
-        "direct_jobs": plan.direct_jobs, "graph": True, "first_run_s_incl_capture": round(first_s, 3),
+        "direct_jobs": plan.direct_jobs, "graph": True, "graph_nodes": plan.graph_nodes,
+        "first_run_s_incl_capture": round(first_s, 3),
         "counts_match_closed_form": ok,
         "pairs_verified_on_device": not bad, "failed_jobs": bad[:8],
         "plain_per_join": {"value": len(wl.jobs) / (ms_plain * 1e-3), "ms": ms_plain,

@@ -275,6 +275,10 @@ size_t hj_batch_workspace_bytes(const hj_batch_plan* plan);
 /* Number of jobs of the plan that run in the multi-job direct kernel. */
 uint32_t hj_batch_direct_jobs(const hj_batch_plan* plan);
 
+/* Nodes (kernels, copies, event records and waits) of the HIP graph the plan
+   captured at its first graph run; 0 before that or with HJ_BATCH_NO_GRAPH. */
+size_t hj_batch_graph_nodes(const hj_batch_plan* plan);
+
 /* Enqueues every job of the plan on `stream` (asynchronous).  Each job's
    d_count receives its pair count; a job whose count exceeds its capacity
    writes nothing past its capacity. */

@@ -321,6 +321,12 @@ size_t hj_batch_workspace_bytes(const hj_batch_plan* plan) { return plan ? plan-
 
 uint32_t hj_batch_direct_jobs(const hj_batch_plan* plan) { return plan ? plan->ndirect : 0; }
 
+size_t hj_batch_graph_nodes(const hj_batch_plan* plan) {
+    if (!plan || !plan->graph) return 0;
+    size_t n = 0;
+    return hipGraphGetNodes(plan->graph, nullptr, &n) == hipSuccess ? n : 0;
+}
+
 hj_status hj_batch_run(hj_batch_plan* b, void* ws, size_t ws_bytes, void* stream) {
     if (!b) return fail(HJ_ERR_INVALID, "plan is NULL");
     if (!ws || ws_bytes < b->ws_bytes)

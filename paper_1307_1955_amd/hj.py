@@ -37,7 +37,7 @@ HJ_BATCH_NO_GRAPH = 1
 EXPORTED = (
     "hj_default_params", "hj_resolve_params", "hj_workspace_bytes", "hj_join", "hj_join_sync", "hj_join_timed",
     "hj_join_noalloc", "hj_join_external", "hj_model_seconds",
-    "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_run",
+    "hj_batch_plan_create", "hj_batch_workspace_bytes", "hj_batch_direct_jobs", "hj_batch_graph_nodes", "hj_batch_run",
     "hj_batch_plan_destroy", "hj_batch_bytes", "hj_batch", "hj_table_bytes", "hj_build",
     "hj_probe_workspace_bytes", "hj_probe", "hj_server_create", "hj_server_submit", "hj_server_submit_probe", "hj_server_poll", "hj_server_drain",
     "hj_server_stats", "hj_server_destroy", "hj_workspace_status", "hj_status_str", "hj_last_error",
@@ -161,6 +161,8 @@ def load() -> ctypes.CDLL:
             lib.hj_batch_workspace_bytes.argtypes = [ctypes.c_void_p]
             lib.hj_batch_direct_jobs.restype = ctypes.c_uint32
             lib.hj_batch_direct_jobs.argtypes = [ctypes.c_void_p]
+            lib.hj_batch_graph_nodes.restype = ctypes.c_size_t
+            lib.hj_batch_graph_nodes.argtypes = [ctypes.c_void_p]
             lib.hj_batch_run.restype = ctypes.c_int
             lib.hj_batch_run.argtypes = [ctypes.c_void_p, vp, ctypes.c_size_t, vp]
             lib.hj_batch_plan_destroy.restype = None
@@ -539,6 +541,11 @@ class BatchPlan:
     @property
     def direct_jobs(self) -> int:
         return int(load().hj_batch_direct_jobs(self._h))
+
+    @property
+    def graph_nodes(self) -> int:
+        """Nodes of the captured graph (0 before the first graph run)."""
+        return int(load().hj_batch_graph_nodes(self._h))
 
     def workspace(self, device="cuda") -> torch.Tensor:
         return torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)

@@ -100,6 +100,7 @@ def test_graph_replays_each_checked():
     d_counts = torch.zeros(len(dev), dtype=torch.int64, device=DEV)
     plan = hj.BatchPlan(dev, d_counts)
     ws = plan.workspace()
+    assert plan.graph_nodes == 0  # nothing captured before the first run
     for rep in range(3):
         for t in dev:
             t[4].fill_(-1)
@@ -109,6 +110,7 @@ def test_graph_replays_each_checked():
         plan.run(ws)
         torch.cuda.synchronize()
         check_jobs(host, dev, d_counts.cpu().numpy())
+        assert plan.graph_nodes >= len(dev)  # at least one kernel per job
         # unrelated eager work between replays
         x = torch.arange(1 << 20, device=DEV)
         assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
