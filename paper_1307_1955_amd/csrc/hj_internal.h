@@ -111,11 +111,13 @@ struct HeavyJob {
 };
 struct HeavyQueue {
     uint32_t n;            // tuples handed in (may exceed kHeavyJobs: the rest stay with their workgroup)
-    // PHJ one-pass write: set by the HBM-table build when a partition can hand
-    // tuples in; the write's workgroups then claim their items from item_next
-    // and, with none left, help the queue until items_done reaches the count
+    // PHJ one-pass write: the HBM-table build sets `wait` when a partition can
+    // hand tuples in (more than kHelpChunk rows) and adds that partition's
+    // work items to items_expected; those items count themselves done, and the
+    // write's helper workgroups help the queue until items_done reaches
+    // items_expected
     uint32_t wait;
-    uint32_t item_next;
+    uint32_t items_expected;
     uint32_t items_done;
     uint32_t pad[12];
     HeavyJob job[kHeavyJobs];

@@ -19,6 +19,8 @@
 // the same item and stores its pairs at the scanned offset, or one pass that
 // reserves each round's pairs on a running total (Section 3.3's dynamic
 // output allocation replaced by counting or by block reservation).
+#include <algorithm>
+
 #include "hj_device.h"
 #include "hj_heavy.h"
 #include "hj_internal.h"
@@ -75,8 +77,12 @@ __global__ void __launch_bounds__(256) k_ovf_build(const PartPair* __restrict__ 
         const RegionStep step{2u * pp.r_len};
         const uint32_t chunk = ovf_chunk(pp.r_len);
         const uint32_t end = min((c + 1) * chunk, pp.r_len);
-        // a partition the one-pass write may queue tuples of: its workgroups stay to help
-        if (heavy && c == 0 && threadIdx.x == 0 && pp.r_len > kHelpChunk) heavy->wait = 1;
+        // a partition the one-pass write may queue tuples of: the write's helpers
+        // wait until its work items are done
+        if (heavy && c == 0 && threadIdx.x == 0 && pp.r_len > kHelpChunk) {
+            atomicAdd(&heavy->items_expected, items_of(pp));
+            heavy->wait = 1;
+        }
         WavePush push;
         push.hot_keys = hot;
         for (uint32_t j0 = c * chunk; j0 < end; j0 += blockDim.x) {  // uniform trip count
@@ -551,23 +557,43 @@ __device__ __forceinline__ void write_item(const ItemLoc L, uint32_t w, uint32_t
     }
 }
 
-// Workgroups of a one-pass write beyond its items that help with queued heavy
-// tuples until every item is done (when a partition may queue tuples), and
-// the polls of the item count after which such a workgroup leaves anyway (its
+// Polls of the item count by a helper workgroup before it leaves anyway (its
 // help is only a speed-up: every queued chunk is also taken by the workgroup
 // that queued it).
-constexpr uint32_t kWaitHelpers = 256;
 constexpr uint32_t kHelpWaitPolls = 1u << 20;
+constexpr uint32_t kMaxHelpers = 256;
+
+// A helper's loop: help with the queued tuples until the items the build
+// counted are done.  Not inlined: inside the write kernel its registers cost
+// the item path 6-10 us at 16M x 16M (measured), while as a call they do not.
+__device__ __attribute__((noinline)) void help_until_done(HeavyQueue* heavy, const int32_t* rk, const int32_t* rr,
+                                                         unsigned long long* total, uint64_t capacity, int32_t* out_r,
+                                                         int32_t* out_s, uint32_t* lds, uint32_t* s_word) {
+    const uint32_t expected = heavy->items_expected;
+    for (uint32_t polls = 0;; ++polls) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            *s_word = __hip_atomic_load(&heavy->items_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const bool all_done = *s_word >= expected;
+        help_heavy<kJoinBlock>(heavy, rk, rr, total, capacity, out_r, out_s, lds);
+        if (all_done || polls >= kHelpWaitPolls) break;
+        __builtin_amdgcn_s_sleep(32);
+    }
+}
 
 // Write pass.  kOnePass: instead of reading a scanned per-wave offset, each
 // probe round reserves its pairs' output slots with block_reserve.  One-pass
-// with `heavy` (the grid then has kWaitHelpers workgroups beyond the items'
-// bound): every workgroup helps with the queued heavy tuples once its own item
-// is written.  When the HBM-table build set heavy->wait (a partition may queue
-// tuples), each workgroup takes its item by ticket (the order the workgroups
-// start in) instead of by its index, and the workgroups whose tickets are past
-// the last item keep helping until every item is done, so that a tuple queued
-// by the last items still finds helpers.
+// with `heavy`: every workgroup helps with the queued heavy tuples once its
+// own item is written, and the grid has helper workgroups past item_grid.
+// When the HBM-table build set heavy->wait (a partition may queue tuples), the
+// items of such partitions count themselves done and the helpers keep helping
+// until all of them are (the build counted them in items_expected), so that a
+// tuple queued late still finds helpers; otherwise the helpers leave at once.
+// (Counting every item instead cost the write ~0.26 ms at 16M x 16M: thousands
+// of atomics on the queue's line, which every workgroup also reads.)  The helpers are at most half
+// of the workgroups the device holds at once, so items always have room to
+// run, whatever order the workgroups start in.
 template <bool kOnePass, uint32_t RPT>
 __global__ void __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(RPT > kRptMid ? 4 : 6)))
 k_join_write(
@@ -577,62 +603,38 @@ k_join_write(
     uint32_t lds_cap, const uint64_t* __restrict__ ovf_table,
     const uint32_t* __restrict__ ovf_next, const HotKeys* __restrict__ hot, const uint64_t* __restrict__ wave_base,
     unsigned long long* __restrict__ total, int32_t* __restrict__ out_r, int32_t* __restrict__ out_s,
-    uint64_t capacity, HeavyQueue* heavy) {
+    uint64_t capacity, HeavyQueue* heavy, uint32_t item_grid) {
     extern __shared__ uint32_t lds[];
     __shared__ uint64_t wtot[kJoinWaves + 1];
     __shared__ uint32_t s_word;
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t live = item_begin[P];
-    const bool claim = kOnePass && heavy && heavy->wait;  // written by an earlier launch: uniform
-    uint32_t item;
-    if (claim) {
-        if (threadIdx.x == 0) s_word = atomicAdd(&heavy->item_next, 1u);
-        __syncthreads();
-        item = s_word;
-    } else {
-        item = live_remap(blockIdx.x, live);
-        if (item >= live) return;
+    if (kOnePass && heavy && blockIdx.x >= item_grid) {  // a helper
+        if (!heavy->wait) return;  // written by an earlier launch: uniform
+        help_until_done(heavy, rk, rr, total, capacity, out_r, out_s, lds, &s_word);
+        return;
     }
-    if (item < live) {
-        const ItemRec r = item_rec[item];
-        ItemLoc L;
-        L.item = item;
-        L.live = true;
-        L.r_off = r.r_off;
-        L.r_len = r.r_len;
-        L.s_begin = r.s_begin;
-        L.s_n = r.s_n;
-        const uint64_t base = kOnePass ? 0ull : wave_base[(uint64_t)item * kJoinWaves + w];
-        write_item<kOnePass, RPT>(L, w, lds, wtot, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, hot, base, total,
-                                  out_r, out_s, capacity, heavy);
-        if (claim) {
-            __syncthreads();  // the item's hand-offs are made
-            if (threadIdx.x == 0)
-                __hip_atomic_fetch_add(&heavy->items_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    const uint32_t item = live_remap(blockIdx.x, live);
+    if (item >= live) return;
+    const ItemRec r = item_rec[item];
+    ItemLoc L;
+    L.item = item;
+    L.live = true;
+    L.r_off = r.r_off;
+    L.r_len = r.r_len;
+    L.s_begin = r.s_begin;
+    L.s_n = r.s_n;
+    const uint64_t base = kOnePass ? 0ull : wave_base[(uint64_t)item * kJoinWaves + w];
+    write_item<kOnePass, RPT>(L, w, lds, wtot, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, hot, base, total,
+                              out_r, out_s, capacity, heavy);
     // one-pass: help with the heavy tuples any workgroup queued (the LDS
-    // tables are free now and give the scratch); with tickets, the first
-    // kWaitHelpers workgroups past the last item keep helping until every item
-    // is done.  Only those wait: their tickets come after every item's, so
-    // every item is then held by a workgroup that is running, while a
-    // workgroup that waited after its own item could keep one that has not
-    // started off the device.
+    // tables are free now and give the scratch)
     if (kOnePass && heavy) {
-        const bool wait = claim && item >= live && item - live < kWaitHelpers;
-        for (uint32_t polls = 0;; ++polls) {
-            bool all_done = true;
-            if (wait) {
-                __syncthreads();  // s_word free
-                if (threadIdx.x == 0)  // relaxed: the queue's own flags order what is read from it
-                    s_word = __hip_atomic_load(&heavy->items_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __syncthreads();
-                all_done = s_word >= live;
-            }
-            help_heavy<kJoinBlock>(heavy, rk, rr, total, capacity, out_r, out_s, lds);
-            if (all_done || polls >= kHelpWaitPolls) break;
-            __builtin_amdgcn_s_sleep(32);
+        if (L.r_len > kHelpChunk) {  // an item the helpers wait for (the build counted it)
+            __syncthreads();  // the item's hand-offs are made
+            if (threadIdx.x == 0) atomicAdd(&heavy->items_done, 1u);
         }
+        help_heavy<kJoinBlock>(heavy, rk, rr, total, capacity, out_r, out_s, lds);
     }
 }
 
@@ -818,10 +820,18 @@ void join_write_t(const PartPair* pairs, const uint32_t* item_begin, const ItemR
     const size_t lds = join_lds_bytes(lds_cap, true);
     allow_lds((const void*)k_join_write<kOnePass, RPT>, lds);
     rec.before(kOnePass ? "join_write_1pass" : "join_write");
-    if (kOnePass && heavy) grid += kWaitHelpers;
+    const uint32_t item_grid = grid;
+    if (kOnePass && heavy) {
+        // helpers: at most half the workgroups resident at once (by LDS and by
+        // the waves the register budget allows: 6 per SIMD, 4 for the large build)
+        const uint32_t by_lds = (uint32_t)(160u * 1024u / (lds + 1024u));  // lds: this launch's dynamic bytes
+        const uint32_t by_waves = (RPT > kRptMid ? 4u : 6u) * 4u / kJoinWaves;
+        const uint32_t resident = 256u * std::max(1u, std::min(by_lds, by_waves));
+        grid += std::max(1u, std::min(kMaxHelpers, resident / 2));
+    }
     hipLaunchKernelGGL((k_join_write<kOnePass, RPT>), dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs,
                        item_begin, item_rec, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, hot, wave_base,
-                       (unsigned long long*)total, out_r, out_s, capacity, heavy);
+                       (unsigned long long*)total, out_r, out_s, capacity, heavy, item_grid);
     rec.after();
 }
 
