@@ -99,7 +99,11 @@ def join_lds_bytes(cap: int) -> int:
 
 
 def join_slots(cap: int) -> int:
-    return CUS * max(1, LDS_PER_CU // (join_lds_bytes(cap) + 1024))
+    """Join work items resident at once: workgroups per CU by LDS and by the
+    waves the kernels' register budget allows (6 per SIMD, 4 with the largest
+    build), 512-thread workgroups."""
+    by_waves = (4 if cap > 4608 else 6) * 4 // 8
+    return CUS * max(1, min(LDS_PER_CU // (join_lds_bytes(cap) + 1024), by_waves))
 
 
 def _nonempty(mean: float) -> float:

@@ -47,9 +47,12 @@ double scatter_slots(uint32_t bits, uint32_t tile) {
 
 double hist_slots(uint32_t tile) { return kCus * std::floor(2048 / part_block(tile)); }
 
+// Join work items resident at once: workgroups per CU by LDS and by the waves
+// the kernels' register budget allows (6 per SIMD, 4 with the largest build).
 double join_slots(uint32_t cap) {
     const double lds = 4.0 * (cap + 128) + 8.0 * cap;
-    return kCus * std::max(1.0, std::floor(kLdsPerCu / (lds + 1024)));
+    const double by_waves = (join_rpt(cap) > kRptMid ? 4.0 : 6.0) * 4.0 / kJoinWaves;
+    return kCus * std::max(1.0, std::min(std::floor(kLdsPerCu / (lds + 1024)), std::floor(by_waves)));
 }
 
 double nonempty(double mean) { return mean < 30 ? 1.0 - std::exp(-mean) : 1.0; }
