@@ -261,9 +261,8 @@ typedef struct hj_batch_plan hj_batch_plan;
 #define HJ_BATCH_NO_GRAPH 1u
 
 /* Creates a plan for `njobs` jobs (host array, copied).  params: host array of
-   njobs parameter sets, or NULL for the library's size rule (passes 0 when |R|
-   fits the LDS budget, else PHJ with about 4096 R tuples per partition and
-   HJ_FLAG_ONE_PASS).  Pointers inside the jobs must stay valid while the plan
+   njobs parameter sets, or NULL for the library's choice per job (HJ_AUTO with
+   HJ_FLAG_ONE_PASS: the plan the cost model rates fastest).  Pointers inside the jobs must stay valid while the plan
    is used.  Allocates pinned host memory and creates streams and events; no
    device memory. */
 hj_status hj_batch_plan_create(uint32_t njobs, const hj_job* jobs, const hj_params* params, uint32_t flags,

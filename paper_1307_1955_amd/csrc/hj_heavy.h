@@ -193,11 +193,12 @@ __device__ __forceinline__ void heavy_writes(const int32_t* __restrict__ rk, con
 // A workgroup hands the heavy tuples it registered to the queue (hand_off);
 // every workgroup, once its own work is written, runs help_heavy: for each
 // queued tuple it claims chunks of the tuple's R rows and writes its matches
-// in them, each
-// scan step reserving its slots on the running total (one-pass output has no
-// fixed order, so no count is needed first).  Nothing waits: a workgroup
-// takes what is unclaimed and leaves; the workgroup that queued a tuple runs
-// help_heavy too, so every chunk is written before the launch ends.
+// in them, each scan step reserving its slots on the running total (one-pass
+// output has no fixed order, so no count is needed first).  A workgroup takes
+// what is unclaimed and leaves; the workgroup that queued a tuple runs
+// help_heavy too, so every chunk is written before the launch ends.  (The
+// PHJ write adds helper workgroups that wait, bounded, for tuples that its
+// last items may still queue: k_join_write.)
 
 // Moves this block's registered heavy tuples to the queue while it has room
 // (marked in hs->queued); a tuple that finds the queue full stays with the

@@ -523,7 +523,8 @@ class BatchPlan:
     jobs: sequence of (r_key, r_rid, s_key, s_rid, out_r, out_s) CUDA tensors;
     d_counts: int64 CUDA tensor with one element per job (job j's count is
     d_counts[j]); params: sequence of HjParams (one per job) or None for the
-    library's size rule; graph=False enqueues without a HIP graph.
+    library's choice per job (HJ_AUTO, one-pass); graph=False enqueues
+    without a HIP graph.
     The tensors must stay alive while the plan is used."""
 
     def __init__(self, jobs, d_counts: torch.Tensor, params=None, graph: bool = True):

@@ -7,8 +7,9 @@ Reads the CSV output of
   * the same two counters for a plain device copy of known size,
 and writes a short markdown table plus a JSON record.  HBM bytes of a kernel
 = counter KiB * 1024 * (copy bytes / copy counter bytes): the copy scales each
-counter to true bytes.  The JSON keeps a hash of the kernel sources so a
-consumer can tell whether the kernels changed since the counters were taken.
+counter to true bytes.  The JSON keeps a hash of the kernel sources' code
+(comments excluded) so a consumer can tell whether the kernels changed since
+the counters were taken.
 """
 from __future__ import annotations
 
@@ -26,11 +27,39 @@ KERNEL_SOURCES = ["csrc/phj_partition.hip", "csrc/phj_join.hip", "csrc/shj.hip",
                   "csrc/hj_device.h", "csrc/hj_heavy.h", "csrc/hj_internal.h"]
 
 
+def code_only(text: str) -> str:
+    """C/C++ source without its comments, each line stripped and empty lines
+    dropped: what the compiler sees, so that edits of comments alone keep the
+    hash (string and character literals are kept as they are)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = (" ".join(ln.split()) for ln in "".join(out).splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def sources_hash() -> str:
+    """sha256 over the kernel sources' code (comments excluded)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(PKG, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(PKG, rel), "r", encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()
 
 
@@ -106,7 +135,7 @@ def main():
         lines.append("| %s | %d | %.1f | %s | %s |" % (r["kernel"], r["calls"], r["avg_us"], fmt(r["hbm_read_mb"]),
                                                       fmt(r["hbm_write_mb"])))
     lines.append("")
-    lines.append("Kernel sources sha256 at measurement: `%s`" % rec["sources_sha256"])
+    lines.append("Kernel sources sha256 at measurement (code without comments): `%s`" % rec["sources_sha256"])
     with open(a.out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(a.out_md, a.out_json)
