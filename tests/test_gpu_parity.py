@@ -233,6 +233,30 @@ def test_phj_heavy_queue(kw, n_heavy_s):
     check_small(hj.params(**kw), rk, r.rid, sk, s.rid)
 
 
+@pytest.mark.parametrize("kw", [dict(algo="phj", passes=1, bits=(6,), one_pass=True),
+                                dict(algo="phj", passes=2, bits=(3, 3), one_pass=True),
+                                dict(algo="phj", passes=2, bits=(3, 3), one_pass=False)],
+                         ids=["6_1pass", "3_3_1pass", "3_3"])
+def test_phj_heavy_queue_many_partitions(kw):
+    """Four keys with 70000 R rows each, in four different partitions (identity
+    hash: the key's low bits), so the overflow build flags four partitions and
+    sums their work items for the write's helpers to wait on; S tuples hit
+    three of the keys (the fourth partition is flagged but queues nothing).
+    Every pair against the oracle."""
+    n_r, n_s = 1 << 20, 1 << 21
+    r, s = gen.unique_uniform(35, n_r, n_s, 2 * n_r)
+    rng = np.random.default_rng(36)
+    rk = r.key.copy()
+    keys = [77, 78, 79, 80]  # partitions 13, 14, 15, 16 of 64
+    rows = rng.permutation(n_r)[: 4 * 70000].reshape(4, 70000)
+    for k, rw in zip(keys, rows):
+        rk[rw] = k
+    sk = s.key.copy()
+    for k in keys[:3]:
+        sk[rng.choice(n_s, 25, replace=False)] = k
+    check_small(hj.params(**kw), rk, r.rid, sk, s.rid)
+
+
 @pytest.mark.parametrize("one_pass", [True, False])
 def test_sorted_r_short_duplicate_runs(one_pass):
     """R sorted with 32 duplicates per key: every build wave pushes runs of 32 rows
