@@ -183,7 +183,10 @@ struct PhjWs {
     hj::PartSeg* segs2;
     uint32_t* tb2;
     uint32_t* tseg2;
-    uint32_t* hist2;
+    uint32_t* hist2;     // pass-2 histogram (not counted)
+    uint16_t* rows;      // pass-1 count rows (counted pass 2)
+    uint32_t* tot2;      // counted pass 2: final partition totals (zeroed block)
+    uint32_t* cur2;      //   and reservation cursors (zeroed block)
     int32_t *keyB, *ridB;
     hj::PartPair* pairs;
     uint32_t* item_begin;
@@ -219,12 +222,16 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, v
     w.hist1 = c.take<uint32_t>(w.tiles1 * pl.P1);
     w.keyA = c.take<int32_t>(n);
     w.ridA = c.take<int32_t>(n);
+    const bool counted = hj::counted_pass2(pl.passes, pl.b1, pl.b2);
     if (pl.passes == 2) {
         w.tiles2_ub = cdiv(n, pl.tile) + 2ull * pl.P1;
         w.segs2 = c.take<hj::PartSeg>(2ull * pl.P1);
         w.tb2 = c.take<uint32_t>(2ull * pl.P1 + 1);
         w.tseg2 = c.take<uint32_t>(w.tiles2_ub);
-        w.hist2 = c.take<uint32_t>(w.tiles2_ub * pl.P2);
+        if (counted)
+            w.rows = c.take<uint16_t>(w.tiles1 * pl.P);
+        else
+            w.hist2 = c.take<uint32_t>(w.tiles2_ub * pl.P2);
         w.keyB = c.take<int32_t>(n);
         w.ridB = c.take<int32_t>(n);
     }
@@ -239,22 +246,27 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, v
     w.ovf_table = c.take<uint64_t>(2 * n_r_tab);
     w.ovf_next = c.take<uint32_t>(n_r_tab);
     const uint64_t n1 = hj::scan_state_words(w.tiles1 * pl.P1);
-    const uint64_t n2 = pl.passes == 2 ? hj::scan_state_words(w.tiles2_ub * pl.P2) : 0;
+    const uint64_t n2 = pl.passes == 2 && !counted ? hj::scan_state_words(w.tiles2_ub * pl.P2) : 0;
     const uint64_t nw = hj::scan_state_words(w.items_ub * hj::kJoinWaves);
     const uint64_t np = hj::plan_state_words(pl.P);
     static_assert(sizeof(hj::HotKeys) % sizeof(uint64_t) == 0, "hot keys in whole words");
     const uint64_t nq = sizeof(hj::HeavyQueue) / sizeof(uint64_t) + sizeof(hj::HotKeys) / sizeof(uint64_t);
-    uint64_t* zero = c.take<uint64_t>(nq + n1 + n2 + nw + np);
+    const uint64_t nc = counted ? 2ull * pl.P : 0;  // totals and cursors: 2 P words of 32 bits each
+    uint64_t* zero = c.take<uint64_t>(nq + nc + n1 + n2 + nw + np);
     w.heavy = reinterpret_cast<hj::HeavyQueue*>(zero);
     w.hot = zero ? reinterpret_cast<hj::HotKeys*>(zero + sizeof(hj::HeavyQueue) / sizeof(uint64_t)) : nullptr;
     if (zero) {  // (sizing only when there is no base: no arithmetic on a null pointer)
-        w.st1 = zero + nq;
+        if (counted) {
+            w.tot2 = reinterpret_cast<uint32_t*>(zero + nq);
+            w.cur2 = w.tot2 + 2ull * pl.P;
+        }
+        w.st1 = zero + nq + nc;
         w.st2 = w.st1 + n1;
         w.stw = w.st2 + n2;
         w.stp = w.stw + nw;
     }
     w.zero = zero;
-    w.nzero = nq + n1 + n2 + nw + np;
+    w.nzero = nq + nc + n1 + n2 + nw + np;
     w.bytes = c.off;
     return w;
 }
@@ -418,8 +430,13 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
                    uint64_t* zero_total, int32_t** fk, int32_t** fr, hj::Recorder& rec) {
     const uint32_t n_r = (uint32_t)R.n, n_s = (uint32_t)S.n;
     const bool two = pl.passes == 2;
-    const hj::Pass1 p1 = hj::make_pass1(R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, w.segs1, w.tb1,
-                                        w.zero, w.nzero, rec.err_clear);
+    const bool counted = two && w.rows;  // (w.rows is set exactly for a counted pass 2 with a workspace)
+    hj::Pass1 p1 = hj::make_pass1(R.key, R.rid, n_r, S.key, S.rid, n_s, pl.tile, pl.b1, w.segs1, w.tb1,
+                                  w.zero, w.nzero, rec.err_clear);
+    if (counted) {
+        p1.rows = w.rows;
+        p1.bits_all = pl.B;
+    }
     // the join plan rides on the last pass's scatter, the pass-2 setup on the first
     // The plan's records are written at offsets from its chained scan; its wait
     // keeps the full bound and no injected stall (every consumer of the other
@@ -431,7 +448,7 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
     plan.plan = hj::PlanArgs{two ? w.segs2 : w.segs1, two ? w.tb2 : w.tb1, two ? w.hist2 : w.hist1,
                              two ? 2 * pl.P1 : 2u, two ? pl.b2 : pl.b1, n_r, n_s, pl.B, pl.lds_cap,
                              w.pairs, w.item_begin, w.ovf_begin, w.item_rec, w.ovf_part, zero_total, w.stp,
-                             r_pairs, plan_ctl};
+                             r_pairs, plan_ctl, counted ? w.tot2 : nullptr};
     hj::SideJob setup2{};
     if (two) {
         setup2.kind = hj::kSideSetup2;
@@ -440,6 +457,11 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
                                        w.segs2, w.tb2, w.tseg2};
     }
     hj::PassCfg c1{pl.b2, pl.b1, pl.hash, pl.tile};
+    if (counted) {  // the count rows are summed beside the pass-1 scatter's tiles
+        setup2.sums = hj::make_count_sums(w.rows, w.tot2, p1.nt_r, p1.ntiles - p1.nt_r, pl.B,
+                                          hj::part_block(pl.tile));
+        setup2.front = hj::count_sum_blocks(setup2.sums, hj::part_block(pl.tile));
+    }
     hj::part_hist_pass1(p1, c1, w.hist1, rec);  // also writes segs1/tb1 and clears the scan states
     hj::scan_u32(w.hist1, w.hist1, w.tiles1 * pl.P1, w.st1, nullptr, rec);
     hj::part_scatter(w.segs1, w.tb1, nullptr, 2, (uint32_t)w.tiles1, c1, w.hist1, w.keyA, w.ridA,
@@ -448,10 +470,16 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
     *fr = w.ridA;
     if (two) {
         hj::PassCfg c2{0, pl.b2, pl.hash, pl.tile};
-        hj::part_hist(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, rec);
-        hj::scan_u32(w.hist2, w.hist2, w.tiles2_ub * pl.P2, w.st2, nullptr, rec);
-        hj::part_scatter(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, w.keyB,
-                         w.ridB, plan, rec);
+        if (counted) {
+            const hj::Reserve rsv{w.tot2, w.cur2};
+            hj::part_scatter(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, nullptr, w.keyB,
+                             w.ridB, plan, rec, &rsv);
+        } else {
+            hj::part_hist(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, rec);
+            hj::scan_u32(w.hist2, w.hist2, w.tiles2_ub * pl.P2, w.st2, nullptr, rec);
+            hj::part_scatter(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, w.keyB,
+                             w.ridB, plan, rec);
+        }
         *fk = w.keyB;
         *fr = w.ridB;
     }

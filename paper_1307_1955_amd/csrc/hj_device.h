@@ -258,6 +258,14 @@ __device__ __forceinline__ uint32_t chain_len(const uint32_t* __restrict__ next,
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Uses v here, on every path: a load or atomic that returns v is awaited at
+// this point (an empty statement that only reads the register).  The
+// compiler's waits on the vector-memory counter do not follow branches: a
+// result that some path may still have in flight makes it wait on that
+// counter again wherever the register is reused, and such a wait also waits
+// for every store in flight, which serializes a store loop.
+__device__ __forceinline__ void settle(uint32_t v) { __asm__ volatile("" ::"v"(v)); }
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const uint32_t l = lane_id();
     return l == 0 ? 0ull : (~0ull >> (64 - l));

@@ -160,6 +160,53 @@ struct PassCfg {
     uint32_t hash_kind;  // hj_hash
     uint32_t tile;       // tuples per tile
 };
+// Two passes whose final partitions number 2^3..2^kCountedMaxBits are
+// "counted": pass 1 also counts every tile's tuples per final partition (one
+// 16-bit row of 2^bits counts per tile: a tile holds at most 8192 tuples),
+// extra workgroups of the pass-1 scatter sum the rows into per-relation
+// totals, and pass 2 has no histogram of its own: each pass-2 tile places
+// its runs at the scanned totals of its segment plus what it reserves on a
+// cursor per final partition (the order of tiles inside a partition is then
+// the order of their reservations).  More bits would make the rows larger
+// than the pass-2 histogram read they replace.
+constexpr uint32_t kCountedMaxBits = 13;
+inline bool counted_pass2(uint32_t passes, uint32_t b1, uint32_t b2) {
+    return passes == 2 && b1 + b2 >= 3 && b1 + b2 <= kCountedMaxBits;
+}
+// A counted pass 2's totals and cursors, each 2^(b1 + b2) entries for R then
+// as many for S (index = segment * 2^b2 + partition in the segment).
+struct Reserve {
+    const uint32_t* tot;
+    uint32_t* cur;  // zero before the pass
+};
+// The sums of a counted pass 2's count rows (Pass1::rows: nt_r rows of R, then
+// nt_s of S, 2^bits 16-bit counts each) into tot[rel * 2^bits + i] (zero
+// before), by extra workgroups at the front of the pass-1 scatter's grid: the
+// totals are needed only by pass 2, so the sums run beside the scatter's
+// tiles.  Each workgroup takes `rows_per` rows of one relation and a group of
+// 8-count columns.
+struct CountSums {
+    const uint16_t* rows;
+    uint32_t* tot;
+    uint32_t nt_r, nt_s, bits, rows_per;
+};
+__host__ __device__ inline uint32_t count_sum_groups(uint32_t bits, uint32_t block) {
+    const uint32_t cols = (1u << bits) / 8;
+    return (cols + block - 1) / block;
+}
+// About 128 workgroups in all (their sums are added with atomics), 8 rows at least.
+inline CountSums make_count_sums(const uint16_t* rows, uint32_t* tot, uint32_t nt_r, uint32_t nt_s, uint32_t bits,
+                                 uint32_t block) {
+    const uint64_t want = ((uint64_t)(nt_r + nt_s) * count_sum_groups(bits, block) + 127) / 128;
+    return CountSums{rows, tot, nt_r, nt_s, bits, want > 8 ? (uint32_t)want : 8u};
+}
+// Workgroups of the sums, rounded up to a multiple of 8 (the scatter's tiles
+// keep their XCD mapping behind them; the extra ones have no rows).
+inline uint32_t count_sum_blocks(const CountSums& c, uint32_t block) {
+    const uint32_t b = count_sum_groups(c.bits, block) *
+                       ((c.nt_r + c.rows_per - 1) / c.rows_per + (c.nt_s + c.rows_per - 1) / c.rows_per);
+    return (b + 7) / 8 * 8;
+}
 // Pass 1 of a join: R and S are its two segments (tiles numbered R first).
 // The pass-1 histogram takes them from here, as plain launch arguments, and
 // its first workgroup writes what later launches read from memory: the two
@@ -178,6 +225,11 @@ struct Pass1 {
     uint64_t* zero;
     uint64_t nzero;
     uint64_t* err_clear;  // the call's error word, cleared with the scan states (or nullptr)
+    // counted pass 2: rows[tile * 2^bits_all + i] = tuples of the tile in final
+    // partition i = hash & (2^bits_all - 1) (nullptr: no counting)
+    uint16_t* rows;
+    uint32_t bits_all;
+    uint32_t pad;
 };
 Pass1 make_pass1(const int32_t* rk, const int32_t* rr, uint32_t n_r, const int32_t* sk, const int32_t* sr,
                  uint32_t n_s, uint32_t tile, uint32_t bits, PartSeg* segs, uint32_t* tile_begin, uint64_t* zero,
@@ -195,9 +247,10 @@ void part_starts(const uint32_t* hist_scan, uint32_t ntiles, uint32_t bits, uint
 // `side`: extra workgroups appended to the grid that run the next step's setup
 // (hj_side.h: the pass-2 segment table or the join plan).
 struct SideJob;
+// rsv (counted pass 2): offsets from the totals and cursors instead of hist_scan.
 void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                   uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
-                  int32_t* rid_out, const SideJob& side, Recorder& rec);
+                  int32_t* rid_out, const SideJob& side, Recorder& rec, const Reserve* rsv = nullptr);
 
 // ---- phj_join.hip ----
 constexpr uint32_t kJoinBlock = 512;

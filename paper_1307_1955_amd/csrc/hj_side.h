@@ -42,6 +42,8 @@ struct PlanArgs {
     // histogram scan like S's
     const PartPair* r_pairs;
     ScanCtl ctl;  // the chained scan of the plan reports a give-up here
+    // counted pass 2: final partition sizes (Reserve::tot) instead of hist_scan
+    const uint32_t* tot;
 };
 
 enum SideKind : uint32_t { kSideNone = 0, kSideSetup2 = 1, kSidePlan = 2 };
@@ -51,6 +53,10 @@ struct SideJob {
     uint32_t blocks;  // extra workgroups at the end of the grid
     Setup2Args setup2;
     PlanArgs plan;
+    // workgroups at the front of the grid (a multiple of 8) that sum count
+    // rows (front == 0: none)
+    uint32_t front, pad;
+    CountSums sums;
 };
 
 // Join-plan workgroups of `block` threads (one partition pair per thread).
@@ -80,14 +86,55 @@ __device__ __forceinline__ uint32_t ovf_chunks_of(const PartPair& pp, uint32_t l
     return (pp.r_len > lds_cap && pp.s_len) ? (pp.r_len + chunk - 1) / chunk : 0u;
 }
 
+// Final partition starts of a counted pass 2 for this workgroup's partitions
+// i = blk * blockDim + threadIdx.x: R's in the low and S's in the high 32 bits
+// (relative to each relation; R's left 0 with r_pairs).  Partition i is
+// partition i mod 2^bits_last of segment i >> bits_last (one per pass-1
+// partition), which starts at the segment's out_base; inside the segment the
+// start is the sum of the totals of the partitions before it.  That sum is a
+// block scan of the totals, less its value at the segment's first partition
+// in the block, plus the totals of the segment's partitions in earlier blocks
+// when the segment began before this block (2^bits_last > blockDim).
+// `ex`: LDS of blockDim words of 64 bits.  Contains __syncthreads().
+__device__ __forceinline__ uint64_t counted_starts(const PlanArgs& A, uint32_t blk, uint64_t* wt, uint64_t* ex,
+                                                   uint64_t* v_out) {
+    const uint32_t P = 1u << A.total_bits, b2 = A.bits_last;
+    const uint32_t P1 = P >> b2;
+    const uint32_t i0 = blk * blockDim.x, i = i0 + threadIdx.x;
+    auto packed = [&](uint32_t j) -> uint64_t {
+        return (A.r_pairs ? 0ull : (uint64_t)A.tot[j]) | (uint64_t)A.tot[P + j] << 32;
+    };
+    const uint64_t v = i < P ? packed(i) : 0ull;
+    *v_out = v;
+    // totals of the block's first segment that lie before the block
+    const uint32_t seg_first = (i0 >> b2) << b2;
+    uint64_t pre = 0;
+    for (uint32_t j = seg_first + threadIdx.x; j < i0; j += blockDim.x) pre += packed(j);
+    uint64_t pre_tot;
+    (void)block_excl_scan(pre, wt, &pre_tot);
+    uint64_t tot;
+    const uint64_t e = block_excl_scan(v, wt, &tot);
+    ex[threadIdx.x] = e;
+    __syncthreads();
+    const uint32_t s_i = max(i0, (i >> b2) << b2);  // first partition of i's segment in this block
+    uint64_t within = e - ex[s_i - i0] + (s_i == i0 ? pre_tot : 0ull);
+    __syncthreads();
+    if (i >= P) return 0;
+    const uint32_t q = i >> b2;
+    const uint64_t r0 = A.r_pairs ? 0ull : A.segs[q].out_base + (uint32_t)within;
+    const uint64_t s0 = A.segs[P1 + q].out_base - A.n_r + (uint32_t)(within >> 32);
+    return (uint64_t)(uint32_t)r0 | (uint64_t)(uint32_t)s0 << 32;
+}
+
 // Plan (one thread per partition pair, workgroups in ticket order): ranges of
-// R_i and S_i from the last pass's histogram scan, the pair's work items and
-// HBM-table build chunks, their exclusive scans over all pairs (one chained
-// scan of both counts packed in one word), the work-item records and the
-// chunk -> pair map.
+// R_i and S_i from the last pass's histogram scan (or a counted pass 2's
+// totals), the pair's work items and HBM-table build chunks, their exclusive
+// scans over all pairs (one chained scan of both counts packed in one word),
+// the work-item records and the chunk -> pair map.
 // state[0]: ticket; state[1 + b]: status of workgroup b (cleared beforehand).
-// Run by plan_blocks(P, blockDim.x) workgroups.
-__device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
+// Run by plan_blocks(P, blockDim.x) workgroups.  `lds`: blockDim words of 64
+// bits of scratch (a counted pass 2).
+__device__ __forceinline__ void join_plan_block(const PlanArgs& A, uint64_t* lds) {
     const PartSeg* __restrict__ segs = A.segs;
     const uint32_t* __restrict__ tile_begin = A.tile_begin;
     const uint32_t nseg = A.nseg, bits_last = A.bits_last, n_r = A.n_r, n_s = A.n_s;
@@ -112,7 +159,27 @@ __device__ __forceinline__ void join_plan_block(const PlanArgs& A) {
     if (i == 0 && zero_total) *zero_total = 0;
     PartPair pp{0, 0, 0, 0};
     uint32_t ni = 0, no = 0;
-    if (i < P) {
+    if (A.tot) {  // uniform
+        uint64_t v;
+        const uint64_t st = counted_starts(A, blk, wt, lds, &v);
+        if (i < P) {
+            // clamped: a partition never extends past its relation
+            const uint32_t s0 = min((uint32_t)(st >> 32), n_s);
+            pp.s_off = s0;
+            pp.s_len = min(s0 + (uint32_t)(v >> 32), n_s) - s0;
+            if (A.r_pairs) {
+                const PartPair q = A.r_pairs[i];
+                pp.r_off = q.r_off;
+                pp.r_len = q.r_len;
+            } else {
+                const uint32_t r0 = min((uint32_t)st, n_r);
+                pp.r_off = r0;
+                pp.r_len = min(r0 + (uint32_t)v, n_r) - r0;
+            }
+            ni = items_of(pp);
+            no = ovf_chunks_of(pp, lds_cap);
+        }
+    } else if (i < P) {
         const uint32_t s0 = min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i, n_s, n_r, P), n_s);
         // clamped: a partition never extends past its relation or runs backwards
         const uint32_t s1 = max(s0, min(final_start(segs, tile_begin, hist_scan, 1, nseg_rel, bits_last, i + 1, n_s, n_r, P), n_s));
@@ -238,13 +305,47 @@ __device__ __forceinline__ void setup_pass2_block(const Setup2Args& A, uint32_t*
 }
 
 
+// Workgroup b of the count-row sums (CountSums): rows [row0, row1) of one
+// relation and the 8-count columns c of one column group, summed in registers
+// (16-byte loads, eight rows in flight), then added to the totals.
+__device__ __forceinline__ void sum_count_rows(const CountSums& A, uint32_t b) {
+    const uint32_t PA = 1u << A.bits;
+    const uint32_t C = PA / 8;
+    const uint32_t cg = count_sum_groups(A.bits, blockDim.x);
+    const uint32_t rg_r = (A.nt_r + A.rows_per - 1) / A.rows_per;
+    const uint32_t rg_s = (A.nt_s + A.rows_per - 1) / A.rows_per;
+    const uint32_t c = (b % cg) * blockDim.x + threadIdx.x;
+    const uint32_t q = b / cg;
+    if (q >= rg_r + rg_s) return;  // rounding workgroups
+    const uint32_t rel = q >= rg_r;
+    const uint32_t first = rel ? A.nt_r : 0u, last = rel ? A.nt_r + A.nt_s : A.nt_r;
+    const uint32_t row0 = first + (q - (rel ? rg_r : 0u)) * A.rows_per;
+    const uint32_t row1 = min(row0 + A.rows_per, last);
+    if (c >= C || row0 >= row1) return;
+    const uint4* __restrict__ src = reinterpret_cast<const uint4*>(A.rows) + (uint64_t)row0 * C + c;
+    uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint32_t n = row1 - row0;
+#pragma unroll 8
+    for (uint32_t r = 0; r < n; ++r) {
+        const uint4 w = src[(uint64_t)r * C];
+        acc[0] += w.x & 0xFFFFu; acc[1] += w.x >> 16;
+        acc[2] += w.y & 0xFFFFu; acc[3] += w.y >> 16;
+        acc[4] += w.z & 0xFFFFu; acc[5] += w.z >> 16;
+        acc[6] += w.w & 0xFFFFu; acc[7] += w.w >> 16;
+    }
+    uint32_t* __restrict__ tot = A.tot + (uint64_t)rel * PA + 8ull * c;
+#pragma unroll
+    for (uint32_t e = 0; e < 8; ++e)
+        if (acc[e]) atomicAdd(&tot[e], acc[e]);
+}
+
 // Runs the side job on workgroup `b` of its extra workgroups.  `lds`: the
 // hosting kernel's dynamic LDS (lds_words words).
 __device__ __forceinline__ void run_side_job(const SideJob& J, uint32_t b, uint32_t* lds, uint32_t lds_words) {
     if (J.kind == kSideSetup2) {
         if (b == 0) setup_pass2_block(J.setup2, lds, lds_words);
     } else if (J.kind == kSidePlan) {
-        join_plan_block(J.plan);
+        join_plan_block(J.plan, reinterpret_cast<uint64_t*>(lds));
     }
 }
 

@@ -131,24 +131,31 @@ __device__ __forceinline__ void pass1_setup(const Pass1& A) {
 }
 
 // kPass1: the tiles of R and S from the launch arguments (p1), and workgroup 0
-// also does the pass's set-up; else the segments in memory.
-template <uint32_t BLOCK, uint32_t IPT, bool kPass1>
+// also does the pass's set-up; else the segments in memory.  kCount (pass 1 of
+// a counted pass 2): the tile's counts per final partition are also written,
+// as row p1.rows + tile * 2^bits_all of 16-bit counts.
+template <uint32_t BLOCK, uint32_t IPT, bool kPass1, bool kCount>
 __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__ segs,
                                                          const uint32_t* __restrict__ tile_begin,
                                                          const uint32_t* __restrict__ tile_seg,
                                                          uint32_t nseg, PassCfg cfg,
                                                          uint32_t* __restrict__ hist, Pass1 p1) {
+    static_assert(kPass1 || !kCount, "counting rides on pass 1");
     extern __shared__ uint32_t lds[];
     constexpr uint32_t T = BLOCK * IPT;
     uint32_t* cnt = lds;
     const uint32_t P = 1u << cfg.bits;
+    const uint32_t PA = kCount ? 1u << p1.bits_all : 0u;
+    uint32_t* cnt_all = lds + P;  // [PA] (kCount)
     const int32_t* __restrict__ kin;
     uint32_t len, tl, nt;
     uint64_t hist_base;
+    uint32_t row = 0;
     if (kPass1) {
         if (blockIdx.x == 0) pass1_setup(p1);
         const uint32_t tile = live_remap(blockIdx.x, p1.ntiles);
         if (tile >= p1.ntiles) return;
+        row = tile;
         const bool s1 = tile >= p1.nt_r;  // field by field: no dynamic index into the arguments
         tl = s1 ? tile - p1.nt_r : tile;
         nt = s1 ? p1.ntiles - p1.nt_r : p1.nt_r;
@@ -171,12 +178,16 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
     const uint64_t valid = load_tile_vec<BLOCK, IPT>(kin, len, keys, kx);
     // counters cleared while the tile's loads are in flight
     for (uint32_t i = threadIdx.x; i < P; i += BLOCK) cnt[i] = 0;
+    if (kCount)
+        for (uint32_t i = threadIdx.x; i < PA; i += BLOCK) cnt_all[i] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (uint32_t k = 0; k < IPT; ++k) {
         const bool ok = (valid >> k) & 1u;
-        const uint32_t p = part_of(keys[k], cfg);
+        const uint32_t h = radix_hash(keys[k], cfg.hash_kind);
+        const uint32_t p = (h >> cfg.shift) & (P - 1u);
+        if (kCount && ok) atomicAdd(&cnt_all[h & (PA - 1u)], 1u);
         if (cfg.bits <= kBallotMaxBits) {
             const uint64_t m = match_mask(p, cfg.bits, ok);
             if (ok && (m & lt) == 0) atomicAdd(&cnt[p], (uint32_t)__popcll(m));
@@ -184,10 +195,22 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
             atomicAdd(&cnt[p], 1u);
         }
     }
-    if ((valid >> IPT) & 1u) atomicAdd(&cnt[part_of(kx, cfg)], 1u);
+    if ((valid >> IPT) & 1u) {
+        const uint32_t h = radix_hash(kx, cfg.hash_kind);
+        atomicAdd(&cnt[(h >> cfg.shift) & (P - 1u)], 1u);
+        if (kCount) atomicAdd(&cnt_all[h & (PA - 1u)], 1u);
+    }
     __syncthreads();
     uint32_t* __restrict__ h = hist + hist_base + tl;
     for (uint32_t p = threadIdx.x; p < P; p += BLOCK) h[(uint64_t)p * nt] = cnt[p];
+    if (kCount) {
+        // 8 counts (each <= T <= 8192) per 16-byte store; PA >= 8
+        uint4* __restrict__ out = reinterpret_cast<uint4*>(p1.rows + (uint64_t)row * PA);
+        for (uint32_t c = threadIdx.x; c < PA / 8; c += BLOCK) {
+            const uint32_t* v = cnt_all + 8 * c;
+            out[c] = make_uint4(v[0] | v[1] << 16, v[2] | v[3] << 16, v[4] | v[5] << 16, v[6] | v[7] << 16);
+        }
+    }
 }
 
 template <uint32_t BLOCK, uint32_t IPT>
@@ -198,23 +221,30 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
                                                             const uint32_t* __restrict__ hist_scan,
                                                             int32_t* __restrict__ key_out,
                                                             int32_t* __restrict__ rid_out, SideJob side,
-                                                            uint32_t lds_words) {
+                                                            uint32_t lds_words, Reserve rsv) {
     extern __shared__ uint32_t lds[];
     if (blockIdx.x >= gridDim.x - side.blocks) {  // extra workgroups: the side job
         run_side_job(side, blockIdx.x - (gridDim.x - side.blocks), lds, lds_words);
         return;
     }
+    if (blockIdx.x < side.front) {  // count-row sums at the front
+        sum_count_rows(side.sums, blockIdx.x);
+        return;
+    }
+    const uint32_t blk = blockIdx.x - side.front;  // (front is a multiple of 8: same XCD)
     constexpr uint32_t T = BLOCK * IPT;
     const uint32_t P = 1u << cfg.bits;
     const uint32_t Pp = P < kWave ? kWave : P;  // scan length, a multiple of 64
+    const bool counted = rsv.tot != nullptr;    // uniform
     uint32_t* cnt = lds;                         // [Pp]  counts, then local starts
     uint32_t* delta = cnt + Pp;                  // [P]   global offset - local start
     uint32_t* ctot = delta + Pp;                 // [kScanScratch]
     int32_t* skey = (int32_t*)(ctot + kScanScratch);  // [T]
     int32_t* srid = skey + T;                        // [T]
+    uint32_t* resv = (uint32_t*)(srid + T);          // [Pp] (counted, P > BLOCK): reserved offsets
 
     const uint32_t ntiles = tile_begin[nseg];
-    const uint32_t tile = live_remap(blockIdx.x, ntiles);
+    const uint32_t tile = live_remap(blk, ntiles);
     if (tile >= ntiles) return;
     const TileLoc t = locate(segs, tile_begin, tile_seg, nseg, tile, T);
     const PartSeg sg = segs[t.seg];
@@ -237,12 +267,21 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
             valid |= (uint64_t)ok << k;
         }
         kx = rx = 0;
+        // awaited here: the compiler joins this branch into the vector one
+        // behind a flag, and loads still in flight on it would put waits
+        // between the vector loads of the other
+#pragma unroll
+        for (uint32_t k = 0; k < IPT; ++k) {
+            settle((uint32_t)keys[k]);
+            settle((uint32_t)rids[k]);
+        }
     }
-    // This tile's global partition offsets do not depend on the tile's data:
-    // fetched together with it (first BLOCK partitions; the rest later).
-    const uint32_t* __restrict__ hs = hist_scan + sg.hist_base;
-    const uint32_t hs_own = threadIdx.x < P ? hs[(uint64_t)threadIdx.x * t.nt + t.tl] : 0u;
-    const uint32_t seg0 = hs[0];
+    // This tile's global partition offsets (counted: its segment's totals) do
+    // not depend on the tile's data: fetched together with it (first BLOCK
+    // partitions; the rest later).
+    const uint32_t* __restrict__ hs = counted ? rsv.tot + (uint64_t)t.seg * P : hist_scan + sg.hist_base;
+    const uint32_t hs_own = threadIdx.x < P ? hs[counted ? threadIdx.x : (uint64_t)threadIdx.x * t.nt + t.tl] : 0u;
+    const uint32_t seg0 = counted ? 0u : hs[0];
     // counters cleared while the loads are in flight
     for (uint32_t i = threadIdx.x; i < Pp; i += BLOCK) cnt[i] = 0;
     __syncthreads();
@@ -268,12 +307,54 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
     const bool xok = (valid >> IPT) & 1u;
     const uint32_t xrank = xok ? atomicAdd(&cnt[part_of(kx, cfg)], 1u) : 0u;
     __syncthreads();
-    lds_excl_scan(cnt, Pp, ctot);
-    __syncthreads();
-    for (uint32_t p = threadIdx.x; p < P; p += BLOCK) {
-        const uint32_t g = p < BLOCK ? hs_own : hs[(uint64_t)p * t.nt + t.tl];
-        const uint32_t rel = g - seg0;  // exact: < segment length
-        delta[p] = rel - cnt[p];
+    uint32_t r_own = 0;  // counted: this thread's partition's reserved offset (in flight until used)
+    if (P <= kWave) {
+        // One wave does it all (uniform branch): lane p scans the counts (local
+        // starts) and, counted, the segment's totals (partition starts) and
+        // reserves the tile's run; one barrier then publishes the starts.
+        if (threadIdx.x < kWave) {
+            const uint32_t p = threadIdx.x;
+            const bool in = p < P;
+            const uint32_t c = in ? cnt[p] : 0u;
+            if (counted && in && c) r_own = atomicAdd(&rsv.cur[(uint64_t)t.seg * P + p], c);
+            const uint32_t ec = wave_incl_scan(c) - c;
+            const uint32_t g = in ? hs_own : 0u;
+            const uint32_t base = counted ? wave_incl_scan(g) - g : g - seg0;  // start inside the segment
+            if (in) {
+                cnt[p] = ec;
+                delta[p] = base - ec;  // counted: + r_own once it is back
+            }
+        }
+        __syncthreads();
+    } else if (counted) {
+        // The segment's totals (the partition starts inside the segment, once
+        // scanned) go to LDS first: a wait for their loads would also wait for
+        // the reservations.  Then this tile's run of every partition is
+        // reserved on the partition's cursor; the offsets are awaited only
+        // after the scans and the reordering below.
+        for (uint32_t p = threadIdx.x; p < Pp; p += BLOCK) delta[p] = p < P ? (p < BLOCK ? hs_own : hs[p]) : 0u;
+        uint32_t* __restrict__ cur = rsv.cur + (uint64_t)t.seg * P;
+        if (threadIdx.x < P) {
+            const uint32_t c = cnt[threadIdx.x];
+            r_own = c ? atomicAdd(&cur[threadIdx.x], c) : 0u;
+        }
+        for (uint32_t p = threadIdx.x + BLOCK; p < P; p += BLOCK) {
+            const uint32_t c = cnt[p];
+            resv[p] = c ? atomicAdd(&cur[p], c) : 0u;
+        }
+        __syncthreads();
+        lds_excl_scan(cnt, Pp, ctot);
+        __syncthreads();
+        lds_excl_scan(delta, Pp, ctot);
+        __syncthreads();
+    } else {
+        lds_excl_scan(cnt, Pp, ctot);
+        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < P; p += BLOCK) {
+            const uint32_t g = p < BLOCK ? hs_own : hs[(uint64_t)p * t.nt + t.tl];
+            const uint32_t rel = g - seg0;  // exact: < segment length
+            delta[p] = rel - cnt[p];
+        }
     }
 #pragma unroll
     for (uint32_t k = 0; k < IPT; ++k) {
@@ -290,6 +371,17 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
         if (pos < T) {
             skey[pos] = kx;
             srid[pos] = rx;
+        }
+    }
+    // the reservations (and the prefetched offsets) are back by now; waiting
+    // for them here keeps the waits out of the store loop below
+    settle(r_own);
+    settle(hs_own);
+    if (counted) {  // global offset - local start
+        if (P <= kWave) {
+            if (threadIdx.x < P) delta[threadIdx.x] += r_own;
+        } else {
+            for (uint32_t p = threadIdx.x; p < P; p += BLOCK) delta[p] += (p < BLOCK ? r_own : resv[p]) - cnt[p];
         }
     }
     __syncthreads();
@@ -313,14 +405,22 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
 template <uint32_t BLOCK, uint32_t IPT>
 void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                  uint32_t grid, const PassCfg& cfg, uint32_t* hist, const Pass1* p1, Recorder& rec) {
-    const size_t lds = sizeof(uint32_t) * ((size_t)1 << cfg.bits);
+    const bool count = p1 && p1->rows;
+    if (count && (p1->bits_all < 3 || p1->bits_all > kCountedMaxBits)) {
+        if (rec.err == hipSuccess) rec.err = hipErrorInvalidValue;
+        return;
+    }
+    const size_t lds = sizeof(uint32_t) * (((size_t)1 << cfg.bits) + (count ? (size_t)1 << p1->bits_all : 0));
     rec.before("part_hist");
     static_assert(BLOCK * IPT >= 1024 && BLOCK * IPT <= 8192 && BLOCK / kWave <= kScanScratch, "tile shape");
-    if (p1)
-        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
+    if (count)
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true, true>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
+                           tile_begin, tile_seg, nseg, cfg, hist, *p1);
+    else if (p1)
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true, false>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
                            tile_begin, tile_seg, nseg, cfg, hist, *p1);
     else
-        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, false>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, false, false>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
                            tile_begin, tile_seg, nseg, cfg, hist, Pass1{});
     rec.after();
 }
@@ -339,14 +439,15 @@ void hist_dispatch(const PartSeg* segs, const uint32_t* tile_begin, const uint32
 template <uint32_t BLOCK, uint32_t IPT>
 void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                     uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
-                    int32_t* rid_out, const SideJob& side, Recorder& rec) {
+                    int32_t* rid_out, const SideJob& side, Recorder& rec, const Reserve& rsv) {
     if (part_block(cfg.tile) != BLOCK) {  // side-job workgroups are sized with part_block()
         if (rec.err == hipSuccess) rec.err = hipErrorInvalidConfiguration;
         return;
     }
     const size_t P = (size_t)1 << cfg.bits;
     const size_t Pp = P < kWave ? kWave : P;
-    size_t lds = sizeof(uint32_t) * (2 * Pp + kScanScratch) + sizeof(int32_t) * 2 * BLOCK * IPT;
+    size_t lds = sizeof(uint32_t) * (2 * Pp + kScanScratch) + sizeof(int32_t) * 2 * BLOCK * IPT +
+                 (rsv.tot && P > BLOCK ? sizeof(uint32_t) * Pp : 0);
     if (side.kind == kSideSetup2) {
         // room for the pass-2 segment tile offsets (else the setup fills the tile map from HBM)
         const size_t want = sizeof(uint32_t) * (kScanScratch + 2 * ((size_t)1 << side.setup2.bits1) + 1);
@@ -357,9 +458,10 @@ void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint3
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
     rec.before("part_scatter");
-    hipLaunchKernelGGL((k_part_scatter<BLOCK, IPT>), dim3(grid + side.blocks), dim3(BLOCK), lds, rec.stream, segs,
+    hipLaunchKernelGGL((k_part_scatter<BLOCK, IPT>), dim3(side.front + grid + side.blocks), dim3(BLOCK), lds,
+                       rec.stream, segs,
                        tile_begin, tile_seg, nseg, cfg, hist_scan, key_out, rid_out, side,
-                       (uint32_t)(lds / sizeof(uint32_t)));
+                       (uint32_t)(lds / sizeof(uint32_t)), rsv);
     rec.after();
 }
 
@@ -421,10 +523,11 @@ void part_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* 
 
 void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                   uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
-                  int32_t* rid_out, const SideJob& side, Recorder& rec) {
-    if (grid + side.blocks == 0) return;
+                  int32_t* rid_out, const SideJob& side, Recorder& rec, const Reserve* rsv) {
+    if (side.front + grid + side.blocks == 0) return;
+    const Reserve r = rsv ? *rsv : Reserve{nullptr, nullptr};
 #define HJ_SCATTER(BLOCK, IPT) \
-    launch_scatter<BLOCK, IPT>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist_scan, key_out, rid_out, side, rec)
+    launch_scatter<BLOCK, IPT>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist_scan, key_out, rid_out, side, rec, r)
     switch (cfg.tile) {  // workgroup size by tile: part_block()
         case 1024: HJ_SCATTER(256, 4); break;
         case 2048: HJ_SCATTER(256, 8); break;
