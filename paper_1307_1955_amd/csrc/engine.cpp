@@ -184,7 +184,8 @@ struct PhjWs {
     uint32_t* tb2;
     uint32_t* tseg2;
     uint32_t* hist2;     // pass-2 histogram (not counted)
-    uint16_t* rows;      // pass-1 count rows (counted pass 2)
+    uint8_t* rows;       // pass-1 count rows (counted pass 2)
+    uint32_t* esc;       //   and their escapes
     uint32_t* tot2;      // counted pass 2: final partition totals (zeroed block)
     uint32_t* cur2;      //   and reservation cursors (zeroed block)
     int32_t *keyB, *ridB;
@@ -228,10 +229,12 @@ PhjWs phj_layout(const Plan& pl, uint64_t n_r, uint64_t n_s, uint64_t n_r_tab, v
         w.segs2 = c.take<hj::PartSeg>(2ull * pl.P1);
         w.tb2 = c.take<uint32_t>(2ull * pl.P1 + 1);
         w.tseg2 = c.take<uint32_t>(w.tiles2_ub);
-        if (counted)
-            w.rows = c.take<uint16_t>(w.tiles1 * pl.P);
-        else
+        if (counted) {
+            w.rows = c.take<uint8_t>(w.tiles1 * pl.P);
+            w.esc = c.take<uint32_t>(w.tiles1 * hj::kCountEsc);
+        } else {
             w.hist2 = c.take<uint32_t>(w.tiles2_ub * pl.P2);
+        }
         w.keyB = c.take<int32_t>(n);
         w.ridB = c.take<int32_t>(n);
     }
@@ -435,6 +438,7 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
                                   w.zero, w.nzero, rec.err_clear);
     if (counted) {
         p1.rows = w.rows;
+        p1.esc = w.esc;
         p1.bits_all = pl.B;
     }
     // the join plan rides on the last pass's scatter, the pass-2 setup on the first
@@ -458,7 +462,7 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
     }
     hj::PassCfg c1{pl.b2, pl.b1, pl.hash, pl.tile};
     if (counted) {  // the count rows are summed beside the pass-1 scatter's tiles
-        setup2.sums = hj::make_count_sums(w.rows, w.tot2, p1.nt_r, p1.ntiles - p1.nt_r, pl.B,
+        setup2.sums = hj::make_count_sums(w.rows, w.esc, w.tot2, p1.nt_r, p1.ntiles - p1.nt_r, pl.B,
                                           hj::part_block(pl.tile));
         setup2.front = hj::count_sum_blocks(setup2.sums, hj::part_block(pl.tile));
     }

@@ -160,18 +160,22 @@ struct PassCfg {
     uint32_t hash_kind;  // hj_hash
     uint32_t tile;       // tuples per tile
 };
-// Two passes whose final partitions number 2^3..2^kCountedMaxBits are
+// Two passes whose final partitions number 2^4..2^kCountedMaxBits are
 // "counted": pass 1 also counts every tile's tuples per final partition (one
-// 16-bit row of 2^bits counts per tile: a tile holds at most 8192 tuples),
-// extra workgroups of the pass-1 scatter sum the rows into per-relation
-// totals, and pass 2 has no histogram of its own: each pass-2 tile places
-// its runs at the scanned totals of its segment plus what it reserves on a
-// cursor per final partition (the order of tiles inside a partition is then
-// the order of their reservations).  More bits would make the rows larger
-// than the pass-2 histogram read they replace.
+// row of 2^bits 8-bit counts per tile; a count of 255 or more is 0 in the row
+// and goes to the tile's list of kCountEsc escapes instead: a tile of at most
+// 8192 tuples has no more than 32 of them), workgroups at the front of the
+// pass-1 scatter sum the rows into per-relation totals, and pass 2 has no
+// histogram of its own: each pass-2 tile places its runs at the scanned
+// totals of its segment plus what it reserves on a cursor per final
+// partition (the order of tiles inside a partition is then the order of
+// their reservations).  More bits would make the rows larger than the pass-2
+// histogram read they replace.
 constexpr uint32_t kCountedMaxBits = 13;
+constexpr uint32_t kCountEsc = 32;       // escapes per tile: (partition << 14) | count, 0 unused
+constexpr uint32_t kCountEscMin = 255;   // counts from here on are escaped
 inline bool counted_pass2(uint32_t passes, uint32_t b1, uint32_t b2) {
-    return passes == 2 && b1 + b2 >= 3 && b1 + b2 <= kCountedMaxBits;
+    return passes == 2 && b1 + b2 >= 4 && b1 + b2 <= kCountedMaxBits;
 }
 // A counted pass 2's totals and cursors, each 2^(b1 + b2) entries for R then
 // as many for S (index = segment * 2^b2 + partition in the segment).
@@ -179,26 +183,29 @@ struct Reserve {
     const uint32_t* tot;
     uint32_t* cur;  // zero before the pass
 };
-// The sums of a counted pass 2's count rows (Pass1::rows: nt_r rows of R, then
-// nt_s of S, 2^bits 16-bit counts each) into tot[rel * 2^bits + i] (zero
-// before), by extra workgroups at the front of the pass-1 scatter's grid: the
-// totals are needed only by pass 2, so the sums run beside the scatter's
-// tiles.  Each workgroup takes `rows_per` rows of one relation and a group of
-// 8-count columns.
+// The sums of a counted pass 2's count rows (Pass1::rows and ::esc: nt_r
+// rows of R, then nt_s of S) into tot[rel * 2^bits + i] (zero before), by
+// workgroups at the front of the pass-1 scatter's grid: the totals are needed
+// only by pass 2, so the sums run beside the scatter's tiles.  Each workgroup
+// takes `rows_per` rows of one relation and a group of 16-count columns
+// (spread over its threads in phases when the group is narrower than it).
 struct CountSums {
-    const uint16_t* rows;
+    const uint8_t* rows;
+    const uint32_t* esc;
     uint32_t* tot;
     uint32_t nt_r, nt_s, bits, rows_per;
 };
+// Column groups of 16-count columns per row for workgroups of `block` threads.
 __host__ __device__ inline uint32_t count_sum_groups(uint32_t bits, uint32_t block) {
-    const uint32_t cols = (1u << bits) / 8;
-    return (cols + block - 1) / block;
+    const uint32_t cols = (1u << bits) / 16;
+    return cols > block ? cols / block : 1u;
 }
-// About 128 workgroups in all (their sums are added with atomics), 8 rows at least.
-inline CountSums make_count_sums(const uint16_t* rows, uint32_t* tot, uint32_t nt_r, uint32_t nt_s, uint32_t bits,
-                                 uint32_t block) {
-    const uint64_t want = ((uint64_t)(nt_r + nt_s) * count_sum_groups(bits, block) + 127) / 128;
-    return CountSums{rows, tot, nt_r, nt_s, bits, want > 8 ? (uint32_t)want : 8u};
+// About 32 workgroups in all: each adds its sums with atomics, and the pass-1
+// scatter they run beside leaves them time for many rows; 8 rows at least.
+inline CountSums make_count_sums(const uint8_t* rows, const uint32_t* esc, uint32_t* tot, uint32_t nt_r,
+                                 uint32_t nt_s, uint32_t bits, uint32_t block) {
+    const uint64_t want = ((uint64_t)(nt_r + nt_s) * count_sum_groups(bits, block) + 31) / 32;
+    return CountSums{rows, esc, tot, nt_r, nt_s, bits, want > 8 ? (uint32_t)want : 8u};
 }
 // Workgroups of the sums, rounded up to a multiple of 8 (the scatter's tiles
 // keep their XCD mapping behind them; the extra ones have no rows).
@@ -226,8 +233,10 @@ struct Pass1 {
     uint64_t nzero;
     uint64_t* err_clear;  // the call's error word, cleared with the scan states (or nullptr)
     // counted pass 2: rows[tile * 2^bits_all + i] = tuples of the tile in final
-    // partition i = hash & (2^bits_all - 1) (nullptr: no counting)
-    uint16_t* rows;
+    // partition i = hash & (2^bits_all - 1), esc[tile * kCountEsc + k] its
+    // escapes (rows == nullptr: no counting)
+    uint8_t* rows;
+    uint32_t* esc;
     uint32_t bits_all;
     uint32_t pad;
 };

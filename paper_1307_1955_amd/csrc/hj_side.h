@@ -306,37 +306,63 @@ __device__ __forceinline__ void setup_pass2_block(const Setup2Args& A, uint32_t*
 
 
 // Workgroup b of the count-row sums (CountSums): rows [row0, row1) of one
-// relation and the 8-count columns c of one column group, summed in registers
-// (16-byte loads, eight rows in flight), then added to the totals.
-__device__ __forceinline__ void sum_count_rows(const CountSums& A, uint32_t b) {
+// relation and cw 16-count columns, each column summed in registers by
+// `phases` threads (16-byte loads, eight rows in flight per thread), the
+// phases combined in LDS (when `lds` holds cw * 16 words), then added to the
+// totals; and the escapes of those rows that fall in the columns.
+__device__ __forceinline__ void sum_count_rows(const CountSums& A, uint32_t b, uint32_t* lds,
+                                               uint32_t lds_words) {
     const uint32_t PA = 1u << A.bits;
-    const uint32_t C = PA / 8;
+    const uint32_t C = PA / 16;
+    const uint32_t cw = min(C, (uint32_t)blockDim.x), phases = blockDim.x / cw;
     const uint32_t cg = count_sum_groups(A.bits, blockDim.x);
     const uint32_t rg_r = (A.nt_r + A.rows_per - 1) / A.rows_per;
     const uint32_t rg_s = (A.nt_s + A.rows_per - 1) / A.rows_per;
-    const uint32_t c = (b % cg) * blockDim.x + threadIdx.x;
     const uint32_t q = b / cg;
-    if (q >= rg_r + rg_s) return;  // rounding workgroups
+    if (q >= rg_r + rg_s) return;  // rounding workgroups (uniform)
     const uint32_t rel = q >= rg_r;
     const uint32_t first = rel ? A.nt_r : 0u, last = rel ? A.nt_r + A.nt_s : A.nt_r;
     const uint32_t row0 = first + (q - (rel ? rg_r : 0u)) * A.rows_per;
     const uint32_t row1 = min(row0 + A.rows_per, last);
-    if (c >= C || row0 >= row1) return;
-    const uint4* __restrict__ src = reinterpret_cast<const uint4*>(A.rows) + (uint64_t)row0 * C + c;
-    uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (row0 >= row1) return;  // uniform
+    const uint32_t lo = (b % cg) * cw * 16;  // first count of the column group
+    const uint32_t col = threadIdx.x % cw, ph = threadIdx.x / cw;
     const uint32_t n = row1 - row0;
-#pragma unroll 8
-    for (uint32_t r = 0; r < n; ++r) {
-        const uint4 w = src[(uint64_t)r * C];
-        acc[0] += w.x & 0xFFFFu; acc[1] += w.x >> 16;
-        acc[2] += w.y & 0xFFFFu; acc[3] += w.y >> 16;
-        acc[4] += w.z & 0xFFFFu; acc[5] += w.z >> 16;
-        acc[6] += w.w & 0xFFFFu; acc[7] += w.w >> 16;
-    }
-    uint32_t* __restrict__ tot = A.tot + (uint64_t)rel * PA + 8ull * c;
+    uint32_t acc[16];
 #pragma unroll
-    for (uint32_t e = 0; e < 8; ++e)
-        if (acc[e]) atomicAdd(&tot[e], acc[e]);
+    for (uint32_t e = 0; e < 16; ++e) acc[e] = 0;
+    if (ph < phases) {
+        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(A.rows) + (uint64_t)row0 * C + lo / 16 + col;
+#pragma unroll 8
+        for (uint32_t r = ph; r < n; r += phases) {
+            const uint4 w = src[(uint64_t)r * C];
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (uint32_t k = 0; k < 16; ++k) acc[k] += (ws[k / 4] >> (8 * (k % 4))) & 0xFFu;
+        }
+    }
+    uint32_t* __restrict__ tot = A.tot + (uint64_t)rel * PA;
+    if (phases > 1 && cw * 16 <= lds_words) {  // uniform
+        for (uint32_t i = threadIdx.x; i < cw * 16; i += blockDim.x) lds[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e)
+            if (acc[e]) atomicAdd(&lds[col * 16 + e], acc[e]);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cw * 16; i += blockDim.x) {
+            const uint32_t v = lds[i];
+            if (v) atomicAdd(&tot[lo + i], v);
+        }
+    } else {
+#pragma unroll
+        for (uint32_t e = 0; e < 16; ++e)
+            if (acc[e]) atomicAdd(&tot[lo + col * 16 + e], acc[e]);
+    }
+    for (uint32_t i = threadIdx.x; i < n * kCountEsc; i += blockDim.x) {
+        const uint32_t v = A.esc[(uint64_t)row0 * kCountEsc + i];
+        const uint32_t c = v & 0x3FFFu, bin = v >> 14;
+        if (c && bin >= lo && bin < lo + cw * 16) atomicAdd(&tot[bin], c);
+    }
 }
 
 // Runs the side job on workgroup `b` of its extra workgroups.  `lds`: the

@@ -133,7 +133,7 @@ __device__ __forceinline__ void pass1_setup(const Pass1& A) {
 // kPass1: the tiles of R and S from the launch arguments (p1), and workgroup 0
 // also does the pass's set-up; else the segments in memory.  kCount (pass 1 of
 // a counted pass 2): the tile's counts per final partition are also written,
-// as row p1.rows + tile * 2^bits_all of 16-bit counts.
+// as row p1.rows + tile * 2^bits_all of 8-bit counts and the tile's escapes.
 template <uint32_t BLOCK, uint32_t IPT, bool kPass1, bool kCount>
 __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__ segs,
                                                          const uint32_t* __restrict__ tile_begin,
@@ -146,7 +146,13 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
     uint32_t* cnt = lds;
     const uint32_t P = 1u << cfg.bits;
     const uint32_t PA = kCount ? 1u << p1.bits_all : 0u;
-    uint32_t* cnt_all = lds + P;  // [PA] (kCount)
+    // [PA] (kCount): count of final partition i at (i mod 16) * PA / 16 + i / 16,
+    // so that the 16 counts one thread packs into a store lie in 16 banks
+    // apart from its neighbours'
+    uint32_t* cnt_all = lds + P;
+    const uint32_t sh_all = kCount ? p1.bits_all - 4 : 0u;
+    uint32_t* esc = cnt_all + PA;  // [kCountEsc] escapes, then their number (kCount)
+    static_assert(!kCount || T < (kCountEsc + 1) * kCountEscMin, "escapes of a tile fit its list");
     const int32_t* __restrict__ kin;
     uint32_t len, tl, nt;
     uint64_t hist_base;
@@ -179,7 +185,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
     // counters cleared while the tile's loads are in flight
     for (uint32_t i = threadIdx.x; i < P; i += BLOCK) cnt[i] = 0;
     if (kCount)
-        for (uint32_t i = threadIdx.x; i < PA; i += BLOCK) cnt_all[i] = 0;
+        for (uint32_t i = threadIdx.x; i < PA + kCountEsc + 1; i += BLOCK) cnt_all[i] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
 #pragma unroll
@@ -187,7 +193,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
         const bool ok = (valid >> k) & 1u;
         const uint32_t h = radix_hash(keys[k], cfg.hash_kind);
         const uint32_t p = (h >> cfg.shift) & (P - 1u);
-        if (kCount && ok) atomicAdd(&cnt_all[h & (PA - 1u)], 1u);
+        if (kCount && ok) atomicAdd(&cnt_all[((h & 15u) << sh_all) | ((h & (PA - 1u)) >> 4)], 1u);
         if (cfg.bits <= kBallotMaxBits) {
             const uint64_t m = match_mask(p, cfg.bits, ok);
             if (ok && (m & lt) == 0) atomicAdd(&cnt[p], (uint32_t)__popcll(m));
@@ -198,18 +204,35 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
     if ((valid >> IPT) & 1u) {
         const uint32_t h = radix_hash(kx, cfg.hash_kind);
         atomicAdd(&cnt[(h >> cfg.shift) & (P - 1u)], 1u);
-        if (kCount) atomicAdd(&cnt_all[h & (PA - 1u)], 1u);
+        if (kCount) atomicAdd(&cnt_all[((h & 15u) << sh_all) | ((h & (PA - 1u)) >> 4)], 1u);
     }
     __syncthreads();
     uint32_t* __restrict__ h = hist + hist_base + tl;
     for (uint32_t p = threadIdx.x; p < P; p += BLOCK) h[(uint64_t)p * nt] = cnt[p];
     if (kCount) {
-        // 8 counts (each <= T <= 8192) per 16-byte store; PA >= 8
+        // 16 counts per 16-byte store (PA >= 16); counts from kCountEscMin on
+        // are 0 here and escaped
         uint4* __restrict__ out = reinterpret_cast<uint4*>(p1.rows + (uint64_t)row * PA);
-        for (uint32_t c = threadIdx.x; c < PA / 8; c += BLOCK) {
-            const uint32_t* v = cnt_all + 8 * c;
-            out[c] = make_uint4(v[0] | v[1] << 16, v[2] | v[3] << 16, v[4] | v[5] << 16, v[6] | v[7] << 16);
+        for (uint32_t c = threadIdx.x; c < PA / 16; c += BLOCK) {
+            uint32_t w[4];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) {
+                w[q] = 0;
+#pragma unroll
+                for (uint32_t e = 0; e < 4; ++e) {
+                    uint32_t x = cnt_all[((4 * q + e) << sh_all) + c];  // partition 16 c + 4 q + e
+                    if (x >= kCountEscMin) {
+                        const uint32_t k = atomicAdd(&esc[kCountEsc], 1u);
+                        if (k < kCountEsc) esc[k] = (16 * c + 4 * q + e) << 14 | x;
+                        x = 0;
+                    }
+                    w[q] |= x << (8 * e);
+                }
+            }
+            out[c] = make_uint4(w[0], w[1], w[2], w[3]);
         }
+        __syncthreads();
+        if (threadIdx.x < kCountEsc) p1.esc[(uint64_t)row * kCountEsc + threadIdx.x] = esc[threadIdx.x];
     }
 }
 
@@ -228,7 +251,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
         return;
     }
     if (blockIdx.x < side.front) {  // count-row sums at the front
-        sum_count_rows(side.sums, blockIdx.x);
+        sum_count_rows(side.sums, blockIdx.x, lds, lds_words);
         return;
     }
     const uint32_t blk = blockIdx.x - side.front;  // (front is a multiple of 8: same XCD)
@@ -406,11 +429,12 @@ template <uint32_t BLOCK, uint32_t IPT>
 void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t* tile_seg, uint32_t nseg,
                  uint32_t grid, const PassCfg& cfg, uint32_t* hist, const Pass1* p1, Recorder& rec) {
     const bool count = p1 && p1->rows;
-    if (count && (p1->bits_all < 3 || p1->bits_all > kCountedMaxBits)) {
+    if (count && (p1->bits_all < 4 || p1->bits_all > kCountedMaxBits)) {
         if (rec.err == hipSuccess) rec.err = hipErrorInvalidValue;
         return;
     }
-    const size_t lds = sizeof(uint32_t) * (((size_t)1 << cfg.bits) + (count ? (size_t)1 << p1->bits_all : 0));
+    const size_t lds =
+        sizeof(uint32_t) * (((size_t)1 << cfg.bits) + (count ? ((size_t)1 << p1->bits_all) + kCountEsc + 1 : 0));
     rec.before("part_hist");
     static_assert(BLOCK * IPT >= 1024 && BLOCK * IPT <= 8192 && BLOCK / kWave <= kScanScratch, "tile shape");
     if (count)
