@@ -40,13 +40,16 @@ OVF_BIG_PART = 1 << 16
 OVF_GRID = 2048            # workgroups of the HBM-table build launches
 SHJ_TILE = 2048            # S tuples per SHJ probe workgroup
 SCAN_CHUNK = 2048          # entries per scan workgroup
+COUNTED_MAX_BITS = 13      # two passes of 4..13 bits in all: pass 1 counts the final partitions
 
 # the fitted constants, in this order (seconds, bytes/s; positive except SIGNED)
 PARAMS = [
     "d_gap",               # delay of a dependent launch behind the previous kernel
     "d_kernel",            # fixed ramp-up and drain of a kernel
     "bw_hist", "t_hist_tile",
+    "t_count_bin",         # a counted pass 2's histogram tile: clear, count and pack 2^bits counters
     "bw_scatter", "run_half", "t_scatter_tile",
+    "t_reserve",           # a counted pass 2's scatter tile: count sums beside it, or reservations
     "t_scan_entry",
     "bw_join", "l_join0", "l_join_r", "l_join_s",
     "f_count", "f_1pass",  # a work item's latency in the count pass and the one-pass write, against the write pass
@@ -123,6 +126,11 @@ def _table_factor(table_bytes: float, gamma: float, base: float = 1 << 20) -> fl
     return (max(table_bytes, base) / base) ** gamma
 
 
+def counted_pass2(passes: int, b1: int, b2: int) -> bool:
+    """Two passes whose pass 2 reserves its runs on counts taken in pass 1."""
+    return passes == 2 and 4 <= b1 + b2 <= COUNTED_MAX_BITS
+
+
 def launches(plan: dict, n_r: int, n_s: int, m: float) -> list[tuple[str, dict]]:
     """The launch sequence of a join (engine.cpp) with each launch's features.
     plan: resolved parameters: algo ("shj"/"phj"), passes, bits (b1, b2), tile,
@@ -159,15 +167,20 @@ def launches(plan: dict, n_r: int, n_s: int, m: float) -> list[tuple[str, dict]]
     P = 1 << B
     P1 = 1 << b1
     tiles1 = math.ceil(n_r / tile) + math.ceil(n_s / tile)
-    out.append(("part_hist", {"n": n, "tiles": tiles1, "tile": tile}))
+    counted = counted_pass2(plan["passes"], b1, b2)
+    rows = float(tiles1 * P) if counted else 0.0  # 8-bit count rows: written by the histogram, summed beside the scatter
+    out.append(("part_hist", {"n": n, "tiles": tiles1, "tile": tile, "extra": rows, "bins": P if counted else 0}))
     out.append(("scan_u32", {"entries": tiles1 * P1}))
-    out.append(("part_scatter", {"n": n, "tiles": tiles1, "tile": tile, "bits": b1}))
+    out.append(("part_scatter", {"n": n, "tiles": tiles1, "tile": tile, "bits": b1, "extra": rows,
+                                 "counted": int(counted)}))
     if plan["passes"] == 2:
         seg = n / (2.0 * P1)
         tiles2 = 2 * P1 * max(1, math.ceil(seg / tile)) if seg > 0 else 0
-        out.append(("part_hist", {"n": n, "tiles": tiles2, "tile": tile}))
-        out.append(("scan_u32", {"entries": (n / tile + 2 * P1) * (1 << b2)}))
-        out.append(("part_scatter", {"n": n, "tiles": tiles2, "tile": tile, "bits": b2}))
+        if not counted:
+            out.append(("part_hist", {"n": n, "tiles": tiles2, "tile": tile, "extra": 0.0, "bins": 0}))
+            out.append(("scan_u32", {"entries": (n / tile + 2 * P1) * (1 << b2)}))
+        out.append(("part_scatter", {"n": n, "tiles": tiles2, "tile": tile, "bits": b2, "extra": 0.0,
+                                     "counted": int(counted)}))
     r_part, s_part = n_r / P, n_s / P
     hbm = r_part > cap
     pairs = P * _nonempty(r_part) * _nonempty(s_part)
@@ -196,14 +209,16 @@ def kernel_seconds(name: str, f: dict, c: dict) -> float:
         if f["tiles"] == 0:
             return d
         rounds = math.ceil(f["tiles"] / _hist_slots(f["tile"]))
-        return d + max(4.0 * f["n"] / c["bw_hist"], rounds * c["t_hist_tile"] * f["tile"] / 8192.0)
+        per_tile = c["t_hist_tile"] * f["tile"] / 8192.0 + c["t_count_bin"] * f["bins"]
+        return d + max((4.0 * f["n"] + f["extra"]) / c["bw_hist"], rounds * per_tile)
     if name == "part_scatter":
         if f["tiles"] == 0:
             return d
         run = f["tile"] / float(1 << f["bits"])
         bw = c["bw_scatter"] * run / (run + c["run_half"])
         rounds = math.ceil(f["tiles"] / _scatter_slots(f["bits"], f["tile"]))
-        return d + max(16.0 * f["n"] / bw, rounds * c["t_scatter_tile"] * f["tile"] / 8192.0)
+        per_tile = c["t_scatter_tile"] * f["tile"] / 8192.0 + c["t_reserve"] * f["counted"]
+        return d + max((16.0 * f["n"] + f["extra"]) / bw, rounds * per_tile)
     if name in ("scan_u32", "scan_u64"):
         return d + f["entries"] * c["t_scan_entry"]
     if name in ("join_count", "join_write", "join_write_1pass", "direct_join"):
@@ -241,8 +256,8 @@ def join_seconds(plan: dict, n_r: int, n_s: int, m: float, c: dict) -> float:
 
 # starting point of the fit: rough MI355X figures
 START = {
-    "d_gap": 2e-6, "d_kernel": 3e-6, "bw_hist": 4.5e12, "t_hist_tile": 5e-6, "bw_scatter": 5.2e12, "run_half": 8.0,
-    "t_scatter_tile": 12e-6, "t_scan_entry": 2e-12, "bw_join": 4e12, "l_join0": 4e-6, "l_join_r": 1e-9,
+    "d_gap": 2e-6, "d_kernel": 3e-6, "bw_hist": 4.5e12, "t_hist_tile": 5e-6, "t_count_bin": 1e-9,
+    "bw_scatter": 5.2e12, "run_half": 8.0, "t_scatter_tile": 12e-6, "t_reserve": 2e-6, "t_scan_entry": 2e-12, "bw_join": 4e12, "l_join0": 4e-6, "l_join_r": 1e-9,
     "l_join_s": 5e-10, "f_count": 0.8, "f_1pass": 1.2, "p_join": 4.0, "l_hbm0": 8e-6, "l_hbm_s": 2e-9, "t_ovf_insert": 1e-10, "l_ovf_round": 4e-6,
     "bw_fill": 5e12, "t_ins": 1e-10, "gamma_ins": -0.2, "t_bround": 1e-5, "gamma_bround": 0.1,
     "t_probe": 3e-11, "gamma_probe": 0.0, "t_pround": 2e-5, "gamma_pround": 0.1, "t_match": 1e-11,

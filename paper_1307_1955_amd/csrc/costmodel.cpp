@@ -64,17 +64,21 @@ double table_factor(double table_bytes, double gamma, double base = 1048576.0) {
 
 double rounds(double items, double slots) { return std::ceil(std::max(items, 1.0) / slots); }
 
-double hist_s(double n, double tiles, uint32_t tile) {
+// extra: bytes beyond the tuples' (a counted pass 2's count rows); bins: the
+// counters a counted pass 2's histogram tile clears, counts and packs
+double hist_s(double n, double tiles, uint32_t tile, double extra, double bins) {
     if (tiles == 0) return k_d_kernel;
-    return k_d_kernel + std::max(4.0 * n / k_bw_hist, rounds(tiles, hist_slots(tile)) * k_t_hist_tile * tile / 8192.0);
+    const double per_tile = k_t_hist_tile * tile / 8192.0 + k_t_count_bin * bins;
+    return k_d_kernel + std::max((4.0 * n + extra) / k_bw_hist, rounds(tiles, hist_slots(tile)) * per_tile);
 }
 
-double scatter_s(double n, double tiles, uint32_t tile, uint32_t bits) {
+// counted: a counted pass 2's scatter (count sums beside pass 1, reservations in pass 2)
+double scatter_s(double n, double tiles, uint32_t tile, uint32_t bits, double extra, bool counted) {
     if (tiles == 0) return k_d_kernel;
     const double run = tile / std::ldexp(1.0, (int)bits);
     const double bw = k_bw_scatter * run / (run + k_run_half);
-    return k_d_kernel +
-           std::max(16.0 * n / bw, rounds(tiles, scatter_slots(bits, tile)) * k_t_scatter_tile * tile / 8192.0);
+    const double per_tile = k_t_scatter_tile * tile / 8192.0 + (counted ? k_t_reserve : 0.0);
+    return k_d_kernel + std::max((16.0 * n + extra) / bw, rounds(tiles, scatter_slots(bits, tile)) * per_tile);
 }
 
 double scan_s(double entries) { return k_d_kernel + entries * k_t_scan_entry; }
@@ -134,14 +138,20 @@ double model_seconds(const Plan& pl, uint64_t n_r_, uint64_t n_s_, double m) {
     const uint32_t tile = pl.tile, b1 = pl.b1, b2 = pl.passes == 2 ? pl.b2 : 0;
     const double P = std::ldexp(1.0, (int)(b1 + b2)), P1 = std::ldexp(1.0, (int)b1);
     const double tiles1 = std::ceil(n_r / tile) + std::ceil(n_s / tile);
-    t += hist_s(n, tiles1, tile) + scan_s(tiles1 * P1) + scatter_s(n, tiles1, tile, b1);
+    const bool counted = counted_pass2(pl.passes, b1, b2);
+    const double rows = counted ? tiles1 * P : 0.0;  // 8-bit count rows: histogram writes, sums beside the scatter read
+    t += hist_s(n, tiles1, tile, rows, counted ? P : 0.0) + scan_s(tiles1 * P1) +
+         scatter_s(n, tiles1, tile, b1, rows, counted);
     nl += 3;
     if (pl.passes == 2) {
         const double seg = n / (2 * P1);
         const double tiles2 = seg > 0 ? 2 * P1 * std::max(1.0, std::ceil(seg / tile)) : 0;
-        t += hist_s(n, tiles2, tile) + scan_s((n / tile + 2 * P1) * std::ldexp(1.0, (int)b2)) +
-             scatter_s(n, tiles2, tile, b2);
-        nl += 3;
+        if (!counted) {
+            t += hist_s(n, tiles2, tile, 0.0, 0.0) + scan_s((n / tile + 2 * P1) * std::ldexp(1.0, (int)b2));
+            nl += 2;
+        }
+        t += scatter_s(n, tiles2, tile, b2, 0.0, counted);
+        nl += 1;
     }
     const double r_part = n_r / P, s_part = n_s / P;
     const bool hbm = r_part > pl.lds_cap;

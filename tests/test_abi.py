@@ -256,6 +256,12 @@ def test_model_geometry_matches_the_kernels():
     assert float(const("kShjSlotsPerRow")) == costmodel.SHJ_SLOTS_PER_ROW
     sub = re.search(r"constexpr uint32_t kJoinSub = (\d+)", hdr)
     assert sub and 2 * int(sub.group(1)) == costmodel.JOIN_CHUNK
+    # which two-pass plans have a counted pass 2 (no pass-2 histogram and scan)
+    assert int(const("kCountedMaxBits")) == costmodel.COUNTED_MAX_BITS
+    rule = re.search(r"return passes == 2 && b1 \+ b2 >= (\d+) && b1 \+ b2 <= kCountedMaxBits;", hdr)
+    assert rule and int(rule.group(1)) == 4
+    assert [b for b in range(2, 16) if costmodel.counted_pass2(2, 1, b - 1)] == list(range(4, 14))
+    assert not costmodel.counted_pass2(1, 6, 0)
 
 
 def test_table_and_probe_sizes(hj):
