@@ -352,8 +352,12 @@ def measure_phj(hj, torch, p, t, out_r, out_s, d_count, n_r, n_s, steps, warmup,
     m = int(d_count.item())
     reps = 5
     phases = summarize(kernel_times(hj, p, t, out_r, out_s, ws, d_count, reps), reps, n_r, n_s, m)
-    # partition passes 20 B/tuple each; join: count pass 4 B/tuple (two-pass output) + write pass 8 B/tuple
-    total_bytes = (20.0 * passes + (8.0 if one_pass else 12.0)) * (n_r + n_s) + 8.0 * m
+    # partition passes 20 B/tuple each (histogram read + scatter read and write), less the histogram read of a
+    # counted pass 2 (its counts come from pass 1); join: count pass 4 B/tuple (two-pass output) + write pass
+    # 8 B/tuple
+    from paper_1307_1955_amd import costmodel
+    counted = costmodel.counted_pass2(passes, int(p.bits[0]), int(p.bits[1]) if passes == 2 else 0)
+    total_bytes = (20.0 * passes - (4.0 if counted else 0.0) + (8.0 if one_pass else 12.0)) * (n_r + n_s) + 8.0 * m
     del ws
     return {"ms": ms, "value": (n_r + n_s) / (ms * 1e-3), "matches": m, "kernels": phases,
             "path_gbs": round(total_bytes / (ms * 1e-3) / 1e9, 1),

@@ -93,6 +93,36 @@ def stats(d: str) -> dict:
     return out
 
 
+def sq_table(d: str) -> str:
+    """Per-kernel means of one SQ counter pass (SQ_WAVES, SQ_WAVE_CYCLES,
+    SQ_WAIT_INST_ANY, SQ_INSTS_VALU, SQ_INSTS_LDS, SQ_LDS_BANK_CONFLICT) as a
+    markdown table: waves, VALU and LDS instructions per wave, bank-conflict
+    cycles per LDS instruction, share of wave cycles waiting on any instruction."""
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    for r in csv.DictReader(open(one_csv(d, "counter_collection.csv"))):
+        k = short_name(r["Kernel_Name"])
+        if not k.startswith("k_"):
+            continue
+        per[(k, r["Dispatch_Id"])][r["Counter_Name"]] += float(r["Counter_Value"])
+    agg = collections.defaultdict(list)
+    for (k, _), c in per.items():
+        agg[k].append(c)
+    lines = ["| kernel | waves | VALU / wave | LDS / wave | conflict cycles / LDS instr | wait / wave cycles |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for k in sorted(agg, key=lambda k: -sum(c.get("SQ_WAVE_CYCLES", 0.0) for c in agg[k])):
+        cs = agg[k]
+
+        def mean(n):
+            return sum(c.get(n, 0.0) for c in cs) / len(cs)
+        w, lds = mean("SQ_WAVES"), mean("SQ_INSTS_LDS")
+        if w == 0:
+            continue
+        lines.append("| %s | %d | %d | %d | %.2f | %.2f |" % (
+            k, w, mean("SQ_INSTS_VALU") / w, lds / w, mean("SQ_LDS_BANK_CONFLICT") / lds if lds else 0.0,
+            mean("SQ_WAIT_INST_ANY") / max(mean("SQ_WAVE_CYCLES"), 1.0)))
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--trace", required=True)
@@ -106,6 +136,9 @@ def main():
     ap.add_argument("--prefix", default="k_", help="only kernels whose name starts with this")
     ap.add_argument("--out-md", required=True)
     ap.add_argument("--out-json", required=True)
+    ap.add_argument("--sq", default=None, metavar="DIR",
+                    help="a --pmc run of the SQ counters of sq_table(): its table is appended")
+    ap.add_argument("--sq-command", default="", help="the command of the --sq run")
     a = ap.parse_args()
     st = stats(a.trace)
     fe, wr = counters(a.fetch), counters(a.write)
@@ -136,6 +169,11 @@ def main():
                                                       fmt(r["hbm_write_mb"])))
     lines.append("")
     lines.append("Kernel sources sha256 at measurement (code without comments): `%s`" % rec["sources_sha256"])
+    if a.sq:
+        lines += ["", "## SQ counters (one pass of 8)", "", "```", a.sq_command, "```", "",
+                  "Per dispatch (means): waves, VALU and LDS instructions per wave, LDS bank-conflict cycles per "
+                  "LDS instruction, and the share of wave cycles spent waiting on any instruction.", "",
+                  sq_table(a.sq).rstrip()]
     with open(a.out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(a.out_md, a.out_json)
