@@ -173,24 +173,27 @@ def launches(plan: dict, n_r: int, n_s: int, m: float) -> list[tuple[str, dict]]
     out.append(("scan_u32", {"entries": tiles1 * P1}))
     out.append(("part_scatter", {"n": n, "tiles": tiles1, "tile": tile, "bits": b1, "extra": rows,
                                  "counted": int(counted)}))
+    r_part, s_part = n_r / P, n_s / P
+    hbm = r_part > cap
+    ovf_r = n_r if hbm else 0
+    # a counted pass 2 of at most 64 partitions per segment clears the HBM tables itself
+    clears = counted and b2 <= 6
     if plan["passes"] == 2:
         seg = n / (2.0 * P1)
         tiles2 = 2 * P1 * max(1, math.ceil(seg / tile)) if seg > 0 else 0
         if not counted:
             out.append(("part_hist", {"n": n, "tiles": tiles2, "tile": tile, "extra": 0.0, "bins": 0}))
             out.append(("scan_u32", {"entries": (n / tile + 2 * P1) * (1 << b2)}))
-        out.append(("part_scatter", {"n": n, "tiles": tiles2, "tile": tile, "bits": b2, "extra": 0.0,
-                                     "counted": int(counted)}))
-    r_part, s_part = n_r / P, n_s / P
-    hbm = r_part > cap
+        out.append(("part_scatter", {"n": n, "tiles": tiles2, "tile": tile, "bits": b2,
+                                     "extra": 16.0 * ovf_r if clears else 0.0, "counted": int(counted)}))
     pairs = P * _nonempty(r_part) * _nonempty(s_part)
     items = pairs * max(1, math.ceil(s_part / JOIN_CHUNK))
     grid = P + math.ceil(n_s / JOIN_CHUNK)
     s_item = min(max(s_part, 1.0), JOIN_CHUNK)
-    ovf_r = n_r if hbm else 0
     chunk = OVF_CHUNK_BIG if r_part > OVF_BIG_PART else OVF_CHUNK
     ovf_items = P * math.ceil(r_part / chunk) if hbm else 0
-    out.append(("ovf_clear", {"bytes": 16.0 * ovf_r}))
+    if not clears:
+        out.append(("ovf_clear", {"bytes": 16.0 * ovf_r}))
     out.append(("ovf_build", {"n": ovf_r, "items": ovf_items, "per": min(r_part, chunk)}))
     jf = {"items": items, "grid": grid, "r": min(r_part, cap), "s": s_item, "cap": cap, "hbm": int(hbm)}
     if not plan["one_pass"]:

@@ -139,6 +139,10 @@ double model_seconds(const Plan& pl, uint64_t n_r_, uint64_t n_s_, double m) {
     const double P = std::ldexp(1.0, (int)(b1 + b2)), P1 = std::ldexp(1.0, (int)b1);
     const double tiles1 = std::ceil(n_r / tile) + std::ceil(n_s / tile);
     const bool counted = counted_pass2(pl.passes, b1, b2);
+    const double r_part = n_r / P, s_part = n_s / P;
+    const bool hbm = r_part > pl.lds_cap;
+    const double ovf_r = hbm ? n_r : 0;
+    const bool clears = counted && counted_clears_tables(b2);  // the pass-2 scatter clears the HBM tables
     const double rows = counted ? tiles1 * P : 0.0;  // 8-bit count rows: histogram writes, sums beside the scatter read
     t += hist_s(n, tiles1, tile, rows, counted ? P : 0.0) + scan_s(tiles1 * P1) +
          scatter_s(n, tiles1, tile, b1, rows, counted);
@@ -150,25 +154,25 @@ double model_seconds(const Plan& pl, uint64_t n_r_, uint64_t n_s_, double m) {
             t += hist_s(n, tiles2, tile, 0.0, 0.0) + scan_s((n / tile + 2 * P1) * std::ldexp(1.0, (int)b2));
             nl += 2;
         }
-        t += scatter_s(n, tiles2, tile, b2, 0.0, counted);
+        t += scatter_s(n, tiles2, tile, b2, clears ? 16 * ovf_r : 0.0, counted);
         nl += 1;
     }
-    const double r_part = n_r / P, s_part = n_s / P;
-    const bool hbm = r_part > pl.lds_cap;
     const double items = P * nonempty(r_part) * nonempty(s_part) * std::max(1.0, std::ceil(s_part / kChunk));
     const double grid = P + std::ceil(n_s / kChunk);
     const double s_item = std::min(std::max(s_part, 1.0), kChunk);
     const double r_item = std::min(r_part, (double)pl.lds_cap);
-    const double ovf_r = hbm ? n_r : 0;
-    t += d + 16 * ovf_r / k_bw_fill;  // clear the HBM tables
-    t += d;                           // build them: inserts, or rounds of items of ovf_chunk() tuples
+    if (!clears) {
+        t += d + 16 * ovf_r / k_bw_fill;  // clear the HBM tables
+        nl += 1;
+    }
+    t += d;  // build them: inserts, or rounds of items of ovf_chunk() tuples
     if (hbm) {
         const double chunk = r_part > kOvfBigPart ? kOvfChunkBig : kOvfChunk;
         const double ovf_items = P * std::ceil(r_part / chunk);
         const double ovf_rounds = std::ceil(ovf_items / std::min(kOvfGridD, 8 * kCus));
         t += std::max(ovf_r * k_t_ovf_insert, ovf_rounds * std::ceil(std::min(r_part, chunk) / 256) * k_l_ovf_round);
     }
-    nl += 2;
+    nl += 1;
     if (!pl.one_pass) {
         t += join_s(items, r_item, s_item, pl.lds_cap, hbm, 4 * n, k_f_count);
         t += scan_s(8 * grid);

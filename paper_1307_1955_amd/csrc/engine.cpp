@@ -429,8 +429,11 @@ void run_shj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
 // w, with the join plan of the partition pairs riding on the last scatter.
 // r_pairs: R's partition ranges from a built table (R is then empty here).
 // The partitioned arrays are returned in *fk / *fr (R first, S from n_r on).
+// *tables_cleared (optional): set when the last scatter cleared the join's HBM tables.
 void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs& w, const hj::PartPair* r_pairs,
-                   uint64_t* zero_total, int32_t** fk, int32_t** fr, hj::Recorder& rec) {
+                   uint64_t* zero_total, int32_t** fk, int32_t** fr, hj::Recorder& rec,
+                   bool* tables_cleared = nullptr) {
+    if (tables_cleared) *tables_cleared = false;
     const uint32_t n_r = (uint32_t)R.n, n_s = (uint32_t)S.n;
     const bool two = pl.passes == 2;
     const bool counted = two && w.rows;  // (w.rows is set exactly for a counted pass 2 with a workspace)
@@ -475,9 +478,12 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
     if (two) {
         hj::PassCfg c2{0, pl.b2, pl.hash, pl.tile};
         if (counted) {
-            const hj::Reserve rsv{w.tot2, w.cur2};
+            // with R scattered here (not a probe of a built table), its HBM tables are cleared by the scatter
+            const bool clears = tables_cleared && !r_pairs && hj::counted_clears_tables(pl.b2);
+            const hj::Reserve rsv{w.tot2, w.cur2, clears ? w.ovf_table : nullptr, pl.lds_cap, 0u};
             hj::part_scatter(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, nullptr, w.keyB,
                              w.ridB, plan, rec, &rsv);
+            if (clears) *tables_cleared = true;
         } else {
             hj::part_hist(w.segs2, w.tb2, w.tseg2, 2 * pl.P1, (uint32_t)w.tiles2_ub, c2, w.hist2, rec);
             hj::scan_u32(w.hist2, w.hist2, w.tiles2_ub * pl.P2, w.st2, nullptr, rec);
@@ -493,9 +499,10 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
 // for oversized R partitions, then count -> scan -> write (or one-pass write).
 // rk/rr: partitioned R, sk/sr: partitioned S.
 void phj_join_pairs(const Plan& pl, const PhjWs& w, const int32_t* rk, const int32_t* rr, const int32_t* sk,
-                    const int32_t* sr, const hj_out& out, uint64_t* d_count, hj::Recorder& rec) {
+                    const int32_t* sr, const hj_out& out, uint64_t* d_count, hj::Recorder& rec,
+                    bool tables_cleared = false) {
     hj::join_ovf_build(w.pairs, w.ovf_begin, w.ovf_part, pl.P, (uint32_t)w.ovf_ub, rk, w.ovf_table, w.ovf_next,
-                       w.hot, pl.one_pass ? w.heavy : nullptr, rec);
+                       w.hot, pl.one_pass ? w.heavy : nullptr, rec, !tables_cleared);
     if (!pl.one_pass) {
         hj::join_count(w.pairs, w.item_begin, w.item_rec, pl.P, (uint32_t)w.items_ub, rk, sk, pl.lds_cap,
                        w.ovf_table, w.ovf_next, w.hot, w.wave_cnt, rec);
@@ -510,8 +517,9 @@ void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out
              uint64_t* d_count, hj::Recorder& rec) {
     const PhjWs w = phj_layout(pl, R.n, S.n, R.n, ws);
     int32_t *fk, *fr;
-    phj_partition(pl, R, S, w, nullptr, pl.one_pass ? d_count : nullptr, &fk, &fr, rec);
-    phj_join_pairs(pl, w, fk, fr, fk + R.n, fr + R.n, out, d_count, rec);
+    bool cleared = false;
+    phj_partition(pl, R, S, w, nullptr, pl.one_pass ? d_count : nullptr, &fk, &fr, rec, &cleared);
+    phj_join_pairs(pl, w, fk, fr, fk + R.n, fr + R.n, out, d_count, rec, cleared);
 }
 
 void run_join(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,

@@ -182,7 +182,15 @@ inline bool counted_pass2(uint32_t passes, uint32_t b1, uint32_t b2) {
 struct Reserve {
     const uint32_t* tot;
     uint32_t* cur;  // zero before the pass
+    // Optional (nullptr: not done here): the HBM tables of R's partitions of more
+    // than lds_cap tuples (2 slots per tuple at twice its position in R) are
+    // cleared by the tiles that write the partitions' runs, in place of the
+    // clearing launch.  Only with at most 64 partitions per segment.
+    uint64_t* ovf_table;
+    uint32_t lds_cap, pad;
 };
+// Whether a counted pass 2 clears the HBM tables (Reserve::ovf_table).
+inline bool counted_clears_tables(uint32_t b2) { return b2 <= 6; }
 // The sums of a counted pass 2's count rows (Pass1::rows and ::esc: nt_r
 // rows of R, then nt_s of S) into tot[rel * 2^bits + i] (zero before), by
 // workgroups at the front of the pass-1 scatter's grid: the totals are needed
@@ -302,9 +310,10 @@ size_t join_lds_bytes(uint32_t lds_cap, bool write);
 size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile);
 // hot: where the build records its hot keys (zeroed before); heavy: the
 // one-pass queue (nullptr for count -> scan -> write), whose `wait` it sets.
+// clear == false: the tables were cleared by the last scatter (Reserve::ovf_table).
 void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint32_t* ovf_part, uint32_t P,
                     uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, HotKeys* hot,
-                    HeavyQueue* heavy, Recorder& rec);
+                    HeavyQueue* heavy, Recorder& rec, bool clear = true);
 // item_begin/item_rec come from the join plan (JoinPlanOut).
 void join_count(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,

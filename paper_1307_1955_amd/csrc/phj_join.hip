@@ -765,13 +765,15 @@ uint32_t join_grid(uint32_t P, uint64_t n_s) {
 
 void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint32_t* ovf_part, uint32_t P,
                     uint32_t grid, const int32_t* rk, uint64_t* ovf_table, uint32_t* ovf_next, HotKeys* hot,
-                    HeavyQueue* heavy, Recorder& rec) {
+                    HeavyQueue* heavy, Recorder& rec, bool clear) {
     if (grid == 0) return;
     grid = grid < kOvfGrid ? grid : kOvfGrid;  // grid-stride: few chunks in the common case
-    rec.before("ovf_clear");
-    hipLaunchKernelGGL(k_ovf_clear, dim3(grid), dim3(256), 0, rec.stream, pairs, ovf_begin, ovf_part, P,
-                       ovf_table);
-    rec.after();
+    if (clear) {
+        rec.before("ovf_clear");
+        hipLaunchKernelGGL(k_ovf_clear, dim3(grid), dim3(256), 0, rec.stream, pairs, ovf_begin, ovf_part, P,
+                           ovf_table);
+        rec.after();
+    }
     rec.before("ovf_build");
     hipLaunchKernelGGL(k_ovf_build, dim3(grid), dim3(256), 0, rec.stream, pairs, ovf_begin, ovf_part, P, rk,
                        ovf_table, ovf_next, hot, heavy);

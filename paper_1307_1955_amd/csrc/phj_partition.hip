@@ -331,6 +331,8 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
     const uint32_t xrank = xok ? atomicAdd(&cnt[part_of(kx, cfg)], 1u) : 0u;
     __syncthreads();
     uint32_t r_own = 0;  // counted: this thread's partition's reserved offset (in flight until used)
+    // partitions of this tile whose HBM tables it clears (counted, P <= 64, R)
+    uint64_t* s_clear = reinterpret_cast<uint64_t*>(ctot);  // (one word of the scan scratch)
     if (P <= kWave) {
         // One wave does it all (uniform branch): lane p scans the counts (local
         // starts) and, counted, the segment's totals (partition starts) and
@@ -347,6 +349,9 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
                 cnt[p] = ec;
                 delta[p] = base - ec;  // counted: + r_own once it is back
             }
+            // R partitions whose join takes an HBM table (counted: g is the partition's size)
+            const uint64_t big = __ballot(in && rsv.ovf_table && t.seg < nseg / 2 && g > rsv.lds_cap);
+            if (p == 0) *s_clear = big;
         }
         __syncthreads();
     } else if (counted) {
@@ -410,15 +415,34 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
     __syncthreads();
     int32_t* __restrict__ kout = key_out + sg.out_base;
     int32_t* __restrict__ rout = rid_out + sg.out_base;
+    const uint64_t clear = (P <= kWave && rsv.ovf_table) ? *s_clear : 0ull;  // uniform
+    if (clear == 0) {
 #pragma unroll
-    for (uint32_t k = 0; k < IPT; ++k) {
-        const uint32_t j = k * BLOCK + threadIdx.x;
-        if (j < t.len) {
-            const int32_t key = skey[j];
-            const uint32_t dst = delta[part_of(key, cfg)] + j;
-            if (dst < sg.n) {  // always true for a consistent histogram scan; keeps stores in the segment
-                kout[dst] = key;
-                rout[dst] = srid[j];
+        for (uint32_t k = 0; k < IPT; ++k) {
+            const uint32_t j = k * BLOCK + threadIdx.x;
+            if (j < t.len) {
+                const int32_t key = skey[j];
+                const uint32_t dst = delta[part_of(key, cfg)] + j;
+                if (dst < sg.n) {  // always true for a consistent histogram scan; keeps stores in the segment
+                    kout[dst] = key;
+                    rout[dst] = srid[j];
+                }
+            }
+        }
+    } else {  // the same, and the 2 table slots of each tuple of a partition marked in `clear`
+        uint4* __restrict__ slots = reinterpret_cast<uint4*>(rsv.ovf_table) + sg.out_base;  // R segment
+#pragma unroll
+        for (uint32_t k = 0; k < IPT; ++k) {
+            const uint32_t j = k * BLOCK + threadIdx.x;
+            if (j < t.len) {
+                const int32_t key = skey[j];
+                const uint32_t p = part_of(key, cfg);
+                const uint32_t dst = delta[p] + j;
+                if (dst < sg.n) {
+                    kout[dst] = key;
+                    rout[dst] = srid[j];
+                    if ((clear >> p) & 1u) slots[dst] = make_uint4(~0u, ~0u, ~0u, ~0u);
+                }
             }
         }
     }
@@ -549,7 +573,7 @@ void part_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint32_
                   uint32_t grid, const PassCfg& cfg, const uint32_t* hist_scan, int32_t* key_out,
                   int32_t* rid_out, const SideJob& side, Recorder& rec, const Reserve* rsv) {
     if (side.front + grid + side.blocks == 0) return;
-    const Reserve r = rsv ? *rsv : Reserve{nullptr, nullptr};
+    const Reserve r = rsv ? *rsv : Reserve{nullptr, nullptr, nullptr, 0u, 0u};
 #define HJ_SCATTER(BLOCK, IPT) \
     launch_scatter<BLOCK, IPT>(segs, tile_begin, tile_seg, nseg, grid, cfg, hist_scan, key_out, rid_out, side, rec, r)
     switch (cfg.tile) {  // workgroup size by tile: part_block()

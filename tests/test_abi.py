@@ -262,6 +262,7 @@ def test_model_geometry_matches_the_kernels():
     assert rule and int(rule.group(1)) == 4
     assert [b for b in range(2, 16) if costmodel.counted_pass2(2, 1, b - 1)] == list(range(4, 14))
     assert not costmodel.counted_pass2(1, 6, 0)
+    assert re.search(r"inline bool counted_clears_tables\(uint32_t b2\) \{ return b2 <= 6; \}", hdr)
 
 
 def test_table_and_probe_sizes(hj):
