@@ -72,6 +72,16 @@ CASES = [
     ("phj2_6_6_1pass", dict(algo="phj", passes=2, bits=(6, 6), one_pass=True)),
     ("phj1_3_1pass_ldscap256", dict(algo="phj", passes=1, bits=(3,), lds_cap=256, one_pass=True)),
     ("phj2_8_5_1pass_murmur", dict(algo="phj", passes=2, bits=(8, 5), hash="murmur2", one_pass=True)),
+    # around the counted pass 2 (4..13 bits in all): 3 bits keep the pass-2
+    # histogram; 12 and 9 bits in pass 2 reserve through LDS (more partitions per
+    # segment than a wave has lanes) and 12 bits span several plan workgroups
+    # per segment; small tiles run 256-thread workgroups; 1+7 bits with small
+    # LDS tables have oversized partitions the scatter does not clear
+    ("phj2_1_2", dict(algo="phj", passes=2, bits=(1, 2))),
+    ("phj2_1_12_t4096", dict(algo="phj", passes=2, bits=(1, 12), tile=4096)),
+    ("phj2_4_9_1pass", dict(algo="phj", passes=2, bits=(4, 9), one_pass=True)),
+    ("phj2_5_5_t1024", dict(algo="phj", passes=2, bits=(5, 5), tile=1024)),
+    ("phj2_1_7_ldscap256_1pass", dict(algo="phj", passes=2, bits=(1, 7), lds_cap=256, one_pass=True)),
 ]
 
 
@@ -434,6 +444,9 @@ C1_C2_PARAMS = [
     ("phj2_7_6_murmur", dict(algo="phj", passes=2, bits=(7, 6), hash="murmur2")),
     ("phj2_6_6_1pass", dict(algo="phj", passes=2, bits=(6, 6), one_pass=True)),
     ("shj_1pass", dict(algo="shj", one_pass=True)),
+    # counted pass 2 with more partitions per segment than a wave has lanes
+    ("phj2_5_8_1pass", dict(algo="phj", passes=2, bits=(5, 8), one_pass=True)),
+    ("phj2_6_7", dict(algo="phj", passes=2, bits=(6, 7))),
 ]
 
 
