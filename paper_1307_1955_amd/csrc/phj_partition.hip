@@ -78,19 +78,28 @@ __device__ __forceinline__ uint64_t match_mask(uint32_t p, uint32_t bits, bool v
 // window (when s > 0) go to `x` of threads 0..2.  Nothing outside the tile is
 // read.  Returns the validity mask: bit i for v[i], bit 4 IPT for x.  Element
 // order inside a tile is free: counts and ranks do not depend on it.
+// Pointers into device memory taken from tables in memory are generic; read
+// through the global address space the loads are global loads, which unlike
+// generic (flat) ones are not counted against LDS accesses (a wait for LDS
+// would otherwise also wait for the tile's loads).
+typedef __attribute__((address_space(1))) const int32_t gint32;
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const i32x4 gi32x4;
+
 template <uint32_t BLOCK, uint32_t IPT>
-__device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ p, uint32_t len, int32_t* v,
+__device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ pg, uint32_t len, int32_t* v,
                                                   int32_t& x) {
     static_assert(IPT % 4 == 0 && IPT <= 32, "vector tile slots");
-    const uint32_t s = (uint32_t)(((uintptr_t)p >> 2) & 3u);
-    const int32_t* __restrict__ q = p - s;  // 16-byte aligned
+    gint32* __restrict__ p = (gint32*)pg;
+    const uint32_t s = (uint32_t)(((uintptr_t)pg >> 2) & 3u);
+    gint32* __restrict__ q = p - s;  // 16-byte aligned
     uint64_t valid = 0;
 #pragma unroll
     for (uint32_t k = 0; k < IPT / 4; ++k) {
         const uint32_t c = threadIdx.x + k * BLOCK;
         const int32_t i0 = (int32_t)(4 * c) - (int32_t)s;  // tile index of the chunk's first element
         if (i0 >= 0 && i0 + 4 <= (int32_t)len) {
-            const int4 w = *reinterpret_cast<const int4*>(q + 4 * c);
+            const i32x4 w = *reinterpret_cast<gi32x4*>(q + 4 * c);
             v[4 * k] = w.x;
             v[4 * k + 1] = w.y;
             v[4 * k + 2] = w.z;
@@ -285,8 +294,8 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
         for (uint32_t k = 0; k < IPT; ++k) {
             const uint32_t idx = k * BLOCK + threadIdx.x;
             const bool ok = idx < t.len;
-            keys[k] = ok ? kin[idx] : 0;
-            rids[k] = ok ? rin[idx] : 0;
+            keys[k] = ok ? ((gint32*)kin)[idx] : 0;
+            rids[k] = ok ? ((gint32*)rin)[idx] : 0;
             valid |= (uint64_t)ok << k;
         }
         kx = rx = 0;
