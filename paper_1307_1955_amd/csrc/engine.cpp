@@ -455,7 +455,7 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
     plan.plan = hj::PlanArgs{two ? w.segs2 : w.segs1, two ? w.tb2 : w.tb1, two ? w.hist2 : w.hist1,
                              two ? 2 * pl.P1 : 2u, two ? pl.b2 : pl.b1, n_r, n_s, pl.B, pl.lds_cap,
                              w.pairs, w.item_begin, w.ovf_begin, w.item_rec, w.ovf_part, zero_total, w.stp,
-                             r_pairs, plan_ctl, counted ? w.tot2 : nullptr};
+                             r_pairs, plan_ctl, counted ? w.tot2 : nullptr, (uint32_t)w.items_ub};
     hj::SideJob setup2{};
     if (two) {
         setup2.kind = hj::kSideSetup2;

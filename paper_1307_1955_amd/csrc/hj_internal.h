@@ -304,7 +304,8 @@ struct JoinPlanOut {
 size_t plan_state_words(uint32_t P);
 // Upper bounds of the HBM-table build items and of the join work items.
 uint32_t ovf_grid(uint32_t P, uint64_t n_r);
-uint32_t join_grid(uint32_t P, uint64_t n_s);
+uint32_t join_grid(uint32_t P, uint64_t n_s);  // (a multiple of 8 kItemGroup)
+constexpr uint32_t kItemGroup = 16;  // consecutive join items dealt to one XCD
 // Dynamic LDS bytes of the join kernels for a given lds_cap.
 size_t join_lds_bytes(uint32_t lds_cap, bool write);
 size_t part_scatter_lds_bytes(uint32_t bits, uint32_t tile);

@@ -44,6 +44,9 @@ struct PlanArgs {
     ScanCtl ctl;  // the chained scan of the plan reports a give-up here
     // counted pass 2: final partition sizes (Reserve::tot) instead of hist_scan
     const uint32_t* tot;
+    // records of item_rec up to here that have no item are written empty (the
+    // join kernels' workgroup b takes record b)
+    uint32_t items_ub;
 };
 
 enum SideKind : uint32_t { kSideNone = 0, kSideSetup2 = 1, kSidePlan = 2 };
@@ -220,6 +223,14 @@ __device__ __forceinline__ void join_plan_block(const PlanArgs& A, uint64_t* lds
     if (i == P - 1) {  // the last pair also writes the totals
         item_begin[P] = ib + ni;
         ovf_begin[P] = ob + no;
+    }
+    // the workgroup of the last pair marks the records past the last item empty
+    __shared__ uint32_t s_live;
+    const bool last_blk = blk * blockDim.x <= P - 1 && P - 1 < (blk + 1) * blockDim.x;  // uniform
+    if (last_blk) {
+        if (i == P - 1) s_live = ib + ni;
+        __syncthreads();
+        for (uint32_t x = s_live + threadIdx.x; x < A.items_ub; x += blockDim.x) item_rec[x] = ItemRec{0, 0, 0, 0};
     }
 }
 

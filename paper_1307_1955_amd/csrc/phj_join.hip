@@ -175,16 +175,22 @@ struct ItemLoc {
     uint32_t s_begin, s_n;
 };
 
-// The work item of this workgroup (items spread over the XCDs in proportion to
-// live work): two dependent loads, the live count and the item's record.
-__device__ __forceinline__ ItemLoc locate_item(const uint32_t* __restrict__ item_begin,
-                                               const ItemRec* __restrict__ item_rec, uint32_t P) {
+// The work item of this workgroup, one dependent load (the plan writes the
+// records past the last item empty; an item has at least one S tuple).
+// Workgroups go to the 8 XCDs round-robin; items are dealt to them in groups
+// of kItemGroup consecutive items (the items of one partition share its table
+// in the XCD's L2), so each XCD gets every 8th group, evenly however many
+// items there are.  A bijection on a grid of a multiple of 8 kItemGroup.
+__device__ __forceinline__ uint32_t item_of_block(uint32_t b) {
+    const uint32_t x = b % 8, l = b / 8;
+    return ((l / kItemGroup) * 8 + x) * kItemGroup + l % kItemGroup;
+}
+
+__device__ __forceinline__ ItemLoc locate_item(const ItemRec* __restrict__ item_rec) {
     ItemLoc L;
-    const uint32_t live = item_begin[P];
-    L.item = live_remap(blockIdx.x, live);
-    L.live = L.item < live;
-    if (!L.live) return L;
+    L.item = item_of_block(blockIdx.x);
     const ItemRec r = item_rec[L.item];
+    L.live = r.s_n != 0;
     L.r_off = r.r_off;
     L.r_len = r.r_len;
     L.s_begin = r.s_begin;
@@ -451,7 +457,7 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
     extern __shared__ uint32_t lds[];
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
-    const ItemLoc L = locate_item(item_begin, item_rec, P);
+    const ItemLoc L = locate_item(item_rec);
     if (!L.live) {
         if (lane == 0) wave_cnt[(uint64_t)L.item * kJoinWaves + w] = 0;
         return;
@@ -608,22 +614,14 @@ k_join_write(
     __shared__ uint64_t wtot[kJoinWaves + 1];
     __shared__ uint32_t s_word;
     const uint32_t w = threadIdx.x / kWave;
-    const uint32_t live = item_begin[P];
     if (kOnePass && heavy && blockIdx.x >= item_grid) {  // a helper
         if (!heavy->wait) return;  // written by an earlier launch: uniform
         help_until_done(heavy, rk, rr, total, capacity, out_r, out_s, lds, &s_word);
         return;
     }
-    const uint32_t item = live_remap(blockIdx.x, live);
-    if (item >= live) return;
-    const ItemRec r = item_rec[item];
-    ItemLoc L;
-    L.item = item;
-    L.live = true;
-    L.r_off = r.r_off;
-    L.r_len = r.r_len;
-    L.s_begin = r.s_begin;
-    L.s_n = r.s_n;
+    const ItemLoc L = locate_item(item_rec);
+    if (!L.live) return;
+    const uint32_t item = L.item;
     const uint64_t base = kOnePass ? 0ull : wave_base[(uint64_t)item * kJoinWaves + w];
     write_item<kOnePass, RPT>(L, w, lds, wtot, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, hot, base, total,
                               out_r, out_s, capacity, heavy);
@@ -760,7 +758,8 @@ uint32_t ovf_grid(uint32_t P, uint64_t n_r) {
 }
 
 uint32_t join_grid(uint32_t P, uint64_t n_s) {
-    return (uint32_t)(P + (n_s + kJoinChunk - 1) / kJoinChunk);
+    const uint64_t items = P + (n_s + kJoinChunk - 1) / kJoinChunk;
+    return (uint32_t)((items + 8 * kItemGroup - 1) / (8 * kItemGroup) * (8 * kItemGroup));  // item_of_block
 }
 
 void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint32_t* ovf_part, uint32_t P,
