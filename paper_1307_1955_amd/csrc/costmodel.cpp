@@ -64,12 +64,20 @@ double table_factor(double table_bytes, double gamma, double base = 1048576.0) {
 
 double rounds(double items, double slots) { return std::ceil(std::max(items, 1.0) / slots); }
 
+// (a^p + b^p)^(1/p): max(a, b) as p grows, more than it when a and b are close.
+double smooth_max(double a, double b, double p) {
+    const double m = std::max(a, b);
+    if (m <= 0) return 0;
+    return m * std::pow(std::pow(a / m, p) + std::pow(b / m, p), 1.0 / p);
+}
+
 // extra: bytes beyond the tuples' (a counted pass 2's count rows); bins: the
 // counters a counted pass 2's histogram tile clears, counts and packs
 double hist_s(double n, double tiles, uint32_t tile, double extra, double bins) {
     if (tiles == 0) return k_d_kernel;
     const double per_tile = k_t_hist_tile * tile / 8192.0 + k_t_count_bin * bins;
-    return k_d_kernel + std::max((4.0 * n + extra) / k_bw_hist, rounds(tiles, hist_slots(tile)) * per_tile);
+    return k_d_kernel +
+           smooth_max((4.0 * n + extra) / k_bw_hist, rounds(tiles, hist_slots(tile)) * per_tile, k_p_part);
 }
 
 // counted: a counted pass 2's scatter (count sums beside pass 1, reservations in pass 2)
@@ -78,17 +86,11 @@ double scatter_s(double n, double tiles, uint32_t tile, uint32_t bits, double ex
     const double run = tile / std::ldexp(1.0, (int)bits);
     const double bw = k_bw_scatter * run / (run + k_run_half);
     const double per_tile = k_t_scatter_tile * tile / 8192.0 + (counted ? k_t_reserve : 0.0);
-    return k_d_kernel + std::max((16.0 * n + extra) / bw, rounds(tiles, scatter_slots(bits, tile)) * per_tile);
+    return k_d_kernel +
+           smooth_max((16.0 * n + extra) / bw, rounds(tiles, scatter_slots(bits, tile)) * per_tile, k_p_part);
 }
 
 double scan_s(double entries) { return k_d_kernel + entries * k_t_scan_entry; }
-
-// (a^p + b^p)^(1/p): max(a, b) as p grows, more than it when a and b are close.
-double smooth_max(double a, double b, double p) {
-    const double m = std::max(a, b);
-    if (m <= 0) return 0;
-    return m * std::pow(std::pow(a / m, p) + std::pow(b / m, p), 1.0 / p);
-}
 
 // f: the kernel's work-item latency against the write pass (k_f_count, k_f_1pass, or 1)
 double join_s(double items, double r, double s, uint32_t cap, bool hbm, double bytes, double f) {
@@ -187,8 +189,11 @@ double model_seconds(const Plan& pl, uint64_t n_r_, uint64_t n_s_, double m) {
 
 // HJ_AUTO: the plan with the least modelled time among SHJ, the direct LDS join
 // (|R| <= 8192) and PHJ in one or two radix passes around ~4096 R tuples per
-// partition, with both partitioning tiles when the caller leaves the tile open.
-// Hash, lds_cap and flags are the caller's.  The output size is taken as |S|
+// partition.  The partitioning tile is the caller's, else the measured size
+// rule (default_tile): between the two tiles the model cannot see which pass
+// loses by shorter runs (pass 1 reads the inputs cold; 16M x 16M ran 9% slower
+// with 4096-tuple tiles, which the model priced faster).  Hash, lds_cap and
+// flags are the caller's.  The output size is taken as |S|
 // (one match per probe tuple), the same for every candidate.
 void auto_params(uint64_t n_r, uint64_t n_s, hj_params* p) {
     const hj_params base = *p;
@@ -218,10 +223,9 @@ void auto_params(uint64_t n_r, uint64_t n_s, hj_params* p) {
     if (n_r <= kMaxLdsCap) consider(q);  // passes 0: one LDS table
     uint32_t B = 0;
     while (B < kMaxRadixBits && (n_r >> B) > 4096) ++B;
-    const uint32_t tiles[2] = {4096, 8192};
     for (uint32_t b = (B > 2 ? B - 2 : 1); b <= std::min(B + 2, kMaxRadixBits); ++b) {
-        for (uint32_t ti = 0; ti < (base.tile ? 1u : 2u); ++ti) {
-            q.tile = base.tile ? base.tile : tiles[ti];
+        {
+            q.tile = base.tile;  // 0: the size rule
             if (b <= 13) {
                 q.passes = 1;
                 q.bits[0] = b;

@@ -171,7 +171,7 @@ def auto_candidates(hj, n_r, flags, tile=0):
     while B < 20 and (n_r >> B) > 4096:
         B += 1
     for b in range(max(1, B - 2), min(B + 2, 20) + 1):
-        for t in ((tile,) if tile else (4096, 8192)):
+        for t in (tile,):  # 0: the library's size rule
             if b <= 13:
                 c.append(hj.params("phj", 1, (b,), tile=t, one_pass=bool(flags)))
             if b >= 2:

@@ -23,8 +23,15 @@ def test_model_prices_every_candidate(hj, n_r, n_s):
     ts = [tune.model_ms(c, n_r, n_s, n_s) for c in cands]  # HJ_AUTO plans for |S| pairs
     assert all(math.isfinite(t) and t > 0 for t in ts)
     # HJ_AUTO keeps the output mode and is the model's minimum over a superset of
-    # these plans, so no candidate with the same (one-pass) output beats it
-    same = [t for c, t in zip(cands[1:], ts[1:]) if c.one_pass]
+    # these plans at the library's tile size rule, so no such candidate with the
+    # same (one-pass) output beats it
+    def rule_tile(c):
+        if c.algo == "shj" or c.passes == 0:
+            return c.tile
+        p = c.params()
+        p.tile = 0
+        return hj.hj_resolve_params(p, n_r, n_s).tile
+    same = [t for c, t in zip(cands[1:], ts[1:]) if c.one_pass and (c.tile == 0 or c.tile == rule_tile(c))]
     assert ts[0] <= min(same) * (1 + 1e-12)
 
 
