@@ -110,13 +110,13 @@ __device__ __forceinline__ uint32_t table_log2H(uint32_t n) {
     return 31u - (uint32_t)__clz(v);
 }
 
-// R_i's keys of this thread, n <= RPT * kJoinBlock.
+// R_i's keys of this thread, n <= RPT * kJoinBlock (read once: non-temporal loads).
 template <uint32_t RPT>
 __device__ __forceinline__ void load_r(const int32_t* __restrict__ rk, uint32_t n, int32_t* k) {
 #pragma unroll
     for (uint32_t u = 0; u < RPT; ++u) {
         const uint32_t j = u * kJoinBlock + threadIdx.x;
-        k[u] = j < n ? rk[j] : 0;
+        k[u] = j < n ? __builtin_nontemporal_load(rk + j) : 0;
     }
 }
 
@@ -198,15 +198,16 @@ __device__ __forceinline__ ItemLoc locate_item(const ItemRec* __restrict__ item_
     return L;
 }
 
-// S keys (and rids) of this lane for the wave's range [wb, we) of the item.
+// S keys (and rids) of this lane for the wave's range [wb, we) of the item
+// (read once: non-temporal loads).
 template <bool kRids>
 __device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const int32_t* __restrict__ srp,
                                        uint32_t wb, uint32_t we, int32_t* q, int32_t* qr) {
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
         const uint32_t j = wb + u * kWave + lane_id();
-        q[u] = j < we ? skp[j] : 0;
-        if (kRids) qr[u] = j < we ? srp[j] : 0;
+        q[u] = j < we ? __builtin_nontemporal_load(skp + j) : 0;
+        if (kRids) qr[u] = j < we ? __builtin_nontemporal_load(srp + j) : 0;
     }
 }
 

@@ -81,12 +81,14 @@ __device__ __forceinline__ uint64_t match_mask(uint32_t p, uint32_t bits, bool v
 // Pointers into device memory taken from tables in memory are generic; read
 // through the global address space the loads are global loads, which unlike
 // generic (flat) ones are not counted against LDS accesses (a wait for LDS
-// would otherwise also wait for the tile's loads).
+// would otherwise also wait for the tile's loads).  kStream: the vector loads
+// are marked non-temporal (data a launch reads once: the histogram's and the
+// scatter's input).
 typedef __attribute__((address_space(1))) const int32_t gint32;
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const i32x4 gi32x4;
 
-template <uint32_t BLOCK, uint32_t IPT>
+template <uint32_t BLOCK, uint32_t IPT, bool kStream = false>
 __device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ pg, uint32_t len, int32_t* v,
                                                   int32_t& x) {
     static_assert(IPT % 4 == 0 && IPT <= 32, "vector tile slots");
@@ -99,7 +101,8 @@ __device__ __forceinline__ uint64_t load_tile_vec(const int32_t* __restrict__ pg
         const uint32_t c = threadIdx.x + k * BLOCK;
         const int32_t i0 = (int32_t)(4 * c) - (int32_t)s;  // tile index of the chunk's first element
         if (i0 >= 0 && i0 + 4 <= (int32_t)len) {
-            const i32x4 w = *reinterpret_cast<gi32x4*>(q + 4 * c);
+            gi32x4* a = reinterpret_cast<gi32x4*>(q + 4 * c);
+            const i32x4 w = kStream ? __builtin_nontemporal_load(a) : *a;
             v[4 * k] = w.x;
             v[4 * k + 1] = w.y;
             v[4 * k + 2] = w.z;
@@ -190,7 +193,12 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
         hist_base = sg.hist_base;
     }
     int32_t keys[IPT], kx;
-    const uint64_t valid = load_tile_vec<BLOCK, IPT>(kin, len, keys, kx);
+    const uint64_t valid = load_tile_vec<BLOCK, IPT, true>(kin, len, keys, kx);
+    // kCount with pass 1 above at least 4 low bits (b2 >= 4): the 16 final
+    // partitions of a packed column below share their pass-1 partition (the
+    // column index >> (b2 - 4)), so the pass-1 counts are summed from the
+    // columns, one LDS atomic per column instead of one per tuple (uniform)
+    const bool from_cols = kCount && cfg.shift >= 4;
     // counters cleared while the tile's loads are in flight
     for (uint32_t i = threadIdx.x; i < P; i += BLOCK) cnt[i] = 0;
     if (kCount)
@@ -203,33 +211,37 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
         const uint32_t h = radix_hash(keys[k], cfg.hash_kind);
         const uint32_t p = (h >> cfg.shift) & (P - 1u);
         if (kCount && ok) atomicAdd(&cnt_all[((h & 15u) << sh_all) | ((h & (PA - 1u)) >> 4)], 1u);
-        if (cfg.bits <= kBallotMaxBits) {
-            const uint64_t m = match_mask(p, cfg.bits, ok);
-            if (ok && (m & lt) == 0) atomicAdd(&cnt[p], (uint32_t)__popcll(m));
-        } else if (ok) {
-            atomicAdd(&cnt[p], 1u);
+        if (!from_cols) {
+            if (cfg.bits <= kBallotMaxBits) {
+                const uint64_t m = match_mask(p, cfg.bits, ok);
+                if (ok && (m & lt) == 0) atomicAdd(&cnt[p], (uint32_t)__popcll(m));
+            } else if (ok) {
+                atomicAdd(&cnt[p], 1u);
+            }
         }
     }
     if ((valid >> IPT) & 1u) {
         const uint32_t h = radix_hash(kx, cfg.hash_kind);
-        atomicAdd(&cnt[(h >> cfg.shift) & (P - 1u)], 1u);
+        if (!from_cols) atomicAdd(&cnt[(h >> cfg.shift) & (P - 1u)], 1u);
         if (kCount) atomicAdd(&cnt_all[((h & 15u) << sh_all) | ((h & (PA - 1u)) >> 4)], 1u);
     }
     __syncthreads();
     uint32_t* __restrict__ h = hist + hist_base + tl;
-    for (uint32_t p = threadIdx.x; p < P; p += BLOCK) h[(uint64_t)p * nt] = cnt[p];
+    if (!from_cols)
+        for (uint32_t p = threadIdx.x; p < P; p += BLOCK) h[(uint64_t)p * nt] = cnt[p];
     if (kCount) {
         // 16 counts per 16-byte store (PA >= 16); counts from kCountEscMin on
         // are 0 here and escaped
         uint4* __restrict__ out = reinterpret_cast<uint4*>(p1.rows + (uint64_t)row * PA);
         for (uint32_t c = threadIdx.x; c < PA / 16; c += BLOCK) {
-            uint32_t w[4];
+            uint32_t w[4], sum = 0;
 #pragma unroll
             for (uint32_t q = 0; q < 4; ++q) {
                 w[q] = 0;
 #pragma unroll
                 for (uint32_t e = 0; e < 4; ++e) {
                     uint32_t x = cnt_all[((4 * q + e) << sh_all) + c];  // partition 16 c + 4 q + e
+                    sum += x;
                     if (x >= kCountEscMin) {
                         const uint32_t k = atomicAdd(&esc[kCountEsc], 1u);
                         if (k < kCountEsc) esc[k] = (16 * c + 4 * q + e) << 14 | x;
@@ -239,8 +251,11 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
                 }
             }
             out[c] = make_uint4(w[0], w[1], w[2], w[3]);
+            if (from_cols && sum) atomicAdd(&cnt[c >> (cfg.shift - 4)], sum);
         }
         __syncthreads();
+        if (from_cols)
+            for (uint32_t p = threadIdx.x; p < P; p += BLOCK) h[(uint64_t)p * nt] = cnt[p];
         if (threadIdx.x < kCountEsc) p1.esc[(uint64_t)row * kCountEsc + threadIdx.x] = esc[threadIdx.x];
     }
 }
@@ -286,8 +301,8 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
     uint32_t rank[IPT];
     uint64_t valid;
     if ((((uintptr_t)kin ^ (uintptr_t)rin) & 15u) == 0) {  // same misalignment: one vector pattern for both
-        valid = load_tile_vec<BLOCK, IPT>(kin, t.len, keys, kx);
-        load_tile_vec<BLOCK, IPT>(rin, t.len, rids, rx);
+        valid = load_tile_vec<BLOCK, IPT, true>(kin, t.len, keys, kx);
+        load_tile_vec<BLOCK, IPT, true>(rin, t.len, rids, rx);
     } else {
         valid = 0;
 #pragma unroll

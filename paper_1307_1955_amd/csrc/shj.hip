@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ k
         int32_t k = 0;
         uint64_t s = kClaimed;
         if (i < n) {
-            k = key[i];
+            k = __builtin_nontemporal_load(key + i);  // read once
             s = push.hot(k) ? push.hot_slot : chain_claim(table, home_slot(k, nslots), k, (uint32_t)i, step);
         }
         push.add(table, next, s, k, (uint32_t)i);
@@ -105,8 +105,8 @@ __device__ __forceinline__ void shj_probe(const int32_t* __restrict__ s_key, con
         q[u] = 0;
         if (kRids) qr[u] = 0;
         if (j < n_s) {
-            q[u] = s_key[j];
-            if (kRids) qr[u] = s_rid[j];
+            q[u] = __builtin_nontemporal_load(s_key + j);  // read once
+            if (kRids) qr[u] = __builtin_nontemporal_load(s_rid + j);
             head[u] = chain_find(table, home_slot(q[u], nslots), q[u], step);
             if (head[u] != kNotFound) {
                 // a chain of one row is never heavy
