@@ -110,13 +110,14 @@ __device__ __forceinline__ uint32_t table_log2H(uint32_t n) {
     return 31u - (uint32_t)__clz(v);
 }
 
-// R_i's keys of this thread, n <= RPT * kJoinBlock (read once: non-temporal loads).
+// R_i's keys of this thread, n <= RPT * kJoinBlock.  Plain loads: every S
+// chunk (work item) of a partition reads R_i again.
 template <uint32_t RPT>
 __device__ __forceinline__ void load_r(const int32_t* __restrict__ rk, uint32_t n, int32_t* k) {
 #pragma unroll
     for (uint32_t u = 0; u < RPT; ++u) {
         const uint32_t j = u * kJoinBlock + threadIdx.x;
-        k[u] = j < n ? __builtin_nontemporal_load(rk + j) : 0;
+        k[u] = j < n ? rk[j] : 0;
     }
 }
 
