@@ -12,9 +12,12 @@
 //  * |R_i| > lds_cap (few, large partitions: low radix bits, duplicate-heavy
 //    R): the pair is joined through a partition-local open-addressing table
 //    in HBM (2 |R_i| slots at twice R_i's offset, plus per-key row chains),
-//    built by separate clear/build launches (compare-and-swap for a new key,
-//    exchange pushes for duplicates); S tuples on very long chains are
-//    counted and written by the whole workgroup (hj_heavy.h).
+//    cleared by the pass-2 scatter (counted plans of up to 6 pass-2 bits) or
+//    by a clear launch, and built by a build launch (compare-and-swap for a
+//    new key, exchange pushes for duplicates); S tuples on very long chains
+//    are counted and written by the whole workgroup (hj_heavy.h).
+// Workgroups take items in groups of 16 consecutive ones per XCD
+// (item_of_block), so one partition's items share that XCD's L2.
 // Output: count pass -> per-wave counts -> scan -> write pass, which re-runs
 // the same item and stores its pairs at the scanned offset, or one pass that
 // reserves each round's pairs on a running total (Section 3.3's dynamic

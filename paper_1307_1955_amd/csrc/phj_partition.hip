@@ -15,6 +15,13 @@
 //            popcount of lower group lanes at low fan-out), the tile is
 //            reordered by partition in LDS and written out run by run, so
 //            consecutive lanes store to consecutive addresses.
+// Counted pass 2 (two passes of 4..13 bits in all): the pass-1 hist also counts
+// every tuple's final partition and writes them as a row of 8-bit counts per
+// tile (larger counts as escapes); workgroups at the front of the pass-1
+// scatter sum the rows into per-segment totals, and each pass-2 scatter tile
+// reserves its run of every partition on a per-partition cursor instead of
+// reading a pass-2 histogram scan.  Tiles are read with non-temporal loads
+// (each launch reads its input once).
 // The paper's partition "buckets" with dynamically allocated storage
 // (Section 3.1, Section 3.3) become contiguous partitions at counted offsets.
 #include "hj_device.h"
