@@ -127,6 +127,8 @@ hj_status check_params(const hj_params* p, uint64_t n_r, uint64_t n_s, Plan* pl)
     pl->b1 = pl->b2 = pl->B = 0;
     pl->P1 = pl->P2 = pl->P = 1;
     pl->lds_cap = 0;
+    pl->nt_part = n_r + n_s >= hj::kNtMinTuples;
+    pl->nt_s = pl->nt_part && n_s <= 2 * n_r;
     if (!pl->phj) {
         fill_resolved(p, pl);
         return HJ_OK;
@@ -399,7 +401,7 @@ hj_status check_call(const hj_params* p, const hj_rel* R, const hj_rel* S, const
 // SHJ build (Algorithm 1, b1-b4): empty slots, then R inserted.
 void shj_build_table(const hj_rel& R, const ShjTableWs& t, hj::Recorder& rec) {
     hj::shj_fill(t.table, t.nslots, t.hot, rec);
-    hj::shj_build(R.key, R.n, t.table, t.next, t.nslots, t.hot, rec);
+    hj::shj_build(R.key, R.n, t.table, t.next, t.nslots, t.hot, R.n >= hj::kNtMinBuild, rec);
 }
 
 // SHJ probe (Algorithm 1, p1-p4) of a table built over R.
@@ -463,7 +465,7 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
         setup2.setup2 = hj::Setup2Args{w.hist1, w.tb1, pl.b1, n_r, n_s, pl.tile, pl.b2, 0u, w.keyA, w.ridA,
                                        w.segs2, w.tb2, w.tseg2};
     }
-    hj::PassCfg c1{pl.b2, pl.b1, pl.hash, pl.tile};
+    hj::PassCfg c1{pl.b2, pl.b1, pl.hash, pl.tile, pl.nt_part};
     if (counted) {  // the count rows are summed beside the pass-1 scatter's tiles
         setup2.sums = hj::make_count_sums(w.rows, w.esc, w.tot2, p1.nt_r, p1.ntiles - p1.nt_r, pl.B,
                                           hj::part_block(pl.tile));
@@ -476,7 +478,7 @@ void phj_partition(const Plan& pl, const hj_rel& R, const hj_rel& S, const PhjWs
     *fk = w.keyA;
     *fr = w.ridA;
     if (two) {
-        hj::PassCfg c2{0, pl.b2, pl.hash, pl.tile};
+        hj::PassCfg c2{0, pl.b2, pl.hash, pl.tile, pl.nt_part};
         if (counted) {
             // with R scattered here (not a probe of a built table), its HBM tables are cleared by the scatter
             const bool clears = tables_cleared && !r_pairs && hj::counted_clears_tables(pl.b2);
@@ -505,12 +507,12 @@ void phj_join_pairs(const Plan& pl, const PhjWs& w, const int32_t* rk, const int
                        w.hot, pl.one_pass ? w.heavy : nullptr, rec, !tables_cleared);
     if (!pl.one_pass) {
         hj::join_count(w.pairs, w.item_begin, w.item_rec, pl.P, (uint32_t)w.items_ub, rk, sk, pl.lds_cap,
-                       w.ovf_table, w.ovf_next, w.hot, w.wave_cnt, rec);
+                       w.ovf_table, w.ovf_next, w.hot, w.wave_cnt, pl.nt_s, rec);
         hj::scan_u64(w.wave_cnt, w.wave_cnt, w.items_ub * hj::kJoinWaves, w.stw, d_count, rec);
     }
     hj::join_write(w.pairs, w.item_begin, w.item_rec, pl.P, (uint32_t)w.items_ub, rk, rr, sk, sr, pl.lds_cap,
                    w.ovf_table, w.ovf_next, pl.one_pass ? nullptr : w.wave_cnt, d_count, out.rid_r, out.rid_s,
-                   w.hot, out.capacity, pl.one_pass ? w.heavy : nullptr, rec);
+                   w.hot, out.capacity, pl.one_pass ? w.heavy : nullptr, pl.nt_s, rec);
 }
 
 void run_phj(const Plan& pl, const hj_rel& R, const hj_rel& S, const hj_out& out, void* ws,

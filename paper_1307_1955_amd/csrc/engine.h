@@ -26,6 +26,8 @@ uint64_t cdiv(uint64_t a, uint64_t b);
 // Validated parameters of one join.
 struct Plan {
     bool phj, one_pass;
+    // non-temporal loads (kNtMinTuples): partitioning tiles, the join's S chunks
+    bool nt_part, nt_s;
     uint32_t passes, b1, b2, B, P1, P2, P, tile, hash, lds_cap;
     hj_params res;  // the parameters as run (HJ_AUTO and size-dependent choices resolved)
 };

@@ -242,7 +242,7 @@ hj_status partition_relation(const hj_rel& X, uint32_t k, uint64_t chunk, Slot* 
         init_recorder(rec, s, err, false);
         const hj::Pass1 p1 = hj::make_pass1(sl.kin, sl.rin, len, nullptr, nullptr, 0, kExtTile, k, sl.segs, sl.tb,
                                             sl.st, sl.nst, nullptr);
-        const hj::PassCfg cfg{32 - k, k, HJ_HASH_MURMUR2, kExtTile};
+        const hj::PassCfg cfg{32 - k, k, HJ_HASH_MURMUR2, kExtTile, len >= hj::kNtMinTuples};
         const uint32_t tiles = (uint32_t)cdiv(len, kExtTile);
         hj::part_hist_pass1(p1, cfg, sl.hist, rec);
         hj::scan_u32(sl.hist, sl.hist, (uint64_t)tiles << k, sl.st, nullptr, rec);

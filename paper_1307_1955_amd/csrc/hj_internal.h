@@ -94,8 +94,9 @@ struct HotKeys;  // keys the build saw in long push runs (hj_device.h)
 // Fills the table with empty slots, clears the hot-key record and the call's
 // error word (rec.err_clear).
 void shj_fill(uint64_t* table, uint64_t nslots, HotKeys* hot, Recorder& rec);
+// nt: R's keys read with non-temporal loads (kNtMinBuild).
 void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint64_t nslots,
-               HotKeys* hot, Recorder& rec);
+               HotKeys* hot, bool nt, Recorder& rec);
 // Heavy S tuples of a one-pass probe (SHJ, and the HBM-table partitions of
 // PHJ) are handed to a device-wide queue: any workgroup that has finished its
 // own work claims chunks of the tuple's R rows and writes their matches (one
@@ -159,7 +160,18 @@ struct PassCfg {
     uint32_t bits;       // partitions = 1 << bits
     uint32_t hash_kind;  // hj_hash
     uint32_t tile;       // tuples per tile
+    uint32_t nt;         // tiles read with non-temporal loads
 };
+// Non-temporal loads of data a launch reads once pay only once a join's
+// relations outgrow the caches; below that, plain loads leave lines that a
+// later launch reads again.  Measured on MI355X (PHJ, one-pass output):
+// partitioning tiles from |R| + |S| = 2^24 on (8M x 16M: -3.7%, 16M x 16M:
+// -5.8%; 1M x 4M: +5.7%, 4M x 8M: +1.6%), the join's S chunks only while
+// also |S| <= 2 |R| (16M x 16M: -1.2%; 2M x 16M and 16M x 64M: +1.5%), the
+// SHJ build's R keys from |R| = 2^23 (16M: -7% build time; the probe's S
+// loads gained nothing and stay plain).
+constexpr uint64_t kNtMinTuples = 1ull << 24;
+constexpr uint64_t kNtMinBuild = 1ull << 23;
 // Two passes whose final partitions number 2^4..2^kCountedMaxBits are
 // "counted": pass 1 also counts every tile's tuples per final partition (one
 // row of 2^bits 8-bit counts per tile; a count of 255 or more is 0 in the row
@@ -319,13 +331,14 @@ void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint
 void join_count(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
-                const uint32_t* ovf_next, const HotKeys* hot, uint64_t* wave_cnt, Recorder& rec);
+                const uint32_t* ovf_next, const HotKeys* hot, uint64_t* wave_cnt, bool nt_s, Recorder& rec);
 void join_write(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                 uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
                 const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
-                const HotKeys* hot, uint64_t capacity, HeavyQueue* heavy, Recorder& rec);
+                const HotKeys* hot, uint64_t capacity, HeavyQueue* heavy, bool nt_s, Recorder& rec);
+// nt_s: S chunks read with non-temporal loads (LDS-table items).
 // wave_base == nullptr selects the one-pass write: `total` must be zero on entry
 // and ends as the number of pairs; `heavy` (one-pass only, zeroed before the
 // HBM-table build, or nullptr) takes the heavy S tuples of HBM-table

@@ -203,15 +203,15 @@ __device__ __forceinline__ ItemLoc locate_item(const ItemRec* __restrict__ item_
 }
 
 // S keys (and rids) of this lane for the wave's range [wb, we) of the item
-// (read once: non-temporal loads).
-template <bool kRids>
+// (kNt: non-temporal loads, for large joins; see kNtMinTuples).
+template <bool kRids, bool kNt = false>
 __device__ __forceinline__ void load_s(const int32_t* __restrict__ skp, const int32_t* __restrict__ srp,
                                        uint32_t wb, uint32_t we, int32_t* q, int32_t* qr) {
 #pragma unroll
     for (uint32_t u = 0; u < kSU; ++u) {
         const uint32_t j = wb + u * kWave + lane_id();
-        q[u] = j < we ? __builtin_nontemporal_load(skp + j) : 0;
-        if (kRids) qr[u] = j < we ? __builtin_nontemporal_load(srp + j) : 0;
+        q[u] = j < we ? (kNt ? __builtin_nontemporal_load(skp + j) : skp[j]) : 0;
+        if (kRids) qr[u] = j < we ? (kNt ? __builtin_nontemporal_load(srp + j) : srp[j]) : 0;
     }
 }
 
@@ -449,7 +449,7 @@ __device__ __forceinline__ uint64_t join_count_hbm(const ItemLoc L, uint32_t w, 
     return cnt;
 }
 
-template <uint32_t RPT>
+template <uint32_t RPT, bool kNt>
 __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __restrict__ pairs,
                                                           const uint32_t* __restrict__ item_begin,
                                                           const ItemRec* __restrict__ item_rec,
@@ -473,13 +473,13 @@ __global__ void __launch_bounds__(kJoinBlock) k_join_count(const PartPair* __res
     if (L.r_len <= lds_cap) {
         int32_t k[RPT];
         load_r<RPT>(rk + L.r_off, L.r_len, k);
-        load_s<false>(skp, nullptr, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, nullptr);
+        load_s<false, kNt>(skp, nullptr, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, nullptr);
         const LdsView v = lds_view(lds, lds_cap);
         const uint32_t log2H = table_log2H(L.r_len);
         build_lds<RPT>(k, L.r_len, log2H, v);
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
-            if (sb) load_s<false>(skp, nullptr, wb, we, q, nullptr);
+            if (sb) load_s<false, kNt>(skp, nullptr, wb, we, q, nullptr);
             uint32_t cf[kSU];
             probe_lds(v, log2H, q, wb, we, cf);
             cnt += lane_pairs_lds(cf);
@@ -532,7 +532,7 @@ __device__ __forceinline__ void join_write_hbm(
 }
 
 // The pairs of one work item (R_i in an LDS table, or its HBM table).
-template <bool kOnePass, uint32_t RPT>
+template <bool kOnePass, uint32_t RPT, bool kNt>
 __device__ __forceinline__ void write_item(const ItemLoc L, uint32_t w, uint32_t* lds, uint64_t* wtot,
                                            const int32_t* __restrict__ rk, const int32_t* __restrict__ rr,
                                            const int32_t* __restrict__ sk, const int32_t* __restrict__ sr,
@@ -548,13 +548,13 @@ __device__ __forceinline__ void write_item(const ItemLoc L, uint32_t w, uint32_t
     if (L.r_len <= lds_cap) {
         int32_t k[RPT];
         load_r<RPT>(rk + L.r_off, L.r_len, k);
-        load_s<true>(skp, srp, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, qr);
+        load_s<true, kNt>(skp, srp, w * kSubJ, min(w * kSubJ + kSubJ, L.s_n), q, qr);
         const LdsView v = lds_view(lds, lds_cap);
         const uint32_t log2H = table_log2H(L.r_len);
         build_lds<RPT>(k, L.r_len, log2H, v);
         for (uint32_t sb = 0; sb < L.s_n; sb += kJoinSub) {
             const uint32_t wb = sb + w * kSubJ, we = min(wb + kSubJ, L.s_n);
-            if (sb) load_s<true>(skp, srp, wb, we, q, qr);
+            if (sb) load_s<true, kNt>(skp, srp, wb, we, q, qr);
             uint32_t cf[kSU];
             int32_t rid0[kSU];
             probe_lds(v, log2H, q, wb, we, cf);
@@ -605,7 +605,7 @@ __device__ __attribute__((noinline)) void help_until_done(HeavyQueue* heavy, con
 // of atomics on the queue's line, which every workgroup also reads.)  The helpers are at most half
 // of the workgroups the device holds at once, so items always have room to
 // run, whatever order the workgroups start in.
-template <bool kOnePass, uint32_t RPT>
+template <bool kOnePass, uint32_t RPT, bool kNt>
 __global__ void __launch_bounds__(kJoinBlock) __attribute__((amdgpu_waves_per_eu(RPT > kRptMid ? 4 : 6)))
 k_join_write(
     const PartPair* __restrict__ pairs, const uint32_t* __restrict__ item_begin,
@@ -628,7 +628,7 @@ k_join_write(
     if (!L.live) return;
     const uint32_t item = L.item;
     const uint64_t base = kOnePass ? 0ull : wave_base[(uint64_t)item * kJoinWaves + w];
-    write_item<kOnePass, RPT>(L, w, lds, wtot, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, hot, base, total,
+    write_item<kOnePass, RPT, kNt>(L, w, lds, wtot, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, hot, base, total,
                               out_r, out_s, capacity, heavy);
     // one-pass: help with the heavy tuples any workgroup queued (the LDS
     // tables are free now and give the scratch)
@@ -784,47 +784,59 @@ void join_ovf_build(const PartPair* pairs, const uint32_t* ovf_begin, const uint
     rec.after();
 }
 
-template <uint32_t RPT>
+template <uint32_t RPT, bool kNt>
 void join_count_t(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                   uint32_t grid, const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
                   const uint32_t* ovf_next, const HotKeys* hot, uint64_t* wave_cnt, Recorder& rec) {
     const size_t lds = join_lds_bytes(lds_cap, false);
-    allow_lds((const void*)k_join_count<RPT>, lds);
+    allow_lds((const void*)k_join_count<RPT, kNt>, lds);
     rec.before("join_count");
-    hipLaunchKernelGGL(k_join_count<RPT>, dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin,
+    hipLaunchKernelGGL((k_join_count<RPT, kNt>), dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs, item_begin,
                        item_rec, P, rk, sk, lds_cap, ovf_table, ovf_next, hot, wave_cnt);
     rec.after();
+}
+
+template <bool kNt>
+void join_count_n(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
+                  uint32_t grid, const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
+                  const uint32_t* ovf_next, const HotKeys* hot, uint64_t* wave_cnt, Recorder& rec) {
+    switch (join_rpt(lds_cap)) {
+        case kRptSmall:
+            join_count_t<kRptSmall, kNt>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
+                                         hot, wave_cnt, rec);
+            break;
+        case kRptMid:
+            join_count_t<kRptMid, kNt>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
+                                       hot, wave_cnt, rec);
+            break;
+        default:
+            join_count_t<kRptLarge, kNt>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
+                                         hot, wave_cnt, rec);
+            break;
+    }
 }
 
 void join_count(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                 uint32_t grid,
                 const int32_t* rk, const int32_t* sk, uint32_t lds_cap, const uint64_t* ovf_table,
-                const uint32_t* ovf_next, const HotKeys* hot, uint64_t* wave_cnt, Recorder& rec) {
+                const uint32_t* ovf_next, const HotKeys* hot, uint64_t* wave_cnt, bool nt_s, Recorder& rec) {
     if (grid == 0) return;
-    switch (join_rpt(lds_cap)) {
-        case kRptSmall:
-            join_count_t<kRptSmall>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
-                                    hot, wave_cnt, rec);
-            break;
-        case kRptMid:
-            join_count_t<kRptMid>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
-                                  hot, wave_cnt, rec);
-            break;
-        default:
-            join_count_t<kRptLarge>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next,
-                                    hot, wave_cnt, rec);
-            break;
-    }
+    if (nt_s)
+        join_count_n<true>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next, hot,
+                           wave_cnt, rec);
+    else
+        join_count_n<false>(pairs, item_begin, item_rec, P, grid, rk, sk, lds_cap, ovf_table, ovf_next, hot,
+                            wave_cnt, rec);
 }
 
-template <bool kOnePass, uint32_t RPT>
+template <bool kOnePass, uint32_t RPT, bool kNt>
 void join_write_t(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                   uint32_t grid, const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                   uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next, const HotKeys* hot,
                   const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s, uint64_t capacity,
                   HeavyQueue* heavy, Recorder& rec) {
     const size_t lds = join_lds_bytes(lds_cap, true);
-    allow_lds((const void*)k_join_write<kOnePass, RPT>, lds);
+    allow_lds((const void*)k_join_write<kOnePass, RPT, kNt>, lds);
     rec.before(kOnePass ? "join_write_1pass" : "join_write");
     const uint32_t item_grid = grid;
     if (kOnePass && heavy) {
@@ -835,13 +847,13 @@ void join_write_t(const PartPair* pairs, const uint32_t* item_begin, const ItemR
         const uint32_t resident = 256u * std::max(1u, std::min(by_lds, by_waves));
         grid += std::max(1u, std::min(kMaxHelpers, resident / 2));
     }
-    hipLaunchKernelGGL((k_join_write<kOnePass, RPT>), dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs,
+    hipLaunchKernelGGL((k_join_write<kOnePass, RPT, kNt>), dim3(grid), dim3(kJoinBlock), lds, rec.stream, pairs,
                        item_begin, item_rec, P, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next, hot, wave_base,
                        (unsigned long long*)total, out_r, out_s, capacity, heavy, item_grid);
     rec.after();
 }
 
-template <bool kOnePass>
+template <bool kOnePass, bool kNt>
 void join_write_p(const PartPair* pairs, const uint32_t* item_begin, const ItemRec* item_rec, uint32_t P,
                   uint32_t grid, const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                   uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next, const HotKeys* hot,
@@ -849,15 +861,15 @@ void join_write_p(const PartPair* pairs, const uint32_t* item_begin, const ItemR
                   HeavyQueue* heavy, Recorder& rec) {
     switch (join_rpt(lds_cap)) {
         case kRptSmall:
-            join_write_t<kOnePass, kRptSmall>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
+            join_write_t<kOnePass, kRptSmall, kNt>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
                                               ovf_table, ovf_next, hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
             break;
         case kRptMid:
-            join_write_t<kOnePass, kRptMid>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
+            join_write_t<kOnePass, kRptMid, kNt>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
                                             ovf_table, ovf_next, hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
             break;
         default:
-            join_write_t<kOnePass, kRptLarge>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
+            join_write_t<kOnePass, kRptLarge, kNt>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap,
                                               ovf_table, ovf_next, hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
             break;
     }
@@ -868,14 +880,23 @@ void join_write(const PartPair* pairs, const uint32_t* item_begin, const ItemRec
                 const int32_t* rk, const int32_t* rr, const int32_t* sk, const int32_t* sr,
                 uint32_t lds_cap, const uint64_t* ovf_table, const uint32_t* ovf_next,
                 const uint64_t* wave_base, uint64_t* total, int32_t* out_r, int32_t* out_s,
-                const HotKeys* hot, uint64_t capacity, HeavyQueue* heavy, Recorder& rec) {
+                const HotKeys* hot, uint64_t capacity, HeavyQueue* heavy, bool nt_s, Recorder& rec) {
     if (grid == 0) return;
-    if (wave_base == nullptr)
-        join_write_p<true>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
-                           hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
-    else
-        join_write_p<false>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table, ovf_next,
-                            hot, wave_base, total, out_r, out_s, capacity, nullptr, rec);
+    if (wave_base == nullptr) {
+        if (nt_s)
+            join_write_p<true, true>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table,
+                                     ovf_next, hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
+        else
+            join_write_p<true, false>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table,
+                                      ovf_next, hot, wave_base, total, out_r, out_s, capacity, heavy, rec);
+    } else {
+        if (nt_s)
+            join_write_p<false, true>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table,
+                                      ovf_next, hot, wave_base, total, out_r, out_s, capacity, nullptr, rec);
+        else
+            join_write_p<false, false>(pairs, item_begin, item_rec, P, grid, rk, rr, sk, sr, lds_cap, ovf_table,
+                                       ovf_next, hot, wave_base, total, out_r, out_s, capacity, nullptr, rec);
+    }
 }
 
 }  // namespace hj

@@ -20,8 +20,8 @@
 // tile (larger counts as escapes); workgroups at the front of the pass-1
 // scatter sum the rows into per-segment totals, and each pass-2 scatter tile
 // reserves its run of every partition on a per-partition cursor instead of
-// reading a pass-2 histogram scan.  Tiles are read with non-temporal loads
-// (each launch reads its input once).
+// reading a pass-2 histogram scan.  Tiles of large joins are read with
+// non-temporal loads (PassCfg::nt).
 // The paper's partition "buckets" with dynamically allocated storage
 // (Section 3.1, Section 3.3) become contiguous partitions at counted offsets.
 #include "hj_device.h"
@@ -89,8 +89,8 @@ __device__ __forceinline__ uint64_t match_mask(uint32_t p, uint32_t bits, bool v
 // through the global address space the loads are global loads, which unlike
 // generic (flat) ones are not counted against LDS accesses (a wait for LDS
 // would otherwise also wait for the tile's loads).  kStream: the vector loads
-// are marked non-temporal (data a launch reads once: the histogram's and the
-// scatter's input).
+// are marked non-temporal (PassCfg::nt, large joins: each launch reads its
+// input once).
 typedef __attribute__((address_space(1))) const int32_t gint32;
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const i32x4 gi32x4;
@@ -153,7 +153,7 @@ __device__ __forceinline__ void pass1_setup(const Pass1& A) {
 // also does the pass's set-up; else the segments in memory.  kCount (pass 1 of
 // a counted pass 2): the tile's counts per final partition are also written,
 // as row p1.rows + tile * 2^bits_all of 8-bit counts and the tile's escapes.
-template <uint32_t BLOCK, uint32_t IPT, bool kPass1, bool kCount>
+template <uint32_t BLOCK, uint32_t IPT, bool kPass1, bool kCount, bool kNt>
 __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__ segs,
                                                          const uint32_t* __restrict__ tile_begin,
                                                          const uint32_t* __restrict__ tile_seg,
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
         hist_base = sg.hist_base;
     }
     int32_t keys[IPT], kx;
-    const uint64_t valid = load_tile_vec<BLOCK, IPT, true>(kin, len, keys, kx);
+    const uint64_t valid = load_tile_vec<BLOCK, IPT, kNt>(kin, len, keys, kx);
     // kCount with pass 1 above at least 4 low bits (b2 >= 4): the 16 final
     // partitions of a packed column below share their pass-1 partition (the
     // column index >> (b2 - 4)), so the pass-1 counts are summed from the
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const PartSeg* __restrict__
     }
 }
 
-template <uint32_t BLOCK, uint32_t IPT>
+template <uint32_t BLOCK, uint32_t IPT, bool kNt>
 __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restrict__ segs,
                                                             const uint32_t* __restrict__ tile_begin,
                                                             const uint32_t* __restrict__ tile_seg,
@@ -308,8 +308,8 @@ __global__ void __launch_bounds__(BLOCK) k_part_scatter(const PartSeg* __restric
     uint32_t rank[IPT];
     uint64_t valid;
     if ((((uintptr_t)kin ^ (uintptr_t)rin) & 15u) == 0) {  // same misalignment: one vector pattern for both
-        valid = load_tile_vec<BLOCK, IPT, true>(kin, t.len, keys, kx);
-        load_tile_vec<BLOCK, IPT, true>(rin, t.len, rids, rx);
+        valid = load_tile_vec<BLOCK, IPT, kNt>(kin, t.len, keys, kx);
+        load_tile_vec<BLOCK, IPT, kNt>(rin, t.len, rids, rx);
     } else {
         valid = 0;
 #pragma unroll
@@ -492,15 +492,24 @@ void launch_hist(const PartSeg* segs, const uint32_t* tile_begin, const uint32_t
         sizeof(uint32_t) * (((size_t)1 << cfg.bits) + (count ? ((size_t)1 << p1->bits_all) + kCountEsc + 1 : 0));
     rec.before("part_hist");
     static_assert(BLOCK * IPT >= 1024 && BLOCK * IPT <= 8192 && BLOCK / kWave <= kScanScratch, "tile shape");
-    if (count)
-        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true, true>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
-                           tile_begin, tile_seg, nseg, cfg, hist, *p1);
+    if (count && cfg.nt)
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true, true, true>), dim3(grid), dim3(BLOCK), lds, rec.stream,
+                           segs, tile_begin, tile_seg, nseg, cfg, hist, *p1);
+    else if (count)
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true, true, false>), dim3(grid), dim3(BLOCK), lds, rec.stream,
+                           segs, tile_begin, tile_seg, nseg, cfg, hist, *p1);
+    else if (p1 && cfg.nt)
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true, false, true>), dim3(grid), dim3(BLOCK), lds, rec.stream,
+                           segs, tile_begin, tile_seg, nseg, cfg, hist, *p1);
     else if (p1)
-        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true, false>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
-                           tile_begin, tile_seg, nseg, cfg, hist, *p1);
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, true, false, false>), dim3(grid), dim3(BLOCK), lds, rec.stream,
+                           segs, tile_begin, tile_seg, nseg, cfg, hist, *p1);
+    else if (cfg.nt)
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, false, false, true>), dim3(grid), dim3(BLOCK), lds, rec.stream,
+                           segs, tile_begin, tile_seg, nseg, cfg, hist, Pass1{});
     else
-        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, false, false>), dim3(grid), dim3(BLOCK), lds, rec.stream, segs,
-                           tile_begin, tile_seg, nseg, cfg, hist, Pass1{});
+        hipLaunchKernelGGL((k_part_hist<BLOCK, IPT, false, false, false>), dim3(grid), dim3(BLOCK), lds, rec.stream,
+                           segs, tile_begin, tile_seg, nseg, cfg, hist, Pass1{});
     rec.after();
 }
 
@@ -532,15 +541,19 @@ void launch_scatter(const PartSeg* segs, const uint32_t* tile_begin, const uint3
         const size_t want = sizeof(uint32_t) * (kScanScratch + 2 * ((size_t)1 << side.setup2.bits1) + 1);
         if (want > lds && want <= 65536) lds = want;
     }
+    const void* kern = cfg.nt ? (const void*)k_part_scatter<BLOCK, IPT, true>
+                              : (const void*)k_part_scatter<BLOCK, IPT, false>;
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)k_part_scatter<BLOCK, IPT>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
+        (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     rec.before("part_scatter");
-    hipLaunchKernelGGL((k_part_scatter<BLOCK, IPT>), dim3(side.front + grid + side.blocks), dim3(BLOCK), lds,
-                       rec.stream, segs,
-                       tile_begin, tile_seg, nseg, cfg, hist_scan, key_out, rid_out, side,
-                       (uint32_t)(lds / sizeof(uint32_t)), rsv);
+    if (cfg.nt)
+        hipLaunchKernelGGL((k_part_scatter<BLOCK, IPT, true>), dim3(side.front + grid + side.blocks), dim3(BLOCK),
+                           lds, rec.stream, segs, tile_begin, tile_seg, nseg, cfg, hist_scan, key_out, rid_out, side,
+                           (uint32_t)(lds / sizeof(uint32_t)), rsv);
+    else
+        hipLaunchKernelGGL((k_part_scatter<BLOCK, IPT, false>), dim3(side.front + grid + side.blocks), dim3(BLOCK),
+                           lds, rec.stream, segs, tile_begin, tile_seg, nseg, cfg, hist_scan, key_out, rid_out, side,
+                           (uint32_t)(lds / sizeof(uint32_t)), rsv);
     rec.after();
 }
 

@@ -54,6 +54,7 @@ __device__ __forceinline__ uint64_t home_slot(int32_t k, uint64_t nslots) {
     return ((uint64_t)slot_hash(k) * nslots) >> 32;
 }
 
+template <bool kNt>
 __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ key, uint64_t n,
                                                   uint64_t* __restrict__ table, uint32_t* __restrict__ next,
                                                   uint64_t nslots, HotKeys* hot) {
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(256) k_shj_build(const int32_t* __restrict__ k
         int32_t k = 0;
         uint64_t s = kClaimed;
         if (i < n) {
-            k = __builtin_nontemporal_load(key + i);  // read once
+            k = kNt ? __builtin_nontemporal_load(key + i) : key[i];  // read once
             s = push.hot(k) ? push.hot_slot : chain_claim(table, home_slot(k, nslots), k, (uint32_t)i, step);
         }
         push.add(table, next, s, k, (uint32_t)i);
@@ -105,8 +106,8 @@ __device__ __forceinline__ void shj_probe(const int32_t* __restrict__ s_key, con
         q[u] = 0;
         if (kRids) qr[u] = 0;
         if (j < n_s) {
-            q[u] = __builtin_nontemporal_load(s_key + j);  // read once
-            if (kRids) qr[u] = __builtin_nontemporal_load(s_rid + j);
+            q[u] = s_key[j];
+            if (kRids) qr[u] = s_rid[j];
             head[u] = chain_find(table, home_slot(q[u], nslots), q[u], step);
             if (head[u] != kNotFound) {
                 // a chain of one row is never heavy
@@ -255,13 +256,17 @@ void shj_zero_one_pass(uint64_t* d_count, HeavyQueue* q, Recorder& rec) {
 }
 
 void shj_build(const int32_t* key, uint64_t n, uint64_t* table, uint32_t* next, uint64_t nslots,
-               HotKeys* hot, Recorder& rec) {
+               HotKeys* hot, bool nt, Recorder& rec) {
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;  // grid-stride: a wave's pending push chain spans its rows
     if (blocks == 0) return;
     rec.before("shj_build");
-    hipLaunchKernelGGL(k_shj_build, dim3((uint32_t)blocks), dim3(256), 0, rec.stream, key, n, table, next,
-                       nslots, hot);
+    if (nt)
+        hipLaunchKernelGGL(k_shj_build<true>, dim3((uint32_t)blocks), dim3(256), 0, rec.stream, key, n, table,
+                           next, nslots, hot);
+    else
+        hipLaunchKernelGGL(k_shj_build<false>, dim3((uint32_t)blocks), dim3(256), 0, rec.stream, key, n, table,
+                           next, nslots, hot);
     rec.after();
 }
 
