@@ -51,6 +51,7 @@ PARAMS = [
     "bw_scatter", "run_half", "t_scatter_tile",
     "t_reserve",           # a counted pass 2's scatter tile: count sums beside it, or reservations
     "p_part",              # the partitioning kernels overlap memory and latency imperfectly: (M^p + W^p)^(1/p)
+    "q_part",              # share of a later round of partitioning tiles whose latency shows (rounds overlap)
     "t_scan_entry",
     "bw_join", "l_join0", "l_join_r", "l_join_s",
     "f_count", "f_1pass",  # a work item's latency in the count pass and the one-pass write, against the write pass
@@ -206,6 +207,12 @@ def launches(plan: dict, n_r: int, n_s: int, m: float) -> list[tuple[str, dict]]
     return out
 
 
+def _part_lat(rounds: int, per_tile: float, c: dict) -> float:
+    """Latency term of a partitioning launch: the first round of tiles, then a
+    share q_part of each later round (rounds overlap)."""
+    return per_tile * (1.0 + (rounds - 1) * c["q_part"])
+
+
 def kernel_seconds(name: str, f: dict, c: dict) -> float:
     """One kernel's duration: ramp-up/drain + max(memory term, workgroup-latency term)."""
     d = c["d_kernel"]
@@ -214,7 +221,8 @@ def kernel_seconds(name: str, f: dict, c: dict) -> float:
             return d
         rounds = math.ceil(f["tiles"] / _hist_slots(f["tile"]))
         per_tile = c["t_hist_tile"] * f["tile"] / 8192.0 + c["t_count_bin"] * f["bins"]
-        return d + _smooth_max((4.0 * f["n"] + f["extra"]) / c["bw_hist"], rounds * per_tile, c["p_part"])
+        return d + _smooth_max((4.0 * f["n"] + f["extra"]) / c["bw_hist"], _part_lat(rounds, per_tile, c),
+                               c["p_part"])
     if name == "part_scatter":
         if f["tiles"] == 0:
             return d
@@ -222,7 +230,7 @@ def kernel_seconds(name: str, f: dict, c: dict) -> float:
         bw = c["bw_scatter"] * run / (run + c["run_half"])
         rounds = math.ceil(f["tiles"] / _scatter_slots(f["bits"], f["tile"]))
         per_tile = c["t_scatter_tile"] * f["tile"] / 8192.0 + c["t_reserve"] * f["counted"]
-        return d + _smooth_max((16.0 * f["n"] + f["extra"]) / bw, rounds * per_tile, c["p_part"])
+        return d + _smooth_max((16.0 * f["n"] + f["extra"]) / bw, _part_lat(rounds, per_tile, c), c["p_part"])
     if name in ("scan_u32", "scan_u64"):
         return d + f["entries"] * c["t_scan_entry"]
     if name in ("join_count", "join_write", "join_write_1pass", "direct_join"):
@@ -261,7 +269,7 @@ def join_seconds(plan: dict, n_r: int, n_s: int, m: float, c: dict) -> float:
 # starting point of the fit: rough MI355X figures
 START = {
     "d_gap": 2e-6, "d_kernel": 3e-6, "bw_hist": 4.5e12, "t_hist_tile": 5e-6, "t_count_bin": 1e-9,
-    "bw_scatter": 5.2e12, "run_half": 8.0, "t_scatter_tile": 12e-6, "t_reserve": 2e-6, "p_part": 4.0, "t_scan_entry": 2e-12, "bw_join": 4e12, "l_join0": 4e-6, "l_join_r": 1e-9,
+    "bw_scatter": 5.2e12, "run_half": 8.0, "t_scatter_tile": 12e-6, "t_reserve": 2e-6, "p_part": 4.0, "q_part": 0.5, "t_scan_entry": 2e-12, "bw_join": 4e12, "l_join0": 4e-6, "l_join_r": 1e-9,
     "l_join_s": 5e-10, "f_count": 0.8, "f_1pass": 1.2, "p_join": 4.0, "l_hbm0": 8e-6, "l_hbm_s": 2e-9, "t_ovf_insert": 1e-10, "l_ovf_round": 4e-6,
     "bw_fill": 5e12, "t_ins": 1e-10, "gamma_ins": -0.2, "t_bround": 1e-5, "gamma_bround": 0.1,
     "t_probe": 3e-11, "gamma_probe": 0.0, "t_pround": 2e-5, "gamma_pround": 0.1, "t_match": 1e-11,

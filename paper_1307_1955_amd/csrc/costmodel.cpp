@@ -10,7 +10,9 @@
 // bandwidth of its access pattern (streaming read, scatter whose bandwidth
 // grows with the run length tile / 2^bits, random table lines served from the
 // caches or from HBM); W_k: rounds of resident workgroups times one
-// workgroup's duration (the latency-bound join items).  The constants come
+// workgroup's duration (the latency-bound join items; for the partitioning
+// tiles the first round's and a share q_part of every later round's, as
+// later rounds overlap the ones before).  The constants come
 // from per-kernel HIP-event times of a grid of joins on MI355X (generated
 // include calib_mi355x.inc; the Python twin paper_1307_1955_amd/costmodel.py
 // fits them and is kept equal to this file by a test).
@@ -73,11 +75,15 @@ double smooth_max(double a, double b, double p) {
 
 // extra: bytes beyond the tuples' (a counted pass 2's count rows); bins: the
 // counters a counted pass 2's histogram tile clears, counts and packs
+// Latency term of a partitioning launch: the first round of tiles, then a
+// share q_part of each later round (rounds overlap).
+double part_lat(double rounds, double per_tile) { return per_tile * (1.0 + (rounds - 1.0) * k_q_part); }
+
 double hist_s(double n, double tiles, uint32_t tile, double extra, double bins) {
     if (tiles == 0) return k_d_kernel;
     const double per_tile = k_t_hist_tile * tile / 8192.0 + k_t_count_bin * bins;
-    return k_d_kernel +
-           smooth_max((4.0 * n + extra) / k_bw_hist, rounds(tiles, hist_slots(tile)) * per_tile, k_p_part);
+    return k_d_kernel + smooth_max((4.0 * n + extra) / k_bw_hist,
+                                   part_lat(rounds(tiles, hist_slots(tile)), per_tile), k_p_part);
 }
 
 // counted: a counted pass 2's scatter (count sums beside pass 1, reservations in pass 2)
@@ -86,8 +92,8 @@ double scatter_s(double n, double tiles, uint32_t tile, uint32_t bits, double ex
     const double run = tile / std::ldexp(1.0, (int)bits);
     const double bw = k_bw_scatter * run / (run + k_run_half);
     const double per_tile = k_t_scatter_tile * tile / 8192.0 + (counted ? k_t_reserve : 0.0);
-    return k_d_kernel +
-           smooth_max((16.0 * n + extra) / bw, rounds(tiles, scatter_slots(bits, tile)) * per_tile, k_p_part);
+    return k_d_kernel + smooth_max((16.0 * n + extra) / bw,
+                                   part_lat(rounds(tiles, scatter_slots(bits, tile)), per_tile), k_p_part);
 }
 
 double scan_s(double entries) { return k_d_kernel + entries * k_t_scan_entry; }
