@@ -53,7 +53,7 @@ typedef enum hj_status {
     HJ_ERR_WORKSPACE = 3,   /* ws_bytes below hj_workspace_bytes(), or ws NULL */
     HJ_ERR_DEVICE = 4,      /* a HIP runtime call failed, or the device reported a failure in the
                                workspace's error word (hj_workspace_status); see hj_last_error() */
-    HJ_ERR_UNSUPPORTED = 5  /* a parameter combination this build does not implement */
+    HJ_ERR_UNSUPPORTED = 5  /* a parameter combination the library does not implement */
 } hj_status;
 
 /* HJ_AUTO: the library evaluates its cost model (hj_model_seconds) for SHJ, for
