@@ -533,6 +533,28 @@ def test_c2_full_hbm_tables(name, kw):
             assert items == 1024, items
 
 
+# Joins of 2^24 tuples and more read their partitioning tiles (and, while
+# |S| <= 2 |R|, the join's S chunks) with non-temporal loads, and SHJ builds of
+# |R| >= 2^23 their R keys: the shapes on both sides of those thresholds, each
+# kernel variant in both output modes, every row against the closed form.
+NT_SHAPES = [
+    ("2m_16m_phj1_9", 1 << 21, 1 << 24, dict(algo="phj", passes=1, bits=(9,), tile=8192, one_pass=True)),
+    ("2m_16m_phj2_4_5", 1 << 21, 1 << 24, dict(algo="phj", passes=2, bits=(4, 5))),
+    ("8m_16m_phj2_5_6_1pass", 1 << 23, 1 << 24, dict(algo="phj", passes=2, bits=(5, 6), tile=4096, one_pass=True)),
+    ("8m_16m_phj2_5_6", 1 << 23, 1 << 24, dict(algo="phj", passes=2, bits=(5, 6), tile=4096)),
+    ("8m_8m_phj2_5_6_1pass", 1 << 23, 1 << 23, dict(algo="phj", passes=2, bits=(5, 6), one_pass=True)),
+    ("8m_8m_shj_1pass", 1 << 23, 1 << 23, dict(algo="shj", one_pass=True)),
+    ("4m_8m_shj", 1 << 22, 1 << 23, dict(algo="shj")),
+]
+
+
+@pytest.mark.parametrize("name,n_r,n_s,kw", NT_SHAPES, ids=[c[0] for c in NT_SHAPES])
+def test_non_temporal_shapes(name, n_r, n_s, kw):
+    """Every row against the closed form, a sample of S rows against the oracle."""
+    rk, rr, sk, sr = dgen.unique_uniform(31, n_r, n_s, 2 * n_r, "cuda")
+    check_full(hj.params(**kw), rk, rr, sk, sr, seed=31)
+
+
 @pytest.mark.parametrize("theta", [0.5, 1.0])
 @pytest.mark.parametrize("kw", [dict(algo="phj", passes=2, bits=(6, 6)), dict(algo="shj"),
                                 dict(algo="phj", passes=2, bits=(6, 6), one_pass=True)],
